@@ -1,0 +1,358 @@
+"""Reference oracle for the MLMC estimator of E[AB] (Wu & Polydorides, arXiv:1904.00429).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product imports this package: only
+``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py``
+do.  It shares no code with the HIP library.
+
+The per-realisation work (random numbers, index draws, sketches, Welford
+updates) is plain sequential FP64 C in ``mlmc_oracle.c``; this module drives it
+the way Alg. 2 of Sec. 3.1 does, for a fixed finest level L, and adds the
+closed-form moments that pin it (Theorem 3.2 specialised to the synthetic
+laws) and the optimal-allocation rule of Remark 3.6, eq. (28).
+
+Parity pins and where they are tested (``tests/test_oracle_*.py``):
+  Philox4x32-10      against rocRAND's open-source engine (a third-party
+                     implementation of the same published generator);
+  index map          against exact big-integer arithmetic and chi-square;
+  sketch (18)        brute force over every index tuple on tiny n and c;
+  Alg. 1 / (10)      telescoping identity on shared realisations;
+  level variances    closed forms (Thm 3.2 with uniform xi) by z-tests;
+  scheduler (28)     Lagrange optimality of the continuous allocation.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mlmc_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "_mlmc_oracle.so")
+
+LAW_NORMAL = 0
+LAW_UNIFORM = 1
+LAW_REPARAM = 2
+SHARED_LEVEL_FIELD = 0xFF
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (IEEE FP64, no contraction)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call([
+            "gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+            "-fno-fast-math", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Law(ctypes.Structure):
+    _fields_ = [("law", ctypes.c_int32), ("loc", ctypes.c_double),
+                ("scale", ctypes.c_double), ("mean", ctypes.c_void_p),
+                ("stdev", ctypes.c_void_p), ("ld", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.orc_philox_batch.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_uint64,
+                                       ctypes.c_void_p]
+        L.orc_draw_index.restype = ctypes.c_int64
+        L.orc_draw_index.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                     ctypes.c_uint32, ctypes.c_int64, ctypes.c_int64]
+        L.orc_draw_indices.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                       ctypes.c_uint32, ctypes.c_int64, ctypes.c_int64,
+                                       ctypes.c_void_p]
+        L.orc_uniform.restype = ctypes.c_double
+        L.orc_uniform.argtypes = [ctypes.c_uint32]
+        L.orc_column.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                 ctypes.c_uint32, ctypes.c_int64, ctypes.c_int64,
+                                 ctypes.c_int64, ctypes.POINTER(_Law), ctypes.POINTER(_Law),
+                                 ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_sketch_pair.argtypes = [ctypes.c_int64] * 5 + [ctypes.c_void_p] * 4
+        L.orc_level_estimation.restype = ctypes.c_int
+        L.orc_level_estimation.argtypes = (
+            [ctypes.c_int64] * 3 + [ctypes.POINTER(_Law)] * 2 + [ctypes.c_int64] * 2
+            + [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64,
+               ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+               ctypes.c_void_p])
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+# --------------------------------------------------------------------------
+# Laws of the random matrices (the "pre-defined" L_A, L_B of Alg. 1 / Alg. 2)
+# --------------------------------------------------------------------------
+@dataclass
+class Law:
+    """Entry law of A (m x n) or B (n x p).
+
+    normal:  loc + scale * N(0, 1);  uniform: loc + scale * U(-1, 1);
+    reparam: mean + stdev * N(0, 1) with A column-major (m x n, element (i, j)
+    at j*ld + i) and B row-major (n x p, element (j, q) at j*ld + q)."""
+    law: int
+    loc: float = 0.0
+    scale: float = 1.0
+    mean: Optional[np.ndarray] = None
+    stdev: Optional[np.ndarray] = None
+    ld: int = 0
+    _keep: list = field(default_factory=list, repr=False)
+
+    @staticmethod
+    def normal(loc: float, scale: float) -> "Law":
+        return Law(LAW_NORMAL, float(loc), float(scale))
+
+    @staticmethod
+    def uniform(loc: float, scale: float) -> "Law":
+        return Law(LAW_UNIFORM, float(loc), float(scale))
+
+    @staticmethod
+    def reparam(mean: np.ndarray, stdev: np.ndarray, ld: int) -> "Law":
+        return Law(LAW_REPARAM, 0.0, 0.0, np.ascontiguousarray(mean, dtype=np.float64),
+                   np.ascontiguousarray(stdev, dtype=np.float64), int(ld))
+
+    def c(self) -> _Law:
+        s = _Law()
+        s.law = self.law
+        s.loc = self.loc
+        s.scale = self.scale
+        if self.law == LAW_REPARAM:
+            s.mean = _ptr(self.mean)
+            s.stdev = _ptr(self.stdev)
+            s.ld = self.ld
+        return s
+
+
+# --------------------------------------------------------------------------
+# Random numbers, index draws, columns, sketches
+# --------------------------------------------------------------------------
+def philox(ctr: np.ndarray, seed: int) -> np.ndarray:
+    """Philox4x32-10 of counters ctr (count x 4 uint32) under key = seed."""
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    out = np.empty_like(ctr)
+    lib().orc_philox_batch(ctr.shape[0], _ptr(ctr), int(seed), _ptr(out))
+    return out
+
+
+def level_field(level: int, shared: bool = False) -> int:
+    return SHARED_LEVEL_FIELD if shared else int(level)
+
+
+def draw_indices(seed: int, problem: int, lfield: int, k: int, c: int, n: int) -> np.ndarray:
+    r = np.empty(int(c), dtype=np.int64)
+    lib().orc_draw_indices(int(seed), int(problem), int(lfield), int(k), int(c), int(n), _ptr(r))
+    return r
+
+
+def uniform(w: int) -> float:
+    return lib().orc_uniform(int(w))
+
+
+def column(seed: int, problem: int, lfield: int, k: int, j: int, m: int, p: int,
+           A: Law, B: Law):
+    a = np.empty(m, dtype=np.float64)
+    b = np.empty(p, dtype=np.float64)
+    la, lb = A.c(), B.c()
+    lib().orc_column(int(seed), int(problem), int(lfield), int(k), int(j), int(m), int(p),
+                     ctypes.byref(la), ctypes.byref(lb), _ptr(a), _ptr(b))
+    return a, b
+
+
+def realisation(seed: int, problem: int, lfield: int, k: int, m: int, n: int, p: int,
+                A: Law, B: Law):
+    """The whole realisation A^(k) (m x n), B^(k) (n x p) -- tiny n only."""
+    Am = np.empty((m, n))
+    Bm = np.empty((n, p))
+    for j in range(n):
+        Am[:, j], Bm[j, :] = column(seed, problem, lfield, k, j, m, p, A, B)
+    return Am, Bm
+
+
+def sketch_pair(n: int, c_f: int, c_c: int, AS: np.ndarray, BS: np.ndarray):
+    """Fine and coarse sketches (eq. (18), xi = 1/n) of gathered columns.
+
+    AS is (c_f, m): row t is the sampled column a_t; BS is (c_f, p)."""
+    AS = np.ascontiguousarray(AS, dtype=np.float64)
+    BS = np.ascontiguousarray(BS, dtype=np.float64)
+    m, p = AS.shape[1], BS.shape[1]
+    Zf = np.zeros((m, p))
+    Zc = np.zeros((m, p))
+    lib().orc_sketch_pair(m, p, int(n), int(c_f), int(c_c), _ptr(AS), _ptr(BS), _ptr(Zf), _ptr(Zc))
+    return Zf, Zc
+
+
+@dataclass
+class LevelState:
+    """Welford state of one level: count, per-entry mean and M2."""
+    count: int
+    mean: np.ndarray
+    m2: np.ndarray
+
+    @staticmethod
+    def empty(m: int, p: int) -> "LevelState":
+        return LevelState(0, np.zeros(m * p), np.zeros(m * p))
+
+    @property
+    def variance(self) -> float:
+        """V_l of Remark 3.6: vectorised variance of one level sample
+        (sum over entries of the unbiased entry variances)."""
+        if self.count < 2:
+            return 0.0
+        return float(self.m2.sum()) / (self.count - 1)
+
+
+def level_estimation(state: LevelState, m: int, n: int, p: int, A: Law, B: Law,
+                     c_l: int, c_prev: int, seed: int, problem: int, lfield: int,
+                     k_begin: int, k_end: int, want_samples: bool = False):
+    """Alg. 1 for realisations [k_begin, k_end), continuing `state` in place."""
+    cnt = ctypes.c_int64(state.count)
+    samples = np.empty((max(k_end - k_begin, 0), m, p)) if want_samples else None
+    la, lb = A.c(), B.c()
+    rc = lib().orc_level_estimation(
+        int(m), int(n), int(p), ctypes.byref(la), ctypes.byref(lb), int(c_l), int(c_prev),
+        int(seed), int(problem), int(lfield), int(k_begin), int(k_end), ctypes.byref(cnt),
+        _ptr(state.mean), _ptr(state.m2), _ptr(samples) if want_samples else None)
+    if rc != 0:
+        raise ValueError("orc_level_estimation rejected its arguments")
+    state.count = cnt.value
+    return samples
+
+
+# --------------------------------------------------------------------------
+# Optimal number of realisations per level: Remark 3.6, eq. (28)
+# --------------------------------------------------------------------------
+def schedule(V: Sequence[float], C: Sequence[float], eps: float) -> list:
+    """N_l = ceil(2 eps^-2 sqrt(V_l / C_l) sum_j sqrt(V_j C_j)).
+
+    Reading: the summand is indexed by j (the printed sqrt(V_l M^l) under a
+    sum over j is a typo) and C_l is the cost of one level-l realisation,
+    proportional to the number of sampled indices (M^l in the paper).  With
+    this choice the variance of the estimator, sum_l V_l / N_l, is at most
+    eps^2 / 2 (the budget of the proof of Theorem 2.3)."""
+    V = np.asarray(V, dtype=np.float64)
+    C = np.asarray(C, dtype=np.float64)
+    total = float(np.sum(np.sqrt(V * C)))
+    out = []
+    for v, c in zip(V, C):
+        out.append(int(math.ceil(2.0 / (eps * eps) * math.sqrt(v / c) * total)))
+    return out
+
+
+# --------------------------------------------------------------------------
+# The estimator (Alg. 2 with a fixed finest level L)
+# --------------------------------------------------------------------------
+@dataclass
+class Estimate:
+    Y: np.ndarray                 # sum_l Ybar_l, m x p (eq. (10))
+    level_means: np.ndarray       # (L+1) x m x p
+    level_var: np.ndarray         # V_l
+    n_used: np.ndarray            # N_l
+    rmse_est: float               # sqrt(sum_l V_l / N_l)
+
+
+def estimate(m: int, n: int, p: int, A: Law, B: Law, c: Sequence[int],
+             n_samples: Optional[Sequence[int]] = None, rmse_target: float = 0.0,
+             pilot: int = 0, seed: int = 0, problem: int = 0, shared: bool = False,
+             max_total_draws: int = 0, pool=None) -> Estimate:
+    """MLMC estimate of E[AB] over the ladder c_0 < c_1 < ... < c_L.
+
+    Fixed-N mode: n_samples gives N_l.  Target mode (rmse_target > 0): `pilot`
+    realisations per level estimate V_l, eq. (28) gives N_l, and every level
+    is extended to max(N_l, pilot) realisations, reusing the pilot ones (the
+    reuse of earlier evaluations in Alg. 2).  `pool` (a ThreadPoolExecutor)
+    runs levels concurrently; each level's arithmetic is unchanged."""
+    L1 = len(c)
+    states = [LevelState.empty(m, p) for _ in range(L1)]
+
+    def run(l, k0, k1):
+        level_estimation(states[l], m, n, p, A, B, c[l], c[l - 1] if l > 0 else 0,
+                         seed, problem, level_field(l, shared), k0, k1)
+
+    def run_all(ranges):
+        if pool is None:
+            for l, (k0, k1) in enumerate(ranges):
+                run(l, k0, k1)
+        else:
+            list(pool.map(lambda a: run(*a), [(l, r[0], r[1]) for l, r in enumerate(ranges)]))
+
+    if rmse_target > 0:
+        if pilot < 2:
+            raise ValueError("target mode needs a pilot of at least 2 realisations")
+        run_all([(0, pilot)] * L1)
+        V = [s.variance for s in states]
+        N = [max(x, pilot) for x in schedule(V, c, rmse_target)]
+        if max_total_draws and sum(x * cl for x, cl in zip(N, c)) > max_total_draws:
+            raise RuntimeError("draw budget exceeded")
+        run_all([(pilot, N[l]) for l in range(L1)])
+    else:
+        if n_samples is None or len(n_samples) != L1:
+            raise ValueError("fixed mode needs one N_l per level")
+        run_all([(0, int(x)) for x in n_samples])
+    means = np.stack([s.mean.reshape(m, p) for s in states])
+    V = np.array([s.variance for s in states])
+    N = np.array([s.count for s in states], dtype=np.int64)
+    rmse = math.sqrt(float(np.sum(V / N)))
+    return Estimate(means.sum(axis=0), means, V, N, rmse)
+
+
+# --------------------------------------------------------------------------
+# Closed forms (Theorem 3.2 with xi = 1/n, specialised to the synthetic laws)
+# --------------------------------------------------------------------------
+def _moments(law: Law):
+    """(E x, E x^2) of one entry of an i.i.d. law."""
+    if law.law == LAW_NORMAL:
+        return law.loc, law.loc ** 2 + law.scale ** 2
+    if law.law == LAW_UNIFORM:
+        return law.loc, law.loc ** 2 + law.scale ** 2 / 3.0
+    raise ValueError("i.i.d. law expected")
+
+
+def closed_form_iid(m: int, n: int, p: int, A: Law, B: Law, c: Sequence[int]):
+    """E[AB] (every entry) and V_l for i.i.d. entries.
+
+    With kappa = E a^2 E b^2 - (E a E b)^2 and the prefix coupling,
+      V_0 = m p (n (n-1) kappa / c_0 + n kappa),
+      V_l = m p n (n-1) kappa (1/c_{l-1} - 1/c_l), l >= 1."""
+    ma, a2 = _moments(A)
+    mb, b2 = _moments(B)
+    kappa = a2 * b2 - (ma * mb) ** 2
+    V = [m * p * (n * (n - 1) * kappa / c[0] + n * kappa)]
+    for l in range(1, len(c)):
+        V.append(m * p * n * (n - 1) * kappa * (1.0 / c[l - 1] - 1.0 / c[l]))
+    return n * ma * mb, np.array(V)
+
+
+def closed_form_reparam(MA, SA, MB, SB, c: Sequence[int]):
+    """E[AB] and V_l for A = MA + SA o Z, B = MB + SB o W (Z, W standard normal).
+
+    With Q = M^2 + S^2 (entrywise),
+      sigma2 = (n-1) QA QB + MA^2 MB^2 - (MA MB)^2   (entrywise squares),
+      V_0 = sum(sigma2 / c_0 + QA QB - MA^2 MB^2),  V_l = (1/c_{l-1} - 1/c_l) sum(sigma2)."""
+    MA, SA, MB, SB = (np.asarray(x, dtype=np.float64) for x in (MA, SA, MB, SB))
+    n = MA.shape[1]
+    QA, QB = MA ** 2 + SA ** 2, MB ** 2 + SB ** 2
+    QQ = QA @ QB
+    MM2 = (MA ** 2) @ (MB ** 2)
+    EAB = MA @ MB
+    sigma2 = (n - 1) * QQ + MM2 - EAB ** 2
+    V = [float(np.sum(sigma2 / c[0] + QQ - MM2))]
+    for l in range(1, len(c)):
+        V.append(float((1.0 / c[l - 1] - 1.0 / c[l]) * np.sum(sigma2)))
+    return EAB, np.array(V)

@@ -1,0 +1,246 @@
+/*
+ * Reference oracle for the multilevel Monte Carlo (MLMC) estimator of E[AB]
+ * of Wu & Polydorides, "A Multilevel Monte Carlo Estimator for Matrix
+ * Multiplication" (arXiv:1904.00429).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is a plain, slow, sequential FP64
+ * implementation used to check the GPU library.  It shares no code with the
+ * HIP path and the product never links it: only the test suite, the smoke
+ * check and the CPU-baseline leg of the benchmark load it.
+ *
+ * What it computes, step by step (f = identity, uniform probabilities):
+ *   - Sec. 2, eq. (4): index probabilities xi_j = 1/n, draws with replacement.
+ *   - Sec. 3, eq. (18): the sketch Z = (n/c) sum_t A[:, r_t] B[r_t, :].
+ *   - Sec. 3.1, Alg. 1 (level_estimation): for every realisation k a pair
+ *     A^(k), B^(k) and c_l indices; the fine sketch uses all c_l indices, the
+ *     coarse sketch uses c_{l-1} of the same indices, and the level sample is
+ *     their difference (at level 0 the fine sketch alone).
+ *   - Sec. 2, eq. (9): the level estimator is the mean of the level samples;
+ *     the per-level variance V_l (Remark 3.6) is the vectorised variance of a
+ *     single level sample, i.e. the sum over entries of the entry variances.
+ *
+ * Readings where the paper is silent (random number generation):
+ *   - Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+ *     easy as 1, 2, 3", SC'11) keyed by the 64-bit seed.
+ *   - Index draw t of sample k: counter (t/2, k, 0, 1<<28 | level<<20 | problem);
+ *     the two words 2(t%2), 2(t%2)+1 form x = hi<<32 | lo and
+ *     r_t = floor(x * n / 2^64).
+ *   - Values of column j of sample k: v = [A^(k)[:, j]; B^(k)[j, :]] of length
+ *     m+p; element e uses word e%4 of Philox(e/4, k, j, 2<<28 | level<<20 | problem).
+ *     The uniform is u = ((w >> 9) + 1/2) 2^-23 (exact in FP32 and FP64);
+ *     pairs (e, e+1), e even, give Box-Muller normals
+ *     z_e = sqrt(-2 ln u_e) cos(2 pi u_{e+1}), z_{e+1} = ... sin(...).
+ *     Values are keyed by the column, so a repeated index reuses the same
+ *     column of the same realisation A^(k), B^(k) (Alg. 1 draws the pair first).
+ *   - The coarse sketch uses the first c_{l-1} of the c_l fine indices.
+ *     Draws are i.i.d., so any fixed subset of c_{l-1} indices has the law the
+ *     paper requires; the prefix nests the levels exactly.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_PHILOX_M0 0xD2511F53u
+#define ORC_PHILOX_M1 0xCD9E8D57u
+#define ORC_PHILOX_W0 0x9E3779B9u
+#define ORC_PHILOX_W1 0xBB67AE85u
+
+#define ORC_TAG_INDEX 1u
+#define ORC_TAG_VALUE 2u
+
+enum { ORC_LAW_NORMAL = 0, ORC_LAW_UNIFORM = 1, ORC_LAW_REPARAM = 2 };
+
+/* Distribution of the entries of A (m x n) or B (n x p).
+ *   NORMAL:  loc + scale * z, z ~ N(0, 1)
+ *   UNIFORM: loc + scale * (2u - 1), u ~ U(0, 1)
+ *   REPARAM: mean[.] + stdev[.] * z; A is column-major (element (i, j) at
+ *            j*ld + i), B is row-major (element (j, q) at j*ld + q). */
+typedef struct {
+    int32_t law;
+    double loc;
+    double scale;
+    const double* mean;
+    const double* stdev;
+    int64_t ld;
+} orc_law;
+
+/* Philox4x32-10: ten rounds of the Philox S-box, the key bumped by the
+ * Weyl constants between rounds (SC'11, Sec. 5). */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)ORC_PHILOX_M0 * (uint64_t)x0;
+        uint64_t p1 = (uint64_t)ORC_PHILOX_M1 * (uint64_t)x2;
+        uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        uint32_t y1 = (uint32_t)p1;
+        uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        uint32_t y3 = (uint32_t)p0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+        k0 += ORC_PHILOX_W0;
+        k1 += ORC_PHILOX_W1;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+void orc_philox_batch(int64_t count, const uint32_t* ctr, uint64_t seed, uint32_t* out)
+{
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    for (int64_t i = 0; i < count; ++i)
+        orc_philox4x32_10(ctr + 4 * i, key, out + 4 * i);
+}
+
+static uint32_t stream_word(uint32_t tag, uint32_t level_field, uint32_t problem)
+{
+    return (tag << 28) | ((level_field & 0xFFu) << 20) | (problem & 0xFFFFFu);
+}
+
+/* Index draw t of realisation k: uniform on {0, ..., n-1}, with replacement
+ * (Sec. 2, eq. (4)).  r = floor(x n / 2^64) from a 64-bit word x. */
+int64_t orc_draw_index(uint64_t seed, uint32_t problem, uint32_t level_field,
+                       uint32_t k, int64_t t, int64_t n)
+{
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    uint32_t ctr[4] = { (uint32_t)(t >> 1), k, 0u,
+                        stream_word(ORC_TAG_INDEX, level_field, problem) };
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+    int h = (int)(t & 1);
+    uint64_t x = ((uint64_t)w[2 * h + 1] << 32) | (uint64_t)w[2 * h];
+    unsigned __int128 prod = (unsigned __int128)x * (unsigned __int128)(uint64_t)n;
+    return (int64_t)(uint64_t)(prod >> 64);
+}
+
+void orc_draw_indices(uint64_t seed, uint32_t problem, uint32_t level_field,
+                      uint32_t k, int64_t c, int64_t n, int64_t* r)
+{
+    for (int64_t t = 0; t < c; ++t)
+        r[t] = orc_draw_index(seed, problem, level_field, k, t, n);
+}
+
+double orc_uniform(uint32_t w)
+{
+    return ((double)(w >> 9) + 0.5) * 0x1p-23;
+}
+
+static uint32_t value_word(uint64_t seed, uint32_t problem, uint32_t level_field,
+                           uint32_t k, int64_t j, int64_t e)
+{
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    uint32_t ctr[4] = { (uint32_t)(e >> 2), k, (uint32_t)j,
+                        stream_word(ORC_TAG_VALUE, level_field, problem) };
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+    return w[e & 3];
+}
+
+/* Standard normal number e of the vector of column j (Box-Muller). */
+static double std_normal(uint64_t seed, uint32_t problem, uint32_t level_field,
+                         uint32_t k, int64_t j, int64_t e)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    int64_t e0 = e & ~(int64_t)1;
+    double u1 = orc_uniform(value_word(seed, problem, level_field, k, j, e0));
+    double u2 = orc_uniform(value_word(seed, problem, level_field, k, j, e0 + 1));
+    double radius = sqrt(-2.0 * log(u1));
+    double angle = two_pi * u2;
+    return (e & 1) ? radius * sin(angle) : radius * cos(angle);
+}
+
+/* Entry (row, col) of one realisation, produced from the element number e of
+ * the column vector v_j. */
+static double law_value(const orc_law* law, uint64_t seed, uint32_t problem,
+                        uint32_t level_field, uint32_t k, int64_t j, int64_t e,
+                        int64_t mat_index)
+{
+    if (law->law == ORC_LAW_UNIFORM) {
+        double u = orc_uniform(value_word(seed, problem, level_field, k, j, e));
+        return law->loc + law->scale * (2.0 * u - 1.0);
+    }
+    double z = std_normal(seed, problem, level_field, k, j, e);
+    if (law->law == ORC_LAW_REPARAM)
+        return law->mean[mat_index] + law->stdev[mat_index] * z;
+    return law->loc + law->scale * z;
+}
+
+/* Column j of A^(k) (length m) and row j of B^(k) (length p). */
+void orc_column(uint64_t seed, uint32_t problem, uint32_t level_field, uint32_t k,
+                int64_t j, int64_t m, int64_t p, const orc_law* A, const orc_law* B,
+                double* a, double* b)
+{
+    for (int64_t i = 0; i < m; ++i)
+        a[i] = law_value(A, seed, problem, level_field, k, j, i, j * A->ld + i);
+    for (int64_t q = 0; q < p; ++q)
+        b[q] = law_value(B, seed, problem, level_field, k, j, m + q, j * B->ld + q);
+}
+
+/* Sketches of Sec. 3, eq. (18) with xi_j = 1/n from gathered columns:
+ *   Zf = (n / c_f) sum_{t < c_f} a_t b_t^T,  Zc = (n / c_c) sum_{t < c_c} a_t b_t^T.
+ * AS holds a_t at AS + t*m, BS holds b_t at BS + t*p.  Z is m x p row-major.
+ * c_c == 0 leaves Zc untouched. */
+void orc_sketch_pair(int64_t m, int64_t p, int64_t n, int64_t c_f, int64_t c_c,
+                     const double* AS, const double* BS, double* Zf, double* Zc)
+{
+    for (int64_t i = 0; i < m; ++i) {
+        for (int64_t q = 0; q < p; ++q) {
+            double sf = 0.0;
+            for (int64_t t = 0; t < c_f; ++t)
+                sf += AS[t * m + i] * BS[t * p + q];
+            Zf[i * p + q] = ((double)n / (double)c_f) * sf;
+            if (c_c > 0) {
+                double sc = 0.0;
+                for (int64_t t = 0; t < c_c; ++t)
+                    sc += AS[t * m + i] * BS[t * p + q];
+                Zc[i * p + q] = ((double)n / (double)c_c) * sc;
+            }
+        }
+    }
+}
+
+/* Alg. 1 (level_estimation) for realisations k_begin <= k < k_end of one
+ * level, f = identity.  Level sample D = Zf - Zc (l > 0) or Zf (l = 0,
+ * c_prev == 0).  Per entry, Welford's running mean/M2 are updated in place, so
+ * a call can continue the samples of an earlier call (Alg. 2 reuses earlier
+ * evaluations).  samples_out (nullable) receives every D, row-major.
+ * Returns 0, or -1 on bad arguments / allocation failure. */
+int orc_level_estimation(int64_t m, int64_t n, int64_t p, const orc_law* A, const orc_law* B,
+                         int64_t c_l, int64_t c_prev, uint64_t seed, uint32_t problem,
+                         uint32_t level_field, int64_t k_begin, int64_t k_end,
+                         int64_t* count, double* mean, double* m2, double* samples_out)
+{
+    if (m < 1 || p < 1 || n < 1 || c_l < 1 || c_prev < 0 || c_prev > c_l || k_end < k_begin)
+        return -1;
+    int64_t mp = m * p;
+    int64_t* r = (int64_t*)malloc(sizeof(int64_t) * (size_t)c_l);
+    double* AS = (double*)malloc(sizeof(double) * (size_t)(c_l * m));
+    double* BS = (double*)malloc(sizeof(double) * (size_t)(c_l * p));
+    double* Zf = (double*)malloc(sizeof(double) * (size_t)mp);
+    double* Zc = (double*)malloc(sizeof(double) * (size_t)mp);
+    if (!r || !AS || !BS || !Zf || !Zc) {
+        free(r); free(AS); free(BS); free(Zf); free(Zc);
+        return -1;
+    }
+    for (int64_t k = k_begin; k < k_end; ++k) {
+        /* Sample c_l indices uniformly, then read the sampled columns of the
+         * realisation A^(k), B^(k). */
+        orc_draw_indices(seed, problem, level_field, (uint32_t)k, c_l, n, r);
+        for (int64_t t = 0; t < c_l; ++t)
+            orc_column(seed, problem, level_field, (uint32_t)k, r[t], m, p, A, B,
+                       AS + t * m, BS + t * p);
+        orc_sketch_pair(m, p, n, c_l, c_prev, AS, BS, Zf, Zc);
+        *count += 1;
+        double cnt = (double)(*count);
+        for (int64_t e = 0; e < mp; ++e) {
+            double d = (c_prev > 0) ? Zf[e] - Zc[e] : Zf[e];
+            if (samples_out)
+                samples_out[(k - k_begin) * mp + e] = d;
+            double delta = d - mean[e];
+            mean[e] += delta / cnt;
+            m2[e] += delta * (d - mean[e]);
+        }
+    }
+    free(r); free(AS); free(BS); free(Zf); free(Zc);
+    return 0;
+}
