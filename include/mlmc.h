@@ -1,0 +1,177 @@
+/*
+ * mlmc.h -- C ABI of the MI355X (gfx950) library for the multilevel Monte
+ * Carlo estimator of E[AB] and E[x^T y] by uniform-probability sketching
+ * (Wu & Polydorides, "A Multilevel Monte Carlo Estimator for Matrix
+ * Multiplication", arXiv:1904.00429).
+ *
+ * The problem (Sec. 3): A (m x n) and B (n x p) are random matrices with
+ * known entry laws; n is large.  Estimate E[AB] by
+ *   Y = sum_{l=0}^{L} Ybar_l                                      (eq. (10))
+ *   Ybar_l = (1/N_l) sum_k (Z_l^(k) - Z_{l-1}^(k)),  Ybar_0 = mean_k Z_0^(k)   (eq. (9))
+ * where Z_l^(k) = (n / c_l) sum_{t < c_l} A^(k)[:, r_t] B^(k)[r_t, :] is the
+ * sketch of eq. (18) with uniform probabilities (eq. (4)) over c_l indices
+ * drawn with replacement, and Z_{l-1}^(k) reuses c_{l-1} of the same indices
+ * of the same realisation A^(k), B^(k) (Alg. 1).  The coarse sketch takes the
+ * first c_{l-1} indices.  N_l is given, or chosen by eq. (28) (Remark 3.6)
+ * for a target RMSE.  The inner product (Sec. 2) is the m = p = 1 case.
+ *
+ * Conventions for every entry point:
+ *   - All device pointers are allocated by the caller; the library never
+ *     allocates device memory.  Scratch comes in through `workspace`, whose
+ *     size in bytes is given by the matching *_workspace_size call.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on
+ *     it.  A call returns after enqueueing, except that the target-RMSE mode
+ *     and a non-NULL `report` synchronise the stream (the scheduler and the
+ *     report need level statistics on the host).
+ *   - No exception crosses the ABI.  A non-zero mlmc_status is returned and a
+ *     thread-local message is available from mlmc_last_error().  On MLMC_EINVAL
+ *     and MLMC_EWORKSPACE nothing has been enqueued.
+ *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by `seed`.
+ *     Index draw t of realisation k at level l uses counter
+ *     (t/2, k, 0, 1<<28 | l<<20 | problem); element e of the column vector
+ *     [A^(k)[:, j]; B^(k)[j, :]] uses word e%4 of counter
+ *     (e/4, k, j, 2<<28 | l<<20 | problem).  With MLMC_FLAG_SHARED_SAMPLES
+ *     every level uses l = 0xFF (realisations and indices shared by all
+ *     levels; for testing the telescoping identity).
+ */
+#ifndef MLMC_H
+#define MLMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MLMC_OK = 0,
+    MLMC_EINVAL = 1,      /* invalid argument (sizes, ladder, null pointer, mode) */
+    MLMC_EDEVICE = 2,     /* a HIP runtime call failed */
+    MLMC_EBUDGET = 3,     /* the scheduled sum_l N_l c_l exceeds max_total_draws */
+    MLMC_EWORKSPACE = 4   /* workspace missing or smaller than required */
+} mlmc_status;
+
+typedef enum {
+    MLMC_LAW_NORMAL = 0,  /* loc + scale * N(0, 1), i.i.d. entries */
+    MLMC_LAW_UNIFORM = 1, /* loc + scale * U(-1, 1), i.i.d. entries */
+    MLMC_LAW_REPARAM = 2  /* mean + stdev (entrywise) * N(0, 1) */
+} mlmc_law;
+
+typedef enum {
+    MLMC_PREC_FP64 = 0,   /* values, products and sums in FP64 */
+    MLMC_PREC_FP32 = 1,   /* values and contraction in FP32, statistics FP64 */
+    MLMC_PREC_BF16 = 2    /* gathered operands BF16 (RNE), FP32 accumulation (MFMA) */
+} mlmc_prec;
+
+#define MLMC_FLAG_SHARED_SAMPLES 1u
+#define MLMC_FLAG_TIMING 2u       /* time every kernel launch with HIP events on `stream` */
+#define MLMC_MAX_LEVELS 32
+
+/* Kernel classes of mlmc_report.kernel_ms (MLMC_FLAG_TIMING). */
+#define MLMC_KERNEL_SAMPLE 0      /* level sampling: inner-product level kernel, matrix sketch kernel */
+#define MLMC_KERNEL_GATHER 1      /* generation of the sampled columns (matrix product) */
+#define MLMC_KERNEL_MERGE 2       /* merge of partial statistics into the level state */
+#define MLMC_KERNEL_FINAL 3       /* level variances, telescoping sum, resets */
+#define MLMC_KERNEL_CLASSES 4
+
+/* Entry law of A (m x n) or B (n x p).  For MLMC_LAW_REPARAM, `mean` and
+ * `stdev` are FP32 device arrays: for A column-major (entry (i, j) at
+ * j*ld + i, ld >= m), for B row-major (entry (j, q) at j*ld + q, ld >= p);
+ * for the inner product x and y are vectors (ld ignored, entry j at j). */
+typedef struct {
+    int32_t law;          /* mlmc_law */
+    double loc;
+    double scale;
+    const float* mean;
+    const float* stdev;
+    int64_t ld;
+} mlmc_dist;
+
+/* The level ladder and the sampling mode (Alg. 2 with a fixed finest level).
+ *   c[l]: indices per realisation at level l (host array, num_levels entries);
+ *         c[0] >= 1 and c[l] an integer multiple >= 2 of c[l-1].
+ *   Fixed mode: n_samples[l] = N_l >= 1 (host array), rmse_target = 0.
+ *   Target mode: n_samples = NULL, rmse_target = eps > 0 (total Frobenius
+ *         RMSE: E||Y - E[AB]||_F^2 <= eps^2); pilot_samples >= 2 realisations
+ *         per level estimate V_l, eq. (28) gives N_l, each level is extended
+ *         to max(N_l, pilot_samples) reusing the pilot realisations.
+ *   max_total_draws: 0, or a cap on sum_l N_l c_l (MLMC_EBUDGET if exceeded;
+ *         checked before the extension is enqueued). */
+typedef struct {
+    int32_t num_levels;
+    const int64_t* c;
+    const int64_t* n_samples;
+    double rmse_target;
+    int64_t pilot_samples;
+    int64_t max_total_draws;
+    uint64_t seed;
+    int32_t prec;         /* mlmc_prec */
+    uint32_t flags;       /* MLMC_FLAG_* */
+    uint32_t problem;     /* stream id < 2^20 (independent problems, same seed) */
+} mlmc_levels;
+
+/* Filled when a non-NULL report is passed (synchronises the stream). */
+typedef struct {
+    int64_t n_used[MLMC_MAX_LEVELS];     /* N_l actually used */
+    double level_var[MLMC_MAX_LEVELS];   /* V_l: vectorised variance of one level sample */
+    double rmse_est;                     /* sqrt(sum_l V_l / N_l) */
+    int64_t total_draws;                 /* sum_l N_l c_l */
+    double kernel_ms[MLMC_KERNEL_CLASSES];        /* MLMC_FLAG_TIMING: summed device time */
+    int64_t kernel_launches[MLMC_KERNEL_CLASSES]; /* MLMC_FLAG_TIMING: launches per class */
+} mlmc_report;
+
+/* Bytes of device workspace needed by mlmc_matmul_estimate / inner product. */
+size_t mlmc_matmul_workspace_size(int64_t m, int64_t n, int64_t p, const mlmc_levels* levels);
+size_t mlmc_inner_product_workspace_size(int64_t n, const mlmc_levels* levels);
+
+/* MLMC estimate of E[AB] (Sec. 3, Alg. 1 and Alg. 2, f = identity).
+ *   out:         device FP64, m x p row-major, receives Y = sum_l Ybar_l.
+ *   level_means: NULL, or device FP64 (num_levels x m x p) receiving Ybar_l.
+ * Errors: EINVAL (m, n, p < 1; n >= 2^32; bad ladder; bad mode; null
+ * pointers; reparam without mean/stdev), EWORKSPACE, EBUDGET, EDEVICE. */
+mlmc_status mlmc_matmul_estimate(int64_t m, int64_t n, int64_t p, const mlmc_dist* A,
+                                 const mlmc_dist* B, const mlmc_levels* levels, double* out,
+                                 double* level_means, void* workspace, size_t workspace_bytes,
+                                 mlmc_report* report, void* stream);
+
+/* MLMC estimate of E[x^T y] for random x, y of length n (Sec. 2; the m = p = 1
+ * case of the matrix estimator).  out: device FP64 scalar.  level_means: NULL
+ * or device FP64 [num_levels].  prec: FP64 or FP32.  Errors as above. */
+mlmc_status mlmc_inner_product_estimate(int64_t n, const mlmc_dist* x, const mlmc_dist* y,
+                                        const mlmc_levels* levels, double* out,
+                                        double* level_means, void* workspace,
+                                        size_t workspace_bytes, mlmc_report* report,
+                                        void* stream);
+
+/* ---- Building blocks, exported for testing ------------------------------ */
+
+/* Philox4x32-10 (SC'11) of `count` counters: ctr and out are device arrays of
+ * 4*count uint32; key = (seed mod 2^32, seed >> 32). */
+mlmc_status mlmc_philox4x32_10(int64_t count, const uint32_t* ctr, uint64_t seed, uint32_t* out,
+                               void* stream);
+
+/* Index draws of realisations k0 .. k0+num_samples-1 (uniform on [0, n),
+ * eq. (4)), as the estimators draw them: out is device int32,
+ * num_samples x c row-major.  level_field is l, or 0xFF for shared mode. */
+mlmc_status mlmc_sample_indices(uint64_t seed, uint32_t problem, uint32_t level_field,
+                                uint32_t k0, int64_t num_samples, int64_t c, int64_t n,
+                                int32_t* out, void* stream);
+
+/* The sampled columns a_t = A^(k)[:, r_t] and rows b_t = B^(k)[r_t, :] as the
+ * matrix estimator generates them, converted to FP64: AS is device
+ * num_samples x c x m, BS is num_samples x c x p (row-major).  prec selects
+ * the generator's arithmetic (FP64, or FP32 / BF16 values widened to FP64). */
+mlmc_status mlmc_gather_columns(int64_t m, int64_t n, int64_t p, const mlmc_dist* A,
+                                const mlmc_dist* B, uint64_t seed, uint32_t problem,
+                                uint32_t level_field, uint32_t k0, int64_t num_samples,
+                                int64_t c, int32_t prec, double* AS, double* BS, void* stream);
+
+const char* mlmc_status_string(mlmc_status status);
+const char* mlmc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLMC_H */

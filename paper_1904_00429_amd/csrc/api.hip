@@ -1,0 +1,438 @@
+// C ABI of the MLMC library: validation, workspace layout, and the driver of
+// Alg. 2 for a fixed finest level L (fixed N_l, or pilot -> eq. (28) ->
+// extension for a target RMSE).
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "mlmc.h"
+
+using namespace mlmc;
+
+namespace {
+
+thread_local std::string g_last_error;
+thread_local std::vector<hipEvent_t> g_event_pool;
+
+mlmc_status fail(mlmc_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+mlmc_status device_fail(hipError_t e, const char* what)
+{
+    return fail(MLMC_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr int64_t kU32 = int64_t(1) << 32;
+
+mlmc_status check_levels(const mlmc_levels* lv, bool inner)
+{
+    if (!lv) return fail(MLMC_EINVAL, "levels is NULL");
+    if (lv->num_levels < 1 || lv->num_levels > MLMC_MAX_LEVELS)
+        return fail(MLMC_EINVAL, "num_levels must be in [1, %d]", MLMC_MAX_LEVELS);
+    if (!lv->c) return fail(MLMC_EINVAL, "ladder c is NULL");
+    if (lv->c[0] < 1) return fail(MLMC_EINVAL, "c[0] must be >= 1");
+    for (int l = 1; l < lv->num_levels; ++l) {
+        if (lv->c[l] < 2 * lv->c[l - 1] || lv->c[l] % lv->c[l - 1] != 0)
+            return fail(MLMC_EINVAL, "c[%d] = %lld is not an integer multiple >= 2 of c[%d] = %lld", l,
+                        (long long)lv->c[l], l - 1, (long long)lv->c[l - 1]);
+    }
+    if (lv->c[lv->num_levels - 1] >= kU32) return fail(MLMC_EINVAL, "c_L must be < 2^32");
+    if (lv->prec < MLMC_PREC_FP64 || lv->prec > (inner ? MLMC_PREC_FP32 : MLMC_PREC_BF16))
+        return fail(MLMC_EINVAL, "unsupported precision %d", lv->prec);
+    if (lv->problem >= (1u << 20)) return fail(MLMC_EINVAL, "problem id must be < 2^20");
+    if (lv->rmse_target > 0.0) {
+        if (lv->n_samples) return fail(MLMC_EINVAL, "give either n_samples or rmse_target, not both");
+        if (lv->pilot_samples < 2 || lv->pilot_samples >= kU32)
+            return fail(MLMC_EINVAL, "target mode needs 2 <= pilot_samples < 2^32");
+        if (!isfinite(lv->rmse_target)) return fail(MLMC_EINVAL, "rmse_target must be finite");
+    } else {
+        if (!lv->n_samples) return fail(MLMC_EINVAL, "fixed mode needs n_samples (or rmse_target > 0)");
+        for (int l = 0; l < lv->num_levels; ++l)
+            if (lv->n_samples[l] < 1 || lv->n_samples[l] >= kU32)
+                return fail(MLMC_EINVAL, "n_samples[%d] must be in [1, 2^32)", l);
+    }
+    if (lv->max_total_draws < 0) return fail(MLMC_EINVAL, "max_total_draws must be >= 0");
+    return MLMC_OK;
+}
+
+mlmc_status check_dist(const mlmc_dist* d, const char* name, int64_t min_ld, bool inner)
+{
+    if (!d) return fail(MLMC_EINVAL, "%s is NULL", name);
+    if (d->law < MLMC_LAW_NORMAL || d->law > MLMC_LAW_REPARAM) return fail(MLMC_EINVAL, "%s: unknown law", name);
+    if (d->law == MLMC_LAW_REPARAM) {
+        if (!d->mean || !d->stdev) return fail(MLMC_EINVAL, "%s: reparam law needs mean and stdev", name);
+        if (!inner && d->ld < min_ld) return fail(MLMC_EINVAL, "%s: ld must be >= %lld", name, (long long)min_ld);
+    } else if (!isfinite(d->loc) || !isfinite(d->scale)) {
+        return fail(MLMC_EINVAL, "%s: loc and scale must be finite", name);
+    }
+    return MLMC_OK;
+}
+
+Law to_law(const mlmc_dist& d)
+{
+    Law l;
+    l.kind = d.law;
+    l.loc = d.loc;
+    l.scale = d.scale;
+    l.mean = d.mean;
+    l.stdev = d.stdev;
+    l.ld = d.ld;
+    return l;
+}
+
+StreamKeys keys_of(const mlmc_levels* lv)
+{
+    StreamKeys k;
+    k.key0 = (uint32_t)lv->seed;
+    k.key1 = (uint32_t)(lv->seed >> 32);
+    k.problem = lv->problem;
+    return k;
+}
+
+// eq. (28): N_l = ceil(2 eps^-2 sqrt(V_l / C_l) sum_j sqrt(V_j C_j)), C_l = c_l.
+mlmc_status schedule(const mlmc_levels* lv, const double* var, int64_t* n_out)
+{
+    const double eps = lv->rmse_target;
+    double total = 0.0;
+    for (int l = 0; l < lv->num_levels; ++l) total += sqrt(var[l] * (double)lv->c[l]);
+    for (int l = 0; l < lv->num_levels; ++l) {
+        const double nl = ceil(2.0 / (eps * eps) * sqrt(var[l] / (double)lv->c[l]) * total);
+        if (!(nl < (double)kU32))
+            return fail(MLMC_EBUDGET, "scheduled N_%d = %g exceeds the realisation counter range", l, nl);
+        int64_t v = (int64_t)nl;
+        if (v < lv->pilot_samples) v = lv->pilot_samples;
+        n_out[l] = v;
+    }
+    if (lv->max_total_draws > 0) {
+        double draws = 0.0;
+        for (int l = 0; l < lv->num_levels; ++l) draws += (double)n_out[l] * (double)lv->c[l];
+        if (draws > (double)lv->max_total_draws)
+            return fail(MLMC_EBUDGET, "scheduled draws %.6g exceed max_total_draws %lld", draws,
+                        (long long)lv->max_total_draws);
+    }
+    return MLMC_OK;
+}
+
+void fill_report(const mlmc_levels* lv, const int64_t* counts, const double* var, const KernelTimer* timer,
+                 mlmc_report* rep)
+{
+    for (int i = 0; i < MLMC_KERNEL_CLASSES; ++i) {
+        rep->kernel_ms[i] = 0.0;
+        rep->kernel_launches[i] = 0;
+    }
+    if (timer) timer->collect(rep->kernel_ms, rep->kernel_launches);
+    double s = 0.0;
+    int64_t draws = 0;
+    for (int l = 0; l < MLMC_MAX_LEVELS; ++l) {
+        rep->n_used[l] = l < lv->num_levels ? counts[l] : 0;
+        rep->level_var[l] = l < lv->num_levels ? var[l] : 0.0;
+    }
+    for (int l = 0; l < lv->num_levels; ++l) {
+        s += var[l] / (double)counts[l];
+        draws += counts[l] * lv->c[l];
+    }
+    rep->rmse_est = sqrt(s);
+    rep->total_draws = draws;
+}
+
+LevelRange range_of(const mlmc_levels* lv, int l, int64_t k_begin, int64_t count)
+{
+    LevelRange r;
+    r.level = l;
+    r.level_field = (lv->flags & MLMC_FLAG_SHARED_SAMPLES) ? 0xFFu : (uint32_t)l;
+    r.c = lv->c[l];
+    r.c_prev = l > 0 ? lv->c[l - 1] : 0;
+    r.k_begin = k_begin;
+    r.count = count;
+    return r;
+}
+
+// Inner-product workspace: per-level Moments, workgroup partials, V_l.
+struct InnerLayout {
+    size_t off_state, off_partials, off_var, total;
+};
+
+InnerLayout inner_layout(int num_levels)
+{
+    InnerLayout L;
+    auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    L.off_state = 0;
+    L.off_partials = align(sizeof(Moments) * num_levels);
+    L.off_var = align(L.off_partials + sizeof(Moments) * inner_partials_capacity());
+    L.total = align(L.off_var + sizeof(double) * num_levels);
+    return L;
+}
+
+}  // namespace
+
+namespace mlmc {
+
+void KernelTimer::begin(int cls)
+{
+    open_cls_ = -1;
+    if (used_ >= sizeof(classes_) / sizeof(classes_[0])) return;
+    while (g_event_pool.size() < 2 * (used_ + 1)) {
+        hipEvent_t ev;
+        if (hipEventCreate(&ev) != hipSuccess) return;
+        g_event_pool.push_back(ev);
+    }
+    if (hipEventRecord(g_event_pool[2 * used_], stream_) != hipSuccess) return;
+    open_cls_ = cls;
+}
+
+void KernelTimer::end()
+{
+    if (open_cls_ < 0) return;
+    if (hipEventRecord(g_event_pool[2 * used_ + 1], stream_) == hipSuccess) classes_[used_++] = open_cls_;
+    open_cls_ = -1;
+}
+
+void KernelTimer::collect(double* ms, int64_t* launches) const
+{
+    for (size_t i = 0; i < used_; ++i) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, g_event_pool[2 * i], g_event_pool[2 * i + 1]) != hipSuccess) continue;
+        ms[classes_[i]] += (double)t;
+        launches[classes_[i]] += 1;
+    }
+}
+
+}  // namespace mlmc
+
+extern "C" {
+
+const char* mlmc_status_string(mlmc_status st)
+{
+    switch (st) {
+    case MLMC_OK: return "MLMC_OK";
+    case MLMC_EINVAL: return "MLMC_EINVAL";
+    case MLMC_EDEVICE: return "MLMC_EDEVICE";
+    case MLMC_EBUDGET: return "MLMC_EBUDGET";
+    case MLMC_EWORKSPACE: return "MLMC_EWORKSPACE";
+    }
+    return "unknown mlmc_status";
+}
+
+const char* mlmc_last_error(void) { return g_last_error.c_str(); }
+
+size_t mlmc_inner_product_workspace_size(int64_t n, const mlmc_levels* levels)
+{
+    (void)n;
+    if (!levels || levels->num_levels < 1 || levels->num_levels > MLMC_MAX_LEVELS) return 0;
+    return inner_layout(levels->num_levels).total;
+}
+
+size_t mlmc_matmul_workspace_size(int64_t m, int64_t n, int64_t p, const mlmc_levels* levels)
+{
+    if (check_levels(levels, false) != MLMC_OK || m < 1 || p < 1 || n < 1) return 0;
+    MatmulPlan plan;
+    if (!matmul_plan(m, n, p, levels->prec, levels->num_levels, levels->c, plan)) return 0;
+    return plan.total;
+}
+
+mlmc_status mlmc_inner_product_estimate(int64_t n, const mlmc_dist* x, const mlmc_dist* y,
+                                        const mlmc_levels* lv, double* out, double* level_means,
+                                        void* workspace, size_t workspace_bytes, mlmc_report* report,
+                                        void* stream_ptr)
+{
+    g_last_error.clear();
+    if (n < 1 || n >= kU32) return fail(MLMC_EINVAL, "n must be in [1, 2^32)");
+    mlmc_status st = check_levels(lv, true);
+    if (st != MLMC_OK) return st;
+    if ((st = check_dist(x, "x", 1, true)) != MLMC_OK) return st;
+    if ((st = check_dist(y, "y", 1, true)) != MLMC_OK) return st;
+    if (!out) return fail(MLMC_EINVAL, "out is NULL");
+    const InnerLayout L = inner_layout(lv->num_levels);
+    if (!workspace || workspace_bytes < L.total)
+        return fail(MLMC_EWORKSPACE, "workspace needs %zu bytes", L.total);
+    hipStream_t stream = static_cast<hipStream_t>(stream_ptr);
+    char* ws = static_cast<char*>(workspace);
+    Moments* state = reinterpret_cast<Moments*>(ws + L.off_state);
+    Moments* partials = reinterpret_cast<Moments*>(ws + L.off_partials);
+    double* var_dev = reinterpret_cast<double*>(ws + L.off_var);
+    const Law lx = to_law(*x), ly = to_law(*y);
+    const StreamKeys keys = keys_of(lv);
+    const int L1 = lv->num_levels;
+    std::vector<int64_t> counts(L1, 0);
+    std::vector<double> var(L1, 0.0);
+    KernelTimer timer_obj(stream);
+    KernelTimer* timer = (lv->flags & MLMC_FLAG_TIMING) ? &timer_obj : nullptr;
+    hipError_t e;
+    {
+        ScopedTiming t(timer, MLMC_KERNEL_FINAL);
+        e = fill_doubles(reinterpret_cast<double*>(state), 3 * L1, 0.0, stream);
+    }
+    if (e != hipSuccess) return device_fail(e, "state reset");
+
+    auto run = [&](int l, int64_t k0, int64_t cnt) -> hipError_t {
+        return inner_level_run(range_of(lv, l, k0, cnt), n, lx, ly, lv->prec, keys, partials, state, stream,
+                               timer);
+    };
+    if (lv->rmse_target > 0.0) {
+        for (int l = 0; l < L1; ++l) {
+            if ((e = run(l, 0, lv->pilot_samples)) != hipSuccess) return device_fail(e, "pilot launch");
+            counts[l] = lv->pilot_samples;
+        }
+        {
+            ScopedTiming t(timer, MLMC_KERNEL_FINAL);
+            e = inner_telescope(state, L1, out, nullptr, var_dev, stream);
+        }
+        if (e != hipSuccess) return device_fail(e, "pilot statistics");
+        if ((e = hipMemcpyAsync(var.data(), var_dev, sizeof(double) * L1, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+            (e = hipStreamSynchronize(stream)) != hipSuccess)
+            return device_fail(e, "pilot readback");
+        std::vector<int64_t> target(L1);
+        if ((st = schedule(lv, var.data(), target.data())) != MLMC_OK) return st;
+        for (int l = 0; l < L1; ++l) {
+            if ((e = run(l, counts[l], target[l] - counts[l])) != hipSuccess) return device_fail(e, "extension launch");
+            counts[l] = target[l];
+        }
+    } else {
+        for (int l = 0; l < L1; ++l) {
+            if ((e = run(l, 0, lv->n_samples[l])) != hipSuccess) return device_fail(e, "level launch");
+            counts[l] = lv->n_samples[l];
+        }
+    }
+    {
+        ScopedTiming t(timer, MLMC_KERNEL_FINAL);
+        e = inner_telescope(state, L1, out, level_means, var_dev, stream);
+    }
+    if (e != hipSuccess) return device_fail(e, "telescope");
+    if (report) {
+        if ((e = hipMemcpyAsync(var.data(), var_dev, sizeof(double) * L1, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+            (e = hipStreamSynchronize(stream)) != hipSuccess)
+            return device_fail(e, "report readback");
+        fill_report(lv, counts.data(), var.data(), timer, report);
+    }
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_matmul_estimate(int64_t m, int64_t n, int64_t p, const mlmc_dist* A, const mlmc_dist* B,
+                                 const mlmc_levels* lv, double* out, double* level_means, void* workspace,
+                                 size_t workspace_bytes, mlmc_report* report, void* stream_ptr)
+{
+    g_last_error.clear();
+    if (m < 1 || p < 1 || n < 1) return fail(MLMC_EINVAL, "m, n, p must be >= 1");
+    if (n >= kU32) return fail(MLMC_EINVAL, "n must be < 2^32");
+    mlmc_status st = check_levels(lv, false);
+    if (st != MLMC_OK) return st;
+    if ((st = check_dist(A, "A", m, false)) != MLMC_OK) return st;
+    if ((st = check_dist(B, "B", p, false)) != MLMC_OK) return st;
+    if (!out) return fail(MLMC_EINVAL, "out is NULL");
+    MatmulPlan plan;
+    if (!matmul_plan(m, n, p, lv->prec, lv->num_levels, lv->c, plan))
+        return fail(MLMC_EINVAL, "no launch plan for this shape and precision");
+    if (!workspace || workspace_bytes < plan.total)
+        return fail(MLMC_EWORKSPACE, "workspace needs %zu bytes", plan.total);
+    hipStream_t stream = static_cast<hipStream_t>(stream_ptr);
+    char* ws = static_cast<char*>(workspace);
+    const Law la = to_law(*A), lb = to_law(*B);
+    const StreamKeys keys = keys_of(lv);
+    const int L1 = lv->num_levels;
+    std::vector<int64_t> counts(L1, 0);
+    std::vector<double> var(L1, 0.0);
+    double* var_dev = matmul_level_var_ptr(plan, ws);
+    KernelTimer timer_obj(stream);
+    KernelTimer* timer = (lv->flags & MLMC_FLAG_TIMING) ? &timer_obj : nullptr;
+    hipError_t e;
+    {
+        ScopedTiming t(timer, MLMC_KERNEL_FINAL);
+        e = matmul_reset(plan, ws, stream);
+    }
+    if (e != hipSuccess) return device_fail(e, "state reset");
+
+    auto run = [&](int l, int64_t k0, int64_t cnt, int64_t before) -> hipError_t {
+        return matmul_level_run(plan, range_of(lv, l, k0, cnt), before, la, lb, keys, ws, stream, timer);
+    };
+    if (lv->rmse_target > 0.0) {
+        for (int l = 0; l < L1; ++l) {
+            if ((e = run(l, 0, lv->pilot_samples, 0)) != hipSuccess) return device_fail(e, "pilot launch");
+            counts[l] = lv->pilot_samples;
+        }
+        {
+            ScopedTiming t(timer, MLMC_KERNEL_FINAL);
+            e = matmul_finalize(plan, counts.data(), ws, out, nullptr, stream);
+        }
+        if (e != hipSuccess) return device_fail(e, "pilot statistics");
+        if ((e = hipMemcpyAsync(var.data(), var_dev, sizeof(double) * L1, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+            (e = hipStreamSynchronize(stream)) != hipSuccess)
+            return device_fail(e, "pilot readback");
+        std::vector<int64_t> target(L1);
+        if ((st = schedule(lv, var.data(), target.data())) != MLMC_OK) return st;
+        for (int l = 0; l < L1; ++l) {
+            if ((e = run(l, counts[l], target[l] - counts[l], counts[l])) != hipSuccess)
+                return device_fail(e, "extension launch");
+            counts[l] = target[l];
+        }
+    } else {
+        for (int l = 0; l < L1; ++l) {
+            if ((e = run(l, 0, lv->n_samples[l], 0)) != hipSuccess) return device_fail(e, "level launch");
+            counts[l] = lv->n_samples[l];
+        }
+    }
+    {
+        ScopedTiming t(timer, MLMC_KERNEL_FINAL);
+        e = matmul_finalize(plan, counts.data(), ws, out, level_means, stream);
+    }
+    if (e != hipSuccess) return device_fail(e, "finalize");
+    if (report) {
+        if ((e = hipMemcpyAsync(var.data(), var_dev, sizeof(double) * L1, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+            (e = hipStreamSynchronize(stream)) != hipSuccess)
+            return device_fail(e, "report readback");
+        fill_report(lv, counts.data(), var.data(), timer, report);
+    }
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_philox4x32_10(int64_t count, const uint32_t* ctr, uint64_t seed, uint32_t* out, void* stream)
+{
+    g_last_error.clear();
+    if (count < 0 || (count > 0 && (!ctr || !out))) return fail(MLMC_EINVAL, "bad philox arguments");
+    hipError_t e = philox_batch(count, ctr, (uint32_t)seed, (uint32_t)(seed >> 32), out,
+                                static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? MLMC_OK : device_fail(e, "philox launch");
+}
+
+mlmc_status mlmc_sample_indices(uint64_t seed, uint32_t problem, uint32_t level_field, uint32_t k0,
+                                int64_t num_samples, int64_t c, int64_t n, int32_t* out, void* stream)
+{
+    g_last_error.clear();
+    if (num_samples < 0 || c < 1 || c >= kU32 || n < 1 || n >= kU32 || (num_samples > 0 && !out) ||
+        problem >= (1u << 20) || level_field > 0xFFu || (int64_t)k0 + num_samples > kU32)
+        return fail(MLMC_EINVAL, "bad sample_indices arguments");
+    StreamKeys keys{(uint32_t)seed, (uint32_t)(seed >> 32), problem};
+    hipError_t e = sample_indices(keys, level_field, k0, num_samples, c, n, out, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? MLMC_OK : device_fail(e, "sample_indices launch");
+}
+
+mlmc_status mlmc_gather_columns(int64_t m, int64_t n, int64_t p, const mlmc_dist* A, const mlmc_dist* B,
+                                uint64_t seed, uint32_t problem, uint32_t level_field, uint32_t k0,
+                                int64_t num_samples, int64_t c, int32_t prec, double* AS, double* BS,
+                                void* stream)
+{
+    g_last_error.clear();
+    if (m < 1 || p < 1 || n < 1 || n >= kU32 || c < 1 || c >= kU32 || num_samples < 0 || !AS || !BS ||
+        prec < MLMC_PREC_FP64 || prec > MLMC_PREC_BF16 || problem >= (1u << 20) || level_field > 0xFFu)
+        return fail(MLMC_EINVAL, "bad gather_columns arguments");
+    mlmc_status st;
+    if ((st = check_dist(A, "A", m, false)) != MLMC_OK) return st;
+    if ((st = check_dist(B, "B", p, false)) != MLMC_OK) return st;
+    StreamKeys keys{(uint32_t)seed, (uint32_t)(seed >> 32), problem};
+    hipError_t e = gather_columns_f64(m, n, p, to_law(*A), to_law(*B), keys, level_field, k0, num_samples, c, prec,
+                                      AS, BS, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? MLMC_OK : device_fail(e, "gather_columns launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Building blocks exported for testing: raw Philox words, the index draws and
+// the sampled columns exactly as the estimators produce them.
+#include <hip/hip_bf16.h>
+
+#include "internal.hpp"
+
+namespace mlmc {
+
+__global__ void philox_batch_kernel(int64_t count, const uint32_t* ctr, uint32_t key0, uint32_t key1,
+                                    uint32_t* out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const Words4 w = philox4x32_10(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], key0, key1);
+    out[4 * i] = w.w0;
+    out[4 * i + 1] = w.w1;
+    out[4 * i + 2] = w.w2;
+    out[4 * i + 3] = w.w3;
+}
+
+__global__ void sample_indices_kernel(uint32_t key0, uint32_t key1, uint32_t sid_index, uint32_t k0,
+                                      int64_t num_samples, int64_t c, uint32_t n, int32_t* out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t pairs = (c + 1) / 2;
+    if (i >= num_samples * pairs) return;
+    const int64_t s = i / pairs;
+    const uint32_t q = (uint32_t)(i % pairs);
+    uint32_t r0, r1;
+    draw_index_pair(q, k0 + (uint32_t)s, sid_index, key0, key1, n, r0, r1);
+    out[s * c + 2 * q] = (int32_t)r0;
+    if (2 * (int64_t)q + 1 < c) out[s * c + 2 * q + 1] = (int32_t)r1;
+}
+
+template <typename Compute, bool ROUND_BF16>
+__global__ void gather_f64_kernel(int64_t m, int64_t p, uint32_t n, Law A, Law B, uint32_t key0,
+                                  uint32_t key1, uint32_t sid_index, uint32_t sid_value, uint32_t k0,
+                                  int64_t num_samples, int64_t c, double* AS, double* BS)
+{
+    const int64_t quads = ceil_div(m + p, 4);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= num_samples * c * quads) return;
+    const int64_t q = i % quads;
+    const int64_t t = (i / quads) % c;
+    const int64_t s = i / (quads * c);
+    const uint32_t k = k0 + (uint32_t)s;
+    const uint32_t j = draw_index((uint32_t)t, k, sid_index, key0, key1, n);
+    const Words4 w = philox4x32_10((uint32_t)q, k, j, sid_value, key0, key1);
+    const bool normal = A.kind != 1 || B.kind != 1;
+    Compute u[4], z[4];
+    quad_values<Compute>(w, normal, u[0], u[1], u[2], u[3], z[0], z[1], z[2], z[3]);
+    for (int r = 0; r < 4; ++r) {
+        const int64_t e = 4 * q + r;
+        if (e >= m + p) break;
+        Compute v;
+        if (e < m) v = law_value<Compute>(A, z[r], u[r], (int64_t)j * A.ld + e);
+        else v = law_value<Compute>(B, z[r], u[r], (int64_t)j * B.ld + (e - m));
+        double out = (double)v;
+        if (ROUND_BF16) out = (double)(float)(__bf16)(float)v;
+        if (e < m) AS[(s * c + t) * m + e] = out;
+        else BS[(s * c + t) * p + (e - m)] = out;
+    }
+}
+
+hipError_t philox_batch(int64_t count, const uint32_t* ctr, uint32_t key0, uint32_t key1, uint32_t* out,
+                        hipStream_t stream)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(philox_batch_kernel, dim3((unsigned)ceil_div(count, 256)), dim3(256), 0, stream, count,
+                       ctr, key0, key1, out);
+    return hipGetLastError();
+}
+
+hipError_t sample_indices(const StreamKeys& keys, uint32_t level_field, uint32_t k0, int64_t num_samples,
+                          int64_t c, int64_t n, int32_t* out, hipStream_t stream)
+{
+    const int64_t work = num_samples * ((c + 1) / 2);
+    if (work <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sample_indices_kernel, dim3((unsigned)ceil_div(work, 256)), dim3(256), 0, stream,
+                       keys.key0, keys.key1, stream_id(kTagIndex, level_field, keys.problem), k0, num_samples, c,
+                       (uint32_t)n, out);
+    return hipGetLastError();
+}
+
+hipError_t gather_columns_f64(int64_t m, int64_t n, int64_t p, const Law& A, const Law& B,
+                              const StreamKeys& keys, uint32_t level_field, uint32_t k0, int64_t num_samples,
+                              int64_t c, int prec, double* AS, double* BS, hipStream_t stream)
+{
+    const int64_t work = num_samples * c * ceil_div(m + p, 4);
+    if (work <= 0) return hipSuccess;
+    const uint32_t si = stream_id(kTagIndex, level_field, keys.problem);
+    const uint32_t sv = stream_id(kTagValue, level_field, keys.problem);
+    const dim3 grid((unsigned)ceil_div(work, 256));
+    if (prec == 0)
+        hipLaunchKernelGGL((gather_f64_kernel<double, false>), grid, dim3(256), 0, stream, m, p, (uint32_t)n, A, B,
+                           keys.key0, keys.key1, si, sv, k0, num_samples, c, AS, BS);
+    else if (prec == 1)
+        hipLaunchKernelGGL((gather_f64_kernel<float, false>), grid, dim3(256), 0, stream, m, p, (uint32_t)n, A, B,
+                           keys.key0, keys.key1, si, sv, k0, num_samples, c, AS, BS);
+    else
+        hipLaunchKernelGGL((gather_f64_kernel<float, true>), grid, dim3(256), 0, stream, m, p, (uint32_t)n, A, B,
+                           keys.key0, keys.key1, si, sv, k0, num_samples, c, AS, BS);
+    return hipGetLastError();
+}
+
+}  // namespace mlmc

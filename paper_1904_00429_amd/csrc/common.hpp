@@ -1,0 +1,75 @@
+// Shared definitions of the MLMC library (host and device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rng.hpp"
+
+namespace mlmc {
+
+constexpr int kWave = 64;
+
+// Entry law as the kernels see it (mirrors mlmc_dist of the C ABI).
+struct Law {
+    int32_t kind;      // 0 normal, 1 uniform, 2 reparam
+    double loc;
+    double scale;
+    const float* mean;
+    const float* stdev;
+    int64_t ld;
+};
+
+// Welford / Chan statistics of a set of scalars: count, mean, sum of squared
+// deviations.  Merging two sets is exact in exact arithmetic (Chan, Golub,
+// LeVeque 1979) and is evaluated in a fixed order everywhere, so results are
+// bitwise reproducible.
+struct Moments {
+    double n;
+    double mean;
+    double m2;
+};
+
+__host__ __device__ inline Moments chan_merge(Moments a, Moments b)
+{
+    if (b.n == 0.0) return a;
+    if (a.n == 0.0) return b;
+    const double n = a.n + b.n;
+    const double delta = b.mean - a.mean;
+    Moments r;
+    r.n = n;
+    r.mean = a.mean + delta * (b.n / n);
+    r.m2 = a.m2 + b.m2 + delta * delta * (a.n * b.n / n);
+    return r;
+}
+
+// Element e (0-based) of the column vector v_j = [A[:, j]; B[j, :]] from the
+// Philox words of its quad.  Normal elements use the Box-Muller pair
+// (e & ~1, e | 1) of the same quad.
+template <typename T>
+__device__ __forceinline__ T law_value(const Law& law, T z_normal, T u_uniform, int64_t mat_index)
+{
+    if (law.kind == 1) return (T)law.loc + (T)law.scale * ((T)2 * u_uniform - (T)1);
+    if (law.kind == 2) return (T)law.mean[mat_index] + (T)law.stdev[mat_index] * z_normal;
+    return (T)law.loc + (T)law.scale * z_normal;
+}
+
+template <typename T>
+__device__ __forceinline__ void quad_values(const Words4& w, bool need_normal, T& u0, T& u1,
+                                            T& u2, T& u3, T& z0, T& z1, T& z2, T& z3)
+{
+    u0 = unit<T>(w.w0);
+    u1 = unit<T>(w.w1);
+    u2 = unit<T>(w.w2);
+    u3 = unit<T>(w.w3);
+    if (need_normal) {
+        box_muller(u0, u1, z0, z1);
+        box_muller(u2, u3, z2, z3);
+    } else {
+        z0 = z1 = z2 = z3 = (T)0;
+    }
+}
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace mlmc

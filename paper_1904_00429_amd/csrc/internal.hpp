@@ -1,0 +1,104 @@
+// Host-side interfaces between the C ABI layer and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace mlmc {
+
+// One level's sample range as the launchers see it.
+struct LevelRange {
+    int level;             // l
+    uint32_t level_field;  // l, or 0xFF in shared-sample mode
+    int64_t c;             // c_l
+    int64_t c_prev;        // c_{l-1}, 0 at level 0
+    int64_t k_begin;       // first realisation
+    int64_t count;         // number of realisations
+};
+
+// Optional HIP-event timing of kernel launches, by kernel class (the
+// MLMC_KERNEL_* classes of the C ABI).  Events come from a per-thread pool
+// that grows on demand; elapsed times are read after the stream is synced.
+class KernelTimer {
+public:
+    explicit KernelTimer(hipStream_t s) : stream_(s) {}
+    void begin(int cls);
+    void end();
+    // Sums elapsed milliseconds and launch counts per class; the stream must
+    // have been synchronised.
+    void collect(double* ms, int64_t* launches) const;
+
+private:
+    hipStream_t stream_;
+    int open_cls_ = -1;
+    size_t used_ = 0;
+    int classes_[4096];
+};
+
+struct ScopedTiming {
+    ScopedTiming(KernelTimer* t, int cls) : t_(t) { if (t_) t_->begin(cls); }
+    ~ScopedTiming() { if (t_) t_->end(); }
+    KernelTimer* t_;
+};
+
+struct StreamKeys {
+    uint32_t key0, key1;
+    uint32_t problem;
+};
+
+// ---- inner product (m = p = 1) -------------------------------------------
+// Device state per level: one Moments (count, mean, M2) of the level samples.
+size_t inner_partials_capacity();  // Moments slots needed in workspace
+hipError_t inner_level_run(const LevelRange& lr, int64_t n, const Law& x, const Law& y,
+                           int prec, const StreamKeys& keys, Moments* partials,
+                           Moments* level_state, hipStream_t stream, KernelTimer* timer);
+hipError_t inner_telescope(const Moments* level_state, int num_levels, double* out,
+                           double* level_means, double* level_var, hipStream_t stream);
+
+// ---- matrix product --------------------------------------------------------
+struct MatmulPlan {
+    int64_t m, n, p;
+    int prec;
+    int num_levels;
+    int64_t c[32];
+    // launch geometry
+    int kstep;             // K granularity of a contraction step (padding unit)
+    int kpack;             // draws packed per element group in the gathered layout
+    int tile_m, tile_n;    // workgroup output tile
+    int64_t tiles_m, tiles_n;
+    int64_t kpad_max;      // padded draws per realisation at the finest level
+    int64_t batch;         // realisations generated per gather pass
+    int64_t groups_max;    // sample groups per pass
+    int64_t merge_blocks;  // blocks of the per-entry merge
+    // workspace layout (byte offsets)
+    size_t off_means, off_between, off_within, off_var, off_gather_a, off_gather_b,
+        off_part_mean, off_part_m2, total;
+};
+
+bool matmul_plan(int64_t m, int64_t n, int64_t p, int prec, int num_levels, const int64_t* c,
+                 MatmulPlan& plan);
+hipError_t matmul_reset(const MatmulPlan& plan, char* ws, hipStream_t stream);
+hipError_t matmul_level_run(const MatmulPlan& plan, const LevelRange& lr, int64_t done_before,
+                            const Law& A, const Law& B, const StreamKeys& keys, char* ws,
+                            hipStream_t stream, KernelTimer* timer);
+hipError_t matmul_finalize(const MatmulPlan& plan, const int64_t* counts, char* ws, double* out,
+                           double* level_means, hipStream_t stream);
+double* matmul_level_var_ptr(const MatmulPlan& plan, char* ws);
+
+hipError_t fill_doubles(double* p, int64_t count, double v, hipStream_t stream);
+
+// ---- building blocks exported for tests -----------------------------------
+hipError_t philox_batch(int64_t count, const uint32_t* ctr, uint32_t key0, uint32_t key1,
+                        uint32_t* out, hipStream_t stream);
+hipError_t sample_indices(const StreamKeys& keys, uint32_t level_field, uint32_t k0,
+                          int64_t num_samples, int64_t c, int64_t n, int32_t* out,
+                          hipStream_t stream);
+hipError_t gather_columns_f64(int64_t m, int64_t n, int64_t p, const Law& A, const Law& B,
+                              const StreamKeys& keys, uint32_t level_field, uint32_t k0,
+                              int64_t num_samples, int64_t c, int prec, double* AS, double* BS,
+                              hipStream_t stream);
+
+}  // namespace mlmc

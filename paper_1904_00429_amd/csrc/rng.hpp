@@ -1,0 +1,117 @@
+// Counter-based random numbers for the MLMC sampler (device side).
+//
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy
+// as 1, 2, 3", SC'11): a 128-bit counter is mixed by ten rounds of two 32x32
+// -> 64-bit products and xors with a 64-bit key that is bumped by the Weyl
+// constants between rounds.  Keyed by the user seed, so every random number
+// of an estimate is a pure function of (seed, stream, realisation, position):
+// realisations can be produced in any order, by any work item, and extended
+// later (the target-RMSE mode reuses its pilot realisations).
+//
+// Stream layout (word 3 of the counter): tag << 28 | level << 20 | problem.
+//   tag 1, index stream:  counter (t / 2, k, 0, .) -> draws t, t+1 of realisation k
+//   tag 2, value stream:  counter (e / 4, k, j, .) -> elements e..e+3 of column j
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mlmc {
+
+constexpr uint32_t kTagIndex = 1u;
+constexpr uint32_t kTagValue = 2u;
+
+struct Words4 {
+    uint32_t w0, w1, w2, w3;
+};
+
+__host__ __device__ inline uint32_t stream_id(uint32_t tag, uint32_t level_field, uint32_t problem)
+{
+    return (tag << 28) | ((level_field & 0xFFu) << 20) | (problem & 0xFFFFFu);
+}
+
+// One Philox4x32-10 evaluation.  The key schedule depends only on the seed,
+// which is uniform across a launch, so it stays in scalar registers.
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t prod_a = (uint64_t)0xD2511F53u * c0;
+        const uint64_t prod_b = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(prod_b >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(prod_a >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)prod_b;
+        c3 = (uint32_t)prod_a;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Words4{c0, c1, c2, c3};
+}
+
+// Uniform index in [0, n) from a 64-bit word x = hi:lo, r = floor(x n / 2^64),
+// evaluated exactly in 64-bit arithmetic for n < 2^32.
+__device__ __forceinline__ uint32_t index_from_words(uint32_t lo, uint32_t hi, uint32_t n)
+{
+    const uint64_t low_part = ((uint64_t)lo * n) >> 32;
+    return (uint32_t)(((uint64_t)hi * n + low_part) >> 32);
+}
+
+// Both draws 2q and 2q+1 of realisation k.
+__device__ __forceinline__ void draw_index_pair(uint32_t q, uint32_t k, uint32_t sid_index,
+                                                uint32_t key0, uint32_t key1, uint32_t n,
+                                                uint32_t& r_even, uint32_t& r_odd)
+{
+    const Words4 w = philox4x32_10(q, k, 0u, sid_index, key0, key1);
+    r_even = index_from_words(w.w0, w.w1, n);
+    r_odd = index_from_words(w.w2, w.w3, n);
+}
+
+__device__ __forceinline__ uint32_t draw_index(uint32_t t, uint32_t k, uint32_t sid_index,
+                                               uint32_t key0, uint32_t key1, uint32_t n)
+{
+    const Words4 w = philox4x32_10(t >> 1, k, 0u, sid_index, key0, key1);
+    return (t & 1u) ? index_from_words(w.w2, w.w3, n) : index_from_words(w.w0, w.w1, n);
+}
+
+// u = ((w >> 9) + 1/2) 2^-23: 2^23 equally spaced points in (0, 1), exactly
+// representable in FP32 and FP64, never 0 or 1.
+__device__ __forceinline__ float unit_f32(uint32_t w)
+{
+    return ((float)(w >> 9) + 0.5f) * 0x1p-23f;
+}
+
+__device__ __forceinline__ double unit_f64(uint32_t w)
+{
+    return ((double)(w >> 9) + 0.5) * 0x1p-23;
+}
+
+// Box-Muller pair from two uniforms: (rho cos 2 pi v, rho sin 2 pi v),
+// rho = sqrt(-2 ln u).  FP32 uses the hardware transcendental units:
+// v_log_f32 gives log2, v_sin/v_cos take their argument in revolutions.
+__device__ __forceinline__ void box_muller(float u, float v, float& z0, float& z1)
+{
+    const float rho = __builtin_sqrtf(-2.0f * 0.69314718055994530942f * __builtin_amdgcn_logf(u));
+    z0 = rho * __builtin_amdgcn_cosf(v);
+    z1 = rho * __builtin_amdgcn_sinf(v);
+}
+
+__device__ __forceinline__ void box_muller(double u, double v, double& z0, double& z1)
+{
+    const double rho = sqrt(-2.0 * log(u));
+    double s, c;
+    sincos(6.283185307179586476925286766559 * v, &s, &c);
+    z0 = rho * c;
+    z1 = rho * s;
+}
+
+template <typename T>
+__device__ __forceinline__ T unit(uint32_t w);
+template <>
+__device__ __forceinline__ float unit<float>(uint32_t w) { return unit_f32(w); }
+template <>
+__device__ __forceinline__ double unit<double>(uint32_t w) { return unit_f64(w); }
+
+}  // namespace mlmc

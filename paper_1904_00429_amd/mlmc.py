@@ -1,0 +1,199 @@
+"""Python binding of libmlmc (include/mlmc.h): argument marshalling only.
+
+Every step of the estimator runs in the HIP kernels of libmlmc.so; PyTorch
+only provides device memory (outputs, workspace, reparameterised inputs) and
+the stream the work is enqueued on.  There is no CPU fallback: calling into a
+missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import Dist, Levels, MLMCError, Report, check, lib
+
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+FLAG_SHARED_SAMPLES = 1
+SHARED_LEVEL_FIELD = 0xFF
+
+
+@dataclass
+class Law:
+    """Entry law of A (m x n), B (n x p), x or y (length n).
+
+    normal: loc + scale N(0, 1); uniform: loc + scale U(-1, 1);
+    reparam: mean + stdev N(0, 1), entrywise, with FP32 device tensors of shape
+    (n, m) for A (row j = column j of A, i.e. A stored column-major),
+    (n, p) for B (row-major), (n,) for x and y."""
+    kind: int
+    loc: float = 0.0
+    scale: float = 1.0
+    mean: Optional[torch.Tensor] = None
+    stdev: Optional[torch.Tensor] = None
+
+    @staticmethod
+    def normal(loc: float, scale: float) -> "Law":
+        return Law(0, float(loc), float(scale))
+
+    @staticmethod
+    def uniform(loc: float, scale: float) -> "Law":
+        return Law(1, float(loc), float(scale))
+
+    @staticmethod
+    def reparam(mean: torch.Tensor, stdev: torch.Tensor) -> "Law":
+        if mean.dtype != torch.float32 or stdev.dtype != torch.float32:
+            raise TypeError("reparam mean/stdev must be float32")
+        if mean.shape != stdev.shape or not mean.is_contiguous() or not stdev.is_contiguous():
+            raise ValueError("reparam mean/stdev must be contiguous and of the same shape")
+        if not mean.is_cuda:
+            raise ValueError("reparam mean/stdev must be device tensors")
+        return Law(2, 0.0, 0.0, mean, stdev)
+
+    def c(self) -> Dist:
+        d = Dist()
+        d.law = self.kind
+        d.loc = self.loc
+        d.scale = self.scale
+        if self.kind == 2:
+            d.mean = self.mean.data_ptr()
+            d.stdev = self.stdev.data_ptr()
+            d.ld = self.mean.shape[1] if self.mean.dim() == 2 else 1
+        return d
+
+
+@dataclass
+class Result:
+    Y: torch.Tensor                        # m x p (or scalar) FP64 on the device
+    level_means: Optional[torch.Tensor]    # (L+1) x m x p, if requested
+    n_used: list
+    level_var: list
+    rmse_est: float
+    total_draws: int
+
+
+class _LevelsHolder:
+    """Keeps the ctypes arrays of a Levels struct alive."""
+
+    def __init__(self, c, n_samples, rmse_target, pilot, seed, prec, shared, problem, max_total_draws):
+        if prec not in PREC:
+            raise ValueError(f"prec must be one of {sorted(PREC)}")
+        self.c = (ctypes.c_int64 * len(c))(*[int(v) for v in c])
+        self.n = None if n_samples is None else (ctypes.c_int64 * len(n_samples))(*[int(v) for v in n_samples])
+        lv = Levels()
+        lv.num_levels = len(c)
+        lv.c = ctypes.cast(self.c, ctypes.POINTER(ctypes.c_int64))
+        lv.n_samples = ctypes.cast(self.n, ctypes.POINTER(ctypes.c_int64)) if self.n is not None else None
+        lv.rmse_target = float(rmse_target)
+        lv.pilot_samples = int(pilot)
+        lv.max_total_draws = int(max_total_draws)
+        lv.seed = int(seed) & (2**64 - 1)
+        lv.prec = PREC[prec]
+        lv.flags = FLAG_SHARED_SAMPLES if shared else 0
+        lv.problem = int(problem)
+        self.lv = lv
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _result(Y, means, rep: Report, num_levels: int) -> Result:
+    return Result(Y, means, [int(rep.n_used[l]) for l in range(num_levels)],
+                  [float(rep.level_var[l]) for l in range(num_levels)], float(rep.rmse_est),
+                  int(rep.total_draws))
+
+
+def matmul_workspace_size(m, n, p, c, prec="fp64", n_samples=None, rmse_target=0.0, pilot=0) -> int:
+    h = _LevelsHolder(c, n_samples, rmse_target, pilot, 0, prec, False, 0, 0)
+    return int(lib().mlmc_matmul_workspace_size(int(m), int(n), int(p), ctypes.byref(h.lv)))
+
+
+def matmul_estimate(m: int, n: int, p: int, A: Law, B: Law, c: Sequence[int],
+                    n_samples: Optional[Sequence[int]] = None, rmse_target: float = 0.0,
+                    pilot: int = 0, seed: int = 0, prec: str = "fp64", shared: bool = False,
+                    problem: int = 0, max_total_draws: int = 0, level_means: bool = False,
+                    report: bool = True, device=None, workspace: Optional[torch.Tensor] = None,
+                    out: Optional[torch.Tensor] = None) -> Result:
+    """MLMC estimate of E[AB] on the GPU (mlmc_matmul_estimate)."""
+    device = torch.device(device or "cuda")
+    h = _LevelsHolder(c, n_samples, rmse_target, pilot, seed, prec, shared, problem, max_total_draws)
+    ws_bytes = int(lib().mlmc_matmul_workspace_size(int(m), int(n), int(p), ctypes.byref(h.lv)))
+    if ws_bytes == 0:
+        raise MLMCError(1, "invalid problem: no workspace size")
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=device)
+    if out is None:
+        out = torch.empty((m, p), dtype=torch.float64, device=device)
+    means = torch.empty((len(c), m, p), dtype=torch.float64, device=device) if level_means else None
+    da, db = A.c(), B.c()
+    rep = Report()
+    check(lib().mlmc_matmul_estimate(int(m), int(n), int(p), ctypes.byref(da), ctypes.byref(db),
+                                     ctypes.byref(h.lv), out.data_ptr(),
+                                     means.data_ptr() if means is not None else None,
+                                     workspace.data_ptr(), ws_bytes,
+                                     ctypes.byref(rep) if report else None, _stream(device)))
+    return _result(out, means, rep, len(c))
+
+
+def inner_product_estimate(n: int, x: Law, y: Law, c: Sequence[int],
+                           n_samples: Optional[Sequence[int]] = None, rmse_target: float = 0.0,
+                           pilot: int = 0, seed: int = 0, prec: str = "fp64", shared: bool = False,
+                           problem: int = 0, max_total_draws: int = 0, level_means: bool = False,
+                           report: bool = True, device=None,
+                           workspace: Optional[torch.Tensor] = None,
+                           out: Optional[torch.Tensor] = None) -> Result:
+    """MLMC estimate of E[x^T y] on the GPU (mlmc_inner_product_estimate)."""
+    device = torch.device(device or "cuda")
+    h = _LevelsHolder(c, n_samples, rmse_target, pilot, seed, prec, shared, problem, max_total_draws)
+    ws_bytes = int(lib().mlmc_inner_product_workspace_size(int(n), ctypes.byref(h.lv)))
+    if ws_bytes == 0:
+        raise MLMCError(1, "invalid problem: no workspace size")
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=device)
+    if out is None:
+        out = torch.empty((), dtype=torch.float64, device=device)
+    means = torch.empty((len(c),), dtype=torch.float64, device=device) if level_means else None
+    dx, dy = x.c(), y.c()
+    rep = Report()
+    check(lib().mlmc_inner_product_estimate(int(n), ctypes.byref(dx), ctypes.byref(dy),
+                                            ctypes.byref(h.lv), out.data_ptr(),
+                                            means.data_ptr() if means is not None else None,
+                                            workspace.data_ptr(), ws_bytes,
+                                            ctypes.byref(rep) if report else None, _stream(device)))
+    return _result(out, means, rep, len(c))
+
+
+def philox(ctr: torch.Tensor, seed: int) -> torch.Tensor:
+    """Philox4x32-10 of device counters (count x 4, int32 holding uint32 bits)."""
+    ctr = ctr.contiguous()
+    out = torch.empty_like(ctr)
+    check(lib().mlmc_philox4x32_10(ctr.shape[0], ctr.data_ptr(), int(seed) & (2**64 - 1),
+                                   out.data_ptr(), _stream(ctr.device)))
+    return out
+
+
+def sample_indices(seed: int, problem: int, level_field: int, k0: int, num_samples: int,
+                   c: int, n: int, device=None) -> torch.Tensor:
+    device = torch.device(device or "cuda")
+    out = torch.empty((num_samples, c), dtype=torch.int32, device=device)
+    check(lib().mlmc_sample_indices(int(seed) & (2**64 - 1), problem, level_field, k0, num_samples,
+                                    c, n, out.data_ptr(), _stream(device)))
+    return out
+
+
+def gather_columns(m: int, n: int, p: int, A: Law, B: Law, seed: int, problem: int,
+                   level_field: int, k0: int, num_samples: int, c: int, prec: str = "fp64",
+                   device=None):
+    """Sampled columns (num_samples x c x m) and rows (num_samples x c x p), FP64."""
+    device = torch.device(device or "cuda")
+    AS = torch.empty((num_samples, c, m), dtype=torch.float64, device=device)
+    BS = torch.empty((num_samples, c, p), dtype=torch.float64, device=device)
+    da, db = A.c(), B.c()
+    check(lib().mlmc_gather_columns(m, n, p, ctypes.byref(da), ctypes.byref(db),
+                                    int(seed) & (2**64 - 1), problem, level_field, k0, num_samples,
+                                    c, PREC[prec], AS.data_ptr(), BS.data_ptr(), _stream(device)))
+    return AS, BS

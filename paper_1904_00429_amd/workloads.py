@@ -1,0 +1,66 @@
+"""Synthetic workloads: shapes, laws, level ladders and seeded inputs.
+
+Holds no arithmetic of the estimator: only the configurations and the seeded
+generators of the inputs that both the GPU path and the oracle receive.
+Every input is synthetic (the paper's own experiments are synthetic too).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+
+@dataclass
+class Workload:
+    name: str
+    kind: str                 # "matmul" or "inner"
+    m: int
+    n: int
+    p: int
+    law_a: tuple              # ("normal"|"uniform", loc, scale) or ("reparam",)
+    law_b: tuple
+    c: list
+    n_samples: Optional[list] = None
+    rmse_target: float = 0.0  # total-Frobenius eps
+    pilot: int = 0
+    prec: str = "fp64"
+    seed: int = 0
+
+
+def ladder(c0: int, levels: int, ratio: int = 2) -> list:
+    return [c0 * ratio ** l for l in range(levels)]
+
+
+# A 64 x 256, B 256 x 64, i.i.d. N(1, 1); c_l = 4 * 2^l, l = 0..3; fixed N_l; FP64.
+MATMUL_SMALL_FP64 = Workload("matmul-64x256x64-fp64", "matmul", 64, 256, 64, ("normal", 1.0, 1.0),
+                             ("normal", 1.0, 1.0), ladder(4, 4), [1000, 500, 250, 125])
+
+# x, y in R^(2^20), i.i.d. 0.5 + U(-1, 1); c_l = 64 * 2^l, l = 0..8;
+# target RMSE eps = 1e-3 |E[x^T y]| with E[x^T y] = n * 0.5 * 0.5.
+_N2 = 2 ** 20
+INNER_2POW20 = Workload("inner-2^20-uniform", "inner", 1, _N2, 1, ("uniform", 0.5, 1.0),
+                        ("uniform", 0.5, 1.0), ladder(64, 9), None, 1e-3 * _N2 * 0.25, 1024, "fp32")
+
+# A 1024 x 65536, B 65536 x 1024, i.i.d. N(0.5, 1); c_l = 32 * 2^l, l = 0..7;
+# eps per entry = 1e-2 ||E[AB]||_F / sqrt(m p) = 1e-2 * n * 0.25; the estimator
+# takes the total-Frobenius eps = sqrt(m p) times that.
+_N3 = 65536
+MATMUL_LARGE = Workload("matmul-1024x65536x1024", "matmul", 1024, _N3, 1024, ("normal", 0.5, 1.0),
+                        ("normal", 0.5, 1.0), ladder(32, 8), None,
+                        1e-2 * _N3 * 0.25 * math.sqrt(1024 * 1024), 64, "bf16")
+
+
+def reparam_inputs(m: int, n: int, p: int, seed: int = 0):
+    """M_A, M_B ~ N(0, 1), S_A, S_B ~ U(0.1, 1), T ~ N(0, 1) (m x p), FP32.
+
+    Returned as A's in (n, m) layout (row j = column j of A) and B's in (n, p)."""
+    rng = np.random.default_rng(seed)
+    MA = rng.standard_normal((n, m), dtype=np.float32)
+    SA = rng.uniform(0.1, 1.0, size=(n, m)).astype(np.float32)
+    MB = rng.standard_normal((n, p), dtype=np.float32)
+    SB = rng.uniform(0.1, 1.0, size=(n, p)).astype(np.float32)
+    T = rng.standard_normal((m, p), dtype=np.float32)
+    return MA, SA, MB, SB, T

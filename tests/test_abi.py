@@ -1,0 +1,119 @@
+"""The C ABI library loads, exports every declared symbol, and rejects bad
+arguments before touching the device (CPU only: no compute call is made)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1904_00429_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1904_00429_amd import build
+        build.build()
+    return _lib.lib()
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "mlmc.h")).read()
+    return sorted(set(re.findall(r"\b(mlmc_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert len(names) >= 9
+    for name in names:
+        assert hasattr(L, name), name
+    from paper_1904_00429_amd import _lib
+    assert sorted(_lib.EXPORTED) == names
+
+
+def test_status_strings(L):
+    for code, name in [(0, b"MLMC_OK"), (1, b"MLMC_EINVAL"), (2, b"MLMC_EDEVICE"),
+                       (3, b"MLMC_EBUDGET"), (4, b"MLMC_EWORKSPACE")]:
+        assert L.mlmc_status_string(code) == name
+
+
+def _levels(c, n_samples=None, eps=0.0, pilot=0, prec=0):
+    from paper_1904_00429_amd._lib import Levels
+    ca = (ctypes.c_int64 * len(c))(*c)
+    lv = Levels()
+    lv.num_levels = len(c)
+    lv.c = ctypes.cast(ca, ctypes.POINTER(ctypes.c_int64))
+    keep = [ca]
+    if n_samples is not None:
+        na = (ctypes.c_int64 * len(n_samples))(*n_samples)
+        lv.n_samples = ctypes.cast(na, ctypes.POINTER(ctypes.c_int64))
+        keep.append(na)
+    lv.rmse_target = eps
+    lv.pilot_samples = pilot
+    lv.prec = prec
+    return lv, keep
+
+
+def _dist(law=0, loc=0.0, scale=1.0):
+    from paper_1904_00429_amd._lib import Dist
+    d = Dist()
+    d.law, d.loc, d.scale = law, loc, scale
+    return d
+
+
+@pytest.mark.parametrize("case", [
+    dict(m=0), dict(p=0), dict(n=0), dict(n=2**32), dict(c=[]), dict(c=[4, 6]), dict(c=[4, 4]),
+    dict(c=[0, 4]), dict(N=[1, 0]), dict(N=None), dict(eps=1.0, pilot=1, N=None),
+    dict(eps=1.0, pilot=10), dict(prec=7), dict(lawA=2), dict(out=False),
+])
+def test_matmul_rejects_invalid(L, case):
+    m, n, p = case.get("m", 4), case.get("n", 16), case.get("p", 3)
+    c = case.get("c", [2, 4])
+    N = case.get("N", [4, 4]) if "N" in case else [4, 4]
+    lv, keep = _levels(c if c else [1], N, case.get("eps", 0.0), case.get("pilot", 0), case.get("prec", 0))
+    if not c:
+        lv.num_levels = 0
+    A = _dist(case.get("lawA", 0))
+    B = _dist()
+    st = L.mlmc_matmul_estimate(m, n, p, ctypes.byref(A), ctypes.byref(B), ctypes.byref(lv),
+                                None if case.get("out", True) is False else 8, None, 16, 1 << 40,
+                                None, None)
+    assert st == 1, L.mlmc_last_error()
+    assert L.mlmc_last_error()
+
+
+def test_workspace_too_small(L):
+    lv, keep = _levels([2, 4], [4, 4])
+    A, B = _dist(), _dist()
+    need = L.mlmc_matmul_workspace_size(4, 16, 3, ctypes.byref(lv))
+    assert need > 0
+    st = L.mlmc_matmul_estimate(4, 16, 3, ctypes.byref(A), ctypes.byref(B), ctypes.byref(lv), 8, None,
+                                16, need - 1, None, None)
+    assert st == 4
+    st = L.mlmc_inner_product_estimate(16, ctypes.byref(A), ctypes.byref(B), ctypes.byref(lv), 8, None,
+                                       None, 0, None, None)
+    assert st == 4
+
+
+def test_inner_rejects_bf16(L):
+    lv, keep = _levels([2, 4], [4, 4], prec=2)
+    A, B = _dist(), _dist()
+    st = L.mlmc_inner_product_estimate(16, ctypes.byref(A), ctypes.byref(B), ctypes.byref(lv), 8, None,
+                                       16, 1 << 30, None, None)
+    assert st == 1
+
+
+def test_workspace_size_scales_with_shape(L):
+    lv, keep = _levels([32, 64, 128], [10, 10, 10], prec=1)
+    small = L.mlmc_matmul_workspace_size(64, 1000, 64, ctypes.byref(lv))
+    big = L.mlmc_matmul_workspace_size(1024, 1000, 1024, ctypes.byref(lv))
+    assert 0 < small < big
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_1904_00429_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        _lib.lib()
