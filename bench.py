@@ -1,0 +1,270 @@
+"""Benchmark: MLMC product estimates/s at fixed RMSE eps on one MI355X.
+
+One step is one whole estimate on synthetic data: pilot realisations on every
+level, the optimal allocation of Remark 3.6 (eq. (28)), the extension of every
+level, the per-level statistics and the telescoping sum (eq. (10)).  Inputs are
+laws, not arrays: every sampled value is generated inside the timed region
+(the method draws its data).
+
+Default workload: x, y in R^(2^20) with i.i.d. 0.5 + U(-1, 1) entries, ladder
+c_l = 64 * 2^l (l = 0..8), eps = 1e-3 |E[x^T y]|, FP32 arithmetic.
+
+Printed: one JSON line with the throughput, the roofline of the dominant
+kernel (device time from HIP events recorded by the library on the stream the
+kernels run on) and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLMC product estimates/s at fixed RMSE eps"
+
+# VALU issue slots per index draw of the inner-product level kernel, counted
+# from the operations the algorithm needs, at gfx950 issue rates (full-rate
+# 32-bit operation = 1 slot; 32x32->64-bit integer multiply-add and 32-bit
+# high multiply are half rate = 2 slots):
+#   1.5 Philox4x32-10 evaluations (half an index call, one value call), each
+#       10 rounds x (2 multiply-adds x 2 + 2 three-input xors x 1) = 60 slots;
+#   index map: 1 shift for a power-of-two n, else high multiply + multiply-add = 4;
+#   two uniform values: shift, convert, fused scale and law map = 4 each;
+#   product and accumulation into the level sum = 2.
+def slots_per_draw_inner(n: int) -> float:
+    index = 1 if n & (n - 1) == 0 else 4
+    return 1.5 * 60 + index + 2 * 4 + 2
+
+
+# MI355X VALU issue: 256 CUs x 128 lanes per clock x 2.4 GHz = 78.6 T lane-ops/s
+# (the 157.3 TFLOP/s FP32 vector peak counts an FMA as two flops).
+PEAK_VALU_SLOTS = 256 * 128 * 2.4e9
+PEAK_MFMA = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15}
+PEAK_HBM = 8.0e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="inner", choices=["inner", "matmul-large", "matmul-small"])
+    ap.add_argument("--prec", default=None, help="fp32 (default) or fp64; bf16 for matmul")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-fraction", type=float, default=0.15,
+                    help="share of every level's realisations the CPU oracle runs")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after timing, run one device copy of 1 GiB (counter calibration)")
+    return ap.parse_args()
+
+
+def cpu_baseline_inner(wl, n_used, fraction):
+    """The oracle (single-threaded C) on the first `fraction` of every level's
+    realisations of the same workload; scaled to estimates/s."""
+    import oracle
+    oracle.build(force=False)
+    law = oracle.Law.uniform(wl.law_a[1], wl.law_a[2])
+    t0 = time.perf_counter()
+    draws = 0
+    for l, N in enumerate(n_used):
+        k = max(2, int(round(N * fraction)))
+        st = oracle.LevelState.empty(1, 1)
+        oracle.level_estimation(st, 1, wl.n, 1, law, law, wl.c[l], wl.c[l - 1] if l else 0, wl.seed, 0, l, 0, k)
+        draws += k * wl.c[l]
+    dt = time.perf_counter() - t0
+    total_draws = sum(N * c for N, c in zip(n_used, wl.c))
+    full = dt * total_draws / draws
+    return {"value": 1.0 / full, "unit": "estimates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{draws} of {total_draws} index draws ({fraction:.0%} of every level's "
+                      f"realisations), {dt:.1f} s, scaled by draws"}
+
+
+def cpu_baseline_matmul(wl, n_used, fraction):
+    import oracle
+    oracle.build(force=False)
+    law = oracle.Law.normal(wl.law_a[1], wl.law_a[2])
+    t0 = time.perf_counter()
+    work = 0.0
+    total = sum(N * wl.c[l] for l, N in enumerate(n_used))
+    for l, N in enumerate(n_used):
+        k = max(1, int(round(N * fraction)))
+        st = oracle.LevelState.empty(wl.m, wl.p)
+        oracle.level_estimation(st, wl.m, wl.n, wl.p, law, law, wl.c[l], wl.c[l - 1] if l else 0,
+                                wl.seed, 0, l, 0, k)
+        work += k * wl.c[l]
+        if time.perf_counter() - t0 > 30:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": work / total / dt, "unit": "estimates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{int(work)} of {total} index draws, {dt:.1f} s, scaled by draws"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported by this build "
+              f"(the per-level work would shard over GPUs with one merge of the level "
+              f"statistics; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1904_00429_amd import Law, inner_product_estimate, matmul_estimate, workloads
+    from paper_1904_00429_amd.mlmc import FLAG_SHARED_SAMPLES  # noqa: F401
+    import paper_1904_00429_amd.mlmc as api
+
+    dev = torch.device("cuda:0")
+    torch.cuda.init()
+    timing_flag = 2
+    if args.workload == "inner":
+        wl = workloads.INNER_2POW20
+        prec = args.prec or "fp32"
+        x = Law.uniform(wl.law_a[1], wl.law_a[2])
+        expected = wl.n * wl.law_a[1] * wl.law_b[1]
+
+        def step(want_timing, seed):
+            return _inner(api, wl, x, prec, dev, want_timing, seed)
+    else:
+        wl = workloads.MATMUL_LARGE if args.workload == "matmul-large" else workloads.MATMUL_SMALL_FP64
+        prec = args.prec or ("bf16" if args.workload == "matmul-large" else "fp64")
+        a = Law.normal(wl.law_a[1], wl.law_a[2])
+        expected = wl.n * wl.law_a[1] * wl.law_b[1]
+
+        def step(want_timing, seed):
+            return _matmul(api, wl, a, prec, dev, want_timing, seed)
+
+    # every step is an independent estimate: seed = step number
+    for i in range(args.warmup):
+        step(False, 1000 + i)
+    torch.cuda.synchronize()
+    results = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        results.append(step(True, i))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = args.steps / elapsed
+
+    # achieved accuracy against the exact E[AB] (closed form of the synthetic law)
+    errs = [float(torch.linalg.norm(r.Y - expected)) for r in results]
+    rmse_obs = math.sqrt(sum(e * e for e in errs) / len(errs))
+    rep = results[-1]
+    k_ms = [sum(r.kernel_ms[i] for r in results) for i in range(4)]
+    k_n = [sum(r.kernel_launches[i] for r in results) for i in range(4)]
+    draws = sum(r.total_draws for r in results)
+
+    if args.workload == "inner":
+        avg = k_ms[0] / max(k_n[0], 1)
+        slots = slots_per_draw_inner(wl.n) * draws / max(k_n[0], 1)
+        achieved = slots / (avg * 1e-3)
+        roof = {"bound": "alu", "kernel": f"inner_multi_kernel<{'float' if prec == 'fp32' else 'double'}>",
+                "achieved": achieved / 1e12, "peak": PEAK_VALU_SLOTS / 1e12, "unit": "Tops/s",
+                "frac": achieved / PEAK_VALU_SLOTS, "traffic": None,
+                "avg_launch_ms": avg, "launches": k_n[0],
+                "ops_per_draw": slots_per_draw_inner(wl.n)}
+        config = {"workload": wl.name, "n": wl.n, "levels": len(wl.c), "c0": wl.c[0], "ratio": 2,
+                  "eps": wl.rmse_target, "pilot": wl.pilot, "law": "0.5 + U(-1, 1) i.i.d.",
+                  "prec": prec}
+    else:
+        # dominant: the sketch (MFMA) kernel; algorithmic flops 2 m p per draw
+        flops = 2.0 * wl.m * wl.p * draws
+        achieved = flops / (k_ms[0] * 1e-3)
+        roof = {"bound": "mfma", "kernel": f"sketch_kernel<{prec}>", "achieved": achieved / 1e12,
+                "peak": PEAK_MFMA[prec] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_MFMA[prec],
+                "traffic": None, "avg_launch_ms": k_ms[0] / max(k_n[0], 1), "launches": k_n[0],
+                "gather_ms_per_step": k_ms[1] / args.steps, "sketch_ms_per_step": k_ms[0] / args.steps,
+                "merge_ms_per_step": k_ms[2] / args.steps}
+        config = {"workload": wl.name, "m": wl.m, "n": wl.n, "p": wl.p, "levels": len(wl.c), "c0": wl.c[0],
+                  "ratio": 2, "eps": wl.rmse_target, "pilot": wl.pilot, "prec": prec}
+
+    out = {"metric": METRIC, "value": value, "unit": "estimates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16"}[prec],
+           "data": "synthetic (entries generated inside the estimate)", "config": config, "roofline": roof,
+           "n_used": rep.n_used, "draws_per_step": draws / args.steps, "rmse_est": rep.rmse_est,
+           "rmse_observed": rmse_obs, "kernel_ms_per_step": {
+               "sample": k_ms[0] / args.steps, "gather": k_ms[1] / args.steps, "merge": k_ms[2] / args.steps,
+               "final": k_ms[3] / args.steps}}
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = src.numel() * 4
+
+    if not args.no_cpu_baseline:
+        if args.workload == "inner":
+            out["cpu_baseline"] = cpu_baseline_inner(wl, rep.n_used, args.cpu_fraction)
+        else:
+            out["cpu_baseline"] = cpu_baseline_matmul(wl, rep.n_used, min(args.cpu_fraction, 0.002))
+    print(json.dumps(out), flush=True)
+
+
+_WS = {}
+
+
+def _inner(api, wl, x, prec, dev, want_timing, seed):
+    import torch
+    key = ("inner", prec)
+    if key not in _WS:
+        _WS[key] = (torch.empty(1 << 20, dtype=torch.uint8, device=dev), torch.empty((), dtype=torch.float64, device=dev))
+    ws, out = _WS[key]
+    return _call_inner(api, wl, x, prec, dev, ws, out, want_timing, seed)
+
+
+def _call_inner(api, wl, x, prec, dev, ws, out, want_timing, seed):
+    import ctypes
+    h = api._LevelsHolder(wl.c, None, wl.rmse_target, wl.pilot, seed, prec, False, 0, 0)
+    if want_timing:
+        h.lv.flags |= 2
+    lib = api.lib()
+    need = int(lib.mlmc_inner_product_workspace_size(wl.n, ctypes.byref(h.lv)))
+    assert ws.numel() >= need
+    d = x.c()
+    rep = api.Report()
+    api.check(lib.mlmc_inner_product_estimate(wl.n, ctypes.byref(d), ctypes.byref(d), ctypes.byref(h.lv),
+                                              out.data_ptr(), None, ws.data_ptr(), ws.numel(), ctypes.byref(rep),
+                                              api._stream(dev)))
+    return _Rep(out.clone(), rep, len(wl.c))
+
+
+def _matmul(api, wl, a, prec, dev, want_timing, seed):
+    import ctypes
+    import torch
+    h = api._LevelsHolder(wl.c, wl.n_samples, wl.rmse_target if wl.n_samples is None else 0.0,
+                          wl.pilot, seed, prec, False, 0, 0)
+    if want_timing:
+        h.lv.flags |= 2
+    lib = api.lib()
+    need = int(lib.mlmc_matmul_workspace_size(wl.m, wl.n, wl.p, ctypes.byref(h.lv)))
+    key = ("matmul", wl.name, prec)
+    if key not in _WS:
+        _WS[key] = (torch.empty(need, dtype=torch.uint8, device=dev),
+                    torch.empty((wl.m, wl.p), dtype=torch.float64, device=dev))
+    ws, out = _WS[key]
+    d = a.c()
+    rep = api.Report()
+    api.check(lib.mlmc_matmul_estimate(wl.m, wl.n, wl.p, ctypes.byref(d), ctypes.byref(d), ctypes.byref(h.lv),
+                                       out.data_ptr(), None, ws.data_ptr(), ws.numel(), ctypes.byref(rep),
+                                       api._stream(dev)))
+    return _Rep(out.clone(), rep, len(wl.c))
+
+
+class _Rep:
+    def __init__(self, Y, rep, L1):
+        self.Y = Y
+        self.n_used = [int(rep.n_used[l]) for l in range(L1)]
+        self.level_var = [float(rep.level_var[l]) for l in range(L1)]
+        self.rmse_est = float(rep.rmse_est)
+        self.total_draws = int(rep.total_draws)
+        self.kernel_ms = [float(rep.kernel_ms[i]) for i in range(4)]
+        self.kernel_launches = [int(rep.kernel_launches[i]) for i in range(4)]
+
+
+if __name__ == "__main__":
+    main()

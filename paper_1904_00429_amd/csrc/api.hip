@@ -276,15 +276,17 @@ mlmc_status mlmc_inner_product_estimate(int64_t n, const mlmc_dist* x, const mlm
     }
     if (e != hipSuccess) return device_fail(e, "state reset");
 
-    auto run = [&](int l, int64_t k0, int64_t cnt) -> hipError_t {
-        return inner_level_run(range_of(lv, l, k0, cnt), n, lx, ly, lv->prec, keys, partials, state, stream,
-                               timer);
+    // every level of a phase goes into one launch
+    auto run_all = [&](const int64_t* k0, const int64_t* cnt) -> hipError_t {
+        LevelRange ranges[MLMC_MAX_LEVELS];
+        for (int l = 0; l < L1; ++l) ranges[l] = range_of(lv, l, k0[l], cnt[l]);
+        return inner_levels_run(ranges, L1, n, lx, ly, lv->prec, keys, partials, state, stream, timer);
     };
+    std::vector<int64_t> zero(L1, 0), amount(L1, 0);
     if (lv->rmse_target > 0.0) {
-        for (int l = 0; l < L1; ++l) {
-            if ((e = run(l, 0, lv->pilot_samples)) != hipSuccess) return device_fail(e, "pilot launch");
-            counts[l] = lv->pilot_samples;
-        }
+        for (int l = 0; l < L1; ++l) amount[l] = lv->pilot_samples;
+        if ((e = run_all(zero.data(), amount.data())) != hipSuccess) return device_fail(e, "pilot launch");
+        for (int l = 0; l < L1; ++l) counts[l] = lv->pilot_samples;
         {
             ScopedTiming t(timer, MLMC_KERNEL_FINAL);
             e = inner_telescope(state, L1, out, nullptr, var_dev, stream);
@@ -295,15 +297,13 @@ mlmc_status mlmc_inner_product_estimate(int64_t n, const mlmc_dist* x, const mlm
             return device_fail(e, "pilot readback");
         std::vector<int64_t> target(L1);
         if ((st = schedule(lv, var.data(), target.data())) != MLMC_OK) return st;
-        for (int l = 0; l < L1; ++l) {
-            if ((e = run(l, counts[l], target[l] - counts[l])) != hipSuccess) return device_fail(e, "extension launch");
-            counts[l] = target[l];
-        }
+        for (int l = 0; l < L1; ++l) amount[l] = target[l] - counts[l];
+        if ((e = run_all(counts.data(), amount.data())) != hipSuccess) return device_fail(e, "extension launch");
+        for (int l = 0; l < L1; ++l) counts[l] = target[l];
     } else {
-        for (int l = 0; l < L1; ++l) {
-            if ((e = run(l, 0, lv->n_samples[l])) != hipSuccess) return device_fail(e, "level launch");
-            counts[l] = lv->n_samples[l];
-        }
+        for (int l = 0; l < L1; ++l) amount[l] = lv->n_samples[l];
+        if ((e = run_all(zero.data(), amount.data())) != hipSuccess) return device_fail(e, "level launch");
+        for (int l = 0; l < L1; ++l) counts[l] = lv->n_samples[l];
     }
     {
         ScopedTiming t(timer, MLMC_KERNEL_FINAL);

@@ -46,12 +46,14 @@ __host__ __device__ inline Moments chan_merge(Moments a, Moments b)
 // Element e (0-based) of the column vector v_j = [A[:, j]; B[j, :]] from the
 // Philox words of its quad.  Normal elements use the Box-Muller pair
 // (e & ~1, e | 1) of the same quad.
+// Uniform entries are loc + scale (2u - 1), evaluated as one fused
+// multiply-add u (2 scale) + (loc - scale) whose constants are launch-uniform.
 template <typename T>
 __device__ __forceinline__ T law_value(const Law& law, T z_normal, T u_uniform, int64_t mat_index)
 {
-    if (law.kind == 1) return (T)law.loc + (T)law.scale * ((T)2 * u_uniform - (T)1);
-    if (law.kind == 2) return (T)law.mean[mat_index] + (T)law.stdev[mat_index] * z_normal;
-    return (T)law.loc + (T)law.scale * z_normal;
+    if (law.kind == 1) return fma(u_uniform, (T)(2.0 * law.scale), (T)(law.loc - law.scale));
+    if (law.kind == 2) return fma((T)law.stdev[mat_index], z_normal, (T)law.mean[mat_index]);
+    return fma(z_normal, (T)law.scale, (T)law.loc);
 }
 
 template <typename T>

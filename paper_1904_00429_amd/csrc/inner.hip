@@ -1,127 +1,192 @@
-// Inner-product level kernel (Sec. 2; Alg. 1 with m = p = 1, f = identity).
+// Inner-product level sampling (Sec. 2; Alg. 1 with m = p = 1, f = identity).
 //
 // A level sample of realisation k is
 //   D_k = (n / c) * ( (1 - c / c_prev) * sum_{t < c_prev} x_{r_t} y_{r_t}
 //                     + sum_{c_prev <= t < c} x_{r_t} y_{r_t} ),
-// which is the fine sketch (eq. (1) with xi = 1/n over c draws) minus the
-// coarse sketch over the first c_prev of the same draws; at level 0
-// (c_prev = 0) it is the fine sketch alone.  Nothing is read from memory
-// except reparameterised means/scales: indices and values are regenerated
-// from the counter-based stream, so the kernel is bound by integer VALU work
-// (Philox) and the roofline that matters is the VALU issue rate.
+// the fine sketch (eq. (1) with xi = 1/n over c draws) minus the coarse sketch
+// over the first c_prev of the same draws; at level 0 (c_prev = 0) the fine
+// sketch alone.  Nothing is read from memory except reparameterised
+// means/scales: indices and values are regenerated from the counter-based
+// stream, so the kernel is bound by VALU issue (Philox is 90% of the work).
 //
-// Work mapping: a group of G lanes (a power of two <= 64) owns one
-// realisation at a time; its lanes take draw pairs (2q, 2q+1), which share one
-// Philox call of the index stream.  The group's partial sums meet in a
-// butterfly of cross-lane shuffles, every lane of the group then holds D_k and
-// updates its Welford state in FP64.  At the end the groups of a workgroup
-// are combined by a fixed-order Chan tree in LDS and one Moments per
-// workgroup goes to global memory; a single-workgroup kernel folds those into
-// the level's running state, again in a fixed order.
+// One launch covers every level of a phase (the pilot, or the extension):
+// workgroups are dealt to levels in proportion to each level's draw count, so
+// the whole GPU works on all levels at once and no level runs a grid too small
+// to fill the chip.  Inside a level, a group of G lanes (a power of two, up to
+// the whole 256-lane workgroup) owns one realisation at a time; its lanes take
+// draw pairs (2q, 2q+1), which share one Philox call of the index stream.  G
+// is chosen so every lane gets at least four pairs, which amortises the
+// per-realisation reduction (a butterfly of cross-lane shuffles, plus an LDS
+// step when the group spans several waves).
+//
+// Statistics: every lane of a group holds D_k after the reduction and updates
+// FP64 sums shifted by the group's first sample K (n, S1 = sum (D - K),
+// S2 = sum (D - K)^2: no division per sample, no cancellation since K is a
+// draw of the same law).  At the end each group turns them into (n, mean, M2),
+// a fixed-order Chan tree in LDS merges the groups of the workgroup, and a
+// one-block-per-level kernel folds the workgroup partials into the level's
+// running state in a fixed order, so results are bitwise reproducible.
 #include "internal.hpp"
 
 namespace mlmc {
 
-struct InnerParams {
-    uint32_t n, c, c_prev;
-    uint32_t key0, key1, sid_index, sid_value;
-    uint32_t k_begin, num_samples;
-    uint32_t group_log2;
-    double scale;   // n / c
-    double omega;   // 1 - c / c_prev, weight of the first c_prev draws
-    Law x, y;
-    Moments* partials;
+constexpr int kInnerBlock = 256;
+constexpr int kInnerMaxBlocks = 8192;
+constexpr int64_t kInnerTargetBlocks = 4096;
+constexpr int64_t kInnerMinPairsPerBlock = 2048;
+
+struct InnerLevel {
+    uint32_t c, c_prev, k_begin, count;
+    uint32_t g_log2;          // lanes per realisation = 1 << g_log2, at most 256
+    uint32_t block_begin, blocks;
+    uint32_t sid_index, sid_value;
+    double scale;             // n / c
+    double omega;             // 1 - c / c_prev, weight of the first c_prev draws
 };
 
-constexpr int kInnerBlock = 256;
-constexpr int kInnerMaxBlocks = 4096;
+struct InnerMultiParams {
+    uint32_t n;
+    uint32_t n_shift;         // 32 - log2(n) when n is a power of two <= 2^32, else 0xFFFFFFFF
+    uint32_t key0, key1;
+    int32_t num_levels;
+    Law x, y;
+    Moments* partials;        // one per workgroup
+    InnerLevel lev[32];
+};
+
+// Index from its two Philox words; a power-of-two n is the top bits of the
+// 64-bit word, floor(x n / 2^64) = hi >> (32 - log2 n), which is the same value.
+__device__ __forceinline__ uint32_t inner_index(uint32_t lo, uint32_t hi, const InnerMultiParams& prm)
+{
+    if (prm.n_shift != 0xFFFFFFFFu) return prm.n_shift >= 32 ? 0u : hi >> prm.n_shift;
+    return index_from_words(lo, hi, prm.n);
+}
 
 template <typename T>
-__device__ __forceinline__ void inner_draw_values(const InnerParams& prm, uint32_t k, uint32_t j,
-                                                  bool normal, T& xv, T& yv)
+__device__ __forceinline__ T inner_product_term(const InnerMultiParams& prm, uint32_t k, uint32_t j,
+                                                uint32_t sid_value, bool normal)
 {
-    const Words4 w = philox4x32_10(0u, k, j, prm.sid_value, prm.key0, prm.key1);
+    const Words4 w = philox4x32_10(0u, k, j, sid_value, prm.key0, prm.key1);
     const T u0 = unit<T>(w.w0);
     const T u1 = unit<T>(w.w1);
     T z0 = (T)0, z1 = (T)0;
     if (normal) box_muller(u0, u1, z0, z1);
-    xv = law_value<T>(prm.x, z0, u0, (int64_t)j);
-    yv = law_value<T>(prm.y, z1, u1, (int64_t)j);
+    const T xv = law_value<T>(prm.x, z0, u0, (int64_t)j);
+    const T yv = law_value<T>(prm.y, z1, u1, (int64_t)j);
+    return xv * yv;
 }
 
 template <typename T>
-__global__ __launch_bounds__(kInnerBlock) void inner_level_kernel(InnerParams prm)
+__global__ __launch_bounds__(kInnerBlock) void inner_multi_kernel(InnerMultiParams prm)
 {
+    __shared__ double wave_sum[kInnerBlock / kWave];
     __shared__ Moments slots[kInnerBlock];
+
+    int l = 0;
+    while (l + 1 < prm.num_levels && blockIdx.x >= prm.lev[l].block_begin + prm.lev[l].blocks) ++l;
+    const InnerLevel& L = prm.lev[l];
+    const uint32_t g = L.g_log2;
+    const int G = 1 << g;
+    const int groups = G >= kInnerBlock ? 1 : kInnerBlock / G;
+    const int gi = threadIdx.x >> g;
+    const int lane_g = threadIdx.x & (G - 1);
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
-    const int G = 1 << prm.group_log2;
-    const int lane_g = lane & (G - 1);
-    const int groups_per_wave = kWave >> prm.group_log2;
-    const int groups_per_block = (kInnerBlock / kWave) * groups_per_wave;
-    const int slot = wave * groups_per_wave + (lane >> prm.group_log2);
-    const int64_t stride = (int64_t)gridDim.x * groups_per_block;
-    const uint32_t pairs = (prm.c + 1u) >> 1;
+    const uint64_t bl = blockIdx.x - L.block_begin;
+    const uint32_t s_lo = (uint32_t)(bl * L.count / L.blocks);
+    const uint32_t s_hi = (uint32_t)((bl + 1) * L.count / L.blocks);
+    const uint32_t iters = (s_hi - s_lo + groups - 1) / groups;
+    const uint32_t pairs = (L.c + 1u) >> 1;
+    const uint32_t coarse_pairs = L.c_prev >> 1;   // pairs whose two draws are both < c_prev
+    const bool odd_prev = (L.c_prev & 1u) != 0u;
     const bool normal = prm.x.kind != 1 || prm.y.kind != 1;
+    const T omega = (T)L.omega;
 
-    Moments st = {0.0, 0.0, 0.0};
-    for (int64_t s = (int64_t)blockIdx.x * groups_per_block + slot;; s += stride) {
-        // every lane of a wave runs the same number of iterations, so the
-        // cross-lane shuffles below always see their whole group
-        const bool active = s < (int64_t)prm.num_samples;
-        if (!__any(active)) break;
-        const uint32_t k = prm.k_begin + (uint32_t)(active ? s : 0);
+    double n = 0.0, K = 0.0, S1 = 0.0, S2 = 0.0;
+    for (uint32_t it = 0; it < iters; ++it) {
+        const uint32_t s = s_lo + (uint32_t)gi + it * (uint32_t)groups;
+        const bool active = s < s_hi;
+        const uint32_t k = L.k_begin + (active ? s : s_lo);
         T acc_coarse = (T)0, acc_fine = (T)0;
         for (uint32_t q = lane_g; q < pairs; q += G) {
-            uint32_t r0, r1;
-            draw_index_pair(q, k, prm.sid_index, prm.key0, prm.key1, prm.n, r0, r1);
-            const uint32_t t0 = 2u * q;
-            T xv, yv;
-            inner_draw_values<T>(prm, k, r0, normal, xv, yv);
-            if (t0 < prm.c_prev) acc_coarse += xv * yv;
-            else acc_fine += xv * yv;
-            if (t0 + 1u < prm.c) {
-                inner_draw_values<T>(prm, k, r1, normal, xv, yv);
-                if (t0 + 1u < prm.c_prev) acc_coarse += xv * yv;
-                else acc_fine += xv * yv;
+            const Words4 w = philox4x32_10(q, k, 0u, L.sid_index, prm.key0, prm.key1);
+            const uint32_t r0 = inner_index(w.w0, w.w1, prm);
+            const uint32_t r1 = inner_index(w.w2, w.w3, prm);
+            const T v0 = inner_product_term<T>(prm, k, r0, L.sid_value, normal);
+            const T v1 = (2u * q + 1u < L.c) ? inner_product_term<T>(prm, k, r1, L.sid_value, normal) : (T)0;
+            if (q < coarse_pairs) {
+                acc_coarse += v0 + v1;
+            } else if (odd_prev && q == coarse_pairs) {
+                acc_coarse += v0;    // draw c_prev - 1 is coarse, draw c_prev is fine
+                acc_fine += v1;
+            } else {
+                acc_fine += v0 + v1;
             }
         }
-        for (int off = G >> 1; off > 0; off >>= 1) {
-            acc_coarse += __shfl_xor(acc_coarse, off, kWave);
-            acc_fine += __shfl_xor(acc_fine, off, kWave);
+        T part = omega * acc_coarse + acc_fine;
+        const int width = G < kWave ? G : kWave;
+        for (int off = width >> 1; off > 0; off >>= 1) part += __shfl_xor(part, off, kWave);
+        double total = (double)part;
+        if (G > kWave) {
+            // the group spans G / 64 waves: add their sums in wave order
+            if (lane == 0) wave_sum[wave] = total;
+            __syncthreads();
+            const int first = (gi * G) / kWave;
+            total = 0.0;
+            for (int w = 0; w < G / kWave; ++w) total += wave_sum[first + w];
+            __syncthreads();
         }
         if (active) {
-            const double d = prm.scale * (prm.omega * (double)acc_coarse + (double)acc_fine);
-            st.n += 1.0;
-            const double delta = d - st.mean;
-            st.mean += delta / st.n;
-            st.m2 += delta * (d - st.mean);
+            const double d = L.scale * total;
+            if (n == 0.0) K = d;
+            n += 1.0;
+            const double dev = d - K;
+            S1 += dev;
+            S2 = fma(dev, dev, S2);
         }
     }
-    if (lane_g == 0) slots[slot] = st;
+    if (lane_g == 0) {
+        Moments m = {0.0, 0.0, 0.0};
+        if (n > 0.0) {
+            m.n = n;
+            m.mean = K + S1 / n;
+            m.m2 = fmax(S2 - S1 * (S1 / n), 0.0);
+        }
+        slots[gi] = m;
+    }
     __syncthreads();
-    for (int half = groups_per_block >> 1; half > 0; half >>= 1) {
+    for (int half = groups >> 1; half > 0; half >>= 1) {
         if ((int)threadIdx.x < half) slots[threadIdx.x] = chan_merge(slots[threadIdx.x], slots[threadIdx.x + half]);
         __syncthreads();
     }
     if (threadIdx.x == 0) prm.partials[blockIdx.x] = slots[0];
 }
 
-// Folds `count` workgroup partials, then the level's earlier state, in a
-// fixed order: thread i merges partials i, i + 256, ..., then a tree.
-__global__ __launch_bounds__(kInnerBlock) void inner_fold_kernel(const Moments* partials, int count,
-                                                                 Moments* level_state)
+// One block per level: fold that level's workgroup partials (thread i takes
+// partials i, i + 256, ... in order, then a tree), then append the result to
+// the level's running state.
+struct InnerFoldParams {
+    int32_t num_levels;
+    uint32_t block_begin[32];
+    uint32_t blocks[32];
+    const Moments* partials;
+    Moments* level_state;
+};
+
+__global__ __launch_bounds__(kInnerBlock) void inner_fold_kernel(InnerFoldParams prm)
 {
     __shared__ Moments slots[kInnerBlock];
+    const int l = blockIdx.x;
+    const Moments* part = prm.partials + prm.block_begin[l];
     Moments st = {0.0, 0.0, 0.0};
-    for (int i = threadIdx.x; i < count; i += kInnerBlock) st = chan_merge(st, partials[i]);
+    for (uint32_t i = threadIdx.x; i < prm.blocks[l]; i += kInnerBlock) st = chan_merge(st, part[i]);
     slots[threadIdx.x] = st;
     __syncthreads();
     for (int half = kInnerBlock >> 1; half > 0; half >>= 1) {
         if ((int)threadIdx.x < half) slots[threadIdx.x] = chan_merge(slots[threadIdx.x], slots[threadIdx.x + half]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) *level_state = chan_merge(*level_state, slots[0]);
+    if (threadIdx.x == 0 && prm.blocks[l] > 0) prm.level_state[l] = chan_merge(prm.level_state[l], slots[0]);
 }
 
 __global__ void inner_telescope_kernel(const Moments* level_state, int num_levels, double* out,
@@ -140,62 +205,114 @@ __global__ void inner_telescope_kernel(const Moments* level_state, int num_level
 
 size_t inner_partials_capacity() { return kInnerMaxBlocks; }
 
-static uint32_t group_log2_for(int64_t c)
+// Lanes per realisation: at least four draw pairs per lane, at most a workgroup.
+static uint32_t lanes_log2_for(int64_t c)
 {
     const int64_t pairs = (c + 1) / 2;
     uint32_t g = 0;
-    while ((int64_t(1) << g) < pairs && g < 6) ++g;
+    while (g < 8 && (int64_t(4) << (g + 1)) <= pairs) ++g;
     return g;
 }
 
-hipError_t inner_level_run(const LevelRange& lr, int64_t n, const Law& x, const Law& y, int prec,
-                           const StreamKeys& keys, Moments* partials, Moments* level_state,
-                           hipStream_t stream, KernelTimer* timer)
+hipError_t inner_levels_run(const LevelRange* ranges, int num_levels, int64_t n, const Law& x, const Law& y,
+                            int prec, const StreamKeys& keys, Moments* partials, Moments* level_state,
+                            hipStream_t stream, KernelTimer* timer)
 {
-    if (lr.count <= 0) return hipSuccess;
-    InnerParams prm;
+    InnerMultiParams prm;
     prm.n = (uint32_t)n;
-    prm.c = (uint32_t)lr.c;
-    prm.c_prev = (uint32_t)lr.c_prev;
+    prm.n_shift = 0xFFFFFFFFu;
+    if ((n & (n - 1)) == 0) {
+        uint32_t lg = 0;
+        while ((int64_t(1) << lg) < n) ++lg;
+        prm.n_shift = 32u - lg;     // n = 1 gives a shift of 32: every index is 0
+    }
     prm.key0 = keys.key0;
     prm.key1 = keys.key1;
-    prm.sid_index = stream_id(kTagIndex, lr.level_field, keys.problem);
-    prm.sid_value = stream_id(kTagValue, lr.level_field, keys.problem);
-    prm.k_begin = (uint32_t)lr.k_begin;
-    prm.num_samples = (uint32_t)lr.count;
-    prm.group_log2 = group_log2_for(lr.c);
-    prm.scale = (double)n / (double)lr.c;
-    prm.omega = lr.c_prev > 0 ? 1.0 - (double)lr.c / (double)lr.c_prev : 0.0;
+    prm.num_levels = num_levels;
     prm.x = x;
     prm.y = y;
     prm.partials = partials;
-    const int64_t groups_per_block = (kInnerBlock / kWave) * (kWave >> prm.group_log2);
-    int64_t blocks = ceil_div(lr.count, groups_per_block);
-    if (blocks > kInnerMaxBlocks) blocks = kInnerMaxBlocks;
+
+    // deal workgroups to levels in proportion to their draw pairs
+    double work[32], total = 0.0;
+    for (int i = 0; i < num_levels; ++i) {
+        work[i] = ranges[i].count > 0 ? (double)ranges[i].count * (double)((ranges[i].c + 1) / 2) : 0.0;
+        total += work[i];
+    }
+    if (total <= 0.0) return hipSuccess;
+    double target = total / (double)kInnerMinPairsPerBlock;
+    if (target > (double)kInnerTargetBlocks) target = (double)kInnerTargetBlocks;
+    if (target < 1.0) target = 1.0;
+    uint32_t next = 0;
+    InnerFoldParams fold;
+    fold.num_levels = num_levels;
+    for (int i = 0; i < num_levels; ++i) {
+        const LevelRange& lr = ranges[i];
+        InnerLevel& L = prm.lev[i];
+        L.c = (uint32_t)lr.c;
+        L.c_prev = (uint32_t)lr.c_prev;
+        L.k_begin = (uint32_t)lr.k_begin;
+        L.count = (uint32_t)(lr.count > 0 ? lr.count : 0);
+        L.g_log2 = lanes_log2_for(lr.c);
+        L.sid_index = stream_id(kTagIndex, lr.level_field, keys.problem);
+        L.sid_value = stream_id(kTagValue, lr.level_field, keys.problem);
+        L.scale = (double)n / (double)lr.c;
+        L.omega = lr.c_prev > 0 ? 1.0 - (double)lr.c / (double)lr.c_prev : 0.0;
+        int64_t blocks = 0;
+        if (L.count > 0) {
+            const int64_t groups = (int64_t)1 << (L.g_log2 >= 8 ? 0 : 8 - L.g_log2);
+            const int64_t most = ceil_div(L.count, groups);
+            blocks = (int64_t)(target * work[i] / total + 0.5);
+            if (blocks < 1) blocks = 1;
+            if (blocks > most) blocks = most;
+        }
+        L.block_begin = next;
+        L.blocks = (uint32_t)blocks;
+        fold.block_begin[i] = next;
+        fold.blocks[i] = (uint32_t)blocks;
+        next += (uint32_t)blocks;
+    }
+    if (next > (uint32_t)kInnerMaxBlocks) {
+        // scale every level down proportionally (at least one block each)
+        uint32_t again = 0;
+        for (int i = 0; i < num_levels; ++i) {
+            int64_t b = prm.lev[i].blocks;
+            if (b > 0) {
+                b = (int64_t)((double)b * (kInnerMaxBlocks - num_levels) / (double)next);
+                if (b < 1) b = 1;
+            }
+            prm.lev[i].block_begin = again;
+            prm.lev[i].blocks = (uint32_t)b;
+            fold.block_begin[i] = again;
+            fold.blocks[i] = (uint32_t)b;
+            again += (uint32_t)b;
+        }
+        next = again;
+    }
+    if (next == 0) return hipSuccess;
     {
         ScopedTiming t(timer, 0);
         if (prec == 0)
-            hipLaunchKernelGGL(inner_level_kernel<double>, dim3((unsigned)blocks), dim3(kInnerBlock), 0,
-                               stream, prm);
+            hipLaunchKernelGGL(inner_multi_kernel<double>, dim3(next), dim3(kInnerBlock), 0, stream, prm);
         else
-            hipLaunchKernelGGL(inner_level_kernel<float>, dim3((unsigned)blocks), dim3(kInnerBlock), 0,
-                               stream, prm);
+            hipLaunchKernelGGL(inner_multi_kernel<float>, dim3(next), dim3(kInnerBlock), 0, stream, prm);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    fold.partials = partials;
+    fold.level_state = level_state;
     {
         ScopedTiming t(timer, 2);
-        hipLaunchKernelGGL(inner_fold_kernel, dim3(1), dim3(kInnerBlock), 0, stream,
-                           (const Moments*)partials, (int)blocks, level_state + lr.level);
+        hipLaunchKernelGGL(inner_fold_kernel, dim3((unsigned)num_levels), dim3(kInnerBlock), 0, stream, fold);
     }
     return hipGetLastError();
 }
 
-hipError_t inner_telescope(const Moments* level_state, int num_levels, double* out,
-                           double* level_means, double* level_var, hipStream_t stream)
+hipError_t inner_telescope(const Moments* level_state, int num_levels, double* out, double* level_means,
+                           double* level_var, hipStream_t stream)
 {
-    hipLaunchKernelGGL(inner_telescope_kernel, dim3(1), dim3(64), 0, stream, level_state,
-                       num_levels, out, level_means, level_var);
+    hipLaunchKernelGGL(inner_telescope_kernel, dim3(1), dim3(64), 0, stream, level_state, num_levels, out,
+                       level_means, level_var);
     return hipGetLastError();
 }
 

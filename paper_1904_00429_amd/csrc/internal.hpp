@@ -52,9 +52,11 @@ struct StreamKeys {
 // ---- inner product (m = p = 1) -------------------------------------------
 // Device state per level: one Moments (count, mean, M2) of the level samples.
 size_t inner_partials_capacity();  // Moments slots needed in workspace
-hipError_t inner_level_run(const LevelRange& lr, int64_t n, const Law& x, const Law& y,
-                           int prec, const StreamKeys& keys, Moments* partials,
-                           Moments* level_state, hipStream_t stream, KernelTimer* timer);
+// One launch over every level's range (pilot, extension or fixed mode), then a
+// fold of the workgroup partials into the running level states.
+hipError_t inner_levels_run(const LevelRange* ranges, int num_levels, int64_t n, const Law& x,
+                            const Law& y, int prec, const StreamKeys& keys, Moments* partials,
+                            Moments* level_state, hipStream_t stream, KernelTimer* timer);
 hipError_t inner_telescope(const Moments* level_state, int num_levels, double* out,
                            double* level_means, double* level_var, hipStream_t stream);
 

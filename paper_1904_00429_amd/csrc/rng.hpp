@@ -30,8 +30,18 @@ __host__ __device__ inline uint32_t stream_id(uint32_t tag, uint32_t level_field
     return (tag << 28) | ((level_field & 0xFFu) << 20) | (problem & 0xFFFFFu);
 }
 
+// a ^ b ^ k in one VALU instruction: gfx950's three-input bit operation with
+// the XOR truth table (0x96).  k is a launch-uniform key word (scalar register).
+__device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t k)
+{
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+    return r;
+}
+
 // One Philox4x32-10 evaluation.  The key schedule depends only on the seed,
-// which is uniform across a launch, so it stays in scalar registers.
+// which is uniform across a launch, so it stays in scalar registers; each
+// round costs two 32x32->64-bit multiply-adds and two three-input xors.
 __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                 uint32_t k0, uint32_t k1)
 {
@@ -39,8 +49,8 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
     for (int round = 0; round < 10; ++round) {
         const uint64_t prod_a = (uint64_t)0xD2511F53u * c0;
         const uint64_t prod_b = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(prod_b >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(prod_a >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3_key((uint32_t)(prod_b >> 32), c1, k0);
+        const uint32_t n2 = xor3_key((uint32_t)(prod_a >> 32), c3, k1);
         c1 = (uint32_t)prod_b;
         c3 = (uint32_t)prod_a;
         c0 = n0;
