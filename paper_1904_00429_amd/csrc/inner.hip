@@ -62,21 +62,61 @@ __device__ __forceinline__ uint32_t inner_index(uint32_t lo, uint32_t hi, const 
     return index_from_words(lo, hi, prm.n);
 }
 
-template <typename T>
+// Law pairs with a specialised instantiation (no per-value law branches in the
+// hot loop); every other combination takes the general path.
+enum { kLawsAny = 0, kLawsUniform = 1, kLawsNormal = 2 };
+
+template <typename T, int LAWS>
 __device__ __forceinline__ T inner_product_term(const InnerMultiParams& prm, uint32_t k, uint32_t j,
-                                                uint32_t sid_value, bool normal)
+                                                uint32_t sid_value)
 {
     const Words4 w = philox4x32_10(0u, k, j, sid_value, prm.key0, prm.key1);
     const T u0 = unit<T>(w.w0);
     const T u1 = unit<T>(w.w1);
-    T z0 = (T)0, z1 = (T)0;
-    if (normal) box_muller(u0, u1, z0, z1);
+    if (LAWS == kLawsUniform) {
+        const T xv = fma(u0, (T)(2.0 * prm.x.scale), (T)(prm.x.loc - prm.x.scale));
+        const T yv = fma(u1, (T)(2.0 * prm.y.scale), (T)(prm.y.loc - prm.y.scale));
+        return xv * yv;
+    }
+    T z0, z1;
+    box_muller(u0, u1, z0, z1);
+    if (LAWS == kLawsNormal) {
+        const T xv = fma(z0, (T)prm.x.scale, (T)prm.x.loc);
+        const T yv = fma(z1, (T)prm.y.scale, (T)prm.y.loc);
+        return xv * yv;
+    }
     const T xv = law_value<T>(prm.x, z0, u0, (int64_t)j);
     const T yv = law_value<T>(prm.y, z1, u1, (int64_t)j);
     return xv * yv;
 }
 
+// The two product terms of draw pair q (draws 2q and 2q + 1) of realisation k.
+template <typename T, int LAWS>
+__device__ __forceinline__ void pair_terms(const InnerMultiParams& prm, const InnerLevel& L, uint32_t q,
+                                           uint32_t k, T& v0, T& v1)
+{
+    const Words4 w = philox4x32_10(q, k, 0u, L.sid_index, prm.key0, prm.key1);
+    const uint32_t r0 = inner_index(w.w0, w.w1, prm);
+    const uint32_t r1 = inner_index(w.w2, w.w3, prm);
+    v0 = inner_product_term<T, LAWS>(prm, k, r0, L.sid_value);
+    v1 = (2u * q + 1u < L.c) ? inner_product_term<T, LAWS>(prm, k, r1, L.sid_value) : (T)0;
+}
+
 template <typename T>
+__device__ __forceinline__ void add_pair(uint32_t q, uint32_t coarse_pairs, bool odd_prev, T v0, T v1,
+                                         T& acc_coarse, T& acc_fine)
+{
+    if (q < coarse_pairs) {
+        acc_coarse += v0 + v1;
+    } else if (odd_prev && q == coarse_pairs) {
+        acc_coarse += v0;    // draw c_prev - 1 is coarse, draw c_prev is fine
+        acc_fine += v1;
+    } else {
+        acc_fine += v0 + v1;
+    }
+}
+
+template <typename T, int LAWS>
 __global__ __launch_bounds__(kInnerBlock) void inner_multi_kernel(InnerMultiParams prm)
 {
     __shared__ double wave_sum[kInnerBlock / kWave];
@@ -99,7 +139,6 @@ __global__ __launch_bounds__(kInnerBlock) void inner_multi_kernel(InnerMultiPara
     const uint32_t pairs = (L.c + 1u) >> 1;
     const uint32_t coarse_pairs = L.c_prev >> 1;   // pairs whose two draws are both < c_prev
     const bool odd_prev = (L.c_prev & 1u) != 0u;
-    const bool normal = prm.x.kind != 1 || prm.y.kind != 1;
     const T omega = (T)L.omega;
 
     double n = 0.0, K = 0.0, S1 = 0.0, S2 = 0.0;
@@ -108,20 +147,19 @@ __global__ __launch_bounds__(kInnerBlock) void inner_multi_kernel(InnerMultiPara
         const bool active = s < s_hi;
         const uint32_t k = L.k_begin + (active ? s : s_lo);
         T acc_coarse = (T)0, acc_fine = (T)0;
-        for (uint32_t q = lane_g; q < pairs; q += G) {
-            const Words4 w = philox4x32_10(q, k, 0u, L.sid_index, prm.key0, prm.key1);
-            const uint32_t r0 = inner_index(w.w0, w.w1, prm);
-            const uint32_t r1 = inner_index(w.w2, w.w3, prm);
-            const T v0 = inner_product_term<T>(prm, k, r0, L.sid_value, normal);
-            const T v1 = (2u * q + 1u < L.c) ? inner_product_term<T>(prm, k, r1, L.sid_value, normal) : (T)0;
-            if (q < coarse_pairs) {
-                acc_coarse += v0 + v1;
-            } else if (odd_prev && q == coarse_pairs) {
-                acc_coarse += v0;    // draw c_prev - 1 is coarse, draw c_prev is fine
-                acc_fine += v1;
-            } else {
-                acc_fine += v0 + v1;
-            }
+        // two pairs per iteration: independent Philox chains the scheduler can interleave
+        uint32_t q = lane_g;
+        for (; q + (uint32_t)G < pairs; q += 2u * (uint32_t)G) {
+            T a0, a1, b0, b1;
+            pair_terms<T, LAWS>(prm, L, q, k, a0, a1);
+            pair_terms<T, LAWS>(prm, L, q + G, k, b0, b1);
+            add_pair(q, coarse_pairs, odd_prev, a0, a1, acc_coarse, acc_fine);
+            add_pair(q + G, coarse_pairs, odd_prev, b0, b1, acc_coarse, acc_fine);
+        }
+        if (q < pairs) {
+            T a0, a1;
+            pair_terms<T, LAWS>(prm, L, q, k, a0, a1);
+            add_pair(q, coarse_pairs, odd_prev, a0, a1, acc_coarse, acc_fine);
         }
         T part = omega * acc_coarse + acc_fine;
         const int width = G < kWave ? G : kWave;
@@ -290,12 +328,19 @@ hipError_t inner_levels_run(const LevelRange* ranges, int num_levels, int64_t n,
         next = again;
     }
     if (next == 0) return hipSuccess;
+    const int laws = (x.kind == 1 && y.kind == 1) ? kLawsUniform : (x.kind == 0 && y.kind == 0) ? kLawsNormal : kLawsAny;
     {
         ScopedTiming t(timer, 0);
-        if (prec == 0)
-            hipLaunchKernelGGL(inner_multi_kernel<double>, dim3(next), dim3(kInnerBlock), 0, stream, prm);
-        else
-            hipLaunchKernelGGL(inner_multi_kernel<float>, dim3(next), dim3(kInnerBlock), 0, stream, prm);
+        const dim3 grid(next), block(kInnerBlock);
+        if (prec == 0) {
+            if (laws == kLawsUniform) hipLaunchKernelGGL((inner_multi_kernel<double, kLawsUniform>), grid, block, 0, stream, prm);
+            else if (laws == kLawsNormal) hipLaunchKernelGGL((inner_multi_kernel<double, kLawsNormal>), grid, block, 0, stream, prm);
+            else hipLaunchKernelGGL((inner_multi_kernel<double, kLawsAny>), grid, block, 0, stream, prm);
+        } else {
+            if (laws == kLawsUniform) hipLaunchKernelGGL((inner_multi_kernel<float, kLawsUniform>), grid, block, 0, stream, prm);
+            else if (laws == kLawsNormal) hipLaunchKernelGGL((inner_multi_kernel<float, kLawsNormal>), grid, block, 0, stream, prm);
+            else hipLaunchKernelGGL((inner_multi_kernel<float, kLawsAny>), grid, block, 0, stream, prm);
+        }
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -30,13 +30,11 @@ __host__ __device__ inline uint32_t stream_id(uint32_t tag, uint32_t level_field
     return (tag << 28) | ((level_field & 0xFFu) << 20) | (problem & 0xFFFFFu);
 }
 
-// a ^ b ^ k in one VALU instruction: gfx950's three-input bit operation with
-// the XOR truth table (0x96).  k is a launch-uniform key word (scalar register).
+// a ^ b ^ k in one VALU instruction: gfx950's three-input bit operation
+// (v_bitop3_b32) with the XOR truth table 0x96.
 __device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t k)
 {
-    uint32_t r;
-    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
-    return r;
+    return __builtin_amdgcn_bitop3_b32(a, b, k, 0x96);
 }
 
 // One Philox4x32-10 evaluation.  The key schedule depends only on the seed,
