@@ -48,6 +48,22 @@ PEAK_MFMA = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15}
 PEAK_HBM = 8.0e12
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    passes (calibrated on a 1 GiB copy), or None once the kernel's sources differ
+    from the ones the counters were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        entry = json.load(open(path))[kernel]
+        h = hashlib.sha256()
+        for src in entry["sources"]:
+            h.update(open(os.path.join(ROOT, src), "rb").read())
+        return entry["bytes_per_launch"] if h.hexdigest() == entry["sha256"] else None
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,7 +179,8 @@ def main():
         achieved = slots / (avg * 1e-3)
         roof = {"bound": "alu", "kernel": f"inner_multi_kernel<{'float' if prec == 'fp32' else 'double'}>",
                 "achieved": achieved / 1e12, "peak": PEAK_VALU_SLOTS / 1e12, "unit": "Tops/s",
-                "frac": achieved / PEAK_VALU_SLOTS, "traffic": None,
+                "frac": achieved / PEAK_VALU_SLOTS, "traffic": measured_traffic("inner_multi_kernel"),
+                "traffic_unit": "bytes per launch",
                 "avg_launch_ms": avg, "launches": k_n[0],
                 "ops_per_draw": slots_per_draw_inner(wl.n)}
         config = {"workload": wl.name, "n": wl.n, "levels": len(wl.c), "c0": wl.c[0], "ratio": 2,

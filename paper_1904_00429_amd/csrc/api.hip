@@ -182,7 +182,6 @@ namespace mlmc {
 void KernelTimer::begin(int cls)
 {
     open_cls_ = -1;
-    if (used_ >= sizeof(classes_) / sizeof(classes_[0])) return;
     while (g_event_pool.size() < 2 * (used_ + 1)) {
         hipEvent_t ev;
         if (hipEventCreate(&ev) != hipSuccess) return;
@@ -195,7 +194,10 @@ void KernelTimer::begin(int cls)
 void KernelTimer::end()
 {
     if (open_cls_ < 0) return;
-    if (hipEventRecord(g_event_pool[2 * used_ + 1], stream_) == hipSuccess) classes_[used_++] = open_cls_;
+    if (hipEventRecord(g_event_pool[2 * used_ + 1], stream_) == hipSuccess) {
+        classes_.push_back(open_cls_);
+        ++used_;
+    }
     open_cls_ = -1;
 }
 

@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "common.hpp"
 
 namespace mlmc {
@@ -35,7 +37,7 @@ private:
     hipStream_t stream_;
     int open_cls_ = -1;
     size_t used_ = 0;
-    int classes_[4096];
+    std::vector<int> classes_;
 };
 
 struct ScopedTiming {
@@ -72,7 +74,9 @@ struct MatmulPlan {
     int tile_m, tile_n;    // workgroup output tile
     int64_t tiles_m, tiles_n;
     int64_t kpad_max;      // padded draws per realisation at the finest level
-    int64_t batch;         // realisations generated per gather pass
+    int64_t gather_bytes;  // capacity of the gathered-operand buffer
+    int elem;              // bytes per gathered value
+    int64_t batch;         // realisations per gather pass at the finest level (smallest batch)
     int64_t groups_max;    // sample groups per pass
     int64_t merge_blocks;  // blocks of the per-entry merge
     // workspace layout (byte offsets)

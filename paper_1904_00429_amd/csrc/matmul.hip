@@ -449,18 +449,20 @@ bool matmul_plan(int64_t m, int64_t n, int64_t p, int prec, int num_levels, cons
     }
     const int64_t per_sample = plan.kpad_max * (m + p) * elem;
     // the gathered operands of one pass stay within a budget sized for the
-    // 256 MB Infinity Cache; MLMC_GATHER_BUDGET (bytes) overrides it
+    // 256 MB Infinity Cache; MLMC_GATHER_BUDGET (bytes) overrides it.  Each
+    // level fills the buffer with as many realisations as fit.
     int64_t budget = kGatherBudgetBytes;
     if (const char* env = getenv("MLMC_GATHER_BUDGET")) {
         const long long v = atoll(env);
         if (v > 0) budget = v;
     }
+    if (budget < per_sample) budget = per_sample;
+    plan.elem = elem;
+    plan.gather_bytes = budget;
     plan.batch = budget / per_sample;
-    if (plan.batch < 1) plan.batch = 1;
     if (plan.batch > 65535) plan.batch = 65535;
     const int64_t tiles = plan.tiles_m * plan.tiles_n;
     plan.groups_max = ceil_div(kTargetSketchBlocks, tiles);
-    if (plan.groups_max > plan.batch) plan.groups_max = plan.batch;
     if (plan.groups_max > 65535) plan.groups_max = 65535;
     plan.merge_blocks = ceil_div(m * p, kMergeThreads);
     const int64_t L1 = num_levels;
@@ -470,8 +472,9 @@ bool matmul_plan(int64_t m, int64_t n, int64_t p, int prec, int num_levels, cons
     plan.off_between = off;  off = align(off + sizeof(double) * L1 * plan.merge_blocks);
     plan.off_within = off;   off = align(off + sizeof(double) * L1);
     plan.off_var = off;      off = align(off + sizeof(double) * L1);
-    plan.off_gather_a = off; off = align(off + (size_t)plan.batch * plan.kpad_max * m * elem);
-    plan.off_gather_b = off; off = align(off + (size_t)plan.batch * plan.kpad_max * p * elem);
+    // one buffer: the A part of a pass first, its B part right after it
+    plan.off_gather_a = off; off = align(off + (size_t)plan.gather_bytes + 256);
+    plan.off_gather_b = plan.off_gather_a;
     plan.off_part_mean = off; off = align(off + sizeof(double) * plan.groups_max * m * p);
     plan.off_part_m2 = off;  off = align(off + sizeof(double) * plan.groups_max * tiles);
     plan.total = off;
@@ -516,7 +519,8 @@ static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t
     g.k_first = (uint32_t)k_first;
     g.A = A; g.B = B;
     g.GA = ws + plan.off_gather_a;
-    g.GB = ws + plan.off_gather_b;
+    const size_t a_bytes = ((size_t)batch * kpad * plan.m * plan.elem + 255) & ~(size_t)255;
+    g.GB = ws + plan.off_gather_a + a_bytes;
     const dim3 ggrid((unsigned)ceil_div(kpad, kGatherPositions), (unsigned)batch);
     {
         ScopedTiming t(timer, 1);
@@ -563,8 +567,13 @@ hipError_t matmul_level_run(const MatmulPlan& plan, const LevelRange& lr, int64_
                             const Law& A, const Law& B, const StreamKeys& keys, char* ws,
                             hipStream_t stream, KernelTimer* timer)
 {
-    for (int64_t b = 0; b < lr.count; b += plan.batch) {
-        const int64_t batch = (lr.count - b) < plan.batch ? (lr.count - b) : plan.batch;
+    int64_t kc, kpad;
+    level_padding(plan, lr.c, lr.c_prev, kc, kpad);
+    int64_t level_batch = plan.gather_bytes / (kpad * (plan.m + plan.p) * plan.elem + 512);
+    if (level_batch < 1) level_batch = 1;
+    if (level_batch > 65535) level_batch = 65535;
+    for (int64_t b = 0; b < lr.count; b += level_batch) {
+        const int64_t batch = (lr.count - b) < level_batch ? (lr.count - b) : level_batch;
         hipError_t err;
         if (plan.prec == 0)
             err = run_pass<PolicyF64, double>(plan, lr, lr.k_begin + b, batch, done_before + b, A, B, keys, ws, stream, timer);

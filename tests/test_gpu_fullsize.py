@@ -1,0 +1,55 @@
+"""Parity at the full size of the benchmarked workload, in the launch
+configuration bench.py times: x, y in R^(2^20), i.i.d. 0.5 + U(-1, 1),
+c_l = 64 * 2^l (l = 0..8), target RMSE 1e-3 |E[x^T y]|, pilot 1024.
+
+The oracle runs the same target-mode estimate (pilot, eq. (28), extension)
+on the host, one thread per level (about 7e8 index draws).  FP64: the
+scheduled N_l must agree exactly and the estimate to 1e-12.  FP32: the pilot
+variances differ at ~1e-6 relative, so each N_l may move by one realisation;
+the estimate and variances agree to 1e-5.
+"""
+import math
+import os
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+from gpu_helpers import flush
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_inner_2pow20_target_mode_full(orc, dev, prec):
+    from paper_1904_00429_amd import Law, inner_product_estimate, workloads
+    wl = workloads.INNER_2POW20
+    flush(f"full-size inner product prec={prec} n={wl.n} levels={len(wl.c)}")
+    g = Law.uniform(wl.law_a[1], wl.law_a[2])
+    est = inner_product_estimate(wl.n, g, g, wl.c, rmse_target=wl.rmse_target, pilot=wl.pilot,
+                                 seed=wl.seed, prec=prec, level_means=True, device=dev)
+    o = orc.Law.uniform(wl.law_a[1], wl.law_a[2])
+    with ThreadPoolExecutor(max_workers=min(len(wl.c), os.cpu_count() or 4)) as pool:
+        ref = orc.estimate(1, wl.n, 1, o, o, wl.c, rmse_target=wl.rmse_target, pilot=wl.pilot,
+                           seed=wl.seed, pool=pool)
+    flush(f"  gpu N={est.n_used}\n  orc N={list(ref.n_used)}")
+    y = float(est.Y.cpu())
+    V = np.array(est.level_var)
+    if prec == "fp64":
+        assert list(est.n_used) == list(ref.n_used)
+        assert abs(y - ref.Y[0, 0]) <= 1e-12 * abs(ref.Y[0, 0])
+        np.testing.assert_allclose(V, ref.level_var, rtol=1e-10)
+    else:
+        assert all(abs(a - b) <= 1 for a, b in zip(est.n_used, ref.n_used))
+        assert abs(y - ref.Y[0, 0]) <= 1e-5 * abs(ref.Y[0, 0])
+        np.testing.assert_allclose(V, ref.level_var, rtol=1e-5)
+    # the target is met: predicted RMSE within the eps^2 / 2 variance budget
+    assert est.rmse_est <= wl.rmse_target / math.sqrt(2) * 1.05
