@@ -144,6 +144,33 @@ mlmc_status mlmc_inner_product_estimate(int64_t n, const mlmc_dist* x, const mlm
                                         size_t workspace_bytes, mlmc_report* report,
                                         void* stream);
 
+/* ---- Differentiation ------------------------------------------------------
+ * Adjoint of mlmc_matmul_estimate for reparameterised laws A = M_A + S_A o Z,
+ * B = M_B + S_B o W (both MLMC_LAW_REPARAM).  Y = sum_l Ybar_l is bilinear in
+ * the sampled columns, so for G = dL/dY
+ *   dL/da_t = kappa_t G b_t,  dL/db_t = kappa_t G^T a_t,
+ *   kappa_t = (n / c_l) w_t / N_l  (w_t = 1 - c_l / c_{l-1} for the first c_{l-1}
+ *   draws of level l >= 1, else 1; Alg. 1 with the prefix coupling),
+ * and dM_A[:, r_t] += dL/da_t, dS_A[:, r_t] += dL/da_t o z_t (likewise for B).
+ * The indices and normals of every realisation are regenerated from the seed
+ * exactly as the forward drew them; nothing of the forward is stored.
+ *   levels:   the forward's ladder, seed, problem and flags, in fixed mode
+ *             (pass the forward report's n_used after a target-RMSE call).
+ *   grad_out: device FP64, m x p row-major, dL/dY.
+ *   dMA, dSA: device FP32 in the layout of A's mean/stdev (column-major m x n,
+ *             ld = A->ld); dMB, dSB: layout of B's (row-major n x p, ld = B->ld).
+ *             Gradients are ADDED (FP32 atomics, so the last bits depend on
+ *             the order in which workgroups finish); zero them first.
+ * Arithmetic: FP32 (values, MFMA contraction, accumulation).
+ * Errors: EINVAL (laws not reparameterised, target mode, null pointers, and
+ * the conditions of mlmc_matmul_estimate), EWORKSPACE, EDEVICE. */
+size_t mlmc_matmul_adjoint_workspace_size(int64_t m, int64_t n, int64_t p, const mlmc_levels* levels);
+mlmc_status mlmc_matmul_adjoint_reparam(int64_t m, int64_t n, int64_t p, const mlmc_dist* A,
+                                        const mlmc_dist* B, const mlmc_levels* levels,
+                                        const double* grad_out, float* dMA, float* dSA, float* dMB,
+                                        float* dSB, void* workspace, size_t workspace_bytes,
+                                        void* stream);
+
 /* ---- Building blocks, exported for testing ------------------------------ */
 
 /* Philox4x32-10 (SC'11) of `count` counters: ctr and out are device arrays of

@@ -1,0 +1,63 @@
+"""Gradient reference for the reparameterised matrix estimator (test
+infrastructure only).
+
+The estimate of Alg. 1 / eq. (10) is rewritten with plain PyTorch CPU FP64
+operations on the same index draws and standard normals as the C oracle
+(taken from it), so torch's autograd gives the exact gradient of
+<G, Y> with respect to the means and scales at a fixed seed.  Pinned to the
+C oracle's forward and to finite differences in the tests."""
+from __future__ import annotations
+
+from typing import Sequence
+
+import numpy as np
+import torch
+
+from . import Law, column, draw_indices, level_field
+
+
+def standard_normals(seed, problem, lfield, k, cols, m, p):
+    """z (len(cols) x m) and w (len(cols) x p) of the draws of realisation k."""
+    unit = Law.normal(0.0, 1.0)
+    Z = np.empty((len(cols), m))
+    W = np.empty((len(cols), p))
+    for t, j in enumerate(cols):
+        Z[t], W[t] = column(seed, problem, lfield, k, int(j), m, p, unit, unit)
+    return torch.from_numpy(Z), torch.from_numpy(W)
+
+
+def reparam_estimate(MA: torch.Tensor, SA: torch.Tensor, MB: torch.Tensor, SB: torch.Tensor,
+                     c: Sequence[int], N: Sequence[int], seed: int = 0, problem: int = 0,
+                     shared: bool = False) -> torch.Tensor:
+    """Y = sum_l (1/N_l) sum_k (Z_l^(k) - Z_{l-1}^(k)) for A = MA^T + SA^T o Z
+    (MA, SA: n x m, row j = column j of A) and B = MB + SB o W (n x p)."""
+    n, m = MA.shape
+    p = MB.shape[1]
+    Y = torch.zeros((m, p), dtype=torch.float64)
+    for l, (cl, Nl) in enumerate(zip(c, N)):
+        cp = c[l - 1] if l > 0 else 0
+        lf = level_field(l, shared)
+        acc = torch.zeros((m, p), dtype=torch.float64)
+        for k in range(Nl):
+            r = draw_indices(seed, problem, lf, k, cl, n)
+            Z, W = standard_normals(seed, problem, lf, k, r, m, p)
+            idx = torch.from_numpy(r)
+            AS = MA[idx] + SA[idx] * Z          # c x m: row t = a_t
+            BS = MB[idx] + SB[idx] * W          # c x p: row t = b_t
+            Zf = (n / cl) * (AS.T @ BS)
+            if cp > 0:
+                Zc = (n / cp) * (AS[:cp].T @ BS[:cp])
+                acc = acc + (Zf - Zc)
+            else:
+                acc = acc + Zf
+        Y = Y + acc / Nl
+    return Y
+
+
+def reparam_gradients(MA, SA, MB, SB, c, N, G, seed=0, problem=0, shared=False):
+    """Gradients of <G, Y> (FP64) with respect to MA, SA, MB, SB."""
+    leaves = [torch.as_tensor(np.asarray(x, dtype=np.float64)).clone().requires_grad_(True)
+              for x in (MA, SA, MB, SB)]
+    Y = reparam_estimate(*leaves, c, N, seed, problem, shared)
+    (Y * torch.as_tensor(np.asarray(G, dtype=np.float64))).sum().backward()
+    return Y.detach().numpy(), [t.grad.numpy() for t in leaves]

@@ -13,6 +13,7 @@ EXPORTED = [
     "mlmc_matmul_workspace_size", "mlmc_inner_product_workspace_size", "mlmc_matmul_estimate",
     "mlmc_inner_product_estimate", "mlmc_philox4x32_10", "mlmc_sample_indices",
     "mlmc_gather_columns", "mlmc_status_string", "mlmc_last_error",
+    "mlmc_matmul_adjoint_workspace_size", "mlmc_matmul_adjoint_reparam",
 ]
 
 
@@ -70,6 +71,10 @@ def lib() -> ctypes.CDLL:
     L.mlmc_sample_indices.argtypes = [u64, u32, u32, u32, i64, i64, i64, vp, vp]
     L.mlmc_gather_columns.restype = ctypes.c_int
     L.mlmc_gather_columns.argtypes = [i64, i64, i64, DP, DP, u64, u32, u32, u32, i64, i64, i32, vp, vp, vp]
+    L.mlmc_matmul_adjoint_workspace_size.restype = ctypes.c_size_t
+    L.mlmc_matmul_adjoint_workspace_size.argtypes = [i64, i64, i64, LP]
+    L.mlmc_matmul_adjoint_reparam.restype = ctypes.c_int
+    L.mlmc_matmul_adjoint_reparam.argtypes = [i64, i64, i64, DP, DP, LP, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
     L.mlmc_status_string.restype = ctypes.c_char_p
     L.mlmc_status_string.argtypes = [ctypes.c_int]
     L.mlmc_last_error.restype = ctypes.c_char_p

@@ -1,0 +1,265 @@
+// Adjoint of the matrix estimator for reparameterised laws
+//   A = M_A + S_A o Z,  B = M_B + S_B o W  (Z, W standard normal, entrywise).
+//
+// The estimate is Y = sum_l (1/N_l) sum_k D_{l,k} with
+// D_{l,k} = (n / c_l) sum_t w_t a_t b_t^T (w_t = 1 - c_l / c_{l-1} for the c_{l-1}
+// coarse draws, 1 otherwise; Alg. 1 with the prefix coupling).  Y is bilinear
+// in (a_t, b_t), so for an upstream gradient G = dL/dY (m x p)
+//   dL/da_t = kappa_t G b_t,   dL/db_t = kappa_t G^T a_t,   kappa_t = (n / c_l) w_t / N_l,
+// and the chain rule through a_t = M_A[:, r_t] + S_A[:, r_t] o z_t gives
+//   dM_A[:, r_t] += dL/da_t,  dS_A[:, r_t] += dL/da_t o z_t   (likewise for B).
+// Nothing of the forward pass is stored: the indices and normals of every
+// realisation are regenerated from the counter-based stream, exactly as the
+// forward drew them, and the sampled columns are regenerated from M and S.
+//
+// Per pass over a batch of realisations of one level:
+//   adjoint_gather:  per realisation, A_S^T (m x K, [i][t]), B_S^T (p x K,
+//                    [q][t]) for the MFMA operands, Z_S (K x m, [t][i]) and
+//                    W_S (K x p, [t][q]) for the epilogue, and the indices;
+//   adjoint_mfma:    U^T = B_S G^T (K x m) and V = A_S^T G (K x p) with
+//                    v_mfma_f32_32x32x2_f32; each output row t is scaled by
+//                    kappa_t and added (FP32 atomics, a contiguous row of the
+//                    gradient per draw) into row r_t of dM/dS.
+#include "internal.hpp"
+
+namespace mlmc {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kAdjGatherThreads = 64;
+constexpr int kAdjPositions = 8;
+constexpr int kAdjThreads = 256;
+constexpr int kAdjTile = 64;          // output tile 64 x 64: 2 x 2 waves of 32 x 32
+constexpr int kAdjKStep = 2;
+constexpr int64_t kAdjBudget = 192ll << 20;
+
+struct AdjGatherParams {
+    int64_t m, p;
+    uint32_t n, c, c_prev;
+    int64_t kpad;                 // draws per realisation rounded up to kAdjPositions
+    uint32_t key0, key1, sid_index, sid_value;
+    uint32_t k_first;
+    Law A, B;
+    float* AT;                    // batch x m x kpad
+    float* BT;                    // batch x p x kpad
+    float* ZS;                    // batch x kpad x m
+    float* WS;                    // batch x kpad x p
+    int32_t* R;                   // batch x kpad (-1 for padding)
+};
+
+__global__ __launch_bounds__(kAdjGatherThreads) void adjoint_gather_kernel(AdjGatherParams prm)
+{
+    __shared__ uint32_t cols[kAdjPositions];
+    __shared__ int valid[kAdjPositions];
+    const int64_t pos0 = (int64_t)blockIdx.x * kAdjPositions;
+    const int64_t slot = blockIdx.y;
+    const uint32_t k = prm.k_first + (uint32_t)slot;
+    if (threadIdx.x < kAdjPositions) {
+        const int64_t t = pos0 + threadIdx.x;
+        const bool ok = t < (int64_t)prm.c;
+        valid[threadIdx.x] = ok;
+        const uint32_t j = ok ? draw_index((uint32_t)t, k, prm.sid_index, prm.key0, prm.key1, prm.n) : 0u;
+        cols[threadIdx.x] = j;
+        prm.R[slot * prm.kpad + t] = ok ? (int32_t)j : -1;
+    }
+    __syncthreads();
+    const int64_t rows = prm.m + prm.p;
+    const int64_t quads = ceil_div(rows, 4);
+    float* AT = prm.AT + slot * prm.m * prm.kpad;
+    float* BT = prm.BT + slot * prm.p * prm.kpad;
+    float* ZS = prm.ZS + slot * prm.kpad * prm.m;
+    float* WS = prm.WS + slot * prm.kpad * prm.p;
+    for (int64_t q = threadIdx.x; q < quads; q += kAdjGatherThreads) {
+        float val[kAdjPositions][4], nrm[kAdjPositions][4];
+        for (int ip = 0; ip < kAdjPositions; ++ip) {
+            if (!valid[ip]) {
+                for (int r = 0; r < 4; ++r) { val[ip][r] = 0.0f; nrm[ip][r] = 0.0f; }
+                continue;
+            }
+            const uint32_t j = cols[ip];
+            const Words4 w = philox4x32_10((uint32_t)q, k, j, prm.sid_value, prm.key0, prm.key1);
+            float u[4], z[4];
+            quad_values<float>(w, true, u[0], u[1], u[2], u[3], z[0], z[1], z[2], z[3]);
+            for (int r = 0; r < 4; ++r) {
+                const int64_t e = 4 * q + r;
+                float v = 0.0f;
+                if (e < prm.m) v = law_value<float>(prm.A, z[r], u[r], (int64_t)j * prm.A.ld + e);
+                else if (e < rows) v = law_value<float>(prm.B, z[r], u[r], (int64_t)j * prm.B.ld + (e - prm.m));
+                val[ip][r] = v;
+                nrm[ip][r] = z[r];
+            }
+        }
+        for (int r = 0; r < 4; ++r) {
+            const int64_t e = 4 * q + r;
+            if (e >= rows) break;
+            const bool in_a = e < prm.m;
+            const int64_t row = in_a ? e : e - prm.m;
+            float* T = in_a ? AT + row * prm.kpad : BT + row * prm.kpad;
+            float* N = in_a ? ZS : WS;
+            const int64_t R = in_a ? prm.m : prm.p;
+            for (int ip = 0; ip < kAdjPositions; ++ip) {
+                T[pos0 + ip] = val[ip][r];
+                N[(pos0 + ip) * R + row] = nrm[ip][r];
+            }
+        }
+    }
+}
+
+struct AdjMfmaParams {
+    int64_t m, p, kpad;
+    uint32_t c_prev;
+    float kappa_coarse, kappa_fine;   // (n / c_l) w_t / N_l for the two segments
+    const float* GT;                  // p x m: G^T
+    const float* G;                   // m x p
+    const float* AT;                  // batch x m x kpad
+    const float* BT;                  // batch x p x kpad
+    const float* ZS;                  // batch x kpad x m
+    const float* WS;                  // batch x kpad x p
+    const int32_t* R;                 // batch x kpad
+    int64_t tiles_t, tiles_u_cols, tiles_v_cols;
+    float* dMA; float* dSA;           // n x m
+    float* dMB; float* dSB;           // n x p
+};
+
+// One 64 x 64 tile of U^T (rows t, columns i; K = p) or of V (rows t,
+// columns q; K = m) for one realisation, then the scaled scatter-add.
+__global__ __launch_bounds__(kAdjThreads) void adjoint_mfma_kernel(AdjMfmaParams prm)
+{
+    const int lane = threadIdx.x % kWave;
+    const int wave = threadIdx.x / kWave;
+    const int64_t s = blockIdx.y;
+    int64_t tile = blockIdx.x;
+    const int64_t u_tiles = prm.tiles_t * prm.tiles_u_cols;
+    const bool is_u = tile < u_tiles;
+    if (!is_u) tile -= u_tiles;
+    const int64_t cols_tiles = is_u ? prm.tiles_u_cols : prm.tiles_v_cols;
+    const int64_t t0 = (tile / cols_tiles) * kAdjTile + (wave / 2) * 32;
+    const int64_t x0 = (tile % cols_tiles) * kAdjTile + (wave % 2) * 32;
+    const int64_t K = is_u ? prm.p : prm.m;           // contraction length
+    const int64_t X = is_u ? prm.m : prm.p;           // output columns
+    // A operand rows t: the transposed gathered operand of the other matrix
+    const float* Aop = is_u ? prm.BT + s * prm.p * prm.kpad : prm.AT + s * prm.m * prm.kpad;
+    // B operand [k][x]: G^T (p x m) for U^T, G (m x p) for V
+    const float* Bop = is_u ? prm.GT : prm.G;
+    f32x16 acc;
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    const int64_t t_lane = t0 + lane % 32;
+    const int64_t x_lane = x0 + lane % 32;
+    for (int64_t kk = 0; kk < K; kk += kAdjKStep) {
+        const int64_t kr = kk + lane / 32;
+        const float a = (kr < K && t_lane < prm.kpad) ? Aop[kr * prm.kpad + t_lane] : 0.0f;
+        const float b = (kr < K && x_lane < X) ? Bop[kr * X + x_lane] : 0.0f;
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+    }
+    // epilogue: lane l, register r holds row t0 + 8(r/4) + 4(l/32) + r%4, column x0 + l%32
+    const int32_t* R = prm.R + s * prm.kpad;
+    const float* N = is_u ? prm.ZS + s * prm.kpad * prm.m : prm.WS + s * prm.kpad * prm.p;
+    float* dM = is_u ? prm.dMA : prm.dMB;
+    float* dS = is_u ? prm.dSA : prm.dSB;
+    if (x_lane >= X) return;
+    for (int r = 0; r < 16; ++r) {
+        const int64_t t = t0 + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
+        if (t >= prm.kpad) continue;
+        const int32_t col = R[t];
+        if (col < 0) continue;
+        const float kappa = t < (int64_t)prm.c_prev ? prm.kappa_coarse : prm.kappa_fine;
+        const float g = kappa * acc[r];
+        unsafeAtomicAdd(dM + (int64_t)col * X + x_lane, g);
+        unsafeAtomicAdd(dS + (int64_t)col * X + x_lane, g * N[t * X + x_lane]);
+    }
+}
+
+__global__ void grad_prepare_kernel(const double* grad, int64_t m, int64_t p, float* G, float* GT)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m * p) return;
+    const int64_t i = e / p, q = e % p;
+    const float v = (float)grad[e];
+    G[e] = v;
+    GT[q * m + i] = v;
+}
+
+static int64_t round_up_adj(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+size_t adjoint_workspace_size(int64_t m, int64_t p, int num_levels, const int64_t* c)
+{
+    const int64_t kpad = round_up_adj(c[num_levels - 1], kAdjPositions);
+    const int64_t per_sample = kpad * (2 * (m + p) * 4 + 4);
+    int64_t budget = kAdjBudget < per_sample ? per_sample : kAdjBudget;
+    size_t total = (size_t)budget + 1024;
+    total += (size_t)(2 * m * p * 4 + 256);
+    return total;
+}
+
+hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law& B, int num_levels,
+                       const int64_t* c, const int64_t* N, const StreamKeys& keys, bool shared,
+                       const double* grad, float* dMA, float* dSA, float* dMB, float* dSB, char* ws,
+                       size_t ws_bytes, hipStream_t stream, KernelTimer* timer)
+{
+    auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    float* G = reinterpret_cast<float*>(ws);
+    float* GT = G + m * p;
+    char* buf = ws + align(2 * m * p * sizeof(float));
+    const size_t budget = ws_bytes - align(2 * m * p * sizeof(float));
+    {
+        ScopedTiming t(timer, 3);
+        hipLaunchKernelGGL(grad_prepare_kernel, dim3((unsigned)ceil_div(m * p, 256)), dim3(256), 0, stream, grad, m,
+                           p, G, GT);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    for (int l = 0; l < num_levels; ++l) {
+        const int64_t cl = c[l], cp = l > 0 ? c[l - 1] : 0;
+        const int64_t kpad = round_up_adj(cl, kAdjPositions);
+        const size_t per_sample = (size_t)kpad * (2 * (m + p) * 4 + 4) + 5 * 256;
+        int64_t batch = (int64_t)(budget / per_sample);
+        if (batch < 1) batch = 1;
+        if (batch > 65535) batch = 65535;
+        const double base = (double)n / (double)cl / (double)N[l];
+        const float kc = (float)(base * (cp > 0 ? 1.0 - (double)cl / (double)cp : 1.0));
+        const float kf = (float)base;
+        for (int64_t b0 = 0; b0 < N[l]; b0 += batch) {
+            const int64_t S = (N[l] - b0) < batch ? (N[l] - b0) : batch;
+            size_t off = 0;
+            float* AT = reinterpret_cast<float*>(buf + off); off = align(off + sizeof(float) * S * m * kpad);
+            float* BT = reinterpret_cast<float*>(buf + off); off = align(off + sizeof(float) * S * p * kpad);
+            float* ZS = reinterpret_cast<float*>(buf + off); off = align(off + sizeof(float) * S * kpad * m);
+            float* WS = reinterpret_cast<float*>(buf + off); off = align(off + sizeof(float) * S * kpad * p);
+            int32_t* Rr = reinterpret_cast<int32_t*>(buf + off); off = align(off + sizeof(int32_t) * S * kpad);
+            if (off > budget) return hipErrorInvalidValue;
+            AdjGatherParams g;
+            g.m = m; g.p = p; g.n = (uint32_t)n; g.c = (uint32_t)cl; g.c_prev = (uint32_t)cp; g.kpad = kpad;
+            g.key0 = keys.key0; g.key1 = keys.key1;
+            const uint32_t lf = shared ? 0xFFu : (uint32_t)l;
+            g.sid_index = stream_id(kTagIndex, lf, keys.problem);
+            g.sid_value = stream_id(kTagValue, lf, keys.problem);
+            g.k_first = (uint32_t)b0;
+            g.A = A; g.B = B;
+            g.AT = AT; g.BT = BT; g.ZS = ZS; g.WS = WS; g.R = Rr;
+            {
+                ScopedTiming t(timer, 1);
+                hipLaunchKernelGGL(adjoint_gather_kernel, dim3((unsigned)(kpad / kAdjPositions), (unsigned)S),
+                                   dim3(kAdjGatherThreads), 0, stream, g);
+            }
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            AdjMfmaParams a;
+            a.m = m; a.p = p; a.kpad = kpad; a.c_prev = (uint32_t)cp;
+            a.kappa_coarse = kc; a.kappa_fine = kf;
+            a.GT = GT; a.G = G; a.AT = AT; a.BT = BT; a.ZS = ZS; a.WS = WS; a.R = Rr;
+            a.tiles_t = ceil_div(kpad, kAdjTile);
+            a.tiles_u_cols = ceil_div(m, kAdjTile);
+            a.tiles_v_cols = ceil_div(p, kAdjTile);
+            a.dMA = dMA; a.dSA = dSA; a.dMB = dMB; a.dSB = dSB;
+            const int64_t tiles = a.tiles_t * (a.tiles_u_cols + a.tiles_v_cols);
+            {
+                ScopedTiming t(timer, 0);
+                hipLaunchKernelGGL(adjoint_mfma_kernel, dim3((unsigned)tiles, (unsigned)S), dim3(kAdjThreads), 0,
+                                   stream, a);
+            }
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+}  // namespace mlmc

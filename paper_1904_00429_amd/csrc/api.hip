@@ -398,6 +398,40 @@ mlmc_status mlmc_matmul_estimate(int64_t m, int64_t n, int64_t p, const mlmc_dis
     return MLMC_OK;
 }
 
+size_t mlmc_matmul_adjoint_workspace_size(int64_t m, int64_t n, int64_t p, const mlmc_levels* levels)
+{
+    if (check_levels(levels, false) != MLMC_OK || m < 1 || p < 1 || n < 1) return 0;
+    return adjoint_workspace_size(m, p, levels->num_levels, levels->c);
+}
+
+mlmc_status mlmc_matmul_adjoint_reparam(int64_t m, int64_t n, int64_t p, const mlmc_dist* A, const mlmc_dist* B,
+                                        const mlmc_levels* lv, const double* grad_out, float* dMA, float* dSA,
+                                        float* dMB, float* dSB, void* workspace, size_t workspace_bytes,
+                                        void* stream_ptr)
+{
+    g_last_error.clear();
+    if (m < 1 || p < 1 || n < 1) return fail(MLMC_EINVAL, "m, n, p must be >= 1");
+    if (n >= kU32) return fail(MLMC_EINVAL, "n must be < 2^32");
+    mlmc_status st = check_levels(lv, false);
+    if (st != MLMC_OK) return st;
+    if (lv->rmse_target > 0.0 || !lv->n_samples)
+        return fail(MLMC_EINVAL, "the adjoint needs the forward's N_l (fixed mode)");
+    if ((st = check_dist(A, "A", m, false)) != MLMC_OK) return st;
+    if ((st = check_dist(B, "B", p, false)) != MLMC_OK) return st;
+    if (A->law != MLMC_LAW_REPARAM || B->law != MLMC_LAW_REPARAM)
+        return fail(MLMC_EINVAL, "the adjoint is defined for reparameterised laws");
+    if (!grad_out || !dMA || !dSA || !dMB || !dSB) return fail(MLMC_EINVAL, "null gradient pointer");
+    const size_t need = adjoint_workspace_size(m, p, lv->num_levels, lv->c);
+    if (!workspace || workspace_bytes < need) return fail(MLMC_EWORKSPACE, "workspace needs %zu bytes", need);
+    hipStream_t stream = static_cast<hipStream_t>(stream_ptr);
+    KernelTimer timer_obj(stream);
+    KernelTimer* timer = (lv->flags & MLMC_FLAG_TIMING) ? &timer_obj : nullptr;
+    hipError_t e = adjoint_run(m, n, p, to_law(*A), to_law(*B), lv->num_levels, lv->c, lv->n_samples, keys_of(lv),
+                               (lv->flags & MLMC_FLAG_SHARED_SAMPLES) != 0, grad_out, dMA, dSA, dMB, dSB,
+                               static_cast<char*>(workspace), workspace_bytes, stream, timer);
+    return e == hipSuccess ? MLMC_OK : device_fail(e, "adjoint launch");
+}
+
 mlmc_status mlmc_philox4x32_10(int64_t count, const uint32_t* ctr, uint64_t seed, uint32_t* out, void* stream)
 {
     g_last_error.clear();

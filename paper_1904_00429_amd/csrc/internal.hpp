@@ -96,6 +96,13 @@ double* matmul_level_var_ptr(const MatmulPlan& plan, char* ws);
 
 hipError_t fill_doubles(double* p, int64_t count, double v, hipStream_t stream);
 
+// ---- adjoint of the matrix estimator (reparameterised laws) ---------------
+size_t adjoint_workspace_size(int64_t m, int64_t p, int num_levels, const int64_t* c);
+hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law& B, int num_levels,
+                       const int64_t* c, const int64_t* N, const StreamKeys& keys, bool shared,
+                       const double* grad, float* dMA, float* dSA, float* dMB, float* dSB, char* ws,
+                       size_t ws_bytes, hipStream_t stream, KernelTimer* timer);
+
 // ---- building blocks exported for tests -----------------------------------
 hipError_t philox_batch(int64_t count, const uint32_t* ctr, uint32_t key0, uint32_t key1,
                         uint32_t* out, hipStream_t stream);

@@ -197,3 +197,29 @@ def gather_columns(m: int, n: int, p: int, A: Law, B: Law, seed: int, problem: i
                                     int(seed) & (2**64 - 1), problem, level_field, k0, num_samples,
                                     c, PREC[prec], AS.data_ptr(), BS.data_ptr(), _stream(device)))
     return AS, BS
+
+
+def matmul_adjoint_reparam(MA: torch.Tensor, SA: torch.Tensor, MB: torch.Tensor, SB: torch.Tensor,
+                           c: Sequence[int], n_samples: Sequence[int], grad_out: torch.Tensor,
+                           seed: int = 0, problem: int = 0, shared: bool = False,
+                           workspace: Optional[torch.Tensor] = None):
+    """Gradients of <grad_out, Y> with respect to M_A, S_A, M_B, S_B
+    (mlmc_matmul_adjoint_reparam).  MA, SA: (n, m) FP32 device tensors (row j =
+    column j of A); MB, SB: (n, p).  Returns (dMA, dSA, dMB, dSB), FP32."""
+    n, m = MA.shape
+    p = MB.shape[1]
+    device = MA.device
+    A, B = Law.reparam(MA, SA), Law.reparam(MB, SB)
+    h = _LevelsHolder(c, n_samples, 0.0, 0, seed, "fp32", shared, problem, 0)
+    ws_bytes = int(lib().mlmc_matmul_adjoint_workspace_size(int(m), int(n), int(p), ctypes.byref(h.lv)))
+    if ws_bytes == 0:
+        raise MLMCError(1, "invalid problem: no workspace size")
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=device)
+    g = grad_out.to(device=device, dtype=torch.float64).contiguous()
+    grads = [torch.zeros_like(t) for t in (MA, SA, MB, SB)]
+    da, db = A.c(), B.c()
+    check(lib().mlmc_matmul_adjoint_reparam(int(m), int(n), int(p), ctypes.byref(da), ctypes.byref(db),
+                                            ctypes.byref(h.lv), g.data_ptr(), *[t.data_ptr() for t in grads],
+                                            workspace.data_ptr(), ws_bytes, _stream(device)))
+    return tuple(grads)

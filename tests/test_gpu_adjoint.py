@@ -1,0 +1,147 @@
+"""GPU parity of the adjoint (mlmc_matmul_adjoint_reparam) and of the autograd
+Function built on it, against the FP64 torch-CPU gradient reference on the
+same seeds; finite differences of the GPU's own FP64 forward; and the
+seed-average against the closed-form gradient of a linear functional.
+
+Tolerance: FP32 adjoint, 1e-5 relative Frobenius per gradient array."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_helpers import flush, rel_frob
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _params(seed, n, m, p):
+    rng = np.random.default_rng(seed)
+    return [rng.standard_normal((n, m)).astype(np.float32), rng.uniform(0.1, 1, (n, m)).astype(np.float32),
+            rng.standard_normal((n, p)).astype(np.float32), rng.uniform(0.1, 1, (n, p)).astype(np.float32)]
+
+
+CASES = [
+    (5, 40, 3, [2, 4, 8], [40, 20, 10]),
+    (70, 300, 33, [16, 32, 64], [30, 12, 5]),
+    (64, 500, 130, [5, 10, 20, 40], [20, 10, 6, 3]),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_adjoint_matches_reference(orc, dev, case):
+    from oracle import grad as og
+    from paper_1904_00429_amd import matmul_adjoint_reparam
+    m, n, p, c, N = CASES[case]
+    flush(f"adjoint case={case} m={m} n={n} p={p} c={c} N={N}")
+    params = _params(case, n, m, p)
+    G = np.random.default_rng(50 + case).standard_normal((m, p))
+    _, ref = og.reparam_gradients(*params, c, N, G, seed=7)
+    dp = [torch.from_numpy(x).to(dev) for x in params]
+    got = matmul_adjoint_reparam(*dp, c, N, torch.from_numpy(G), seed=7)
+    for name, g, r in zip(("dMA", "dSA", "dMB", "dSB"), got, ref):
+        err = rel_frob(g.cpu().numpy(), r)
+        flush(f"  {name} rel err {err:.3g}")
+        assert err <= 1e-5, (name, err)
+
+
+def test_autograd_loss_gradient(orc, dev):
+    from oracle import grad as og
+    from paper_1904_00429_amd import mlmc_matmul
+    m, n, p, c, N = 24, 400, 17, [8, 16, 32], [30, 15, 8]
+    flush("autograd end to end")
+    params = _params(11, n, m, p)
+    T = np.random.default_rng(12).standard_normal((m, p))
+    leaves = [torch.from_numpy(x).to(dev).requires_grad_(True) for x in params]
+    Y = mlmc_matmul(*leaves, c, N, seed=3, prec="fp32")
+    loss = ((Y - torch.from_numpy(T).to(dev)) ** 2).sum()
+    loss.backward()
+    # reference: gradient of the same loss, G = 2 (Y - T) at the oracle's Y
+    Y_ref = og.reparam_estimate(*[torch.from_numpy(x.astype(np.float64)) for x in params], c, N, seed=3).numpy()
+    assert rel_frob(Y.detach().cpu().numpy(), Y_ref) <= 1e-5
+    _, ref = og.reparam_gradients(*params, c, N, 2 * (Y_ref - T), seed=3)
+    for g, r in zip(leaves, ref):
+        assert rel_frob(g.grad.cpu().numpy(), r) <= 1e-5
+
+
+def test_adjoint_full_shape_few_realisations(orc, dev):
+    """The differentiation workload's shapes (512 x 32768 x 512, c_l = 32 * 2^l,
+    l = 0..6) with a handful of realisations per level, against the reference."""
+    from oracle import grad as og
+    from paper_1904_00429_amd import matmul_adjoint_reparam
+    m, n, p = 512, 32768, 512
+    c = [32 * 2 ** l for l in range(7)]
+    N = [3, 2, 2, 1, 1, 1, 1]
+    flush("adjoint full shape")
+    params = _params(21, n, m, p)
+    G = np.random.default_rng(22).standard_normal((m, p))
+    _, ref = og.reparam_gradients(*params, c, N, G, seed=5)
+    dp = [torch.from_numpy(x).to(dev) for x in params]
+    got = matmul_adjoint_reparam(*dp, c, N, torch.from_numpy(G), seed=5)
+    for g, r in zip(got, ref):
+        assert rel_frob(g.cpu().numpy(), r) <= 1e-5
+
+
+def test_adjoint_matches_finite_differences_of_gpu_forward(dev):
+    """Y is affine in each single mean or scale entry, so a central difference of
+    the GPU's FP64 forward is exact up to rounding."""
+    from paper_1904_00429_amd import Law, matmul_adjoint_reparam, matmul_estimate
+    m, n, p, c, N = 9, 50, 7, [2, 4, 8], [40, 20, 10]
+    params = _params(31, n, m, p)
+    G = np.random.default_rng(32).standard_normal((m, p))
+    dp = [torch.from_numpy(x).to(dev) for x in params]
+    got = [g.cpu().numpy() for g in matmul_adjoint_reparam(*dp, c, N, torch.from_numpy(G), seed=9)]
+
+    def L(ps):
+        t = [torch.from_numpy(x).to(dev) for x in ps]
+        est = matmul_estimate(m, n, p, Law.reparam(t[0], t[1]), Law.reparam(t[2], t[3]), c, n_samples=N,
+                              seed=9, prec="fp64", device=dev)
+        return float((est.Y.cpu().numpy() * G).sum())
+
+    rng = np.random.default_rng(33)
+    checked = 0
+    for which in range(4):
+        # entries whose row was drawn carry a gradient; pick those
+        rows = np.nonzero(np.abs(got[which]).sum(axis=1))[0]
+        for _ in range(3):
+            j = int(rng.choice(rows))
+            i = int(rng.integers(0, params[which].shape[1]))
+            plus = [x.copy() for x in params]
+            minus = [x.copy() for x in params]
+            plus[which][j, i] = np.float32(params[which][j, i] + 0.25)
+            minus[which][j, i] = np.float32(params[which][j, i] - 0.25)
+            step = float(plus[which][j, i]) - float(minus[which][j, i])
+            fd = (L(plus) - L(minus)) / step
+            assert abs(fd - got[which][j, i]) <= 1e-5 * (1 + abs(fd)), (which, j, i, fd, got[which][j, i])
+            checked += 1
+    assert checked == 12
+
+
+def test_adjoint_seed_average_matches_closed_form(dev):
+    """E over seeds of grad <G0, Y> equals grad <G0, M_A M_B>:
+    (M_B G0^T, 0, M_A G0, 0) in the row-j layouts."""
+    from paper_1904_00429_amd import matmul_adjoint_reparam
+    m, n, p, c, N = 6, 16, 5, [2, 4], [8, 4]
+    params = _params(41, n, m, p)
+    G0 = np.random.default_rng(42).standard_normal((m, p))
+    dp = [torch.from_numpy(x).to(dev) for x in params]
+    seeds = 400
+    acc = [np.zeros((seeds,) + x.shape) for x in params]
+    for s in range(seeds):
+        g = matmul_adjoint_reparam(*dp, c, N, torch.from_numpy(G0), seed=10_000 + s)
+        for i in range(4):
+            acc[i][s] = g[i].cpu().numpy()
+    MA, SA, MB, SB = [x.astype(np.float64) for x in params]
+    expected = [MB @ G0.T, np.zeros_like(SA), MA @ G0, np.zeros_like(SB)]
+    for i in range(4):
+        mean = acc[i].mean(axis=0)
+        se = acc[i].std(axis=0, ddof=1) / math.sqrt(seeds) + 1e-9
+        z = np.abs(mean - expected[i]) / se
+        assert z.max() < 5.5, (i, z.max())
