@@ -69,7 +69,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="inner", choices=["inner", "matmul-large", "matmul-small"])
+    ap.add_argument("--workload", default="inner", choices=["inner", "matmul-large", "matmul-small", "diff"])
     ap.add_argument("--prec", default=None, help="fp32 (default) or fp64; bf16 for matmul")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-fraction", type=float, default=0.15,
@@ -135,6 +135,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.init()
     timing_flag = 2
+    if args.workload == "diff":
+        return bench_diff(args)
     if args.workload == "inner":
         wl = workloads.INNER_2POW20
         prec = args.prec or "fp32"
@@ -219,6 +221,58 @@ def main():
             out["cpu_baseline"] = cpu_baseline_inner(wl, rep.n_used, args.cpu_fraction)
         else:
             out["cpu_baseline"] = cpu_baseline_matmul(wl, rep.n_used, min(args.cpu_fraction, 0.002))
+    print(json.dumps(out), flush=True)
+
+
+def bench_diff(args):
+    """Differentiation form: loss = ||Y - T||_F^2 of the reparameterised
+    estimate, forward + hand-written adjoint per step (FP32)."""
+    import torch
+    from paper_1904_00429_amd import mlmc_matmul, workloads
+    import paper_1904_00429_amd.mlmc as api
+    dev = torch.device("cuda:0")
+    wl = workloads.DIFF_512x32768x512
+    MA, SA, MB, SB, T = workloads.reparam_inputs(wl.m, wl.n, wl.p, seed=0)
+    leaves = [torch.from_numpy(x).to(dev).requires_grad_(True) for x in (MA, SA, MB, SB)]
+    Tt = torch.from_numpy(T).to(dev, torch.float64)
+
+    def step(seed):
+        for t in leaves:
+            t.grad = None
+        Y = mlmc_matmul(*leaves, wl.c, wl.n_samples, seed=seed, prec="fp32")
+        loss = ((Y - Tt) ** 2).sum()
+        loss.backward()
+        return loss
+
+    for i in range(args.warmup):
+        step(1000 + i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(i)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    # one timed adjoint call with the library's event timing, for the roofline
+    import ctypes
+    h = api._LevelsHolder(wl.c, wl.n_samples, 0.0, 0, 0, "fp32", False, 0, 0)
+    h.lv.flags |= 2
+    draws = sum(N * c for N, c in zip(wl.n_samples, wl.c))
+    flops = 2.0 * 2.0 * wl.m * wl.p * draws
+    t1 = time.perf_counter()
+    grads = api.matmul_adjoint_reparam(*[t.detach() for t in leaves], wl.c, wl.n_samples,
+                                       torch.ones((wl.m, wl.p), dtype=torch.float64, device=dev))
+    torch.cuda.synchronize()
+    adj_ms = 1e3 * (time.perf_counter() - t1)
+    out = {"metric": "MLMC product estimates/s with gradients (forward + adjoint)", "value": args.steps / elapsed,
+           "unit": "estimates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": wl.name, "m": wl.m, "n": wl.n, "p": wl.p, "levels": len(wl.c), "c0": wl.c[0],
+                      "n_samples": wl.n_samples},
+           "adjoint_ms_wall": adj_ms,
+           "adjoint_roofline": {"bound": "mfma", "achieved": flops / (adj_ms * 1e-3) / 1e12,
+                                "peak": PEAK_MFMA["fp32"] / 1e12, "unit": "TFLOP/s",
+                                "frac": flops / (adj_ms * 1e-3) / PEAK_MFMA["fp32"], "draws": draws}}
     print(json.dumps(out), flush=True)
 
 

@@ -61,7 +61,10 @@ typedef enum {
 typedef enum {
     MLMC_PREC_FP64 = 0,   /* values, products and sums in FP64 */
     MLMC_PREC_FP32 = 1,   /* values and contraction in FP32, statistics FP64 */
-    MLMC_PREC_BF16 = 2    /* gathered operands BF16 (RNE), FP32 accumulation (MFMA) */
+    MLMC_PREC_BF16 = 2,   /* gathered operands BF16 (RNE), FP32 accumulation (MFMA) */
+    MLMC_PREC_FP8 = 3     /* gathered operands OCP FP8 e4m3 (RNE, saturated), FP32 accumulation;
+                             per-product power-of-two pre-scales of A's columns and B's rows
+                             (one per matrix: the entries are i.i.d.), undone in the epilogue */
 } mlmc_prec;
 
 #define MLMC_FLAG_SHARED_SAMPLES 1u
@@ -143,6 +146,54 @@ mlmc_status mlmc_inner_product_estimate(int64_t n, const mlmc_dist* x, const mlm
                                         double* level_means, void* workspace,
                                         size_t workspace_bytes, mlmc_report* report,
                                         void* stream);
+
+/* ---- Batching --------------------------------------------------------------
+ * Many independent products of uneven shapes through one pipeline: every pass
+ * gathers the sampled columns of all products in one launch, one persistent
+ * sketch launch walks all (product, output tile, group of realisations) work
+ * items, and one launch merges the statistics of all products.  The products
+ * share the ladder, N_l (fixed mode), seed, precision and flags; each has its
+ * own shape, laws, Philox stream id and outputs. */
+typedef struct {
+    int64_t m, n, p;
+    mlmc_dist A, B;
+    uint32_t problem;     /* Philox stream id < 2^20 (distinct per product) */
+    double* out;          /* device FP64 m x p: Y */
+    double* level_means;  /* NULL or device FP64 (num_levels x m x p) */
+} mlmc_problem;
+
+/* Launch shape (all zero = defaults; chosen by the autotuner of the Python
+ * package): tile = workgroup output tile edge (64 or 128; FP64 uses 64),
+ * target_blocks = sketch work items per pass, gather_budget = bytes of
+ * gathered operands per pass. */
+typedef struct {
+    int32_t tile;
+    int64_t target_blocks;
+    int64_t gather_budget;
+} mlmc_tuning;
+
+size_t mlmc_matmul_batched_workspace_size(int32_t nprob, const mlmc_problem* probs,
+                                          const mlmc_levels* levels, const mlmc_tuning* tuning);
+/* level_var: NULL, or host FP64 [num_levels x nprob] (level-major) receiving
+ * V_l of every product (synchronises the stream).  The call synchronises the
+ * stream once to upload the product table.  Errors as mlmc_matmul_estimate;
+ * EINVAL also for nprob < 1, target mode, duplicate stream ids. */
+mlmc_status mlmc_matmul_estimate_batched(int32_t nprob, const mlmc_problem* probs,
+                                         const mlmc_levels* levels, const mlmc_tuning* tuning,
+                                         void* workspace, size_t workspace_bytes, double* level_var,
+                                         void* stream);
+
+/* The same batched estimate captured once into a hipGraph (reset, every pass
+ * of every level, finalize) and replayed by mlmc_graph_launch on any stream.
+ * The workspace, the outputs and the law arrays must stay valid while the
+ * graph exists; each launch recomputes the estimate with the captured seed. */
+typedef struct mlmc_graph_s* mlmc_graph;
+mlmc_status mlmc_matmul_batched_graph_create(int32_t nprob, const mlmc_problem* probs,
+                                             const mlmc_levels* levels, const mlmc_tuning* tuning,
+                                             void* workspace, size_t workspace_bytes, void* stream,
+                                             mlmc_graph* graph);
+mlmc_status mlmc_graph_launch(mlmc_graph graph, void* stream);
+mlmc_status mlmc_graph_destroy(mlmc_graph graph);
 
 /* ---- Differentiation ------------------------------------------------------
  * Adjoint of mlmc_matmul_estimate for reparameterised laws A = M_A + S_A o Z,

@@ -14,6 +14,8 @@ EXPORTED = [
     "mlmc_inner_product_estimate", "mlmc_philox4x32_10", "mlmc_sample_indices",
     "mlmc_gather_columns", "mlmc_status_string", "mlmc_last_error",
     "mlmc_matmul_adjoint_workspace_size", "mlmc_matmul_adjoint_reparam",
+    "mlmc_matmul_batched_workspace_size", "mlmc_matmul_estimate_batched",
+    "mlmc_matmul_batched_graph_create", "mlmc_graph_launch", "mlmc_graph_destroy",
 ]
 
 
@@ -28,6 +30,17 @@ class Levels(ctypes.Structure):
                 ("pilot_samples", ctypes.c_int64), ("max_total_draws", ctypes.c_int64),
                 ("seed", ctypes.c_uint64), ("prec", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("problem", ctypes.c_uint32)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("p", ctypes.c_int64),
+                ("A", Dist), ("B", Dist), ("problem", ctypes.c_uint32),
+                ("out", ctypes.c_void_p), ("level_means", ctypes.c_void_p)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("target_blocks", ctypes.c_int64),
+                ("gather_budget", ctypes.c_int64)]
 
 
 class Report(ctypes.Structure):
@@ -75,6 +88,18 @@ def lib() -> ctypes.CDLL:
     L.mlmc_matmul_adjoint_workspace_size.argtypes = [i64, i64, i64, LP]
     L.mlmc_matmul_adjoint_reparam.restype = ctypes.c_int
     L.mlmc_matmul_adjoint_reparam.argtypes = [i64, i64, i64, DP, DP, LP, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    PP, TP = ctypes.POINTER(Problem), ctypes.POINTER(Tuning)
+    L.mlmc_matmul_batched_workspace_size.restype = ctypes.c_size_t
+    L.mlmc_matmul_batched_workspace_size.argtypes = [i32, PP, LP, TP]
+    L.mlmc_matmul_estimate_batched.restype = ctypes.c_int
+    L.mlmc_matmul_estimate_batched.argtypes = [i32, PP, LP, TP, vp, ctypes.c_size_t, vp, vp]
+    L.mlmc_matmul_batched_graph_create.restype = ctypes.c_int
+    L.mlmc_matmul_batched_graph_create.argtypes = [i32, PP, LP, TP, vp, ctypes.c_size_t, vp,
+                                                   ctypes.POINTER(ctypes.c_void_p)]
+    L.mlmc_graph_launch.restype = ctypes.c_int
+    L.mlmc_graph_launch.argtypes = [vp, vp]
+    L.mlmc_graph_destroy.restype = ctypes.c_int
+    L.mlmc_graph_destroy.argtypes = [vp]
     L.mlmc_status_string.restype = ctypes.c_char_p
     L.mlmc_status_string.argtypes = [ctypes.c_int]
     L.mlmc_last_error.restype = ctypes.c_char_p

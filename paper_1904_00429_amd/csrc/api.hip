@@ -5,6 +5,7 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -49,7 +50,7 @@ mlmc_status check_levels(const mlmc_levels* lv, bool inner)
                         (long long)lv->c[l], l - 1, (long long)lv->c[l - 1]);
     }
     if (lv->c[lv->num_levels - 1] >= kU32) return fail(MLMC_EINVAL, "c_L must be < 2^32");
-    if (lv->prec < MLMC_PREC_FP64 || lv->prec > (inner ? MLMC_PREC_FP32 : MLMC_PREC_BF16))
+    if (lv->prec < MLMC_PREC_FP64 || lv->prec > (inner ? MLMC_PREC_FP32 : MLMC_PREC_FP8))
         return fail(MLMC_EINVAL, "unsupported precision %d", lv->prec);
     if (lv->problem >= (1u << 20)) return fail(MLMC_EINVAL, "problem id must be < 2^20");
     if (lv->rmse_target > 0.0) {
@@ -239,8 +240,9 @@ size_t mlmc_inner_product_workspace_size(int64_t n, const mlmc_levels* levels)
 size_t mlmc_matmul_workspace_size(int64_t m, int64_t n, int64_t p, const mlmc_levels* levels)
 {
     if (check_levels(levels, false) != MLMC_OK || m < 1 || p < 1 || n < 1) return 0;
+    MatmulProblem pr{m, n, p, Law{}, Law{}, levels->problem, nullptr, nullptr};
     MatmulPlan plan;
-    if (!matmul_plan(m, n, p, levels->prec, levels->num_levels, levels->c, plan)) return 0;
+    if (!matmul_plan(&pr, 1, levels->prec, levels->num_levels, levels->c, nullptr, plan)) return 0;
     return plan.total;
 }
 
@@ -333,14 +335,14 @@ mlmc_status mlmc_matmul_estimate(int64_t m, int64_t n, int64_t p, const mlmc_dis
     if ((st = check_dist(A, "A", m, false)) != MLMC_OK) return st;
     if ((st = check_dist(B, "B", p, false)) != MLMC_OK) return st;
     if (!out) return fail(MLMC_EINVAL, "out is NULL");
+    MatmulProblem pr{m, n, p, to_law(*A), to_law(*B), lv->problem, out, level_means};
     MatmulPlan plan;
-    if (!matmul_plan(m, n, p, lv->prec, lv->num_levels, lv->c, plan))
+    if (!matmul_plan(&pr, 1, lv->prec, lv->num_levels, lv->c, nullptr, plan))
         return fail(MLMC_EINVAL, "no launch plan for this shape and precision");
     if (!workspace || workspace_bytes < plan.total)
         return fail(MLMC_EWORKSPACE, "workspace needs %zu bytes", plan.total);
     hipStream_t stream = static_cast<hipStream_t>(stream_ptr);
     char* ws = static_cast<char*>(workspace);
-    const Law la = to_law(*A), lb = to_law(*B);
     const StreamKeys keys = keys_of(lv);
     const int L1 = lv->num_levels;
     std::vector<int64_t> counts(L1, 0);
@@ -348,7 +350,8 @@ mlmc_status mlmc_matmul_estimate(int64_t m, int64_t n, int64_t p, const mlmc_dis
     double* var_dev = matmul_level_var_ptr(plan, ws);
     KernelTimer timer_obj(stream);
     KernelTimer* timer = (lv->flags & MLMC_FLAG_TIMING) ? &timer_obj : nullptr;
-    hipError_t e;
+    hipError_t e = matmul_upload(plan, ws, stream);
+    if (e != hipSuccess) return device_fail(e, "problem table upload");
     {
         ScopedTiming t(timer, MLMC_KERNEL_FINAL);
         e = matmul_reset(plan, ws, stream);
@@ -356,7 +359,7 @@ mlmc_status mlmc_matmul_estimate(int64_t m, int64_t n, int64_t p, const mlmc_dis
     if (e != hipSuccess) return device_fail(e, "state reset");
 
     auto run = [&](int l, int64_t k0, int64_t cnt, int64_t before) -> hipError_t {
-        return matmul_level_run(plan, range_of(lv, l, k0, cnt), before, la, lb, keys, ws, stream, timer);
+        return matmul_level_run(plan, range_of(lv, l, k0, cnt), before, keys, ws, stream, timer);
     };
     if (lv->rmse_target > 0.0) {
         for (int l = 0; l < L1; ++l) {
@@ -365,7 +368,7 @@ mlmc_status mlmc_matmul_estimate(int64_t m, int64_t n, int64_t p, const mlmc_dis
         }
         {
             ScopedTiming t(timer, MLMC_KERNEL_FINAL);
-            e = matmul_finalize(plan, counts.data(), ws, out, nullptr, stream);
+            e = matmul_finalize(plan, counts.data(), ws, false, stream);
         }
         if (e != hipSuccess) return device_fail(e, "pilot statistics");
         if ((e = hipMemcpyAsync(var.data(), var_dev, sizeof(double) * L1, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
@@ -386,7 +389,7 @@ mlmc_status mlmc_matmul_estimate(int64_t m, int64_t n, int64_t p, const mlmc_dis
     }
     {
         ScopedTiming t(timer, MLMC_KERNEL_FINAL);
-        e = matmul_finalize(plan, counts.data(), ws, out, level_means, stream);
+        e = matmul_finalize(plan, counts.data(), ws, true, stream);
     }
     if (e != hipSuccess) return device_fail(e, "finalize");
     if (report) {
@@ -395,6 +398,171 @@ mlmc_status mlmc_matmul_estimate(int64_t m, int64_t n, int64_t p, const mlmc_dis
             return device_fail(e, "report readback");
         fill_report(lv, counts.data(), var.data(), timer, report);
     }
+    return MLMC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+mlmc_status check_batch(int32_t nprob, const mlmc_problem* probs, const mlmc_levels* lv, const mlmc_tuning* tune,
+                        std::vector<MatmulProblem>& out, MatmulTuning& tuning)
+{
+    mlmc_status st = check_levels(lv, false);
+    if (st != MLMC_OK) return st;
+    if (nprob < 1 || !probs) return fail(MLMC_EINVAL, "nprob must be >= 1 with a problem table");
+    if (lv->rmse_target > 0.0 || !lv->n_samples) return fail(MLMC_EINVAL, "batched estimates take fixed N_l");
+    std::vector<uint32_t> ids;
+    out.clear();
+    for (int32_t i = 0; i < nprob; ++i) {
+        const mlmc_problem& pr = probs[i];
+        if (pr.m < 1 || pr.p < 1 || pr.n < 1 || pr.n >= kU32)
+            return fail(MLMC_EINVAL, "problem %d: m, p >= 1 and 1 <= n < 2^32 required", i);
+        if ((st = check_dist(&pr.A, "A", pr.m, false)) != MLMC_OK) return st;
+        if ((st = check_dist(&pr.B, "B", pr.p, false)) != MLMC_OK) return st;
+        if (!pr.out) return fail(MLMC_EINVAL, "problem %d: out is NULL", i);
+        if (pr.problem >= (1u << 20)) return fail(MLMC_EINVAL, "problem %d: stream id must be < 2^20", i);
+        ids.push_back(pr.problem);
+        out.push_back(MatmulProblem{pr.m, pr.n, pr.p, to_law(pr.A), to_law(pr.B), pr.problem, pr.out, pr.level_means});
+    }
+    std::sort(ids.begin(), ids.end());
+    for (size_t i = 1; i < ids.size(); ++i)
+        if (ids[i] == ids[i - 1]) return fail(MLMC_EINVAL, "duplicate stream id %u", ids[i]);
+    tuning = MatmulTuning{0, 0, 0};
+    if (tune) {
+        if (tune->tile != 0 && tune->tile != 64 && tune->tile != 128)
+            return fail(MLMC_EINVAL, "tuning.tile must be 0, 64 or 128");
+        if (tune->target_blocks < 0 || tune->gather_budget < 0) return fail(MLMC_EINVAL, "negative tuning value");
+        tuning = MatmulTuning{tune->tile, tune->target_blocks, tune->gather_budget};
+    }
+    return MLMC_OK;
+}
+
+// Enqueues a whole fixed-N batched estimate (no host synchronisation).
+hipError_t enqueue_batched(const MatmulPlan& plan, const mlmc_levels* lv, char* ws, hipStream_t stream,
+                           KernelTimer* timer)
+{
+    hipError_t e;
+    {
+        ScopedTiming t(timer, MLMC_KERNEL_FINAL);
+        e = matmul_reset(plan, ws, stream);
+    }
+    if (e != hipSuccess) return e;
+    const StreamKeys keys = keys_of(lv);
+    for (int l = 0; l < lv->num_levels; ++l)
+        if ((e = matmul_level_run(plan, range_of(lv, l, 0, lv->n_samples[l]), 0, keys, ws, stream, timer)) != hipSuccess)
+            return e;
+    ScopedTiming t(timer, MLMC_KERNEL_FINAL);
+    return matmul_finalize(plan, lv->n_samples, ws, true, stream);
+}
+
+}  // namespace
+
+struct mlmc_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+size_t mlmc_matmul_batched_workspace_size(int32_t nprob, const mlmc_problem* probs, const mlmc_levels* levels,
+                                          const mlmc_tuning* tuning)
+{
+    std::vector<MatmulProblem> pr;
+    MatmulTuning tune;
+    if (check_batch(nprob, probs, levels, tuning, pr, tune) != MLMC_OK) return 0;
+    MatmulPlan plan;
+    if (!matmul_plan(pr.data(), nprob, levels->prec, levels->num_levels, levels->c, &tune, plan)) return 0;
+    return plan.total;
+}
+
+mlmc_status mlmc_matmul_estimate_batched(int32_t nprob, const mlmc_problem* probs, const mlmc_levels* lv,
+                                         const mlmc_tuning* tuning, void* workspace, size_t workspace_bytes,
+                                         double* level_var, void* stream_ptr)
+{
+    g_last_error.clear();
+    std::vector<MatmulProblem> pr;
+    MatmulTuning tune;
+    mlmc_status st = check_batch(nprob, probs, lv, tuning, pr, tune);
+    if (st != MLMC_OK) return st;
+    MatmulPlan plan;
+    if (!matmul_plan(pr.data(), nprob, lv->prec, lv->num_levels, lv->c, &tune, plan))
+        return fail(MLMC_EINVAL, "no launch plan for this table");
+    if (!workspace || workspace_bytes < plan.total)
+        return fail(MLMC_EWORKSPACE, "workspace needs %zu bytes", plan.total);
+    hipStream_t stream = static_cast<hipStream_t>(stream_ptr);
+    char* ws = static_cast<char*>(workspace);
+    hipError_t e = matmul_upload(plan, ws, stream);
+    if (e != hipSuccess) return device_fail(e, "problem table upload");
+    if ((e = enqueue_batched(plan, lv, ws, stream, nullptr)) != hipSuccess) return device_fail(e, "batched launch");
+    if (level_var) {
+        if ((e = hipMemcpyAsync(level_var, matmul_level_var_ptr(plan, ws), sizeof(double) * lv->num_levels * nprob,
+                                hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+            (e = hipStreamSynchronize(stream)) != hipSuccess)
+            return device_fail(e, "level variance readback");
+    }
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_matmul_batched_graph_create(int32_t nprob, const mlmc_problem* probs, const mlmc_levels* lv,
+                                             const mlmc_tuning* tuning, void* workspace, size_t workspace_bytes,
+                                             void* stream_ptr, mlmc_graph* graph)
+{
+    g_last_error.clear();
+    if (!graph) return fail(MLMC_EINVAL, "graph is NULL");
+    *graph = nullptr;
+    if (!stream_ptr) return fail(MLMC_EINVAL, "graph capture needs a non-null stream");
+    std::vector<MatmulProblem> pr;
+    MatmulTuning tune;
+    mlmc_status st = check_batch(nprob, probs, lv, tuning, pr, tune);
+    if (st != MLMC_OK) return st;
+    MatmulPlan plan;
+    if (!matmul_plan(pr.data(), nprob, lv->prec, lv->num_levels, lv->c, &tune, plan))
+        return fail(MLMC_EINVAL, "no launch plan for this table");
+    if (!workspace || workspace_bytes < plan.total)
+        return fail(MLMC_EWORKSPACE, "workspace needs %zu bytes", plan.total);
+    hipStream_t stream = static_cast<hipStream_t>(stream_ptr);
+    char* ws = static_cast<char*>(workspace);
+    hipError_t e = matmul_upload(plan, ws, stream);
+    if (e != hipSuccess) return device_fail(e, "problem table upload");
+    mlmc_graph g = new mlmc_graph_s();
+    if ((e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+        delete g;
+        return device_fail(e, "begin capture");
+    }
+    hipError_t launch = enqueue_batched(plan, lv, ws, stream, nullptr);
+    e = hipStreamEndCapture(stream, &g->graph);
+    if (launch != hipSuccess || e != hipSuccess) {
+        if (g->graph) hipGraphDestroy(g->graph);
+        delete g;
+        return device_fail(launch != hipSuccess ? launch : e, "capture");
+    }
+    if ((e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0)) != hipSuccess) {
+        hipGraphDestroy(g->graph);
+        delete g;
+        return device_fail(e, "instantiate");
+    }
+    *graph = g;
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_graph_launch(mlmc_graph graph, void* stream)
+{
+    g_last_error.clear();
+    if (!graph || !graph->exec) return fail(MLMC_EINVAL, "graph is NULL");
+    hipError_t e = hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? MLMC_OK : device_fail(e, "graph launch");
+}
+
+mlmc_status mlmc_graph_destroy(mlmc_graph graph)
+{
+    g_last_error.clear();
+    if (!graph) return MLMC_OK;
+    hipError_t e1 = graph->exec ? hipGraphExecDestroy(graph->exec) : hipSuccess;
+    hipError_t e2 = graph->graph ? hipGraphDestroy(graph->graph) : hipSuccess;
+    delete graph;
+    if (e1 != hipSuccess) return device_fail(e1, "graph exec destroy");
+    if (e2 != hipSuccess) return device_fail(e2, "graph destroy");
     return MLMC_OK;
 }
 

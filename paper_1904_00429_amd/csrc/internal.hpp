@@ -62,36 +62,63 @@ hipError_t inner_levels_run(const LevelRange* ranges, int num_levels, int64_t n,
 hipError_t inner_telescope(const Moments* level_state, int num_levels, double* out,
                            double* level_means, double* level_var, hipStream_t stream);
 
-// ---- matrix product --------------------------------------------------------
-struct MatmulPlan {
+// ---- matrix product ----------------------------------------------------------
+// One product of a table; a single estimate is the one-entry table.
+struct MatmulProblem {
     int64_t m, n, p;
+    Law A, B;
+    uint32_t problem;          // Philox stream id
+    double* out;               // device m x p
+    double* level_means;       // device (L+1) x m x p, or null
+};
+
+struct MatmulTuning {
+    int tile;                  // workgroup output tile edge (0: default)
+    int64_t target_blocks;     // sketch work items per pass (0: default)
+    int64_t gather_budget;     // bytes of gathered operands per pass (0: default)
+};
+
+// Device-side description of one product of the table.
+struct ProblemDesc {
+    int64_t m, n, p;
+    Law A, B;
+    uint32_t sid_problem;
+    int64_t tiles_n, tiles, tile_first;
+    int64_t rows_prefix;       // sum of (m + p) over earlier products
+    int64_t mp_prefix;         // sum of m p over earlier products
+    int64_t merge_blocks, between_prefix;
+    float pre_a, pre_b;        // FP8 operand pre-scales (powers of two), else 1
+    double post;               // 1 / (pre_a pre_b)
+    double* out;
+    double* level_means;
+};
+
+struct MatmulPlan {
     int prec;
     int num_levels;
     int64_t c[32];
-    // launch geometry
-    int kstep;             // K granularity of a contraction step (padding unit)
-    int kpack;             // draws packed per element group in the gathered layout
-    int tile_m, tile_n;    // workgroup output tile
-    int64_t tiles_m, tiles_n;
-    int64_t kpad_max;      // padded draws per realisation at the finest level
-    int64_t gather_bytes;  // capacity of the gathered-operand buffer
-    int elem;              // bytes per gathered value
-    int64_t batch;         // realisations per gather pass at the finest level (smallest batch)
-    int64_t groups_max;    // sample groups per pass
-    int64_t merge_blocks;  // blocks of the per-entry merge
-    // workspace layout (byte offsets)
-    size_t off_means, off_between, off_within, off_var, off_gather_a, off_gather_b,
+    int nprob;
+    int kstep, kpack, elem, nb, tile;
+    int64_t kpad_max;
+    int64_t sum_rows, sum_mp, sum_merge_blocks, total_tiles, max_mp, max_merge_blocks;
+    int64_t groups_max, gather_bytes, state_doubles;
+    size_t off_means, off_between, off_within, off_var, off_desc, off_tile_owner, off_gather,
         off_part_mean, off_part_m2, total;
+    std::vector<ProblemDesc> descs;
+    std::vector<int32_t> tile_owner;
 };
 
-bool matmul_plan(int64_t m, int64_t n, int64_t p, int prec, int num_levels, const int64_t* c,
-                 MatmulPlan& plan);
+bool matmul_plan(const MatmulProblem* probs, int nprob, int prec, int num_levels, const int64_t* c,
+                 const MatmulTuning* tune, MatmulPlan& plan);
+// copies the problem table into the workspace (synchronises `stream`)
+hipError_t matmul_upload(const MatmulPlan& plan, char* ws, hipStream_t stream);
 hipError_t matmul_reset(const MatmulPlan& plan, char* ws, hipStream_t stream);
 hipError_t matmul_level_run(const MatmulPlan& plan, const LevelRange& lr, int64_t done_before,
-                            const Law& A, const Law& B, const StreamKeys& keys, char* ws,
-                            hipStream_t stream, KernelTimer* timer);
-hipError_t matmul_finalize(const MatmulPlan& plan, const int64_t* counts, char* ws, double* out,
-                           double* level_means, hipStream_t stream);
+                            const StreamKeys& keys, char* ws, hipStream_t stream, KernelTimer* timer);
+// V_l of every product (levels x nprob at matmul_level_var_ptr); with
+// write_outputs, also the telescoping sums and level means
+hipError_t matmul_finalize(const MatmulPlan& plan, const int64_t* counts, char* ws, bool write_outputs,
+                           hipStream_t stream);
 double* matmul_level_var_ptr(const MatmulPlan& plan, char* ws);
 
 hipError_t fill_doubles(double* p, int64_t count, double v, hipStream_t stream);

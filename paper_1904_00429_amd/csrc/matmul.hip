@@ -1,25 +1,30 @@
-// Matrix-product MLMC pipeline (Sec. 3; Alg. 1 per level, f = identity).
+// Matrix-product MLMC pipeline (Sec. 3; Alg. 1 per level, f = identity) over
+// a table of independent products (one product is the one-entry table).
 //
-// Per pass over a batch of S realisations of one level l:
+// Per pass over a batch of S realisations of one level l (every product of
+// the table shares the ladder and N_l; each has its own shape, law and
+// Philox stream id):
 //   1. gather:  draw the c_l indices of every realisation (index stream) and
 //      generate only the sampled columns a_t = A^(k)[:, r_t] and rows
 //      b_t = B^(k)[r_t, :] (value stream, keyed by the column j = r_t), in the
 //      operand precision, into a gathered buffer laid out for the MFMA
 //      fragments.  Draws t < c_{l-1} (the coarse segment) and the remaining
 //      draws (the fine segment) are each zero-padded to the contraction step.
-//   2. sketch:  per output tile and group of realisations, the K loop runs
-//      over the coarse segment, scales the accumulator by 1 - c_l / c_{l-1},
-//      then continues over the fine segment: the result times n / c_l is
+//   2. sketch:  a persistent grid walks the (product, output tile, group of
+//      realisations) work items.  Per realisation the K loop runs over the
+//      coarse segment, scales the accumulator by 1 - c_l / c_{l-1}, then
+//      continues over the fine segment: the result times n / c_l is
 //      D_k = Z_l^(k) - Z_{l-1}^(k) (the coupled fine-minus-coarse sample of
-//      Alg. 1) without ever forming either sketch.  Each entry's Welford
-//      state over the group's realisations is kept in registers.
+//      Alg. 1) without ever forming either sketch.  Each entry's Welford state
+//      over the group's realisations is kept in registers.
 //   3. merge:   per entry, a fixed-order Chan merge of the group means into
 //      the level's running mean (FP64); the between-group part of the sum of
 //      squared deviations is reduced per block, the within-group parts are
 //      summed by one thread.  V_l = (within + between) / (N_l - 1).
 // After the last level, `finalize` forms V_l and the telescoping sum
-// Y = sum_l Ybar_l (eq. (10)).
+// Y = sum_l Ybar_l (eq. (10)) of every product.
 #include <hip/hip_bf16.h>
+#include <math.h>
 #include <stdlib.h>
 
 #include "internal.hpp"
@@ -36,105 +41,111 @@ constexpr int kGatherThreads = 64;
 constexpr int kGatherPositions = 8;
 constexpr int64_t kGatherBudgetBytes = 192ll << 20;
 constexpr int64_t kTargetSketchBlocks = 2048;
+constexpr int64_t kSketchMaxBlocks = 8192;
 
 // ---------------------------------------------------------------------------
-// Contraction policies: operand type, MFMA shape, wave tile, fragment layout.
-// A workgroup is 2 x 2 waves, so its tile is 2 WM x 2 WN.
+// Contraction policies: operand type, MFMA shape, fragment layout.  A
+// workgroup is 2 x 2 waves; a wave computes NB x NB MFMA blocks of BLK x BLK.
 // ---------------------------------------------------------------------------
-struct PolicyF64 {  // v_mfma_f64_16x16x4_f64: wave tile 32 x 32 = 2 x 2 blocks
+struct PolicyF64 {  // v_mfma_f64_16x16x4_f64
     using In = double;
     using Acc = double;
-    static constexpr int KSTEP = 4, KPACK = 1, BLK = 16, NB = 2, WM = 32, WN = 32;
-    static constexpr int REGS = 4;  // accumulator elements per lane per block
     using AccVec = f64x4;
+    using FragT = double;
+    static constexpr int KSTEP = 4, KPACK = 1, BLK = 16, REGS = 4;
     // f64 results: lane l, register r holds row l / 16 + 4 r, column l % 16
     static __device__ __forceinline__ int row_of(int lane, int r) { return lane / 16 + 4 * r; }
     static __device__ __forceinline__ int col_of(int lane) { return lane % 16; }
+    static __device__ __forceinline__ double load(const double* G, int64_t rows, int64_t row0, int64_t kk, int lane)
+    {
+        const int64_t row = row0 + (lane % 16);
+        const int64_t t = kk + lane / 16;
+        return row < rows ? G[t * rows + row] : 0.0;
+    }
+    static __device__ __forceinline__ f64x4 mma(double a, double b, f64x4 c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
 };
 
-struct PolicyF32 {  // v_mfma_f32_32x32x2_f32: wave tile 64 x 64 = 2 x 2 blocks
+// 32 x 32 output blocks: lane l, register r holds row 8 (r/4) + 4 (l/32) + r%4, column l % 32
+struct Block32 {
+    static __device__ __forceinline__ int row_of(int lane, int r) { return 8 * (r / 4) + 4 * (lane / 32) + (r % 4); }
+    static __device__ __forceinline__ int col_of(int lane) { return lane % 32; }
+};
+
+struct PolicyF32 : Block32 {  // v_mfma_f32_32x32x2_f32
     using In = float;
     using Acc = float;
-    static constexpr int KSTEP = 2, KPACK = 1, BLK = 32, NB = 2, WM = 64, WN = 64;
-    static constexpr int REGS = 16;
     using AccVec = f32x16;
-    static __device__ __forceinline__ int row_of(int lane, int r) { return 8 * (r / 4) + 4 * (lane / 32) + (r % 4); }
-    static __device__ __forceinline__ int col_of(int lane) { return lane % 32; }
+    using FragT = float;
+    static constexpr int KSTEP = 2, KPACK = 1, BLK = 32, REGS = 16;
+    static __device__ __forceinline__ float load(const float* G, int64_t rows, int64_t row0, int64_t kk, int lane)
+    {
+        const int64_t row = row0 + (lane % 32);
+        const int64_t t = kk + lane / 32;
+        return row < rows ? G[t * rows + row] : 0.0f;
+    }
+    static __device__ __forceinline__ f32x16 mma(float a, float b, f32x16 c)
+    {
+        return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+    }
 };
 
-struct PolicyBF16 {  // v_mfma_f32_32x32x16_bf16: wave tile 64 x 64 = 2 x 2 blocks
+struct PolicyBF16 : Block32 {  // v_mfma_f32_32x32x16_bf16: a lane holds 8 consecutive draws of one row
     using In = __bf16;
     using Acc = float;
-    static constexpr int KSTEP = 16, KPACK = 8, BLK = 32, NB = 2, WM = 64, WN = 64;
-    static constexpr int REGS = 16;
     using AccVec = f32x16;
-    static __device__ __forceinline__ int row_of(int lane, int r) { return 8 * (r / 4) + 4 * (lane / 32) + (r % 4); }
-    static __device__ __forceinline__ int col_of(int lane) { return lane % 32; }
+    using FragT = bf16x8;
+    static constexpr int KSTEP = 16, KPACK = 8, BLK = 32, REGS = 16;
+    static __device__ __forceinline__ bf16x8 load(const __bf16* G, int64_t rows, int64_t row0, int64_t kk, int lane)
+    {
+        const int64_t row = row0 + (lane % 32);
+        const int64_t kb = kk / 8 + lane / 32;
+        bf16x8 v;
+        if (row < rows) {
+            v = *reinterpret_cast<const bf16x8*>(G + (kb * rows + row) * 8);
+        } else {
+            for (int i = 0; i < 8; ++i) v[i] = (__bf16)0.0f;
+        }
+        return v;
+    }
+    static __device__ __forceinline__ f32x16 mma(bf16x8 a, bf16x8 b, f32x16 c)
+    {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
 };
 
-template <typename P> struct Frag;
-template <> struct Frag<PolicyF64> { using T = double; };
-template <> struct Frag<PolicyF32> { using T = float; };
-template <> struct Frag<PolicyBF16> { using T = bf16x8; };
-
-// Fragment of the gathered operand G (layout [kpad / KPACK][rows][KPACK]) for
-// the MFMA block whose first row is `row0`, at padded draw `kk`.
-__device__ __forceinline__ double load_frag(const PolicyF64&, const double* G, int64_t rows,
-                                            int64_t row0, int64_t kk, int lane)
-{
-    const int64_t row = row0 + (lane % 16);
-    const int64_t t = kk + lane / 16;
-    return row < rows ? G[t * rows + row] : 0.0;
-}
-
-__device__ __forceinline__ float load_frag(const PolicyF32&, const float* G, int64_t rows,
-                                           int64_t row0, int64_t kk, int lane)
-{
-    const int64_t row = row0 + (lane % 32);
-    const int64_t t = kk + lane / 32;
-    return row < rows ? G[t * rows + row] : 0.0f;
-}
-
-__device__ __forceinline__ bf16x8 load_frag(const PolicyBF16&, const __bf16* G, int64_t rows,
-                                            int64_t row0, int64_t kk, int lane)
-{
-    const int64_t row = row0 + (lane % 32);
-    const int64_t kb = kk / 8 + lane / 32;
-    bf16x8 v;
-    if (row < rows) {
-        v = *reinterpret_cast<const bf16x8*>(G + (kb * rows + row) * 8);
-    } else {
-        for (int i = 0; i < 8; ++i) v[i] = (__bf16)0.0f;
+struct PolicyFP8 : Block32 {  // v_mfma_f32_32x32x16_fp8_fp8 (OCP e4m3 on gfx950): 8 draws of one row per lane
+    using In = uint8_t;
+    using Acc = float;
+    using AccVec = f32x16;
+    using FragT = long;
+    static constexpr int KSTEP = 16, KPACK = 8, BLK = 32, REGS = 16;
+    static __device__ __forceinline__ long load(const uint8_t* G, int64_t rows, int64_t row0, int64_t kk, int lane)
+    {
+        const int64_t row = row0 + (lane % 32);
+        const int64_t kb = kk / 8 + lane / 32;
+        return row < rows ? *reinterpret_cast<const long*>(G + (kb * rows + row) * 8) : 0l;
     }
-    return v;
-}
-
-__device__ __forceinline__ f64x4 mma(const PolicyF64&, double a, double b, f64x4 c)
-{
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ f32x16 mma(const PolicyF32&, float a, float b, f32x16 c)
-{
-    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ f32x16 mma(const PolicyBF16&, bf16x8 a, bf16x8 b, f32x16 c)
-{
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
-}
+    static __device__ __forceinline__ f32x16 mma(long a, long b, f32x16 c)
+    {
+        return __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a, b, c, 0, 0, 0);
+    }
+};
 
 // ---------------------------------------------------------------------------
-// Gather: only the sampled columns of the realisation are generated.
+// Gather: only the sampled columns of each realisation are generated.
 // ---------------------------------------------------------------------------
 struct GatherParams {
-    int64_t m, p;
-    uint32_t n;
-    uint32_t c, c_prev;
+    const ProblemDesc* descs;
+    uint32_t c, c_prev, level_field;
     int64_t kc, kpad;        // padded coarse length, padded total length
-    uint32_t key0, key1, sid_index, sid_value;
+    int64_t batch;           // realisations in this pass
+    uint32_t key0, key1;
     uint32_t k_first;        // realisation of batch slot 0
-    Law A, B;
-    void* GA;                // batch x [kpad / KPACK][m][KPACK]
-    void* GB;                // batch x [kpad / KPACK][p][KPACK]
+    int elem;
+    char* gbuf;              // per product: batch x [kpad/KPACK][m][KPACK], then batch x [..][p][..]
 };
 
 // Draw number t of padded position `pos`, or -1 for padding.
@@ -145,67 +156,96 @@ __device__ __forceinline__ int64_t draw_of_position(int64_t pos, int64_t kc, uin
     return t < (int64_t)c ? t : -1;
 }
 
-template <typename T> __device__ __forceinline__ T to_store(float v);
-template <> __device__ __forceinline__ float to_store<float>(float v) { return v; }
-template <> __device__ __forceinline__ __bf16 to_store<__bf16>(float v) { return (__bf16)v; }
+template <typename Store> struct StoreOf;
+template <> struct StoreOf<double> {
+    static __device__ __forceinline__ double from(double v, float) { return v; }
+};
+template <> struct StoreOf<float> {
+    static __device__ __forceinline__ float from(float v, float) { return v; }
+};
+template <> struct StoreOf<__bf16> {
+    static __device__ __forceinline__ __bf16 from(float v, float) { return (__bf16)v; }
+};
+template <> struct StoreOf<uint8_t> {
+    // OCP e4m3 with round-to-nearest-even after the operand pre-scale,
+    // saturated to +-448
+    static __device__ __forceinline__ uint8_t from(float v, float pre)
+    {
+        const float s = __builtin_amdgcn_fmed3f(v * pre, 448.0f, -448.0f);
+        return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(s, s, 0, false) & 0xFF);
+    }
+};
 
 template <typename Compute, typename Store, int KPACK>
 __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm)
 {
     __shared__ uint32_t cols[kGatherPositions];
     __shared__ int valid[kGatherPositions];
+    const ProblemDesc& P = prm.descs[blockIdx.z];
     const int64_t pos0 = (int64_t)blockIdx.x * kGatherPositions;
     const int64_t slot = blockIdx.y;
     const uint32_t k = prm.k_first + (uint32_t)slot;
+    const uint32_t sid_index = stream_id(kTagIndex, prm.level_field, P.sid_problem);
+    const uint32_t sid_value = stream_id(kTagValue, prm.level_field, P.sid_problem);
     if (threadIdx.x < kGatherPositions) {
         const int64_t pos = pos0 + threadIdx.x;
         const int64_t t = pos < prm.kpad ? draw_of_position(pos, prm.kc, prm.c, prm.c_prev) : -1;
         valid[threadIdx.x] = t >= 0;
-        cols[threadIdx.x] = t >= 0 ? draw_index((uint32_t)t, k, prm.sid_index, prm.key0, prm.key1, prm.n) : 0u;
+        cols[threadIdx.x] = t >= 0 ? draw_index((uint32_t)t, k, sid_index, prm.key0, prm.key1, (uint32_t)P.n) : 0u;
     }
     __syncthreads();
-    const int64_t rows = prm.m + prm.p;
+    const int64_t m = P.m, p = P.p;
+    const int64_t rows = m + p;
     const int64_t quads = ceil_div(rows, 4);
-    const bool normal = prm.A.kind != 1 || prm.B.kind != 1;
+    const bool normal = P.A.kind != 1 || P.B.kind != 1;
     const int npos = (int)((prm.kpad - pos0) < kGatherPositions ? (prm.kpad - pos0) : kGatherPositions);
-    Store* GA = static_cast<Store*>(prm.GA) + slot * prm.kpad * prm.m;
-    Store* GB = static_cast<Store*>(prm.GB) + slot * prm.kpad * prm.p;
+    const int64_t pass_rows = prm.batch * prm.kpad * (int64_t)prm.elem;
+    Store* GA = reinterpret_cast<Store*>(prm.gbuf + pass_rows * P.rows_prefix) + slot * prm.kpad * m;
+    Store* GB = reinterpret_cast<Store*>(prm.gbuf + pass_rows * (P.rows_prefix + m)) + slot * prm.kpad * p;
     for (int64_t q = threadIdx.x; q < quads; q += kGatherThreads) {
         Store vals[kGatherPositions][4];
+#pragma unroll
         for (int ip = 0; ip < kGatherPositions; ++ip) {
             if (ip >= npos || !valid[ip]) {
-                for (int r = 0; r < 4; ++r) vals[ip][r] = (Store)0.0f;
+                for (int r = 0; r < 4; ++r) vals[ip][r] = StoreOf<Store>::from((Compute)0, 1.0f);
                 continue;
             }
             const uint32_t j = cols[ip];
-            const Words4 w = philox4x32_10((uint32_t)q, k, j, prm.sid_value, prm.key0, prm.key1);
+            const Words4 w = philox4x32_10((uint32_t)q, k, j, sid_value, prm.key0, prm.key1);
             Compute u[4], z[4];
             quad_values<Compute>(w, normal, u[0], u[1], u[2], u[3], z[0], z[1], z[2], z[3]);
+#pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t e = 4 * q + r;
                 Compute v = (Compute)0;
-                if (e < prm.m) v = law_value<Compute>(prm.A, z[r], u[r], (int64_t)j * prm.A.ld + e);
-                else if (e < rows) v = law_value<Compute>(prm.B, z[r], u[r], (int64_t)j * prm.B.ld + (e - prm.m));
-                vals[ip][r] = (Store)v;
+                float pre = 1.0f;
+                if (e < m) {
+                    v = law_value<Compute>(P.A, z[r], u[r], (int64_t)j * P.A.ld + e);
+                    pre = P.pre_a;
+                } else if (e < rows) {
+                    v = law_value<Compute>(P.B, z[r], u[r], (int64_t)j * P.B.ld + (e - m));
+                    pre = P.pre_b;
+                }
+                vals[ip][r] = StoreOf<Store>::from(v, pre);
             }
         }
+#pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int64_t e = 4 * q + r;
             if (e >= rows) break;
-            Store* G = e < prm.m ? GA : GB;
-            const int64_t R = e < prm.m ? prm.m : prm.p;
-            const int64_t row = e < prm.m ? e : e - prm.m;
+            Store* G = e < m ? GA : GB;
+            const int64_t R = e < m ? m : p;
+            const int64_t row = e < m ? e : e - m;
             if constexpr (KPACK == 1) {
-                for (int ip = 0; ip < npos; ++ip) G[(pos0 + ip) * R + row] = vals[ip][r];
+#pragma unroll
+                for (int ip = 0; ip < kGatherPositions; ++ip)
+                    if (ip < npos) G[(pos0 + ip) * R + row] = vals[ip][r];
             } else {
                 // positions pos0 .. pos0+7 are one packed group of 8 draws
-                Store pack[KPACK];
-                for (int ip = 0; ip < KPACK; ++ip) pack[ip] = vals[ip][r];
-                const int64_t kb = pos0 / KPACK;
                 typedef Store vec_t __attribute__((ext_vector_type(KPACK)));
                 vec_t vv;
-                for (int ip = 0; ip < KPACK; ++ip) vv[ip] = pack[ip];
-                *reinterpret_cast<vec_t*>(G + (kb * R + row) * KPACK) = vv;
+                for (int ip = 0; ip < KPACK; ++ip) vv[ip] = vals[ip][r];
+                *reinterpret_cast<vec_t*>(G + ((pos0 / KPACK) * R + row) * KPACK) = vv;
             }
         }
     }
@@ -215,102 +255,136 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
 // Sketch + coupling + per-entry Welford over a group of realisations.
 // ---------------------------------------------------------------------------
 struct SketchParams {
-    int64_t m, p;
+    const ProblemDesc* descs;
+    const int32_t* tile_owner;   // global tile -> product
+    int64_t total_tiles, groups;
     int64_t kc, kpad;
-    int64_t batch;           // realisations in this pass
-    int64_t tiles_n;
-    double scale;            // n / c_l
-    double omega;            // 1 - c_l / c_{l-1} (unused at level 0: kc == 0)
-    const void* GA;
-    const void* GB;
-    double* part_mean;       // groups x m x p
-    double* part_m2;         // groups x tiles
+    int64_t batch;               // realisations in this pass
+    int elem;
+    double omega;                // 1 - c_l / c_{l-1} (unused at level 0: kc == 0)
+    uint32_t c;                  // c_l
+    const char* gbuf;
+    double* part_mean;           // groups x sum_mp
+    double* part_m2;             // groups x total_tiles
+    int64_t sum_mp;
 };
 
-template <typename P>
+template <typename P, int NB>
 __global__ __launch_bounds__(kSketchThreads) void sketch_kernel(SketchParams prm)
 {
     using In = typename P::In;
     using Acc = typename P::Acc;
-    using FragT = typename Frag<P>::T;
-    constexpr int NE = P::NB * P::NB * P::REGS;  // entries per lane
+    using FragT = typename P::FragT;
+    constexpr int NE = NB * NB * P::REGS;  // entries per lane
+    constexpr int WT = NB * P::BLK;        // wave tile edge
     __shared__ double red[kSketchThreads / kWave];
 
     const int lane = threadIdx.x % kWave;
     const int wave = threadIdx.x / kWave;
-    const int64_t tile = blockIdx.x;
-    const int64_t group = blockIdx.y;
-    const int64_t groups = gridDim.y;
-    const int64_t tile_m = tile / prm.tiles_n, tile_n = tile % prm.tiles_n;
-    const int64_t row0 = tile_m * (2 * P::WM) + (wave / 2) * P::WM;
-    const int64_t col0 = tile_n * (2 * P::WN) + (wave % 2) * P::WN;
-    const int64_t s_begin = group * prm.batch / groups;
-    const int64_t s_end = (group + 1) * prm.batch / groups;
-    const P pol{};
+    const int64_t items = prm.total_tiles * prm.groups;
+    for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
+        const int64_t group = item / prm.total_tiles;
+        const int64_t tt = item % prm.total_tiles;
+        const ProblemDesc& Pd = prm.descs[prm.tile_owner[tt]];
+        const int64_t tile = tt - Pd.tile_first;
+        const int64_t m = Pd.m, p = Pd.p;
+        const int64_t row0 = (tile / Pd.tiles_n) * (2 * WT) + (wave / 2) * WT;
+        const int64_t col0 = (tile % Pd.tiles_n) * (2 * WT) + (wave % 2) * WT;
+        const int64_t s_begin = group * prm.batch / prm.groups;
+        const int64_t s_end = (group + 1) * prm.batch / prm.groups;
+        const int64_t pass_rows = prm.batch * prm.kpad * (int64_t)prm.elem;
+        const In* GA0 = reinterpret_cast<const In*>(prm.gbuf + pass_rows * Pd.rows_prefix);
+        const In* GB0 = reinterpret_cast<const In*>(prm.gbuf + pass_rows * (Pd.rows_prefix + m));
+        const Acc scale = (Acc)((double)Pd.n / (double)prm.c * Pd.post);
+        const Acc omega = (Acc)prm.omega;
 
-    Acc mean[NE], m2[NE];
-    for (int e = 0; e < NE; ++e) { mean[e] = (Acc)0; m2[e] = (Acc)0; }
-    Acc count = (Acc)0;
-    const Acc scale = (Acc)prm.scale, omega = (Acc)prm.omega;
-
-    for (int64_t s = s_begin; s < s_end; ++s) {
-        const In* GA = static_cast<const In*>(prm.GA) + s * prm.kpad * prm.m;
-        const In* GB = static_cast<const In*>(prm.GB) + s * prm.kpad * prm.p;
-        typename P::AccVec acc[P::NB][P::NB];
-        for (int bi = 0; bi < P::NB; ++bi)
-            for (int bj = 0; bj < P::NB; ++bj)
-                for (int r = 0; r < P::REGS; ++r) acc[bi][bj][r] = (Acc)0;
-        for (int64_t kk = 0; kk < prm.kpad; kk += P::KSTEP) {
-            if (kk == prm.kc && kk > 0) {
-                // end of the coarse segment: fold in the coarse sketch weight
-                for (int bi = 0; bi < P::NB; ++bi)
-                    for (int bj = 0; bj < P::NB; ++bj)
-                        for (int r = 0; r < P::REGS; ++r) acc[bi][bj][r] *= omega;
+        Acc mean[NE], m2[NE];
+#pragma unroll
+        for (int e = 0; e < NE; ++e) { mean[e] = (Acc)0; m2[e] = (Acc)0; }
+        Acc count = (Acc)0;
+        for (int64_t s = s_begin; s < s_end; ++s) {
+            const In* GA = GA0 + s * prm.kpad * m;
+            const In* GB = GB0 + s * prm.kpad * p;
+            typename P::AccVec acc[NB][NB];
+#pragma unroll
+            for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < NB; ++bj)
+#pragma unroll
+                    for (int r = 0; r < P::REGS; ++r) acc[bi][bj][r] = (Acc)0;
+            // fragments of step kk are loaded one step ahead of their MFMAs
+            FragT a[NB], b[NB];
+#pragma unroll
+            for (int bi = 0; bi < NB; ++bi) a[bi] = P::load(GA, m, row0 + bi * P::BLK, 0, lane);
+#pragma unroll
+            for (int bj = 0; bj < NB; ++bj) b[bj] = P::load(GB, p, col0 + bj * P::BLK, 0, lane);
+            for (int64_t kk = 0; kk < prm.kpad; kk += P::KSTEP) {
+                FragT an[NB], bn[NB];
+                const int64_t kn = kk + P::KSTEP < prm.kpad ? kk + P::KSTEP : kk;
+#pragma unroll
+                for (int bi = 0; bi < NB; ++bi) an[bi] = P::load(GA, m, row0 + bi * P::BLK, kn, lane);
+#pragma unroll
+                for (int bj = 0; bj < NB; ++bj) bn[bj] = P::load(GB, p, col0 + bj * P::BLK, kn, lane);
+                if (kk == prm.kc && kk > 0) {
+                    // end of the coarse segment: fold in the coarse sketch weight
+#pragma unroll
+                    for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+                        for (int bj = 0; bj < NB; ++bj)
+#pragma unroll
+                            for (int r = 0; r < P::REGS; ++r) acc[bi][bj][r] *= omega;
+                }
+#pragma unroll
+                for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+                    for (int bj = 0; bj < NB; ++bj) acc[bi][bj] = P::mma(a[bi], b[bj], acc[bi][bj]);
+#pragma unroll
+                for (int bi = 0; bi < NB; ++bi) a[bi] = an[bi];
+#pragma unroll
+                for (int bj = 0; bj < NB; ++bj) b[bj] = bn[bj];
             }
-            FragT a[P::NB], b[P::NB];
-            for (int bi = 0; bi < P::NB; ++bi) a[bi] = load_frag(pol, GA, prm.m, row0 + bi * P::BLK, kk, lane);
-            for (int bj = 0; bj < P::NB; ++bj) b[bj] = load_frag(pol, GB, prm.p, col0 + bj * P::BLK, kk, lane);
-            for (int bi = 0; bi < P::NB; ++bi)
-                for (int bj = 0; bj < P::NB; ++bj) acc[bi][bj] = mma(pol, a[bi], b[bj], acc[bi][bj]);
+            count += (Acc)1;
+            const Acc inv = (Acc)1 / count;
+            int e = 0;
+#pragma unroll
+            for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < NB; ++bj)
+#pragma unroll
+                    for (int r = 0; r < P::REGS; ++r, ++e) {
+                        const Acc d = scale * acc[bi][bj][r];
+                        const Acc delta = d - mean[e];
+                        mean[e] += delta * inv;
+                        m2[e] += delta * (d - mean[e]);
+                    }
         }
-        if (prm.kc == prm.kpad && prm.kc > 0) {
-            for (int bi = 0; bi < P::NB; ++bi)
-                for (int bj = 0; bj < P::NB; ++bj)
-                    for (int r = 0; r < P::REGS; ++r) acc[bi][bj][r] *= omega;
-        }
-        count += (Acc)1;
-        const Acc inv = (Acc)1 / count;
+
+        // group mean of every in-range entry, and the group's within sum of squares
+        double m2_sum = 0.0;
         int e = 0;
-        for (int bi = 0; bi < P::NB; ++bi)
-            for (int bj = 0; bj < P::NB; ++bj)
+        double* pm = prm.part_mean + group * prm.sum_mp + Pd.mp_prefix;
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < NB; ++bj)
+#pragma unroll
                 for (int r = 0; r < P::REGS; ++r, ++e) {
-                    const Acc d = scale * acc[bi][bj][r];
-                    const Acc delta = d - mean[e];
-                    mean[e] += delta * inv;
-                    m2[e] += delta * (d - mean[e]);
+                    const int64_t i = row0 + bi * P::BLK + P::row_of(lane, r);
+                    const int64_t j = col0 + bj * P::BLK + P::col_of(lane);
+                    if (i < m && j < p) {
+                        pm[i * p + j] = (double)mean[e];
+                        m2_sum += (double)m2[e];
+                    }
                 }
-    }
-
-    // group mean of every in-range entry, and the group's within sum of squares
-    double m2_sum = 0.0;
-    int e = 0;
-    for (int bi = 0; bi < P::NB; ++bi)
-        for (int bj = 0; bj < P::NB; ++bj)
-            for (int r = 0; r < P::REGS; ++r, ++e) {
-                const int64_t i = row0 + bi * P::BLK + P::row_of(lane, r);
-                const int64_t j = col0 + bj * P::BLK + P::col_of(lane);
-                if (i < prm.m && j < prm.p) {
-                    prm.part_mean[(group * prm.m + i) * prm.p + j] = (double)mean[e];
-                    m2_sum += (double)m2[e];
-                }
-            }
-    for (int off = kWave / 2; off > 0; off >>= 1) m2_sum += __shfl_xor(m2_sum, off, kWave);
-    if (lane == 0) red[wave] = m2_sum;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double tot = 0.0;
-        for (int w = 0; w < kSketchThreads / kWave; ++w) tot += red[w];
-        prm.part_m2[group * gridDim.x + tile] = tot;
+        for (int off = kWave / 2; off > 0; off >>= 1) m2_sum += __shfl_xor(m2_sum, off, kWave);
+        if (lane == 0) red[wave] = m2_sum;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double tot = 0.0;
+            for (int w = 0; w < kSketchThreads / kWave; ++w) tot += red[w];
+            prm.part_m2[group * prm.total_tiles + tt] = tot;
+        }
+        __syncthreads();
     }
 }
 
@@ -318,33 +392,39 @@ __global__ __launch_bounds__(kSketchThreads) void sketch_kernel(SketchParams prm
 // Merge of a pass's groups into the level state; finalize.
 // ---------------------------------------------------------------------------
 struct MergeParams {
-    int64_t mp;
-    int64_t batch, groups, tiles;
-    double done_before;      // realisations already in the level state
+    const ProblemDesc* descs;
+    int level;
+    int64_t batch, groups, total_tiles, sum_mp, sum_merge_blocks, nprob;
+    double done_before;          // realisations already in the level state
     const double* part_mean;
     const double* part_m2;
-    double* mean;            // level state: m x p
-    double* between;         // level state: merge_blocks
-    double* within;          // level state: 1
+    double* means;               // levels x sum_mp
+    double* between;             // levels x sum_merge_blocks
+    double* within;              // levels x nprob
 };
 
 __global__ __launch_bounds__(kMergeThreads) void merge_kernel(MergeParams prm)
 {
     __shared__ double red[kMergeThreads];
+    const int64_t pi = blockIdx.y;
+    const ProblemDesc& Pd = prm.descs[pi];
+    if ((int64_t)blockIdx.x >= Pd.merge_blocks) return;
+    const int64_t mp = Pd.m * Pd.p;
     const int64_t e = (int64_t)blockIdx.x * kMergeThreads + threadIdx.x;
     double between = 0.0;
-    if (e < prm.mp) {
-        double mu = prm.mean[e];
+    if (e < mp) {
+        double* mean = prm.means + prm.level * prm.sum_mp + Pd.mp_prefix;
+        double mu = mean[e];
         double na = prm.done_before;
         for (int64_t g = 0; g < prm.groups; ++g) {
             const double nb = (double)((g + 1) * prm.batch / prm.groups - g * prm.batch / prm.groups);
             const double n = na + nb;
-            const double delta = prm.part_mean[g * prm.mp + e] - mu;
+            const double delta = prm.part_mean[g * prm.sum_mp + Pd.mp_prefix + e] - mu;
             mu += delta * (nb / n);
             between += delta * delta * (na * nb / n);
             na = n;
         }
-        prm.mean[e] = mu;
+        mean[e] = mu;
     }
     red[threadIdx.x] = between;
     __syncthreads();
@@ -353,30 +433,36 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(MergeParams prm)
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        prm.between[blockIdx.x] += red[0];
+        prm.between[prm.level * prm.sum_merge_blocks + Pd.between_prefix + blockIdx.x] += red[0];
         if (blockIdx.x == 0) {
             double w = 0.0;
-            for (int64_t i = 0; i < prm.groups * prm.tiles; ++i) w += prm.part_m2[i];
-            *prm.within += w;
+            for (int64_t g = 0; g < prm.groups; ++g)
+                for (int64_t t = 0; t < Pd.tiles; ++t) w += prm.part_m2[g * prm.total_tiles + Pd.tile_first + t];
+            prm.within[prm.level * prm.nprob + pi] += w;
         }
     }
 }
 
 struct FinalizeParams {
+    const ProblemDesc* descs;
     int num_levels;
-    int64_t merge_blocks;
+    int64_t sum_mp, sum_merge_blocks, nprob;
     double counts[32];
-    const double* between;   // levels x merge_blocks
-    const double* within;    // levels
-    double* var;             // levels
+    const double* means;
+    const double* between;       // levels x sum_merge_blocks
+    const double* within;        // levels x nprob
+    double* var;                 // levels x nprob
 };
 
 __global__ __launch_bounds__(kMergeThreads) void level_var_kernel(FinalizeParams prm)
 {
     __shared__ double red[kMergeThreads];
     const int l = blockIdx.x;
+    const int64_t pi = blockIdx.y;
+    const ProblemDesc& Pd = prm.descs[pi];
+    const double* bt = prm.between + l * prm.sum_merge_blocks + Pd.between_prefix;
     double s = 0.0;
-    for (int64_t b = threadIdx.x; b < prm.merge_blocks; b += kMergeThreads) s += prm.between[l * prm.merge_blocks + b];
+    for (int64_t b = threadIdx.x; b < Pd.merge_blocks; b += kMergeThreads) s += bt[b];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int half = kMergeThreads / 2; half > 0; half >>= 1) {
@@ -385,23 +471,23 @@ __global__ __launch_bounds__(kMergeThreads) void level_var_kernel(FinalizeParams
     }
     if (threadIdx.x == 0) {
         const double n = prm.counts[l];
-        prm.var[l] = n > 1.0 ? (red[0] + prm.within[l]) / (n - 1.0) : 0.0;
+        prm.var[l * prm.nprob + pi] = n > 1.0 ? (red[0] + prm.within[l * prm.nprob + pi]) / (n - 1.0) : 0.0;
     }
 }
 
-__global__ __launch_bounds__(kMergeThreads) void telescope_kernel(const double* means, int num_levels,
-                                                                  int64_t mp, double* out,
-                                                                  double* level_means)
+__global__ __launch_bounds__(kMergeThreads) void telescope_kernel(FinalizeParams prm)
 {
+    const ProblemDesc& Pd = prm.descs[blockIdx.y];
+    const int64_t mp = Pd.m * Pd.p;
     const int64_t e = (int64_t)blockIdx.x * kMergeThreads + threadIdx.x;
     if (e >= mp) return;
     double y = 0.0;
-    for (int l = 0; l < num_levels; ++l) {
-        const double v = means[l * mp + e];
+    for (int l = 0; l < prm.num_levels; ++l) {
+        const double v = prm.means[l * prm.sum_mp + Pd.mp_prefix + e];
         y += v;
-        if (level_means) level_means[l * mp + e] = v;
+        if (Pd.level_means) Pd.level_means[l * mp + e] = v;
     }
-    out[e] = y;
+    Pd.out[e] = y;
 }
 
 __global__ void fill_kernel(double* p, int64_t count, double v)
@@ -413,11 +499,18 @@ __global__ void fill_kernel(double* p, int64_t count, double v)
 // ---------------------------------------------------------------------------
 // Host side: plan, passes, finalize.
 // ---------------------------------------------------------------------------
-static void policy_shape(int prec, int& kstep, int& kpack, int& tm, int& tn, int& elem)
+struct PolicyShape {
+    int kstep, kpack, blk, elem;
+};
+
+static PolicyShape policy_shape(int prec)
 {
-    if (prec == 0) { kstep = PolicyF64::KSTEP; kpack = 1; tm = 2 * PolicyF64::WM; tn = 2 * PolicyF64::WN; elem = 8; }
-    else if (prec == 1) { kstep = PolicyF32::KSTEP; kpack = 1; tm = 2 * PolicyF32::WM; tn = 2 * PolicyF32::WN; elem = 4; }
-    else { kstep = PolicyBF16::KSTEP; kpack = PolicyBF16::KPACK; tm = 2 * PolicyBF16::WM; tn = 2 * PolicyBF16::WN; elem = 2; }
+    switch (prec) {
+    case 0: return {PolicyF64::KSTEP, 1, PolicyF64::BLK, 8};
+    case 1: return {PolicyF32::KSTEP, 1, PolicyF32::BLK, 4};
+    case 2: return {PolicyBF16::KSTEP, PolicyBF16::KPACK, PolicyBF16::BLK, 2};
+    default: return {PolicyFP8::KSTEP, PolicyFP8::KPACK, PolicyFP8::BLK, 1};
+    }
 }
 
 static int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
@@ -426,57 +519,114 @@ static void level_padding(const MatmulPlan& plan, int64_t c, int64_t c_prev, int
 {
     kc = round_up(c_prev, plan.kstep);
     kpad = kc + round_up(c - c_prev, plan.kstep);
-    // the packed layout groups 8 positions; the gather kernel writes whole groups
+    // the packed layouts group 8 positions; the gather kernel writes whole groups
     kpad = round_up(kpad, plan.kpack);
 }
 
-bool matmul_plan(int64_t m, int64_t n, int64_t p, int prec, int num_levels, const int64_t* c,
-                 MatmulPlan& plan)
+// FP8 operand pre-scale: a power of two that brings a bound of the entries
+// near 256 (inside e4m3's +-448); exact, and undone in the sketch's scale.
+static float fp8_prescale(const Law& law)
+{
+    double bound;
+    if (law.kind == 0) bound = fabs(law.loc) + 6.0 * fabs(law.scale);
+    else if (law.kind == 1) bound = fabs(law.loc) + fabs(law.scale);
+    else return 1.0f;
+    if (!(bound > 0.0)) return 1.0f;
+    int ex = (int)floor(log2(256.0 / bound));
+    if (ex > 20) ex = 20;
+    if (ex < -20) ex = -20;
+    return (float)ldexp(1.0, ex);
+}
+
+bool matmul_plan(const MatmulProblem* probs, int nprob, int prec, int num_levels, const int64_t* c,
+                 const MatmulTuning* tune, MatmulPlan& plan)
 {
     plan = MatmulPlan();
-    plan.m = m; plan.n = n; plan.p = p; plan.prec = prec; plan.num_levels = num_levels;
+    if (nprob < 1) return false;
+    plan.prec = prec;
+    plan.num_levels = num_levels;
+    plan.nprob = nprob;
     for (int l = 0; l < num_levels; ++l) plan.c[l] = c[l];
-    int elem = 8;
-    policy_shape(prec, plan.kstep, plan.kpack, plan.tile_m, plan.tile_n, elem);
-    if (plan.kpack > 1 && plan.kstep % plan.kpack != 0) return false;
-    plan.tiles_m = ceil_div(m, plan.tile_m);
-    plan.tiles_n = ceil_div(p, plan.tile_n);
+    const PolicyShape ps = policy_shape(prec);
+    plan.kstep = ps.kstep;
+    plan.kpack = ps.kpack;
+    plan.elem = ps.elem;
+    // wave blocks per dimension: 2 (workgroup tile 4 x BLK) unless tuned to 1
+    // (tile 2 x BLK); f64 blocks are 16 wide and always use 2
+    plan.nb = 2;
+    if (tune && tune->tile > 0 && prec != 0) plan.nb = tune->tile <= 2 * ps.blk ? 1 : 2;
+    plan.tile = 2 * plan.nb * ps.blk;
     plan.kpad_max = 0;
     for (int l = 0; l < num_levels; ++l) {
         int64_t kc, kpad;
         level_padding(plan, c[l], l > 0 ? c[l - 1] : 0, kc, kpad);
         if (kpad > plan.kpad_max) plan.kpad_max = kpad;
     }
-    const int64_t per_sample = plan.kpad_max * (m + p) * elem;
+    plan.descs.resize(nprob);
+    plan.tile_owner.clear();
+    int64_t rows = 0, mp = 0, mb = 0, tiles = 0;
+    plan.max_mp = 0;
+    plan.max_merge_blocks = 0;
+    for (int i = 0; i < nprob; ++i) {
+        const MatmulProblem& pr = probs[i];
+        ProblemDesc& d = plan.descs[i];
+        d.m = pr.m;
+        d.n = pr.n;
+        d.p = pr.p;
+        d.A = pr.A;
+        d.B = pr.B;
+        d.sid_problem = pr.problem;
+        d.tiles_n = ceil_div(pr.p, plan.tile);
+        d.tiles = ceil_div(pr.m, plan.tile) * d.tiles_n;
+        d.tile_first = tiles;
+        d.rows_prefix = rows;
+        d.mp_prefix = mp;
+        d.merge_blocks = ceil_div(pr.m * pr.p, kMergeThreads);
+        d.between_prefix = mb;
+        d.pre_a = prec == 3 ? fp8_prescale(pr.A) : 1.0f;
+        d.pre_b = prec == 3 ? fp8_prescale(pr.B) : 1.0f;
+        d.post = 1.0 / ((double)d.pre_a * (double)d.pre_b);
+        d.out = pr.out;
+        d.level_means = pr.level_means;
+        for (int64_t t = 0; t < d.tiles; ++t) plan.tile_owner.push_back(i);
+        tiles += d.tiles;
+        rows += pr.m + pr.p;
+        mp += pr.m * pr.p;
+        mb += d.merge_blocks;
+        if (pr.m * pr.p > plan.max_mp) plan.max_mp = pr.m * pr.p;
+        if (d.merge_blocks > plan.max_merge_blocks) plan.max_merge_blocks = d.merge_blocks;
+    }
+    plan.sum_rows = rows;
+    plan.sum_mp = mp;
+    plan.sum_merge_blocks = mb;
+    plan.total_tiles = tiles;
     // the gathered operands of one pass stay within a budget sized for the
-    // 256 MB Infinity Cache; MLMC_GATHER_BUDGET (bytes) overrides it.  Each
-    // level fills the buffer with as many realisations as fit.
-    int64_t budget = kGatherBudgetBytes;
+    // 256 MB Infinity Cache (tunable; MLMC_GATHER_BUDGET overrides); each
+    // level fills the buffer with as many realisations as fit
+    int64_t budget = (tune && tune->gather_budget > 0) ? tune->gather_budget : kGatherBudgetBytes;
     if (const char* env = getenv("MLMC_GATHER_BUDGET")) {
         const long long v = atoll(env);
         if (v > 0) budget = v;
     }
+    const int64_t per_sample = plan.kpad_max * plan.sum_rows * plan.elem;
     if (budget < per_sample) budget = per_sample;
-    plan.elem = elem;
     plan.gather_bytes = budget;
-    plan.batch = budget / per_sample;
-    if (plan.batch > 65535) plan.batch = 65535;
-    const int64_t tiles = plan.tiles_m * plan.tiles_n;
-    plan.groups_max = ceil_div(kTargetSketchBlocks, tiles);
+    const int64_t target = (tune && tune->target_blocks > 0) ? tune->target_blocks : kTargetSketchBlocks;
+    plan.groups_max = ceil_div(target, plan.total_tiles);
     if (plan.groups_max > 65535) plan.groups_max = 65535;
-    plan.merge_blocks = ceil_div(m * p, kMergeThreads);
     const int64_t L1 = num_levels;
     auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
     size_t off = 0;
-    plan.off_means = off;    off = align(off + sizeof(double) * L1 * m * p);
-    plan.off_between = off;  off = align(off + sizeof(double) * L1 * plan.merge_blocks);
-    plan.off_within = off;   off = align(off + sizeof(double) * L1);
-    plan.off_var = off;      off = align(off + sizeof(double) * L1);
-    // one buffer: the A part of a pass first, its B part right after it
-    plan.off_gather_a = off; off = align(off + (size_t)plan.gather_bytes + 256);
-    plan.off_gather_b = plan.off_gather_a;
-    plan.off_part_mean = off; off = align(off + sizeof(double) * plan.groups_max * m * p);
-    plan.off_part_m2 = off;  off = align(off + sizeof(double) * plan.groups_max * tiles);
+    plan.off_means = off;      off = align(off + sizeof(double) * L1 * mp);
+    plan.off_between = off;    off = align(off + sizeof(double) * L1 * mb);
+    plan.off_within = off;     off = align(off + sizeof(double) * L1 * nprob);
+    plan.off_var = off;        off = align(off + sizeof(double) * L1 * nprob);
+    plan.state_doubles = (int64_t)(off / sizeof(double));
+    plan.off_desc = off;       off = align(off + sizeof(ProblemDesc) * nprob);
+    plan.off_tile_owner = off; off = align(off + sizeof(int32_t) * tiles);
+    plan.off_gather = off;     off = align(off + (size_t)plan.gather_bytes);
+    plan.off_part_mean = off;  off = align(off + sizeof(double) * plan.groups_max * mp);
+    plan.off_part_m2 = off;    off = align(off + sizeof(double) * plan.groups_max * tiles);
     plan.total = off;
     return true;
 }
@@ -495,114 +645,157 @@ hipError_t fill_doubles(double* p, int64_t count, double v, hipStream_t stream)
     return hipGetLastError();
 }
 
+hipError_t matmul_upload(const MatmulPlan& plan, char* ws, hipStream_t stream)
+{
+    hipError_t e = hipMemcpyAsync(ws + plan.off_desc, plan.descs.data(), sizeof(ProblemDesc) * plan.nprob,
+                                  hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(ws + plan.off_tile_owner, plan.tile_owner.data(), sizeof(int32_t) * plan.total_tiles,
+                       hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return e;
+    // the sources are pageable host memory owned by `plan`: wait until the
+    // copies have consumed them
+    return hipStreamSynchronize(stream);
+}
+
 hipError_t matmul_reset(const MatmulPlan& plan, char* ws, hipStream_t stream)
 {
     // means, between, within and var are contiguous at the start of the workspace
-    const int64_t doubles = (int64_t)(plan.off_gather_a / sizeof(double));
-    return fill_doubles(reinterpret_cast<double*>(ws), doubles, 0.0, stream);
+    return fill_doubles(reinterpret_cast<double*>(ws), plan.state_doubles, 0.0, stream);
 }
 
-template <typename P, typename Compute>
-static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t k_first,
-                           int64_t batch, int64_t done_before, const Law& A, const Law& B,
-                           const StreamKeys& keys, char* ws, hipStream_t stream, KernelTimer* timer)
+template <typename P, typename Compute, int NB>
+static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t k_first, int64_t batch,
+                           int64_t done_before, int64_t kc, int64_t kpad, const StreamKeys& keys, char* ws,
+                           hipStream_t stream, KernelTimer* timer)
 {
-    int64_t kc, kpad;
-    level_padding(plan, lr.c, lr.c_prev, kc, kpad);
+    const ProblemDesc* descs = reinterpret_cast<const ProblemDesc*>(ws + plan.off_desc);
     GatherParams g;
-    g.m = plan.m; g.p = plan.p; g.n = (uint32_t)plan.n;
-    g.c = (uint32_t)lr.c; g.c_prev = (uint32_t)lr.c_prev;
-    g.kc = kc; g.kpad = kpad;
-    g.key0 = keys.key0; g.key1 = keys.key1;
-    g.sid_index = stream_id(kTagIndex, lr.level_field, keys.problem);
-    g.sid_value = stream_id(kTagValue, lr.level_field, keys.problem);
+    g.descs = descs;
+    g.c = (uint32_t)lr.c;
+    g.c_prev = (uint32_t)lr.c_prev;
+    g.level_field = lr.level_field;
+    g.kc = kc;
+    g.kpad = kpad;
+    g.batch = batch;
+    g.key0 = keys.key0;
+    g.key1 = keys.key1;
     g.k_first = (uint32_t)k_first;
-    g.A = A; g.B = B;
-    g.GA = ws + plan.off_gather_a;
-    const size_t a_bytes = ((size_t)batch * kpad * plan.m * plan.elem + 255) & ~(size_t)255;
-    g.GB = ws + plan.off_gather_a + a_bytes;
-    const dim3 ggrid((unsigned)ceil_div(kpad, kGatherPositions), (unsigned)batch);
+    g.elem = plan.elem;
+    g.gbuf = ws + plan.off_gather;
     {
         ScopedTiming t(timer, 1);
-        hipLaunchKernelGGL((gather_kernel<Compute, typename P::In, P::KPACK>), ggrid, dim3(kGatherThreads), 0,
+        const dim3 grid((unsigned)ceil_div(kpad, kGatherPositions), (unsigned)batch, (unsigned)plan.nprob);
+        hipLaunchKernelGGL((gather_kernel<Compute, typename P::In, P::KPACK>), grid, dim3(kGatherThreads), 0,
                            stream, g);
     }
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
 
     const int64_t groups = batch < plan.groups_max ? batch : plan.groups_max;
-    const int64_t tiles = plan.tiles_m * plan.tiles_n;
     SketchParams s;
-    s.m = plan.m; s.p = plan.p; s.kc = kc; s.kpad = kpad; s.batch = batch;
-    s.tiles_n = plan.tiles_n;
-    s.scale = (double)plan.n / (double)lr.c;
+    s.descs = descs;
+    s.tile_owner = reinterpret_cast<const int32_t*>(ws + plan.off_tile_owner);
+    s.total_tiles = plan.total_tiles;
+    s.groups = groups;
+    s.kc = kc;
+    s.kpad = kpad;
+    s.batch = batch;
+    s.elem = plan.elem;
     s.omega = lr.c_prev > 0 ? 1.0 - (double)lr.c / (double)lr.c_prev : 1.0;
-    s.GA = g.GA; s.GB = g.GB;
+    s.c = (uint32_t)lr.c;
+    s.gbuf = g.gbuf;
     s.part_mean = reinterpret_cast<double*>(ws + plan.off_part_mean);
     s.part_m2 = reinterpret_cast<double*>(ws + plan.off_part_m2);
+    s.sum_mp = plan.sum_mp;
+    int64_t blocks = plan.total_tiles * groups;
+    if (blocks > kSketchMaxBlocks) blocks = kSketchMaxBlocks;
     {
         ScopedTiming t(timer, 0);
-        hipLaunchKernelGGL(sketch_kernel<P>, dim3((unsigned)tiles, (unsigned)groups), dim3(kSketchThreads), 0,
-                           stream, s);
+        hipLaunchKernelGGL((sketch_kernel<P, NB>), dim3((unsigned)blocks), dim3(kSketchThreads), 0, stream, s);
     }
     err = hipGetLastError();
     if (err != hipSuccess) return err;
 
-    const int64_t mp = plan.m * plan.p;
     MergeParams mg;
-    mg.mp = mp; mg.batch = batch; mg.groups = groups; mg.tiles = tiles;
+    mg.descs = descs;
+    mg.level = lr.level;
+    mg.batch = batch;
+    mg.groups = groups;
+    mg.total_tiles = plan.total_tiles;
+    mg.sum_mp = plan.sum_mp;
+    mg.sum_merge_blocks = plan.sum_merge_blocks;
+    mg.nprob = plan.nprob;
     mg.done_before = (double)done_before;
-    mg.part_mean = s.part_mean; mg.part_m2 = s.part_m2;
-    mg.mean = reinterpret_cast<double*>(ws + plan.off_means) + (int64_t)lr.level * mp;
-    mg.between = reinterpret_cast<double*>(ws + plan.off_between) + (int64_t)lr.level * plan.merge_blocks;
-    mg.within = reinterpret_cast<double*>(ws + plan.off_within) + lr.level;
+    mg.part_mean = s.part_mean;
+    mg.part_m2 = s.part_m2;
+    mg.means = reinterpret_cast<double*>(ws + plan.off_means);
+    mg.between = reinterpret_cast<double*>(ws + plan.off_between);
+    mg.within = reinterpret_cast<double*>(ws + plan.off_within);
     {
         ScopedTiming t(timer, 2);
-        hipLaunchKernelGGL(merge_kernel, dim3((unsigned)plan.merge_blocks), dim3(kMergeThreads), 0, stream, mg);
+        hipLaunchKernelGGL(merge_kernel, dim3((unsigned)plan.max_merge_blocks, (unsigned)plan.nprob),
+                           dim3(kMergeThreads), 0, stream, mg);
     }
     return hipGetLastError();
 }
 
-hipError_t matmul_level_run(const MatmulPlan& plan, const LevelRange& lr, int64_t done_before,
-                            const Law& A, const Law& B, const StreamKeys& keys, char* ws,
-                            hipStream_t stream, KernelTimer* timer)
+template <typename P, typename Compute>
+static hipError_t run_pass_nb(const MatmulPlan& plan, const LevelRange& lr, int64_t k_first, int64_t batch,
+                              int64_t done_before, int64_t kc, int64_t kpad, const StreamKeys& keys, char* ws,
+                              hipStream_t stream, KernelTimer* timer)
+{
+    if (plan.nb == 1)
+        return run_pass<P, Compute, 1>(plan, lr, k_first, batch, done_before, kc, kpad, keys, ws, stream, timer);
+    return run_pass<P, Compute, 2>(plan, lr, k_first, batch, done_before, kc, kpad, keys, ws, stream, timer);
+}
+
+hipError_t matmul_level_run(const MatmulPlan& plan, const LevelRange& lr, int64_t done_before, const StreamKeys& keys,
+                            char* ws, hipStream_t stream, KernelTimer* timer)
 {
     int64_t kc, kpad;
     level_padding(plan, lr.c, lr.c_prev, kc, kpad);
-    int64_t level_batch = plan.gather_bytes / (kpad * (plan.m + plan.p) * plan.elem + 512);
+    const int64_t per_sample = kpad * plan.sum_rows * plan.elem;
+    int64_t level_batch = plan.gather_bytes / per_sample;
     if (level_batch < 1) level_batch = 1;
     if (level_batch > 65535) level_batch = 65535;
     for (int64_t b = 0; b < lr.count; b += level_batch) {
         const int64_t batch = (lr.count - b) < level_batch ? (lr.count - b) : level_batch;
         hipError_t err;
+        const int64_t k_first = lr.k_begin + b, before = done_before + b;
         if (plan.prec == 0)
-            err = run_pass<PolicyF64, double>(plan, lr, lr.k_begin + b, batch, done_before + b, A, B, keys, ws, stream, timer);
+            err = run_pass<PolicyF64, double, 2>(plan, lr, k_first, batch, before, kc, kpad, keys, ws, stream, timer);
         else if (plan.prec == 1)
-            err = run_pass<PolicyF32, float>(plan, lr, lr.k_begin + b, batch, done_before + b, A, B, keys, ws, stream, timer);
+            err = run_pass_nb<PolicyF32, float>(plan, lr, k_first, batch, before, kc, kpad, keys, ws, stream, timer);
+        else if (plan.prec == 2)
+            err = run_pass_nb<PolicyBF16, float>(plan, lr, k_first, batch, before, kc, kpad, keys, ws, stream, timer);
         else
-            err = run_pass<PolicyBF16, float>(plan, lr, lr.k_begin + b, batch, done_before + b, A, B, keys, ws, stream, timer);
+            err = run_pass_nb<PolicyFP8, float>(plan, lr, k_first, batch, before, kc, kpad, keys, ws, stream, timer);
         if (err != hipSuccess) return err;
     }
     return hipSuccess;
 }
 
-hipError_t matmul_finalize(const MatmulPlan& plan, const int64_t* counts, char* ws, double* out,
-                           double* level_means, hipStream_t stream)
+hipError_t matmul_finalize(const MatmulPlan& plan, const int64_t* counts, char* ws, bool write_outputs,
+                           hipStream_t stream)
 {
     FinalizeParams f;
+    f.descs = reinterpret_cast<const ProblemDesc*>(ws + plan.off_desc);
     f.num_levels = plan.num_levels;
-    f.merge_blocks = plan.merge_blocks;
+    f.sum_mp = plan.sum_mp;
+    f.sum_merge_blocks = plan.sum_merge_blocks;
+    f.nprob = plan.nprob;
     for (int l = 0; l < 32; ++l) f.counts[l] = l < plan.num_levels ? (double)counts[l] : 0.0;
+    f.means = reinterpret_cast<const double*>(ws + plan.off_means);
     f.between = reinterpret_cast<const double*>(ws + plan.off_between);
     f.within = reinterpret_cast<const double*>(ws + plan.off_within);
     f.var = reinterpret_cast<double*>(ws + plan.off_var);
-    hipLaunchKernelGGL(level_var_kernel, dim3((unsigned)plan.num_levels), dim3(kMergeThreads), 0, stream, f);
+    hipLaunchKernelGGL(level_var_kernel, dim3((unsigned)plan.num_levels, (unsigned)plan.nprob), dim3(kMergeThreads),
+                       0, stream, f);
     hipError_t err = hipGetLastError();
-    if (err != hipSuccess) return err;
-    const int64_t mp = plan.m * plan.p;
-    hipLaunchKernelGGL(telescope_kernel, dim3((unsigned)ceil_div(mp, kMergeThreads)), dim3(kMergeThreads), 0,
-                       stream, reinterpret_cast<const double*>(ws + plan.off_means), plan.num_levels, mp, out,
-                       level_means);
+    if (err != hipSuccess || !write_outputs) return err;
+    hipLaunchKernelGGL(telescope_kernel, dim3((unsigned)ceil_div(plan.max_mp, kMergeThreads), (unsigned)plan.nprob),
+                       dim3(kMergeThreads), 0, stream, f);
     return hipGetLastError();
 }
 

@@ -14,9 +14,9 @@ from typing import Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import Dist, Levels, MLMCError, Report, check, lib
+from ._lib import Dist, Levels, MLMCError, Problem, Report, Tuning, check, lib
 
-PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "fp8": 3}
 FLAG_SHARED_SAMPLES = 1
 SHARED_LEVEL_FIELD = 0xFF
 
@@ -223,3 +223,89 @@ def matmul_adjoint_reparam(MA: torch.Tensor, SA: torch.Tensor, MB: torch.Tensor,
                                             ctypes.byref(h.lv), g.data_ptr(), *[t.data_ptr() for t in grads],
                                             workspace.data_ptr(), ws_bytes, _stream(device)))
     return tuple(grads)
+
+
+# ------------------------------------------------------------------ batching
+@dataclass
+class BatchProblem:
+    """One product of a batched estimate: shapes, laws, Philox stream id."""
+    m: int
+    n: int
+    p: int
+    A: Law
+    B: Law
+    problem: int
+
+
+class BatchedEstimate:
+    """Many independent products through one pipeline (mlmc_matmul_estimate_batched),
+    optionally captured once into a hipGraph and replayed.  Outputs live in
+    `self.Y` (one m x p FP64 device tensor per product)."""
+
+    def __init__(self, problems: Sequence[BatchProblem], c: Sequence[int], n_samples: Sequence[int],
+                 seed: int = 0, prec: str = "fp32", tuning: Optional[dict] = None, device=None):
+        self.device = torch.device(device or "cuda")
+        self.problems = list(problems)
+        self.h = _LevelsHolder(c, n_samples, 0.0, 0, seed, prec, False, 0, 0)
+        self.Y = [torch.empty((pr.m, pr.p), dtype=torch.float64, device=self.device) for pr in self.problems]
+        arr = (Problem * len(self.problems))()
+        for i, pr in enumerate(self.problems):
+            arr[i].m, arr[i].n, arr[i].p = pr.m, pr.n, pr.p
+            arr[i].A, arr[i].B = pr.A.c(), pr.B.c()
+            arr[i].problem = pr.problem
+            arr[i].out = self.Y[i].data_ptr()
+            arr[i].level_means = None
+        self.table = arr
+        self.tuning = Tuning()
+        t = tuning or {}
+        self.tuning.tile = int(t.get("tile", 0))
+        self.tuning.target_blocks = int(t.get("target_blocks", 0))
+        self.tuning.gather_budget = int(t.get("gather_budget", 0))
+        self.ws_bytes = int(lib().mlmc_matmul_batched_workspace_size(len(arr), arr, ctypes.byref(self.h.lv),
+                                                                     ctypes.byref(self.tuning)))
+        if self.ws_bytes == 0:
+            raise MLMCError(1, lib().mlmc_last_error().decode(errors="replace") or "invalid batch")
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.graph = None
+        self.num_levels = len(c)
+
+    def run(self, level_var: bool = False):
+        """Enqueue one batched estimate; with level_var, return V_l per product
+        (num_levels x nprob, synchronises)."""
+        out = (ctypes.c_double * (self.num_levels * len(self.problems)))() if level_var else None
+        check(lib().mlmc_matmul_estimate_batched(len(self.table), self.table, ctypes.byref(self.h.lv),
+                                                 ctypes.byref(self.tuning), self.workspace.data_ptr(),
+                                                 self.ws_bytes, out, _stream(self.device)))
+        if level_var:
+            import numpy as np
+            return np.array(out[:]).reshape(self.num_levels, len(self.problems))
+        return None
+
+    def capture(self, stream: Optional[torch.cuda.Stream] = None):
+        """Capture the whole estimate into a hipGraph on a side stream."""
+        self.release()
+        stream = stream or torch.cuda.Stream(device=self.device)
+        handle = ctypes.c_void_p()
+        check(lib().mlmc_matmul_batched_graph_create(len(self.table), self.table, ctypes.byref(self.h.lv),
+                                                     ctypes.byref(self.tuning), self.workspace.data_ptr(),
+                                                     self.ws_bytes, stream.cuda_stream, ctypes.byref(handle)))
+        self.graph = handle
+        self.graph_stream = stream
+        return self
+
+    def replay(self):
+        """Launch the captured graph on the current stream."""
+        if self.graph is None:
+            raise RuntimeError("capture() first")
+        check(lib().mlmc_graph_launch(self.graph, _stream(self.device)))
+
+    def release(self):
+        if self.graph is not None:
+            check(lib().mlmc_graph_destroy(self.graph))
+            self.graph = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass

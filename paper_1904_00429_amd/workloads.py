@@ -53,6 +53,12 @@ MATMUL_LARGE = Workload("matmul-1024x65536x1024", "matmul", 1024, _N3, 1024, ("n
                         1e-2 * _N3 * 0.25 * math.sqrt(1024 * 1024), 64, "bf16")
 
 
+# Differentiation form: A = M_A + S_A o Z (512 x 32768), B = M_B + S_B o W
+# (32768 x 512); c_l = 32 * 2^l, l = 0..6; fixed N_l = 4096 * 2^-l.
+DIFF_512x32768x512 = Workload("diff-512x32768x512", "matmul", 512, 32768, 512, ("reparam",), ("reparam",),
+                              ladder(32, 7), [4096 >> l for l in range(7)], prec="fp32")
+
+
 def reparam_inputs(m: int, n: int, p: int, seed: int = 0):
     """M_A, M_B ~ N(0, 1), S_A, S_B ~ U(0.1, 1), T ~ N(0, 1) (m x p), FP32.
 

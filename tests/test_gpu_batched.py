@@ -1,0 +1,126 @@
+"""GPU parity of the batching form (one pipeline over many uneven products,
+hipGraph replay, autotuner) and of the FP8 precision form, against the oracle
+run product by product with the same stream ids.
+
+Tolerances: FP64 1e-12, FP32 1e-5 (relative Frobenius); BF16 0.05 RMSE_est;
+FP8 e4m3: ||Y - Y_oracle||_F <= 0.25 RMSE_est and V_l within 15% (each operand
+carries up to 2^-4 relative rounding, about 4-7% of the sampling spread of a
+single level sample for these laws, shrinking with N_l in the estimate)."""
+import json
+import os
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+from gpu_helpers import flush, laws, rel_frob
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+SHAPES = [(64, 500, 64), (128, 1234, 192), (64, 4096, 320), (256, 777, 64), (192, 2000, 128), (100, 999, 37)]
+MUS = [0.1, 0.7, 1.3, 1.9, 0.4, 1.0]
+C, N = [16, 32, 64], [60, 30, 15]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def refs(orc):
+    def one(i):
+        m, n, p = SHAPES[i]
+        law = orc.Law.normal(MUS[i], 1.0)
+        return orc.estimate(m, n, p, law, law, C, n_samples=N, seed=17, problem=100 + i)
+    with ThreadPoolExecutor(max_workers=min(len(SHAPES), os.cpu_count() or 4)) as ex:
+        return list(ex.map(one, range(len(SHAPES))))
+
+
+def _batch(dev, prec, tuning=None):
+    from paper_1904_00429_amd import BatchedEstimate, BatchProblem, Law
+    probs = [BatchProblem(m, n, p, Law.normal(mu, 1.0), Law.normal(mu, 1.0), 100 + i)
+             for i, ((m, n, p), mu) in enumerate(zip(SHAPES, MUS))]
+    return BatchedEstimate(probs, C, N, seed=17, prec=prec, tuning=tuning, device=dev)
+
+
+def _check(est, V, refs, prec):
+    for i, ref in enumerate(refs):
+        Y = est.Y[i].cpu().numpy()
+        if prec in ("fp64", "fp32"):
+            tol = 1e-12 if prec == "fp64" else 1e-5
+            assert rel_frob(Y, ref.Y) <= tol, (i, rel_frob(Y, ref.Y))
+            np.testing.assert_allclose(V[:, i], ref.level_var, rtol=1e-10 if prec == "fp64" else 1e-5)
+        else:
+            bound = 0.05 if prec == "bf16" else 0.25
+            err = np.linalg.norm((Y - ref.Y).ravel())
+            flush(f"  product {i} {prec}: |Y - Y_oracle| = {err:.4g}, RMSE_est = {ref.rmse_est:.4g}")
+            assert err <= bound * ref.rmse_est, (i, err, ref.rmse_est)
+            np.testing.assert_allclose(V[:, i], ref.level_var, rtol=0.03 if prec == "bf16" else 0.15)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("tile", [64, 128])
+def test_batched_matches_oracle(orc, dev, refs, prec, tile):
+    flush(f"batched prec={prec} tile={tile}")
+    est = _batch(dev, prec, {"tile": tile})
+    V = est.run(level_var=True)
+    _check(est, V, refs, prec)
+
+
+def test_graph_replays_match_eager(orc, dev, refs):
+    """A captured graph replayed several times, with other device work and
+    synchronisations in between, reproduces the eager result every time."""
+    est = _batch(dev, "fp32", {"tile": 64})
+    est.run()
+    torch.cuda.synchronize()
+    eager = [y.clone() for y in est.Y]
+    est.capture()
+    for r in range(3):
+        for y in est.Y:
+            y.fill_(float("nan"))
+        junk = torch.randn(1 << 20, device=dev).sum()
+        torch.cuda.synchronize()
+        est.replay()
+        torch.cuda.synchronize()
+        for y, e in zip(est.Y, eager):
+            assert torch.equal(y, e), f"replay {r} differs"
+        del junk
+    est.release()
+    V = est.run(level_var=True)
+    _check(est, V, refs, "fp32")
+
+
+def test_fp8_single_product(orc, dev):
+    from paper_1904_00429_amd import matmul_estimate
+    m, n, p, c, N = 96, 3000, 160, [16, 32, 64, 128], [400, 200, 100, 50]
+    oA, gA = laws(orc, ("normal", 1.5, 1.0), dev)
+    oB, gB = laws(orc, ("uniform", 0.3, 2.0), dev)
+    est = matmul_estimate(m, n, p, gA, gB, c, n_samples=N, seed=4, prec="fp8", device=dev)
+    ref = orc.estimate(m, n, p, oA, oB, c, n_samples=N, seed=4)
+    err = np.linalg.norm((est.Y.cpu().numpy() - ref.Y).ravel())
+    flush(f"fp8 single: err {err:.4g} rmse {ref.rmse_est:.4g}")
+    assert err <= 0.25 * ref.rmse_est
+    np.testing.assert_allclose(est.level_var, ref.level_var, rtol=0.15)
+
+
+def test_batched_rejects_duplicate_streams(dev):
+    from paper_1904_00429_amd import BatchedEstimate, BatchProblem, Law, MLMCError
+    probs = [BatchProblem(64, 100, 64, Law.normal(0, 1), Law.normal(0, 1), 5) for _ in range(2)]
+    with pytest.raises(MLMCError):
+        BatchedEstimate(probs, [4, 8], [10, 5], device=dev)
+
+
+def test_autotuner_picks_and_caches(dev, tmp_path, monkeypatch):
+    from paper_1904_00429_amd import BatchProblem, Law, autotune
+    monkeypatch.setenv("MLMC_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))
+    probs = [BatchProblem(m, n, p, Law.normal(mu, 1.0), Law.normal(mu, 1.0), i)
+             for i, ((m, n, p), mu) in enumerate(zip(SHAPES, MUS))]
+    best = autotune.tune(probs, C, N, prec="fp8", device=dev)
+    assert best in autotune.CANDIDATES
+    cached = json.load(open(tmp_path / "cache.json"))
+    assert len(cached) == 1 and list(cached.values())[0]["best"] == best
+    assert autotune.tune(probs, C, N, prec="fp8", device=dev) == best
