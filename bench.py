@@ -69,7 +69,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="inner", choices=["inner", "matmul-large", "matmul-small", "diff"])
+    ap.add_argument("--workload", default="inner", choices=["inner", "matmul-large", "matmul-small", "diff", "batched", "matmul-large-fixed"])
     ap.add_argument("--prec", default=None, help="fp32 (default) or fp64; bf16 for matmul")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-fraction", type=float, default=0.15,
@@ -137,6 +137,10 @@ def main():
     timing_flag = 2
     if args.workload == "diff":
         return bench_diff(args)
+    if args.workload == "batched":
+        return bench_batched(args)
+    if args.workload == "matmul-large-fixed":
+        return bench_large_fixed(args)
     if args.workload == "inner":
         wl = workloads.INNER_2POW20
         prec = args.prec or "fp32"
@@ -274,6 +278,86 @@ def bench_diff(args):
                                 "peak": PEAK_MFMA["fp32"] / 1e12, "unit": "TFLOP/s",
                                 "frac": flops / (adj_ms * 1e-3) / PEAK_MFMA["fp32"], "draws": draws}}
     print(json.dumps(out), flush=True)
+
+
+def _time_replays(est, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        est.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        est.replay()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def bench_batched(args):
+    """Batching form: 256 uneven products per estimate, one hipGraph replay per
+    step; FP8 e4m3 (the value) and FP32 (for the ratio), autotuned tiles."""
+    import torch
+    from paper_1904_00429_amd import BatchedEstimate, BatchProblem, Law, autotune, workloads
+    dev = torch.device("cuda:0")
+    shapes, mus, c, N = workloads.batched_products()
+    probs = [BatchProblem(m, n, p, Law.normal(mu, 1.0), Law.normal(mu, 1.0), i)
+             for i, ((m, n, p), mu) in enumerate(zip(shapes, mus))]
+    draws = sum(Nl * cl for Nl, cl in zip(N, c))
+    flops = sum(2.0 * m * p for m, n, p in shapes) * draws
+    out = {}
+    for prec in ("fp8", "fp32"):
+        best = autotune.tune(probs, c, N, prec=prec, device=dev)
+        est = BatchedEstimate(probs, c, N, seed=0, prec=prec, tuning=best, device=dev)
+        est.capture()
+        sec = _time_replays(est, args.steps, args.warmup)
+        out[prec] = {"s_per_estimate": sec, "tuning": best, "mfma_tflops_whole_graph": flops / sec / 1e12}
+        est.release()
+        del est
+        torch.cuda.empty_cache()
+    value = 1.0 / out["fp8"]["s_per_estimate"]
+    res = {"metric": "MLMC batched estimates/s (256 products per estimate, fixed N_l)", "value": value,
+           "unit": "estimates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1e3 * out["fp8"]["s_per_estimate"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "fp8", "data": "synthetic",
+           "config": {"workload": "batched-256-uneven", "products": len(shapes), "c0": c[0], "levels": len(c),
+                      "N": N, "graph": True},
+           "products_per_s": len(shapes) * value,
+           "fp32_value": 1.0 / out["fp32"]["s_per_estimate"],
+           "fp8_over_fp32": out["fp32"]["s_per_estimate"] / out["fp8"]["s_per_estimate"],
+           "forms": out,
+           "roofline": {"bound": "mfma", "achieved": out["fp8"]["mfma_tflops_whole_graph"],
+                        "peak": 5000.0, "unit": "TFLOP/s",
+                        "frac": out["fp8"]["mfma_tflops_whole_graph"] / 5000.0, "traffic": None,
+                        "note": "algorithmic 2 m p flops per draw over the whole graph time"}}
+    print(json.dumps(res), flush=True)
+
+
+def bench_large_fixed(args):
+    """1024 x 65536 x 1024 at the N_l a target-RMSE run chose, through the
+    table pipeline with each tile shape, BF16 and FP32 (sketch-kernel study)."""
+    import torch
+    from paper_1904_00429_amd import BatchedEstimate, BatchProblem, Law, workloads
+    dev = torch.device("cuda:0")
+    wl = workloads.MATMUL_LARGE
+    N = [120032, 60001, 30001, 15001, 7501, 3751, 1876, 938]
+    draws = sum(a * b for a, b in zip(N, wl.c))
+    flops = 2.0 * wl.m * wl.p * draws
+    prob = [BatchProblem(wl.m, wl.n, wl.p, Law.normal(0.5, 1.0), Law.normal(0.5, 1.0), 0)]
+    res = {}
+    for prec in ("bf16", "fp32"):
+        for tile in (64, 128):
+            est = BatchedEstimate(prob, wl.c, N, seed=0, prec=prec, tuning={"tile": tile}, device=dev)
+            est.run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                est.run()
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t0) / args.steps
+            res[f"{prec}-tile{tile}"] = {"s_per_estimate": sec, "estimates_per_s": 1.0 / sec,
+                                         "mfma_tflops_whole_pipeline": flops / sec / 1e12}
+            del est
+            torch.cuda.empty_cache()
+    print(json.dumps({"workload": "matmul-1024x65536x1024-fixedN", "N": N, "results": res}), flush=True)
 
 
 _WS = {}

@@ -56,6 +56,53 @@ __device__ __forceinline__ T law_value(const Law& law, T z_normal, T u_uniform, 
     return fma(z_normal, (T)law.scale, (T)law.loc);
 }
 
+// Law pairs with a specialised kernel instantiation (no per-value law branches
+// in hot loops); every other combination takes the general path.
+enum { kLawsAny = 0, kLawsUniform = 1, kLawsNormal = 2 };
+
+__host__ __device__ inline int law_pair_kind(int a, int b)
+{
+    return (a == 1 && b == 1) ? kLawsUniform : (a == 0 && b == 0) ? kLawsNormal : kLawsAny;
+}
+
+// A law with its affine constants precomputed in the arithmetic type T, held
+// in registers: value = fma(u, mul, add) (uniform), fma(z, mul, add) (normal),
+// fma(stdev[i], z, mean[i]) (reparameterised).
+template <typename T>
+struct LawEval {
+    int kind;
+    T mul, add;
+    const float* mean;
+    const float* stdev;
+    int64_t ld;
+
+    __device__ __forceinline__ static LawEval make(const Law& law)
+    {
+        LawEval e;
+        e.kind = law.kind;
+        e.mul = (T)(law.kind == 1 ? 2.0 * law.scale : law.scale);
+        e.add = (T)(law.kind == 1 ? law.loc - law.scale : law.loc);
+        e.mean = law.mean;
+        e.stdev = law.stdev;
+        e.ld = law.ld;
+        return e;
+    }
+    __device__ __forceinline__ T operator()(T z, T u, int64_t idx) const
+    {
+        if (kind == 1) return fma(u, mul, add);
+        if (kind == 2) return fma((T)stdev[idx], z, (T)mean[idx]);
+        return fma(z, mul, add);
+    }
+    // the same with the kind fixed at compile time by the law pair
+    template <int LAWS>
+    __device__ __forceinline__ T eval(T z, T u, int64_t idx) const
+    {
+        if (LAWS == kLawsUniform) return fma(u, mul, add);
+        if (LAWS == kLawsNormal) return fma(z, mul, add);
+        return (*this)(z, u, idx);
+    }
+};
+
 template <typename T>
 __device__ __forceinline__ void quad_values(const Words4& w, bool need_normal, T& u0, T& u1,
                                             T& u2, T& u3, T& z0, T& z1, T& z2, T& z3)

@@ -62,10 +62,6 @@ __device__ __forceinline__ uint32_t inner_index(uint32_t lo, uint32_t hi, const 
     return index_from_words(lo, hi, prm.n);
 }
 
-// Law pairs with a specialised instantiation (no per-value law branches in the
-// hot loop); every other combination takes the general path.
-enum { kLawsAny = 0, kLawsUniform = 1, kLawsNormal = 2 };
-
 template <typename T, int LAWS>
 __device__ __forceinline__ T inner_product_term(const InnerMultiParams& prm, uint32_t k, uint32_t j,
                                                 uint32_t sid_value)
@@ -328,7 +324,7 @@ hipError_t inner_levels_run(const LevelRange* ranges, int num_levels, int64_t n,
         next = again;
     }
     if (next == 0) return hipSuccess;
-    const int laws = (x.kind == 1 && y.kind == 1) ? kLawsUniform : (x.kind == 0 && y.kind == 0) ? kLawsNormal : kLawsAny;
+    const int laws = law_pair_kind(x.kind, y.kind);
     {
         ScopedTiming t(timer, 0);
         const dim3 grid(next), block(kInnerBlock);

@@ -81,10 +81,11 @@ struct MatmulTuning {
 // Device-side description of one product of the table.
 struct ProblemDesc {
     int64_t m, n, p;
+    int64_t m_pad, p_pad;      // gathered row counts, padded to the workgroup tile
     Law A, B;
     uint32_t sid_problem;
     int64_t tiles_n, tiles, tile_first;
-    int64_t rows_prefix;       // sum of (m + p) over earlier products
+    int64_t rows_prefix;       // sum of (m_pad + p_pad) over earlier products
     int64_t mp_prefix;         // sum of m p over earlier products
     int64_t merge_blocks, between_prefix;
     float pre_a, pre_b;        // FP8 operand pre-scales (powers of two), else 1
@@ -99,6 +100,7 @@ struct MatmulPlan {
     int64_t c[32];
     int nprob;
     int kstep, kpack, elem, nb, tile;
+    int laws;                  // law pair shared by every product (kLaws*), else kLawsAny
     int64_t kpad_max;
     int64_t sum_rows, sum_mp, sum_merge_blocks, total_tiles, max_mp, max_merge_blocks;
     int64_t groups_max, gather_bytes, state_doubles;

@@ -176,65 +176,93 @@ template <> struct StoreOf<uint8_t> {
     }
 };
 
-template <typename Compute, typename Store, int KPACK>
+template <typename Compute, typename Store, int KPACK, int LAWS>
 __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm)
 {
     __shared__ uint32_t cols[kGatherPositions];
     __shared__ int valid[kGatherPositions];
-    const ProblemDesc& P = prm.descs[blockIdx.z];
+    // the product's description is copied to registers once: the stores into
+    // the gathered buffer below could otherwise alias it and force reloads
+    const ProblemDesc* Pp = prm.descs + blockIdx.z;
+    const int64_t m = Pp->m, p = Pp->p;
+    const int64_t m_pad = Pp->m_pad, p_pad = Pp->p_pad;
+    const uint32_t n = (uint32_t)Pp->n;
+    const uint32_t sid_problem = Pp->sid_problem;
+    const int64_t rows_prefix = Pp->rows_prefix;
+    const LawEval<Compute> LA = LawEval<Compute>::make(Pp->A);
+    const LawEval<Compute> LB = LawEval<Compute>::make(Pp->B);
+    const float pre_a = Pp->pre_a, pre_b = Pp->pre_b;
     const int64_t pos0 = (int64_t)blockIdx.x * kGatherPositions;
     const int64_t slot = blockIdx.y;
     const uint32_t k = prm.k_first + (uint32_t)slot;
-    const uint32_t sid_index = stream_id(kTagIndex, prm.level_field, P.sid_problem);
-    const uint32_t sid_value = stream_id(kTagValue, prm.level_field, P.sid_problem);
+    const uint32_t sid_index = stream_id(kTagIndex, prm.level_field, sid_problem);
+    const uint32_t sid_value = stream_id(kTagValue, prm.level_field, sid_problem);
     if (threadIdx.x < kGatherPositions) {
         const int64_t pos = pos0 + threadIdx.x;
         const int64_t t = pos < prm.kpad ? draw_of_position(pos, prm.kc, prm.c, prm.c_prev) : -1;
         valid[threadIdx.x] = t >= 0;
-        cols[threadIdx.x] = t >= 0 ? draw_index((uint32_t)t, k, sid_index, prm.key0, prm.key1, (uint32_t)P.n) : 0u;
+        cols[threadIdx.x] = t >= 0 ? draw_index((uint32_t)t, k, sid_index, prm.key0, prm.key1, n) : 0u;
     }
     __syncthreads();
-    const int64_t m = P.m, p = P.p;
     const int64_t rows = m + p;
     const int64_t quads = ceil_div(rows, 4);
-    const bool normal = P.A.kind != 1 || P.B.kind != 1;
+    const bool normal = LAWS == kLawsNormal || (LAWS == kLawsAny && (LA.kind != 1 || LB.kind != 1));
     const int npos = (int)((prm.kpad - pos0) < kGatherPositions ? (prm.kpad - pos0) : kGatherPositions);
     const int64_t pass_rows = prm.batch * prm.kpad * (int64_t)prm.elem;
-    Store* GA = reinterpret_cast<Store*>(prm.gbuf + pass_rows * P.rows_prefix) + slot * prm.kpad * m;
-    Store* GB = reinterpret_cast<Store*>(prm.gbuf + pass_rows * (P.rows_prefix + m)) + slot * prm.kpad * p;
+    Store* __restrict__ GA = reinterpret_cast<Store*>(prm.gbuf + pass_rows * rows_prefix) + slot * prm.kpad * m_pad;
+    Store* __restrict__ GB = reinterpret_cast<Store*>(prm.gbuf + pass_rows * (rows_prefix + m_pad)) + slot * prm.kpad * p_pad;
+    uint32_t jv[kGatherPositions];
+    bool ok[kGatherPositions];
+#pragma unroll
+    for (int ip = 0; ip < kGatherPositions; ++ip) {
+        jv[ip] = cols[ip];
+        ok[ip] = ip < npos && valid[ip];
+    }
     for (int64_t q = threadIdx.x; q < quads; q += kGatherThreads) {
         Store vals[kGatherPositions][4];
+        const int64_t e0 = 4 * q;
 #pragma unroll
         for (int ip = 0; ip < kGatherPositions; ++ip) {
-            if (ip >= npos || !valid[ip]) {
+            if (!ok[ip]) {
+#pragma unroll
                 for (int r = 0; r < 4; ++r) vals[ip][r] = StoreOf<Store>::from((Compute)0, 1.0f);
                 continue;
             }
-            const uint32_t j = cols[ip];
+            const uint32_t j = jv[ip];
             const Words4 w = philox4x32_10((uint32_t)q, k, j, sid_value, prm.key0, prm.key1);
             Compute u[4], z[4];
             quad_values<Compute>(w, normal, u[0], u[1], u[2], u[3], z[0], z[1], z[2], z[3]);
+            if (e0 + 3 < m) {            // the whole quad is in A's column
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t e = 4 * q + r;
-                Compute v = (Compute)0;
-                float pre = 1.0f;
-                if (e < m) {
-                    v = law_value<Compute>(P.A, z[r], u[r], (int64_t)j * P.A.ld + e);
-                    pre = P.pre_a;
-                } else if (e < rows) {
-                    v = law_value<Compute>(P.B, z[r], u[r], (int64_t)j * P.B.ld + (e - m));
-                    pre = P.pre_b;
+                for (int r = 0; r < 4; ++r)
+                    vals[ip][r] = StoreOf<Store>::from(LA.template eval<LAWS>(z[r], u[r], (int64_t)j * LA.ld + e0 + r), pre_a);
+            } else if (e0 >= m) {        // the whole quad is in B's row
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    vals[ip][r] = StoreOf<Store>::from(LB.template eval<LAWS>(z[r], u[r], (int64_t)j * LB.ld + (e0 + r - m)), pre_b);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t e = e0 + r;
+                    Compute v = (Compute)0;
+                    float pre = 1.0f;
+                    if (e < m) {
+                        v = LA.template eval<LAWS>(z[r], u[r], (int64_t)j * LA.ld + e);
+                        pre = pre_a;
+                    } else if (e < rows) {
+                        v = LB.template eval<LAWS>(z[r], u[r], (int64_t)j * LB.ld + (e - m));
+                        pre = pre_b;
+                    }
+                    vals[ip][r] = StoreOf<Store>::from(v, pre);
                 }
-                vals[ip][r] = StoreOf<Store>::from(v, pre);
             }
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int64_t e = 4 * q + r;
+            const int64_t e = e0 + r;
             if (e >= rows) break;
             Store* G = e < m ? GA : GB;
-            const int64_t R = e < m ? m : p;
+            const int64_t R = e < m ? m_pad : p_pad;
             const int64_t row = e < m ? e : e - m;
             if constexpr (KPACK == 1) {
 #pragma unroll
@@ -244,6 +272,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
                 // positions pos0 .. pos0+7 are one packed group of 8 draws
                 typedef Store vec_t __attribute__((ext_vector_type(KPACK)));
                 vec_t vv;
+#pragma unroll
                 for (int ip = 0; ip < KPACK; ++ip) vv[ip] = vals[ip][r];
                 *reinterpret_cast<vec_t*>(G + ((pos0 / KPACK) * R + row) * KPACK) = vv;
             }
@@ -269,63 +298,135 @@ struct SketchParams {
     int64_t sum_mp;
 };
 
+// LDS fragment reads: the staged chunk keeps the global slab layout
+// [position / KPACK][tile rows][KPACK] of the gathered buffer.
+template <typename P> struct LdsFrag;
+template <> struct LdsFrag<PolicyF64> {
+    static __device__ __forceinline__ double load(const double* L, int BM, int kk, int row, int lane)
+    {
+        return L[(kk + lane / 16) * BM + row + lane % 16];
+    }
+};
+template <> struct LdsFrag<PolicyF32> {
+    static __device__ __forceinline__ float load(const float* L, int BM, int kk, int row, int lane)
+    {
+        return L[(kk + lane / 32) * BM + row + lane % 32];
+    }
+};
+template <> struct LdsFrag<PolicyBF16> {
+    static __device__ __forceinline__ bf16x8 load(const __bf16* L, int BM, int kk, int row, int lane)
+    {
+        return *reinterpret_cast<const bf16x8*>(L + ((kk / 8 + lane / 32) * BM + row + lane % 32) * 8);
+    }
+};
+template <> struct LdsFrag<PolicyFP8> {
+    static __device__ __forceinline__ long load(const uint8_t* L, int BM, int kk, int row, int lane)
+    {
+        return *reinterpret_cast<const long*>(L + ((kk / 8 + lane / 32) * BM + row + lane % 32) * 8);
+    }
+};
+
+// draws staged per chunk: several MFMA steps per synchronisation
+template <typename P> struct ChunkOf { static constexpr int KC = 64; };
+template <> struct ChunkOf<PolicyF64> { static constexpr int KC = 16; };
+template <> struct ChunkOf<PolicyF32> { static constexpr int KC = 32; };
+
 template <typename P, int NB>
 __global__ __launch_bounds__(kSketchThreads) void sketch_kernel(SketchParams prm)
 {
     using In = typename P::In;
     using Acc = typename P::Acc;
     using FragT = typename P::FragT;
-    constexpr int NE = NB * NB * P::REGS;  // entries per lane
-    constexpr int WT = NB * P::BLK;        // wave tile edge
+    constexpr int NE = NB * NB * P::REGS;            // entries per lane
+    constexpr int WT = NB * P::BLK;                  // wave tile edge
+    constexpr int BM = 2 * WT;                       // workgroup tile edge (rows = columns)
+    constexpr int KC = ChunkOf<P>::KC;               // draws per staged chunk
+    constexpr int SLABS = KC / P::KPACK;
+    constexpr int VEC = 16 / (int)sizeof(In);        // elements per 16-byte vector
+    constexpr int V_SLAB = BM * P::KPACK / VEC;      // vectors per slab of one operand
+    constexpr int VPT = SLABS * V_SLAB / kSketchThreads;  // vectors per thread per operand
+    static_assert(SLABS * V_SLAB % kSketchThreads == 0, "chunk must split evenly over the workgroup");
+    __shared__ __align__(16) In lds[2][2][KC * BM];  // [buffer][A, B][chunk]
     __shared__ double red[kSketchThreads / kWave];
 
     const int lane = threadIdx.x % kWave;
     const int wave = threadIdx.x / kWave;
+    const int wrow = (wave / 2) * WT, wcol = (wave % 2) * WT;  // wave tile inside the workgroup tile
     const int64_t items = prm.total_tiles * prm.groups;
     for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
         const int64_t group = item / prm.total_tiles;
         const int64_t tt = item % prm.total_tiles;
         const ProblemDesc& Pd = prm.descs[prm.tile_owner[tt]];
         const int64_t tile = tt - Pd.tile_first;
-        const int64_t m = Pd.m, p = Pd.p;
-        const int64_t row0 = (tile / Pd.tiles_n) * (2 * WT) + (wave / 2) * WT;
-        const int64_t col0 = (tile % Pd.tiles_n) * (2 * WT) + (wave % 2) * WT;
+        const int64_t m = Pd.m, p = Pd.p, m_pad = Pd.m_pad, p_pad = Pd.p_pad;
+        const int64_t trow = (tile / Pd.tiles_n) * BM, tcol = (tile % Pd.tiles_n) * BM;
         const int64_t s_begin = group * prm.batch / prm.groups;
         const int64_t s_end = (group + 1) * prm.batch / prm.groups;
         const int64_t pass_rows = prm.batch * prm.kpad * (int64_t)prm.elem;
         const In* GA0 = reinterpret_cast<const In*>(prm.gbuf + pass_rows * Pd.rows_prefix);
-        const In* GB0 = reinterpret_cast<const In*>(prm.gbuf + pass_rows * (Pd.rows_prefix + m));
+        const In* GB0 = reinterpret_cast<const In*>(prm.gbuf + pass_rows * (Pd.rows_prefix + m_pad));
         const Acc scale = (Acc)((double)Pd.n / (double)prm.c * Pd.post);
         const Acc omega = (Acc)prm.omega;
+        const int64_t nch = (prm.kpad + KC - 1) / KC;
+        const int64_t total = (s_end - s_begin) * nch;
+
+        // chunk c: realisation s_begin + c / nch, draws [(c % nch) KC, +KC)
+        uint4 ra[VPT], rb[VPT];
+        auto fetch = [&](int64_t c) {
+            const int64_t s = s_begin + c / nch;
+            const int64_t k0 = (c % nch) * KC;
+            const In* ga = GA0 + s * prm.kpad * m_pad;
+            const In* gb = GB0 + s * prm.kpad * p_pad;
+#pragma unroll
+            for (int v = 0; v < VPT; ++v) {
+                const int vid = threadIdx.x + v * kSketchThreads;
+                const int slab = vid / V_SLAB, iv = vid % V_SLAB;
+                const int64_t kb = k0 / P::KPACK + slab;
+                if (k0 + slab * P::KPACK < prm.kpad) {
+                    ra[v] = *reinterpret_cast<const uint4*>(ga + (kb * m_pad + trow) * P::KPACK + iv * VEC);
+                    rb[v] = *reinterpret_cast<const uint4*>(gb + (kb * p_pad + tcol) * P::KPACK + iv * VEC);
+                } else {
+                    ra[v] = make_uint4(0, 0, 0, 0);
+                    rb[v] = make_uint4(0, 0, 0, 0);
+                }
+            }
+        };
+        auto stash = [&](int buf) {
+#pragma unroll
+            for (int v = 0; v < VPT; ++v) {
+                const int vid = threadIdx.x + v * kSketchThreads;
+                *reinterpret_cast<uint4*>(&lds[buf][0][vid * VEC]) = ra[v];
+                *reinterpret_cast<uint4*>(&lds[buf][1][vid * VEC]) = rb[v];
+            }
+        };
 
         Acc mean[NE], m2[NE];
 #pragma unroll
         for (int e = 0; e < NE; ++e) { mean[e] = (Acc)0; m2[e] = (Acc)0; }
         Acc count = (Acc)0;
-        for (int64_t s = s_begin; s < s_end; ++s) {
-            const In* GA = GA0 + s * prm.kpad * m;
-            const In* GB = GB0 + s * prm.kpad * p;
-            typename P::AccVec acc[NB][NB];
+        typename P::AccVec acc[NB][NB];
 #pragma unroll
-            for (int bi = 0; bi < NB; ++bi)
+        for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
-                for (int bj = 0; bj < NB; ++bj)
+            for (int bj = 0; bj < NB; ++bj)
 #pragma unroll
-                    for (int r = 0; r < P::REGS; ++r) acc[bi][bj][r] = (Acc)0;
-            // fragments of step kk are loaded one step ahead of their MFMAs
-            FragT a[NB], b[NB];
-#pragma unroll
-            for (int bi = 0; bi < NB; ++bi) a[bi] = P::load(GA, m, row0 + bi * P::BLK, 0, lane);
-#pragma unroll
-            for (int bj = 0; bj < NB; ++bj) b[bj] = P::load(GB, p, col0 + bj * P::BLK, 0, lane);
-            for (int64_t kk = 0; kk < prm.kpad; kk += P::KSTEP) {
-                FragT an[NB], bn[NB];
-                const int64_t kn = kk + P::KSTEP < prm.kpad ? kk + P::KSTEP : kk;
-#pragma unroll
-                for (int bi = 0; bi < NB; ++bi) an[bi] = P::load(GA, m, row0 + bi * P::BLK, kn, lane);
-#pragma unroll
-                for (int bj = 0; bj < NB; ++bj) bn[bj] = P::load(GB, p, col0 + bj * P::BLK, kn, lane);
-                if (kk == prm.kc && kk > 0) {
+                for (int r = 0; r < P::REGS; ++r) acc[bi][bj][r] = (Acc)0;
+
+        if (total > 0) {
+            fetch(0);
+            stash(0);
+        }
+        __syncthreads();
+        for (int64_t c = 0; c < total; ++c) {
+            const int buf = (int)(c & 1);
+            if (c + 1 < total) fetch(c + 1);     // global loads in flight during the MFMAs
+            const int64_t k0 = (c % nch) * KC;
+            const int64_t steps = (prm.kpad - k0 < KC ? prm.kpad - k0 : KC) / P::KSTEP;
+            const In* LA = lds[buf][0];
+            const In* LB = lds[buf][1];
+            for (int64_t st = 0; st < steps; ++st) {
+                const int kk = (int)(st * P::KSTEP);
+                if (k0 + kk == prm.kc && prm.kc > 0) {
                     // end of the coarse segment: fold in the coarse sketch weight
 #pragma unroll
                     for (int bi = 0; bi < NB; ++bi)
@@ -334,29 +435,36 @@ __global__ __launch_bounds__(kSketchThreads) void sketch_kernel(SketchParams prm
 #pragma unroll
                             for (int r = 0; r < P::REGS; ++r) acc[bi][bj][r] *= omega;
                 }
+                FragT a[NB], b[NB];
+#pragma unroll
+                for (int bi = 0; bi < NB; ++bi) a[bi] = LdsFrag<P>::load(LA, BM, kk, wrow + bi * P::BLK, lane);
+#pragma unroll
+                for (int bj = 0; bj < NB; ++bj) b[bj] = LdsFrag<P>::load(LB, BM, kk, wcol + bj * P::BLK, lane);
 #pragma unroll
                 for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
                     for (int bj = 0; bj < NB; ++bj) acc[bi][bj] = P::mma(a[bi], b[bj], acc[bi][bj]);
-#pragma unroll
-                for (int bi = 0; bi < NB; ++bi) a[bi] = an[bi];
-#pragma unroll
-                for (int bj = 0; bj < NB; ++bj) b[bj] = bn[bj];
             }
-            count += (Acc)1;
-            const Acc inv = (Acc)1 / count;
-            int e = 0;
+            if (c % nch == nch - 1) {
+                // the realisation is complete: D = scale * acc enters the Welford state
+                count += (Acc)1;
+                const Acc inv = (Acc)1 / count;
+                int e = 0;
 #pragma unroll
-            for (int bi = 0; bi < NB; ++bi)
+                for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
-                for (int bj = 0; bj < NB; ++bj)
+                    for (int bj = 0; bj < NB; ++bj)
 #pragma unroll
-                    for (int r = 0; r < P::REGS; ++r, ++e) {
-                        const Acc d = scale * acc[bi][bj][r];
-                        const Acc delta = d - mean[e];
-                        mean[e] += delta * inv;
-                        m2[e] += delta * (d - mean[e]);
-                    }
+                        for (int r = 0; r < P::REGS; ++r, ++e) {
+                            const Acc d = scale * acc[bi][bj][r];
+                            const Acc delta = d - mean[e];
+                            mean[e] += delta * inv;
+                            m2[e] += delta * (d - mean[e]);
+                            acc[bi][bj][r] = (Acc)0;
+                        }
+            }
+            if (c + 1 < total) stash(buf ^ 1);
+            __syncthreads();
         }
 
         // group mean of every in-range entry, and the group's within sum of squares
@@ -369,8 +477,8 @@ __global__ __launch_bounds__(kSketchThreads) void sketch_kernel(SketchParams prm
             for (int bj = 0; bj < NB; ++bj)
 #pragma unroll
                 for (int r = 0; r < P::REGS; ++r, ++e) {
-                    const int64_t i = row0 + bi * P::BLK + P::row_of(lane, r);
-                    const int64_t j = col0 + bj * P::BLK + P::col_of(lane);
+                    const int64_t i = trow + wrow + bi * P::BLK + P::row_of(lane, r);
+                    const int64_t j = tcol + wcol + bj * P::BLK + P::col_of(lane);
                     if (i < m && j < p) {
                         pm[i * p + j] = (double)mean[e];
                         m2_sum += (double)m2[e];
@@ -432,14 +540,21 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(MergeParams prm)
         if ((int)threadIdx.x < half) red[threadIdx.x] += red[threadIdx.x + half];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        prm.between[prm.level * prm.sum_merge_blocks + Pd.between_prefix + blockIdx.x] += red[0];
-        if (blockIdx.x == 0) {
-            double w = 0.0;
-            for (int64_t g = 0; g < prm.groups; ++g)
-                for (int64_t t = 0; t < Pd.tiles; ++t) w += prm.part_m2[g * prm.total_tiles + Pd.tile_first + t];
-            prm.within[prm.level * prm.nprob + pi] += w;
+    if (threadIdx.x == 0) prm.between[prm.level * prm.sum_merge_blocks + Pd.between_prefix + blockIdx.x] += red[0];
+    if (blockIdx.x == 0) {
+        // within-group sums of this product: strided over the block, then a tree
+        __syncthreads();
+        double w = 0.0;
+        const int64_t count = prm.groups * Pd.tiles;
+        for (int64_t i = threadIdx.x; i < count; i += kMergeThreads)
+            w += prm.part_m2[(i / Pd.tiles) * prm.total_tiles + Pd.tile_first + (i % Pd.tiles)];
+        red[threadIdx.x] = w;
+        __syncthreads();
+        for (int half = kMergeThreads / 2; half > 0; half >>= 1) {
+            if ((int)threadIdx.x < half) red[threadIdx.x] += red[threadIdx.x + half];
+            __syncthreads();
         }
+        if (threadIdx.x == 0) prm.within[prm.level * prm.nprob + pi] += red[0];
     }
 }
 
@@ -551,9 +666,10 @@ bool matmul_plan(const MatmulProblem* probs, int nprob, int prec, int num_levels
     plan.kstep = ps.kstep;
     plan.kpack = ps.kpack;
     plan.elem = ps.elem;
-    // wave blocks per dimension: 2 (workgroup tile 4 x BLK) unless tuned to 1
-    // (tile 2 x BLK); f64 blocks are 16 wide and always use 2
-    plan.nb = 2;
+    // wave blocks per dimension: 1 (workgroup tile 2 x BLK = 64: four waves per
+    // SIMD fit, the measured best on every workload) unless tuned to 2
+    // (tile 128); f64 blocks are 16 wide and always use 2 (tile 64)
+    plan.nb = prec == 0 ? 2 : 1;
     if (tune && tune->tile > 0 && prec != 0) plan.nb = tune->tile <= 2 * ps.blk ? 1 : 2;
     plan.tile = 2 * plan.nb * ps.blk;
     plan.kpad_max = 0;
@@ -573,6 +689,8 @@ bool matmul_plan(const MatmulProblem* probs, int nprob, int prec, int num_levels
         d.m = pr.m;
         d.n = pr.n;
         d.p = pr.p;
+        d.m_pad = round_up(pr.m, plan.tile);
+        d.p_pad = round_up(pr.p, plan.tile);
         d.A = pr.A;
         d.B = pr.B;
         d.sid_problem = pr.problem;
@@ -590,12 +708,15 @@ bool matmul_plan(const MatmulProblem* probs, int nprob, int prec, int num_levels
         d.level_means = pr.level_means;
         for (int64_t t = 0; t < d.tiles; ++t) plan.tile_owner.push_back(i);
         tiles += d.tiles;
-        rows += pr.m + pr.p;
+        rows += d.m_pad + d.p_pad;
         mp += pr.m * pr.p;
         mb += d.merge_blocks;
         if (pr.m * pr.p > plan.max_mp) plan.max_mp = pr.m * pr.p;
         if (d.merge_blocks > plan.max_merge_blocks) plan.max_merge_blocks = d.merge_blocks;
     }
+    plan.laws = law_pair_kind(probs[0].A.kind, probs[0].B.kind);
+    for (int i = 1; i < nprob; ++i)
+        if (law_pair_kind(probs[i].A.kind, probs[i].B.kind) != plan.laws) plan.laws = kLawsAny;
     plan.sum_rows = rows;
     plan.sum_mp = mp;
     plan.sum_merge_blocks = mb;
@@ -686,8 +807,15 @@ static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t
     {
         ScopedTiming t(timer, 1);
         const dim3 grid((unsigned)ceil_div(kpad, kGatherPositions), (unsigned)batch, (unsigned)plan.nprob);
-        hipLaunchKernelGGL((gather_kernel<Compute, typename P::In, P::KPACK>), grid, dim3(kGatherThreads), 0,
-                           stream, g);
+        if (plan.laws == kLawsNormal)
+            hipLaunchKernelGGL((gather_kernel<Compute, typename P::In, P::KPACK, kLawsNormal>), grid,
+                               dim3(kGatherThreads), 0, stream, g);
+        else if (plan.laws == kLawsUniform)
+            hipLaunchKernelGGL((gather_kernel<Compute, typename P::In, P::KPACK, kLawsUniform>), grid,
+                               dim3(kGatherThreads), 0, stream, g);
+        else
+            hipLaunchKernelGGL((gather_kernel<Compute, typename P::In, P::KPACK, kLawsAny>), grid,
+                               dim3(kGatherThreads), 0, stream, g);
     }
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;

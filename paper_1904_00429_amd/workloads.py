@@ -70,3 +70,17 @@ def reparam_inputs(m: int, n: int, p: int, seed: int = 0):
     SB = rng.uniform(0.1, 1.0, size=(n, p)).astype(np.float32)
     T = rng.standard_normal((m, p), dtype=np.float32)
     return MA, SA, MB, SB, T
+
+
+def batched_products(count: int = 256, seed: int = 0):
+    """The batching workload: `count` independent products, m and p uniform on
+    {64, 128, ..., 512}, n log-uniform on [4096, 131072] (rounded), entries
+    i.i.d. N(mu, 1) with mu uniform on (0, 2) per product; c_l = 16 * 2^l,
+    l = 0..6; N_l = 2048 * 2^-l.  Returns (shapes, mus, c, N)."""
+    rng = np.random.default_rng(seed)
+    m = rng.integers(1, 9, size=count) * 64
+    p = rng.integers(1, 9, size=count) * 64
+    n = np.rint(np.exp(rng.uniform(np.log(4096), np.log(131072), size=count))).astype(np.int64)
+    mu = rng.uniform(0.0, 2.0, size=count)
+    shapes = [(int(a), int(b), int(c)) for a, b, c in zip(m, n, p)]
+    return shapes, [float(x) for x in mu], ladder(16, 7), [2048 >> l for l in range(7)]
