@@ -89,6 +89,11 @@ def lib():
             + [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64,
                ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                ctypes.c_void_p])
+        L.orc_level_entries.argtypes = (
+            [ctypes.c_int64] * 3 + [ctypes.POINTER(_Law)] * 2 + [ctypes.c_int64] * 2
+            + [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64,
+               ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p])
         _lib = L
     return _lib
 
@@ -310,6 +315,56 @@ def estimate(m: int, n: int, p: int, A: Law, B: Law, c: Sequence[int],
     N = np.array([s.count for s in states], dtype=np.int64)
     rmse = math.sqrt(float(np.sum(V / N)))
     return Estimate(means.sum(axis=0), means, V, N, rmse)
+
+
+@dataclass
+class EntriesEstimate:
+    Y: np.ndarray                 # sum_l Ybar_l at the chosen entries (nr x nc)
+    level_means: np.ndarray       # (L+1) x nr x nc
+    entry_var: np.ndarray         # (L+1) x nr x nc: unbiased variance of one level sample
+    n_used: np.ndarray            # N_l
+
+
+def estimate_entries(m: int, n: int, p: int, A: Law, B: Law, c: Sequence[int],
+                     n_samples: Sequence[int], rows: Sequence[int], cols: Sequence[int],
+                     seed: int = 0, problem: int = 0, shared: bool = False,
+                     pool=None) -> EntriesEstimate:
+    """The fixed-N estimate of eq. (10) at the entries rows x cols only.
+
+    Level l runs realisations 0 .. N_l - 1 exactly as `estimate` does, so its
+    values at these entries equal the full estimate's (same arithmetic and
+    order); products whose full sketch the CPU cannot afford are checked this
+    way.  A target-mode run is reproduced by passing the N_l it used."""
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    cols = np.ascontiguousarray(cols, dtype=np.int64)
+    nr, nc = len(rows), len(cols)
+    L1 = len(c)
+    if len(n_samples) != L1:
+        raise ValueError("one N_l per level expected")
+    means = np.zeros((L1, nr * nc))
+    m2s = np.zeros((L1, nr * nc))
+    la, lb = A.c(), B.c()
+
+    def run(l):
+        cnt = ctypes.c_int64(0)
+        rc = lib().orc_level_entries(
+            int(m), int(n), int(p), ctypes.byref(la), ctypes.byref(lb), int(c[l]),
+            int(c[l - 1]) if l > 0 else 0, int(seed), int(problem), level_field(l, shared), 0,
+            int(n_samples[l]), nr, _ptr(rows), nc, _ptr(cols), ctypes.byref(cnt),
+            _ptr(means[l]), _ptr(m2s[l]))
+        if rc != 0:
+            raise ValueError("orc_level_entries rejected its arguments")
+
+    if pool is None:
+        for l in range(L1):
+            run(l)
+    else:
+        list(pool.map(run, range(L1)))
+    N = np.asarray(n_samples, dtype=np.int64)
+    var = m2s / np.maximum(N - 1, 1)[:, None]
+    shape = (L1, nr, nc)
+    return EntriesEstimate(means.sum(axis=0).reshape(nr, nc), means.reshape(shape),
+                           var.reshape(shape), N)
 
 
 # --------------------------------------------------------------------------

@@ -244,3 +244,65 @@ int orc_level_estimation(int64_t m, int64_t n, int64_t p, const orc_law* A, cons
     free(r); free(AS); free(BS); free(Zf); free(Zc);
     return 0;
 }
+
+/* Alg. 1 restricted to the entries (rows[a], cols[b]), 0 <= a < nr,
+ * 0 <= b < nc, of the level sample: the same definition as
+ * orc_level_estimation (eq. (18) per entry, the same realisations, index
+ * draws and values, the same summation order), evaluated only where it is
+ * asked for, so that products far too large for the whole sketch can be
+ * checked entry by entry.  mean and m2 are nr x nc, row-major. */
+int orc_level_entries(int64_t m, int64_t n, int64_t p, const orc_law* A, const orc_law* B,
+                      int64_t c_l, int64_t c_prev, uint64_t seed, uint32_t problem,
+                      uint32_t level_field, int64_t k_begin, int64_t k_end,
+                      int64_t nr, const int64_t* rows, int64_t nc, const int64_t* cols,
+                      int64_t* count, double* mean, double* m2)
+{
+    if (m < 1 || p < 1 || n < 1 || c_l < 1 || c_prev < 0 || c_prev > c_l || k_end < k_begin ||
+        nr < 1 || nc < 1)
+        return -1;
+    for (int64_t a = 0; a < nr; ++a)
+        if (rows[a] < 0 || rows[a] >= m) return -1;
+    for (int64_t b = 0; b < nc; ++b)
+        if (cols[b] < 0 || cols[b] >= p) return -1;
+    int64_t* r = (int64_t*)malloc(sizeof(int64_t) * (size_t)c_l);
+    double* AS = (double*)malloc(sizeof(double) * (size_t)(c_l * nr));
+    double* BS = (double*)malloc(sizeof(double) * (size_t)(c_l * nc));
+    if (!r || !AS || !BS) {
+        free(r); free(AS); free(BS);
+        return -1;
+    }
+    for (int64_t k = k_begin; k < k_end; ++k) {
+        orc_draw_indices(seed, problem, level_field, (uint32_t)k, c_l, n, r);
+        for (int64_t t = 0; t < c_l; ++t) {
+            int64_t j = r[t];
+            for (int64_t a = 0; a < nr; ++a)
+                AS[t * nr + a] = law_value(A, seed, problem, level_field, (uint32_t)k, j, rows[a],
+                                           j * A->ld + rows[a]);
+            for (int64_t b = 0; b < nc; ++b)
+                BS[t * nc + b] = law_value(B, seed, problem, level_field, (uint32_t)k, j, m + cols[b],
+                                           j * B->ld + cols[b]);
+        }
+        *count += 1;
+        double cnt = (double)(*count);
+        for (int64_t a = 0; a < nr; ++a) {
+            for (int64_t b = 0; b < nc; ++b) {
+                double sf = 0.0;
+                for (int64_t t = 0; t < c_l; ++t)
+                    sf += AS[t * nr + a] * BS[t * nc + b];
+                double d = ((double)n / (double)c_l) * sf;
+                if (c_prev > 0) {
+                    double sc = 0.0;
+                    for (int64_t t = 0; t < c_prev; ++t)
+                        sc += AS[t * nr + a] * BS[t * nc + b];
+                    d = d - ((double)n / (double)c_prev) * sc;
+                }
+                int64_t e = a * nc + b;
+                double delta = d - mean[e];
+                mean[e] += delta / cnt;
+                m2[e] += delta * (d - mean[e]);
+            }
+        }
+    }
+    free(r); free(AS); free(BS);
+    return 0;
+}

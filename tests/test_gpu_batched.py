@@ -124,3 +124,52 @@ def test_autotuner_picks_and_caches(dev, tmp_path, monkeypatch):
     cached = json.load(open(tmp_path / "cache.json"))
     assert len(cached) == 1 and list(cached.values())[0]["best"] == best
     assert autotune.tune(probs, C, N, prec="fp8", device=dev) == best
+
+
+@pytest.fixture(scope="module")
+def full_batch(orc):
+    """The benchmarked batch (256 uneven products, c_l = 16 * 2^l, l = 0..6,
+    N_l = 2048 * 2^-l); the oracle evaluates every 4th product at a 4 x 4 grid
+    of entries."""
+    from paper_1904_00429_amd import workloads
+    shapes, mus, c, N = workloads.batched_products()
+    picked = list(range(0, len(shapes), 4))
+
+    def one(i):
+        m, n, p = shapes[i]
+        law = orc.Law.normal(mus[i], 1.0)
+        rows = [0, m // 3, (2 * m) // 3, m - 1]
+        cols = [p - 1, p // 2, 1, p // 4]
+        return rows, cols, orc.estimate_entries(m, n, p, law, law, c, N, rows, cols, seed=0, problem=i)
+    with ThreadPoolExecutor(max_workers=os.cpu_count() or 4) as ex:
+        refs = list(ex.map(one, picked))
+    return shapes, mus, c, N, picked, refs
+
+
+@pytest.mark.parametrize("prec", ["fp8", "fp32"])
+@pytest.mark.parametrize("tile", [64, 128])
+def test_full_batch_sampled_entries(dev, full_batch, prec, tile):
+    """The benchmarked batch in its launch configuration (one captured graph
+    per estimate, both tile shapes the autotuner chooses between), checked at
+    sampled entries of sampled products."""
+    from paper_1904_00429_amd import BatchedEstimate, BatchProblem, Law
+    shapes, mus, c, N, picked, refs = full_batch
+    flush(f"full batch prec={prec} tile={tile} products={len(shapes)}")
+    probs = [BatchProblem(m, n, p, Law.normal(mu, 1.0), Law.normal(mu, 1.0), i)
+             for i, ((m, n, p), mu) in enumerate(zip(shapes, mus))]
+    est = BatchedEstimate(probs, c, N, seed=0, prec=prec, tuning={"tile": tile}, device=dev)
+    est.capture()
+    est.replay()
+    torch.cuda.synchronize()
+    err2 = var2 = ref2 = 0.0
+    for i, (rows, cols, ref) in zip(picked, refs):
+        Y = est.Y[i].cpu().numpy()[np.ix_(rows, cols)]
+        err2 += float(np.sum((Y - ref.Y) ** 2))
+        ref2 += float(np.sum(ref.Y ** 2))
+        var2 += float(np.sum((ref.entry_var / ref.n_used[:, None, None]).sum(axis=0)))
+        if prec == "fp32":
+            assert rel_frob(Y, ref.Y) <= 1e-5, (i, rel_frob(Y, ref.Y))
+    est.release()
+    flush(f"  RMS error / estimator sd = {np.sqrt(err2 / var2):.4g}, rel = {np.sqrt(err2 / ref2):.3g}")
+    if prec == "fp8":
+        assert np.sqrt(err2 / var2) <= 0.25

@@ -1,6 +1,8 @@
-"""Parity at the full size of the benchmarked workload, in the launch
-configuration bench.py times: x, y in R^(2^20), i.i.d. 0.5 + U(-1, 1),
-c_l = 64 * 2^l (l = 0..8), target RMSE 1e-3 |E[x^T y]|, pilot 1024.
+"""Parity at the full sizes of the benchmarked workloads, in the launch
+configurations bench.py times.
+
+Inner product: x, y in R^(2^20), i.i.d. 0.5 + U(-1, 1), c_l = 64 * 2^l
+(l = 0..8), target RMSE 1e-3 |E[x^T y]|, pilot 1024.
 
 The oracle runs the same target-mode estimate (pilot, eq. (28), extension)
 on the host, one thread per level (about 7e8 index draws).  FP64: the
@@ -15,7 +17,7 @@ from concurrent.futures import ThreadPoolExecutor
 import numpy as np
 import pytest
 
-from gpu_helpers import flush
+from gpu_helpers import flush, rel_frob
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -53,3 +55,41 @@ def test_inner_2pow20_target_mode_full(orc, dev, prec):
         np.testing.assert_allclose(V, ref.level_var, rtol=1e-5)
     # the target is met: predicted RMSE within the eps^2 / 2 variance budget
     assert est.rmse_est <= wl.rmse_target / math.sqrt(2) * 1.05
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_matmul_1024x65536x1024_target_mode_sampled_entries(orc, dev, prec):
+    """The precision-form workload at its full size and in the benchmark's
+    launch configuration (target mode: 64-realisation pilot, eq. (28), then
+    extension), checked at an 8 x 8 grid of output entries that the oracle
+    computes one by one with the N_l the GPU used.
+
+    FP32: relative error 1e-5 over the sampled entries, level by level.
+    BF16: RMS error over the sampled entries <= 5% of the estimator's own
+    standard deviation there (sum_l var_l / N_l from the oracle's samples)."""
+    from paper_1904_00429_amd import Law, matmul_estimate, workloads
+    wl = workloads.MATMUL_LARGE
+    flush(f"full-size target-mode matmul prec={prec} m={wl.m} n={wl.n} p={wl.p}")
+    g = Law.normal(wl.law_a[1], wl.law_a[2])
+    est = matmul_estimate(wl.m, wl.n, wl.p, g, g, wl.c, rmse_target=wl.rmse_target, pilot=wl.pilot,
+                          seed=3, prec=prec, level_means=True, device=dev)
+    N = [int(x) for x in est.n_used]
+    flush(f"  N_l = {N}")
+    rows = list(range(3, wl.m, wl.m // 8))
+    cols = list(range(wl.p - 1, 0, -(wl.p // 8)))
+    o = orc.Law.normal(wl.law_a[1], wl.law_a[2])
+    with ThreadPoolExecutor(max_workers=min(len(wl.c), os.cpu_count() or 4)) as pool:
+        ref = orc.estimate_entries(wl.m, wl.n, wl.p, o, o, wl.c, N, rows, cols, seed=3, pool=pool)
+    ix = np.ix_(rows, cols)
+    Y = est.Y.cpu().numpy()[ix]
+    means = est.level_means.cpu().numpy()[(slice(None),) + ix]
+    if prec == "fp32":
+        assert rel_frob(Y, ref.Y) <= 1e-5, rel_frob(Y, ref.Y)
+        for l in range(len(wl.c)):
+            scale = max(np.linalg.norm(ref.level_means[l]), 1e-3 * np.linalg.norm(ref.Y))
+            assert np.linalg.norm(means[l] - ref.level_means[l]) <= 1e-5 * scale, l
+    else:
+        sd = math.sqrt(float(np.mean((ref.entry_var / ref.n_used[:, None, None]).sum(axis=0))))
+        rms = math.sqrt(float(np.mean((Y - ref.Y) ** 2)))
+        flush(f"  bf16 RMS error {rms:.4g}, estimator sd {sd:.4g}")
+        assert rms <= 0.05 * sd

@@ -136,3 +136,33 @@ def test_target_mode_meets_rmse(orc):
     assert est.rmse_est <= eps / math.sqrt(2) * 1.2
     assert np.all(est.n_used >= 200)
     assert abs(est.Y[0, 0] - E) < 5 * est.rmse_est
+
+
+@pytest.mark.parametrize("law", ["normal", "uniform", "reparam"])
+def test_entries_restriction_equals_full_estimate(orc, law):
+    """The entry-restricted evaluation reproduces the full estimate at the
+    chosen entries bit for bit (same realisations, same arithmetic order),
+    including repeated and unsorted rows/columns."""
+    m, n, p, c, N = 7, 90, 6, [3, 6, 12], [25, 12, 6]
+    rng = np.random.default_rng(5)
+    if law == "reparam":
+        # A column-major: row j of the (n, m) arrays is column j of A
+        MA, SA = rng.standard_normal((n, m)), rng.uniform(0.1, 1, (n, m))
+        MB, SB = rng.standard_normal((n, p)), rng.uniform(0.1, 1, (n, p))
+        A, B = orc.Law.reparam(MA.ravel(), SA.ravel(), m), orc.Law.reparam(MB.ravel(), SB.ravel(), p)
+    elif law == "uniform":
+        A, B = orc.Law.uniform(0.3, 1.2), orc.Law.uniform(-0.4, 2.0)
+    else:
+        A, B = orc.Law.normal(1.0, 0.5), orc.Law.normal(-0.2, 1.5)
+    rows, cols = [6, 0, 3, 3], [5, 1]
+    for shared in (False, True):
+        full = orc.estimate(m, n, p, A, B, c, n_samples=N, seed=8, problem=4, shared=shared)
+        sub = orc.estimate_entries(m, n, p, A, B, c, N, rows, cols, seed=8, problem=4, shared=shared)
+        ix = np.ix_(rows, cols)
+        assert np.array_equal(sub.Y, full.Y[ix])
+        for l in range(len(c)):
+            assert np.array_equal(sub.level_means[l], full.level_means[l][ix])
+        # the entry variances sum (over all entries) to V_l
+        every = orc.estimate_entries(m, n, p, A, B, c, N, range(m), range(p), seed=8, problem=4,
+                                     shared=shared)
+        np.testing.assert_allclose(every.entry_var.sum(axis=(1, 2)), full.level_var, rtol=1e-12)
