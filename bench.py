@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--workload", default="inner", choices=["inner", "matmul-large", "matmul-small", "diff", "batched", "matmul-large-fixed"])
     ap.add_argument("--prec", default=None, help="fp32 (default) or fp64; bf16 for matmul")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision-check", action="store_true",
+                    help="skip the low-precision vs FP64 comparison of the matrix workloads")
     ap.add_argument("--cpu-fraction", type=float, default=0.15,
                     help="share of every level's realisations the CPU oracle runs")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -100,32 +102,42 @@ def cpu_baseline_inner(wl, n_used, fraction):
                       f"realisations), {dt:.1f} s, scaled by draws"}
 
 
-def cpu_baseline_matmul(wl, n_used, fraction):
+def cpu_baseline_matmul(wl, n_used, fraction, edge=256):
+    """The oracle (one core) on the same ladder, laws and N_l with m = p = edge.
+
+    A full-shape realisation of the finest level costs the oracle minutes, so
+    each level runs max(1, fraction N_l) realisations at the reduced shape; the
+    time per realisation t_l gives sum_l N_l t_l, scaled by m p / edge^2 (the
+    oracle's sketch loop, m p (c_l + c_{l-1}) multiply-adds per realisation,
+    dominates its per-realisation cost)."""
     import oracle
     oracle.build(force=False)
     law = oracle.Law.normal(wl.law_a[1], wl.law_a[2])
-    t0 = time.perf_counter()
-    work = 0.0
-    total = sum(N * wl.c[l] for l, N in enumerate(n_used))
+    m, p = min(edge, wl.m), min(edge, wl.p)
+    total = 0.0
+    run = 0
+    t_all = time.perf_counter()
     for l, N in enumerate(n_used):
         k = max(1, int(round(N * fraction)))
-        st = oracle.LevelState.empty(wl.m, wl.p)
-        oracle.level_estimation(st, wl.m, wl.n, wl.p, law, law, wl.c[l], wl.c[l - 1] if l else 0,
+        st = oracle.LevelState.empty(m, p)
+        t0 = time.perf_counter()
+        oracle.level_estimation(st, m, wl.n, p, law, law, wl.c[l], wl.c[l - 1] if l else 0,
                                 wl.seed, 0, l, 0, k)
-        work += k * wl.c[l]
-        if time.perf_counter() - t0 > 30:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": work / total / dt, "unit": "estimates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{int(work)} of {total} index draws, {dt:.1f} s, scaled by draws"}
+        total += N * (time.perf_counter() - t0) / k
+        run += k
+    total *= (wl.m * wl.p) / float(m * p)
+    dt = time.perf_counter() - t_all
+    return {"value": 1.0 / total, "unit": "estimates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{run} realisations (max(1, {fraction} N_l) per level) at m = p = {m}, {dt:.1f} s; "
+                      f"sum_l N_l t_l scaled by m p / {m * p}"}
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported by this build "
-              f"(the per-level work would shard over GPUs with one merge of the level "
-              f"statistics; see the design notes)", file=sys.stderr)
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported (the library "
+              f"drives one GPU; the per-level work would shard over GPUs with one merge of the "
+              f"level statistics per phase)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1904_00429_amd import Law, inner_product_estimate, matmul_estimate, workloads
@@ -213,6 +225,20 @@ def main():
                "sample": k_ms[0] / args.steps, "gather": k_ms[1] / args.steps, "merge": k_ms[2] / args.steps,
                "final": k_ms[3] / args.steps}}
 
+    if args.workload != "inner" and prec != "fp64" and not args.no_precision_check:
+        # precision form: the same estimate (seed 0, the N_l of the last step,
+        # fixed mode) in the low precision and in FP64, outside the timed region
+        from paper_1904_00429_amd import matmul_estimate
+        ys = {}
+        for pr in (prec, "fp64"):
+            ys[pr] = matmul_estimate(wl.m, wl.n, wl.p, a, a, wl.c, n_samples=rep.n_used, seed=0, prec=pr,
+                                     device=dev, report=True)
+        out["precision_check"] = {
+            "lp_minus_fp64_frob": float(torch.linalg.norm(ys[prec].Y - ys["fp64"].Y)),
+            "rmse_est_fp64": ys["fp64"].rmse_est, "seed": 0, "n_samples": rep.n_used}
+        del ys
+        torch.cuda.empty_cache()
+
     if args.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -224,7 +250,7 @@ def main():
         if args.workload == "inner":
             out["cpu_baseline"] = cpu_baseline_inner(wl, rep.n_used, args.cpu_fraction)
         else:
-            out["cpu_baseline"] = cpu_baseline_matmul(wl, rep.n_used, min(args.cpu_fraction, 0.002))
+            out["cpu_baseline"] = cpu_baseline_matmul(wl, rep.n_used, 0.001)
     print(json.dumps(out), flush=True)
 
 
