@@ -17,7 +17,7 @@ import torch
 
 from .mlmc import BatchedEstimate, BatchProblem
 
-CANDIDATES = [{"tile": t, "target_blocks": b} for t in (64, 128) for b in (1024, 2048, 4096)]
+CANDIDATES = [{"tile": t, "target_blocks": b} for t in (64, 128) for b in (512, 1024, 2048, 4096)]
 
 
 def cache_path() -> str:

@@ -35,13 +35,12 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kSketchThreads = 256;
 constexpr int kMergeThreads = 256;
 constexpr int kGatherThreads = 64;
 constexpr int kGatherPositions = 8;
 constexpr int64_t kGatherBudgetBytes = 192ll << 20;
-constexpr int64_t kTargetSketchBlocks = 2048;
 constexpr int64_t kSketchMaxBlocks = 8192;
+constexpr int kXcds = 8;                     // accelerator complex dies of an MI355X
 
 // ---------------------------------------------------------------------------
 // Contraction policies: operand type, MFMA shape, fragment layout.  A
@@ -278,6 +277,24 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
             }
         }
     }
+    // rows m .. m_pad - 1 of A's block and p .. p_pad - 1 of B's block are
+    // zero, so the sketch's entries outside the product see D = 0
+    const int64_t pad_a = m_pad - m, pad_b = p_pad - p;
+    for (int64_t q = threadIdx.x; q < pad_a + pad_b; q += kGatherThreads) {
+        Store* G = q < pad_a ? GA : GB;
+        const int64_t R = q < pad_a ? m_pad : p_pad;
+        const int64_t row = q < pad_a ? m + q : p + (q - pad_a);
+        const Store zero = StoreOf<Store>::from((Compute)0, 1.0f);
+        if constexpr (KPACK == 1) {
+            for (int ip = 0; ip < npos; ++ip) G[(pos0 + ip) * R + row] = zero;
+        } else {
+            typedef Store vec_t __attribute__((ext_vector_type(KPACK)));
+            vec_t vv;
+#pragma unroll
+            for (int ip = 0; ip < KPACK; ++ip) vv[ip] = zero;
+            *reinterpret_cast<vec_t*>(G + ((pos0 / KPACK) * R + row) * KPACK) = vv;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -331,35 +348,53 @@ template <typename P> struct ChunkOf { static constexpr int KC = 64; };
 template <> struct ChunkOf<PolicyF64> { static constexpr int KC = 16; };
 template <> struct ChunkOf<PolicyF32> { static constexpr int KC = 32; };
 
-template <typename P, int NB>
-__global__ __launch_bounds__(kSketchThreads) void sketch_kernel(SketchParams prm)
+// Workgroup = WR x WC waves; a wave computes NBR x NBC MFMA blocks of
+// BLK x BLK; the workgroup tile is square (rows = columns = tile).
+template <typename P, int WR, int WC, int NBR, int NBC>
+struct SketchShape {
+    static constexpr int THREADS = kWave * WR * WC;
+    static constexpr int WTR = NBR * P::BLK, WTC = NBC * P::BLK;  // wave tile
+    static constexpr int BM = WR * WTR;
+    static_assert(BM == WC * WTC, "square workgroup tile");
+};
+
+// PF register sets (1 or 2) hold the global loads of the next PF chunks.
+// WPE: waves per SIMD the register allocation must leave room for.
+template <typename P, int WR, int WC, int NBR, int NBC, int PF, int WPE>
+__global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchParams prm)
 {
     using In = typename P::In;
     using Acc = typename P::Acc;
     using FragT = typename P::FragT;
-    constexpr int NE = NB * NB * P::REGS;            // entries per lane
-    constexpr int WT = NB * P::BLK;                  // wave tile edge
-    constexpr int BM = 2 * WT;                       // workgroup tile edge (rows = columns)
+    using S = SketchShape<P, WR, WC, NBR, NBC>;
+    constexpr int THREADS = S::THREADS;
+    constexpr int NE = NBR * NBC * P::REGS;          // entries per lane
+    constexpr int BM = S::BM;                        // workgroup tile edge
     constexpr int KC = ChunkOf<P>::KC;               // draws per staged chunk
     constexpr int SLABS = KC / P::KPACK;
     constexpr int VEC = 16 / (int)sizeof(In);        // elements per 16-byte vector
     constexpr int V_SLAB = BM * P::KPACK / VEC;      // vectors per slab of one operand
-    constexpr int VPT = SLABS * V_SLAB / kSketchThreads;  // vectors per thread per operand
-    static_assert(SLABS * V_SLAB % kSketchThreads == 0, "chunk must split evenly over the workgroup");
+    constexpr int VPT = SLABS * V_SLAB / THREADS;    // vectors per thread per operand
+    static_assert(SLABS * V_SLAB % THREADS == 0, "chunk must split evenly over the workgroup");
     __shared__ __align__(16) In lds[2][2][KC * BM];  // [buffer][A, B][chunk]
-    __shared__ double red[kSketchThreads / kWave];
+    __shared__ double red[THREADS / kWave];
 
     const int lane = threadIdx.x % kWave;
     const int wave = threadIdx.x / kWave;
-    const int wrow = (wave / 2) * WT, wcol = (wave % 2) * WT;  // wave tile inside the workgroup tile
+    const int wrow = (wave / WC) * S::WTR, wcol = (wave % WC) * S::WTC;  // wave tile inside the workgroup tile
     const int64_t items = prm.total_tiles * prm.groups;
-    for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
+    // Workgroups are dealt to the 8 XCDs round-robin by id; renumber them so
+    // that each XCD walks a contiguous run of items (one group's consecutive
+    // tiles), whose workgroups then share operand rows through that XCD's L2.
+    // The grid is a multiple of kXcds.
+    const int64_t first = (int64_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) + blockIdx.x / kXcds;
+    for (int64_t item = first; item < items; item += gridDim.x) {
         const int64_t group = item / prm.total_tiles;
         const int64_t tt = item % prm.total_tiles;
         const ProblemDesc& Pd = prm.descs[prm.tile_owner[tt]];
-        const int64_t tile = tt - Pd.tile_first;
-        const int64_t m = Pd.m, p = Pd.p, m_pad = Pd.m_pad, p_pad = Pd.p_pad;
-        const int64_t trow = (tile / Pd.tiles_n) * BM, tcol = (tile % Pd.tiles_n) * BM;
+        const int tile = (int)(tt - Pd.tile_first);
+        const int m = (int)Pd.m, p = (int)Pd.p, m_pad = (int)Pd.m_pad, p_pad = (int)Pd.p_pad;
+        const int trow = (tile / (int)Pd.tiles_n) * BM, tcol = (tile % (int)Pd.tiles_n) * BM;
         const int64_t s_begin = group * prm.batch / prm.groups;
         const int64_t s_end = (group + 1) * prm.batch / prm.groups;
         const int64_t pass_rows = prm.batch * prm.kpad * (int64_t)prm.elem;
@@ -367,129 +402,176 @@ __global__ __launch_bounds__(kSketchThreads) void sketch_kernel(SketchParams prm
         const In* GB0 = reinterpret_cast<const In*>(prm.gbuf + pass_rows * (Pd.rows_prefix + m_pad));
         const Acc scale = (Acc)((double)Pd.n / (double)prm.c * Pd.post);
         const Acc omega = (Acc)prm.omega;
-        const int64_t nch = (prm.kpad + KC - 1) / KC;
-        const int64_t total = (s_end - s_begin) * nch;
+        // chunks per realisation; the coarse length is a multiple of the MFMA step
+        const int nch = (int)((prm.kpad + KC - 1) / KC);
+        const int kc = (int)prm.kc;
+        const int kpad = (int)prm.kpad;
+        const int total = (int)(s_end - s_begin) * nch;
 
-        // chunk c: realisation s_begin + c / nch, draws [(c % nch) KC, +KC)
-        uint4 ra[VPT], rb[VPT];
-        auto fetch = [&](int64_t c) {
-            const int64_t s = s_begin + c / nch;
-            const int64_t k0 = (c % nch) * KC;
-            const In* ga = GA0 + s * prm.kpad * m_pad;
-            const In* gb = GB0 + s * prm.kpad * p_pad;
+        // Chunk (s, q) = realisation s_begin + s, draws [q KC, q KC + KC): the
+        // slabs k0 / KPACK .. of the realisation's [kpad / KPACK][rows][KPACK]
+        // block.  The chunk's base is uniform (scalar); a thread's vectors sit
+        // at fixed element offsets from it.  The register sets keep the global
+        // loads of the next PF chunks in flight while the MFMAs run on the
+        // chunk staged in LDS.
+        uint4 ra[PF][VPT], rb[PF][VPT];
+        auto fetch = [&](int set, int s, int q) {
+            const int k0 = q * KC;
+            const int64_t real = (s_begin + s) * prm.kpad;
+            const In* ga = GA0 + (real + k0) * m_pad;
+            const In* gb = GB0 + (real + k0) * p_pad;
 #pragma unroll
             for (int v = 0; v < VPT; ++v) {
-                const int vid = threadIdx.x + v * kSketchThreads;
+                const int vid = threadIdx.x + v * THREADS;
                 const int slab = vid / V_SLAB, iv = vid % V_SLAB;
-                const int64_t kb = k0 / P::KPACK + slab;
-                if (k0 + slab * P::KPACK < prm.kpad) {
-                    ra[v] = *reinterpret_cast<const uint4*>(ga + (kb * m_pad + trow) * P::KPACK + iv * VEC);
-                    rb[v] = *reinterpret_cast<const uint4*>(gb + (kb * p_pad + tcol) * P::KPACK + iv * VEC);
+                if (k0 + slab * P::KPACK < kpad) {
+                    ra[set][v] = *reinterpret_cast<const uint4*>(ga + (slab * m_pad + trow) * P::KPACK + iv * VEC);
+                    rb[set][v] = *reinterpret_cast<const uint4*>(gb + (slab * p_pad + tcol) * P::KPACK + iv * VEC);
                 } else {
-                    ra[v] = make_uint4(0, 0, 0, 0);
-                    rb[v] = make_uint4(0, 0, 0, 0);
+                    ra[set][v] = make_uint4(0, 0, 0, 0);
+                    rb[set][v] = make_uint4(0, 0, 0, 0);
                 }
             }
         };
-        auto stash = [&](int buf) {
+        auto stash = [&](int set, int buf) {
 #pragma unroll
             for (int v = 0; v < VPT; ++v) {
-                const int vid = threadIdx.x + v * kSketchThreads;
-                *reinterpret_cast<uint4*>(&lds[buf][0][vid * VEC]) = ra[v];
-                *reinterpret_cast<uint4*>(&lds[buf][1][vid * VEC]) = rb[v];
+                const int vid = threadIdx.x + v * THREADS;
+                *reinterpret_cast<uint4*>(&lds[buf][0][vid * VEC]) = ra[set][v];
+                *reinterpret_cast<uint4*>(&lds[buf][1][vid * VEC]) = rb[set][v];
             }
         };
 
-        Acc mean[NE], m2[NE];
+        // Welford: a running mean per entry; the squared-deviation updates of
+        // a realisation are summed over the lane's entries and added to one
+        // FP64 sum (only the sum over entries enters V_l).  Entries outside
+        // the product (ragged tiles) see zero-padded operand rows, so D = 0
+        // there and they contribute nothing.
+        Acc mean[NE];
 #pragma unroll
-        for (int e = 0; e < NE; ++e) { mean[e] = (Acc)0; m2[e] = (Acc)0; }
+        for (int e = 0; e < NE; ++e) mean[e] = (Acc)0;
+        double m2_sum = 0.0;
         Acc count = (Acc)0;
-        typename P::AccVec acc[NB][NB];
+        typename P::AccVec acc[NBR][NBC];
 #pragma unroll
-        for (int bi = 0; bi < NB; ++bi)
+        for (int bi = 0; bi < NBR; ++bi)
 #pragma unroll
-            for (int bj = 0; bj < NB; ++bj)
+            for (int bj = 0; bj < NBC; ++bj)
 #pragma unroll
                 for (int r = 0; r < P::REGS; ++r) acc[bi][bj][r] = (Acc)0;
 
+        // one MFMA step at draw offset kk of the staged chunk
+        auto step = [&](const In* LA, const In* LB, int kk) {
+            FragT a[NBR], b[NBC];
+#pragma unroll
+            for (int bi = 0; bi < NBR; ++bi) a[bi] = LdsFrag<P>::load(LA, BM, kk, wrow + bi * P::BLK, lane);
+#pragma unroll
+            for (int bj = 0; bj < NBC; ++bj) b[bj] = LdsFrag<P>::load(LB, BM, kk, wcol + bj * P::BLK, lane);
+#pragma unroll
+            for (int bi = 0; bi < NBR; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < NBC; ++bj) acc[bi][bj] = P::mma(a[bi], b[bj], acc[bi][bj]);
+        };
+        auto fold_coarse = [&]() {
+#pragma unroll
+            for (int bi = 0; bi < NBR; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < NBC; ++bj)
+#pragma unroll
+                    for (int r = 0; r < P::REGS; ++r) acc[bi][bj][r] *= omega;
+        };
+
+        int fs = 0, fq = 0;                      // the last chunk fetched
+        auto advance = [&]() {
+            if (++fq == nch) { fq = 0; ++fs; }
+        };
         if (total > 0) {
-            fetch(0);
-            stash(0);
+            fetch(0, 0, 0);
+            stash(0, 0);
+        }
+        if constexpr (PF == 2) {
+            if (total > 1) {
+                advance();
+                fetch(1, fs, fq);
+            }
         }
         __syncthreads();
-        for (int64_t c = 0; c < total; ++c) {
-            const int buf = (int)(c & 1);
-            if (c + 1 < total) fetch(c + 1);     // global loads in flight during the MFMAs
-            const int64_t k0 = (c % nch) * KC;
-            const int64_t steps = (prm.kpad - k0 < KC ? prm.kpad - k0 : KC) / P::KSTEP;
+        int cq = 0;                              // chunk (within its realisation) being multiplied
+        for (int c = 0; c < total; ++c) {
+            const int buf = c & 1;
+            if constexpr (PF == 2) {
+                if (c + 2 < total) {             // chunk c + 2 into the set chunk c came through
+                    advance();
+                    if (buf == 0) fetch(0, fs, fq);
+                    else fetch(1, fs, fq);
+                }
+            } else {
+                if (c + 1 < total) {
+                    advance();
+                    fetch(0, fs, fq);
+                }
+            }
+            const int k0 = cq * KC;
             const In* LA = lds[buf][0];
             const In* LB = lds[buf][1];
-            for (int64_t st = 0; st < steps; ++st) {
-                const int kk = (int)(st * P::KSTEP);
-                if (k0 + kk == prm.kc && prm.kc > 0) {
-                    // end of the coarse segment: fold in the coarse sketch weight
-#pragma unroll
-                    for (int bi = 0; bi < NB; ++bi)
-#pragma unroll
-                        for (int bj = 0; bj < NB; ++bj)
-#pragma unroll
-                            for (int r = 0; r < P::REGS; ++r) acc[bi][bj][r] *= omega;
-                }
-                FragT a[NB], b[NB];
-#pragma unroll
-                for (int bi = 0; bi < NB; ++bi) a[bi] = LdsFrag<P>::load(LA, BM, kk, wrow + bi * P::BLK, lane);
-#pragma unroll
-                for (int bj = 0; bj < NB; ++bj) b[bj] = LdsFrag<P>::load(LB, BM, kk, wcol + bj * P::BLK, lane);
-#pragma unroll
-                for (int bi = 0; bi < NB; ++bi)
-#pragma unroll
-                    for (int bj = 0; bj < NB; ++bj) acc[bi][bj] = P::mma(a[bi], b[bj], acc[bi][bj]);
+            const int steps = (kpad - k0 < KC ? kpad - k0 : KC) / P::KSTEP;
+            for (int st = 0; st < steps; ++st) {
+                const int kk = st * P::KSTEP;
+                // end of the coarse segment: fold in the coarse sketch weight
+                if (k0 + kk == kc && kc > 0) fold_coarse();
+                step(LA, LB, kk);
             }
-            if (c % nch == nch - 1) {
+            if (cq == nch - 1) {
                 // the realisation is complete: D = scale * acc enters the Welford state
                 count += (Acc)1;
                 const Acc inv = (Acc)1 / count;
+                Acc m2_r = (Acc)0;
                 int e = 0;
 #pragma unroll
-                for (int bi = 0; bi < NB; ++bi)
+                for (int bi = 0; bi < NBR; ++bi)
 #pragma unroll
-                    for (int bj = 0; bj < NB; ++bj)
+                    for (int bj = 0; bj < NBC; ++bj)
 #pragma unroll
                         for (int r = 0; r < P::REGS; ++r, ++e) {
                             const Acc d = scale * acc[bi][bj][r];
                             const Acc delta = d - mean[e];
                             mean[e] += delta * inv;
-                            m2[e] += delta * (d - mean[e]);
+                            m2_r += delta * (d - mean[e]);
                             acc[bi][bj][r] = (Acc)0;
                         }
+                m2_sum += (double)m2_r;
             }
-            if (c + 1 < total) stash(buf ^ 1);
+            if (++cq == nch) cq = 0;
+            if (c + 1 < total) {                 // chunk c + 1 into the other LDS buffer
+                if constexpr (PF == 2) {
+                    if (buf == 0) stash(1, 1);
+                    else stash(0, 0);
+                } else {
+                    stash(0, buf ^ 1);
+                }
+            }
             __syncthreads();
         }
 
         // group mean of every in-range entry, and the group's within sum of squares
-        double m2_sum = 0.0;
         int e = 0;
         double* pm = prm.part_mean + group * prm.sum_mp + Pd.mp_prefix;
 #pragma unroll
-        for (int bi = 0; bi < NB; ++bi)
+        for (int bi = 0; bi < NBR; ++bi)
 #pragma unroll
-            for (int bj = 0; bj < NB; ++bj)
+            for (int bj = 0; bj < NBC; ++bj)
 #pragma unroll
                 for (int r = 0; r < P::REGS; ++r, ++e) {
-                    const int64_t i = trow + wrow + bi * P::BLK + P::row_of(lane, r);
-                    const int64_t j = tcol + wcol + bj * P::BLK + P::col_of(lane);
-                    if (i < m && j < p) {
-                        pm[i * p + j] = (double)mean[e];
-                        m2_sum += (double)m2[e];
-                    }
+                    const int i = trow + wrow + bi * P::BLK + P::row_of(lane, r);
+                    const int j = tcol + wcol + bj * P::BLK + P::col_of(lane);
+                    if (i < m && j < p) pm[(int64_t)i * p + j] = (double)mean[e];
                 }
         for (int off = kWave / 2; off > 0; off >>= 1) m2_sum += __shfl_xor(m2_sum, off, kWave);
         if (lane == 0) red[wave] = m2_sum;
         __syncthreads();
         if (threadIdx.x == 0) {
             double tot = 0.0;
-            for (int w = 0; w < kSketchThreads / kWave; ++w) tot += red[w];
+            for (int w = 0; w < THREADS / kWave; ++w) tot += red[w];
             prm.part_m2[group * prm.total_tiles + tt] = tot;
         }
         __syncthreads();
@@ -666,10 +748,10 @@ bool matmul_plan(const MatmulProblem* probs, int nprob, int prec, int num_levels
     plan.kstep = ps.kstep;
     plan.kpack = ps.kpack;
     plan.elem = ps.elem;
-    // wave blocks per dimension: 1 (workgroup tile 2 x BLK = 64: four waves per
-    // SIMD fit, the measured best on every workload) unless tuned to 2
-    // (tile 128); f64 blocks are 16 wide and always use 2 (tile 64)
-    plan.nb = prec == 0 ? 2 : 1;
+    // workgroup tile: 128 (4 x 2 waves of 32 x 64) for the 32 x 32 MFMA
+    // blocks unless tuned to 64 (2 x 2 waves of 32 x 32); f64 blocks are 16
+    // wide and always use tile 64 (2 x 2 waves of 32 x 32 in 16 x 16 blocks)
+    plan.nb = 2;
     if (tune && tune->tile > 0 && prec != 0) plan.nb = tune->tile <= 2 * ps.blk ? 1 : 2;
     plan.tile = 2 * plan.nb * ps.blk;
     plan.kpad_max = 0;
@@ -732,7 +814,9 @@ bool matmul_plan(const MatmulProblem* probs, int nprob, int prec, int num_levels
     const int64_t per_sample = plan.kpad_max * plan.sum_rows * plan.elem;
     if (budget < per_sample) budget = per_sample;
     plan.gather_bytes = budget;
-    const int64_t target = (tune && tune->target_blocks > 0) ? tune->target_blocks : kTargetSketchBlocks;
+    // about two rounds of resident workgroups: tile 64 runs 4 per CU, tile 128 runs 2
+    const int64_t target = (tune && tune->target_blocks > 0) ? tune->target_blocks
+                                                             : (plan.tile == 64 ? 2048 : 1024);
     plan.groups_max = ceil_div(target, plan.total_tiles);
     if (plan.groups_max > 65535) plan.groups_max = 65535;
     const int64_t L1 = num_levels;
@@ -785,7 +869,7 @@ hipError_t matmul_reset(const MatmulPlan& plan, char* ws, hipStream_t stream)
     return fill_doubles(reinterpret_cast<double*>(ws), plan.state_doubles, 0.0, stream);
 }
 
-template <typename P, typename Compute, int NB>
+template <typename P, typename Compute, int WR, int WC, int NBR, int NBC, int PF, int WPE>
 static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t k_first, int64_t batch,
                            int64_t done_before, int64_t kc, int64_t kpad, const StreamKeys& keys, char* ws,
                            hipStream_t stream, KernelTimer* timer)
@@ -838,9 +922,11 @@ static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t
     s.sum_mp = plan.sum_mp;
     int64_t blocks = plan.total_tiles * groups;
     if (blocks > kSketchMaxBlocks) blocks = kSketchMaxBlocks;
+    blocks = ceil_div(blocks, kXcds) * kXcds;
     {
         ScopedTiming t(timer, 0);
-        hipLaunchKernelGGL((sketch_kernel<P, NB>), dim3((unsigned)blocks), dim3(kSketchThreads), 0, stream, s);
+        hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, WPE>), dim3((unsigned)blocks), dim3(kWave * WR * WC),
+                           0, stream, s);
     }
     err = hipGetLastError();
     if (err != hipSuccess) return err;
@@ -873,9 +959,12 @@ static hipError_t run_pass_nb(const MatmulPlan& plan, const LevelRange& lr, int6
                               int64_t done_before, int64_t kc, int64_t kpad, const StreamKeys& keys, char* ws,
                               hipStream_t stream, KernelTimer* timer)
 {
-    if (plan.nb == 1)
-        return run_pass<P, Compute, 1>(plan, lr, k_first, batch, done_before, kc, kpad, keys, ws, stream, timer);
-    return run_pass<P, Compute, 2>(plan, lr, k_first, batch, done_before, kc, kpad, keys, ws, stream, timer);
+    // tile 64: 2 x 2 waves of 32 x 32; tile 128: 4 x 2 waves of 32 x 64
+    if (plan.tile == 64)
+        return run_pass<P, Compute, 2, 2, 1, 1, 2, 4>(plan, lr, k_first, batch, done_before, kc, kpad, keys, ws, stream,
+                                                   timer);
+    return run_pass<P, Compute, 4, 2, 1, 2, 1, 4>(plan, lr, k_first, batch, done_before, kc, kpad, keys, ws, stream,
+                                               timer);
 }
 
 hipError_t matmul_level_run(const MatmulPlan& plan, const LevelRange& lr, int64_t done_before, const StreamKeys& keys,
@@ -892,7 +981,8 @@ hipError_t matmul_level_run(const MatmulPlan& plan, const LevelRange& lr, int64_
         hipError_t err;
         const int64_t k_first = lr.k_begin + b, before = done_before + b;
         if (plan.prec == 0)
-            err = run_pass<PolicyF64, double, 2>(plan, lr, k_first, batch, before, kc, kpad, keys, ws, stream, timer);
+            err = run_pass<PolicyF64, double, 2, 2, 2, 2, 2, 2>(plan, lr, k_first, batch, before, kc, kpad, keys, ws,
+                                                             stream, timer);
         else if (plan.prec == 1)
             err = run_pass_nb<PolicyF32, float>(plan, lr, k_first, batch, before, kc, kpad, keys, ws, stream, timer);
         else if (plan.prec == 2)
