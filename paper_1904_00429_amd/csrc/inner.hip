@@ -98,17 +98,25 @@ __device__ __forceinline__ void pair_terms(const InnerMultiParams& prm, const In
     v1 = (2u * q + 1u < L.c) ? inner_product_term<T, LAWS>(prm, k, r1, L.sid_value) : (T)0;
 }
 
-template <typename T>
-__device__ __forceinline__ void add_pair(uint32_t q, uint32_t coarse_pairs, bool odd_prev, T v0, T v1,
-                                         T& acc_coarse, T& acc_fine)
+// Sum of the product terms of pairs q0, q0 + G, q0 + 2G, ... below q_end into
+// acc, in increasing q; two pairs per iteration give the scheduler two
+// independent Philox chains to interleave.
+template <typename T, int LAWS>
+__device__ __forceinline__ void sum_pairs(const InnerMultiParams& prm, const InnerLevel& L, uint32_t q0,
+                                          uint32_t q_end, uint32_t G, uint32_t k, T& acc)
 {
-    if (q < coarse_pairs) {
-        acc_coarse += v0 + v1;
-    } else if (odd_prev && q == coarse_pairs) {
-        acc_coarse += v0;    // draw c_prev - 1 is coarse, draw c_prev is fine
-        acc_fine += v1;
-    } else {
-        acc_fine += v0 + v1;
+    uint32_t q = q0;
+    for (; q + G < q_end; q += 2u * G) {
+        T a0, a1, b0, b1;
+        pair_terms<T, LAWS>(prm, L, q, k, a0, a1);
+        pair_terms<T, LAWS>(prm, L, q + G, k, b0, b1);
+        acc += a0 + a1;
+        acc += b0 + b1;
+    }
+    if (q < q_end) {
+        T a0, a1;
+        pair_terms<T, LAWS>(prm, L, q, k, a0, a1);
+        acc += a0 + a1;
     }
 }
 
@@ -142,21 +150,20 @@ __global__ __launch_bounds__(kInnerBlock) void inner_multi_kernel(InnerMultiPara
         const uint32_t s = s_lo + (uint32_t)gi + it * (uint32_t)groups;
         const bool active = s < s_hi;
         const uint32_t k = L.k_begin + (active ? s : s_lo);
+        // Pairs below coarse_pairs hold two coarse draws; with an odd c_prev
+        // the next pair straddles (its first draw is coarse, its second
+        // fine); the rest are fine.  The lane takes pairs q = lane_g (mod G).
         T acc_coarse = (T)0, acc_fine = (T)0;
-        // two pairs per iteration: independent Philox chains the scheduler can interleave
-        uint32_t q = lane_g;
-        for (; q + (uint32_t)G < pairs; q += 2u * (uint32_t)G) {
-            T a0, a1, b0, b1;
-            pair_terms<T, LAWS>(prm, L, q, k, a0, a1);
-            pair_terms<T, LAWS>(prm, L, q + G, k, b0, b1);
-            add_pair(q, coarse_pairs, odd_prev, a0, a1, acc_coarse, acc_fine);
-            add_pair(q + G, coarse_pairs, odd_prev, b0, b1, acc_coarse, acc_fine);
-        }
-        if (q < pairs) {
+        sum_pairs<T, LAWS>(prm, L, (uint32_t)lane_g, coarse_pairs, (uint32_t)G, k, acc_coarse);
+        if (odd_prev && (coarse_pairs & (uint32_t)(G - 1)) == (uint32_t)lane_g) {
             T a0, a1;
-            pair_terms<T, LAWS>(prm, L, q, k, a0, a1);
-            add_pair(q, coarse_pairs, odd_prev, a0, a1, acc_coarse, acc_fine);
+            pair_terms<T, LAWS>(prm, L, coarse_pairs, k, a0, a1);
+            acc_coarse += a0;
+            acc_fine += a1;
         }
+        const uint32_t fine_begin = coarse_pairs + (odd_prev ? 1u : 0u);
+        const uint32_t q_fine = fine_begin + (((uint32_t)lane_g - fine_begin) & (uint32_t)(G - 1));
+        sum_pairs<T, LAWS>(prm, L, q_fine, pairs, (uint32_t)G, k, acc_fine);
         T part = omega * acc_coarse + acc_fine;
         const int width = G < kWave ? G : kWave;
         for (int off = width >> 1; off > 0; off >>= 1) part += __shfl_xor(part, off, kWave);

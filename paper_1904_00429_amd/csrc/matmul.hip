@@ -310,7 +310,7 @@ struct SketchParams {
     double omega;                // 1 - c_l / c_{l-1} (unused at level 0: kc == 0)
     uint32_t c;                  // c_l
     const char* gbuf;
-    double* part_mean;           // groups x sum_mp
+    void* part_mean;             // groups x sum_mp, in the accumulation type
     double* part_m2;             // groups x total_tiles
     int64_t sum_mp;
 };
@@ -555,7 +555,7 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
 
         // group mean of every in-range entry, and the group's within sum of squares
         int e = 0;
-        double* pm = prm.part_mean + group * prm.sum_mp + Pd.mp_prefix;
+        Acc* pm = static_cast<Acc*>(prm.part_mean) + group * prm.sum_mp + Pd.mp_prefix;
 #pragma unroll
         for (int bi = 0; bi < NBR; ++bi)
 #pragma unroll
@@ -564,7 +564,7 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
                 for (int r = 0; r < P::REGS; ++r, ++e) {
                     const int i = trow + wrow + bi * P::BLK + P::row_of(lane, r);
                     const int j = tcol + wcol + bj * P::BLK + P::col_of(lane);
-                    if (i < m && j < p) pm[(int64_t)i * p + j] = (double)mean[e];
+                    if (i < m && j < p) pm[(int64_t)i * p + j] = mean[e];
                 }
         for (int off = kWave / 2; off > 0; off >>= 1) m2_sum += __shfl_xor(m2_sum, off, kWave);
         if (lane == 0) red[wave] = m2_sum;
@@ -586,13 +586,15 @@ struct MergeParams {
     int level;
     int64_t batch, groups, total_tiles, sum_mp, sum_merge_blocks, nprob;
     double done_before;          // realisations already in the level state
-    const double* part_mean;
+    const void* part_mean;       // groups x sum_mp, PartT
     const double* part_m2;
     double* means;               // levels x sum_mp
     double* between;             // levels x sum_merge_blocks
     double* within;              // levels x nprob
 };
 
+// PartT: the sketch's accumulation type, in which it wrote the group means.
+template <typename PartT>
 __global__ __launch_bounds__(kMergeThreads) void merge_kernel(MergeParams prm)
 {
     __shared__ double red[kMergeThreads];
@@ -606,10 +608,13 @@ __global__ __launch_bounds__(kMergeThreads) void merge_kernel(MergeParams prm)
         double* mean = prm.means + prm.level * prm.sum_mp + Pd.mp_prefix;
         double mu = mean[e];
         double na = prm.done_before;
-        for (int64_t g = 0; g < prm.groups; ++g) {
-            const double nb = (double)((g + 1) * prm.batch / prm.groups - g * prm.batch / prm.groups);
+        const PartT* part = static_cast<const PartT*>(prm.part_mean) + Pd.mp_prefix + e;
+        const uint32_t batch = (uint32_t)prm.batch, groups = (uint32_t)prm.groups;
+        for (uint32_t g = 0; g < groups; ++g) {
+            // group g holds realisations [g batch / groups, (g + 1) batch / groups)
+            const double nb = (double)((g + 1) * batch / groups - g * batch / groups);
             const double n = na + nb;
-            const double delta = prm.part_mean[g * prm.sum_mp + Pd.mp_prefix + e] - mu;
+            const double delta = (double)part[(int64_t)g * prm.sum_mp] - mu;
             mu += delta * (nb / n);
             between += delta * delta * (na * nb / n);
             na = n;
@@ -917,7 +922,7 @@ static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t
     s.omega = lr.c_prev > 0 ? 1.0 - (double)lr.c / (double)lr.c_prev : 1.0;
     s.c = (uint32_t)lr.c;
     s.gbuf = g.gbuf;
-    s.part_mean = reinterpret_cast<double*>(ws + plan.off_part_mean);
+    s.part_mean = ws + plan.off_part_mean;
     s.part_m2 = reinterpret_cast<double*>(ws + plan.off_part_m2);
     s.sum_mp = plan.sum_mp;
     int64_t blocks = plan.total_tiles * groups;
@@ -948,8 +953,8 @@ static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t
     mg.within = reinterpret_cast<double*>(ws + plan.off_within);
     {
         ScopedTiming t(timer, 2);
-        hipLaunchKernelGGL(merge_kernel, dim3((unsigned)plan.max_merge_blocks, (unsigned)plan.nprob),
-                           dim3(kMergeThreads), 0, stream, mg);
+        hipLaunchKernelGGL((merge_kernel<typename P::Acc>), dim3((unsigned)plan.max_merge_blocks,
+                           (unsigned)plan.nprob), dim3(kMergeThreads), 0, stream, mg);
     }
     return hipGetLastError();
 }

@@ -85,10 +85,11 @@ __device__ __forceinline__ uint32_t draw_index(uint32_t t, uint32_t k, uint32_t 
 }
 
 // u = ((w >> 9) + 1/2) 2^-23: 2^23 equally spaced points in (0, 1), exactly
-// representable in FP32 and FP64, never 0 or 1.
+// representable in FP32 and FP64, never 0 or 1.  (w >> 9) 2^-23 + 2^-24 is
+// exact in FP32, so the single fma gives the same value.
 __device__ __forceinline__ float unit_f32(uint32_t w)
 {
-    return ((float)(w >> 9) + 0.5f) * 0x1p-23f;
+    return __builtin_fmaf((float)(w >> 9), 0x1p-23f, 0x1p-24f);
 }
 
 __device__ __forceinline__ double unit_f64(uint32_t w)
@@ -98,10 +99,12 @@ __device__ __forceinline__ double unit_f64(uint32_t w)
 
 // Box-Muller pair from two uniforms: (rho cos 2 pi v, rho sin 2 pi v),
 // rho = sqrt(-2 ln u).  FP32 uses the hardware transcendental units:
-// v_log_f32 gives log2, v_sin/v_cos take their argument in revolutions.
+// v_log_f32 gives log2, v_sqrt_f32 (1 ulp, no IEEE fix-up sequence: its
+// argument is at least 2^-23 ln 2 > 0), v_sin/v_cos take their argument in
+// revolutions.
 __device__ __forceinline__ void box_muller(float u, float v, float& z0, float& z1)
 {
-    const float rho = __builtin_sqrtf(-2.0f * 0.69314718055994530942f * __builtin_amdgcn_logf(u));
+    const float rho = __builtin_amdgcn_sqrtf(-2.0f * 0.69314718055994530942f * __builtin_amdgcn_logf(u));
     z0 = rho * __builtin_amdgcn_cosf(v);
     z1 = rho * __builtin_amdgcn_sinf(v);
 }
