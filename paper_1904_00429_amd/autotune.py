@@ -1,7 +1,9 @@
 """Autotuner of the batched matrix pipeline's launch shape.
 
 Candidates: workgroup output tile (64 or 128) x sketch work items per pass
-(target_blocks).  Each candidate runs one level-0 pass of the given batch on
+(target_blocks) x bytes of gathered operands per pass (gather_budget: the
+larger budget means fewer, larger passes and fewer merges of the level
+state).  Each candidate runs one level-0 pass of the given batch on
 the GPU (warm-up, then timed with HIP events via torch on the current
 stream); the fastest is cached in a JSON file keyed by a signature of the
 batch (precision, ladder head, per-product shapes bucketed to powers of two),
@@ -17,7 +19,8 @@ import torch
 
 from .mlmc import BatchedEstimate, BatchProblem
 
-CANDIDATES = [{"tile": t, "target_blocks": b} for t in (64, 128) for b in (512, 1024, 2048, 4096)]
+CANDIDATES = [{"tile": t, "target_blocks": b, "gather_budget": g}
+              for t in (64, 128) for b in (1024, 4096) for g in (192 << 20, 768 << 20)]
 
 
 def cache_path() -> str:
@@ -52,7 +55,7 @@ def _store(table: dict) -> None:
 
 def tune(problems: Sequence[BatchProblem], c: Sequence[int], n_samples: Sequence[int], prec: str = "fp32",
          device=None, repeats: int = 2, use_cache: bool = True) -> dict:
-    """Return the fastest {"tile", "target_blocks"} for this batch."""
+    """Return the fastest {"tile", "target_blocks", "gather_budget"} for this batch."""
     sig = signature(problems, c, prec)
     table = _load() if use_cache else {}
     if sig in table:

@@ -37,8 +37,9 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kMergeThreads = 256;
 constexpr int kGatherThreads = 64;
-constexpr int kGatherPositions = 8;
-constexpr int64_t kGatherBudgetBytes = 192ll << 20;
+constexpr int kGatherPositions = 8;           // positions of one packed group (KPACK = 8)
+constexpr int kGatherMaxOctets = 8;           // position groups per gather block, at most
+constexpr int64_t kGatherBudgetBytes = 768ll << 20;
 constexpr int64_t kSketchMaxBlocks = 8192;
 constexpr int kXcds = 8;                     // accelerator complex dies of an MI355X
 
@@ -141,6 +142,7 @@ struct GatherParams {
     uint32_t c, c_prev, level_field;
     int64_t kc, kpad;        // padded coarse length, padded total length
     int64_t batch;           // realisations in this pass
+    int octets;              // groups of 8 positions per block (1 .. kGatherMaxOctets)
     uint32_t key0, key1;
     uint32_t k_first;        // realisation of batch slot 0
     int elem;
@@ -175,11 +177,15 @@ template <> struct StoreOf<uint8_t> {
     }
 };
 
+// A block covers prm.octets groups of 8 consecutive padded positions of one
+// realisation of one product; its lanes walk the (octet, quad of 4 rows)
+// items, so a product with few rows still keeps every lane busy.
 template <typename Compute, typename Store, int KPACK, int LAWS>
 __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm)
 {
-    __shared__ uint32_t cols[kGatherPositions];
-    __shared__ int valid[kGatherPositions];
+    constexpr int MAXPOS = kGatherPositions * kGatherMaxOctets;
+    __shared__ uint32_t cols[MAXPOS];
+    __shared__ int valid[MAXPOS];
     // the product's description is copied to registers once: the stores into
     // the gathered buffer below could otherwise alias it and force reloads
     const ProblemDesc* Pp = prm.descs + blockIdx.z;
@@ -191,33 +197,30 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
     const LawEval<Compute> LA = LawEval<Compute>::make(Pp->A);
     const LawEval<Compute> LB = LawEval<Compute>::make(Pp->B);
     const float pre_a = Pp->pre_a, pre_b = Pp->pre_b;
-    const int64_t pos0 = (int64_t)blockIdx.x * kGatherPositions;
+    const int64_t pos_base = (int64_t)blockIdx.x * kGatherPositions * prm.octets;
     const int64_t slot = blockIdx.y;
     const uint32_t k = prm.k_first + (uint32_t)slot;
     const uint32_t sid_index = stream_id(kTagIndex, prm.level_field, sid_problem);
     const uint32_t sid_value = stream_id(kTagValue, prm.level_field, sid_problem);
-    if (threadIdx.x < kGatherPositions) {
-        const int64_t pos = pos0 + threadIdx.x;
-        const int64_t t = pos < prm.kpad ? draw_of_position(pos, prm.kc, prm.c, prm.c_prev) : -1;
-        valid[threadIdx.x] = t >= 0;
-        cols[threadIdx.x] = t >= 0 ? draw_index((uint32_t)t, k, sid_index, prm.key0, prm.key1, n) : 0u;
+    const int npos_block = (int)((prm.kpad - pos_base) < kGatherPositions * prm.octets ? (prm.kpad - pos_base)
+                                                                                     : kGatherPositions * prm.octets);
+    const int octets = (npos_block + kGatherPositions - 1) / kGatherPositions;
+    for (int i = threadIdx.x; i < npos_block; i += kGatherThreads) {
+        const int64_t t = draw_of_position(pos_base + i, prm.kc, prm.c, prm.c_prev);
+        valid[i] = t >= 0;
+        cols[i] = t >= 0 ? draw_index((uint32_t)t, k, sid_index, prm.key0, prm.key1, n) : 0u;
     }
     __syncthreads();
     const int64_t rows = m + p;
-    const int64_t quads = ceil_div(rows, 4);
+    const uint32_t quads = (uint32_t)ceil_div(rows, 4);
     const bool normal = LAWS == kLawsNormal || (LAWS == kLawsAny && (LA.kind != 1 || LB.kind != 1));
-    const int npos = (int)((prm.kpad - pos0) < kGatherPositions ? (prm.kpad - pos0) : kGatherPositions);
     const int64_t pass_rows = prm.batch * prm.kpad * (int64_t)prm.elem;
     Store* __restrict__ GA = reinterpret_cast<Store*>(prm.gbuf + pass_rows * rows_prefix) + slot * prm.kpad * m_pad;
     Store* __restrict__ GB = reinterpret_cast<Store*>(prm.gbuf + pass_rows * (rows_prefix + m_pad)) + slot * prm.kpad * p_pad;
-    uint32_t jv[kGatherPositions];
-    bool ok[kGatherPositions];
-#pragma unroll
-    for (int ip = 0; ip < kGatherPositions; ++ip) {
-        jv[ip] = cols[ip];
-        ok[ip] = ip < npos && valid[ip];
-    }
-    for (int64_t q = threadIdx.x; q < quads; q += kGatherThreads) {
+    // values of rows 4q .. 4q+3 at the 8 positions of group oc
+    auto generate = [&](uint32_t oc, int64_t q, const uint32_t* jv, const bool* ok) {
+        const int64_t pos0 = pos_base + (int64_t)oc * kGatherPositions;
+        const int npos = (int)((prm.kpad - pos0) < kGatherPositions ? (prm.kpad - pos0) : kGatherPositions);
         Store vals[kGatherPositions][4];
         const int64_t e0 = 4 * q;
 #pragma unroll
@@ -276,15 +279,42 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
                 *reinterpret_cast<vec_t*>(G + ((pos0 / KPACK) * R + row) * KPACK) = vv;
             }
         }
+    };
+    uint32_t jv[kGatherPositions];
+    bool ok[kGatherPositions];
+    if (octets == 1) {
+        // one group: its columns are uniform over the block
+#pragma unroll
+        for (int ip = 0; ip < kGatherPositions; ++ip) {
+            jv[ip] = cols[ip];
+            ok[ip] = ip < npos_block && valid[ip];
+        }
+        for (int64_t q = threadIdx.x; q < (int64_t)quads; q += kGatherThreads) generate(0u, q, jv, ok);
+    } else {
+        const uint32_t items = quads * (uint32_t)octets;
+        for (uint32_t it = threadIdx.x; it < items; it += kGatherThreads) {
+            const uint32_t oc = it / quads;
+            const int npos = npos_block - (int)oc * kGatherPositions;
+#pragma unroll
+            for (int ip = 0; ip < kGatherPositions; ++ip) {
+                jv[ip] = cols[oc * kGatherPositions + ip];
+                ok[ip] = ip < npos && valid[oc * kGatherPositions + ip];
+            }
+            generate(oc, (int64_t)(it - oc * quads), jv, ok);
+        }
     }
     // rows m .. m_pad - 1 of A's block and p .. p_pad - 1 of B's block are
     // zero, so the sketch's entries outside the product see D = 0
-    const int64_t pad_a = m_pad - m, pad_b = p_pad - p;
-    for (int64_t q = threadIdx.x; q < pad_a + pad_b; q += kGatherThreads) {
-        Store* G = q < pad_a ? GA : GB;
-        const int64_t R = q < pad_a ? m_pad : p_pad;
-        const int64_t row = q < pad_a ? m + q : p + (q - pad_a);
-        const Store zero = StoreOf<Store>::from((Compute)0, 1.0f);
+    const uint32_t pad_a = (uint32_t)(m_pad - m), pad_rows = (uint32_t)(m_pad - m + p_pad - p);
+    const Store zero = StoreOf<Store>::from((Compute)0, 1.0f);
+    for (uint32_t it = threadIdx.x; it < pad_rows * (uint32_t)octets; it += kGatherThreads) {
+        const uint32_t oc = it / pad_rows;
+        const uint32_t qr = it - oc * pad_rows;
+        const int64_t pos0 = pos_base + (int64_t)oc * kGatherPositions;
+        const int npos = (int)((prm.kpad - pos0) < kGatherPositions ? (prm.kpad - pos0) : kGatherPositions);
+        Store* G = qr < pad_a ? GA : GB;
+        const int64_t R = qr < pad_a ? m_pad : p_pad;
+        const int64_t row = qr < pad_a ? m + qr : p + (qr - pad_a);
         if constexpr (KPACK == 1) {
             for (int ip = 0; ip < npos; ++ip) G[(pos0 + ip) * R + row] = zero;
         } else {
@@ -808,9 +838,11 @@ bool matmul_plan(const MatmulProblem* probs, int nprob, int prec, int num_levels
     plan.sum_mp = mp;
     plan.sum_merge_blocks = mb;
     plan.total_tiles = tiles;
-    // the gathered operands of one pass stay within a budget sized for the
-    // 256 MB Infinity Cache (tunable; MLMC_GATHER_BUDGET overrides); each
-    // level fills the buffer with as many realisations as fit
+    // the gathered operands of one pass stay within a budget (768 MiB by
+    // default: larger passes mean fewer merges of the level state, measured
+    // faster than a buffer sized for the 256 MB Infinity Cache; tunable,
+    // MLMC_GATHER_BUDGET overrides); each level fills the buffer with as many
+    // realisations as fit
     int64_t budget = (tune && tune->gather_budget > 0) ? tune->gather_budget : kGatherBudgetBytes;
     if (const char* env = getenv("MLMC_GATHER_BUDGET")) {
         const long long v = atoll(env);
@@ -895,7 +927,15 @@ static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t
     g.gbuf = ws + plan.off_gather;
     {
         ScopedTiming t(timer, 1);
-        const dim3 grid((unsigned)ceil_div(kpad, kGatherPositions), (unsigned)batch, (unsigned)plan.nprob);
+        // more position groups per block while the grid still holds at least
+        // 8192 blocks (eight waves per SIMD)
+        int oct = 1;
+        while (oct < kGatherMaxOctets &&
+               ceil_div(kpad, (int64_t)kGatherPositions * oct * 2) * batch * plan.nprob >= 8192)
+            oct *= 2;
+        g.octets = oct;
+        const dim3 grid((unsigned)ceil_div(kpad, (int64_t)kGatherPositions * oct), (unsigned)batch,
+                        (unsigned)plan.nprob);
         if (plan.laws == kLawsNormal)
             hipLaunchKernelGGL((gather_kernel<Compute, typename P::In, P::KPACK, kLawsNormal>), grid,
                                dim3(kGatherThreads), 0, stream, g);
