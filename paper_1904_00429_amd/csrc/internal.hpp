@@ -90,6 +90,7 @@ struct ProblemDesc {
     int64_t merge_blocks, between_prefix;
     float pre_a, pre_b;        // FP8 operand pre-scales (powers of two), else 1
     double post;               // 1 / (pre_a pre_b)
+    double mean0;              // E[Z_0] entry for i.i.d. laws: n E[a] E[b]
     double* out;
     double* level_means;
 };
@@ -101,6 +102,7 @@ struct MatmulPlan {
     int nprob;
     int kstep, kpack, elem, nb, tile;
     int laws;                  // law pair shared by every product (kLaws*), else kLawsAny
+    bool iid;                  // no product has a reparameterised law
     int64_t kpad_max;
     int64_t sum_rows, sum_mp, sum_merge_blocks, total_tiles, max_mp, max_merge_blocks;
     int64_t groups_max, gather_bytes, state_doubles;

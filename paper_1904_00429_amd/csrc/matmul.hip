@@ -390,7 +390,8 @@ struct SketchShape {
 
 // PF register sets (1 or 2) hold the global loads of the next PF chunks.
 // WPE: waves per SIMD the register allocation must leave room for.
-template <typename P, int WR, int WC, int NBR, int NBC, int PF, int WPE>
+// SHIFTED: statistics by sums shifted by E[D] (i.i.d. laws), else Welford.
+template <typename P, int WR, int WC, int NBR, int NBC, int PF, int WPE, bool SHIFTED>
 __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchParams prm)
 {
     using In = typename P::In;
@@ -400,7 +401,7 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
     constexpr int THREADS = S::THREADS;
     constexpr int NE = NBR * NBC * P::REGS;          // entries per lane
     constexpr int BM = S::BM;                        // workgroup tile edge
-    constexpr int KC = ChunkOf<P>::KC;               // draws per staged chunk
+    constexpr int KC = ChunkOf<P>::KC;               // positions per staged chunk
     constexpr int SLABS = KC / P::KPACK;
     constexpr int VEC = 16 / (int)sizeof(In);        // elements per 16-byte vector
     constexpr int V_SLAB = BM * P::KPACK / VEC;      // vectors per slab of one operand
@@ -428,33 +429,33 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
         const int64_t s_begin = group * prm.batch / prm.groups;
         const int64_t s_end = (group + 1) * prm.batch / prm.groups;
         const int64_t pass_rows = prm.batch * prm.kpad * (int64_t)prm.elem;
-        const In* GA0 = reinterpret_cast<const In*>(prm.gbuf + pass_rows * Pd.rows_prefix);
-        const In* GB0 = reinterpret_cast<const In*>(prm.gbuf + pass_rows * (Pd.rows_prefix + m_pad));
-        const Acc scale = (Acc)((double)Pd.n / (double)prm.c * Pd.post);
+        // the group's realisations are consecutive blocks [kpad / KPACK][rows][KPACK]:
+        // position P of the group's stream (P = s kpad + k) sits at element P * rows
+        const In* GA0 = reinterpret_cast<const In*>(prm.gbuf + pass_rows * Pd.rows_prefix) + s_begin * prm.kpad * m_pad;
+        const In* GB0 = reinterpret_cast<const In*>(prm.gbuf + pass_rows * (Pd.rows_prefix + m_pad)) +
+                        s_begin * prm.kpad * p_pad;
+        const double scale64 = (double)Pd.n / (double)prm.c * Pd.post;
+        const Acc scale = (Acc)scale64;
         const Acc omega = (Acc)prm.omega;
-        // chunks per realisation; the coarse length is a multiple of the MFMA step
-        const int nch = (int)((prm.kpad + KC - 1) / KC);
         const int kc = (int)prm.kc;
         const int kpad = (int)prm.kpad;
-        const int total = (int)(s_end - s_begin) * nch;
+        const int npos = (int)(s_end - s_begin) * kpad;     // positions of the group's stream
+        const int total = (npos + KC - 1) / KC;             // chunks; a chunk may span realisations
 
-        // Chunk (s, q) = realisation s_begin + s, draws [q KC, q KC + KC): the
-        // slabs k0 / KPACK .. of the realisation's [kpad / KPACK][rows][KPACK]
-        // block.  The chunk's base is uniform (scalar); a thread's vectors sit
-        // at fixed element offsets from it.  The register sets keep the global
-        // loads of the next PF chunks in flight while the MFMAs run on the
-        // chunk staged in LDS.
+        // Chunk c holds stream positions [c KC, c KC + KC).  The chunk's base
+        // is uniform (scalar); a thread's vectors sit at fixed element offsets
+        // from it.  The register sets keep the global loads of the next PF
+        // chunks in flight while the MFMAs run on the chunk staged in LDS.
         uint4 ra[PF][VPT], rb[PF][VPT];
-        auto fetch = [&](int set, int s, int q) {
-            const int k0 = q * KC;
-            const int64_t real = (s_begin + s) * prm.kpad;
-            const In* ga = GA0 + (real + k0) * m_pad;
-            const In* gb = GB0 + (real + k0) * p_pad;
+        auto fetch = [&](int set, int c) {
+            const int k0 = c * KC;
+            const In* ga = GA0 + (int64_t)k0 * m_pad;
+            const In* gb = GB0 + (int64_t)k0 * p_pad;
 #pragma unroll
             for (int v = 0; v < VPT; ++v) {
                 const int vid = threadIdx.x + v * THREADS;
                 const int slab = vid / V_SLAB, iv = vid % V_SLAB;
-                if (k0 + slab * P::KPACK < kpad) {
+                if (k0 + slab * P::KPACK < npos) {
                     ra[set][v] = *reinterpret_cast<const uint4*>(ga + (slab * m_pad + trow) * P::KPACK + iv * VEC);
                     rb[set][v] = *reinterpret_cast<const uint4*>(gb + (slab * p_pad + tcol) * P::KPACK + iv * VEC);
                 } else {
@@ -472,16 +473,38 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
             }
         };
 
-        // Welford: a running mean per entry; the squared-deviation updates of
-        // a realisation are summed over the lane's entries and added to one
-        // FP64 sum (only the sum over entries enters V_l).  Entries outside
-        // the product (ragged tiles) see zero-padded operand rows, so D = 0
-        // there and they contribute nothing.
-        Acc mean[NE];
+        // Per entry one running value: the Welford mean, or (SHIFTED) the sum
+        // of acc - shift, where shift = E[D] / scale in accumulator units
+        // (n E[a] E[b] at level 0, 0 above it: E[D_l] = 0).  The squared
+        // deviations of a realisation are summed over the lane's entries into
+        // one FP64 sum (only the sum over entries enters V_l).  Entries
+        // outside the product see zero-padded operand rows: D = 0 there, and
+        // the shift is not applied to them.
+        Acc run[NE];
 #pragma unroll
-        for (int e = 0; e < NE; ++e) mean[e] = (Acc)0;
+        for (int e = 0; e < NE; ++e) run[e] = (Acc)0;
         double m2_sum = 0.0;
         Acc count = (Acc)0;
+        const Acc shift = SHIFTED && kc == 0 ? (Acc)(Pd.mean0 / scale64) : (Acc)0;
+        // with a non-zero shift, entries outside the product (ragged tiles only)
+        // are masked: bit e of `inside` is set for an entry inside the product
+        static_assert(NE <= 32, "one mask bit per entry");
+        const bool ragged = SHIFTED && shift != (Acc)0 && (trow + BM > m || tcol + BM > p);
+        uint32_t inside = 0xFFFFFFFFu;
+        if (ragged) {
+            inside = 0u;
+            int e = 0;
+#pragma unroll
+            for (int bi = 0; bi < NBR; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < NBC; ++bj)
+#pragma unroll
+                    for (int r = 0; r < P::REGS; ++r, ++e) {
+                        const int i = trow + wrow + bi * P::BLK + P::row_of(lane, r);
+                        const int j = tcol + wcol + bj * P::BLK + P::col_of(lane);
+                        if (i < m && j < p) inside |= 1u << e;
+                    }
+        }
         typename P::AccVec acc[NBR][NBC];
 #pragma unroll
         for (int bi = 0; bi < NBR; ++bi)
@@ -490,7 +513,7 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
 #pragma unroll
                 for (int r = 0; r < P::REGS; ++r) acc[bi][bj][r] = (Acc)0;
 
-        // one MFMA step at draw offset kk of the staged chunk
+        // one MFMA step at position offset kk of the staged chunk
         auto step = [&](const In* LA, const In* LB, int kk) {
             FragT a[NBR], b[NBC];
 #pragma unroll
@@ -510,53 +533,25 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
 #pragma unroll
                     for (int r = 0; r < P::REGS; ++r) acc[bi][bj][r] *= omega;
         };
-
-        int fs = 0, fq = 0;                      // the last chunk fetched
-        auto advance = [&]() {
-            if (++fq == nch) { fq = 0; ++fs; }
-        };
-        if (total > 0) {
-            fetch(0, 0, 0);
-            stash(0, 0);
-        }
-        if constexpr (PF == 2) {
-            if (total > 1) {
-                advance();
-                fetch(1, fs, fq);
-            }
-        }
-        __syncthreads();
-        int cq = 0;                              // chunk (within its realisation) being multiplied
-        for (int c = 0; c < total; ++c) {
-            const int buf = c & 1;
-            if constexpr (PF == 2) {
-                if (c + 2 < total) {             // chunk c + 2 into the set chunk c came through
-                    advance();
-                    if (buf == 0) fetch(0, fs, fq);
-                    else fetch(1, fs, fq);
-                }
+        // the realisation is complete: D = scale * acc enters the statistics
+        auto realisation_done = [&]() {
+            count += (Acc)1;
+            Acc part = (Acc)0;
+            int e = 0;
+            if constexpr (SHIFTED) {
+#pragma unroll
+                for (int bi = 0; bi < NBR; ++bi)
+#pragma unroll
+                    for (int bj = 0; bj < NBC; ++bj)
+#pragma unroll
+                        for (int r = 0; r < P::REGS; ++r, ++e) {
+                            const Acc d = ((inside >> e) & 1u) ? acc[bi][bj][r] - shift : (Acc)0;
+                            run[e] += d;
+                            part = fma(d, d, part);
+                            acc[bi][bj][r] = (Acc)0;
+                        }
             } else {
-                if (c + 1 < total) {
-                    advance();
-                    fetch(0, fs, fq);
-                }
-            }
-            const int k0 = cq * KC;
-            const In* LA = lds[buf][0];
-            const In* LB = lds[buf][1];
-            const int steps = (kpad - k0 < KC ? kpad - k0 : KC) / P::KSTEP;
-            for (int st = 0; st < steps; ++st) {
-                const int kk = st * P::KSTEP;
-                // end of the coarse segment: fold in the coarse sketch weight
-                if (k0 + kk == kc && kc > 0) fold_coarse();
-                step(LA, LB, kk);
-            }
-            if (cq == nch - 1) {
-                // the realisation is complete: D = scale * acc enters the Welford state
-                count += (Acc)1;
                 const Acc inv = (Acc)1 / count;
-                Acc m2_r = (Acc)0;
-                int e = 0;
 #pragma unroll
                 for (int bi = 0; bi < NBR; ++bi)
 #pragma unroll
@@ -564,14 +559,54 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
 #pragma unroll
                         for (int r = 0; r < P::REGS; ++r, ++e) {
                             const Acc d = scale * acc[bi][bj][r];
-                            const Acc delta = d - mean[e];
-                            mean[e] += delta * inv;
-                            m2_r += delta * (d - mean[e]);
+                            const Acc delta = d - run[e];
+                            run[e] += delta * inv;
+                            part += delta * (d - run[e]);
                             acc[bi][bj][r] = (Acc)0;
                         }
-                m2_sum += (double)m2_r;
             }
-            if (++cq == nch) cq = 0;
+            m2_sum += (double)part;
+        };
+
+        if (total > 0) {
+            fetch(0, 0);
+            stash(0, 0);
+        }
+        if constexpr (PF == 2) {
+            if (total > 1) fetch(1, 1);
+        }
+        __syncthreads();
+        int o = 0;                               // position within the current realisation
+        for (int c = 0; c < total; ++c) {
+            const int buf = c & 1;
+            if constexpr (PF == 2) {
+                if (c + 2 < total) {             // chunk c + 2 into the set chunk c came through
+                    if (buf == 0) fetch(0, c + 2);
+                    else fetch(1, c + 2);
+                }
+            } else {
+                if (c + 1 < total) fetch(0, c + 1);
+            }
+            const In* LA = lds[buf][0];
+            const In* LB = lds[buf][1];
+            const int left = npos - c * KC;
+            const int steps = (left < KC ? left : KC) / P::KSTEP;
+            // runs of steps that end at the chunk's end, the end of the coarse
+            // segment or the end of a realisation
+            for (int st = 0; st < steps;) {
+                // end of the coarse segment: fold in the coarse sketch weight
+                if (o == kc && kc > 0) fold_coarse();
+                const int lim = kc > o ? kc : kpad;
+                int run_steps = (lim - o) / P::KSTEP;
+                if (run_steps > steps - st) run_steps = steps - st;
+                for (int i = 0; i < run_steps; ++i) step(LA, LB, (st + i) * P::KSTEP);
+                st += run_steps;
+                o += run_steps * P::KSTEP;
+                if (o == kpad) {
+                    realisation_done();
+                    o = 0;
+                }
+            }
             if (c + 1 < total) {                 // chunk c + 1 into the other LDS buffer
                 if constexpr (PF == 2) {
                     if (buf == 0) stash(1, 1);
@@ -584,8 +619,9 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
         }
 
         // group mean of every in-range entry, and the group's within sum of squares
-        int e = 0;
         Acc* pm = static_cast<Acc*>(prm.part_mean) + group * prm.sum_mp + Pd.mp_prefix;
+        double sq_mean = 0.0;
+        int e = 0;
 #pragma unroll
         for (int bi = 0; bi < NBR; ++bi)
 #pragma unroll
@@ -594,10 +630,21 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
                 for (int r = 0; r < P::REGS; ++r, ++e) {
                     const int i = trow + wrow + bi * P::BLK + P::row_of(lane, r);
                     const int j = tcol + wcol + bj * P::BLK + P::col_of(lane);
-                    if (i < m && j < p) pm[(int64_t)i * p + j] = mean[e];
+                    if (i < m && j < p) {
+                        if constexpr (SHIFTED) {
+                            const double s1 = (double)run[e];
+                            sq_mean += s1 * s1;
+                            pm[(int64_t)i * p + j] = (Acc)(scale64 * ((double)shift + s1 / (double)count));
+                        } else {
+                            pm[(int64_t)i * p + j] = run[e];
+                        }
+                    }
                 }
-        for (int off = kWave / 2; off > 0; off >>= 1) m2_sum += __shfl_xor(m2_sum, off, kWave);
-        if (lane == 0) red[wave] = m2_sum;
+        // SHIFTED: sum (d - dbar)^2 = sum d^2 - sum_e s1_e^2 / count, in scale^2 units
+        double m2_group = m2_sum;
+        if constexpr (SHIFTED) m2_group = count > (Acc)0 ? scale64 * scale64 * (m2_sum - sq_mean / (double)count) : 0.0;
+        for (int off = kWave / 2; off > 0; off >>= 1) m2_group += __shfl_xor(m2_group, off, kWave);
+        if (lane == 0) red[wave] = m2_group;
         __syncthreads();
         if (threadIdx.x == 0) {
             double tot = 0.0;
@@ -795,6 +842,9 @@ bool matmul_plan(const MatmulProblem* probs, int nprob, int prec, int num_levels
         level_padding(plan, c[l], l > 0 ? c[l - 1] : 0, kc, kpad);
         if (kpad > plan.kpad_max) plan.kpad_max = kpad;
     }
+    plan.iid = true;
+    for (int i = 0; i < nprob; ++i)
+        if (probs[i].A.kind == 2 || probs[i].B.kind == 2) plan.iid = false;
     plan.descs.resize(nprob);
     plan.tile_owner.clear();
     int64_t rows = 0, mp = 0, mb = 0, tiles = 0;
@@ -821,6 +871,8 @@ bool matmul_plan(const MatmulProblem* probs, int nprob, int prec, int num_levels
         d.pre_a = prec == 3 ? fp8_prescale(pr.A) : 1.0f;
         d.pre_b = prec == 3 ? fp8_prescale(pr.B) : 1.0f;
         d.post = 1.0 / ((double)d.pre_a * (double)d.pre_b);
+        // both i.i.d. laws have mean loc: E[Z_0] = n loc_A loc_B in every entry
+        d.mean0 = plan.iid ? (double)pr.n * pr.A.loc * pr.B.loc : 0.0;
         d.out = pr.out;
         d.level_means = pr.level_means;
         for (int64_t t = 0; t < d.tiles; ++t) plan.tile_owner.push_back(i);
@@ -970,8 +1022,15 @@ static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t
     blocks = ceil_div(blocks, kXcds) * kXcds;
     {
         ScopedTiming t(timer, 0);
-        hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, WPE>), dim3((unsigned)blocks), dim3(kWave * WR * WC),
-                           0, stream, s);
+        // shifted sums for i.i.d. laws, except where their extra live values
+        // spill in the 4 x 2-wave BF16/FP32 kernels (measured slower there)
+        constexpr bool kShiftedFits = !(WR == 4 && sizeof(typename P::In) >= 2);
+        if (plan.iid && kShiftedFits)
+            hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, WPE, kShiftedFits>), dim3((unsigned)blocks),
+                               dim3(kWave * WR * WC), 0, stream, s);
+        else
+            hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, WPE, false>), dim3((unsigned)blocks),
+                               dim3(kWave * WR * WC), 0, stream, s);
     }
     err = hipGetLastError();
     if (err != hipSuccess) return err;
