@@ -173,3 +173,27 @@ def test_full_batch_sampled_entries(dev, full_batch, prec, tile):
     flush(f"  RMS error / estimator sd = {np.sqrt(err2 / var2):.4g}, rel = {np.sqrt(err2 / ref2):.3g}")
     if prec == "fp8":
         assert np.sqrt(err2 / var2) <= 0.25
+
+
+@pytest.mark.parametrize("prec,tile", [("fp64", 64), ("fp32", 64), ("fp32", 128), ("fp8", 64)])
+def test_batched_large_mean_ragged(orc, dev, prec, tile):
+    """Products whose level-0 mean is far above its spread, with ragged tiles:
+    the statistics shifted by E[D] (i.i.d. laws) must match the oracle."""
+    from paper_1904_00429_amd import BatchedEstimate, BatchProblem, Law
+    shapes = [(100, 600, 37), (64, 300, 64), (130, 450, 70)]
+    c, N = [4, 8, 16], [300, 150, 60]
+    la, lb = (5.0, 0.1), (-3.0, 0.25)
+    flush(f"batched large mean prec={prec} tile={tile}")
+    probs = [BatchProblem(m, n, p, Law.normal(*la), Law.normal(*lb), 40 + i) for i, (m, n, p) in enumerate(shapes)]
+    est = BatchedEstimate(probs, c, N, seed=5, prec=prec, tuning={"tile": tile}, device=dev)
+    V = est.run(level_var=True)
+    for i, (m, n, p) in enumerate(shapes):
+        ref = orc.estimate(m, n, p, orc.Law.normal(*la), orc.Law.normal(*lb), c, n_samples=N, seed=5, problem=40 + i)
+        Y = est.Y[i].cpu().numpy()
+        if prec == "fp8":
+            # e4m3 rounding of 5 +- 0.1 is not small against the spread; only check the mean level
+            assert rel_frob(Y, ref.Y) <= 0.02, (i, rel_frob(Y, ref.Y))
+            continue
+        tol = 1e-12 if prec == "fp64" else 1e-5
+        assert rel_frob(Y, ref.Y) <= tol, (i, rel_frob(Y, ref.Y))
+        np.testing.assert_allclose(V[:, i], ref.level_var, rtol=1e-10 if prec == "fp64" else 1e-4)
