@@ -17,7 +17,8 @@
 //                    [q][t]) for the MFMA operands, Z_S (K x m, [t][i]) and
 //                    W_S (K x p, [t][q]) for the epilogue, and the indices;
 //   adjoint_mfma:    U^T = B_S G^T (K x m) and V = A_S^T G (K x p) with
-//                    v_mfma_f32_32x32x2_f32; each output row t is scaled by
+//                    v_mfma_f32_32x32x2_f32 on LDS-staged operand chunks;
+//                    each output row t is scaled by
 //                    kappa_t and added (FP32 atomics, a contiguous row of the
 //                    gradient per draw) into row r_t of dM/dS.
 #include "internal.hpp"
@@ -29,7 +30,6 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kAdjGatherThreads = 64;
 constexpr int kAdjPositions = 8;
 constexpr int kAdjThreads = 256;
-constexpr int kAdjTile = 64;          // output tile 64 x 64: 2 x 2 waves of 32 x 32
 constexpr int kAdjKStep = 2;
 constexpr int64_t kAdjBudget = 192ll << 20;
 
@@ -121,10 +121,21 @@ struct AdjMfmaParams {
     float* dMB; float* dSB;           // n x p
 };
 
-// One 64 x 64 tile of U^T (rows t, columns i; K = p) or of V (rows t,
-// columns q; K = m) for one realisation, then the scaled scatter-add.
+// One 64 x 128 tile of U^T (rows t, columns i; K = p) or of V (rows t,
+// columns q; K = m) for one realisation, then the scaled scatter-add.  Both
+// operands are K-major ([k][t] and [k][x]); chunks of kAdjChunk k-values are
+// staged in LDS with 16-byte loads, double-buffered so the next chunk's
+// global loads are in flight during the MFMAs.  2 x 2 waves, each 32 x 64
+// (two 32x32x2 f32 blocks sharing the t fragment).
+constexpr int kAdjChunk = 32;
+constexpr int kAdjTileT = 64, kAdjTileX = 128;
+
 __global__ __launch_bounds__(kAdjThreads) void adjoint_mfma_kernel(AdjMfmaParams prm)
 {
+    constexpr int VA = kAdjChunk * kAdjTileT / 4 / kAdjThreads;   // uint4 per thread, t operand
+    constexpr int VB = kAdjChunk * kAdjTileX / 4 / kAdjThreads;   // uint4 per thread, x operand
+    __shared__ __align__(16) float lds_a[2][kAdjChunk * kAdjTileT];
+    __shared__ __align__(16) float lds_b[2][kAdjChunk * kAdjTileX];
     const int lane = threadIdx.x % kWave;
     const int wave = threadIdx.x / kWave;
     const int64_t s = blockIdx.y;
@@ -133,39 +144,104 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_mfma_kernel(AdjMfmaParams
     const bool is_u = tile < u_tiles;
     if (!is_u) tile -= u_tiles;
     const int64_t cols_tiles = is_u ? prm.tiles_u_cols : prm.tiles_v_cols;
-    const int64_t t0 = (tile / cols_tiles) * kAdjTile + (wave / 2) * 32;
-    const int64_t x0 = (tile % cols_tiles) * kAdjTile + (wave % 2) * 32;
-    const int64_t K = is_u ? prm.p : prm.m;           // contraction length
-    const int64_t X = is_u ? prm.m : prm.p;           // output columns
-    // A operand rows t: the transposed gathered operand of the other matrix
+    const int tb = (int)(tile / cols_tiles) * kAdjTileT;     // first t of the tile
+    const int xb = (int)(tile % cols_tiles) * kAdjTileX;     // first x of the tile
+    const int wt = (wave / 2) * 32, wx = (wave % 2) * 64;    // wave tile inside the workgroup tile
+    const int K = (int)(is_u ? prm.p : prm.m);               // contraction length
+    const int X = (int)(is_u ? prm.m : prm.p);               // output columns
+    const int kpad = (int)prm.kpad;
+    // t operand [k][t] (row stride kpad): the transposed gathered operand of the other matrix
     const float* Aop = is_u ? prm.BT + s * prm.p * prm.kpad : prm.AT + s * prm.m * prm.kpad;
-    // B operand [k][x]: G^T (p x m) for U^T, G (m x p) for V
+    // x operand [k][x] (row stride X): G^T (p x m) for U^T, G (m x p) for V
     const float* Bop = is_u ? prm.GT : prm.G;
-    f32x16 acc;
-    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-    const int64_t t_lane = t0 + lane % 32;
-    const int64_t x_lane = x0 + lane % 32;
-    for (int64_t kk = 0; kk < K; kk += kAdjKStep) {
-        const int64_t kr = kk + lane / 32;
-        const float a = (kr < K && t_lane < prm.kpad) ? Aop[kr * prm.kpad + t_lane] : 0.0f;
-        const float b = (kr < K && x_lane < X) ? Bop[kr * X + x_lane] : 0.0f;
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+    const bool vec_x = (X % 4) == 0;                         // 16-byte rows of the x operand
+
+    float4 ra[VA], rb[VB];
+    auto fetch = [&](int c) {
+        const int k0 = c * kAdjChunk;
+#pragma unroll
+        for (int v = 0; v < VA; ++v) {
+            const int vid = threadIdx.x + v * kAdjThreads;
+            const int kk = vid / (kAdjTileT / 4), t = tb + (vid % (kAdjTileT / 4)) * 4;
+            const int k = k0 + kk;
+            // kpad is a multiple of 8, so a vector of 4 t values is whole or absent
+            ra[v] = (k < K && t < kpad) ? *reinterpret_cast<const float4*>(Aop + (int64_t)k * kpad + t)
+                                        : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int v = 0; v < VB; ++v) {
+            const int vid = threadIdx.x + v * kAdjThreads;
+            const int kk = vid / (kAdjTileX / 4), x = xb + (vid % (kAdjTileX / 4)) * 4;
+            const int k = k0 + kk;
+            float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (k < K) {
+                const float* row = Bop + (int64_t)k * X;
+                if (vec_x && x < X) {
+                    val = *reinterpret_cast<const float4*>(row + x);
+                } else {
+                    if (x < X) val.x = row[x];
+                    if (x + 1 < X) val.y = row[x + 1];
+                    if (x + 2 < X) val.z = row[x + 2];
+                    if (x + 3 < X) val.w = row[x + 3];
+                }
+            }
+            rb[v] = val;
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int v = 0; v < VA; ++v)
+            *reinterpret_cast<float4*>(&lds_a[buf][(threadIdx.x + v * kAdjThreads) * 4]) = ra[v];
+#pragma unroll
+        for (int v = 0; v < VB; ++v)
+            *reinterpret_cast<float4*>(&lds_b[buf][(threadIdx.x + v * kAdjThreads) * 4]) = rb[v];
+    };
+
+    f32x16 acc[2];
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[bj][r] = 0.0f;
+    const int chunks = (K + kAdjChunk - 1) / kAdjChunk;
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int c = 0; c < chunks; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < chunks) fetch(c + 1);
+        const float* LA = lds_a[buf];
+        const float* LB = lds_b[buf];
+#pragma unroll 4
+        for (int kk = 0; kk < kAdjChunk; kk += kAdjKStep) {
+            const float a = LA[(kk + lane / 32) * kAdjTileT + wt + lane % 32];
+            const float b0 = LB[(kk + lane / 32) * kAdjTileX + wx + lane % 32];
+            const float b1 = LB[(kk + lane / 32) * kAdjTileX + wx + 32 + lane % 32];
+            acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b0, acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b1, acc[1], 0, 0, 0);
+        }
+        if (c + 1 < chunks) stash(buf ^ 1);
+        __syncthreads();
     }
-    // epilogue: lane l, register r holds row t0 + 8(r/4) + 4(l/32) + r%4, column x0 + l%32
+    // epilogue: lane l, register r holds row 8(r/4) + 4(l/32) + r%4, column l%32 of its block
     const int32_t* R = prm.R + s * prm.kpad;
     const float* N = is_u ? prm.ZS + s * prm.kpad * prm.m : prm.WS + s * prm.kpad * prm.p;
     float* dM = is_u ? prm.dMA : prm.dMB;
     float* dS = is_u ? prm.dSA : prm.dSB;
-    if (x_lane >= X) return;
-    for (int r = 0; r < 16; ++r) {
-        const int64_t t = t0 + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
-        if (t >= prm.kpad) continue;
-        const int32_t col = R[t];
-        if (col < 0) continue;
-        const float kappa = t < (int64_t)prm.c_prev ? prm.kappa_coarse : prm.kappa_fine;
-        const float g = kappa * acc[r];
-        unsafeAtomicAdd(dM + (int64_t)col * X + x_lane, g);
-        unsafeAtomicAdd(dS + (int64_t)col * X + x_lane, g * N[t * X + x_lane]);
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+        const int x = xb + wx + bj * 32 + lane % 32;
+        if (x >= X) continue;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int t = tb + wt + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
+            if (t >= kpad) continue;
+            const int32_t col = R[t];
+            if (col < 0) continue;
+            const float kappa = t < (int)prm.c_prev ? prm.kappa_coarse : prm.kappa_fine;
+            const float g = kappa * acc[bj][r];
+            unsafeAtomicAdd(dM + (int64_t)col * X + x, g);
+            unsafeAtomicAdd(dS + (int64_t)col * X + x, g * N[(int64_t)t * X + x]);
+        }
     }
 }
 
@@ -246,9 +322,9 @@ hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law&
             a.m = m; a.p = p; a.kpad = kpad; a.c_prev = (uint32_t)cp;
             a.kappa_coarse = kc; a.kappa_fine = kf;
             a.GT = GT; a.G = G; a.AT = AT; a.BT = BT; a.ZS = ZS; a.WS = WS; a.R = Rr;
-            a.tiles_t = ceil_div(kpad, kAdjTile);
-            a.tiles_u_cols = ceil_div(m, kAdjTile);
-            a.tiles_v_cols = ceil_div(p, kAdjTile);
+            a.tiles_t = ceil_div(kpad, kAdjTileT);
+            a.tiles_u_cols = ceil_div(m, kAdjTileX);
+            a.tiles_v_cols = ceil_div(p, kAdjTileX);
             a.dMA = dMA; a.dSA = dSA; a.dMB = dMB; a.dSB = dSB;
             const int64_t tiles = a.tiles_t * (a.tiles_u_cols + a.tiles_v_cols);
             {

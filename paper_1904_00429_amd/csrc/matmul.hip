@@ -27,6 +27,8 @@
 #include <math.h>
 #include <stdlib.h>
 
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace mlmc {
@@ -194,9 +196,23 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
     const uint32_t n = (uint32_t)Pp->n;
     const uint32_t sid_problem = Pp->sid_problem;
     const int64_t rows_prefix = Pp->rows_prefix;
-    const LawEval<Compute> LA = LawEval<Compute>::make(Pp->A);
-    const LawEval<Compute> LB = LawEval<Compute>::make(Pp->B);
-    const float pre_a = Pp->pre_a, pre_b = Pp->pre_b;
+    constexpr bool kFp8 = sizeof(Store) == 1;
+    LawEval<Compute> LA = LawEval<Compute>::make(Pp->A);
+    LawEval<Compute> LB = LawEval<Compute>::make(Pp->B);
+    float pre_a = Pp->pre_a, pre_b = Pp->pre_b;
+    if constexpr (kFp8) {
+        // the power-of-two operand pre-scales fold exactly into the law
+        // constants (i.i.d. laws only in FP8)
+        LA.mul *= pre_a; LA.add *= pre_a;
+        LB.mul *= pre_b; LB.add *= pre_b;
+        pre_a = pre_b = 1.0f;
+    }
+    // FP8 values stay FP32 (saturated to +-448) until they are packed in pairs
+    using Val = typename std::conditional<kFp8, float, Store>::type;
+    auto to_val = [](Compute v, float pre) -> Val {
+        if constexpr (kFp8) return __builtin_amdgcn_fmed3f((float)v, 448.0f, -448.0f);
+        else return StoreOf<Store>::from(v, pre);
+    };
     const int64_t pos_base = (int64_t)blockIdx.x * kGatherPositions * prm.octets;
     const int64_t slot = blockIdx.y;
     const uint32_t k = prm.k_first + (uint32_t)slot;
@@ -221,13 +237,13 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
     auto generate = [&](uint32_t oc, int64_t q, const uint32_t* jv, const bool* ok) {
         const int64_t pos0 = pos_base + (int64_t)oc * kGatherPositions;
         const int npos = (int)((prm.kpad - pos0) < kGatherPositions ? (prm.kpad - pos0) : kGatherPositions);
-        Store vals[kGatherPositions][4];
+        Val vals[kGatherPositions][4];
         const int64_t e0 = 4 * q;
 #pragma unroll
         for (int ip = 0; ip < kGatherPositions; ++ip) {
             if (!ok[ip]) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) vals[ip][r] = StoreOf<Store>::from((Compute)0, 1.0f);
+                for (int r = 0; r < 4; ++r) vals[ip][r] = to_val((Compute)0, 1.0f);
                 continue;
             }
             const uint32_t j = jv[ip];
@@ -237,11 +253,11 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
             if (e0 + 3 < m) {            // the whole quad is in A's column
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    vals[ip][r] = StoreOf<Store>::from(LA.template eval<LAWS>(z[r], u[r], (int64_t)j * LA.ld + e0 + r), pre_a);
+                    vals[ip][r] = to_val(LA.template eval<LAWS>(z[r], u[r], (int64_t)j * LA.ld + e0 + r), pre_a);
             } else if (e0 >= m) {        // the whole quad is in B's row
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    vals[ip][r] = StoreOf<Store>::from(LB.template eval<LAWS>(z[r], u[r], (int64_t)j * LB.ld + (e0 + r - m)), pre_b);
+                    vals[ip][r] = to_val(LB.template eval<LAWS>(z[r], u[r], (int64_t)j * LB.ld + (e0 + r - m)), pre_b);
             } else {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -255,7 +271,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
                         v = LB.template eval<LAWS>(z[r], u[r], (int64_t)j * LB.ld + (e - m));
                         pre = pre_b;
                     }
-                    vals[ip][r] = StoreOf<Store>::from(v, pre);
+                    vals[ip][r] = to_val(v, pre);
                 }
             }
         }
@@ -270,6 +286,15 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
 #pragma unroll
                 for (int ip = 0; ip < kGatherPositions; ++ip)
                     if (ip < npos) G[(pos0 + ip) * R + row] = vals[ip][r];
+            } else if constexpr (kFp8) {
+                // positions pos0 .. pos0+7 are one packed group of 8 draws:
+                // OCP e4m3, round to nearest even, two values per conversion
+                uint2 vv;
+                int w = __builtin_amdgcn_cvt_pk_fp8_f32(vals[0][r], vals[1][r], 0, false);
+                vv.x = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(vals[2][r], vals[3][r], w, true);
+                w = __builtin_amdgcn_cvt_pk_fp8_f32(vals[4][r], vals[5][r], 0, false);
+                vv.y = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(vals[6][r], vals[7][r], w, true);
+                *reinterpret_cast<uint2*>(G + ((pos0 / KPACK) * R + row) * KPACK) = vv;
             } else {
                 // positions pos0 .. pos0+7 are one packed group of 8 draws
                 typedef Store vec_t __attribute__((ext_vector_type(KPACK)));
