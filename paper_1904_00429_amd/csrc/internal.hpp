@@ -106,7 +106,7 @@ struct MatmulPlan {
     int64_t kpad_max;
     int64_t sum_rows, sum_mp, sum_merge_blocks, total_tiles, max_mp, max_merge_blocks;
     int64_t groups_max, gather_bytes, state_doubles;
-    size_t off_means, off_between, off_within, off_var, off_desc, off_tile_owner, off_gather,
+    size_t off_means, off_between, off_within, off_tile_acc, off_var, off_desc, off_tile_owner, off_gather,
         off_part_mean, off_part_m2, total;
     std::vector<ProblemDesc> descs;
     std::vector<int32_t> tile_owner;

@@ -368,6 +368,11 @@ struct SketchParams {
     void* part_mean;             // groups x sum_mp, in the accumulation type
     double* part_m2;             // groups x total_tiles
     int64_t sum_mp;
+    // one group per pass: the epilogue merges straight into the level state
+    int fuse;
+    double done_before;          // realisations already in the level state
+    double* level_mean;          // sum_mp, this level's running means
+    double* tile_acc;            // total_tiles, this level's summed squared deviations per tile
 };
 
 // LDS fragment reads: the staged chunk keeps the global slab layout
@@ -643,9 +648,14 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
             __syncthreads();
         }
 
-        // group mean of every in-range entry, and the group's within sum of squares
+        // group mean of every in-range entry, and the group's within sum of
+        // squares.  With one group per pass (fuse) the group is merged here
+        // into the level's running mean (Chan, FP64: the merge kernel's
+        // arithmetic), its between-part added to the tile's slot.
         Acc* pm = static_cast<Acc*>(prm.part_mean) + group * prm.sum_mp + Pd.mp_prefix;
-        double sq_mean = 0.0;
+        double* mu_row = prm.level_mean + Pd.mp_prefix;
+        const double na = prm.done_before, nb = (double)count, nn = na + nb;
+        double sq_mean = 0.0, between = 0.0;
         int e = 0;
 #pragma unroll
         for (int bi = 0; bi < NBR; ++bi)
@@ -656,25 +666,37 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
                     const int i = trow + wrow + bi * P::BLK + P::row_of(lane, r);
                     const int j = tcol + wcol + bj * P::BLK + P::col_of(lane);
                     if (i < m && j < p) {
+                        Acc gm;
                         if constexpr (SHIFTED) {
                             const double s1 = (double)run[e];
                             sq_mean += s1 * s1;
-                            pm[(int64_t)i * p + j] = (Acc)(scale64 * ((double)shift + s1 / (double)count));
+                            gm = (Acc)(scale64 * ((double)shift + s1 / (double)count));
                         } else {
-                            pm[(int64_t)i * p + j] = run[e];
+                            gm = run[e];
+                        }
+                        const int64_t idx = (int64_t)i * p + j;
+                        if (prm.fuse) {
+                            const double mu = mu_row[idx];
+                            const double delta = (double)gm - mu;
+                            mu_row[idx] = mu + delta * (nb / nn);
+                            between += delta * delta * (na * nb / nn);
+                        } else {
+                            pm[idx] = gm;
                         }
                     }
                 }
         // SHIFTED: sum (d - dbar)^2 = sum d^2 - sum_e s1_e^2 / count, in scale^2 units
         double m2_group = m2_sum;
         if constexpr (SHIFTED) m2_group = count > (Acc)0 ? scale64 * scale64 * (m2_sum - sq_mean / (double)count) : 0.0;
-        for (int off = kWave / 2; off > 0; off >>= 1) m2_group += __shfl_xor(m2_group, off, kWave);
-        if (lane == 0) red[wave] = m2_group;
+        double tile_sum = m2_group + between;
+        for (int off = kWave / 2; off > 0; off >>= 1) tile_sum += __shfl_xor(tile_sum, off, kWave);
+        if (lane == 0) red[wave] = tile_sum;
         __syncthreads();
         if (threadIdx.x == 0) {
             double tot = 0.0;
             for (int w = 0; w < THREADS / kWave; ++w) tot += red[w];
-            prm.part_m2[group * prm.total_tiles + tt] = tot;
+            if (prm.fuse) prm.tile_acc[tt] += tot;
+            else prm.part_m2[group * prm.total_tiles + tt] = tot;
         }
         __syncthreads();
     }
@@ -755,6 +777,8 @@ struct FinalizeParams {
     const double* means;
     const double* between;       // levels x sum_merge_blocks
     const double* within;        // levels x nprob
+    const double* tile_acc;      // levels x total_tiles (passes merged by the sketch)
+    int64_t total_tiles;
     double* var;                 // levels x nprob
 };
 
@@ -767,6 +791,8 @@ __global__ __launch_bounds__(kMergeThreads) void level_var_kernel(FinalizeParams
     const double* bt = prm.between + l * prm.sum_merge_blocks + Pd.between_prefix;
     double s = 0.0;
     for (int64_t b = threadIdx.x; b < Pd.merge_blocks; b += kMergeThreads) s += bt[b];
+    const double* ta = prm.tile_acc + l * prm.total_tiles + Pd.tile_first;
+    for (int64_t t = threadIdx.x; t < Pd.tiles; t += kMergeThreads) s += ta[t];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int half = kMergeThreads / 2; half > 0; half >>= 1) {
@@ -939,6 +965,7 @@ bool matmul_plan(const MatmulProblem* probs, int nprob, int prec, int num_levels
     plan.off_means = off;      off = align(off + sizeof(double) * L1 * mp);
     plan.off_between = off;    off = align(off + sizeof(double) * L1 * mb);
     plan.off_within = off;     off = align(off + sizeof(double) * L1 * nprob);
+    plan.off_tile_acc = off;   off = align(off + sizeof(double) * L1 * tiles);
     plan.off_var = off;        off = align(off + sizeof(double) * L1 * nprob);
     plan.state_doubles = (int64_t)(off / sizeof(double));
     plan.off_desc = off;       off = align(off + sizeof(ProblemDesc) * nprob);
@@ -1042,6 +1069,10 @@ static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t
     s.part_mean = ws + plan.off_part_mean;
     s.part_m2 = reinterpret_cast<double*>(ws + plan.off_part_m2);
     s.sum_mp = plan.sum_mp;
+    s.fuse = groups == 1;
+    s.done_before = (double)done_before;
+    s.level_mean = reinterpret_cast<double*>(ws + plan.off_means) + lr.level * plan.sum_mp;
+    s.tile_acc = reinterpret_cast<double*>(ws + plan.off_tile_acc) + lr.level * plan.total_tiles;
     int64_t blocks = plan.total_tiles * groups;
     if (blocks > kSketchMaxBlocks) blocks = kSketchMaxBlocks;
     blocks = ceil_div(blocks, kXcds) * kXcds;
@@ -1060,6 +1091,7 @@ static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t
     err = hipGetLastError();
     if (err != hipSuccess) return err;
 
+    if (s.fuse) return hipSuccess;           // merged by the sketch epilogue
     MergeParams mg;
     mg.descs = descs;
     mg.level = lr.level;
@@ -1136,6 +1168,8 @@ hipError_t matmul_finalize(const MatmulPlan& plan, const int64_t* counts, char* 
     f.means = reinterpret_cast<const double*>(ws + plan.off_means);
     f.between = reinterpret_cast<const double*>(ws + plan.off_between);
     f.within = reinterpret_cast<const double*>(ws + plan.off_within);
+    f.tile_acc = reinterpret_cast<const double*>(ws + plan.off_tile_acc);
+    f.total_tiles = plan.total_tiles;
     f.var = reinterpret_cast<double*>(ws + plan.off_var);
     hipLaunchKernelGGL(level_var_kernel, dim3((unsigned)plan.num_levels, (unsigned)plan.nprob), dim3(kMergeThreads),
                        0, stream, f);

@@ -197,3 +197,13 @@ def test_batched_large_mean_ragged(orc, dev, prec, tile):
         tol = 1e-12 if prec == "fp64" else 1e-5
         assert rel_frob(Y, ref.Y) <= tol, (i, rel_frob(Y, ref.Y))
         np.testing.assert_allclose(V[:, i], ref.level_var, rtol=1e-10 if prec == "fp64" else 1e-4)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batched_one_group_per_pass(orc, dev, refs, prec):
+    """target_blocks = 1 leaves one realisation group per tile and pass, so
+    each pass is merged into the level state by the sketch epilogue itself."""
+    flush(f"batched one group per pass prec={prec}")
+    est = _batch(dev, prec, {"tile": 64, "target_blocks": 1})
+    V = est.run(level_var=True)
+    _check(est, V, refs, prec)
