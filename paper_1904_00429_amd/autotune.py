@@ -3,11 +3,12 @@
 Candidates: workgroup output tile (64 or 128) x sketch work items per pass
 (target_blocks) x bytes of gathered operands per pass (gather_budget: the
 larger budget means fewer, larger passes and fewer merges of the level
-state).  Each candidate runs one level-0 pass of the given batch on
-the GPU (warm-up, then timed with HIP events via torch on the current
-stream); the fastest is cached in a JSON file keyed by a signature of the
-batch (precision, ladder head, per-product shapes bucketed to powers of two),
-so later runs with a similar batch reuse it without timing."""
+state).  Each candidate runs the batch's whole ladder with a quarter of every
+level's realisations on the GPU (warm-up, then timed with HIP events via
+torch on the current stream); the fastest is cached in a JSON file keyed by
+a signature of the batch (precision, ladder head, per-product shapes bucketed
+to powers of two), so later runs with a similar batch reuse it without
+timing."""
 from __future__ import annotations
 
 import hashlib
@@ -60,8 +61,9 @@ def tune(problems: Sequence[BatchProblem], c: Sequence[int], n_samples: Sequence
     table = _load() if use_cache else {}
     if sig in table:
         return table[sig]["best"]
-    # time level 0 only, with its own realisation count (the dominant level)
-    probe_c, probe_n = [c[0]], [n_samples[0]]
+    # time the whole ladder with a quarter of every level's realisations (at
+    # least 2), so that every level's pass shape weighs in
+    probe_c, probe_n = list(c), [max(2, int(x) // 4) for x in n_samples]
     timings = []
     for cand in CANDIDATES:
         est = BatchedEstimate(problems, probe_c, probe_n, seed=0, prec=prec, tuning=cand, device=device)

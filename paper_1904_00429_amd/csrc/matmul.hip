@@ -9,18 +9,20 @@
 //      b_t = B^(k)[r_t, :] (value stream, keyed by the column j = r_t), in the
 //      operand precision, into a gathered buffer laid out for the MFMA
 //      fragments.  Draws t < c_{l-1} (the coarse segment) and the remaining
-//      draws (the fine segment) are each zero-padded to the contraction step.
+//      draws (the fine segment) are each zero-padded to the contraction step;
+//      the coarse draws' a_t are stored multiplied by 1 - c_l / c_{l-1}.
 //   2. sketch:  a persistent grid walks the (product, output tile, group of
-//      realisations) work items.  Per realisation the K loop runs over the
-//      coarse segment, scales the accumulator by 1 - c_l / c_{l-1}, then
-//      continues over the fine segment: the result times n / c_l is
+//      realisations) work items.  Per realisation the K loop sums
+//      w_t a_t b_t^T over all c_l draws (w_t = 1 - c_l / c_{l-1} for the
+//      coarse draws, 1 for the rest): the result times n / c_l is
 //      D_k = Z_l^(k) - Z_{l-1}^(k) (the coupled fine-minus-coarse sample of
-//      Alg. 1) without ever forming either sketch.  Each entry's Welford state
-//      over the group's realisations is kept in registers.
+//      Alg. 1) without ever forming either sketch.  Each entry's running
+//      statistic over the group's realisations is kept in registers.
 //   3. merge:   per entry, a fixed-order Chan merge of the group means into
 //      the level's running mean (FP64); the between-group part of the sum of
 //      squared deviations is reduced per block, the within-group parts are
-//      summed by one thread.  V_l = (within + between) / (N_l - 1).
+//      summed by one thread.  V_l = (within + between) / (N_l - 1).  With one
+//      group per tile the sketch's epilogue does this merge itself.
 // After the last level, `finalize` forms V_l and the telescoping sum
 // Y = sum_l Ybar_l (eq. (10)) of every product.
 #include <hip/hip_bf16.h>
@@ -145,6 +147,7 @@ struct GatherParams {
     int64_t kc, kpad;        // padded coarse length, padded total length
     int64_t batch;           // realisations in this pass
     int octets;              // groups of 8 positions per block (1 .. kGatherMaxOctets)
+    double omega;            // 1 - c_l / c_{l-1}: weight of the coarse draws, folded into a_t
     uint32_t key0, key1;
     uint32_t k_first;        // realisation of batch slot 0
     int elem;
@@ -233,6 +236,11 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
     const int64_t pass_rows = prm.batch * prm.kpad * (int64_t)prm.elem;
     Store* __restrict__ GA = reinterpret_cast<Store*>(prm.gbuf + pass_rows * rows_prefix) + slot * prm.kpad * m_pad;
     Store* __restrict__ GB = reinterpret_cast<Store*>(prm.gbuf + pass_rows * (rows_prefix + m_pad)) + slot * prm.kpad * p_pad;
+    // The coarse sketch's weight enters through the operand: a_t of a coarse
+    // draw (position < kc) is stored as omega a_t, so the sketch's K loop sums
+    // w_t a_t b_t^T directly (D = (n / c_l) sum_t w_t a_t b_t^T, w_t = omega
+    // for t < c_{l-1}, 1 otherwise).
+    const Compute omega = (Compute)prm.omega;
     // values of rows 4q .. 4q+3 at the 8 positions of group oc
     auto generate = [&](uint32_t oc, int64_t q, const uint32_t* jv, const bool* ok) {
         const int64_t pos0 = pos_base + (int64_t)oc * kGatherPositions;
@@ -247,13 +255,14 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
                 continue;
             }
             const uint32_t j = jv[ip];
+            const Compute wa = pos0 + ip < prm.kc ? omega : (Compute)1;
             const Words4 w = philox4x32_10((uint32_t)q, k, j, sid_value, prm.key0, prm.key1);
             Compute u[4], z[4];
             quad_values<Compute>(w, normal, u[0], u[1], u[2], u[3], z[0], z[1], z[2], z[3]);
             if (e0 + 3 < m) {            // the whole quad is in A's column
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    vals[ip][r] = to_val(LA.template eval<LAWS>(z[r], u[r], (int64_t)j * LA.ld + e0 + r), pre_a);
+                    vals[ip][r] = to_val(wa * LA.template eval<LAWS>(z[r], u[r], (int64_t)j * LA.ld + e0 + r), pre_a);
             } else if (e0 >= m) {        // the whole quad is in B's row
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
@@ -265,7 +274,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
                     Compute v = (Compute)0;
                     float pre = 1.0f;
                     if (e < m) {
-                        v = LA.template eval<LAWS>(z[r], u[r], (int64_t)j * LA.ld + e);
+                        v = wa * LA.template eval<LAWS>(z[r], u[r], (int64_t)j * LA.ld + e);
                         pre = pre_a;
                     } else if (e < rows) {
                         v = LB.template eval<LAWS>(z[r], u[r], (int64_t)j * LB.ld + (e - m));
@@ -362,7 +371,6 @@ struct SketchParams {
     int64_t kc, kpad;
     int64_t batch;               // realisations in this pass
     int elem;
-    double omega;                // 1 - c_l / c_{l-1} (unused at level 0: kc == 0)
     uint32_t c;                  // c_l
     const char* gbuf;
     void* part_mean;             // groups x sum_mp, in the accumulation type
@@ -466,7 +474,6 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
                         s_begin * prm.kpad * p_pad;
         const double scale64 = (double)Pd.n / (double)prm.c * Pd.post;
         const Acc scale = (Acc)scale64;
-        const Acc omega = (Acc)prm.omega;
         const int kc = (int)prm.kc;
         const int kpad = (int)prm.kpad;
         const int npos = (int)(s_end - s_begin) * kpad;     // positions of the group's stream
@@ -555,31 +562,49 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
 #pragma unroll
                 for (int bj = 0; bj < NBC; ++bj) acc[bi][bj] = P::mma(a[bi], b[bj], acc[bi][bj]);
         };
-        auto fold_coarse = [&]() {
-#pragma unroll
-            for (int bi = 0; bi < NBR; ++bi)
-#pragma unroll
-                for (int bj = 0; bj < NBC; ++bj)
-#pragma unroll
-                    for (int r = 0; r < P::REGS; ++r) acc[bi][bj][r] *= omega;
-        };
         // the realisation is complete: D = scale * acc enters the statistics
         auto realisation_done = [&]() {
             count += (Acc)1;
             Acc part = (Acc)0;
             int e = 0;
             if constexpr (SHIFTED) {
+                if (shift == (Acc)0) {           // levels l >= 1: E[D] = 0
 #pragma unroll
-                for (int bi = 0; bi < NBR; ++bi)
+                    for (int bi = 0; bi < NBR; ++bi)
 #pragma unroll
-                    for (int bj = 0; bj < NBC; ++bj)
+                        for (int bj = 0; bj < NBC; ++bj)
 #pragma unroll
-                        for (int r = 0; r < P::REGS; ++r, ++e) {
-                            const Acc d = ((inside >> e) & 1u) ? acc[bi][bj][r] - shift : (Acc)0;
-                            run[e] += d;
-                            part = fma(d, d, part);
-                            acc[bi][bj][r] = (Acc)0;
-                        }
+                            for (int r = 0; r < P::REGS; ++r, ++e) {
+                                const Acc d = acc[bi][bj][r];
+                                run[e] += d;
+                                part = fma(d, d, part);
+                                acc[bi][bj][r] = (Acc)0;
+                            }
+                } else if (!ragged) {
+#pragma unroll
+                    for (int bi = 0; bi < NBR; ++bi)
+#pragma unroll
+                        for (int bj = 0; bj < NBC; ++bj)
+#pragma unroll
+                            for (int r = 0; r < P::REGS; ++r, ++e) {
+                                const Acc d = acc[bi][bj][r] - shift;
+                                run[e] += d;
+                                part = fma(d, d, part);
+                                acc[bi][bj][r] = (Acc)0;
+                            }
+                } else {
+#pragma unroll
+                    for (int bi = 0; bi < NBR; ++bi)
+#pragma unroll
+                        for (int bj = 0; bj < NBC; ++bj)
+#pragma unroll
+                            for (int r = 0; r < P::REGS; ++r, ++e) {
+                                const Acc d = ((inside >> e) & 1u) ? acc[bi][bj][r] - shift : (Acc)0;
+                                run[e] += d;
+                                part = fma(d, d, part);
+                                acc[bi][bj][r] = (Acc)0;
+                            }
+                }
             } else {
                 const Acc inv = (Acc)1 / count;
 #pragma unroll
@@ -621,13 +646,9 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
             const In* LB = lds[buf][1];
             const int left = npos - c * KC;
             const int steps = (left < KC ? left : KC) / P::KSTEP;
-            // runs of steps that end at the chunk's end, the end of the coarse
-            // segment or the end of a realisation
+            // runs of steps that end at the chunk's end or the end of a realisation
             for (int st = 0; st < steps;) {
-                // end of the coarse segment: fold in the coarse sketch weight
-                if (o == kc && kc > 0) fold_coarse();
-                const int lim = kc > o ? kc : kpad;
-                int run_steps = (lim - o) / P::KSTEP;
+                int run_steps = (kpad - o) / P::KSTEP;
                 if (run_steps > steps - st) run_steps = steps - st;
                 for (int i = 0; i < run_steps; ++i) step(LA, LB, (st + i) * P::KSTEP);
                 st += run_steps;
@@ -1038,6 +1059,7 @@ static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t
                ceil_div(kpad, (int64_t)kGatherPositions * oct * 2) * batch * plan.nprob >= 8192)
             oct *= 2;
         g.octets = oct;
+        g.omega = lr.c_prev > 0 ? 1.0 - (double)lr.c / (double)lr.c_prev : 1.0;
         const dim3 grid((unsigned)ceil_div(kpad, (int64_t)kGatherPositions * oct), (unsigned)batch,
                         (unsigned)plan.nprob);
         if (plan.laws == kLawsNormal)
@@ -1063,7 +1085,6 @@ static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t
     s.kpad = kpad;
     s.batch = batch;
     s.elem = plan.elem;
-    s.omega = lr.c_prev > 0 ? 1.0 - (double)lr.c / (double)lr.c_prev : 1.0;
     s.c = (uint32_t)lr.c;
     s.gbuf = g.gbuf;
     s.part_mean = ws + plan.off_part_mean;
