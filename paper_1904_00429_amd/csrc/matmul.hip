@@ -568,19 +568,7 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
             Acc part = (Acc)0;
             int e = 0;
             if constexpr (SHIFTED) {
-                if (shift == (Acc)0) {           // levels l >= 1: E[D] = 0
-#pragma unroll
-                    for (int bi = 0; bi < NBR; ++bi)
-#pragma unroll
-                        for (int bj = 0; bj < NBC; ++bj)
-#pragma unroll
-                            for (int r = 0; r < P::REGS; ++r, ++e) {
-                                const Acc d = acc[bi][bj][r];
-                                run[e] += d;
-                                part = fma(d, d, part);
-                                acc[bi][bj][r] = (Acc)0;
-                            }
-                } else if (!ragged) {
+                if (!ragged) {
 #pragma unroll
                     for (int bi = 0; bi < NBR; ++bi)
 #pragma unroll
