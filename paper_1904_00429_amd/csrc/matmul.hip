@@ -428,8 +428,9 @@ struct SketchShape {
 
 // PF register sets (1 or 2) hold the global loads of the next PF chunks.
 // WPE: waves per SIMD the register allocation must leave room for.
-// SHIFTED: statistics by sums shifted by E[D] (i.i.d. laws), else Welford.
-template <typename P, int WR, int WC, int NBR, int NBC, int PF, int WPE, bool SHIFTED>
+// STATS: 0 Welford; 1 sums shifted by E[D] (i.i.d. laws); 2 the same for
+// products that fill whole tiles (no masking code).
+template <typename P, int WR, int WC, int NBR, int NBC, int PF, int WPE, int STATS>
 __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchParams prm)
 {
     using In = typename P::In;
@@ -522,11 +523,12 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
         for (int e = 0; e < NE; ++e) run[e] = (Acc)0;
         double m2_sum = 0.0;
         Acc count = (Acc)0;
+        constexpr bool SHIFTED = STATS != 0;
         const Acc shift = SHIFTED && kc == 0 ? (Acc)(Pd.mean0 / scale64) : (Acc)0;
         // with a non-zero shift, entries outside the product (ragged tiles only)
         // are masked: bit e of `inside` is set for an entry inside the product
         static_assert(NE <= 32, "one mask bit per entry");
-        const bool ragged = SHIFTED && shift != (Acc)0 && (trow + BM > m || tcol + BM > p);
+        const bool ragged = STATS == 1 && shift != (Acc)0 && (trow + BM > m || tcol + BM > p);
         uint32_t inside = 0xFFFFFFFFu;
         if (ragged) {
             inside = 0u;
@@ -903,8 +905,11 @@ bool matmul_plan(const MatmulProblem* probs, int nprob, int prec, int num_levels
         if (kpad > plan.kpad_max) plan.kpad_max = kpad;
     }
     plan.iid = true;
-    for (int i = 0; i < nprob; ++i)
+    plan.whole_tiles = true;
+    for (int i = 0; i < nprob; ++i) {
         if (probs[i].A.kind == 2 || probs[i].B.kind == 2) plan.iid = false;
+        if (probs[i].m % plan.tile != 0 || probs[i].p % plan.tile != 0) plan.whole_tiles = false;
+    }
     plan.descs.resize(nprob);
     plan.tile_owner.clear();
     int64_t rows = 0, mp = 0, mb = 0, tiles = 0;
@@ -1087,15 +1092,19 @@ static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t
     blocks = ceil_div(blocks, kXcds) * kXcds;
     {
         ScopedTiming t(timer, 0);
-        // shifted sums for i.i.d. laws, except where their extra live values
-        // spill in the 4 x 2-wave BF16/FP32 kernels (measured slower there)
+        // shifted sums for i.i.d. laws (the mask-free form when every product
+        // fills whole tiles), except in the 4 x 2-wave BF16/FP32 kernels,
+        // where their extra live values spill (measured slower than Welford)
         constexpr bool kShiftedFits = !(WR == 4 && sizeof(typename P::In) >= 2);
-        if (plan.iid && kShiftedFits)
-            hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, WPE, kShiftedFits>), dim3((unsigned)blocks),
-                               dim3(kWave * WR * WC), 0, stream, s);
+        const dim3 grid((unsigned)blocks), block(kWave * WR * WC);
+        if (plan.iid && kShiftedFits && plan.whole_tiles)
+            hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, WPE, kShiftedFits ? 2 : 0>), grid, block, 0,
+                               stream, s);
+        else if (plan.iid && kShiftedFits)
+            hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, WPE, kShiftedFits ? 1 : 0>), grid, block, 0,
+                               stream, s);
         else
-            hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, WPE, false>), dim3((unsigned)blocks),
-                               dim3(kWave * WR * WC), 0, stream, s);
+            hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, WPE, 0>), grid, block, 0, stream, s);
     }
     err = hipGetLastError();
     if (err != hipSuccess) return err;
