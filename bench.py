@@ -210,7 +210,9 @@ def main():
         achieved = flops / (k_ms[0] * 1e-3)
         roof = {"bound": "mfma", "kernel": f"sketch_kernel<{prec}>", "achieved": achieved / 1e12,
                 "peak": PEAK_MFMA[prec] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_MFMA[prec],
-                "traffic": None, "avg_launch_ms": k_ms[0] / max(k_n[0], 1), "launches": k_n[0],
+                "traffic": measured_traffic(f"sketch_kernel<{prec}>") if wl is workloads.MATMUL_LARGE else None,
+                "traffic_unit": "bytes per launch",
+                "avg_launch_ms": k_ms[0] / max(k_n[0], 1), "launches": k_n[0],
                 "gather_ms_per_step": k_ms[1] / args.steps, "sketch_ms_per_step": k_ms[0] / args.steps,
                 "merge_ms_per_step": k_ms[2] / args.steps}
         config = {"workload": wl.name, "m": wl.m, "n": wl.n, "p": wl.p, "levels": len(wl.c), "c0": wl.c[0],
