@@ -104,6 +104,7 @@ struct MatmulPlan {
     int laws;                  // law pair shared by every product (kLaws*), else kLawsAny
     bool iid;                  // no product has a reparameterised law
     bool whole_tiles;          // every m and p is a multiple of the workgroup tile
+    int64_t min_rows;          // smallest m + p over the products
     int64_t kpad_max;
     int64_t sum_rows, sum_mp, sum_merge_blocks, total_tiles, max_mp, max_merge_blocks;
     int64_t groups_max, gather_bytes, state_doubles;

@@ -190,7 +190,6 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
 {
     constexpr int MAXPOS = kGatherPositions * kGatherMaxOctets;
     __shared__ uint32_t cols[MAXPOS];
-    __shared__ int valid[MAXPOS];
     // the product's description is copied to registers once: the stores into
     // the gathered buffer below could otherwise alias it and force reloads
     const ProblemDesc* Pp = prm.descs + blockIdx.z;
@@ -224,10 +223,11 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
     const int npos_block = (int)((prm.kpad - pos_base) < kGatherPositions * prm.octets ? (prm.kpad - pos_base)
                                                                                      : kGatherPositions * prm.octets);
     const int octets = (npos_block + kGatherPositions - 1) / kGatherPositions;
+    // column of each position, or kNoDraw for padding
+    constexpr uint32_t kNoDraw = 0xFFFFFFFFu;
     for (int i = threadIdx.x; i < npos_block; i += kGatherThreads) {
         const int64_t t = draw_of_position(pos_base + i, prm.kc, prm.c, prm.c_prev);
-        valid[i] = t >= 0;
-        cols[i] = t >= 0 ? draw_index((uint32_t)t, k, sid_index, prm.key0, prm.key1, n) : 0u;
+        cols[i] = t >= 0 ? draw_index((uint32_t)t, k, sid_index, prm.key0, prm.key1, n) : kNoDraw;
     }
     __syncthreads();
     const int64_t rows = m + p;
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
 #pragma unroll
         for (int ip = 0; ip < kGatherPositions; ++ip) {
             jv[ip] = cols[ip];
-            ok[ip] = ip < npos_block && valid[ip];
+            ok[ip] = ip < npos_block && jv[ip] != kNoDraw;
         }
         for (int64_t q = threadIdx.x; q < (int64_t)quads; q += kGatherThreads) generate(0u, q, jv, ok);
     } else {
@@ -332,7 +332,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
 #pragma unroll
             for (int ip = 0; ip < kGatherPositions; ++ip) {
                 jv[ip] = cols[oc * kGatherPositions + ip];
-                ok[ip] = ip < npos && valid[oc * kGatherPositions + ip];
+                ok[ip] = ip < npos && jv[ip] != kNoDraw;
             }
             generate(oc, (int64_t)(it - oc * quads), jv, ok);
         }
@@ -906,6 +906,9 @@ bool matmul_plan(const MatmulProblem* probs, int nprob, int prec, int num_levels
     }
     plan.iid = true;
     plan.whole_tiles = true;
+    plan.min_rows = probs[0].m + probs[0].p;
+    for (int i = 1; i < nprob; ++i)
+        if (probs[i].m + probs[i].p < plan.min_rows) plan.min_rows = probs[i].m + probs[i].p;
     for (int i = 0; i < nprob; ++i) {
         if (probs[i].A.kind == 2 || probs[i].B.kind == 2) plan.iid = false;
         if (probs[i].m % plan.tile != 0 || probs[i].p % plan.tile != 0) plan.whole_tiles = false;
@@ -1045,10 +1048,11 @@ static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t
     g.gbuf = ws + plan.off_gather;
     {
         ScopedTiming t(timer, 1);
-        // more position groups per block while the grid still holds at least
-        // 8192 blocks (eight waves per SIMD)
+        // more position groups per block (lanes over (group, quad) items) when
+        // some product has fewer than 1024 rows, while the grid still holds at
+        // least 8192 blocks (eight waves per SIMD)
         int oct = 1;
-        while (oct < kGatherMaxOctets &&
+        while (plan.min_rows < 1024 && oct < kGatherMaxOctets &&
                ceil_div(kpad, (int64_t)kGatherPositions * oct * 2) * batch * plan.nprob >= 8192)
             oct *= 2;
         g.octets = oct;
