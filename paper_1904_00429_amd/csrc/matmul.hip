@@ -46,6 +46,7 @@ constexpr int kGatherMaxOctets = 8;           // position groups per gather bloc
 constexpr int64_t kGatherBudgetBytes = 768ll << 20;
 constexpr int64_t kSketchMaxBlocks = 8192;
 constexpr int kXcds = 8;                     // accelerator complex dies of an MI355X
+constexpr int64_t kDualMaxDraws = 32;        // realisations this short use the two-accumulator statistics
 
 // ---------------------------------------------------------------------------
 // Contraction policies: operand type, MFMA shape, fragment layout.  A
@@ -429,7 +430,9 @@ struct SketchShape {
 // PF register sets (1 or 2) hold the global loads of the next PF chunks.
 // WPE: waves per SIMD the register allocation must leave room for.
 // STATS: 0 Welford; 1 sums shifted by E[D] (i.i.d. laws); 2 the same for
-// products that fill whole tiles (no masking code).
+// products that fill whole tiles (no masking code); 3 (whole tiles, short
+// realisations) a second accumulator collects every realisation's sum
+// through the same MFMAs, so a realisation costs one fma per entry.
 template <typename P, int WR, int WC, int NBR, int NBC, int PF, int WPE, int STATS>
 __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchParams prm)
 {
@@ -518,9 +521,19 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
         // one FP64 sum (only the sum over entries enters V_l).  Entries
         // outside the product see zero-padded operand rows: D = 0 there, and
         // the shift is not applied to them.
-        Acc run[NE];
+        constexpr bool DUAL = STATS == 3;
+        Acc run[DUAL ? 1 : NE];
 #pragma unroll
-        for (int e = 0; e < NE; ++e) run[e] = (Acc)0;
+        for (int e = 0; e < (DUAL ? 1 : NE); ++e) run[e] = (Acc)0;
+        typename P::AccVec tot[DUAL ? NBR : 1][DUAL ? NBC : 1];
+        if constexpr (DUAL) {
+#pragma unroll
+            for (int bi = 0; bi < NBR; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < NBC; ++bj)
+#pragma unroll
+                    for (int r = 0; r < P::REGS; ++r) tot[bi][bj][r] = (Acc)0;
+        }
         double m2_sum = 0.0;
         Acc count = (Acc)0;
         constexpr bool SHIFTED = STATS != 0;
@@ -562,14 +575,28 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
 #pragma unroll
             for (int bi = 0; bi < NBR; ++bi)
 #pragma unroll
-                for (int bj = 0; bj < NBC; ++bj) acc[bi][bj] = P::mma(a[bi], b[bj], acc[bi][bj]);
+                for (int bj = 0; bj < NBC; ++bj) {
+                    acc[bi][bj] = P::mma(a[bi], b[bj], acc[bi][bj]);
+                    if constexpr (DUAL) tot[bi][bj] = P::mma(a[bi], b[bj], tot[bi][bj]);
+                }
         };
         // the realisation is complete: D = scale * acc enters the statistics
         auto realisation_done = [&]() {
             count += (Acc)1;
             Acc part = (Acc)0;
             int e = 0;
-            if constexpr (SHIFTED) {
+            if constexpr (DUAL) {
+#pragma unroll
+                for (int bi = 0; bi < NBR; ++bi)
+#pragma unroll
+                    for (int bj = 0; bj < NBC; ++bj)
+#pragma unroll
+                        for (int r = 0; r < P::REGS; ++r) {
+                            const Acc d = acc[bi][bj][r] - shift;
+                            part = fma(d, d, part);
+                            acc[bi][bj][r] = (Acc)0;
+                        }
+            } else if constexpr (SHIFTED) {
                 if (!ragged) {
 #pragma unroll
                     for (int bi = 0; bi < NBR; ++bi)
@@ -679,7 +706,10 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
                     if (i < m && j < p) {
                         Acc gm;
                         if constexpr (SHIFTED) {
-                            const double s1 = (double)run[e];
+                            // DUAL: the running total minus count shifts
+                            double s1;
+                            if constexpr (DUAL) s1 = (double)tot[bi][bj][r] - (double)count * (double)shift;
+                            else s1 = (double)run[e];
                             sq_mean += s1 * s1;
                             gm = (Acc)(scale64 * ((double)shift + s1 / (double)count));
                         } else {
@@ -1100,8 +1130,12 @@ static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t
         // fills whole tiles), except in the 4 x 2-wave BF16/FP32 kernels,
         // where their extra live values spill (measured slower than Welford)
         constexpr bool kShiftedFits = !(WR == 4 && sizeof(typename P::In) >= 2);
+        constexpr bool kDualForm = sizeof(typename P::In) <= 2;   // BF16, FP8: FP32 totals suffice
         const dim3 grid((unsigned)blocks), block(kWave * WR * WC);
-        if (plan.iid && kShiftedFits && plan.whole_tiles)
+        if (plan.iid && plan.whole_tiles && kDualForm && lr.c <= kDualMaxDraws)
+            hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, WPE, kDualForm ? 3 : 0>), grid, block, 0,
+                               stream, s);
+        else if (plan.iid && kShiftedFits && plan.whole_tiles)
             hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, WPE, kShiftedFits ? 2 : 0>), grid, block, 0,
                                stream, s);
         else if (plan.iid && kShiftedFits)
