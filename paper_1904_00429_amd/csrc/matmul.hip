@@ -540,11 +540,11 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
         const Acc shift = SHIFTED && kc == 0 ? (Acc)(Pd.mean0 / scale64) : (Acc)0;
         // with a non-zero shift, entries outside the product (ragged tiles only)
         // are masked: bit e of `inside` is set for an entry inside the product
-        static_assert(NE <= 32, "one mask bit per entry");
+        static_assert(NE <= 64, "one mask bit per entry");
         const bool ragged = STATS == 1 && shift != (Acc)0 && (trow + BM > m || tcol + BM > p);
-        uint32_t inside = 0xFFFFFFFFu;
+        uint64_t inside = ~0ull;
         if (ragged) {
-            inside = 0u;
+            inside = 0ull;
             int e = 0;
 #pragma unroll
             for (int bi = 0; bi < NBR; ++bi)
@@ -554,7 +554,7 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
                     for (int r = 0; r < P::REGS; ++r, ++e) {
                         const int i = trow + wrow + bi * P::BLK + P::row_of(lane, r);
                         const int j = tcol + wcol + bj * P::BLK + P::col_of(lane);
-                        if (i < m && j < p) inside |= 1u << e;
+                        if (i < m && j < p) inside |= 1ull << e;
                     }
         }
         typename P::AccVec acc[NBR][NBC];
@@ -616,7 +616,7 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
                         for (int bj = 0; bj < NBC; ++bj)
 #pragma unroll
                             for (int r = 0; r < P::REGS; ++r, ++e) {
-                                const Acc d = ((inside >> e) & 1u) ? acc[bi][bj][r] - shift : (Acc)0;
+                                const Acc d = ((inside >> e) & 1ull) ? acc[bi][bj][r] - shift : (Acc)0;
                                 run[e] += d;
                                 part = fma(d, d, part);
                                 acc[bi][bj][r] = (Acc)0;
@@ -1128,8 +1128,10 @@ static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t
         ScopedTiming t(timer, 0);
         // shifted sums for i.i.d. laws (the mask-free form when every product
         // fills whole tiles), except in the 4 x 2-wave BF16/FP32 kernels,
-        // where their extra live values spill (measured slower than Welford)
+        // where their extra live values spill (measured slower than Welford);
+        // the masked form only where a lane holds at most 32 entries
         constexpr bool kShiftedFits = !(WR == 4 && sizeof(typename P::In) >= 2);
+        constexpr bool kMaskedFits = kShiftedFits && NBR * NBC * P::REGS <= 32;
         constexpr bool kDualForm = sizeof(typename P::In) <= 2;   // BF16, FP8: FP32 totals suffice
         const dim3 grid((unsigned)blocks), block(kWave * WR * WC);
         if (plan.iid && plan.whole_tiles && kDualForm && lr.c <= kDualMaxDraws)
@@ -1138,8 +1140,8 @@ static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t
         else if (plan.iid && kShiftedFits && plan.whole_tiles)
             hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, WPE, kShiftedFits ? 2 : 0>), grid, block, 0,
                                stream, s);
-        else if (plan.iid && kShiftedFits)
-            hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, WPE, kShiftedFits ? 1 : 0>), grid, block, 0,
+        else if (plan.iid && kMaskedFits)
+            hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, WPE, kMaskedFits ? 1 : 0>), grid, block, 0,
                                stream, s);
         else
             hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, WPE, 0>), grid, block, 0, stream, s);
@@ -1176,12 +1178,19 @@ static hipError_t run_pass_nb(const MatmulPlan& plan, const LevelRange& lr, int6
                               int64_t done_before, int64_t kc, int64_t kpad, const StreamKeys& keys, char* ws,
                               hipStream_t stream, KernelTimer* timer)
 {
-    // tile 64: 2 x 2 waves of 32 x 32; tile 128: 4 x 2 waves of 32 x 64
+    // tile 64: 2 x 2 waves of 32 x 32.  Tile 128: BF16/FP32 2 x 2 waves of
+    // 64 x 64 (two waves per SIMD, fewer LDS fragment reads per MFMA), FP8
+    // 4 x 2 waves of 32 x 64 (four waves per SIMD; measured faster on the
+    // small products of batches)
     if (plan.tile == 64)
         return run_pass<P, Compute, 2, 2, 1, 1, 2, 4>(plan, lr, k_first, batch, done_before, kc, kpad, keys, ws, stream,
                                                    timer);
-    return run_pass<P, Compute, 4, 2, 1, 2, 1, 4>(plan, lr, k_first, batch, done_before, kc, kpad, keys, ws, stream,
-                                               timer);
+    if constexpr (sizeof(typename P::In) >= 2)
+        return run_pass<P, Compute, 2, 2, 2, 2, 1, 2>(plan, lr, k_first, batch, done_before, kc, kpad, keys, ws, stream,
+                                                   timer);
+    else
+        return run_pass<P, Compute, 4, 2, 1, 2, 1, 4>(plan, lr, k_first, batch, done_before, kc, kpad, keys, ws, stream,
+                                                   timer);
 }
 
 hipError_t matmul_level_run(const MatmulPlan& plan, const LevelRange& lr, int64_t done_before, const StreamKeys& keys,
