@@ -15,7 +15,7 @@
 // to fill the chip.  Inside a level, a group of G lanes (a power of two, up to
 // the whole 256-lane workgroup) owns one realisation at a time; its lanes take
 // draw pairs (2q, 2q+1), which share one Philox call of the index stream.  G
-// is chosen so every lane gets at least four pairs, which amortises the
+// is chosen so every lane gets at least eight pairs, which amortises the
 // per-realisation reduction (a butterfly of cross-lane shuffles, plus an LDS
 // step when the group spans several waves).
 //
@@ -32,7 +32,7 @@ namespace mlmc {
 
 constexpr int kInnerBlock = 256;
 constexpr int kInnerMaxBlocks = 8192;
-constexpr int64_t kInnerTargetBlocks = 4096;
+constexpr int64_t kInnerTargetBlocks = 8192;
 constexpr int64_t kInnerMinPairsPerBlock = 2048;
 
 struct InnerLevel {
@@ -246,12 +246,12 @@ __global__ void inner_telescope_kernel(const Moments* level_state, int num_level
 
 size_t inner_partials_capacity() { return kInnerMaxBlocks; }
 
-// Lanes per realisation: at least four draw pairs per lane, at most a workgroup.
+// Lanes per realisation: at least eight draw pairs per lane, at most a workgroup.
 static uint32_t lanes_log2_for(int64_t c)
 {
     const int64_t pairs = (c + 1) / 2;
     uint32_t g = 0;
-    while (g < 8 && (int64_t(4) << (g + 1)) <= pairs) ++g;
+    while (g < 8 && (int64_t(8) << (g + 1)) <= pairs) ++g;
     return g;
 }
 
