@@ -57,6 +57,10 @@ class _Law(ctypes.Structure):
                 ("stdev", ctypes.c_void_p), ("ld", ctypes.c_int64)]
 
 
+class _Func(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("theta0", ctypes.c_double), ("theta1", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -87,8 +91,10 @@ def lib():
         L.orc_level_estimation.argtypes = (
             [ctypes.c_int64] * 3 + [ctypes.POINTER(_Law)] * 2 + [ctypes.c_int64] * 2
             + [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64,
-               ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-               ctypes.c_void_p])
+               ctypes.c_int64, ctypes.POINTER(_Func), ctypes.c_void_p, ctypes.c_void_p,
+               ctypes.c_void_p, ctypes.c_void_p])
+        L.orc_apply_func.restype = ctypes.c_double
+        L.orc_apply_func.argtypes = [ctypes.POINTER(_Func), ctypes.c_double]
         L.orc_level_entries.argtypes = (
             [ctypes.c_int64] * 3 + [ctypes.POINTER(_Law)] * 2 + [ctypes.c_int64] * 2
             + [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64,
@@ -143,6 +149,41 @@ class Law:
             s.stdev = _ptr(self.stdev)
             s.ld = self.ld
         return s
+
+
+# --------------------------------------------------------------------------
+# Target function f of Sec. 3 (entrywise on every sketch)
+# --------------------------------------------------------------------------
+F_IDENTITY, F_ABS_STEP, F_INV_ABS_STEP = 0, 1, 2
+
+
+@dataclass
+class Func:
+    """f(x) = x (identity); |x| H(theta0 - x) (abs_step, Sec. 4.2 with
+    theta0 = 2); 1 / (|x| H(x + theta0) + theta1) (inv_abs_step, Sec. 4.1 with
+    theta0 = 0.4, theta1 = 0.01).  H(0) = 1."""
+    kind: int = F_IDENTITY
+    theta0: float = 0.0
+    theta1: float = 0.0
+
+    @staticmethod
+    def abs_step(theta0: float = 2.0) -> "Func":
+        return Func(F_ABS_STEP, float(theta0), 0.0)
+
+    @staticmethod
+    def inv_abs_step(theta0: float = 0.4, theta1: float = 0.01) -> "Func":
+        return Func(F_INV_ABS_STEP, float(theta0), float(theta1))
+
+    def c(self) -> _Func:
+        s = _Func()
+        s.kind = self.kind
+        s.theta0 = self.theta0
+        s.theta1 = self.theta1
+        return s
+
+    def __call__(self, x: float) -> float:
+        fc = self.c()
+        return float(lib().orc_apply_func(ctypes.byref(fc), float(x)))
 
 
 # --------------------------------------------------------------------------
@@ -225,15 +266,18 @@ class LevelState:
 
 def level_estimation(state: LevelState, m: int, n: int, p: int, A: Law, B: Law,
                      c_l: int, c_prev: int, seed: int, problem: int, lfield: int,
-                     k_begin: int, k_end: int, want_samples: bool = False):
-    """Alg. 1 for realisations [k_begin, k_end), continuing `state` in place."""
+                     k_begin: int, k_end: int, want_samples: bool = False,
+                     func: Optional[Func] = None):
+    """Alg. 1 for realisations [k_begin, k_end), continuing `state` in place;
+    level samples f(Zf) - f(Zc) (identity when func is None)."""
     cnt = ctypes.c_int64(state.count)
     samples = np.empty((max(k_end - k_begin, 0), m, p)) if want_samples else None
     la, lb = A.c(), B.c()
+    fc = (func or Func()).c()
     rc = lib().orc_level_estimation(
         int(m), int(n), int(p), ctypes.byref(la), ctypes.byref(lb), int(c_l), int(c_prev),
-        int(seed), int(problem), int(lfield), int(k_begin), int(k_end), ctypes.byref(cnt),
-        _ptr(state.mean), _ptr(state.m2), _ptr(samples) if want_samples else None)
+        int(seed), int(problem), int(lfield), int(k_begin), int(k_end), ctypes.byref(fc),
+        ctypes.byref(cnt), _ptr(state.mean), _ptr(state.m2), _ptr(samples) if want_samples else None)
     if rc != 0:
         raise ValueError("orc_level_estimation rejected its arguments")
     state.count = cnt.value
@@ -275,8 +319,9 @@ class Estimate:
 def estimate(m: int, n: int, p: int, A: Law, B: Law, c: Sequence[int],
              n_samples: Optional[Sequence[int]] = None, rmse_target: float = 0.0,
              pilot: int = 0, seed: int = 0, problem: int = 0, shared: bool = False,
-             max_total_draws: int = 0, pool=None) -> Estimate:
-    """MLMC estimate of E[AB] over the ladder c_0 < c_1 < ... < c_L.
+             max_total_draws: int = 0, pool=None, func: Optional[Func] = None) -> Estimate:
+    """MLMC estimate of E[f(AB)] (f entrywise, identity by default) over the
+    ladder c_0 < c_1 < ... < c_L.
 
     Fixed-N mode: n_samples gives N_l.  Target mode (rmse_target > 0): `pilot`
     realisations per level estimate V_l, eq. (28) gives N_l, and every level
@@ -288,7 +333,7 @@ def estimate(m: int, n: int, p: int, A: Law, B: Law, c: Sequence[int],
 
     def run(l, k0, k1):
         level_estimation(states[l], m, n, p, A, B, c[l], c[l - 1] if l > 0 else 0,
-                         seed, problem, level_field(l, shared), k0, k1)
+                         seed, problem, level_field(l, shared), k0, k1, func=func)
 
     def run_all(ranges):
         if pool is None:

@@ -8,13 +8,18 @@
  * HIP path and the product never links it: only the test suite, the smoke
  * check and the CPU-baseline leg of the benchmark load it.
  *
- * What it computes, step by step (f = identity, uniform probabilities):
+ * What it computes, step by step (uniform probabilities; f = identity unless
+ * a target function is given):
  *   - Sec. 2, eq. (4): index probabilities xi_j = 1/n, draws with replacement.
  *   - Sec. 3, eq. (18): the sketch Z = (n/c) sum_t A[:, r_t] B[r_t, :].
  *   - Sec. 3.1, Alg. 1 (level_estimation): for every realisation k a pair
  *     A^(k), B^(k) and c_l indices; the fine sketch uses all c_l indices, the
  *     coarse sketch uses c_{l-1} of the same indices, and the level sample is
  *     their difference (at level 0 the fine sketch alone).
+ *   - Sec. 3 and Alg. 1 with a target function f: both sketches are mapped
+ *     entrywise by f before the difference, D = f(Zf) - f(Zc) (f(Zf) at
+ *     level 0).  The functions are those of the experiments of Sec. 4 (see
+ *     orc_func below).
  *   - Sec. 2, eq. (9): the level estimator is the mean of the level samples;
  *     the per-level variance V_l (Remark 3.6) is the vectorised variance of a
  *     single level sample, i.e. the sum over entries of the entry variances.
@@ -64,6 +69,34 @@ typedef struct {
     const double* stdev;
     int64_t ld;
 } orc_law;
+
+/* Target function f of Sec. 3, applied entrywise to a sketch.
+ *   ORC_F_IDENTITY:     f(x) = x
+ *   ORC_F_ABS_STEP:     f(x) = |x| H(theta0 - x)              (Sec. 4.2: theta0 = 2)
+ *   ORC_F_INV_ABS_STEP: f(x) = 1 / (|x| H(x + theta0) + theta1)  (Sec. 4.1: 0.4, 0.01)
+ * H is the Heaviside step; the paper does not fix H(0), read here as H(0) = 1. */
+enum { ORC_F_IDENTITY = 0, ORC_F_ABS_STEP = 1, ORC_F_INV_ABS_STEP = 2 };
+
+typedef struct {
+    int32_t kind;
+    double theta0;
+    double theta1;
+} orc_func;
+
+static double heaviside(double x)
+{
+    return x >= 0.0 ? 1.0 : 0.0;
+}
+
+/* f(x); a NULL f is the identity. */
+double orc_apply_func(const orc_func* f, double x)
+{
+    if (!f || f->kind == ORC_F_IDENTITY)
+        return x;
+    if (f->kind == ORC_F_ABS_STEP)
+        return fabs(x) * heaviside(f->theta0 - x);
+    return 1.0 / (fabs(x) * heaviside(x + f->theta0) + f->theta1);
+}
 
 /* Philox4x32-10: ten rounds of the Philox S-box, the key bumped by the
  * Weyl constants between rounds (SC'11, Sec. 5). */
@@ -200,14 +233,15 @@ void orc_sketch_pair(int64_t m, int64_t p, int64_t n, int64_t c_f, int64_t c_c,
 }
 
 /* Alg. 1 (level_estimation) for realisations k_begin <= k < k_end of one
- * level, f = identity.  Level sample D = Zf - Zc (l > 0) or Zf (l = 0,
- * c_prev == 0).  Per entry, Welford's running mean/M2 are updated in place, so
+ * level.  Level sample D = f(Zf) - f(Zc) (l > 0) or f(Zf) (l = 0,
+ * c_prev == 0), f entrywise (NULL: identity).  Per entry, Welford's running
+ * mean/M2 are updated in place, so
  * a call can continue the samples of an earlier call (Alg. 2 reuses earlier
  * evaluations).  samples_out (nullable) receives every D, row-major.
  * Returns 0, or -1 on bad arguments / allocation failure. */
 int orc_level_estimation(int64_t m, int64_t n, int64_t p, const orc_law* A, const orc_law* B,
                          int64_t c_l, int64_t c_prev, uint64_t seed, uint32_t problem,
-                         uint32_t level_field, int64_t k_begin, int64_t k_end,
+                         uint32_t level_field, int64_t k_begin, int64_t k_end, const orc_func* f,
                          int64_t* count, double* mean, double* m2, double* samples_out)
 {
     if (m < 1 || p < 1 || n < 1 || c_l < 1 || c_prev < 0 || c_prev > c_l || k_end < k_begin)
@@ -233,7 +267,8 @@ int orc_level_estimation(int64_t m, int64_t n, int64_t p, const orc_law* A, cons
         *count += 1;
         double cnt = (double)(*count);
         for (int64_t e = 0; e < mp; ++e) {
-            double d = (c_prev > 0) ? Zf[e] - Zc[e] : Zf[e];
+            double d = (c_prev > 0) ? orc_apply_func(f, Zf[e]) - orc_apply_func(f, Zc[e])
+                                    : orc_apply_func(f, Zf[e]);
             if (samples_out)
                 samples_out[(k - k_begin) * mp + e] = d;
             double delta = d - mean[e];
