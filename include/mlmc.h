@@ -5,7 +5,8 @@
  * Multiplication", arXiv:1904.00429).
  *
  * The problem (Sec. 3): A (m x n) and B (n x p) are random matrices with
- * known entry laws; n is large.  Estimate E[AB] by
+ * known entry laws; n is large.  Estimate E[AB] (more generally E[f(AB)],
+ * f entrywise: see mlmc_func) by
  *   Y = sum_{l=0}^{L} Ybar_l                                      (eq. (10))
  *   Ybar_l = (1/N_l) sum_k (Z_l^(k) - Z_{l-1}^(k)),  Ybar_0 = mean_k Z_0^(k)   (eq. (9))
  * where Z_l^(k) = (n / c_l) sum_{t < c_l} A^(k)[:, r_t] B^(k)[r_t, :] is the
@@ -67,6 +68,17 @@ typedef enum {
                              (one per matrix: the entries are i.i.d.), undone in the epilogue */
 } mlmc_prec;
 
+/* Target function f (Sec. 3): the estimate is of E[f(AB)] (E[f(x^T y)] for
+ * the inner product), f applied entrywise to both sketches of every
+ * realisation, so the level sample is D = f(Z_l) - f(Z_{l-1}) (f(Z_0) at
+ * level 0).  H is the Heaviside step, read as H(0) = 1. */
+typedef enum {
+    MLMC_FUNC_IDENTITY = 0,     /* f(x) = x */
+    MLMC_FUNC_ABS_STEP = 1,     /* f(x) = |x| H(theta0 - x)                (Sec. 4.2: theta0 = 2) */
+    MLMC_FUNC_INV_ABS_STEP = 2  /* f(x) = 1 / (|x| H(x + theta0) + theta1) (Sec. 4.1: theta0 = 0.4,
+                                   theta1 = 0.01); theta1 > 0 */
+} mlmc_func;
+
 #define MLMC_FLAG_SHARED_SAMPLES 1u
 #define MLMC_FLAG_TIMING 2u       /* time every kernel launch with HIP events on `stream` */
 #define MLMC_MAX_LEVELS 32
@@ -112,6 +124,8 @@ typedef struct {
     int32_t prec;         /* mlmc_prec */
     uint32_t flags;       /* MLMC_FLAG_* */
     uint32_t problem;     /* stream id < 2^20 (independent problems, same seed) */
+    int32_t func;         /* mlmc_func; 0 (identity) when the struct is zero-initialised */
+    double func_param[2]; /* theta0, theta1 of f (finite) */
 } mlmc_levels;
 
 /* Filled when a non-NULL report is passed (synchronises the stream). */
@@ -128,19 +142,22 @@ typedef struct {
 size_t mlmc_matmul_workspace_size(int64_t m, int64_t n, int64_t p, const mlmc_levels* levels);
 size_t mlmc_inner_product_workspace_size(int64_t n, const mlmc_levels* levels);
 
-/* MLMC estimate of E[AB] (Sec. 3, Alg. 1 and Alg. 2, f = identity).
+/* MLMC estimate of E[f(AB)] (Sec. 3, Alg. 1 and Alg. 2; f = levels->func,
+ * the identity by default).
  *   out:         device FP64, m x p row-major, receives Y = sum_l Ybar_l.
  *   level_means: NULL, or device FP64 (num_levels x m x p) receiving Ybar_l.
  * Errors: EINVAL (m, n, p < 1; n >= 2^32; bad ladder; bad mode; null
- * pointers; reparam without mean/stdev), EWORKSPACE, EBUDGET, EDEVICE. */
+ * pointers; reparam without mean/stdev; unknown f or non-finite or
+ * out-of-range f parameters), EWORKSPACE, EBUDGET, EDEVICE. */
 mlmc_status mlmc_matmul_estimate(int64_t m, int64_t n, int64_t p, const mlmc_dist* A,
                                  const mlmc_dist* B, const mlmc_levels* levels, double* out,
                                  double* level_means, void* workspace, size_t workspace_bytes,
                                  mlmc_report* report, void* stream);
 
-/* MLMC estimate of E[x^T y] for random x, y of length n (Sec. 2; the m = p = 1
- * case of the matrix estimator).  out: device FP64 scalar.  level_means: NULL
- * or device FP64 [num_levels].  prec: FP64 or FP32.  Errors as above. */
+/* MLMC estimate of E[f(x^T y)] for random x, y of length n (Sec. 2; the
+ * m = p = 1 case of the matrix estimator).  out: device FP64 scalar.
+ * level_means: NULL or device FP64 [num_levels].  prec: FP64 or FP32.
+ * Errors as above. */
 mlmc_status mlmc_inner_product_estimate(int64_t n, const mlmc_dist* x, const mlmc_dist* y,
                                         const mlmc_levels* levels, double* out,
                                         double* level_means, void* workspace,
@@ -213,8 +230,9 @@ mlmc_status mlmc_graph_destroy(mlmc_graph graph);
  *             Gradients are ADDED (FP32 atomics, so the last bits depend on
  *             the order in which workgroups finish); zero them first.
  * Arithmetic: FP32 (values, MFMA contraction, accumulation).
- * Errors: EINVAL (laws not reparameterised, target mode, null pointers, and
- * the conditions of mlmc_matmul_estimate), EWORKSPACE, EDEVICE. */
+ * Errors: EINVAL (laws not reparameterised, target mode, f other than the
+ * identity, null pointers, and the conditions of mlmc_matmul_estimate),
+ * EWORKSPACE, EDEVICE. */
 size_t mlmc_matmul_adjoint_workspace_size(int64_t m, int64_t n, int64_t p, const mlmc_levels* levels);
 mlmc_status mlmc_matmul_adjoint_reparam(int64_t m, int64_t n, int64_t p, const mlmc_dist* A,
                                         const mlmc_dist* B, const mlmc_levels* levels,

@@ -29,7 +29,8 @@ class Levels(ctypes.Structure):
                 ("n_samples", ctypes.POINTER(ctypes.c_int64)), ("rmse_target", ctypes.c_double),
                 ("pilot_samples", ctypes.c_int64), ("max_total_draws", ctypes.c_int64),
                 ("seed", ctypes.c_uint64), ("prec", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("problem", ctypes.c_uint32)]
+                ("problem", ctypes.c_uint32), ("func", ctypes.c_int32),
+                ("func_param", ctypes.c_double * 2)]
 
 
 class Problem(ctypes.Structure):

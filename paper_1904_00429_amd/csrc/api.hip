@@ -65,6 +65,12 @@ mlmc_status check_levels(const mlmc_levels* lv, bool inner)
                 return fail(MLMC_EINVAL, "n_samples[%d] must be in [1, 2^32)", l);
     }
     if (lv->max_total_draws < 0) return fail(MLMC_EINVAL, "max_total_draws must be >= 0");
+    if (lv->func < MLMC_FUNC_IDENTITY || lv->func > MLMC_FUNC_INV_ABS_STEP)
+        return fail(MLMC_EINVAL, "unknown target function %d", lv->func);
+    if (lv->func != MLMC_FUNC_IDENTITY && (!isfinite(lv->func_param[0]) || !isfinite(lv->func_param[1])))
+        return fail(MLMC_EINVAL, "target function parameters must be finite");
+    if (lv->func == MLMC_FUNC_INV_ABS_STEP && !(lv->func_param[1] > 0.0))
+        return fail(MLMC_EINVAL, "1 / (|x| H(x + theta0) + theta1) needs theta1 > 0");
     return MLMC_OK;
 }
 
@@ -91,6 +97,11 @@ Law to_law(const mlmc_dist& d)
     l.stdev = d.stdev;
     l.ld = d.ld;
     return l;
+}
+
+TargetFunc func_of(const mlmc_levels* lv)
+{
+    return TargetFunc{lv->func, lv->func_param[0], lv->func_param[1]};
 }
 
 StreamKeys keys_of(const mlmc_levels* lv)
@@ -242,7 +253,7 @@ size_t mlmc_matmul_workspace_size(int64_t m, int64_t n, int64_t p, const mlmc_le
     if (check_levels(levels, false) != MLMC_OK || m < 1 || p < 1 || n < 1) return 0;
     MatmulProblem pr{m, n, p, Law{}, Law{}, levels->problem, nullptr, nullptr};
     MatmulPlan plan;
-    if (!matmul_plan(&pr, 1, levels->prec, levels->num_levels, levels->c, nullptr, plan)) return 0;
+    if (!matmul_plan(&pr, 1, levels->prec, levels->num_levels, levels->c, nullptr, func_of(levels), plan)) return 0;
     return plan.total;
 }
 
@@ -284,7 +295,8 @@ mlmc_status mlmc_inner_product_estimate(int64_t n, const mlmc_dist* x, const mlm
     auto run_all = [&](const int64_t* k0, const int64_t* cnt) -> hipError_t {
         LevelRange ranges[MLMC_MAX_LEVELS];
         for (int l = 0; l < L1; ++l) ranges[l] = range_of(lv, l, k0[l], cnt[l]);
-        return inner_levels_run(ranges, L1, n, lx, ly, lv->prec, keys, partials, state, stream, timer);
+        return inner_levels_run(ranges, L1, n, lx, ly, func_of(lv), lv->prec, keys, partials, state, stream,
+                                timer);
     };
     std::vector<int64_t> zero(L1, 0), amount(L1, 0);
     if (lv->rmse_target > 0.0) {
@@ -337,7 +349,7 @@ mlmc_status mlmc_matmul_estimate(int64_t m, int64_t n, int64_t p, const mlmc_dis
     if (!out) return fail(MLMC_EINVAL, "out is NULL");
     MatmulProblem pr{m, n, p, to_law(*A), to_law(*B), lv->problem, out, level_means};
     MatmulPlan plan;
-    if (!matmul_plan(&pr, 1, lv->prec, lv->num_levels, lv->c, nullptr, plan))
+    if (!matmul_plan(&pr, 1, lv->prec, lv->num_levels, lv->c, nullptr, func_of(lv), plan))
         return fail(MLMC_EINVAL, "no launch plan for this shape and precision");
     if (!workspace || workspace_bytes < plan.total)
         return fail(MLMC_EWORKSPACE, "workspace needs %zu bytes", plan.total);
@@ -472,7 +484,8 @@ size_t mlmc_matmul_batched_workspace_size(int32_t nprob, const mlmc_problem* pro
     MatmulTuning tune;
     if (check_batch(nprob, probs, levels, tuning, pr, tune) != MLMC_OK) return 0;
     MatmulPlan plan;
-    if (!matmul_plan(pr.data(), nprob, levels->prec, levels->num_levels, levels->c, &tune, plan)) return 0;
+    if (!matmul_plan(pr.data(), nprob, levels->prec, levels->num_levels, levels->c, &tune, func_of(levels), plan))
+        return 0;
     return plan.total;
 }
 
@@ -486,7 +499,7 @@ mlmc_status mlmc_matmul_estimate_batched(int32_t nprob, const mlmc_problem* prob
     mlmc_status st = check_batch(nprob, probs, lv, tuning, pr, tune);
     if (st != MLMC_OK) return st;
     MatmulPlan plan;
-    if (!matmul_plan(pr.data(), nprob, lv->prec, lv->num_levels, lv->c, &tune, plan))
+    if (!matmul_plan(pr.data(), nprob, lv->prec, lv->num_levels, lv->c, &tune, func_of(lv), plan))
         return fail(MLMC_EINVAL, "no launch plan for this table");
     if (!workspace || workspace_bytes < plan.total)
         return fail(MLMC_EWORKSPACE, "workspace needs %zu bytes", plan.total);
@@ -517,7 +530,7 @@ mlmc_status mlmc_matmul_batched_graph_create(int32_t nprob, const mlmc_problem* 
     mlmc_status st = check_batch(nprob, probs, lv, tuning, pr, tune);
     if (st != MLMC_OK) return st;
     MatmulPlan plan;
-    if (!matmul_plan(pr.data(), nprob, lv->prec, lv->num_levels, lv->c, &tune, plan))
+    if (!matmul_plan(pr.data(), nprob, lv->prec, lv->num_levels, lv->c, &tune, func_of(lv), plan))
         return fail(MLMC_EINVAL, "no launch plan for this table");
     if (!workspace || workspace_bytes < plan.total)
         return fail(MLMC_EWORKSPACE, "workspace needs %zu bytes", plan.total);
@@ -584,6 +597,7 @@ mlmc_status mlmc_matmul_adjoint_reparam(int64_t m, int64_t n, int64_t p, const m
     if (st != MLMC_OK) return st;
     if (lv->rmse_target > 0.0 || !lv->n_samples)
         return fail(MLMC_EINVAL, "the adjoint needs the forward's N_l (fixed mode)");
+    if (lv->func != MLMC_FUNC_IDENTITY) return fail(MLMC_EINVAL, "the adjoint is defined for f = identity");
     if ((st = check_dist(A, "A", m, false)) != MLMC_OK) return st;
     if ((st = check_dist(B, "B", p, false)) != MLMC_OK) return st;
     if (A->law != MLMC_LAW_REPARAM || B->law != MLMC_LAW_REPARAM)

@@ -56,6 +56,23 @@ __device__ __forceinline__ T law_value(const Law& law, T z_normal, T u_uniform, 
     return fma(z_normal, (T)law.scale, (T)law.loc);
 }
 
+// Target function f of Sec. 3, applied entrywise to every sketch (kinds as
+// mlmc_func): 0 f(x) = x; 1 f(x) = |x| H(theta0 - x); 2 f(x) =
+// 1 / (|x| H(x + theta0) + theta1); H(0) = 1.  x <= theta0 and x >= -theta0
+// are the exact floating-point forms of the two step conditions.
+struct TargetFunc {
+    int32_t kind;
+    double theta0, theta1;
+};
+
+template <typename T>
+__device__ __forceinline__ T target_value(int kind, T x, T theta0, T theta1)
+{
+    if (kind == 1) return x <= theta0 ? fabs(x) : (T)0;
+    if (kind == 2) return (T)1 / ((x >= -theta0 ? fabs(x) : (T)0) + theta1);
+    return x;
+}
+
 // Law pairs with a specialised kernel instantiation (no per-value law branches
 // in hot loops); every other combination takes the general path.
 enum { kLawsAny = 0, kLawsUniform = 1, kLawsNormal = 2 };

@@ -41,6 +41,7 @@ struct InnerLevel {
     uint32_t block_begin, blocks;
     uint32_t sid_index, sid_value;
     double scale;             // n / c
+    double scale_c;           // n / c_prev (0 at level 0)
     double omega;             // 1 - c / c_prev, weight of the first c_prev draws
 };
 
@@ -50,6 +51,7 @@ struct InnerMultiParams {
     uint32_t key0, key1;
     int32_t num_levels;
     Law x, y;
+    TargetFunc f;             // applied to both sketches (FN kernels)
     Moments* partials;        // one per workgroup
     InnerLevel lev[32];
 };
@@ -120,10 +122,15 @@ __device__ __forceinline__ void sum_pairs(const InnerMultiParams& prm, const Inn
     }
 }
 
-template <typename T, int LAWS>
+// FN: a target function f other than the identity.  The level sample is then
+// f(Z_l) - f(Z_{l-1}) with Z_l = (n / c_l)(C + F) and Z_{l-1} = (n / c_{l-1}) C,
+// C and F the sums over the coarse and the remaining draws, so both sums are
+// reduced over the group instead of their weighted combination.
+template <typename T, int LAWS, bool FN>
 __global__ __launch_bounds__(kInnerBlock) void inner_multi_kernel(InnerMultiParams prm)
 {
     __shared__ double wave_sum[kInnerBlock / kWave];
+    __shared__ double wave_sum_c[FN ? kInnerBlock / kWave : 1];
     __shared__ Moments slots[kInnerBlock];
 
     int l = 0;
@@ -164,21 +171,38 @@ __global__ __launch_bounds__(kInnerBlock) void inner_multi_kernel(InnerMultiPara
         const uint32_t fine_begin = coarse_pairs + (odd_prev ? 1u : 0u);
         const uint32_t q_fine = fine_begin + (((uint32_t)lane_g - fine_begin) & (uint32_t)(G - 1));
         sum_pairs<T, LAWS>(prm, L, q_fine, pairs, (uint32_t)G, k, acc_fine);
-        T part = omega * acc_coarse + acc_fine;
+        T part = FN ? acc_fine : omega * acc_coarse + acc_fine;
+        T part_c = acc_coarse;
         const int width = G < kWave ? G : kWave;
-        for (int off = width >> 1; off > 0; off >>= 1) part += __shfl_xor(part, off, kWave);
-        double total = (double)part;
+        for (int off = width >> 1; off > 0; off >>= 1) {
+            part += __shfl_xor(part, off, kWave);
+            if constexpr (FN) part_c += __shfl_xor(part_c, off, kWave);
+        }
+        double total = (double)part, total_c = (double)part_c;
         if (G > kWave) {
             // the group spans G / 64 waves: add their sums in wave order
-            if (lane == 0) wave_sum[wave] = total;
+            if (lane == 0) {
+                wave_sum[wave] = total;
+                if constexpr (FN) wave_sum_c[wave] = total_c;
+            }
             __syncthreads();
             const int first = (gi * G) / kWave;
             total = 0.0;
-            for (int w = 0; w < G / kWave; ++w) total += wave_sum[first + w];
+            total_c = 0.0;
+            for (int w = 0; w < G / kWave; ++w) {
+                total += wave_sum[first + w];
+                if constexpr (FN) total_c += wave_sum_c[first + w];
+            }
             __syncthreads();
         }
         if (active) {
-            const double d = L.scale * total;
+            double d;
+            if constexpr (FN) {
+                d = target_value(prm.f.kind, L.scale * (total_c + total), prm.f.theta0, prm.f.theta1);
+                if (L.c_prev > 0u) d -= target_value(prm.f.kind, L.scale_c * total_c, prm.f.theta0, prm.f.theta1);
+            } else {
+                d = L.scale * total;
+            }
             if (n == 0.0) K = d;
             n += 1.0;
             const double dev = d - K;
@@ -255,11 +279,21 @@ static uint32_t lanes_log2_for(int64_t c)
     return g;
 }
 
+template <typename T, bool FN>
+static void launch_inner(int laws, dim3 grid, hipStream_t stream, const InnerMultiParams& prm)
+{
+    const dim3 block(kInnerBlock);
+    if (laws == kLawsUniform) hipLaunchKernelGGL((inner_multi_kernel<T, kLawsUniform, FN>), grid, block, 0, stream, prm);
+    else if (laws == kLawsNormal) hipLaunchKernelGGL((inner_multi_kernel<T, kLawsNormal, FN>), grid, block, 0, stream, prm);
+    else hipLaunchKernelGGL((inner_multi_kernel<T, kLawsAny, FN>), grid, block, 0, stream, prm);
+}
+
 hipError_t inner_levels_run(const LevelRange* ranges, int num_levels, int64_t n, const Law& x, const Law& y,
-                            int prec, const StreamKeys& keys, Moments* partials, Moments* level_state,
-                            hipStream_t stream, KernelTimer* timer)
+                            const TargetFunc& f, int prec, const StreamKeys& keys, Moments* partials,
+                            Moments* level_state, hipStream_t stream, KernelTimer* timer)
 {
     InnerMultiParams prm;
+    prm.f = f;
     prm.n = (uint32_t)n;
     prm.n_shift = 0xFFFFFFFFu;
     if ((n & (n - 1)) == 0) {
@@ -298,6 +332,7 @@ hipError_t inner_levels_run(const LevelRange* ranges, int num_levels, int64_t n,
         L.sid_index = stream_id(kTagIndex, lr.level_field, keys.problem);
         L.sid_value = stream_id(kTagValue, lr.level_field, keys.problem);
         L.scale = (double)n / (double)lr.c;
+        L.scale_c = lr.c_prev > 0 ? (double)n / (double)lr.c_prev : 0.0;
         L.omega = lr.c_prev > 0 ? 1.0 - (double)lr.c / (double)lr.c_prev : 0.0;
         int64_t blocks = 0;
         if (L.count > 0) {
@@ -334,15 +369,14 @@ hipError_t inner_levels_run(const LevelRange* ranges, int num_levels, int64_t n,
     const int laws = law_pair_kind(x.kind, y.kind);
     {
         ScopedTiming t(timer, 0);
-        const dim3 grid(next), block(kInnerBlock);
+        const dim3 grid(next);
+        const bool fn = f.kind != 0;
         if (prec == 0) {
-            if (laws == kLawsUniform) hipLaunchKernelGGL((inner_multi_kernel<double, kLawsUniform>), grid, block, 0, stream, prm);
-            else if (laws == kLawsNormal) hipLaunchKernelGGL((inner_multi_kernel<double, kLawsNormal>), grid, block, 0, stream, prm);
-            else hipLaunchKernelGGL((inner_multi_kernel<double, kLawsAny>), grid, block, 0, stream, prm);
+            if (fn) launch_inner<double, true>(laws, grid, stream, prm);
+            else launch_inner<double, false>(laws, grid, stream, prm);
         } else {
-            if (laws == kLawsUniform) hipLaunchKernelGGL((inner_multi_kernel<float, kLawsUniform>), grid, block, 0, stream, prm);
-            else if (laws == kLawsNormal) hipLaunchKernelGGL((inner_multi_kernel<float, kLawsNormal>), grid, block, 0, stream, prm);
-            else hipLaunchKernelGGL((inner_multi_kernel<float, kLawsAny>), grid, block, 0, stream, prm);
+            if (fn) launch_inner<float, true>(laws, grid, stream, prm);
+            else launch_inner<float, false>(laws, grid, stream, prm);
         }
     }
     hipError_t e = hipGetLastError();

@@ -57,8 +57,8 @@ size_t inner_partials_capacity();  // Moments slots needed in workspace
 // One launch over every level's range (pilot, extension or fixed mode), then a
 // fold of the workgroup partials into the running level states.
 hipError_t inner_levels_run(const LevelRange* ranges, int num_levels, int64_t n, const Law& x,
-                            const Law& y, int prec, const StreamKeys& keys, Moments* partials,
-                            Moments* level_state, hipStream_t stream, KernelTimer* timer);
+                            const Law& y, const TargetFunc& f, int prec, const StreamKeys& keys,
+                            Moments* partials, Moments* level_state, hipStream_t stream, KernelTimer* timer);
 hipError_t inner_telescope(const Moments* level_state, int num_levels, double* out,
                            double* level_means, double* level_var, hipStream_t stream);
 
@@ -102,6 +102,7 @@ struct MatmulPlan {
     int nprob;
     int kstep, kpack, elem, nb, tile;
     int laws;                  // law pair shared by every product (kLaws*), else kLawsAny
+    TargetFunc func;           // f of E[f(AB)]; not the identity: both sketches kept (tile 64)
     bool iid;                  // no product has a reparameterised law
     bool whole_tiles;          // every m and p is a multiple of the workgroup tile
     int64_t min_rows;          // smallest m + p over the products
@@ -115,7 +116,7 @@ struct MatmulPlan {
 };
 
 bool matmul_plan(const MatmulProblem* probs, int nprob, int prec, int num_levels, const int64_t* c,
-                 const MatmulTuning* tune, MatmulPlan& plan);
+                 const MatmulTuning* tune, const TargetFunc& func, MatmulPlan& plan);
 // copies the problem table into the workspace (synchronises `stream`)
 hipError_t matmul_upload(const MatmulPlan& plan, char* ws, hipStream_t stream);
 hipError_t matmul_reset(const MatmulPlan& plan, char* ws, hipStream_t stream);

@@ -373,6 +373,8 @@ struct SketchParams {
     int64_t batch;               // realisations in this pass
     int elem;
     uint32_t c;                  // c_l
+    uint32_t c_prev;             // c_{l-1}, 0 at level 0
+    TargetFunc func;             // STATS 4: f applied to both sketches
     const char* gbuf;
     void* part_mean;             // groups x sum_mp, in the accumulation type
     double* part_m2;             // groups x total_tiles
@@ -522,6 +524,11 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
         // outside the product see zero-padded operand rows: D = 0 there, and
         // the shift is not applied to them.
         constexpr bool DUAL = STATS == 3;
+        // STATS 4: a target function f.  The accumulator is copied when the
+        // coarse draws are done (the gathered a_t are unweighted), and the
+        // level sample of every entry is f(n / c_l acc) - f(n / c_{l-1} snap),
+        // or f(n / c_0 acc) at level 0, into Welford's mean and M2.
+        constexpr bool FUNC = STATS == 4;
         Acc run[DUAL ? 1 : NE];
 #pragma unroll
         for (int e = 0; e < (DUAL ? 1 : NE); ++e) run[e] = (Acc)0;
@@ -534,9 +541,14 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
 #pragma unroll
                     for (int r = 0; r < P::REGS; ++r) tot[bi][bj][r] = (Acc)0;
         }
+        typename P::AccVec snap[FUNC ? NBR : 1][FUNC ? NBC : 1];
+        const bool has_coarse = prm.c_prev > 0u;
+        const Acc scale_c = (Acc)(has_coarse ? (double)Pd.n / (double)prm.c_prev * Pd.post : 0.0);
+        const int fkind = prm.func.kind;
+        const Acc th0 = (Acc)prm.func.theta0, th1 = (Acc)prm.func.theta1;
         double m2_sum = 0.0;
         Acc count = (Acc)0;
-        constexpr bool SHIFTED = STATS != 0;
+        constexpr bool SHIFTED = STATS >= 1 && STATS <= 3;
         const Acc shift = SHIFTED && kc == 0 ? (Acc)(Pd.mean0 / scale64) : (Acc)0;
         // with a non-zero shift, entries outside the product (ragged tiles only)
         // are masked: bit e of `inside` is set for an entry inside the product
@@ -630,7 +642,13 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
                     for (int bj = 0; bj < NBC; ++bj)
 #pragma unroll
                         for (int r = 0; r < P::REGS; ++r, ++e) {
-                            const Acc d = scale * acc[bi][bj][r];
+                            Acc d;
+                            if constexpr (FUNC) {
+                                d = target_value(fkind, scale * acc[bi][bj][r], th0, th1);
+                                if (has_coarse) d -= target_value(fkind, scale_c * snap[bi][bj][r], th0, th1);
+                            } else {
+                                d = scale * acc[bi][bj][r];
+                            }
                             const Acc delta = d - run[e];
                             run[e] += delta * inv;
                             part += delta * (d - run[e]);
@@ -665,11 +683,21 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
             const int steps = (left < KC ? left : KC) / P::KSTEP;
             // runs of steps that end at the chunk's end or the end of a realisation
             for (int st = 0; st < steps;) {
-                int run_steps = (kpad - o) / P::KSTEP;
+                // FUNC: a run also ends where the coarse draws end (o = kc)
+                const int stop = FUNC && o < kc ? kc : kpad;
+                int run_steps = (stop - o) / P::KSTEP;
                 if (run_steps > steps - st) run_steps = steps - st;
                 for (int i = 0; i < run_steps; ++i) step(LA, LB, (st + i) * P::KSTEP);
                 st += run_steps;
                 o += run_steps * P::KSTEP;
+                if constexpr (FUNC) {
+                    if (kc > 0 && o == kc) {
+#pragma unroll
+                        for (int bi = 0; bi < NBR; ++bi)
+#pragma unroll
+                            for (int bj = 0; bj < NBC; ++bj) snap[bi][bj] = acc[bi][bj];
+                    }
+                }
                 if (o == kpad) {
                     realisation_done();
                     o = 0;
@@ -910,9 +938,10 @@ static float fp8_prescale(const Law& law)
 }
 
 bool matmul_plan(const MatmulProblem* probs, int nprob, int prec, int num_levels, const int64_t* c,
-                 const MatmulTuning* tune, MatmulPlan& plan)
+                 const MatmulTuning* tune, const TargetFunc& func, MatmulPlan& plan)
 {
     plan = MatmulPlan();
+    plan.func = func;
     if (nprob < 1) return false;
     plan.prec = prec;
     plan.num_levels = num_levels;
@@ -927,6 +956,9 @@ bool matmul_plan(const MatmulProblem* probs, int nprob, int prec, int num_levels
     // wide and always use tile 64 (2 x 2 waves of 32 x 32 in 16 x 16 blocks)
     plan.nb = 2;
     if (tune && tune->tile > 0 && prec != 0) plan.nb = tune->tile <= 2 * ps.blk ? 1 : 2;
+    // a target function keeps the coarse sketch beside the fine one: the
+    // 32 x 32-per-wave layout (tile 64) leaves room for the extra registers
+    if (func.kind != 0 && prec != 0) plan.nb = 1;
     plan.tile = 2 * plan.nb * ps.blk;
     plan.kpad_max = 0;
     for (int l = 0; l < num_levels; ++l) {
@@ -1086,7 +1118,8 @@ static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t
                ceil_div(kpad, (int64_t)kGatherPositions * oct * 2) * batch * plan.nprob >= 8192)
             oct *= 2;
         g.octets = oct;
-        g.omega = lr.c_prev > 0 ? 1.0 - (double)lr.c / (double)lr.c_prev : 1.0;
+        // with a target function the sketch needs the coarse sum itself: no weight
+        g.omega = lr.c_prev > 0 && plan.func.kind == 0 ? 1.0 - (double)lr.c / (double)lr.c_prev : 1.0;
         const dim3 grid((unsigned)ceil_div(kpad, (int64_t)kGatherPositions * oct), (unsigned)batch,
                         (unsigned)plan.nprob);
         if (plan.laws == kLawsNormal)
@@ -1113,6 +1146,8 @@ static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t
     s.batch = batch;
     s.elem = plan.elem;
     s.c = (uint32_t)lr.c;
+    s.c_prev = (uint32_t)lr.c_prev;
+    s.func = plan.func;
     s.gbuf = g.gbuf;
     s.part_mean = ws + plan.off_part_mean;
     s.part_m2 = reinterpret_cast<double*>(ws + plan.off_part_m2);
@@ -1134,7 +1169,15 @@ static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t
         constexpr bool kMaskedFits = kShiftedFits && NBR * NBC * P::REGS <= 32;
         constexpr bool kDualForm = sizeof(typename P::In) <= 2;   // BF16, FP8: FP32 totals suffice
         const dim3 grid((unsigned)blocks), block(kWave * WR * WC);
-        if (plan.iid && plan.whole_tiles && kDualForm && lr.c <= kDualMaxDraws)
+        constexpr bool kFuncForm = NBR * NBC * P::REGS <= 16;   // the layouts a target function uses
+        if (plan.func.kind != 0) {
+            // the copied accumulators need more than 128 registers: two waves per SIMD
+            if constexpr (kFuncForm)
+                hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, (WPE > 2 ? 2 : WPE), 4>), grid, block, 0,
+                                   stream, s);
+            else
+                return hipErrorInvalidConfiguration;   // matmul_plan picks tile 64 for a target function
+        } else if (plan.iid && plan.whole_tiles && kDualForm && lr.c <= kDualMaxDraws)
             hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, WPE, kDualForm ? 3 : 0>), grid, block, 0,
                                stream, s);
         else if (plan.iid && kShiftedFits && plan.whole_tiles)

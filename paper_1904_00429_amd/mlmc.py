@@ -66,6 +66,28 @@ class Law:
 
 
 @dataclass
+class Func:
+    """Target function f of E[f(AB)] (mlmc_func), applied entrywise to both
+    sketches of every realisation: identity; abs_step f(x) = |x| H(theta0 - x);
+    inv_abs_step f(x) = 1 / (|x| H(x + theta0) + theta1); H(0) = 1."""
+    kind: int = 0
+    theta0: float = 0.0
+    theta1: float = 0.0
+
+    @staticmethod
+    def identity() -> "Func":
+        return Func()
+
+    @staticmethod
+    def abs_step(theta0: float = 2.0) -> "Func":
+        return Func(1, float(theta0), 0.0)
+
+    @staticmethod
+    def inv_abs_step(theta0: float = 0.4, theta1: float = 0.01) -> "Func":
+        return Func(2, float(theta0), float(theta1))
+
+
+@dataclass
 class Result:
     Y: torch.Tensor                        # m x p (or scalar) FP64 on the device
     level_means: Optional[torch.Tensor]    # (L+1) x m x p, if requested
@@ -78,7 +100,8 @@ class Result:
 class _LevelsHolder:
     """Keeps the ctypes arrays of a Levels struct alive."""
 
-    def __init__(self, c, n_samples, rmse_target, pilot, seed, prec, shared, problem, max_total_draws):
+    def __init__(self, c, n_samples, rmse_target, pilot, seed, prec, shared, problem, max_total_draws,
+                 func: Optional[Func] = None):
         if prec not in PREC:
             raise ValueError(f"prec must be one of {sorted(PREC)}")
         self.c = (ctypes.c_int64 * len(c))(*[int(v) for v in c])
@@ -94,6 +117,10 @@ class _LevelsHolder:
         lv.prec = PREC[prec]
         lv.flags = FLAG_SHARED_SAMPLES if shared else 0
         lv.problem = int(problem)
+        f = func or Func()
+        lv.func = int(f.kind)
+        lv.func_param[0] = float(f.theta0)
+        lv.func_param[1] = float(f.theta1)
         self.lv = lv
 
 
@@ -107,8 +134,9 @@ def _result(Y, means, rep: Report, num_levels: int) -> Result:
                   int(rep.total_draws))
 
 
-def matmul_workspace_size(m, n, p, c, prec="fp64", n_samples=None, rmse_target=0.0, pilot=0) -> int:
-    h = _LevelsHolder(c, n_samples, rmse_target, pilot, 0, prec, False, 0, 0)
+def matmul_workspace_size(m, n, p, c, prec="fp64", n_samples=None, rmse_target=0.0, pilot=0,
+                          func: Optional[Func] = None) -> int:
+    h = _LevelsHolder(c, n_samples, rmse_target, pilot, 0, prec, False, 0, 0, func)
     return int(lib().mlmc_matmul_workspace_size(int(m), int(n), int(p), ctypes.byref(h.lv)))
 
 
@@ -117,10 +145,11 @@ def matmul_estimate(m: int, n: int, p: int, A: Law, B: Law, c: Sequence[int],
                     pilot: int = 0, seed: int = 0, prec: str = "fp64", shared: bool = False,
                     problem: int = 0, max_total_draws: int = 0, level_means: bool = False,
                     report: bool = True, device=None, workspace: Optional[torch.Tensor] = None,
-                    out: Optional[torch.Tensor] = None) -> Result:
-    """MLMC estimate of E[AB] on the GPU (mlmc_matmul_estimate)."""
+                    out: Optional[torch.Tensor] = None, func: Optional[Func] = None) -> Result:
+    """MLMC estimate of E[f(AB)] on the GPU (mlmc_matmul_estimate; f = identity
+    unless func is given)."""
     device = torch.device(device or "cuda")
-    h = _LevelsHolder(c, n_samples, rmse_target, pilot, seed, prec, shared, problem, max_total_draws)
+    h = _LevelsHolder(c, n_samples, rmse_target, pilot, seed, prec, shared, problem, max_total_draws, func)
     ws_bytes = int(lib().mlmc_matmul_workspace_size(int(m), int(n), int(p), ctypes.byref(h.lv)))
     if ws_bytes == 0:
         raise MLMCError(1, "invalid problem: no workspace size")
@@ -145,10 +174,11 @@ def inner_product_estimate(n: int, x: Law, y: Law, c: Sequence[int],
                            problem: int = 0, max_total_draws: int = 0, level_means: bool = False,
                            report: bool = True, device=None,
                            workspace: Optional[torch.Tensor] = None,
-                           out: Optional[torch.Tensor] = None) -> Result:
-    """MLMC estimate of E[x^T y] on the GPU (mlmc_inner_product_estimate)."""
+                           out: Optional[torch.Tensor] = None, func: Optional[Func] = None) -> Result:
+    """MLMC estimate of E[f(x^T y)] on the GPU (mlmc_inner_product_estimate;
+    f = identity unless func is given)."""
     device = torch.device(device or "cuda")
-    h = _LevelsHolder(c, n_samples, rmse_target, pilot, seed, prec, shared, problem, max_total_draws)
+    h = _LevelsHolder(c, n_samples, rmse_target, pilot, seed, prec, shared, problem, max_total_draws, func)
     ws_bytes = int(lib().mlmc_inner_product_workspace_size(int(n), ctypes.byref(h.lv)))
     if ws_bytes == 0:
         raise MLMCError(1, "invalid problem: no workspace size")
@@ -243,10 +273,11 @@ class BatchedEstimate:
     `self.Y` (one m x p FP64 device tensor per product)."""
 
     def __init__(self, problems: Sequence[BatchProblem], c: Sequence[int], n_samples: Sequence[int],
-                 seed: int = 0, prec: str = "fp32", tuning: Optional[dict] = None, device=None):
+                 seed: int = 0, prec: str = "fp32", tuning: Optional[dict] = None, device=None,
+                 func: Optional[Func] = None):
         self.device = torch.device(device or "cuda")
         self.problems = list(problems)
-        self.h = _LevelsHolder(c, n_samples, 0.0, 0, seed, prec, False, 0, 0)
+        self.h = _LevelsHolder(c, n_samples, 0.0, 0, seed, prec, False, 0, 0, func)
         self.Y = [torch.empty((pr.m, pr.p), dtype=torch.float64, device=self.device) for pr in self.problems]
         arr = (Problem * len(self.problems))()
         for i, pr in enumerate(self.problems):

@@ -117,3 +117,33 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         _lib.lib()
+
+
+@pytest.mark.parametrize("func, params", [(3, (0.0, 0.0)), (-1, (0.0, 0.0)), (1, (float("inf"), 0.0)),
+                                          (2, (0.4, 0.0)), (2, (0.4, -1.0)), (2, (float("nan"), 0.01))])
+def test_rejects_bad_target_function(L, func, params):
+    lv, keep = _levels([2, 4], [4, 4])
+    lv.func = func
+    lv.func_param[0], lv.func_param[1] = params
+    A, B = _dist(), _dist()
+    st = L.mlmc_matmul_estimate(4, 16, 3, ctypes.byref(A), ctypes.byref(B), ctypes.byref(lv), 8, None,
+                                16, 1 << 40, None, None)
+    assert st == 1, L.mlmc_last_error()
+    st = L.mlmc_inner_product_estimate(16, ctypes.byref(A), ctypes.byref(B), ctypes.byref(lv), 8, None,
+                                       16, 1 << 40, None, None)
+    assert st == 1
+    assert L.mlmc_matmul_workspace_size(4, 16, 3, ctypes.byref(lv)) == 0
+
+
+def test_adjoint_rejects_target_function(L):
+    lv, keep = _levels([2, 4], [4, 4], prec=1)
+    lv.func = 1
+    lv.func_param[0] = 2.0
+    A = _dist(2)
+    B = _dist(2)
+    A.mean = A.stdev = B.mean = B.stdev = 16
+    A.ld, B.ld = 4, 3
+    st = L.mlmc_matmul_adjoint_reparam(4, 16, 3, ctypes.byref(A), ctypes.byref(B), ctypes.byref(lv), 16, 16, 16,
+                                       16, 16, 16, 1 << 40, None)
+    assert st == 1
+    assert b"identity" in L.mlmc_last_error()
