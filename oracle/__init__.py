@@ -314,14 +314,36 @@ class Estimate:
     level_var: np.ndarray         # V_l
     n_used: np.ndarray            # N_l
     rmse_est: float               # sqrt(sum_l V_l / N_l)
+    levels_used: int = 0          # adaptive mode: levels that were run
+    bias_test_passed: bool = True  # adaptive mode: the stopping test held
+
+
+def bias_bound(c: Sequence[int], L: int, eps: float, kind: str) -> float:
+    """The finest correction Ybar_L is small enough when its norm is below
+    (sqrt(M) + 1) eps / sqrt(2) for a matrix product (Remark 3.5, eq. (27),
+    Frobenius norm) or (sqrt(M) - 1) eps / sqrt(2) for the inner product
+    (Sec. 2, eq. (15), absolute value); M is read as the ladder's ratio at the
+    finest level, c_L / c_{L-1}."""
+    M = c[L] / c[L - 1]
+    return (math.sqrt(M) + (1.0 if kind == "matrix" else -1.0)) * eps / math.sqrt(2.0)
 
 
 def estimate(m: int, n: int, p: int, A: Law, B: Law, c: Sequence[int],
              n_samples: Optional[Sequence[int]] = None, rmse_target: float = 0.0,
              pilot: int = 0, seed: int = 0, problem: int = 0, shared: bool = False,
-             max_total_draws: int = 0, pool=None, func: Optional[Func] = None) -> Estimate:
+             max_total_draws: int = 0, pool=None, func: Optional[Func] = None,
+             adaptive: Optional[str] = None) -> Estimate:
     """MLMC estimate of E[f(AB)] (f entrywise, identity by default) over the
     ladder c_0 < c_1 < ... < c_L.
+
+    Adaptive mode (adaptive = "matrix" or "inner", the entry point whose
+    stopping test applies; Alg. 2's loop over L, target mode only; c is the
+    longest ladder allowed): levels are added one at a time.  A new level first runs
+    `pilot` realisations (its V_l must be estimated before eq. (28) can give
+    N_l), then eq. (28) over the levels so far gives every N_l, and each level
+    is extended to max(N_l, the realisations it already has), reusing them.
+    From three levels on, the loop stops once the finest level mean passes
+    the test of Remark 3.5 (bias_bound).
 
     Fixed-N mode: n_samples gives N_l.  Target mode (rmse_target > 0): `pilot`
     realisations per level estimate V_l, eq. (28) gives N_l, and every level
@@ -342,6 +364,28 @@ def estimate(m: int, n: int, p: int, A: Law, B: Law, c: Sequence[int],
         else:
             list(pool.map(lambda a: run(*a), [(l, r[0], r[1]) for l, r in enumerate(ranges)]))
 
+    if adaptive:
+        if adaptive not in ("matrix", "inner"):
+            raise ValueError("adaptive must be 'matrix' or 'inner'")
+        if rmse_target <= 0 or pilot < 2:
+            raise ValueError("adaptive mode needs rmse_target > 0 and a pilot of at least 2 realisations")
+        used, passed = 0, False
+        for L in range(L1):
+            run(L, 0, pilot)
+            used = L + 1
+            V = [s.variance for s in states[:used]]
+            N = [max(x, pilot) for x in schedule(V, c[:used], rmse_target)]
+            if max_total_draws and sum(x * cl for x, cl in zip(N, c)) > max_total_draws:
+                raise RuntimeError("draw budget exceeded")
+            run_all([(states[l].count, max(N[l], states[l].count)) for l in range(used)])
+            if used >= 3 and float(np.linalg.norm(states[L].mean)) < bias_bound(c, L, rmse_target, adaptive):
+                passed = True
+                break
+        means = np.stack([s.mean.reshape(m, p) for s in states])
+        V = np.array([s.variance for s in states])
+        N = np.array([s.count for s in states], dtype=np.int64)
+        rmse = math.sqrt(float(np.sum(V[:used] / N[:used])))
+        return Estimate(means.sum(axis=0), means, V, N, rmse, used, passed)
     if rmse_target > 0:
         if pilot < 2:
             raise ValueError("target mode needs a pilot of at least 2 realisations")
@@ -359,7 +403,7 @@ def estimate(m: int, n: int, p: int, A: Law, B: Law, c: Sequence[int],
     V = np.array([s.variance for s in states])
     N = np.array([s.count for s in states], dtype=np.int64)
     rmse = math.sqrt(float(np.sum(V / N)))
-    return Estimate(means.sum(axis=0), means, V, N, rmse)
+    return Estimate(means.sum(axis=0), means, V, N, rmse, L1, True)
 
 
 @dataclass
