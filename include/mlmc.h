@@ -81,6 +81,16 @@ typedef enum {
 
 #define MLMC_FLAG_SHARED_SAMPLES 1u
 #define MLMC_FLAG_TIMING 2u       /* time every kernel launch with HIP events on `stream` */
+/* Adaptive number of levels (Alg. 2's loop over L; target mode, single-product
+ * entry points): c[] is the longest ladder allowed.  Levels are added one at a
+ * time; a new level first runs pilot_samples realisations, then eq. (28) over
+ * the levels so far gives every N_l and each level is extended to
+ * max(N_l, its realisations so far), reusing them.  From three levels on the
+ * loop stops once the finest level mean Ybar_L passes the bias test:
+ * ||Ybar_L||_F < (sqrt(M) + 1) eps / sqrt(2) (matrix, Remark 3.5, eq. (27)) or
+ * |Ybar_L| < (sqrt(M) - 1) eps / sqrt(2) (inner product, Sec. 2, eq. (15)),
+ * M = c[L] / c[L-1].  Levels never reached report N_l = 0 and add nothing. */
+#define MLMC_FLAG_ADAPTIVE_LEVELS 4u
 #define MLMC_MAX_LEVELS 32
 
 /* Kernel classes of mlmc_report.kernel_ms (MLMC_FLAG_TIMING). */
@@ -136,6 +146,8 @@ typedef struct {
     int64_t total_draws;                 /* sum_l N_l c_l */
     double kernel_ms[MLMC_KERNEL_CLASSES];        /* MLMC_FLAG_TIMING: summed device time */
     int64_t kernel_launches[MLMC_KERNEL_CLASSES]; /* MLMC_FLAG_TIMING: launches per class */
+    int32_t levels_used;                 /* levels run (num_levels unless adaptive) */
+    int32_t bias_test_passed;            /* adaptive: 1 if the loop stopped on the bias test */
 } mlmc_report;
 
 /* Bytes of device workspace needed by mlmc_matmul_estimate / inner product. */

@@ -48,7 +48,8 @@ class Report(ctypes.Structure):
     _fields_ = [("n_used", ctypes.c_int64 * MLMC_MAX_LEVELS),
                 ("level_var", ctypes.c_double * MLMC_MAX_LEVELS),
                 ("rmse_est", ctypes.c_double), ("total_draws", ctypes.c_int64),
-                ("kernel_ms", ctypes.c_double * 4), ("kernel_launches", ctypes.c_int64 * 4)]
+                ("kernel_ms", ctypes.c_double * 4), ("kernel_launches", ctypes.c_int64 * 4),
+                ("levels_used", ctypes.c_int32), ("bias_test_passed", ctypes.c_int32)]
 
 
 class MLMCError(RuntimeError):

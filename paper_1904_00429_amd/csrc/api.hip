@@ -65,6 +65,8 @@ mlmc_status check_levels(const mlmc_levels* lv, bool inner)
                 return fail(MLMC_EINVAL, "n_samples[%d] must be in [1, 2^32)", l);
     }
     if (lv->max_total_draws < 0) return fail(MLMC_EINVAL, "max_total_draws must be >= 0");
+    if ((lv->flags & MLMC_FLAG_ADAPTIVE_LEVELS) && !(lv->rmse_target > 0.0))
+        return fail(MLMC_EINVAL, "the adaptive number of levels needs target mode (rmse_target > 0)");
     if (lv->func < MLMC_FUNC_IDENTITY || lv->func > MLMC_FUNC_INV_ABS_STEP)
         return fail(MLMC_EINVAL, "unknown target function %d", lv->func);
     if (lv->func != MLMC_FUNC_IDENTITY && (!isfinite(lv->func_param[0]) || !isfinite(lv->func_param[1])))
@@ -114,12 +116,13 @@ StreamKeys keys_of(const mlmc_levels* lv)
 }
 
 // eq. (28): N_l = ceil(2 eps^-2 sqrt(V_l / C_l) sum_j sqrt(V_j C_j)), C_l = c_l.
-mlmc_status schedule(const mlmc_levels* lv, const double* var, int64_t* n_out)
+// eq. (28) over levels 0 .. nlev - 1
+mlmc_status schedule(const mlmc_levels* lv, const double* var, int nlev, int64_t* n_out)
 {
     const double eps = lv->rmse_target;
     double total = 0.0;
-    for (int l = 0; l < lv->num_levels; ++l) total += sqrt(var[l] * (double)lv->c[l]);
-    for (int l = 0; l < lv->num_levels; ++l) {
+    for (int l = 0; l < nlev; ++l) total += sqrt(var[l] * (double)lv->c[l]);
+    for (int l = 0; l < nlev; ++l) {
         const double nl = ceil(2.0 / (eps * eps) * sqrt(var[l] / (double)lv->c[l]) * total);
         if (!(nl < (double)kU32))
             return fail(MLMC_EBUDGET, "scheduled N_%d = %g exceeds the realisation counter range", l, nl);
@@ -129,7 +132,7 @@ mlmc_status schedule(const mlmc_levels* lv, const double* var, int64_t* n_out)
     }
     if (lv->max_total_draws > 0) {
         double draws = 0.0;
-        for (int l = 0; l < lv->num_levels; ++l) draws += (double)n_out[l] * (double)lv->c[l];
+        for (int l = 0; l < nlev; ++l) draws += (double)n_out[l] * (double)lv->c[l];
         if (draws > (double)lv->max_total_draws)
             return fail(MLMC_EBUDGET, "scheduled draws %.6g exceed max_total_draws %lld", draws,
                         (long long)lv->max_total_draws);
@@ -137,8 +140,16 @@ mlmc_status schedule(const mlmc_levels* lv, const double* var, int64_t* n_out)
     return MLMC_OK;
 }
 
+// The bias test of the adaptive loop on the finest level mean so far (its
+// Frobenius norm, or absolute value for the inner product).
+bool bias_test(const mlmc_levels* lv, int L, double norm, bool inner)
+{
+    const double M = (double)lv->c[L] / (double)lv->c[L - 1];
+    return norm < (sqrt(M) + (inner ? -1.0 : 1.0)) * lv->rmse_target / sqrt(2.0);
+}
+
 void fill_report(const mlmc_levels* lv, const int64_t* counts, const double* var, const KernelTimer* timer,
-                 mlmc_report* rep)
+                 mlmc_report* rep, int levels_used, bool passed)
 {
     for (int i = 0; i < MLMC_KERNEL_CLASSES; ++i) {
         rep->kernel_ms[i] = 0.0;
@@ -152,11 +163,13 @@ void fill_report(const mlmc_levels* lv, const int64_t* counts, const double* var
         rep->level_var[l] = l < lv->num_levels ? var[l] : 0.0;
     }
     for (int l = 0; l < lv->num_levels; ++l) {
-        s += var[l] / (double)counts[l];
+        if (counts[l] > 0) s += var[l] / (double)counts[l];
         draws += counts[l] * lv->c[l];
     }
     rep->rmse_est = sqrt(s);
     rep->total_draws = draws;
+    rep->levels_used = levels_used;
+    rep->bias_test_passed = passed ? 1 : 0;
 }
 
 LevelRange range_of(const mlmc_levels* lv, int l, int64_t k_begin, int64_t count)
@@ -299,7 +312,43 @@ mlmc_status mlmc_inner_product_estimate(int64_t n, const mlmc_dist* x, const mlm
                                 timer);
     };
     std::vector<int64_t> zero(L1, 0), amount(L1, 0);
-    if (lv->rmse_target > 0.0) {
+    int used = L1;
+    bool passed = true;
+    if (lv->flags & MLMC_FLAG_ADAPTIVE_LEVELS) {
+        // Alg. 2's loop over L: pilot of the new level, eq. (28) over the
+        // levels so far, extension of every level, then the bias test
+        used = 0;
+        passed = false;
+        std::vector<int64_t> target(L1);
+        for (int L = 0; L < L1 && !passed; ++L) {
+            std::fill(amount.begin(), amount.end(), 0);
+            amount[L] = lv->pilot_samples;
+            if ((e = run_all(counts.data(), amount.data())) != hipSuccess) return device_fail(e, "pilot launch");
+            counts[L] = lv->pilot_samples;
+            used = L + 1;
+            {
+                ScopedTiming t(timer, MLMC_KERNEL_FINAL);
+                e = inner_telescope(state, L1, out, nullptr, var_dev, stream);
+            }
+            if (e != hipSuccess) return device_fail(e, "level statistics");
+            if ((e = hipMemcpyAsync(var.data(), var_dev, sizeof(double) * L1, hipMemcpyDeviceToHost, stream)) !=
+                    hipSuccess ||
+                (e = hipStreamSynchronize(stream)) != hipSuccess)
+                return device_fail(e, "level statistics readback");
+            if ((st = schedule(lv, var.data(), used, target.data())) != MLMC_OK) return st;
+            for (int l = 0; l < L1; ++l) amount[l] = l < used && target[l] > counts[l] ? target[l] - counts[l] : 0;
+            if ((e = run_all(counts.data(), amount.data())) != hipSuccess) return device_fail(e, "extension launch");
+            for (int l = 0; l < L1; ++l) counts[l] += amount[l];
+            if (used >= 3) {
+                Moments fin;
+                if ((e = hipMemcpyAsync(&fin, state + L, sizeof(Moments), hipMemcpyDeviceToHost, stream)) !=
+                        hipSuccess ||
+                    (e = hipStreamSynchronize(stream)) != hipSuccess)
+                    return device_fail(e, "level mean readback");
+                passed = bias_test(lv, L, fabs(fin.mean), true);
+            }
+        }
+    } else if (lv->rmse_target > 0.0) {
         for (int l = 0; l < L1; ++l) amount[l] = lv->pilot_samples;
         if ((e = run_all(zero.data(), amount.data())) != hipSuccess) return device_fail(e, "pilot launch");
         for (int l = 0; l < L1; ++l) counts[l] = lv->pilot_samples;
@@ -312,7 +361,7 @@ mlmc_status mlmc_inner_product_estimate(int64_t n, const mlmc_dist* x, const mlm
             (e = hipStreamSynchronize(stream)) != hipSuccess)
             return device_fail(e, "pilot readback");
         std::vector<int64_t> target(L1);
-        if ((st = schedule(lv, var.data(), target.data())) != MLMC_OK) return st;
+        if ((st = schedule(lv, var.data(), L1, target.data())) != MLMC_OK) return st;
         for (int l = 0; l < L1; ++l) amount[l] = target[l] - counts[l];
         if ((e = run_all(counts.data(), amount.data())) != hipSuccess) return device_fail(e, "extension launch");
         for (int l = 0; l < L1; ++l) counts[l] = target[l];
@@ -330,7 +379,7 @@ mlmc_status mlmc_inner_product_estimate(int64_t n, const mlmc_dist* x, const mlm
         if ((e = hipMemcpyAsync(var.data(), var_dev, sizeof(double) * L1, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
             (e = hipStreamSynchronize(stream)) != hipSuccess)
             return device_fail(e, "report readback");
-        fill_report(lv, counts.data(), var.data(), timer, report);
+        fill_report(lv, counts.data(), var.data(), timer, report, used, passed);
     }
     return MLMC_OK;
 }
@@ -373,7 +422,45 @@ mlmc_status mlmc_matmul_estimate(int64_t m, int64_t n, int64_t p, const mlmc_dis
     auto run = [&](int l, int64_t k0, int64_t cnt, int64_t before) -> hipError_t {
         return matmul_level_run(plan, range_of(lv, l, k0, cnt), before, keys, ws, stream, timer);
     };
-    if (lv->rmse_target > 0.0) {
+    int used = L1;
+    bool passed = true;
+    if (lv->flags & MLMC_FLAG_ADAPTIVE_LEVELS) {
+        // Alg. 2's loop over L: pilot of the new level, eq. (28) over the
+        // levels so far, extension of every level, then the bias test
+        used = 0;
+        passed = false;
+        std::vector<int64_t> target(L1);
+        for (int L = 0; L < L1 && !passed; ++L) {
+            if ((e = run(L, 0, lv->pilot_samples, 0)) != hipSuccess) return device_fail(e, "pilot launch");
+            counts[L] = lv->pilot_samples;
+            used = L + 1;
+            {
+                ScopedTiming t(timer, MLMC_KERNEL_FINAL);
+                e = matmul_finalize(plan, counts.data(), ws, false, stream);
+            }
+            if (e != hipSuccess) return device_fail(e, "level statistics");
+            if ((e = hipMemcpyAsync(var.data(), var_dev, sizeof(double) * L1, hipMemcpyDeviceToHost, stream)) !=
+                    hipSuccess ||
+                (e = hipStreamSynchronize(stream)) != hipSuccess)
+                return device_fail(e, "level statistics readback");
+            if ((st = schedule(lv, var.data(), used, target.data())) != MLMC_OK) return st;
+            for (int l = 0; l < used; ++l) {
+                if (target[l] <= counts[l]) continue;
+                if ((e = run(l, counts[l], target[l] - counts[l], counts[l])) != hipSuccess)
+                    return device_fail(e, "extension launch");
+                counts[l] = target[l];
+            }
+            if (used >= 3) {
+                double norm2 = 0.0;
+                if ((e = matmul_level_norm2(plan, ws, L, stream)) != hipSuccess ||
+                    (e = hipMemcpyAsync(&norm2, matmul_norm_ptr(plan, ws), sizeof(double), hipMemcpyDeviceToHost,
+                                        stream)) != hipSuccess ||
+                    (e = hipStreamSynchronize(stream)) != hipSuccess)
+                    return device_fail(e, "level mean norm");
+                passed = bias_test(lv, L, sqrt(norm2), false);
+            }
+        }
+    } else if (lv->rmse_target > 0.0) {
         for (int l = 0; l < L1; ++l) {
             if ((e = run(l, 0, lv->pilot_samples, 0)) != hipSuccess) return device_fail(e, "pilot launch");
             counts[l] = lv->pilot_samples;
@@ -387,7 +474,7 @@ mlmc_status mlmc_matmul_estimate(int64_t m, int64_t n, int64_t p, const mlmc_dis
             (e = hipStreamSynchronize(stream)) != hipSuccess)
             return device_fail(e, "pilot readback");
         std::vector<int64_t> target(L1);
-        if ((st = schedule(lv, var.data(), target.data())) != MLMC_OK) return st;
+        if ((st = schedule(lv, var.data(), L1, target.data())) != MLMC_OK) return st;
         for (int l = 0; l < L1; ++l) {
             if ((e = run(l, counts[l], target[l] - counts[l], counts[l])) != hipSuccess)
                 return device_fail(e, "extension launch");
@@ -408,7 +495,7 @@ mlmc_status mlmc_matmul_estimate(int64_t m, int64_t n, int64_t p, const mlmc_dis
         if ((e = hipMemcpyAsync(var.data(), var_dev, sizeof(double) * L1, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
             (e = hipStreamSynchronize(stream)) != hipSuccess)
             return device_fail(e, "report readback");
-        fill_report(lv, counts.data(), var.data(), timer, report);
+        fill_report(lv, counts.data(), var.data(), timer, report, used, passed);
     }
     return MLMC_OK;
 }

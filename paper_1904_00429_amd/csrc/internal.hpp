@@ -109,8 +109,8 @@ struct MatmulPlan {
     int64_t kpad_max;
     int64_t sum_rows, sum_mp, sum_merge_blocks, total_tiles, max_mp, max_merge_blocks;
     int64_t groups_max, gather_bytes, state_doubles;
-    size_t off_means, off_between, off_within, off_tile_acc, off_var, off_desc, off_tile_owner, off_gather,
-        off_part_mean, off_part_m2, total;
+    size_t off_means, off_between, off_within, off_tile_acc, off_var, off_norm, off_desc, off_tile_owner,
+        off_gather, off_part_mean, off_part_m2, total;
     std::vector<ProblemDesc> descs;
     std::vector<int32_t> tile_owner;
 };
@@ -127,6 +127,9 @@ hipError_t matmul_level_run(const MatmulPlan& plan, const LevelRange& lr, int64_
 hipError_t matmul_finalize(const MatmulPlan& plan, const int64_t* counts, char* ws, bool write_outputs,
                            hipStream_t stream);
 double* matmul_level_var_ptr(const MatmulPlan& plan, char* ws);
+// ||Ybar_level||_F^2 of the first product into matmul_norm_ptr (device)
+hipError_t matmul_level_norm2(const MatmulPlan& plan, char* ws, int level, hipStream_t stream);
+double* matmul_norm_ptr(const MatmulPlan& plan, char* ws);
 
 hipError_t fill_doubles(double* p, int64_t count, double v, hipStream_t stream);
 

@@ -1046,6 +1046,7 @@ bool matmul_plan(const MatmulProblem* probs, int nprob, int prec, int num_levels
     plan.off_within = off;     off = align(off + sizeof(double) * L1 * nprob);
     plan.off_tile_acc = off;   off = align(off + sizeof(double) * L1 * tiles);
     plan.off_var = off;        off = align(off + sizeof(double) * L1 * nprob);
+    plan.off_norm = off;       off = align(off + sizeof(double));
     plan.state_doubles = (int64_t)(off / sizeof(double));
     plan.off_desc = off;       off = align(off + sizeof(ProblemDesc) * nprob);
     plan.off_tile_owner = off; off = align(off + sizeof(int32_t) * tiles);
@@ -1081,6 +1082,35 @@ hipError_t matmul_upload(const MatmulPlan& plan, char* ws, hipStream_t stream)
     // the sources are pageable host memory owned by `plan`: wait until the
     // copies have consumed them
     return hipStreamSynchronize(stream);
+}
+
+// Sum of squares of `count` doubles into *out: one workgroup, strided
+// per-thread sums then a tree (fixed order).
+__global__ __launch_bounds__(kMergeThreads) void sum_squares_kernel(const double* x, int64_t count, double* out)
+{
+    __shared__ double red[kMergeThreads];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < count; i += kMergeThreads) s = fma(x[i], x[i], s);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int half = kMergeThreads / 2; half > 0; half >>= 1) {
+        if ((int)threadIdx.x < half) red[threadIdx.x] += red[threadIdx.x + half];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+hipError_t matmul_level_norm2(const MatmulPlan& plan, char* ws, int level, hipStream_t stream)
+{
+    const double* means = reinterpret_cast<const double*>(ws + plan.off_means) + level * plan.sum_mp;
+    hipLaunchKernelGGL(sum_squares_kernel, dim3(1), dim3(kMergeThreads), 0, stream, means,
+                       plan.descs[0].m * plan.descs[0].p, reinterpret_cast<double*>(ws + plan.off_norm));
+    return hipGetLastError();
+}
+
+double* matmul_norm_ptr(const MatmulPlan& plan, char* ws)
+{
+    return reinterpret_cast<double*>(ws + plan.off_norm);
 }
 
 hipError_t matmul_reset(const MatmulPlan& plan, char* ws, hipStream_t stream)

@@ -18,6 +18,7 @@ from ._lib import Dist, Levels, MLMCError, Problem, Report, Tuning, check, lib
 
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "fp8": 3}
 FLAG_SHARED_SAMPLES = 1
+FLAG_ADAPTIVE_LEVELS = 4
 SHARED_LEVEL_FIELD = 0xFF
 
 
@@ -95,13 +96,15 @@ class Result:
     level_var: list
     rmse_est: float
     total_draws: int
+    levels_used: int = 0                   # levels run (all unless adaptive)
+    bias_test_passed: bool = True          # adaptive: stopped on the bias test
 
 
 class _LevelsHolder:
     """Keeps the ctypes arrays of a Levels struct alive."""
 
     def __init__(self, c, n_samples, rmse_target, pilot, seed, prec, shared, problem, max_total_draws,
-                 func: Optional[Func] = None):
+                 func: Optional[Func] = None, adaptive: bool = False):
         if prec not in PREC:
             raise ValueError(f"prec must be one of {sorted(PREC)}")
         self.c = (ctypes.c_int64 * len(c))(*[int(v) for v in c])
@@ -115,7 +118,7 @@ class _LevelsHolder:
         lv.max_total_draws = int(max_total_draws)
         lv.seed = int(seed) & (2**64 - 1)
         lv.prec = PREC[prec]
-        lv.flags = FLAG_SHARED_SAMPLES if shared else 0
+        lv.flags = (FLAG_SHARED_SAMPLES if shared else 0) | (FLAG_ADAPTIVE_LEVELS if adaptive else 0)
         lv.problem = int(problem)
         f = func or Func()
         lv.func = int(f.kind)
@@ -131,7 +134,7 @@ def _stream(device) -> int:
 def _result(Y, means, rep: Report, num_levels: int) -> Result:
     return Result(Y, means, [int(rep.n_used[l]) for l in range(num_levels)],
                   [float(rep.level_var[l]) for l in range(num_levels)], float(rep.rmse_est),
-                  int(rep.total_draws))
+                  int(rep.total_draws), int(rep.levels_used), bool(rep.bias_test_passed))
 
 
 def matmul_workspace_size(m, n, p, c, prec="fp64", n_samples=None, rmse_target=0.0, pilot=0,
@@ -145,11 +148,14 @@ def matmul_estimate(m: int, n: int, p: int, A: Law, B: Law, c: Sequence[int],
                     pilot: int = 0, seed: int = 0, prec: str = "fp64", shared: bool = False,
                     problem: int = 0, max_total_draws: int = 0, level_means: bool = False,
                     report: bool = True, device=None, workspace: Optional[torch.Tensor] = None,
-                    out: Optional[torch.Tensor] = None, func: Optional[Func] = None) -> Result:
+                    out: Optional[torch.Tensor] = None, func: Optional[Func] = None,
+                    adaptive: bool = False) -> Result:
     """MLMC estimate of E[f(AB)] on the GPU (mlmc_matmul_estimate; f = identity
-    unless func is given)."""
+    unless func is given; adaptive: number of levels chosen by the bias test,
+    c being the longest ladder allowed)."""
     device = torch.device(device or "cuda")
-    h = _LevelsHolder(c, n_samples, rmse_target, pilot, seed, prec, shared, problem, max_total_draws, func)
+    h = _LevelsHolder(c, n_samples, rmse_target, pilot, seed, prec, shared, problem, max_total_draws, func,
+                      adaptive)
     ws_bytes = int(lib().mlmc_matmul_workspace_size(int(m), int(n), int(p), ctypes.byref(h.lv)))
     if ws_bytes == 0:
         raise MLMCError(1, "invalid problem: no workspace size")
@@ -174,11 +180,13 @@ def inner_product_estimate(n: int, x: Law, y: Law, c: Sequence[int],
                            problem: int = 0, max_total_draws: int = 0, level_means: bool = False,
                            report: bool = True, device=None,
                            workspace: Optional[torch.Tensor] = None,
-                           out: Optional[torch.Tensor] = None, func: Optional[Func] = None) -> Result:
+                           out: Optional[torch.Tensor] = None, func: Optional[Func] = None,
+                           adaptive: bool = False) -> Result:
     """MLMC estimate of E[f(x^T y)] on the GPU (mlmc_inner_product_estimate;
-    f = identity unless func is given)."""
+    f = identity unless func is given; adaptive as for matmul_estimate)."""
     device = torch.device(device or "cuda")
-    h = _LevelsHolder(c, n_samples, rmse_target, pilot, seed, prec, shared, problem, max_total_draws, func)
+    h = _LevelsHolder(c, n_samples, rmse_target, pilot, seed, prec, shared, problem, max_total_draws, func,
+                      adaptive)
     ws_bytes = int(lib().mlmc_inner_product_workspace_size(int(n), ctypes.byref(h.lv)))
     if ws_bytes == 0:
         raise MLMCError(1, "invalid problem: no workspace size")

@@ -147,3 +147,15 @@ def test_adjoint_rejects_target_function(L):
                                        16, 16, 16, 1 << 40, None)
     assert st == 1
     assert b"identity" in L.mlmc_last_error()
+
+
+def test_adaptive_levels_need_target_mode(L):
+    lv, keep = _levels([2, 4, 8], [4, 4, 4])
+    lv.flags = 4
+    A, B = _dist(), _dist()
+    st = L.mlmc_matmul_estimate(4, 16, 3, ctypes.byref(A), ctypes.byref(B), ctypes.byref(lv), 8, None,
+                                16, 1 << 40, None, None)
+    assert st == 1 and b"adaptive" in L.mlmc_last_error()
+    st = L.mlmc_inner_product_estimate(16, ctypes.byref(A), ctypes.byref(B), ctypes.byref(lv), 8, None,
+                                       16, 1 << 40, None, None)
+    assert st == 1
