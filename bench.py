@@ -76,23 +76,36 @@ def parse():
                     help="skip the low-precision vs FP64 comparison of the matrix workloads")
     ap.add_argument("--cpu-fraction", type=float, default=0.15,
                     help="share of every level's realisations the CPU oracle runs")
+    ap.add_argument("--func", default="identity", choices=["identity", "abs_step", "inv_abs_step"],
+                    help="target function f of E[f(AB)]: |x| H(2 - x) or 1 / (|x| H(x + 0.4) + 0.01) (Sec. 4)")
+    ap.add_argument("--adaptive", action="store_true",
+                    help="choose the number of levels by the bias test (the workload's ladder is the longest)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, run one device copy of 1 GiB (counter calibration)")
     return ap.parse_args()
 
 
-def cpu_baseline_inner(wl, n_used, fraction):
+def _oracle_func(oracle, name):
+    return {"identity": None, "abs_step": oracle.Func.abs_step(2.0),
+            "inv_abs_step": oracle.Func.inv_abs_step(0.4, 0.01)}[name]
+
+
+def cpu_baseline_inner(wl, n_used, fraction, func="identity"):
     """The oracle (single-threaded C) on the first `fraction` of every level's
     realisations of the same workload; scaled to estimates/s."""
     import oracle
     oracle.build(force=False)
     law = oracle.Law.uniform(wl.law_a[1], wl.law_a[2])
+    f = _oracle_func(oracle, func)
     t0 = time.perf_counter()
     draws = 0
     for l, N in enumerate(n_used):
+        if N == 0:
+            continue
         k = max(2, int(round(N * fraction)))
         st = oracle.LevelState.empty(1, 1)
-        oracle.level_estimation(st, 1, wl.n, 1, law, law, wl.c[l], wl.c[l - 1] if l else 0, wl.seed, 0, l, 0, k)
+        oracle.level_estimation(st, 1, wl.n, 1, law, law, wl.c[l], wl.c[l - 1] if l else 0, wl.seed, 0, l, 0, k,
+                                func=f)
         draws += k * wl.c[l]
     dt = time.perf_counter() - t0
     total_draws = sum(N * c for N, c in zip(n_used, wl.c))
@@ -102,7 +115,7 @@ def cpu_baseline_inner(wl, n_used, fraction):
                       f"realisations), {dt:.1f} s, scaled by draws"}
 
 
-def cpu_baseline_matmul(wl, n_used, fraction, edge=256):
+def cpu_baseline_matmul(wl, n_used, fraction, edge=256, func="identity"):
     """The oracle (one core) on the same ladder, laws and N_l with m = p = edge.
 
     A full-shape realisation of the finest level costs the oracle minutes, so
@@ -113,16 +126,19 @@ def cpu_baseline_matmul(wl, n_used, fraction, edge=256):
     import oracle
     oracle.build(force=False)
     law = oracle.Law.normal(wl.law_a[1], wl.law_a[2])
+    f = _oracle_func(oracle, func)
     m, p = min(edge, wl.m), min(edge, wl.p)
     total = 0.0
     run = 0
     t_all = time.perf_counter()
     for l, N in enumerate(n_used):
+        if N == 0:
+            continue
         k = max(1, int(round(N * fraction)))
         st = oracle.LevelState.empty(m, p)
         t0 = time.perf_counter()
         oracle.level_estimation(st, m, wl.n, p, law, law, wl.c[l], wl.c[l - 1] if l else 0,
-                                wl.seed, 0, l, 0, k)
+                                wl.seed, 0, l, 0, k, func=f)
         total += N * (time.perf_counter() - t0) / k
         run += k
     total *= (wl.m * wl.p) / float(m * p)
@@ -147,6 +163,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.init()
     timing_flag = 2
+    _OPTS["func"] = _func_of(args.func)
+    _OPTS["adaptive"] = bool(args.adaptive)
     if args.workload == "diff":
         return bench_diff(args)
     if args.workload == "batched":
@@ -183,9 +201,12 @@ def main():
     ms_per_step = 1e3 * elapsed / args.steps
     value = args.steps / elapsed
 
-    # achieved accuracy against the exact E[AB] (closed form of the synthetic law)
-    errs = [float(torch.linalg.norm(r.Y - expected)) for r in results]
-    rmse_obs = math.sqrt(sum(e * e for e in errs) / len(errs))
+    # achieved accuracy against the exact E[AB] (closed form of the synthetic
+    # law; no closed form for a nonlinear f)
+    rmse_obs = None
+    if args.func == "identity" and not args.adaptive:
+        errs = [float(torch.linalg.norm(r.Y - expected)) for r in results]
+        rmse_obs = math.sqrt(sum(e * e for e in errs) / len(errs))
     rep = results[-1]
     k_ms = [sum(r.kernel_ms[i] for r in results) for i in range(4)]
     k_n = [sum(r.kernel_launches[i] for r in results) for i in range(4)]
@@ -203,7 +224,7 @@ def main():
                 "ops_per_draw": slots_per_draw_inner(wl.n)}
         config = {"workload": wl.name, "n": wl.n, "levels": len(wl.c), "c0": wl.c[0], "ratio": 2,
                   "eps": wl.rmse_target, "pilot": wl.pilot, "law": "0.5 + U(-1, 1) i.i.d.",
-                  "prec": prec}
+                  "prec": prec, "func": args.func, "adaptive": bool(args.adaptive)}
     else:
         # dominant: the sketch (MFMA) kernel; algorithmic flops 2 m p per draw
         flops = 2.0 * wl.m * wl.p * draws
@@ -216,25 +237,26 @@ def main():
                 "gather_ms_per_step": k_ms[1] / args.steps, "sketch_ms_per_step": k_ms[0] / args.steps,
                 "merge_ms_per_step": k_ms[2] / args.steps}
         config = {"workload": wl.name, "m": wl.m, "n": wl.n, "p": wl.p, "levels": len(wl.c), "c0": wl.c[0],
-                  "ratio": 2, "eps": wl.rmse_target, "pilot": wl.pilot, "prec": prec}
+                  "ratio": 2, "eps": wl.rmse_target, "pilot": wl.pilot, "prec": prec, "func": args.func,
+                  "adaptive": bool(args.adaptive)}
 
     out = {"metric": METRIC, "value": value, "unit": "estimates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16"}[prec],
            "data": "synthetic (entries generated inside the estimate)", "config": config, "roofline": roof,
            "n_used": rep.n_used, "draws_per_step": draws / args.steps, "rmse_est": rep.rmse_est,
-           "rmse_observed": rmse_obs, "kernel_ms_per_step": {
+           "rmse_observed": rmse_obs, "levels_used": rep.levels_used, "kernel_ms_per_step": {
                "sample": k_ms[0] / args.steps, "gather": k_ms[1] / args.steps, "merge": k_ms[2] / args.steps,
                "final": k_ms[3] / args.steps}}
 
-    if args.workload != "inner" and prec != "fp64" and not args.no_precision_check:
+    if args.workload != "inner" and prec != "fp64" and not args.no_precision_check and not args.adaptive:
         # precision form: the same estimate (seed 0, the N_l of the last step,
         # fixed mode) in the low precision and in FP64, outside the timed region
         from paper_1904_00429_amd import matmul_estimate
         ys = {}
         for pr in (prec, "fp64"):
             ys[pr] = matmul_estimate(wl.m, wl.n, wl.p, a, a, wl.c, n_samples=rep.n_used, seed=0, prec=pr,
-                                     device=dev, report=True)
+                                     device=dev, report=True, func=_OPTS["func"])
         out["precision_check"] = {
             "lp_minus_fp64_frob": float(torch.linalg.norm(ys[prec].Y - ys["fp64"].Y)),
             "rmse_est_fp64": ys["fp64"].rmse_est, "seed": 0, "n_samples": rep.n_used}
@@ -250,9 +272,9 @@ def main():
 
     if not args.no_cpu_baseline:
         if args.workload == "inner":
-            out["cpu_baseline"] = cpu_baseline_inner(wl, rep.n_used, args.cpu_fraction)
+            out["cpu_baseline"] = cpu_baseline_inner(wl, rep.n_used, args.cpu_fraction, args.func)
         else:
-            out["cpu_baseline"] = cpu_baseline_matmul(wl, rep.n_used, 0.001)
+            out["cpu_baseline"] = cpu_baseline_matmul(wl, rep.n_used, 0.001, func=args.func)
     print(json.dumps(out), flush=True)
 
 
@@ -361,7 +383,8 @@ def bench_batched(args):
 
 def bench_large_fixed(args):
     """1024 x 65536 x 1024 at the N_l a target-RMSE run chose, through the
-    table pipeline with each tile shape, BF16 and FP32 (sketch-kernel study)."""
+    table pipeline with each tile shape, BF16 and FP32 (sketch-kernel study;
+    with --func, the target-function form at the same N_l)."""
     import torch
     from paper_1904_00429_amd import BatchedEstimate, BatchProblem, Law, workloads
     dev = torch.device("cuda:0")
@@ -371,9 +394,11 @@ def bench_large_fixed(args):
     flops = 2.0 * wl.m * wl.p * draws
     prob = [BatchProblem(wl.m, wl.n, wl.p, Law.normal(0.5, 1.0), Law.normal(0.5, 1.0), 0)]
     res = {}
+    func = _func_of(args.func)
     for prec in ("bf16", "fp32"):
-        for tile in (64, 128):
-            est = BatchedEstimate(prob, wl.c, N, seed=0, prec=prec, tuning={"tile": tile}, device=dev)
+        # a target function always runs the tile-64 sketch
+        for tile in ((64, 128) if func is None else (64,)):
+            est = BatchedEstimate(prob, wl.c, N, seed=0, prec=prec, tuning={"tile": tile}, device=dev, func=func)
             est.run()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -385,10 +410,17 @@ def bench_large_fixed(args):
                                          "mfma_tflops_whole_pipeline": flops / sec / 1e12}
             del est
             torch.cuda.empty_cache()
-    print(json.dumps({"workload": "matmul-1024x65536x1024-fixedN", "N": N, "results": res}), flush=True)
+    print(json.dumps({"workload": "matmul-1024x65536x1024-fixedN", "func": args.func, "N": N, "results": res}),
+          flush=True)
 
 
 _WS = {}
+_OPTS = {"func": None, "adaptive": False}
+
+
+def _func_of(name):
+    from paper_1904_00429_amd import Func
+    return {"identity": None, "abs_step": Func.abs_step(2.0), "inv_abs_step": Func.inv_abs_step(0.4, 0.01)}[name]
 
 
 def _inner(api, wl, x, prec, dev, want_timing, seed):
@@ -402,7 +434,8 @@ def _inner(api, wl, x, prec, dev, want_timing, seed):
 
 def _call_inner(api, wl, x, prec, dev, ws, out, want_timing, seed):
     import ctypes
-    h = api._LevelsHolder(wl.c, None, wl.rmse_target, wl.pilot, seed, prec, False, 0, 0)
+    h = api._LevelsHolder(wl.c, None, wl.rmse_target, wl.pilot, seed, prec, False, 0, 0, _OPTS["func"],
+                          _OPTS["adaptive"])
     if want_timing:
         h.lv.flags |= 2
     lib = api.lib()
@@ -420,7 +453,8 @@ def _matmul(api, wl, a, prec, dev, want_timing, seed):
     import ctypes
     import torch
     h = api._LevelsHolder(wl.c, wl.n_samples, wl.rmse_target if wl.n_samples is None else 0.0,
-                          wl.pilot, seed, prec, False, 0, 0)
+                          wl.pilot, seed, prec, False, 0, 0, _OPTS["func"],
+                          _OPTS["adaptive"] and wl.n_samples is None)
     if want_timing:
         h.lv.flags |= 2
     lib = api.lib()
@@ -447,6 +481,7 @@ class _Rep:
         self.total_draws = int(rep.total_draws)
         self.kernel_ms = [float(rep.kernel_ms[i]) for i in range(4)]
         self.kernel_launches = [int(rep.kernel_launches[i]) for i in range(4)]
+        self.levels_used = int(rep.levels_used)
 
 
 if __name__ == "__main__":
