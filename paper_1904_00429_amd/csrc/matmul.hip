@@ -285,6 +285,28 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
                 }
             }
         }
+        if constexpr (KPACK == 1) {
+            // rows 4q .. 4q+3 of one position are adjacent: one vector store
+            // per position when the quad lies in A, or in B at an aligned row
+            const bool in_a = e0 + 3 < m;
+            const bool in_b = e0 >= m && e0 + 3 < rows && ((e0 - m) & 3) == 0;
+            if (in_a || in_b) {
+                typedef Store vec4_t __attribute__((ext_vector_type(4)));
+                Store* G = in_a ? GA : GB;
+                const int64_t R = in_a ? m_pad : p_pad;
+                const int64_t row = in_a ? e0 : e0 - m;
+#pragma unroll
+                for (int ip = 0; ip < kGatherPositions; ++ip) {
+                    if (ip < npos) {
+                        vec4_t vv;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) vv[r] = vals[ip][r];
+                        *reinterpret_cast<vec4_t*>(G + (pos0 + ip) * R + row) = vv;
+                    }
+                }
+                return;
+            }
+        }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int64_t e = e0 + r;
