@@ -89,17 +89,38 @@ __global__ __launch_bounds__(kAdjGatherThreads) void adjoint_gather_kernel(AdjGa
                 nrm[ip][r] = z[r];
             }
         }
+        // K-major values: a row's eight positions are adjacent (two 16-byte
+        // stores; kpad and pos0 are multiples of 8)
         for (int r = 0; r < 4; ++r) {
             const int64_t e = 4 * q + r;
             if (e >= rows) break;
             const bool in_a = e < prm.m;
             const int64_t row = in_a ? e : e - prm.m;
-            float* T = in_a ? AT + row * prm.kpad : BT + row * prm.kpad;
-            float* N = in_a ? ZS : WS;
-            const int64_t R = in_a ? prm.m : prm.p;
-            for (int ip = 0; ip < kAdjPositions; ++ip) {
-                T[pos0 + ip] = val[ip][r];
-                N[(pos0 + ip) * R + row] = nrm[ip][r];
+            float4* T = reinterpret_cast<float4*>((in_a ? AT + row * prm.kpad : BT + row * prm.kpad) + pos0);
+            T[0] = make_float4(val[0][r], val[1][r], val[2][r], val[3][r]);
+            T[1] = make_float4(val[4][r], val[5][r], val[6][r], val[7][r]);
+        }
+        // position-major normals: the quad's four rows are adjacent (one
+        // 16-byte store per position when the row count keeps them aligned)
+        const int64_t e0 = 4 * q;
+        const bool quad_a = e0 + 3 < prm.m && (prm.m & 3) == 0;
+        const bool quad_b = e0 >= prm.m && e0 + 3 < rows && (prm.m & 3) == 0 && (prm.p & 3) == 0;
+        if (quad_a || quad_b) {
+            float* N = quad_a ? ZS : WS;
+            const int64_t R = quad_a ? prm.m : prm.p;
+            const int64_t row = quad_a ? e0 : e0 - prm.m;
+            for (int ip = 0; ip < kAdjPositions; ++ip)
+                *reinterpret_cast<float4*>(N + (pos0 + ip) * R + row) =
+                    make_float4(nrm[ip][0], nrm[ip][1], nrm[ip][2], nrm[ip][3]);
+        } else {
+            for (int r = 0; r < 4; ++r) {
+                const int64_t e = e0 + r;
+                if (e >= rows) break;
+                const bool in_a = e < prm.m;
+                float* N = in_a ? ZS : WS;
+                const int64_t R = in_a ? prm.m : prm.p;
+                const int64_t row = in_a ? e : e - prm.m;
+                for (int ip = 0; ip < kAdjPositions; ++ip) N[(pos0 + ip) * R + row] = nrm[ip][r];
             }
         }
     }
