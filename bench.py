@@ -280,7 +280,8 @@ def main():
 
 def bench_diff(args):
     """Differentiation form: loss = ||Y - T||_F^2 of the reparameterised
-    estimate, forward + hand-written adjoint per step (FP32)."""
+    estimate, forward + hand-written adjoint per step (FP32, or --prec bf16:
+    BF16 operands on MFMA in both)."""
     import torch
     from paper_1904_00429_amd import mlmc_matmul, workloads
     import paper_1904_00429_amd.mlmc as api
@@ -289,11 +290,14 @@ def bench_diff(args):
     MA, SA, MB, SB, T = workloads.reparam_inputs(wl.m, wl.n, wl.p, seed=0)
     leaves = [torch.from_numpy(x).to(dev).requires_grad_(True) for x in (MA, SA, MB, SB)]
     Tt = torch.from_numpy(T).to(dev, torch.float64)
+    prec = args.prec or "fp32"
+    if prec not in ("fp32", "bf16"):
+        raise SystemExit("the differentiation form runs in fp32 or bf16")
 
     def step(seed):
         for t in leaves:
             t.grad = None
-        Y = mlmc_matmul(*leaves, wl.c, wl.n_samples, seed=seed, prec="fp32")
+        Y = mlmc_matmul(*leaves, wl.c, wl.n_samples, seed=seed, prec=prec)
         loss = ((Y - Tt) ** 2).sum()
         loss.backward()
         return loss
@@ -308,25 +312,23 @@ def bench_diff(args):
     elapsed = time.perf_counter() - t0
     # one timed adjoint call with the library's event timing, for the roofline
     import ctypes
-    h = api._LevelsHolder(wl.c, wl.n_samples, 0.0, 0, 0, "fp32", False, 0, 0)
-    h.lv.flags |= 2
     draws = sum(N * c for N, c in zip(wl.n_samples, wl.c))
     flops = 2.0 * 2.0 * wl.m * wl.p * draws
     t1 = time.perf_counter()
     grads = api.matmul_adjoint_reparam(*[t.detach() for t in leaves], wl.c, wl.n_samples,
-                                       torch.ones((wl.m, wl.p), dtype=torch.float64, device=dev))
+                                       torch.ones((wl.m, wl.p), dtype=torch.float64, device=dev), prec=prec)
     torch.cuda.synchronize()
     adj_ms = 1e3 * (time.perf_counter() - t1)
     out = {"metric": "MLMC product estimates/s with gradients (forward + adjoint)", "value": args.steps / elapsed,
            "unit": "estimates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "vs_baseline": None, "dtype": {"fp32": "f32", "bf16": "bf16"}[prec], "data": "synthetic",
            "config": {"workload": wl.name, "m": wl.m, "n": wl.n, "p": wl.p, "levels": len(wl.c), "c0": wl.c[0],
-                      "n_samples": wl.n_samples},
+                      "n_samples": wl.n_samples, "prec": prec},
            "adjoint_ms_wall": adj_ms,
            "adjoint_roofline": {"bound": "mfma", "achieved": flops / (adj_ms * 1e-3) / 1e12,
-                                "peak": PEAK_MFMA["fp32"] / 1e12, "unit": "TFLOP/s",
-                                "frac": flops / (adj_ms * 1e-3) / PEAK_MFMA["fp32"], "draws": draws}}
+                                "peak": PEAK_MFMA[prec] / 1e12, "unit": "TFLOP/s",
+                                "frac": flops / (adj_ms * 1e-3) / PEAK_MFMA[prec], "draws": draws}}
     print(json.dumps(out), flush=True)
 
 

@@ -241,10 +241,13 @@ mlmc_status mlmc_graph_destroy(mlmc_graph graph);
  *             ld = A->ld); dMB, dSB: layout of B's (row-major n x p, ld = B->ld).
  *             Gradients are ADDED (FP32 atomics, so the last bits depend on
  *             the order in which workgroups finish); zero them first.
- * Arithmetic: FP32 (values, MFMA contraction, accumulation).
+ * Arithmetic (levels->prec): MLMC_PREC_FP32 — FP32 values, FP32 MFMA
+ * contraction and accumulation; MLMC_PREC_BF16 — the regenerated values and
+ * G rounded to BF16 (nearest even), BF16 MFMA, FP32 accumulation and FP32
+ * gradients.  Other precisions: MLMC_EINVAL.
  * Errors: EINVAL (laws not reparameterised, target mode, f other than the
- * identity, null pointers, and the conditions of mlmc_matmul_estimate),
- * EWORKSPACE, EDEVICE. */
+ * identity, precision other than FP32/BF16, null pointers, and the
+ * conditions of mlmc_matmul_estimate), EWORKSPACE, EDEVICE. */
 size_t mlmc_matmul_adjoint_workspace_size(int64_t m, int64_t n, int64_t p, const mlmc_levels* levels);
 mlmc_status mlmc_matmul_adjoint_reparam(int64_t m, int64_t n, int64_t p, const mlmc_dist* A,
                                         const mlmc_dist* B, const mlmc_levels* levels,

@@ -22,15 +22,17 @@ class MLMCMatmul(torch.autograd.Function):
                               n_samples=list(n_samples), seed=seed, prec=prec, problem=problem,
                               report=False, device=MA.device)
         ctx.save_for_backward(MA, SA, MB, SB)
-        ctx.cfg = (list(c), list(n_samples), seed, problem)
+        ctx.cfg = (list(c), list(n_samples), seed, problem, prec)
         return res.Y
 
     @staticmethod
     def backward(ctx, grad_out):
         MA, SA, MB, SB = ctx.saved_tensors
-        c, n_samples, seed, problem = ctx.cfg
+        c, n_samples, seed, problem, prec = ctx.cfg
+        # a BF16 forward gets the BF16-operand adjoint; every other form the FP32 one
         dMA, dSA, dMB, dSB = matmul_adjoint_reparam(MA.detach(), SA.detach(), MB.detach(), SB.detach(),
-                                                    c, n_samples, grad_out, seed=seed, problem=problem)
+                                                    c, n_samples, grad_out, seed=seed, problem=problem,
+                                                    prec="bf16" if prec == "bf16" else "fp32")
         return dMA, dSA, dMB, dSB, None, None, None, None, None
 
 

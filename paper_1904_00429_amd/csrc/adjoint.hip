@@ -45,8 +45,17 @@ struct AdjGatherParams {
     float* ZS;                    // batch x kpad x m
     float* WS;                    // batch x kpad x p
     int32_t* R;                   // batch x kpad (-1 for padding)
+    // BF16 form: the values position-major instead of AT/BT, element (t, i)
+    // at t mk + i (mk, pk: m and p rounded up to 8)
+    __bf16* ASb;                  // batch x kpad x mk
+    __bf16* BSb;                  // batch x kpad x pk
+    int64_t mk, pk;
 };
 
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <bool BF16>
 __global__ __launch_bounds__(kAdjGatherThreads) void adjoint_gather_kernel(AdjGatherParams prm)
 {
     __shared__ uint32_t cols[kAdjPositions];
@@ -89,20 +98,50 @@ __global__ __launch_bounds__(kAdjGatherThreads) void adjoint_gather_kernel(AdjGa
                 nrm[ip][r] = z[r];
             }
         }
-        // K-major values: a row's eight positions are adjacent (two 16-byte
-        // stores; kpad and pos0 are multiples of 8)
-        for (int r = 0; r < 4; ++r) {
-            const int64_t e = 4 * q + r;
-            if (e >= rows) break;
-            const bool in_a = e < prm.m;
-            const int64_t row = in_a ? e : e - prm.m;
-            float4* T = reinterpret_cast<float4*>((in_a ? AT + row * prm.kpad : BT + row * prm.kpad) + pos0);
-            T[0] = make_float4(val[0][r], val[1][r], val[2][r], val[3][r]);
-            T[1] = make_float4(val[4][r], val[5][r], val[6][r], val[7][r]);
+        const int64_t e0 = 4 * q;
+        if constexpr (BF16) {
+            // position-major BF16 values (round to nearest even): the quad's
+            // four rows are adjacent, one 8-byte store per position when they
+            // lie in A, or in B at a row that is a multiple of 4
+            __bf16* AS = prm.ASb + slot * prm.kpad * prm.mk;
+            __bf16* BS = prm.BSb + slot * prm.kpad * prm.pk;
+            const bool qa = e0 + 3 < prm.m;
+            const bool qb = e0 >= prm.m && e0 + 3 < rows && ((e0 - prm.m) & 3) == 0;
+            if (qa || qb) {
+                __bf16* V = qa ? AS : BS;
+                const int64_t st = qa ? prm.mk : prm.pk;
+                const int64_t row = qa ? e0 : e0 - prm.m;
+                for (int ip = 0; ip < kAdjPositions; ++ip) {
+                    bf16x4 v;
+                    for (int r = 0; r < 4; ++r) v[r] = (__bf16)val[ip][r];
+                    *reinterpret_cast<bf16x4*>(V + (pos0 + ip) * st + row) = v;
+                }
+            } else {
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t e = e0 + r;
+                    if (e >= rows) break;
+                    const bool in_a = e < prm.m;
+                    __bf16* V = in_a ? AS : BS;
+                    const int64_t st = in_a ? prm.mk : prm.pk;
+                    const int64_t row = in_a ? e : e - prm.m;
+                    for (int ip = 0; ip < kAdjPositions; ++ip) V[(pos0 + ip) * st + row] = (__bf16)val[ip][r];
+                }
+            }
+        } else {
+            // K-major values: a row's eight positions are adjacent (two 16-byte
+            // stores; kpad and pos0 are multiples of 8)
+            for (int r = 0; r < 4; ++r) {
+                const int64_t e = e0 + r;
+                if (e >= rows) break;
+                const bool in_a = e < prm.m;
+                const int64_t row = in_a ? e : e - prm.m;
+                float4* T = reinterpret_cast<float4*>((in_a ? AT + row * prm.kpad : BT + row * prm.kpad) + pos0);
+                T[0] = make_float4(val[0][r], val[1][r], val[2][r], val[3][r]);
+                T[1] = make_float4(val[4][r], val[5][r], val[6][r], val[7][r]);
+            }
         }
         // position-major normals: the quad's four rows are adjacent (one
         // 16-byte store per position when the row count keeps them aligned)
-        const int64_t e0 = 4 * q;
         const bool quad_a = e0 + 3 < prm.m && (prm.m & 3) == 0;
         const bool quad_b = e0 >= prm.m && e0 + 3 < rows && (prm.m & 3) == 0 && (prm.p & 3) == 0;
         if (quad_a || quad_b) {
@@ -266,6 +305,114 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_mfma_kernel(AdjMfmaParams
     }
 }
 
+// BF16 form of the same tiles: both operands are K-contiguous, so a lane's
+// fragment (8 consecutive K of its row t or column x) is one 16-byte load
+// from global memory (L2-resident: the values of one realisation and G),
+// and v_mfma_f32_32x32x16_bf16 accumulates in FP32.  t operand: the
+// position-major BF16 values of the other matrix ([t][K], row stride KS);
+// x operand: G (for U^T, [i][q]) or G^T (for V, [q][i]) in BF16, stride KS.
+// The accumulator layout is that of the FP32 kernel, so is the epilogue.
+struct AdjBf16Params {
+    int64_t m, p, kpad, mk, pk;
+    uint32_t c_prev;
+    float kappa_coarse, kappa_fine;
+    const __bf16* Gb;                 // m x pk: G
+    const __bf16* GTb;                // p x mk: G^T
+    const __bf16* ASb;                // batch x kpad x mk
+    const __bf16* BSb;                // batch x kpad x pk
+    const float* ZS;                  // batch x kpad x m
+    const float* WS;                  // batch x kpad x p
+    const int32_t* R;                 // batch x kpad
+    int64_t tiles_t, tiles_u_cols, tiles_v_cols;
+    float* dMA; float* dSA;
+    float* dMB; float* dSB;
+};
+
+// 8 consecutive K values of one row (stride KS), zero beyond K or for an
+// absent row; KS and k0 are multiples of 8, so the vector is aligned.
+__device__ __forceinline__ bf16x8 adj_frag(const __bf16* base, int64_t row, bool row_ok, int k0, int K, int64_t KS)
+{
+    bf16x8 v;
+    if (row_ok && k0 + 8 <= K) {
+        v = *reinterpret_cast<const bf16x8*>(base + row * KS + k0);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = (row_ok && k0 + i < K) ? base[row * KS + k0 + i] : (__bf16)0.0f;
+    }
+    return v;
+}
+
+__global__ __launch_bounds__(kAdjThreads) void adjoint_mfma_bf16_kernel(AdjBf16Params prm)
+{
+    const int lane = threadIdx.x % kWave;
+    const int wave = threadIdx.x / kWave;
+    const int64_t s = blockIdx.y;
+    int64_t tile = blockIdx.x;
+    const int64_t u_tiles = prm.tiles_t * prm.tiles_u_cols;
+    const bool is_u = tile < u_tiles;
+    if (!is_u) tile -= u_tiles;
+    const int64_t cols_tiles = is_u ? prm.tiles_u_cols : prm.tiles_v_cols;
+    const int tb = (int)(tile / cols_tiles) * kAdjTileT;
+    const int xb = (int)(tile % cols_tiles) * kAdjTileX;
+    const int wt = (wave / 2) * 32, wx = (wave % 2) * 64;
+    const int K = (int)(is_u ? prm.p : prm.m);
+    const int X = (int)(is_u ? prm.m : prm.p);
+    const int64_t KS = is_u ? prm.pk : prm.mk;
+    const int kpad = (int)prm.kpad;
+    const __bf16* Aop = is_u ? prm.BSb + s * prm.kpad * prm.pk : prm.ASb + s * prm.kpad * prm.mk;
+    const __bf16* Bop = is_u ? prm.Gb : prm.GTb;
+    const int t = tb + wt + lane % 32;
+    const int x0 = xb + wx + lane % 32, x1 = x0 + 32;
+    const bool t_ok = t < kpad, x0_ok = x0 < X, x1_ok = x1 < X;
+    const int koff = 8 * (lane / 32);
+
+    f32x16 acc[2];
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[bj][r] = 0.0f;
+#pragma unroll 2
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        const bf16x8 a = adj_frag(Aop, t, t_ok, k0 + koff, K, KS);
+        const bf16x8 b0 = adj_frag(Bop, x0, x0_ok, k0 + koff, K, KS);
+        const bf16x8 b1 = adj_frag(Bop, x1, x1_ok, k0 + koff, K, KS);
+        acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc[1], 0, 0, 0);
+    }
+    const int32_t* R = prm.R + s * prm.kpad;
+    const float* N = is_u ? prm.ZS + s * prm.kpad * prm.m : prm.WS + s * prm.kpad * prm.p;
+    float* dM = is_u ? prm.dMA : prm.dMB;
+    float* dS = is_u ? prm.dSA : prm.dSB;
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+        const int x = xb + wx + bj * 32 + lane % 32;
+        if (x >= X) continue;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int tt = tb + wt + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
+            if (tt >= kpad) continue;
+            const int32_t col = R[tt];
+            if (col < 0) continue;
+            const float kappa = tt < (int)prm.c_prev ? prm.kappa_coarse : prm.kappa_fine;
+            const float g = kappa * acc[bj][r];
+            unsafeAtomicAdd(dM + (int64_t)col * X + x, g);
+            unsafeAtomicAdd(dS + (int64_t)col * X + x, g * N[(int64_t)tt * X + x]);
+        }
+    }
+}
+
+// G and G^T in BF16 (round to nearest even), K-contiguous with padded strides
+__global__ void grad_prepare_bf16_kernel(const double* grad, int64_t m, int64_t p, int64_t mk, int64_t pk,
+                                         __bf16* Gb, __bf16* GTb)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m * p) return;
+    const int64_t i = e / p, q = e % p;
+    const __bf16 v = (__bf16)(float)grad[e];
+    Gb[i * pk + q] = v;
+    GTb[q * mk + i] = v;
+}
+
 __global__ void grad_prepare_kernel(const double* grad, int64_t m, int64_t p, float* G, float* GT)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -278,37 +425,62 @@ __global__ void grad_prepare_kernel(const double* grad, int64_t m, int64_t p, fl
 
 static int64_t round_up_adj(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 
+// Head of the workspace: G and G^T in FP32, then in BF16 (padded strides).
+static size_t adj_head_bytes(int64_t m, int64_t p)
+{
+    auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const int64_t mk = round_up_adj(m, 8), pk = round_up_adj(p, 8);
+    return align(2 * m * p * sizeof(float)) + align((size_t)(m * pk + p * mk) * sizeof(__bf16));
+}
+
+// Bytes per draw position of the gathered values of A (or B): FP32 K-major
+// or BF16 position-major with the row padded to 8, whichever is larger.
+static int64_t adj_value_bytes(int64_t rows)
+{
+    const int64_t f32 = 4 * rows, b16 = 2 * round_up_adj(rows, 8);
+    return f32 > b16 ? f32 : b16;
+}
+
 size_t adjoint_workspace_size(int64_t m, int64_t p, int num_levels, const int64_t* c)
 {
     const int64_t kpad = round_up_adj(c[num_levels - 1], kAdjPositions);
-    const int64_t per_sample = kpad * (2 * (m + p) * 4 + 4);
+    const int64_t per_sample = kpad * (adj_value_bytes(m) + adj_value_bytes(p) + (m + p) * 4 + 4);
     int64_t budget = kAdjBudget < per_sample ? per_sample : kAdjBudget;
-    size_t total = (size_t)budget + 1024;
-    total += (size_t)(2 * m * p * 4 + 256);
+    // slack for the five 256-byte-aligned regions of a pass
+    size_t total = (size_t)budget + 2048;
+    total += adj_head_bytes(m, p);
     return total;
 }
 
 hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law& B, int num_levels,
                        const int64_t* c, const int64_t* N, const StreamKeys& keys, bool shared,
                        const double* grad, float* dMA, float* dSA, float* dMB, float* dSB, char* ws,
-                       size_t ws_bytes, hipStream_t stream, KernelTimer* timer)
+                       size_t ws_bytes, bool bf16, hipStream_t stream, KernelTimer* timer)
 {
     auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const int64_t mk = round_up_adj(m, 8), pk = round_up_adj(p, 8);
     float* G = reinterpret_cast<float*>(ws);
     float* GT = G + m * p;
-    char* buf = ws + align(2 * m * p * sizeof(float));
-    const size_t budget = ws_bytes - align(2 * m * p * sizeof(float));
+    __bf16* Gb = reinterpret_cast<__bf16*>(ws + align(2 * m * p * sizeof(float)));
+    __bf16* GTb = Gb + m * pk;
+    const size_t head = adj_head_bytes(m, p);
+    char* buf = ws + head;
+    const size_t budget = ws_bytes - head;
     {
         ScopedTiming t(timer, 3);
-        hipLaunchKernelGGL(grad_prepare_kernel, dim3((unsigned)ceil_div(m * p, 256)), dim3(256), 0, stream, grad, m,
-                           p, G, GT);
+        if (bf16)
+            hipLaunchKernelGGL(grad_prepare_bf16_kernel, dim3((unsigned)ceil_div(m * p, 256)), dim3(256), 0, stream,
+                               grad, m, p, mk, pk, Gb, GTb);
+        else
+            hipLaunchKernelGGL(grad_prepare_kernel, dim3((unsigned)ceil_div(m * p, 256)), dim3(256), 0, stream, grad,
+                               m, p, G, GT);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     for (int l = 0; l < num_levels; ++l) {
         const int64_t cl = c[l], cp = l > 0 ? c[l - 1] : 0;
         const int64_t kpad = round_up_adj(cl, kAdjPositions);
-        const size_t per_sample = (size_t)kpad * (2 * (m + p) * 4 + 4) + 5 * 256;
+        const size_t per_sample = (size_t)kpad * (adj_value_bytes(m) + adj_value_bytes(p) + (m + p) * 4 + 4) + 5 * 256;
         int64_t batch = (int64_t)(budget / per_sample);
         if (batch < 1) batch = 1;
         if (batch > 65535) batch = 65535;
@@ -318,8 +490,11 @@ hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law&
         for (int64_t b0 = 0; b0 < N[l]; b0 += batch) {
             const int64_t S = (N[l] - b0) < batch ? (N[l] - b0) : batch;
             size_t off = 0;
-            float* AT = reinterpret_cast<float*>(buf + off); off = align(off + sizeof(float) * S * m * kpad);
-            float* BT = reinterpret_cast<float*>(buf + off); off = align(off + sizeof(float) * S * p * kpad);
+            // FP32: K-major AT, BT; BF16: position-major ASb, BSb in the same regions
+            float* AT = reinterpret_cast<float*>(buf + off); off = align(off + (size_t)(S * kpad * adj_value_bytes(m)));
+            float* BT = reinterpret_cast<float*>(buf + off); off = align(off + (size_t)(S * kpad * adj_value_bytes(p)));
+            __bf16* ASb = reinterpret_cast<__bf16*>(AT);
+            __bf16* BSb = reinterpret_cast<__bf16*>(BT);
             float* ZS = reinterpret_cast<float*>(buf + off); off = align(off + sizeof(float) * S * kpad * m);
             float* WS = reinterpret_cast<float*>(buf + off); off = align(off + sizeof(float) * S * kpad * p);
             int32_t* Rr = reinterpret_cast<int32_t*>(buf + off); off = align(off + sizeof(int32_t) * S * kpad);
@@ -333,12 +508,32 @@ hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law&
             g.k_first = (uint32_t)b0;
             g.A = A; g.B = B;
             g.AT = AT; g.BT = BT; g.ZS = ZS; g.WS = WS; g.R = Rr;
+            g.ASb = ASb; g.BSb = BSb; g.mk = mk; g.pk = pk;
             {
                 ScopedTiming t(timer, 1);
-                hipLaunchKernelGGL(adjoint_gather_kernel, dim3((unsigned)(kpad / kAdjPositions), (unsigned)S),
-                                   dim3(kAdjGatherThreads), 0, stream, g);
+                const dim3 grid((unsigned)(kpad / kAdjPositions), (unsigned)S);
+                if (bf16) hipLaunchKernelGGL(adjoint_gather_kernel<true>, grid, dim3(kAdjGatherThreads), 0, stream, g);
+                else hipLaunchKernelGGL(adjoint_gather_kernel<false>, grid, dim3(kAdjGatherThreads), 0, stream, g);
             }
             if ((e = hipGetLastError()) != hipSuccess) return e;
+            if (bf16) {
+                AdjBf16Params a;
+                a.m = m; a.p = p; a.kpad = kpad; a.mk = mk; a.pk = pk; a.c_prev = (uint32_t)cp;
+                a.kappa_coarse = kc; a.kappa_fine = kf;
+                a.Gb = Gb; a.GTb = GTb; a.ASb = ASb; a.BSb = BSb; a.ZS = ZS; a.WS = WS; a.R = Rr;
+                a.tiles_t = ceil_div(kpad, kAdjTileT);
+                a.tiles_u_cols = ceil_div(m, kAdjTileX);
+                a.tiles_v_cols = ceil_div(p, kAdjTileX);
+                a.dMA = dMA; a.dSA = dSA; a.dMB = dMB; a.dSB = dSB;
+                const int64_t tiles = a.tiles_t * (a.tiles_u_cols + a.tiles_v_cols);
+                {
+                    ScopedTiming t(timer, 0);
+                    hipLaunchKernelGGL(adjoint_mfma_bf16_kernel, dim3((unsigned)tiles, (unsigned)S), dim3(kAdjThreads),
+                                       0, stream, a);
+                }
+                if ((e = hipGetLastError()) != hipSuccess) return e;
+                continue;
+            }
             AdjMfmaParams a;
             a.m = m; a.p = p; a.kpad = kpad; a.c_prev = (uint32_t)cp;
             a.kappa_coarse = kc; a.kappa_fine = kf;

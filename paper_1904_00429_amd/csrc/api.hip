@@ -685,6 +685,8 @@ mlmc_status mlmc_matmul_adjoint_reparam(int64_t m, int64_t n, int64_t p, const m
     if (lv->rmse_target > 0.0 || !lv->n_samples)
         return fail(MLMC_EINVAL, "the adjoint needs the forward's N_l (fixed mode)");
     if (lv->func != MLMC_FUNC_IDENTITY) return fail(MLMC_EINVAL, "the adjoint is defined for f = identity");
+    if (lv->prec != MLMC_PREC_FP32 && lv->prec != MLMC_PREC_BF16)
+        return fail(MLMC_EINVAL, "the adjoint runs in FP32 or with BF16 operands");
     if ((st = check_dist(A, "A", m, false)) != MLMC_OK) return st;
     if ((st = check_dist(B, "B", p, false)) != MLMC_OK) return st;
     if (A->law != MLMC_LAW_REPARAM || B->law != MLMC_LAW_REPARAM)
@@ -697,7 +699,8 @@ mlmc_status mlmc_matmul_adjoint_reparam(int64_t m, int64_t n, int64_t p, const m
     KernelTimer* timer = (lv->flags & MLMC_FLAG_TIMING) ? &timer_obj : nullptr;
     hipError_t e = adjoint_run(m, n, p, to_law(*A), to_law(*B), lv->num_levels, lv->c, lv->n_samples, keys_of(lv),
                                (lv->flags & MLMC_FLAG_SHARED_SAMPLES) != 0, grad_out, dMA, dSA, dMB, dSB,
-                               static_cast<char*>(workspace), workspace_bytes, stream, timer);
+                               static_cast<char*>(workspace), workspace_bytes, lv->prec == MLMC_PREC_BF16, stream,
+                               timer);
     return e == hipSuccess ? MLMC_OK : device_fail(e, "adjoint launch");
 }
 

@@ -138,7 +138,7 @@ size_t adjoint_workspace_size(int64_t m, int64_t p, int num_levels, const int64_
 hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law& B, int num_levels,
                        const int64_t* c, const int64_t* N, const StreamKeys& keys, bool shared,
                        const double* grad, float* dMA, float* dSA, float* dMB, float* dSB, char* ws,
-                       size_t ws_bytes, hipStream_t stream, KernelTimer* timer);
+                       size_t ws_bytes, bool bf16, hipStream_t stream, KernelTimer* timer);
 
 // ---- building blocks exported for tests -----------------------------------
 hipError_t philox_batch(int64_t count, const uint32_t* ctr, uint32_t key0, uint32_t key1,

@@ -240,15 +240,16 @@ def gather_columns(m: int, n: int, p: int, A: Law, B: Law, seed: int, problem: i
 def matmul_adjoint_reparam(MA: torch.Tensor, SA: torch.Tensor, MB: torch.Tensor, SB: torch.Tensor,
                            c: Sequence[int], n_samples: Sequence[int], grad_out: torch.Tensor,
                            seed: int = 0, problem: int = 0, shared: bool = False,
-                           workspace: Optional[torch.Tensor] = None):
+                           workspace: Optional[torch.Tensor] = None, prec: str = "fp32"):
     """Gradients of <grad_out, Y> with respect to M_A, S_A, M_B, S_B
     (mlmc_matmul_adjoint_reparam).  MA, SA: (n, m) FP32 device tensors (row j =
-    column j of A); MB, SB: (n, p).  Returns (dMA, dSA, dMB, dSB), FP32."""
+    column j of A); MB, SB: (n, p).  prec: "fp32" or "bf16" (BF16 operands
+    on MFMA, FP32 accumulation).  Returns (dMA, dSA, dMB, dSB), FP32."""
     n, m = MA.shape
     p = MB.shape[1]
     device = MA.device
     A, B = Law.reparam(MA, SA), Law.reparam(MB, SB)
-    h = _LevelsHolder(c, n_samples, 0.0, 0, seed, "fp32", shared, problem, 0)
+    h = _LevelsHolder(c, n_samples, 0.0, 0, seed, prec, shared, problem, 0)
     ws_bytes = int(lib().mlmc_matmul_adjoint_workspace_size(int(m), int(n), int(p), ctypes.byref(h.lv)))
     if ws_bytes == 0:
         raise MLMCError(1, "invalid problem: no workspace size")

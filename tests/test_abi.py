@@ -159,3 +159,15 @@ def test_adaptive_levels_need_target_mode(L):
     st = L.mlmc_inner_product_estimate(16, ctypes.byref(A), ctypes.byref(B), ctypes.byref(lv), 8, None,
                                        16, 1 << 40, None, None)
     assert st == 1
+
+
+def test_adjoint_rejects_fp64_and_fp8(L):
+    for prec in (0, 3):
+        lv, keep = _levels([2, 4], [4, 4], prec=prec)
+        A = _dist(2)
+        B = _dist(2)
+        A.mean = A.stdev = B.mean = B.stdev = 16
+        A.ld, B.ld = 4, 3
+        st = L.mlmc_matmul_adjoint_reparam(4, 16, 3, ctypes.byref(A), ctypes.byref(B), ctypes.byref(lv), 16, 16,
+                                           16, 16, 16, 16, 1 << 40, None)
+        assert st == 1
