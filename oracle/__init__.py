@@ -17,7 +17,12 @@ Parity pins and where they are tested (``tests/test_oracle_*.py``):
   sketch (18)        brute force over every index tuple on tiny n and c;
   Alg. 1 / (10)      telescoping identity on shared realisations;
   level variances    closed forms (Thm 3.2 with uniform xi) by z-tests;
-  scheduler (28)     Lagrange optimality of the continuous allocation.
+  scheduler (28)     Lagrange optimality of the continuous allocation;
+  target function f  hand-evaluated steps, constant matrices, telescoping,
+                     brute force over index tuples;
+  adaptive L         constant laws, reuse of realisations, the stopping test;
+  weighted xi        unit weights = uniform draws, chi-square, unbiasedness
+                     and exact error by brute force, Theorem 3.1's minimum.
 """
 from __future__ import annotations
 
@@ -57,6 +62,10 @@ class _Law(ctypes.Structure):
                 ("stdev", ctypes.c_void_p), ("ld", ctypes.c_int64)]
 
 
+class _Weights(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_void_p), ("cum", ctypes.c_void_p), ("total", ctypes.c_uint64)]
+
+
 class _Func(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("theta0", ctypes.c_double), ("theta1", ctypes.c_double)]
 
@@ -91,8 +100,14 @@ def lib():
         L.orc_level_estimation.argtypes = (
             [ctypes.c_int64] * 3 + [ctypes.POINTER(_Law)] * 2 + [ctypes.c_int64] * 2
             + [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64,
-               ctypes.c_int64, ctypes.POINTER(_Func), ctypes.c_void_p, ctypes.c_void_p,
-               ctypes.c_void_p, ctypes.c_void_p])
+               ctypes.c_int64, ctypes.POINTER(_Func), ctypes.POINTER(_Weights), ctypes.c_void_p,
+               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p])
+        L.orc_weights_cumulative.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+        L.orc_draw_index_weighted.restype = ctypes.c_int64
+        L.orc_draw_index_weighted.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                              ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(_Weights)]
+        L.orc_optimal_weights.argtypes = ([ctypes.c_int64] * 3 + [ctypes.POINTER(_Law)] * 2 + [ctypes.c_void_p])
+        L.orc_sketch_pair_weighted.argtypes = [ctypes.c_int64] * 4 + [ctypes.c_void_p] * 5
         L.orc_apply_func.restype = ctypes.c_double
         L.orc_apply_func.argtypes = [ctypes.POINTER(_Func), ctypes.c_double]
         L.orc_level_entries.argtypes = (
@@ -187,6 +202,58 @@ class Func:
 
 
 # --------------------------------------------------------------------------
+# Index probabilities xi_j = w_j / W (eq. (18) with a general xi)
+# --------------------------------------------------------------------------
+class Weights:
+    """Integer column weights w_j >= 1 and their cumulative sums."""
+
+    def __init__(self, w):
+        self.w = np.ascontiguousarray(w, dtype=np.uint32)
+        if self.w.ndim != 1 or self.w.size == 0 or int(self.w.min()) < 1:
+            raise ValueError("weights must be a non-empty vector of integers >= 1")
+        self.cum = np.empty(self.w.size, dtype=np.uint64)
+        lib().orc_weights_cumulative(_ptr(self.w), self.w.size, _ptr(self.cum))
+        self.total = int(self.cum[-1])
+
+    @property
+    def xi(self) -> np.ndarray:
+        return self.w.astype(np.float64) / float(self.total)
+
+    def c(self) -> _Weights:
+        s = _Weights()
+        s.w = _ptr(self.w)
+        s.cum = _ptr(self.cum)
+        s.total = self.total
+        return s
+
+
+def optimal_weights(m: int, n: int, p: int, A: Law, B: Law) -> np.ndarray:
+    """Theorem 3.1's xi** as integer weights (orc_optimal_weights)."""
+    w = np.empty(n, dtype=np.uint32)
+    la, lb = A.c(), B.c()
+    lib().orc_optimal_weights(int(m), int(n), int(p), ctypes.byref(la), ctypes.byref(lb), _ptr(w))
+    return w
+
+
+def draw_index_weighted(seed: int, problem: int, lfield: int, k: int, t: int, weights: Weights) -> int:
+    wc = weights.c()
+    return int(lib().orc_draw_index_weighted(int(seed), int(problem), int(lfield), int(k), int(t),
+                                             weights.w.size, ctypes.byref(wc)))
+
+
+def sketch_pair_weighted(c_f: int, c_c: int, factor, AS: np.ndarray, BS: np.ndarray):
+    """Zf, Zc of eq. (18) with per-draw factors 1 / xi_{r_t}."""
+    AS = np.ascontiguousarray(AS, dtype=np.float64)
+    BS = np.ascontiguousarray(BS, dtype=np.float64)
+    factor = np.ascontiguousarray(factor, dtype=np.float64)
+    m, p = AS.shape[1], BS.shape[1]
+    Zf = np.zeros((m, p))
+    Zc = np.zeros((m, p))
+    lib().orc_sketch_pair_weighted(m, p, int(c_f), int(c_c), _ptr(factor), _ptr(AS), _ptr(BS), _ptr(Zf), _ptr(Zc))
+    return Zf, Zc
+
+
+# --------------------------------------------------------------------------
 # Random numbers, index draws, columns, sketches
 # --------------------------------------------------------------------------
 def philox(ctr: np.ndarray, seed: int) -> np.ndarray:
@@ -267,16 +334,20 @@ class LevelState:
 def level_estimation(state: LevelState, m: int, n: int, p: int, A: Law, B: Law,
                      c_l: int, c_prev: int, seed: int, problem: int, lfield: int,
                      k_begin: int, k_end: int, want_samples: bool = False,
-                     func: Optional[Func] = None):
+                     func: Optional[Func] = None, weights: Optional["Weights"] = None):
     """Alg. 1 for realisations [k_begin, k_end), continuing `state` in place;
     level samples f(Zf) - f(Zc) (identity when func is None)."""
     cnt = ctypes.c_int64(state.count)
     samples = np.empty((max(k_end - k_begin, 0), m, p)) if want_samples else None
     la, lb = A.c(), B.c()
     fc = (func or Func()).c()
+    if weights is not None and weights.w.size != n:
+        raise ValueError("one weight per column")
+    wc = weights.c() if weights is not None else None
     rc = lib().orc_level_estimation(
         int(m), int(n), int(p), ctypes.byref(la), ctypes.byref(lb), int(c_l), int(c_prev),
         int(seed), int(problem), int(lfield), int(k_begin), int(k_end), ctypes.byref(fc),
+        ctypes.byref(wc) if wc is not None else None,
         ctypes.byref(cnt), _ptr(state.mean), _ptr(state.m2), _ptr(samples) if want_samples else None)
     if rc != 0:
         raise ValueError("orc_level_estimation rejected its arguments")
@@ -332,7 +403,7 @@ def estimate(m: int, n: int, p: int, A: Law, B: Law, c: Sequence[int],
              n_samples: Optional[Sequence[int]] = None, rmse_target: float = 0.0,
              pilot: int = 0, seed: int = 0, problem: int = 0, shared: bool = False,
              max_total_draws: int = 0, pool=None, func: Optional[Func] = None,
-             adaptive: Optional[str] = None) -> Estimate:
+             adaptive: Optional[str] = None, weights: Optional[Weights] = None) -> Estimate:
     """MLMC estimate of E[f(AB)] (f entrywise, identity by default) over the
     ladder c_0 < c_1 < ... < c_L.
 
@@ -355,7 +426,7 @@ def estimate(m: int, n: int, p: int, A: Law, B: Law, c: Sequence[int],
 
     def run(l, k0, k1):
         level_estimation(states[l], m, n, p, A, B, c[l], c[l - 1] if l > 0 else 0,
-                         seed, problem, level_field(l, shared), k0, k1, func=func)
+                         seed, problem, level_field(l, shared), k0, k1, func=func, weights=weights)
 
     def run_all(ranges):
         if pool is None:

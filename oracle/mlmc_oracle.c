@@ -37,6 +37,10 @@
  *     z_e = sqrt(-2 ln u_e) cos(2 pi u_{e+1}), z_{e+1} = ... sin(...).
  *     Values are keyed by the column, so a repeated index reuses the same
  *     column of the same realisation A^(k), B^(k) (Alg. 1 draws the pair first).
+ *   - Optional non-uniform probabilities xi_j = w_j / W from integer weights
+ *     (eq. (18) with a general xi; Theorem 3.1's xi** quantised, see
+ *     orc_optimal_weights): the same 64-bit word x gives T = floor(x W / 2^64)
+ *     and r is the column whose cumulative-weight interval holds T.
  *   - The coarse sketch uses the first c_{l-1} of the c_l fine indices.
  *     Draws are i.i.d., so any fixed subset of c_{l-1} indices has the law the
  *     paper requires; the prefix nests the levels exactly.
@@ -153,6 +157,86 @@ void orc_draw_indices(uint64_t seed, uint32_t problem, uint32_t level_field,
         r[t] = orc_draw_index(seed, problem, level_field, k, t, n);
 }
 
+/* Non-uniform index probabilities (eq. (18) with a general xi): xi_j = w_j / W
+ * for integer weights w_j >= 1, W = sum_j w_j, cum[j] = w_0 + ... + w_j.
+ * Draw t uses the same 64-bit word x as the uniform draw:
+ * T = floor(x W / 2^64) is uniform on {0, ..., W-1} (to within 2^-64 per
+ * value) and r is the column whose interval [cum[r] - w_r, cum[r]) holds T.
+ * With every w_j = 1, W = n and r = T: exactly the uniform draw. */
+typedef struct {
+    const uint32_t* w;
+    const uint64_t* cum;
+    uint64_t total;
+} orc_weights;
+
+void orc_weights_cumulative(const uint32_t* w, int64_t n, uint64_t* cum)
+{
+    uint64_t s = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        s += w[j];
+        cum[j] = s;
+    }
+}
+
+int64_t orc_draw_index_weighted(uint64_t seed, uint32_t problem, uint32_t level_field,
+                                uint32_t k, int64_t t, int64_t n, const orc_weights* iw)
+{
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    uint32_t ctr[4] = { (uint32_t)(t >> 1), k, 0u,
+                        stream_word(ORC_TAG_INDEX, level_field, problem) };
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+    int h = (int)(t & 1);
+    uint64_t x = ((uint64_t)w[2 * h + 1] << 32) | (uint64_t)w[2 * h];
+    uint64_t T = (uint64_t)(((unsigned __int128)x * (unsigned __int128)iw->total) >> 64);
+    /* smallest j with cum[j] > T */
+    int64_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (iw->cum[mid] > T) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+/* Theorem 3.1's xi**_j, proportional to sqrt(E||A_{:,j}||^2 E||B_{j,:}||^2),
+ * quantised to integer weights: s_j = sqrt(EA_j) sqrt(EB_j) with
+ * EA_j = sum_i (mean_ij^2 + stdev_ij^2) accumulated in FP64 for i = 0, 1, ...
+ * (the mean's square first), likewise EB_j over the row of B;
+ * w_j = max(1, floor(2^24 s_j / max_i s_i)).  For i.i.d. laws every column
+ * has the same moments: w_j = 2^24 (xi** is uniform). */
+void orc_optimal_weights(int64_t m, int64_t n, int64_t p, const orc_law* A, const orc_law* B, uint32_t* w)
+{
+    if (A->law != ORC_LAW_REPARAM || B->law != ORC_LAW_REPARAM) {
+        for (int64_t j = 0; j < n; ++j)
+            w[j] = 1u << 24;
+        return;
+    }
+    double* s = (double*)malloc(sizeof(double) * (size_t)n);
+    double smax = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        double ea = 0.0, eb = 0.0;
+        for (int64_t i = 0; i < m; ++i) {
+            double mu = A->mean[j * A->ld + i], sd = A->stdev[j * A->ld + i];
+            ea = ea + mu * mu;
+            ea = ea + sd * sd;
+        }
+        for (int64_t q = 0; q < p; ++q) {
+            double mu = B->mean[j * B->ld + q], sd = B->stdev[j * B->ld + q];
+            eb = eb + mu * mu;
+            eb = eb + sd * sd;
+        }
+        s[j] = sqrt(ea) * sqrt(eb);
+        if (s[j] > smax)
+            smax = s[j];
+    }
+    for (int64_t j = 0; j < n; ++j) {
+        double v = smax > 0.0 ? floor(s[j] / smax * 16777216.0) : 1.0;
+        w[j] = v < 1.0 ? 1u : (uint32_t)v;
+    }
+    free(s);
+}
+
 double orc_uniform(uint32_t w)
 {
     return ((double)(w >> 9) + 0.5) * 0x1p-23;
@@ -209,6 +293,28 @@ void orc_column(uint64_t seed, uint32_t problem, uint32_t level_field, uint32_t 
         b[q] = law_value(B, seed, problem, level_field, k, j, m + q, j * B->ld + q);
 }
 
+/* Sketches of eq. (18) with general probabilities: Zf = (1/c_f) sum_{t < c_f}
+ * a_t b_t^T / xi_t (xi_t = w_{r_t} / W: factor[t] = W / w_{r_t}), likewise
+ * Zc over the first c_c draws. */
+void orc_sketch_pair_weighted(int64_t m, int64_t p, int64_t c_f, int64_t c_c, const double* factor,
+                              const double* AS, const double* BS, double* Zf, double* Zc)
+{
+    for (int64_t i = 0; i < m; ++i) {
+        for (int64_t q = 0; q < p; ++q) {
+            double sf = 0.0;
+            for (int64_t t = 0; t < c_f; ++t)
+                sf += factor[t] * (AS[t * m + i] * BS[t * p + q]);
+            Zf[i * p + q] = sf / (double)c_f;
+            if (c_c > 0) {
+                double sc = 0.0;
+                for (int64_t t = 0; t < c_c; ++t)
+                    sc += factor[t] * (AS[t * m + i] * BS[t * p + q]);
+                Zc[i * p + q] = sc / (double)c_c;
+            }
+        }
+    }
+}
+
 /* Sketches of Sec. 3, eq. (18) with xi_j = 1/n from gathered columns:
  *   Zf = (n / c_f) sum_{t < c_f} a_t b_t^T,  Zc = (n / c_c) sum_{t < c_c} a_t b_t^T.
  * AS holds a_t at AS + t*m, BS holds b_t at BS + t*p.  Z is m x p row-major.
@@ -242,7 +348,8 @@ void orc_sketch_pair(int64_t m, int64_t p, int64_t n, int64_t c_f, int64_t c_c,
 int orc_level_estimation(int64_t m, int64_t n, int64_t p, const orc_law* A, const orc_law* B,
                          int64_t c_l, int64_t c_prev, uint64_t seed, uint32_t problem,
                          uint32_t level_field, int64_t k_begin, int64_t k_end, const orc_func* f,
-                         int64_t* count, double* mean, double* m2, double* samples_out)
+                         const orc_weights* iw, int64_t* count, double* mean, double* m2,
+                         double* samples_out)
 {
     if (m < 1 || p < 1 || n < 1 || c_l < 1 || c_prev < 0 || c_prev > c_l || k_end < k_begin)
         return -1;
@@ -252,18 +359,29 @@ int orc_level_estimation(int64_t m, int64_t n, int64_t p, const orc_law* A, cons
     double* BS = (double*)malloc(sizeof(double) * (size_t)(c_l * p));
     double* Zf = (double*)malloc(sizeof(double) * (size_t)mp);
     double* Zc = (double*)malloc(sizeof(double) * (size_t)mp);
-    if (!r || !AS || !BS || !Zf || !Zc) {
-        free(r); free(AS); free(BS); free(Zf); free(Zc);
+    double* factor = (double*)malloc(sizeof(double) * (size_t)c_l);
+    if (!r || !AS || !BS || !Zf || !Zc || !factor) {
+        free(r); free(AS); free(BS); free(Zf); free(Zc); free(factor);
         return -1;
     }
     for (int64_t k = k_begin; k < k_end; ++k) {
-        /* Sample c_l indices uniformly, then read the sampled columns of the
-         * realisation A^(k), B^(k). */
-        orc_draw_indices(seed, problem, level_field, (uint32_t)k, c_l, n, r);
+        /* Sample c_l indices (uniformly, or with probabilities w_j / W), then
+         * read the sampled columns of the realisation A^(k), B^(k). */
+        if (iw) {
+            for (int64_t t = 0; t < c_l; ++t) {
+                r[t] = orc_draw_index_weighted(seed, problem, level_field, (uint32_t)k, t, n, iw);
+                factor[t] = (double)iw->total / (double)iw->w[r[t]];
+            }
+        } else {
+            orc_draw_indices(seed, problem, level_field, (uint32_t)k, c_l, n, r);
+        }
         for (int64_t t = 0; t < c_l; ++t)
             orc_column(seed, problem, level_field, (uint32_t)k, r[t], m, p, A, B,
                        AS + t * m, BS + t * p);
-        orc_sketch_pair(m, p, n, c_l, c_prev, AS, BS, Zf, Zc);
+        if (iw)
+            orc_sketch_pair_weighted(m, p, c_l, c_prev, factor, AS, BS, Zf, Zc);
+        else
+            orc_sketch_pair(m, p, n, c_l, c_prev, AS, BS, Zf, Zc);
         *count += 1;
         double cnt = (double)(*count);
         for (int64_t e = 0; e < mp; ++e) {
@@ -276,7 +394,7 @@ int orc_level_estimation(int64_t m, int64_t n, int64_t p, const orc_law* A, cons
             m2[e] += delta * (d - mean[e]);
         }
     }
-    free(r); free(AS); free(BS); free(Zf); free(Zc);
+    free(r); free(AS); free(BS); free(Zf); free(Zc); free(factor);
     return 0;
 }
 
