@@ -136,6 +136,15 @@ typedef struct {
     uint32_t problem;     /* stream id < 2^20 (independent problems, same seed) */
     int32_t func;         /* mlmc_func; 0 (identity) when the struct is zero-initialised */
     double func_param[2]; /* theta0, theta1 of f (finite) */
+    /* Index probabilities (eq. (18) with a general xi): NULL for uniform
+     * draws, or a device array of n integer weights w_j >= 1 with
+     * xi_j = w_j / W, W = sum_j w_j < 2^64 (mlmc_optimal_index_weights gives
+     * Theorem 3.1's xi**).  Draw t uses the same 64-bit word x as the
+     * uniform draw: T = floor(x W / 2^64) and r_t is the smallest j with
+     * w_0 + ... + w_j > T (all weights 1 give the uniform draw); the sketch
+     * weighs draw t by 1 / (c_l xi_{r_t}).  Single-product entry points
+     * (matrix, inner product, adjoint) with FP64, FP32 or BF16 operands. */
+    const uint32_t* index_weights;
 } mlmc_levels;
 
 /* Filled when a non-NULL report is passed (synchronises the stream). */
@@ -277,6 +286,27 @@ mlmc_status mlmc_gather_columns(int64_t m, int64_t n, int64_t p, const mlmc_dist
                                 const mlmc_dist* B, uint64_t seed, uint32_t problem,
                                 uint32_t level_field, uint32_t k0, int64_t num_samples,
                                 int64_t c, int32_t prec, double* AS, double* BS, void* stream);
+
+/* Theorem 3.1's xi** (eq. (20)), proportional to
+ * sqrt(E||A_{:,j}||^2 E||B_{j,:}||^2), as integer weights for
+ * mlmc_levels.index_weights: s_j = sqrt(EA_j) sqrt(EB_j) with
+ * EA_j = sum_i (mean_ij^2 + stdev_ij^2) accumulated in FP64 for i = 0, 1, ...
+ * (mean's square first), EB_j likewise over row j of B, and
+ * w_j = max(1, floor(2^24 s_j / max_i s_i)).  For i.i.d. laws every column
+ * has the same moments and w_j = 2^24.  weights: device uint32[n];
+ * scratch: device, at least (n + 1) doubles (reparameterised laws).
+ * Errors: EINVAL (sizes, null pointers, mixed law kinds). */
+mlmc_status mlmc_optimal_index_weights(int64_t m, int64_t n, int64_t p, const mlmc_dist* A,
+                                       const mlmc_dist* B, uint32_t* weights, double* scratch,
+                                       void* stream);
+
+/* Index draws with probabilities w_j / W, as the estimators draw them with
+ * mlmc_levels.index_weights; cum: device uint64[n] scratch that receives the
+ * cumulative weights.  Other arguments as mlmc_sample_indices. */
+mlmc_status mlmc_sample_indices_weighted(uint64_t seed, uint32_t problem, uint32_t level_field,
+                                         uint32_t k0, int64_t num_samples, int64_t c, int64_t n,
+                                         const uint32_t* weights, uint64_t* cum, int32_t* out,
+                                         void* stream);
 
 const char* mlmc_status_string(mlmc_status status);
 const char* mlmc_last_error(void);

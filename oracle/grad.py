@@ -13,7 +13,7 @@ from typing import Sequence
 import numpy as np
 import torch
 
-from . import Law, column, draw_indices, level_field
+from . import Law, column, draw_index_weighted, draw_indices, level_field
 
 
 def standard_normals(seed, problem, lfield, k, cols, m, p):
@@ -28,9 +28,11 @@ def standard_normals(seed, problem, lfield, k, cols, m, p):
 
 def reparam_estimate(MA: torch.Tensor, SA: torch.Tensor, MB: torch.Tensor, SB: torch.Tensor,
                      c: Sequence[int], N: Sequence[int], seed: int = 0, problem: int = 0,
-                     shared: bool = False) -> torch.Tensor:
+                     shared: bool = False, weights=None) -> torch.Tensor:
     """Y = sum_l (1/N_l) sum_k (Z_l^(k) - Z_{l-1}^(k)) for A = MA^T + SA^T o Z
-    (MA, SA: n x m, row j = column j of A) and B = MB + SB o W (n x p)."""
+    (MA, SA: n x m, row j = column j of A) and B = MB + SB o W (n x p).  With
+    `weights` (oracle.Weights) the indices are drawn with xi_j = w_j / W and
+    Z_l = (1/c_l) sum_t a_t b_t^T / xi_{r_t} (eq. (18))."""
     n, m = MA.shape
     p = MB.shape[1]
     Y = torch.zeros((m, p), dtype=torch.float64)
@@ -39,25 +41,31 @@ def reparam_estimate(MA: torch.Tensor, SA: torch.Tensor, MB: torch.Tensor, SB: t
         lf = level_field(l, shared)
         acc = torch.zeros((m, p), dtype=torch.float64)
         for k in range(Nl):
-            r = draw_indices(seed, problem, lf, k, cl, n)
+            if weights is None:
+                r = draw_indices(seed, problem, lf, k, cl, n)
+            else:
+                r = np.array([draw_index_weighted(seed, problem, lf, k, t, weights) for t in range(cl)],
+                             dtype=np.int64)
             Z, W = standard_normals(seed, problem, lf, k, r, m, p)
             idx = torch.from_numpy(r)
             AS = MA[idx] + SA[idx] * Z          # c x m: row t = a_t
             BS = MB[idx] + SB[idx] * W          # c x p: row t = b_t
-            Zf = (n / cl) * (AS.T @ BS)
-            if cp > 0:
-                Zc = (n / cp) * (AS[:cp].T @ BS[:cp])
-                acc = acc + (Zf - Zc)
+            if weights is None:
+                Zf = (n / cl) * (AS.T @ BS)
+                Zc = (n / cp) * (AS[:cp].T @ BS[:cp]) if cp > 0 else None
             else:
-                acc = acc + Zf
+                f = torch.from_numpy(weights.total / weights.w[r].astype(np.float64))[:, None]
+                Zf = ((AS * f).T @ BS) / cl
+                Zc = ((AS[:cp] * f[:cp]).T @ BS[:cp]) / cp if cp > 0 else None
+            acc = acc + (Zf - Zc if Zc is not None else Zf)
         Y = Y + acc / Nl
     return Y
 
 
-def reparam_gradients(MA, SA, MB, SB, c, N, G, seed=0, problem=0, shared=False):
-    """Gradients of <G, Y> (FP64) with respect to MA, SA, MB, SB."""
+def reparam_gradients(MA, SA, MB, SB, c, N, G, seed=0, problem=0, shared=False, weights=None):
+    """Gradients of <G, Y> (FP64) with respect to MA, SA, MB, SB (weights held fixed)."""
     leaves = [torch.as_tensor(np.asarray(x, dtype=np.float64)).clone().requires_grad_(True)
               for x in (MA, SA, MB, SB)]
-    Y = reparam_estimate(*leaves, c, N, seed, problem, shared)
+    Y = reparam_estimate(*leaves, c, N, seed, problem, shared, weights)
     (Y * torch.as_tensor(np.asarray(G, dtype=np.float64))).sum().backward()
     return Y.detach().numpy(), [t.grad.numpy() for t in leaves]

@@ -16,6 +16,7 @@ EXPORTED = [
     "mlmc_matmul_adjoint_workspace_size", "mlmc_matmul_adjoint_reparam",
     "mlmc_matmul_batched_workspace_size", "mlmc_matmul_estimate_batched",
     "mlmc_matmul_batched_graph_create", "mlmc_graph_launch", "mlmc_graph_destroy",
+    "mlmc_optimal_index_weights", "mlmc_sample_indices_weighted",
 ]
 
 
@@ -30,7 +31,7 @@ class Levels(ctypes.Structure):
                 ("pilot_samples", ctypes.c_int64), ("max_total_draws", ctypes.c_int64),
                 ("seed", ctypes.c_uint64), ("prec", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("problem", ctypes.c_uint32), ("func", ctypes.c_int32),
-                ("func_param", ctypes.c_double * 2)]
+                ("func_param", ctypes.c_double * 2), ("index_weights", ctypes.c_void_p)]
 
 
 class Problem(ctypes.Structure):
@@ -86,6 +87,10 @@ def lib() -> ctypes.CDLL:
     L.mlmc_sample_indices.argtypes = [u64, u32, u32, u32, i64, i64, i64, vp, vp]
     L.mlmc_gather_columns.restype = ctypes.c_int
     L.mlmc_gather_columns.argtypes = [i64, i64, i64, DP, DP, u64, u32, u32, u32, i64, i64, i32, vp, vp, vp]
+    L.mlmc_optimal_index_weights.restype = ctypes.c_int
+    L.mlmc_optimal_index_weights.argtypes = [i64, i64, i64, DP, DP, vp, vp, vp]
+    L.mlmc_sample_indices_weighted.restype = ctypes.c_int
+    L.mlmc_sample_indices_weighted.argtypes = [u64, u32, u32, u32, i64, i64, i64, vp, vp, vp, vp]
     L.mlmc_matmul_adjoint_workspace_size.restype = ctypes.c_size_t
     L.mlmc_matmul_adjoint_workspace_size.argtypes = [i64, i64, i64, LP]
     L.mlmc_matmul_adjoint_reparam.restype = ctypes.c_int

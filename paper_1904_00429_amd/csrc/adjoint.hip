@@ -50,6 +50,7 @@ struct AdjGatherParams {
     __bf16* ASb;                  // batch x kpad x mk
     __bf16* BSb;                  // batch x kpad x pk
     int64_t mk, pk;
+    const uint64_t* cum;          // cumulative index weights (NULL: uniform draws)
 };
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
@@ -67,7 +68,11 @@ __global__ __launch_bounds__(kAdjGatherThreads) void adjoint_gather_kernel(AdjGa
         const int64_t t = pos0 + threadIdx.x;
         const bool ok = t < (int64_t)prm.c;
         valid[threadIdx.x] = ok;
-        const uint32_t j = ok ? draw_index((uint32_t)t, k, prm.sid_index, prm.key0, prm.key1, prm.n) : 0u;
+        uint32_t j = 0u;
+        if (ok)
+            j = prm.cum ? draw_index_weighted((uint32_t)t, k, prm.sid_index, prm.key0, prm.key1, prm.cum, prm.n,
+                                              prm.cum[prm.n - 1])
+                        : draw_index((uint32_t)t, k, prm.sid_index, prm.key0, prm.key1, prm.n);
         cols[threadIdx.x] = j;
         prm.R[slot * prm.kpad + t] = ok ? (int32_t)j : -1;
     }
@@ -179,6 +184,9 @@ struct AdjMfmaParams {
     int64_t tiles_t, tiles_u_cols, tiles_v_cols;
     float* dMA; float* dSA;           // n x m
     float* dMB; float* dSB;           // n x p
+    const uint32_t* iw;               // index weights (NULL: uniform): factor 1 / (n xi_j) per draw
+    const uint64_t* cum;
+    uint32_t n;
 };
 
 // One 64 x 128 tile of U^T (rows t, columns i; K = p) or of V (rows t,
@@ -297,7 +305,8 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_mfma_kernel(AdjMfmaParams
             if (t >= kpad) continue;
             const int32_t col = R[t];
             if (col < 0) continue;
-            const float kappa = t < (int)prm.c_prev ? prm.kappa_coarse : prm.kappa_fine;
+            float kappa = t < (int)prm.c_prev ? prm.kappa_coarse : prm.kappa_fine;
+            if (prm.iw) kappa *= (float)((double)prm.cum[prm.n - 1] / ((double)prm.n * (double)prm.iw[col]));
             const float g = kappa * acc[bj][r];
             unsafeAtomicAdd(dM + (int64_t)col * X + x, g);
             unsafeAtomicAdd(dS + (int64_t)col * X + x, g * N[(int64_t)t * X + x]);
@@ -326,6 +335,9 @@ struct AdjBf16Params {
     int64_t tiles_t, tiles_u_cols, tiles_v_cols;
     float* dMA; float* dSA;
     float* dMB; float* dSB;
+    const uint32_t* iw;
+    const uint64_t* cum;
+    uint32_t n;
 };
 
 // 8 consecutive K values of one row (stride KS), zero beyond K or for an
@@ -393,7 +405,8 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_mfma_bf16_kernel(AdjBf16P
             if (tt >= kpad) continue;
             const int32_t col = R[tt];
             if (col < 0) continue;
-            const float kappa = tt < (int)prm.c_prev ? prm.kappa_coarse : prm.kappa_fine;
+            float kappa = tt < (int)prm.c_prev ? prm.kappa_coarse : prm.kappa_fine;
+            if (prm.iw) kappa *= (float)((double)prm.cum[prm.n - 1] / ((double)prm.n * (double)prm.iw[col]));
             const float g = kappa * acc[bj][r];
             unsafeAtomicAdd(dM + (int64_t)col * X + x, g);
             unsafeAtomicAdd(dS + (int64_t)col * X + x, g * N[(int64_t)tt * X + x]);
@@ -441,7 +454,7 @@ static int64_t adj_value_bytes(int64_t rows)
     return f32 > b16 ? f32 : b16;
 }
 
-size_t adjoint_workspace_size(int64_t m, int64_t p, int num_levels, const int64_t* c)
+size_t adjoint_workspace_size(int64_t m, int64_t n, int64_t p, int num_levels, const int64_t* c, bool weighted)
 {
     const int64_t kpad = round_up_adj(c[num_levels - 1], kAdjPositions);
     const int64_t per_sample = kpad * (adj_value_bytes(m) + adj_value_bytes(p) + (m + p) * 4 + 4);
@@ -449,13 +462,15 @@ size_t adjoint_workspace_size(int64_t m, int64_t p, int num_levels, const int64_
     // slack for the five 256-byte-aligned regions of a pass
     size_t total = (size_t)budget + 2048;
     total += adj_head_bytes(m, p);
+    if (weighted) total += ((size_t)n * sizeof(uint64_t) + 255) & ~(size_t)255;
     return total;
 }
 
 hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law& B, int num_levels,
                        const int64_t* c, const int64_t* N, const StreamKeys& keys, bool shared,
-                       const double* grad, float* dMA, float* dSA, float* dMB, float* dSB, char* ws,
-                       size_t ws_bytes, bool bf16, hipStream_t stream, KernelTimer* timer)
+                       const double* grad, float* dMA, float* dSA, float* dMB, float* dSB,
+                       const uint32_t* index_weights, char* ws, size_t ws_bytes, bool bf16, hipStream_t stream,
+                       KernelTimer* timer)
 {
     auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const int64_t mk = round_up_adj(m, 8), pk = round_up_adj(p, 8);
@@ -464,8 +479,11 @@ hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law&
     __bf16* Gb = reinterpret_cast<__bf16*>(ws + align(2 * m * p * sizeof(float)));
     __bf16* GTb = Gb + m * pk;
     const size_t head = adj_head_bytes(m, p);
-    char* buf = ws + head;
-    const size_t budget = ws_bytes - head;
+    // the cumulative index weights follow the head
+    uint64_t* cum = index_weights ? reinterpret_cast<uint64_t*>(ws + head) : nullptr;
+    const size_t cum_bytes = index_weights ? align((size_t)n * sizeof(uint64_t)) : 0;
+    char* buf = ws + head + cum_bytes;
+    const size_t budget = ws_bytes - head - cum_bytes;
     {
         ScopedTiming t(timer, 3);
         if (bf16)
@@ -477,6 +495,7 @@ hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law&
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (index_weights && (e = build_cumulative(index_weights, n, cum, stream)) != hipSuccess) return e;
     for (int l = 0; l < num_levels; ++l) {
         const int64_t cl = c[l], cp = l > 0 ? c[l - 1] : 0;
         const int64_t kpad = round_up_adj(cl, kAdjPositions);
@@ -509,6 +528,7 @@ hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law&
             g.A = A; g.B = B;
             g.AT = AT; g.BT = BT; g.ZS = ZS; g.WS = WS; g.R = Rr;
             g.ASb = ASb; g.BSb = BSb; g.mk = mk; g.pk = pk;
+            g.cum = cum;
             {
                 ScopedTiming t(timer, 1);
                 const dim3 grid((unsigned)(kpad / kAdjPositions), (unsigned)S);
@@ -525,6 +545,7 @@ hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law&
                 a.tiles_u_cols = ceil_div(m, kAdjTileX);
                 a.tiles_v_cols = ceil_div(p, kAdjTileX);
                 a.dMA = dMA; a.dSA = dSA; a.dMB = dMB; a.dSB = dSB;
+                a.iw = index_weights; a.cum = cum; a.n = (uint32_t)n;
                 const int64_t tiles = a.tiles_t * (a.tiles_u_cols + a.tiles_v_cols);
                 {
                     ScopedTiming t(timer, 0);
@@ -542,6 +563,7 @@ hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law&
             a.tiles_u_cols = ceil_div(m, kAdjTileX);
             a.tiles_v_cols = ceil_div(p, kAdjTileX);
             a.dMA = dMA; a.dSA = dSA; a.dMB = dMB; a.dSB = dSB;
+            a.iw = index_weights; a.cum = cum; a.n = (uint32_t)n;
             const int64_t tiles = a.tiles_t * (a.tiles_u_cols + a.tiles_v_cols);
             {
                 ScopedTiming t(timer, 0);

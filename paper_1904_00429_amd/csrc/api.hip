@@ -65,6 +65,8 @@ mlmc_status check_levels(const mlmc_levels* lv, bool inner)
                 return fail(MLMC_EINVAL, "n_samples[%d] must be in [1, 2^32)", l);
     }
     if (lv->max_total_draws < 0) return fail(MLMC_EINVAL, "max_total_draws must be >= 0");
+    if (lv->index_weights && lv->prec == MLMC_PREC_FP8)
+        return fail(MLMC_EINVAL, "weighted index draws are not offered with FP8 operands");
     if ((lv->flags & MLMC_FLAG_ADAPTIVE_LEVELS) && !(lv->rmse_target > 0.0))
         return fail(MLMC_EINVAL, "the adaptive number of levels needs target mode (rmse_target > 0)");
     if (lv->func < MLMC_FUNC_IDENTITY || lv->func > MLMC_FUNC_INV_ABS_STEP)
@@ -184,19 +186,21 @@ LevelRange range_of(const mlmc_levels* lv, int l, int64_t k_begin, int64_t count
     return r;
 }
 
-// Inner-product workspace: per-level Moments, workgroup partials, V_l.
+// Inner-product workspace: per-level Moments, workgroup partials, V_l, and
+// the cumulative index weights when the draws are weighted.
 struct InnerLayout {
-    size_t off_state, off_partials, off_var, total;
+    size_t off_state, off_partials, off_var, off_cum, total;
 };
 
-InnerLayout inner_layout(int num_levels)
+InnerLayout inner_layout(int num_levels, int64_t n, bool weighted)
 {
     InnerLayout L;
     auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
     L.off_state = 0;
     L.off_partials = align(sizeof(Moments) * num_levels);
     L.off_var = align(L.off_partials + sizeof(Moments) * inner_partials_capacity());
-    L.total = align(L.off_var + sizeof(double) * num_levels);
+    L.off_cum = align(L.off_var + sizeof(double) * num_levels);
+    L.total = align(L.off_cum + (weighted ? sizeof(uint64_t) * n : 0));
     return L;
 }
 
@@ -258,7 +262,7 @@ size_t mlmc_inner_product_workspace_size(int64_t n, const mlmc_levels* levels)
 {
     (void)n;
     if (!levels || levels->num_levels < 1 || levels->num_levels > MLMC_MAX_LEVELS) return 0;
-    return inner_layout(levels->num_levels).total;
+    return inner_layout(levels->num_levels, n, levels->index_weights != nullptr).total;
 }
 
 size_t mlmc_matmul_workspace_size(int64_t m, int64_t n, int64_t p, const mlmc_levels* levels)
@@ -266,7 +270,9 @@ size_t mlmc_matmul_workspace_size(int64_t m, int64_t n, int64_t p, const mlmc_le
     if (check_levels(levels, false) != MLMC_OK || m < 1 || p < 1 || n < 1) return 0;
     MatmulProblem pr{m, n, p, Law{}, Law{}, levels->problem, nullptr, nullptr};
     MatmulPlan plan;
-    if (!matmul_plan(&pr, 1, levels->prec, levels->num_levels, levels->c, nullptr, func_of(levels), plan)) return 0;
+    if (!matmul_plan(&pr, 1, levels->prec, levels->num_levels, levels->c, nullptr, func_of(levels),
+                     levels->index_weights, plan))
+        return 0;
     return plan.total;
 }
 
@@ -282,7 +288,7 @@ mlmc_status mlmc_inner_product_estimate(int64_t n, const mlmc_dist* x, const mlm
     if ((st = check_dist(x, "x", 1, true)) != MLMC_OK) return st;
     if ((st = check_dist(y, "y", 1, true)) != MLMC_OK) return st;
     if (!out) return fail(MLMC_EINVAL, "out is NULL");
-    const InnerLayout L = inner_layout(lv->num_levels);
+    const InnerLayout L = inner_layout(lv->num_levels, n, lv->index_weights != nullptr);
     if (!workspace || workspace_bytes < L.total)
         return fail(MLMC_EWORKSPACE, "workspace needs %zu bytes", L.total);
     hipStream_t stream = static_cast<hipStream_t>(stream_ptr);
@@ -290,6 +296,8 @@ mlmc_status mlmc_inner_product_estimate(int64_t n, const mlmc_dist* x, const mlm
     Moments* state = reinterpret_cast<Moments*>(ws + L.off_state);
     Moments* partials = reinterpret_cast<Moments*>(ws + L.off_partials);
     double* var_dev = reinterpret_cast<double*>(ws + L.off_var);
+    const IndexWeights iw{lv->index_weights,
+                          lv->index_weights ? reinterpret_cast<const uint64_t*>(ws + L.off_cum) : nullptr};
     const Law lx = to_law(*x), ly = to_law(*y);
     const StreamKeys keys = keys_of(lv);
     const int L1 = lv->num_levels;
@@ -301,6 +309,8 @@ mlmc_status mlmc_inner_product_estimate(int64_t n, const mlmc_dist* x, const mlm
     {
         ScopedTiming t(timer, MLMC_KERNEL_FINAL);
         e = fill_doubles(reinterpret_cast<double*>(state), 3 * L1, 0.0, stream);
+        if (e == hipSuccess && iw.w)
+            e = build_cumulative(iw.w, n, reinterpret_cast<uint64_t*>(ws + L.off_cum), stream);
     }
     if (e != hipSuccess) return device_fail(e, "state reset");
 
@@ -308,7 +318,7 @@ mlmc_status mlmc_inner_product_estimate(int64_t n, const mlmc_dist* x, const mlm
     auto run_all = [&](const int64_t* k0, const int64_t* cnt) -> hipError_t {
         LevelRange ranges[MLMC_MAX_LEVELS];
         for (int l = 0; l < L1; ++l) ranges[l] = range_of(lv, l, k0[l], cnt[l]);
-        return inner_levels_run(ranges, L1, n, lx, ly, func_of(lv), lv->prec, keys, partials, state, stream,
+        return inner_levels_run(ranges, L1, n, lx, ly, func_of(lv), iw, lv->prec, keys, partials, state, stream,
                                 timer);
     };
     std::vector<int64_t> zero(L1, 0), amount(L1, 0);
@@ -398,7 +408,7 @@ mlmc_status mlmc_matmul_estimate(int64_t m, int64_t n, int64_t p, const mlmc_dis
     if (!out) return fail(MLMC_EINVAL, "out is NULL");
     MatmulProblem pr{m, n, p, to_law(*A), to_law(*B), lv->problem, out, level_means};
     MatmulPlan plan;
-    if (!matmul_plan(&pr, 1, lv->prec, lv->num_levels, lv->c, nullptr, func_of(lv), plan))
+    if (!matmul_plan(&pr, 1, lv->prec, lv->num_levels, lv->c, nullptr, func_of(lv), lv->index_weights, plan))
         return fail(MLMC_EINVAL, "no launch plan for this shape and precision");
     if (!workspace || workspace_bytes < plan.total)
         return fail(MLMC_EWORKSPACE, "workspace needs %zu bytes", plan.total);
@@ -416,6 +426,8 @@ mlmc_status mlmc_matmul_estimate(int64_t m, int64_t n, int64_t p, const mlmc_dis
     {
         ScopedTiming t(timer, MLMC_KERNEL_FINAL);
         e = matmul_reset(plan, ws, stream);
+        if (e == hipSuccess && lv->index_weights)
+            e = build_cumulative(lv->index_weights, n, reinterpret_cast<uint64_t*>(ws + plan.off_cum), stream);
     }
     if (e != hipSuccess) return device_fail(e, "state reset");
 
@@ -511,6 +523,7 @@ mlmc_status check_batch(int32_t nprob, const mlmc_problem* probs, const mlmc_lev
     if (st != MLMC_OK) return st;
     if (nprob < 1 || !probs) return fail(MLMC_EINVAL, "nprob must be >= 1 with a problem table");
     if (lv->rmse_target > 0.0 || !lv->n_samples) return fail(MLMC_EINVAL, "batched estimates take fixed N_l");
+    if (lv->index_weights) return fail(MLMC_EINVAL, "batched estimates draw indices uniformly");
     std::vector<uint32_t> ids;
     out.clear();
     for (int32_t i = 0; i < nprob; ++i) {
@@ -571,7 +584,7 @@ size_t mlmc_matmul_batched_workspace_size(int32_t nprob, const mlmc_problem* pro
     MatmulTuning tune;
     if (check_batch(nprob, probs, levels, tuning, pr, tune) != MLMC_OK) return 0;
     MatmulPlan plan;
-    if (!matmul_plan(pr.data(), nprob, levels->prec, levels->num_levels, levels->c, &tune, func_of(levels), plan))
+    if (!matmul_plan(pr.data(), nprob, levels->prec, levels->num_levels, levels->c, &tune, func_of(levels), nullptr, plan))
         return 0;
     return plan.total;
 }
@@ -586,7 +599,7 @@ mlmc_status mlmc_matmul_estimate_batched(int32_t nprob, const mlmc_problem* prob
     mlmc_status st = check_batch(nprob, probs, lv, tuning, pr, tune);
     if (st != MLMC_OK) return st;
     MatmulPlan plan;
-    if (!matmul_plan(pr.data(), nprob, lv->prec, lv->num_levels, lv->c, &tune, func_of(lv), plan))
+    if (!matmul_plan(pr.data(), nprob, lv->prec, lv->num_levels, lv->c, &tune, func_of(lv), nullptr, plan))
         return fail(MLMC_EINVAL, "no launch plan for this table");
     if (!workspace || workspace_bytes < plan.total)
         return fail(MLMC_EWORKSPACE, "workspace needs %zu bytes", plan.total);
@@ -617,7 +630,7 @@ mlmc_status mlmc_matmul_batched_graph_create(int32_t nprob, const mlmc_problem* 
     mlmc_status st = check_batch(nprob, probs, lv, tuning, pr, tune);
     if (st != MLMC_OK) return st;
     MatmulPlan plan;
-    if (!matmul_plan(pr.data(), nprob, lv->prec, lv->num_levels, lv->c, &tune, func_of(lv), plan))
+    if (!matmul_plan(pr.data(), nprob, lv->prec, lv->num_levels, lv->c, &tune, func_of(lv), nullptr, plan))
         return fail(MLMC_EINVAL, "no launch plan for this table");
     if (!workspace || workspace_bytes < plan.total)
         return fail(MLMC_EWORKSPACE, "workspace needs %zu bytes", plan.total);
@@ -669,7 +682,7 @@ mlmc_status mlmc_graph_destroy(mlmc_graph graph)
 size_t mlmc_matmul_adjoint_workspace_size(int64_t m, int64_t n, int64_t p, const mlmc_levels* levels)
 {
     if (check_levels(levels, false) != MLMC_OK || m < 1 || p < 1 || n < 1) return 0;
-    return adjoint_workspace_size(m, p, levels->num_levels, levels->c);
+    return adjoint_workspace_size(m, n, p, levels->num_levels, levels->c, levels->index_weights != nullptr);
 }
 
 mlmc_status mlmc_matmul_adjoint_reparam(int64_t m, int64_t n, int64_t p, const mlmc_dist* A, const mlmc_dist* B,
@@ -692,15 +705,15 @@ mlmc_status mlmc_matmul_adjoint_reparam(int64_t m, int64_t n, int64_t p, const m
     if (A->law != MLMC_LAW_REPARAM || B->law != MLMC_LAW_REPARAM)
         return fail(MLMC_EINVAL, "the adjoint is defined for reparameterised laws");
     if (!grad_out || !dMA || !dSA || !dMB || !dSB) return fail(MLMC_EINVAL, "null gradient pointer");
-    const size_t need = adjoint_workspace_size(m, p, lv->num_levels, lv->c);
+    const size_t need = adjoint_workspace_size(m, n, p, lv->num_levels, lv->c, lv->index_weights != nullptr);
     if (!workspace || workspace_bytes < need) return fail(MLMC_EWORKSPACE, "workspace needs %zu bytes", need);
     hipStream_t stream = static_cast<hipStream_t>(stream_ptr);
     KernelTimer timer_obj(stream);
     KernelTimer* timer = (lv->flags & MLMC_FLAG_TIMING) ? &timer_obj : nullptr;
     hipError_t e = adjoint_run(m, n, p, to_law(*A), to_law(*B), lv->num_levels, lv->c, lv->n_samples, keys_of(lv),
                                (lv->flags & MLMC_FLAG_SHARED_SAMPLES) != 0, grad_out, dMA, dSA, dMB, dSB,
-                               static_cast<char*>(workspace), workspace_bytes, lv->prec == MLMC_PREC_BF16, stream,
-                               timer);
+                               lv->index_weights, static_cast<char*>(workspace), workspace_bytes,
+                               lv->prec == MLMC_PREC_BF16, stream, timer);
     return e == hipSuccess ? MLMC_OK : device_fail(e, "adjoint launch");
 }
 
@@ -723,6 +736,38 @@ mlmc_status mlmc_sample_indices(uint64_t seed, uint32_t problem, uint32_t level_
     StreamKeys keys{(uint32_t)seed, (uint32_t)(seed >> 32), problem};
     hipError_t e = sample_indices(keys, level_field, k0, num_samples, c, n, out, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? MLMC_OK : device_fail(e, "sample_indices launch");
+}
+
+mlmc_status mlmc_sample_indices_weighted(uint64_t seed, uint32_t problem, uint32_t level_field, uint32_t k0,
+                                         int64_t num_samples, int64_t c, int64_t n, const uint32_t* weights,
+                                         uint64_t* cum, int32_t* out, void* stream)
+{
+    g_last_error.clear();
+    if (num_samples < 0 || c < 1 || c >= kU32 || n < 1 || n >= kU32 || (num_samples > 0 && !out) || !weights ||
+        !cum || problem >= (1u << 20) || level_field > 0xFFu || (int64_t)k0 + num_samples > kU32)
+        return fail(MLMC_EINVAL, "bad sample_indices_weighted arguments");
+    StreamKeys keys{(uint32_t)seed, (uint32_t)(seed >> 32), problem};
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = build_cumulative(weights, n, cum, st);
+    if (e == hipSuccess) e = sample_indices_weighted(keys, level_field, k0, num_samples, c, n, cum, out, st);
+    return e == hipSuccess ? MLMC_OK : device_fail(e, "sample_indices_weighted launch");
+}
+
+mlmc_status mlmc_optimal_index_weights(int64_t m, int64_t n, int64_t p, const mlmc_dist* A, const mlmc_dist* B,
+                                       uint32_t* weights, double* scratch, void* stream)
+{
+    g_last_error.clear();
+    if (m < 1 || p < 1 || n < 1 || n >= kU32) return fail(MLMC_EINVAL, "m, p >= 1 and 1 <= n < 2^32 required");
+    if (!weights) return fail(MLMC_EINVAL, "weights is NULL");
+    mlmc_status st;
+    if ((st = check_dist(A, "A", m, false)) != MLMC_OK) return st;
+    if ((st = check_dist(B, "B", p, false)) != MLMC_OK) return st;
+    const bool reparam = A->law == MLMC_LAW_REPARAM;
+    if (reparam != (B->law == MLMC_LAW_REPARAM))
+        return fail(MLMC_EINVAL, "A and B must both be reparameterised, or both i.i.d.");
+    if (reparam && !scratch) return fail(MLMC_EINVAL, "scratch is NULL");
+    hipError_t e = optimal_weights(m, n, p, to_law(*A), to_law(*B), weights, scratch, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? MLMC_OK : device_fail(e, "optimal weights launch");
 }
 
 mlmc_status mlmc_gather_columns(int64_t m, int64_t n, int64_t p, const mlmc_dist* A, const mlmc_dist* B,

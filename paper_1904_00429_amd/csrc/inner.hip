@@ -52,6 +52,8 @@ struct InnerMultiParams {
     int32_t num_levels;
     Law x, y;
     TargetFunc f;             // applied to both sketches (FN kernels)
+    const uint32_t* iw;       // index weights (IW kernels): xi_j = w_j / W
+    const uint64_t* cum;      // their cumulative sums, W = cum[n - 1]
     Moments* partials;        // one per workgroup
     InnerLevel lev[32];
 };
@@ -88,36 +90,48 @@ __device__ __forceinline__ T inner_product_term(const InnerMultiParams& prm, uin
     return xv * yv;
 }
 
-// The two product terms of draw pair q (draws 2q and 2q + 1) of realisation k.
-template <typename T, int LAWS>
+// The two product terms of draw pair q (draws 2q and 2q + 1) of realisation k;
+// IW: weighted draws, each term times 1 / (n xi_j) (eq. (18) with a general xi).
+template <typename T, int LAWS, bool IW>
 __device__ __forceinline__ void pair_terms(const InnerMultiParams& prm, const InnerLevel& L, uint32_t q,
                                            uint32_t k, T& v0, T& v1)
 {
     const Words4 w = philox4x32_10(q, k, 0u, L.sid_index, prm.key0, prm.key1);
-    const uint32_t r0 = inner_index(w.w0, w.w1, prm);
-    const uint32_t r1 = inner_index(w.w2, w.w3, prm);
-    v0 = inner_product_term<T, LAWS>(prm, k, r0, L.sid_value);
-    v1 = (2u * q + 1u < L.c) ? inner_product_term<T, LAWS>(prm, k, r1, L.sid_value) : (T)0;
+    if constexpr (IW) {
+        const uint64_t total = prm.cum[prm.n - 1];
+        const uint32_t r0 = index_from_cumulative(w.w0, w.w1, prm.cum, prm.n, total);
+        const uint32_t r1 = index_from_cumulative(w.w2, w.w3, prm.cum, prm.n, total);
+        const double tn = (double)total / (double)prm.n;
+        v0 = inner_product_term<T, LAWS>(prm, k, r0, L.sid_value) * (T)(tn / (double)prm.iw[r0]);
+        v1 = (2u * q + 1u < L.c)
+                 ? inner_product_term<T, LAWS>(prm, k, r1, L.sid_value) * (T)(tn / (double)prm.iw[r1])
+                 : (T)0;
+    } else {
+        const uint32_t r0 = inner_index(w.w0, w.w1, prm);
+        const uint32_t r1 = inner_index(w.w2, w.w3, prm);
+        v0 = inner_product_term<T, LAWS>(prm, k, r0, L.sid_value);
+        v1 = (2u * q + 1u < L.c) ? inner_product_term<T, LAWS>(prm, k, r1, L.sid_value) : (T)0;
+    }
 }
 
 // Sum of the product terms of pairs q0, q0 + G, q0 + 2G, ... below q_end into
 // acc, in increasing q; two pairs per iteration give the scheduler two
 // independent Philox chains to interleave.
-template <typename T, int LAWS>
+template <typename T, int LAWS, bool IW>
 __device__ __forceinline__ void sum_pairs(const InnerMultiParams& prm, const InnerLevel& L, uint32_t q0,
                                           uint32_t q_end, uint32_t G, uint32_t k, T& acc)
 {
     uint32_t q = q0;
     for (; q + G < q_end; q += 2u * G) {
         T a0, a1, b0, b1;
-        pair_terms<T, LAWS>(prm, L, q, k, a0, a1);
-        pair_terms<T, LAWS>(prm, L, q + G, k, b0, b1);
+        pair_terms<T, LAWS, IW>(prm, L, q, k, a0, a1);
+        pair_terms<T, LAWS, IW>(prm, L, q + G, k, b0, b1);
         acc += a0 + a1;
         acc += b0 + b1;
     }
     if (q < q_end) {
         T a0, a1;
-        pair_terms<T, LAWS>(prm, L, q, k, a0, a1);
+        pair_terms<T, LAWS, IW>(prm, L, q, k, a0, a1);
         acc += a0 + a1;
     }
 }
@@ -126,7 +140,7 @@ __device__ __forceinline__ void sum_pairs(const InnerMultiParams& prm, const Inn
 // f(Z_l) - f(Z_{l-1}) with Z_l = (n / c_l)(C + F) and Z_{l-1} = (n / c_{l-1}) C,
 // C and F the sums over the coarse and the remaining draws, so both sums are
 // reduced over the group instead of their weighted combination.
-template <typename T, int LAWS, bool FN>
+template <typename T, int LAWS, bool FN, bool IW>
 __global__ __launch_bounds__(kInnerBlock) void inner_multi_kernel(InnerMultiParams prm)
 {
     __shared__ double wave_sum[kInnerBlock / kWave];
@@ -161,16 +175,16 @@ __global__ __launch_bounds__(kInnerBlock) void inner_multi_kernel(InnerMultiPara
         // the next pair straddles (its first draw is coarse, its second
         // fine); the rest are fine.  The lane takes pairs q = lane_g (mod G).
         T acc_coarse = (T)0, acc_fine = (T)0;
-        sum_pairs<T, LAWS>(prm, L, (uint32_t)lane_g, coarse_pairs, (uint32_t)G, k, acc_coarse);
+        sum_pairs<T, LAWS, IW>(prm, L, (uint32_t)lane_g, coarse_pairs, (uint32_t)G, k, acc_coarse);
         if (odd_prev && (coarse_pairs & (uint32_t)(G - 1)) == (uint32_t)lane_g) {
             T a0, a1;
-            pair_terms<T, LAWS>(prm, L, coarse_pairs, k, a0, a1);
+            pair_terms<T, LAWS, IW>(prm, L, coarse_pairs, k, a0, a1);
             acc_coarse += a0;
             acc_fine += a1;
         }
         const uint32_t fine_begin = coarse_pairs + (odd_prev ? 1u : 0u);
         const uint32_t q_fine = fine_begin + (((uint32_t)lane_g - fine_begin) & (uint32_t)(G - 1));
-        sum_pairs<T, LAWS>(prm, L, q_fine, pairs, (uint32_t)G, k, acc_fine);
+        sum_pairs<T, LAWS, IW>(prm, L, q_fine, pairs, (uint32_t)G, k, acc_fine);
         T part = FN ? acc_fine : omega * acc_coarse + acc_fine;
         T part_c = acc_coarse;
         const int width = G < kWave ? G : kWave;
@@ -279,21 +293,36 @@ static uint32_t lanes_log2_for(int64_t c)
     return g;
 }
 
-template <typename T, bool FN>
+template <typename T, bool FN, bool IW>
 static void launch_inner(int laws, dim3 grid, hipStream_t stream, const InnerMultiParams& prm)
 {
     const dim3 block(kInnerBlock);
-    if (laws == kLawsUniform) hipLaunchKernelGGL((inner_multi_kernel<T, kLawsUniform, FN>), grid, block, 0, stream, prm);
-    else if (laws == kLawsNormal) hipLaunchKernelGGL((inner_multi_kernel<T, kLawsNormal, FN>), grid, block, 0, stream, prm);
-    else hipLaunchKernelGGL((inner_multi_kernel<T, kLawsAny, FN>), grid, block, 0, stream, prm);
+    if (laws == kLawsUniform)
+        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsUniform, FN, IW>), grid, block, 0, stream, prm);
+    else if (laws == kLawsNormal)
+        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsNormal, FN, IW>), grid, block, 0, stream, prm);
+    else
+        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsAny, FN, IW>), grid, block, 0, stream, prm);
+}
+
+template <typename T>
+static void launch_inner_forms(int laws, dim3 grid, hipStream_t stream, const InnerMultiParams& prm)
+{
+    const bool fn = prm.f.kind != 0, iw = prm.iw != nullptr;
+    if (fn && iw) launch_inner<T, true, true>(laws, grid, stream, prm);
+    else if (fn) launch_inner<T, true, false>(laws, grid, stream, prm);
+    else if (iw) launch_inner<T, false, true>(laws, grid, stream, prm);
+    else launch_inner<T, false, false>(laws, grid, stream, prm);
 }
 
 hipError_t inner_levels_run(const LevelRange* ranges, int num_levels, int64_t n, const Law& x, const Law& y,
-                            const TargetFunc& f, int prec, const StreamKeys& keys, Moments* partials,
-                            Moments* level_state, hipStream_t stream, KernelTimer* timer)
+                            const TargetFunc& f, const IndexWeights& iw, int prec, const StreamKeys& keys,
+                            Moments* partials, Moments* level_state, hipStream_t stream, KernelTimer* timer)
 {
     InnerMultiParams prm;
     prm.f = f;
+    prm.iw = iw.w;
+    prm.cum = iw.cum;
     prm.n = (uint32_t)n;
     prm.n_shift = 0xFFFFFFFFu;
     if ((n & (n - 1)) == 0) {
@@ -370,14 +399,8 @@ hipError_t inner_levels_run(const LevelRange* ranges, int num_levels, int64_t n,
     {
         ScopedTiming t(timer, 0);
         const dim3 grid(next);
-        const bool fn = f.kind != 0;
-        if (prec == 0) {
-            if (fn) launch_inner<double, true>(laws, grid, stream, prm);
-            else launch_inner<double, false>(laws, grid, stream, prm);
-        } else {
-            if (fn) launch_inner<float, true>(laws, grid, stream, prm);
-            else launch_inner<float, false>(laws, grid, stream, prm);
-        }
+        if (prec == 0) launch_inner_forms<double>(laws, grid, stream, prm);
+        else launch_inner_forms<float>(laws, grid, stream, prm);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -46,6 +46,13 @@ struct ScopedTiming {
     KernelTimer* t_;
 };
 
+// Index weights of a call (eq. (18) with a general xi): w is NULL for
+// uniform draws; cum is the library's cumulative table in workspace.
+struct IndexWeights {
+    const uint32_t* w;
+    const uint64_t* cum;
+};
+
 struct StreamKeys {
     uint32_t key0, key1;
     uint32_t problem;
@@ -57,8 +64,9 @@ size_t inner_partials_capacity();  // Moments slots needed in workspace
 // One launch over every level's range (pilot, extension or fixed mode), then a
 // fold of the workgroup partials into the running level states.
 hipError_t inner_levels_run(const LevelRange* ranges, int num_levels, int64_t n, const Law& x,
-                            const Law& y, const TargetFunc& f, int prec, const StreamKeys& keys,
-                            Moments* partials, Moments* level_state, hipStream_t stream, KernelTimer* timer);
+                            const Law& y, const TargetFunc& f, const IndexWeights& iw, int prec,
+                            const StreamKeys& keys, Moments* partials, Moments* level_state, hipStream_t stream,
+                            KernelTimer* timer);
 hipError_t inner_telescope(const Moments* level_state, int num_levels, double* out,
                            double* level_means, double* level_var, hipStream_t stream);
 
@@ -103,6 +111,8 @@ struct MatmulPlan {
     int kstep, kpack, elem, nb, tile;
     int laws;                  // law pair shared by every product (kLaws*), else kLawsAny
     TargetFunc func;           // f of E[f(AB)]; not the identity: both sketches kept (tile 64)
+    const uint32_t* index_weights;   // NULL: uniform draws
+    size_t off_cum;                  // the cumulative weights (n uint64) when index_weights is set
     bool iid;                  // no product has a reparameterised law
     bool whole_tiles;          // every m and p is a multiple of the workgroup tile
     int64_t min_rows;          // smallest m + p over the products
@@ -115,8 +125,11 @@ struct MatmulPlan {
     std::vector<int32_t> tile_owner;
 };
 
+// index_weights: NULL, or (one product) the device weights whose cumulative
+// table the plan keeps in workspace (off_cum)
 bool matmul_plan(const MatmulProblem* probs, int nprob, int prec, int num_levels, const int64_t* c,
-                 const MatmulTuning* tune, const TargetFunc& func, MatmulPlan& plan);
+                 const MatmulTuning* tune, const TargetFunc& func, const uint32_t* index_weights,
+                 MatmulPlan& plan);
 // copies the problem table into the workspace (synchronises `stream`)
 hipError_t matmul_upload(const MatmulPlan& plan, char* ws, hipStream_t stream);
 hipError_t matmul_reset(const MatmulPlan& plan, char* ws, hipStream_t stream);
@@ -134,11 +147,12 @@ double* matmul_norm_ptr(const MatmulPlan& plan, char* ws);
 hipError_t fill_doubles(double* p, int64_t count, double v, hipStream_t stream);
 
 // ---- adjoint of the matrix estimator (reparameterised laws) ---------------
-size_t adjoint_workspace_size(int64_t m, int64_t p, int num_levels, const int64_t* c);
+size_t adjoint_workspace_size(int64_t m, int64_t n, int64_t p, int num_levels, const int64_t* c, bool weighted);
 hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law& B, int num_levels,
                        const int64_t* c, const int64_t* N, const StreamKeys& keys, bool shared,
-                       const double* grad, float* dMA, float* dSA, float* dMB, float* dSB, char* ws,
-                       size_t ws_bytes, bool bf16, hipStream_t stream, KernelTimer* timer);
+                       const double* grad, float* dMA, float* dSA, float* dMB, float* dSB,
+                       const uint32_t* index_weights, char* ws, size_t ws_bytes, bool bf16, hipStream_t stream,
+                       KernelTimer* timer);
 
 // ---- building blocks exported for tests -----------------------------------
 hipError_t philox_batch(int64_t count, const uint32_t* ctr, uint32_t key0, uint32_t key1,
@@ -146,6 +160,14 @@ hipError_t philox_batch(int64_t count, const uint32_t* ctr, uint32_t key0, uint3
 hipError_t sample_indices(const StreamKeys& keys, uint32_t level_field, uint32_t k0,
                           int64_t num_samples, int64_t c, int64_t n, int32_t* out,
                           hipStream_t stream);
+// cum[j] = w_0 + ... + w_j (one workgroup, exact integer sums)
+hipError_t build_cumulative(const uint32_t* w, int64_t n, uint64_t* cum, hipStream_t stream);
+hipError_t sample_indices_weighted(const StreamKeys& keys, uint32_t level_field, uint32_t k0,
+                                   int64_t num_samples, int64_t c, int64_t n, const uint64_t* cum, int32_t* out,
+                                   hipStream_t stream);
+// Theorem 3.1's xi** as integer weights; scratch: n + 1 doubles
+hipError_t optimal_weights(int64_t m, int64_t n, int64_t p, const Law& A, const Law& B, uint32_t* w,
+                           double* scratch, hipStream_t stream);
 hipError_t gather_columns_f64(int64_t m, int64_t n, int64_t p, const Law& A, const Law& B,
                               const StreamKeys& keys, uint32_t level_field, uint32_t k0,
                               int64_t num_samples, int64_t c, int prec, double* AS, double* BS,

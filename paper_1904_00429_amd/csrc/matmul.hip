@@ -149,6 +149,8 @@ struct GatherParams {
     int64_t batch;           // realisations in this pass
     int octets;              // groups of 8 positions per block (1 .. kGatherMaxOctets)
     double omega;            // 1 - c_l / c_{l-1}: weight of the coarse draws, folded into a_t
+    const uint32_t* iw;      // index weights (NULL: uniform draws)
+    const uint64_t* cum;     // their cumulative sums
     uint32_t key0, key1;
     uint32_t k_first;        // realisation of batch slot 0
     int elem;
@@ -191,6 +193,8 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
 {
     constexpr int MAXPOS = kGatherPositions * kGatherMaxOctets;
     __shared__ uint32_t cols[MAXPOS];
+    // per-draw factor 1 / (n xi_j) of eq. (18) with weighted draws (1 uniform)
+    __shared__ Compute colf[MAXPOS];
     // the product's description is copied to registers once: the stores into
     // the gathered buffer below could otherwise alias it and force reloads
     const ProblemDesc* Pp = prm.descs + blockIdx.z;
@@ -228,7 +232,19 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
     constexpr uint32_t kNoDraw = 0xFFFFFFFFu;
     for (int i = threadIdx.x; i < npos_block; i += kGatherThreads) {
         const int64_t t = draw_of_position(pos_base + i, prm.kc, prm.c, prm.c_prev);
-        cols[i] = t >= 0 ? draw_index((uint32_t)t, k, sid_index, prm.key0, prm.key1, n) : kNoDraw;
+        uint32_t j = kNoDraw;
+        Compute f = (Compute)1;
+        if (t >= 0) {
+            if (prm.cum) {
+                const uint64_t total = prm.cum[n - 1];
+                j = draw_index_weighted((uint32_t)t, k, sid_index, prm.key0, prm.key1, prm.cum, n, total);
+                f = (Compute)((double)total / ((double)n * (double)prm.iw[j]));
+            } else {
+                j = draw_index((uint32_t)t, k, sid_index, prm.key0, prm.key1, n);
+            }
+        }
+        cols[i] = j;
+        colf[i] = f;
     }
     __syncthreads();
     const int64_t rows = m + p;
@@ -244,6 +260,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
     const Compute omega = (Compute)prm.omega;
     // values of rows 4q .. 4q+3 at the 8 positions of group oc
     auto generate = [&](uint32_t oc, int64_t q, const uint32_t* jv, const bool* ok) {
+        const Compute* fv = colf + oc * kGatherPositions;
         const int64_t pos0 = pos_base + (int64_t)oc * kGatherPositions;
         const int npos = (int)((prm.kpad - pos0) < kGatherPositions ? (prm.kpad - pos0) : kGatherPositions);
         Val vals[kGatherPositions][4];
@@ -256,7 +273,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
                 continue;
             }
             const uint32_t j = jv[ip];
-            const Compute wa = pos0 + ip < prm.kc ? omega : (Compute)1;
+            const Compute wa = (pos0 + ip < prm.kc ? omega : (Compute)1) * fv[ip];
             const Words4 w = philox4x32_10((uint32_t)q, k, j, sid_value, prm.key0, prm.key1);
             Compute u[4], z[4];
             quad_values<Compute>(w, normal, u[0], u[1], u[2], u[3], z[0], z[1], z[2], z[3]);
@@ -960,10 +977,13 @@ static float fp8_prescale(const Law& law)
 }
 
 bool matmul_plan(const MatmulProblem* probs, int nprob, int prec, int num_levels, const int64_t* c,
-                 const MatmulTuning* tune, const TargetFunc& func, MatmulPlan& plan)
+                 const MatmulTuning* tune, const TargetFunc& func, const uint32_t* index_weights,
+                 MatmulPlan& plan)
 {
     plan = MatmulPlan();
     plan.func = func;
+    plan.index_weights = index_weights;
+    if (index_weights && (nprob != 1 || prec == 3)) return false;   // one product; not FP8 (range of 1/xi)
     if (nprob < 1) return false;
     plan.prec = prec;
     plan.num_levels = num_levels;
@@ -1072,6 +1092,7 @@ bool matmul_plan(const MatmulProblem* probs, int nprob, int prec, int num_levels
     plan.state_doubles = (int64_t)(off / sizeof(double));
     plan.off_desc = off;       off = align(off + sizeof(ProblemDesc) * nprob);
     plan.off_tile_owner = off; off = align(off + sizeof(int32_t) * tiles);
+    plan.off_cum = off;        off = align(off + (index_weights ? sizeof(uint64_t) * probs[0].n : 0));
     plan.off_gather = off;     off = align(off + (size_t)plan.gather_bytes);
     plan.off_part_mean = off;  off = align(off + sizeof(double) * plan.groups_max * mp);
     plan.off_part_m2 = off;    off = align(off + sizeof(double) * plan.groups_max * tiles);
@@ -1172,6 +1193,8 @@ static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t
         g.octets = oct;
         // with a target function the sketch needs the coarse sum itself: no weight
         g.omega = lr.c_prev > 0 && plan.func.kind == 0 ? 1.0 - (double)lr.c / (double)lr.c_prev : 1.0;
+        g.iw = plan.index_weights;
+        g.cum = plan.index_weights ? reinterpret_cast<const uint64_t*>(ws + plan.off_cum) : nullptr;
         const dim3 grid((unsigned)ceil_div(kpad, (int64_t)kGatherPositions * oct), (unsigned)batch,
                         (unsigned)plan.nprob);
         if (plan.laws == kLawsNormal)

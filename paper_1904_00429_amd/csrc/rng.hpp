@@ -84,6 +84,34 @@ __device__ __forceinline__ uint32_t draw_index(uint32_t t, uint32_t k, uint32_t 
     return (t & 1u) ? index_from_words(w.w2, w.w3, n) : index_from_words(w.w0, w.w1, n);
 }
 
+// Non-uniform index probabilities xi_j = w_j / W (eq. (18) with a general
+// xi): cum[j] = w_0 + ... + w_j (exact integers), W = cum[n-1].  The same
+// 64-bit word x = hi:lo as the uniform draw gives T = floor(x W / 2^64), and
+// the index is the smallest j with cum[j] > T.  With every w_j = 1 this is
+// floor(x n / 2^64): the uniform draw.
+__device__ __forceinline__ uint32_t index_from_cumulative(uint32_t lo, uint32_t hi, const uint64_t* cum,
+                                                          uint32_t n, uint64_t total)
+{
+    const uint64_t x = ((uint64_t)hi << 32) | (uint64_t)lo;
+    const uint64_t T = __umul64hi(x, total);
+    uint32_t a = 0, b = n - 1u;
+    while (a < b) {
+        const uint32_t mid = a + (b - a) / 2u;
+        if (cum[mid] > T) b = mid;
+        else a = mid + 1u;
+    }
+    return a;
+}
+
+__device__ __forceinline__ uint32_t draw_index_weighted(uint32_t t, uint32_t k, uint32_t sid_index, uint32_t key0,
+                                                        uint32_t key1, const uint64_t* cum, uint32_t n,
+                                                        uint64_t total)
+{
+    const Words4 w = philox4x32_10(t >> 1, k, 0u, sid_index, key0, key1);
+    return (t & 1u) ? index_from_cumulative(w.w2, w.w3, cum, n, total)
+                    : index_from_cumulative(w.w0, w.w1, cum, n, total);
+}
+
 // u = ((w >> 9) + 1/2) 2^-23: 2^23 equally spaced points in (0, 1), exactly
 // representable in FP32 and FP64, never 0 or 1.  (w >> 9) 2^-23 + 2^-24 is
 // exact in FP32, so the single fma gives the same value.

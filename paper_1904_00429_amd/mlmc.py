@@ -104,7 +104,8 @@ class _LevelsHolder:
     """Keeps the ctypes arrays of a Levels struct alive."""
 
     def __init__(self, c, n_samples, rmse_target, pilot, seed, prec, shared, problem, max_total_draws,
-                 func: Optional[Func] = None, adaptive: bool = False):
+                 func: Optional[Func] = None, adaptive: bool = False,
+                 index_weights: Optional[torch.Tensor] = None):
         if prec not in PREC:
             raise ValueError(f"prec must be one of {sorted(PREC)}")
         self.c = (ctypes.c_int64 * len(c))(*[int(v) for v in c])
@@ -124,6 +125,11 @@ class _LevelsHolder:
         lv.func = int(f.kind)
         lv.func_param[0] = float(f.theta0)
         lv.func_param[1] = float(f.theta1)
+        if index_weights is not None:
+            if index_weights.dtype != torch.int32 or not index_weights.is_cuda or not index_weights.is_contiguous():
+                raise TypeError("index_weights must be a contiguous int32 device tensor of positive weights")
+            lv.index_weights = index_weights.data_ptr()
+        self.index_weights = index_weights
         self.lv = lv
 
 
@@ -149,13 +155,14 @@ def matmul_estimate(m: int, n: int, p: int, A: Law, B: Law, c: Sequence[int],
                     problem: int = 0, max_total_draws: int = 0, level_means: bool = False,
                     report: bool = True, device=None, workspace: Optional[torch.Tensor] = None,
                     out: Optional[torch.Tensor] = None, func: Optional[Func] = None,
-                    adaptive: bool = False) -> Result:
+                    adaptive: bool = False, index_weights: Optional[torch.Tensor] = None) -> Result:
     """MLMC estimate of E[f(AB)] on the GPU (mlmc_matmul_estimate; f = identity
     unless func is given; adaptive: number of levels chosen by the bias test,
-    c being the longest ladder allowed)."""
+    c being the longest ladder allowed; index_weights: int32 device tensor of n
+    positive weights, xi_j = w_j / sum w, e.g. optimal_index_weights)."""
     device = torch.device(device or "cuda")
     h = _LevelsHolder(c, n_samples, rmse_target, pilot, seed, prec, shared, problem, max_total_draws, func,
-                      adaptive)
+                      adaptive, index_weights)
     ws_bytes = int(lib().mlmc_matmul_workspace_size(int(m), int(n), int(p), ctypes.byref(h.lv)))
     if ws_bytes == 0:
         raise MLMCError(1, "invalid problem: no workspace size")
@@ -181,12 +188,13 @@ def inner_product_estimate(n: int, x: Law, y: Law, c: Sequence[int],
                            report: bool = True, device=None,
                            workspace: Optional[torch.Tensor] = None,
                            out: Optional[torch.Tensor] = None, func: Optional[Func] = None,
-                           adaptive: bool = False) -> Result:
+                           adaptive: bool = False, index_weights: Optional[torch.Tensor] = None) -> Result:
     """MLMC estimate of E[f(x^T y)] on the GPU (mlmc_inner_product_estimate;
-    f = identity unless func is given; adaptive as for matmul_estimate)."""
+    f = identity unless func is given; adaptive and index_weights as for
+    matmul_estimate)."""
     device = torch.device(device or "cuda")
     h = _LevelsHolder(c, n_samples, rmse_target, pilot, seed, prec, shared, problem, max_total_draws, func,
-                      adaptive)
+                      adaptive, index_weights)
     ws_bytes = int(lib().mlmc_inner_product_workspace_size(int(n), ctypes.byref(h.lv)))
     if ws_bytes == 0:
         raise MLMCError(1, "invalid problem: no workspace size")
@@ -223,6 +231,30 @@ def sample_indices(seed: int, problem: int, level_field: int, k0: int, num_sampl
     return out
 
 
+def sample_indices_weighted(seed: int, problem: int, level_field: int, k0: int, num_samples: int,
+                            c: int, weights: torch.Tensor) -> torch.Tensor:
+    """Index draws with probabilities w_j / sum w (mlmc_sample_indices_weighted)."""
+    n = weights.numel()
+    device = weights.device
+    cum = torch.empty(n, dtype=torch.int64, device=device)
+    out = torch.empty((num_samples, c), dtype=torch.int32, device=device)
+    check(lib().mlmc_sample_indices_weighted(int(seed) & (2**64 - 1), problem, level_field, k0, num_samples, c, n,
+                                             weights.data_ptr(), cum.data_ptr(), out.data_ptr(), _stream(device)))
+    return out
+
+
+def optimal_index_weights(m: int, n: int, p: int, A: Law, B: Law, device=None) -> torch.Tensor:
+    """Theorem 3.1's xi** as integer weights (mlmc_optimal_index_weights):
+    an int32 device tensor of n entries for index_weights."""
+    device = torch.device(device or "cuda")
+    w = torch.empty(n, dtype=torch.int32, device=device)
+    scratch = torch.empty(n + 1, dtype=torch.float64, device=device)
+    da, db = A.c(), B.c()
+    check(lib().mlmc_optimal_index_weights(int(m), int(n), int(p), ctypes.byref(da), ctypes.byref(db),
+                                           w.data_ptr(), scratch.data_ptr(), _stream(device)))
+    return w
+
+
 def gather_columns(m: int, n: int, p: int, A: Law, B: Law, seed: int, problem: int,
                    level_field: int, k0: int, num_samples: int, c: int, prec: str = "fp64",
                    device=None):
@@ -240,7 +272,8 @@ def gather_columns(m: int, n: int, p: int, A: Law, B: Law, seed: int, problem: i
 def matmul_adjoint_reparam(MA: torch.Tensor, SA: torch.Tensor, MB: torch.Tensor, SB: torch.Tensor,
                            c: Sequence[int], n_samples: Sequence[int], grad_out: torch.Tensor,
                            seed: int = 0, problem: int = 0, shared: bool = False,
-                           workspace: Optional[torch.Tensor] = None, prec: str = "fp32"):
+                           workspace: Optional[torch.Tensor] = None, prec: str = "fp32",
+                           index_weights: Optional[torch.Tensor] = None):
     """Gradients of <grad_out, Y> with respect to M_A, S_A, M_B, S_B
     (mlmc_matmul_adjoint_reparam).  MA, SA: (n, m) FP32 device tensors (row j =
     column j of A); MB, SB: (n, p).  prec: "fp32" or "bf16" (BF16 operands
@@ -249,7 +282,7 @@ def matmul_adjoint_reparam(MA: torch.Tensor, SA: torch.Tensor, MB: torch.Tensor,
     p = MB.shape[1]
     device = MA.device
     A, B = Law.reparam(MA, SA), Law.reparam(MB, SB)
-    h = _LevelsHolder(c, n_samples, 0.0, 0, seed, prec, shared, problem, 0)
+    h = _LevelsHolder(c, n_samples, 0.0, 0, seed, prec, shared, problem, 0, None, False, index_weights)
     ws_bytes = int(lib().mlmc_matmul_adjoint_workspace_size(int(m), int(n), int(p), ctypes.byref(h.lv)))
     if ws_bytes == 0:
         raise MLMCError(1, "invalid problem: no workspace size")

@@ -171,3 +171,20 @@ def test_adjoint_rejects_fp64_and_fp8(L):
         st = L.mlmc_matmul_adjoint_reparam(4, 16, 3, ctypes.byref(A), ctypes.byref(B), ctypes.byref(lv), 16, 16,
                                            16, 16, 16, 16, 1 << 40, None)
         assert st == 1
+
+
+def test_weighted_draws_rejected_with_fp8_and_in_batches(L):
+    from paper_1904_00429_amd._lib import Problem, Tuning
+    lv, keep = _levels([2, 4], [4, 4], prec=3)
+    lv.index_weights = 16
+    A, B = _dist(), _dist()
+    st = L.mlmc_matmul_estimate(4, 16, 3, ctypes.byref(A), ctypes.byref(B), ctypes.byref(lv), 8, None,
+                                16, 1 << 40, None, None)
+    assert st == 1 and b"FP8" in L.mlmc_last_error()
+    lv.prec = 1
+    probs = (Problem * 1)()
+    probs[0].m, probs[0].n, probs[0].p = 4, 16, 3
+    probs[0].A, probs[0].B = _dist(), _dist()
+    probs[0].out = 8
+    st = L.mlmc_matmul_estimate_batched(1, probs, ctypes.byref(lv), None, 16, 1 << 40, None, None)
+    assert st == 1 and b"uniformly" in L.mlmc_last_error()

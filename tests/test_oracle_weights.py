@@ -117,3 +117,20 @@ def test_weighted_mlmc_converges_to_the_mean():
     assert np.linalg.norm(est.Y - exact) <= 5.0 * est.rmse_est
     # importance sampling lowers every level's variance for these laws
     assert np.all(est.level_var < uni.level_var)
+
+
+def test_gradient_reference_with_weights_matches_the_c_oracle():
+    import torch
+    from oracle import grad as og
+    rng = np.random.default_rng(9)
+    m, n, p = 3, 40, 2
+    MA = rng.normal(size=(n, m)) * np.linspace(0.2, 2.0, n)[:, None]
+    SA = rng.uniform(0.1, 1.0, size=(n, m))
+    MB = rng.normal(size=(n, p))
+    SB = rng.uniform(0.1, 1.0, size=(n, p))
+    A, B = orc.Law.reparam(MA, SA, m), orc.Law.reparam(MB, SB, p)
+    weights = orc.Weights(orc.optimal_weights(m, n, p, A, B))
+    c, N = [2, 4], [30, 15]
+    ref = orc.estimate(m, n, p, A, B, c, n_samples=N, seed=6, weights=weights)
+    Y = og.reparam_estimate(*[torch.from_numpy(x) for x in (MA, SA, MB, SB)], c, N, seed=6, weights=weights)
+    assert np.abs(Y.numpy() - ref.Y).max() <= 1e-12 * np.abs(ref.Y).max()
