@@ -72,6 +72,26 @@ def reparam_inputs(m: int, n: int, p: int, seed: int = 0):
     return MA, SA, MB, SB, T
 
 
+# Importance sampling: A = M_A + S_A o Z (512 x 32768) whose column j is
+# scaled by r_j = 0.05 + 2.95 j / (n - 1) (column-dependent laws, as in the
+# experiments of Sec. 4), B = M_B + S_B o W; c_l = 32 * 2^l, l = 0..6; target
+# RMSE 10% of ||E[AB]||_F (set at run time from the inputs), pilot 64, FP32.
+IS_512x32768x512 = Workload("is-512x32768x512", "matmul", 512, 32768, 512, ("reparam",), ("reparam",),
+                            ladder(32, 7), None, 0.0, 64, "fp32")
+
+
+def reparam_ramp_inputs(m: int, n: int, p: int, seed: int = 0):
+    """M_A ~ N(0, 1) r_j, S_A ~ U(0.1, 1) r_j with r_j = 0.05 + 2.95 j / (n - 1),
+    M_B ~ N(0, 1), S_B ~ U(0.1, 1), FP32; A's in (n, m) layout, B's in (n, p)."""
+    rng = np.random.default_rng(seed)
+    r = (0.05 + 2.95 * np.arange(n) / max(n - 1, 1)).astype(np.float32)[:, None]
+    MA = rng.standard_normal((n, m), dtype=np.float32) * r
+    SA = rng.uniform(0.1, 1.0, size=(n, m)).astype(np.float32) * r
+    MB = rng.standard_normal((n, p), dtype=np.float32)
+    SB = rng.uniform(0.1, 1.0, size=(n, p)).astype(np.float32)
+    return MA, SA, MB, SB
+
+
 def batched_products(count: int = 256, seed: int = 0):
     """The batching workload: `count` independent products, m and p uniform on
     {64, 128, ..., 512}, n log-uniform on [4096, 131072] (rounded), entries
