@@ -22,7 +22,10 @@ Parity pins and where they are tested (``tests/test_oracle_*.py``):
                      brute force over index tuples;
   adaptive L         constant laws, reuse of realisations, the stopping test;
   weighted xi        unit weights = uniform draws, chi-square, unbiasedness
-                     and exact error by brute force, Theorem 3.1's minimum.
+                     and exact error by brute force, Theorem 3.1's minimum;
+  Sec. 4 laws        sample moments against closed forms (characteristic
+                     functions of Poisson, exponential and normal variables)
+                     and the Poisson probabilities by chi-square.
 """
 from __future__ import annotations
 
@@ -42,6 +45,10 @@ _LIB_PATH = os.path.join(_HERE, "_mlmc_oracle.so")
 LAW_NORMAL = 0
 LAW_UNIFORM = 1
 LAW_REPARAM = 2
+LAW_RAMP_NORMAL = 3         # Sec. 4.1's a_j: (j scale)(loc - z)
+LAW_COS_POISSON_EXP = 4     # Sec. 4.1's b_j: cos(K + 2E) [u < scale], K ~ Poisson(loc)
+LAW_SIN_RAMP = 5            # Sec. 4.2's A_ij: sin(x) + z' x, x = (j scale)(loc - z)
+LAW_COS_POISSON_STEP = 6    # Sec. 4.2's B_jk: cos(K) H(5 - K) [u < scale], K ~ Poisson(loc)
 SHARED_LEVEL_FIELD = 0xFF
 
 
@@ -59,7 +66,8 @@ def build(force: bool = True) -> str:
 class _Law(ctypes.Structure):
     _fields_ = [("law", ctypes.c_int32), ("loc", ctypes.c_double),
                 ("scale", ctypes.c_double), ("mean", ctypes.c_void_p),
-                ("stdev", ctypes.c_void_p), ("ld", ctypes.c_int64)]
+                ("stdev", ctypes.c_void_p), ("ld", ctypes.c_int64),
+                ("exp_neg_loc", ctypes.c_double)]
 
 
 class _Weights(ctypes.Structure):
@@ -150,6 +158,11 @@ class Law:
         return Law(LAW_UNIFORM, float(loc), float(scale))
 
     @staticmethod
+    def experiment(kind: int, loc: float, scale: float) -> "Law":
+        """One of the laws of the experiments of Sec. 4 (LAW_RAMP_NORMAL ...)."""
+        return Law(int(kind), float(loc), float(scale))
+
+    @staticmethod
     def reparam(mean: np.ndarray, stdev: np.ndarray, ld: int) -> "Law":
         return Law(LAW_REPARAM, 0.0, 0.0, np.ascontiguousarray(mean, dtype=np.float64),
                    np.ascontiguousarray(stdev, dtype=np.float64), int(ld))
@@ -159,6 +172,7 @@ class Law:
         s.law = self.law
         s.loc = self.loc
         s.scale = self.scale
+        s.exp_neg_loc = math.exp(-self.loc) if self.law in (LAW_COS_POISSON_EXP, LAW_COS_POISSON_STEP) else 0.0
         if self.law == LAW_REPARAM:
             s.mean = _ptr(self.mean)
             s.stdev = _ptr(self.stdev)

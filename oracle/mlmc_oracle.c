@@ -41,6 +41,12 @@
  *     (eq. (18) with a general xi; Theorem 3.1's xi** quantised, see
  *     orc_optimal_weights): the same 64-bit word x gives T = floor(x W / 2^64)
  *     and r is the column whose cumulative-weight interval holds T.
+ *   - The laws of the experiments of Sec. 4 (orc_law below): element e of
+ *     column j draws its own Philox call, counter (e, k, j, 3<<28 | level<<20
+ *     | problem), and uses its four uniforms for the normal (Box-Muller from
+ *     u0, u1, both of its normals where the law needs two), the Poisson
+ *     variable (inverse CDF from u0), the exponential (-ln u1) and the
+ *     Bernoulli decision (u < scale, u2 or u1).
  *   - The coarse sketch uses the first c_{l-1} of the c_l fine indices.
  *     Draws are i.i.d., so any fixed subset of c_{l-1} indices has the law the
  *     paper requires; the prefix nests the levels exactly.
@@ -57,14 +63,24 @@
 
 #define ORC_TAG_INDEX 1u
 #define ORC_TAG_VALUE 2u
+#define ORC_TAG_EXPERIMENT 3u
 
-enum { ORC_LAW_NORMAL = 0, ORC_LAW_UNIFORM = 1, ORC_LAW_REPARAM = 2 };
+enum { ORC_LAW_NORMAL = 0, ORC_LAW_UNIFORM = 1, ORC_LAW_REPARAM = 2, ORC_LAW_RAMP_NORMAL = 3,
+       ORC_LAW_COS_POISSON_EXP = 4, ORC_LAW_SIN_RAMP = 5, ORC_LAW_COS_POISSON_STEP = 6 };
 
 /* Distribution of the entries of A (m x n) or B (n x p).
  *   NORMAL:  loc + scale * z, z ~ N(0, 1)
  *   UNIFORM: loc + scale * (2u - 1), u ~ U(0, 1)
  *   REPARAM: mean[.] + stdev[.] * z; A is column-major (element (i, j) at
- *            j*ld + i), B is row-major (element (j, q) at j*ld + q). */
+ *            j*ld + i), B is row-major (element (j, q) at j*ld + q).
+ * The laws of the experiments of Sec. 4 (column j counted from 1 as in the
+ * paper, K ~ Poisson(loc), E ~ Exp(1), z, z' ~ N(0, 1), u ~ U(0, 1)):
+ *   RAMP_NORMAL:       (j scale) (loc - z)                    (Sec. 4.1, a_j: scale 1/50, loc 0.4)
+ *   COS_POISSON_EXP:   cos(K + 2 E) [u < scale]               (Sec. 4.1, b_j: loc 10, scale 0.05)
+ *   SIN_RAMP:          sin(x) + z' x, x = (j scale)(loc - z)  (Sec. 4.2, A_ij: scale 1e-4, loc 0.5)
+ *   COS_POISSON_STEP:  cos(K) H(5 - K) [u < scale]            (Sec. 4.2, B_jk: loc 2, scale 0.2)
+ * exp_neg_loc = exp(-loc) for the Poisson laws (the first term of the
+ * inverse-CDF walk). */
 typedef struct {
     int32_t law;
     double loc;
@@ -72,6 +88,7 @@ typedef struct {
     const double* mean;
     const double* stdev;
     int64_t ld;
+    double exp_neg_loc;
 } orc_law;
 
 /* Target function f of Sec. 3, applied entrywise to a sketch.
@@ -266,12 +283,60 @@ static double std_normal(uint64_t seed, uint32_t problem, uint32_t level_field,
     return (e & 1) ? radius * sin(angle) : radius * cos(angle);
 }
 
+/* Poisson(lambda) by walking the CDF from 0: the smallest K with
+ * F(K) >= u, F accumulated term by term (p_K = p_{K-1} lambda / K). */
+static int64_t poisson_inverse(double u, double lambda, double exp_neg_lambda)
+{
+    int64_t K = 0;
+    double p = exp_neg_lambda, F = p;
+    while (u > F && K < 1000) {
+        K += 1;
+        p = (p * lambda) / (double)K;
+        F = F + p;
+    }
+    return K;
+}
+
+/* The experiment laws: element e of column j of realisation k draws its own
+ * Philox call (counter (e, k, j, 3<<28 | level<<20 | problem)), four uniforms
+ * u0..u3; normals by Box-Muller from (u0, u1). */
+static double experiment_value(const orc_law* law, uint64_t seed, uint32_t problem, uint32_t level_field,
+                               uint32_t k, int64_t j, int64_t e)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    uint32_t ctr[4] = { (uint32_t)e, k, (uint32_t)j, stream_word(ORC_TAG_EXPERIMENT, level_field, problem) };
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+    double u[4];
+    for (int i = 0; i < 4; ++i)
+        u[i] = orc_uniform(w[i]);
+    double col = (double)(j + 1);
+    if (law->law == ORC_LAW_RAMP_NORMAL || law->law == ORC_LAW_SIN_RAMP) {
+        double radius = sqrt(-2.0 * log(u[0]));
+        double z = radius * cos(two_pi * u[1]);
+        double x = (col * law->scale) * (law->loc - z);
+        if (law->law == ORC_LAW_RAMP_NORMAL)
+            return x;
+        double z2 = radius * sin(two_pi * u[1]);
+        return sin(x) + z2 * x;
+    }
+    int64_t K = poisson_inverse(u[0], law->loc, law->exp_neg_loc);
+    if (law->law == ORC_LAW_COS_POISSON_EXP) {
+        double E = -log(u[1]);
+        return u[2] < law->scale ? cos((double)K + 2.0 * E) : 0.0;
+    }
+    return (u[1] < law->scale && K <= 5) ? cos((double)K) : 0.0;
+}
+
 /* Entry (row, col) of one realisation, produced from the element number e of
  * the column vector v_j. */
 static double law_value(const orc_law* law, uint64_t seed, uint32_t problem,
                         uint32_t level_field, uint32_t k, int64_t j, int64_t e,
                         int64_t mat_index)
 {
+    if (law->law >= ORC_LAW_RAMP_NORMAL)
+        return experiment_value(law, seed, problem, level_field, k, j, e);
     if (law->law == ORC_LAW_UNIFORM) {
         double u = orc_uniform(value_word(seed, problem, level_field, k, j, e));
         return law->loc + law->scale * (2.0 * u - 1.0);
