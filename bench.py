@@ -70,7 +70,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="inner", choices=["inner", "matmul-large", "matmul-small", "diff", "batched", "matmul-large-fixed",
-                             "importance"])
+                             "importance", "experiments"])
     ap.add_argument("--prec", default=None, help="fp32 (default) or fp64; bf16 for matmul")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-check", action="store_true",
@@ -174,6 +174,8 @@ def main():
         return bench_large_fixed(args)
     if args.workload == "importance":
         return bench_importance(args)
+    if args.workload == "experiments":
+        return bench_experiments(args)
     if args.workload == "inner":
         wl = workloads.INNER_2POW20
         prec = args.prec or "fp32"
@@ -385,6 +387,174 @@ def bench_importance(args):
     print(json.dumps(out), flush=True)
 
 
+def _experiment_laws(wl):
+    from paper_1904_00429_amd import Func, Law
+    return (getattr(Law, wl.law_a[0])(*wl.law_a[1]), getattr(Law, wl.law_b[0])(*wl.law_b[1]),
+            getattr(Func, wl.func[0])(*wl.func[1]))
+
+
+def _experiment_run(api, wl, A, B, f, prec, dev, seed, eps=0.0, n_samples=None, timing=False):
+    """One estimate through the C ABI (adaptive L in target mode), with the
+    library's per-class kernel times when `timing`."""
+    import ctypes
+    import torch
+    c = wl.c if n_samples is None else wl.c[:len(n_samples)]
+    h = api._LevelsHolder(c, n_samples, eps, wl.pilot, seed, prec, False, 0, 0, f, n_samples is None)
+    if timing:
+        h.lv.flags |= 2
+    lib = api.lib()
+    rep = api.Report()
+    da, db = A.c(), B.c()
+    if wl.kind == "inner":
+        need = int(lib.mlmc_inner_product_workspace_size(wl.n, ctypes.byref(h.lv)))
+    else:
+        need = int(lib.mlmc_matmul_workspace_size(wl.m, wl.n, wl.p, ctypes.byref(h.lv)))
+    key = ("exp", wl.name, prec, len(c))
+    if key not in _WS or _WS[key][0].numel() < need:
+        _WS.pop(key, None)
+        torch.cuda.empty_cache()
+        _WS[key] = (torch.empty(need, dtype=torch.uint8, device=dev),
+                    torch.empty((wl.m, wl.p), dtype=torch.float64, device=dev))
+    ws, out = _WS[key]
+    if wl.kind == "inner":
+        st = lib.mlmc_inner_product_estimate(wl.n, ctypes.byref(da), ctypes.byref(db), ctypes.byref(h.lv),
+                                             out.data_ptr(), None, ws.data_ptr(), ws.numel(), ctypes.byref(rep),
+                                             api._stream(dev))
+    else:
+        st = lib.mlmc_matmul_estimate(wl.m, wl.n, wl.p, ctypes.byref(da), ctypes.byref(db), ctypes.byref(h.lv),
+                                      out.data_ptr(), None, ws.data_ptr(), ws.numel(), ctypes.byref(rep),
+                                      api._stream(dev))
+    api.check(st)
+    return _Rep(out.clone(), rep, len(c))
+
+
+def cpu_baseline_experiment(wl, n_used, budget_s=6.0):
+    """The oracle (one core) on the same laws, f, ladder and N_l.
+
+    Inner product: max(2, N_l / 20) realisations per level at the full n,
+    scaled by N_l.  Matrix product: per level, the time per realisation is
+    measured at m = p = 24 and 48 (a few realisations, capped by the draws a
+    level needs) and fitted as alpha (m + p) + beta m p (generation of the
+    sampled columns plus the sketch), evaluated at the full shape and summed
+    over N_l."""
+    import oracle
+    oracle.build(force=False)
+    kinds = {"ramp_normal": (oracle.LAW_RAMP_NORMAL, 1, 0), "cos_poisson_exp": (oracle.LAW_COS_POISSON_EXP, 0, 1),
+             "sin_ramp": (oracle.LAW_SIN_RAMP, 1, 0), "cos_poisson_step": (oracle.LAW_COS_POISSON_STEP, 0, 1)}
+
+    def law(desc):
+        kind, iscale, iloc = kinds[desc[0]]
+        return oracle.Law.experiment(kind, desc[1][iloc], desc[1][iscale])
+    A, B = law(wl.law_a), law(wl.law_b)
+    f = getattr(oracle.Func, wl.func[0])(*wl.func[1])
+    total, run, t_all = 0.0, 0, time.perf_counter()
+    for l, N in enumerate(n_used):
+        if N == 0:
+            continue
+        cp = wl.c[l - 1] if l else 0
+        if wl.kind == "inner":
+            k = max(2, N // 20)
+            st = oracle.LevelState.empty(1, 1)
+            t0 = time.perf_counter()
+            oracle.level_estimation(st, 1, wl.n, 1, A, B, wl.c[l], cp, 0, 0, l, 0, k, func=f)
+            total += N * (time.perf_counter() - t0) / k
+            run += k
+            continue
+        times = []
+        for e in (24, 48):
+            k = max(1, min(N, int(5e4 // wl.c[l])))
+            st = oracle.LevelState.empty(e, e)
+            t0 = time.perf_counter()
+            oracle.level_estimation(st, e, wl.n, e, A, B, wl.c[l], cp, 0, 0, l, 0, k, func=f)
+            times.append((time.perf_counter() - t0) / k)
+            run += k
+        # t = alpha (2e) + beta e^2 at e = 24, 48
+        beta = (times[1] - 2.0 * times[0]) / (48.0 ** 2 - 2.0 * 24.0 ** 2)
+        alpha = (times[0] - beta * 24.0 ** 2) / 48.0
+        beta, alpha = max(beta, 0.0), max(alpha, 0.0)
+        total += N * (alpha * (wl.m + wl.p) + beta * wl.m * wl.p)
+    dt = time.perf_counter() - t_all
+    sample = (f"{run} realisations (N_l / 20 per level) at n = {wl.n}" if wl.kind == "inner" else
+              f"{run} realisations at m = p = 24 and 48 per level, time per realisation fitted as "
+              f"alpha (m + p) + beta m p and evaluated at {wl.m} x {wl.p}")
+    return {"value": 1.0 / total, "unit": "estimates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sample}; {dt:.1f} s"}
+
+
+def bench_experiments(args):
+    """The experiments of Sec. 4 at the paper's sizes: adaptive L on M = 10
+    ladders, eps = 0.1 of the size of E[f] (from an untimed fixed-N reference
+    estimate; Sec. 4.1's N_l scaled by 1/20); estimates/s of each, with the
+    spread of the independent estimates as the observed RMSE."""
+    import torch
+    import paper_1904_00429_amd.mlmc as api
+    from paper_1904_00429_amd import workloads
+    dev = torch.device("cuda:0")
+    prec = args.prec or "fp32"
+    res = {}
+    for wl in (workloads.EXP41_INNER, workloads.EXP42_MATMUL):
+        A, B, f = _experiment_laws(wl)
+        print(f"[experiments] {wl.name}: reference", flush=True)
+        ref = _experiment_run(api, wl, A, B, f, "fp64" if wl.kind == "inner" else prec, dev, 10 ** 6,
+                              n_samples=wl.ref_n)
+        # every entry of E[f(AB)] is the same (the laws depend on the column j
+        # of A and row j of B only): the mean of the entries estimates it
+        size = abs(float(ref.Y.mean())) * math.sqrt(wl.m * wl.p)
+        eps = wl.rel_eps * size / math.sqrt(wl.n_scale)
+        for i in range(args.warmup):
+            _experiment_run(api, wl, A, B, f, prec, dev, 1000 + i, eps=eps)
+        torch.cuda.synchronize()
+        print(f"[experiments] {wl.name}: timing", flush=True)
+        t0 = time.perf_counter()
+        runs = [_experiment_run(api, wl, A, B, f, prec, dev, i, eps=eps, timing=True) for i in range(args.steps)]
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / args.steps
+        # observed RMSE: spread of the independent estimates around their mean
+        ybar = sum(r.Y for r in runs) / len(runs)
+        spread = math.sqrt(sum(float(torch.linalg.norm(r.Y - ybar)) ** 2 for r in runs) / max(len(runs) - 1, 1))
+        k_ms = [sum(r.kernel_ms[i] for r in runs) / args.steps for i in range(4)]
+        k_n = [sum(r.kernel_launches[i] for r in runs) for i in range(4)]
+        draws = sum(r.total_draws for r in runs) / args.steps
+        entry = {"estimates_per_s": 1.0 / sec, "ms_per_estimate": 1e3 * sec, "eps": eps,
+                 "reference": {"norm": size, "rmse_est": ref.rmse_est, "n_samples": wl.ref_n},
+                 "levels_used": [r.levels_used for r in runs],
+                 "bias_test_passed": [r.bias_test_passed for r in runs],
+                 "n_used": runs[-1].n_used, "rmse_est": runs[-1].rmse_est, "draws_per_estimate": draws,
+                 "rmse_observed": spread, "relative_rmse_observed": spread / size,
+                 "kernel_ms_per_estimate": {"sample": k_ms[0], "gather": k_ms[1], "merge": k_ms[2], "final": k_ms[3]},
+                 "launches_per_estimate": [x / args.steps for x in k_n]}
+        if wl.kind == "inner":
+            entry["paper_time_s"] = 0.047
+        else:
+            flops = 2.0 * wl.m * wl.p * draws
+            entry["sketch_tflops"] = flops / (k_ms[0] * 1e-3) / 1e12
+            entry["values_per_s_gather"] = draws * (wl.m + wl.p) / (k_ms[1] * 1e-3)
+            entry["paper_time_s"] = 2.240
+        res[wl.name] = (wl, entry)
+        print(f"[experiments] {wl.name}: {json.dumps(entry)}", flush=True)
+    wl, e = res[workloads.EXP42_MATMUL.name]
+    flops = 2.0 * wl.m * wl.p * e["draws_per_estimate"]
+    sk = e["kernel_ms_per_estimate"]["sample"]
+    out = {"metric": "MLMC estimates/s of E[f(AB)] on the laws of Sec. 4.2 (adaptive L, eps 0.1 relative)",
+           "value": e["estimates_per_s"], "unit": "estimates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": e["ms_per_estimate"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16"}[prec],
+           "data": "synthetic (the laws of Sec. 4 generated inside the estimate)",
+           "config": {"workload": wl.name, "m": wl.m, "n": wl.n, "p": wl.p, "ladder": "c_l = 10^l, l <= 6",
+                      "func": "|x| H(2 - x)", "eps": e["eps"], "prec": prec, "adaptive": True},
+           "experiments": {name: entry for name, (_, entry) in res.items()},
+           "roofline": {"bound": "mfma", "kernel": f"sketch_kernel<{prec}> (target-function form)",
+                        "achieved": flops / (sk * 1e-3) / 1e12, "peak": PEAK_MFMA[prec] / 1e12,
+                        "unit": "TFLOP/s", "frac": flops / (sk * 1e-3) / PEAK_MFMA[prec], "traffic": None,
+                        "note": "algorithmic 2 m p flops per draw over the sketch launches of an estimate; "
+                                "the gather of the sampled columns is timed separately"}}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_experiment(wl, e["n_used"])
+        wi, ei = res[workloads.EXP41_INNER.name]
+        out["experiments"][wi.name]["cpu_baseline"] = cpu_baseline_experiment(wi, ei["n_used"])
+    print(json.dumps(out), flush=True)
+
+
 def _time_replays(est, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -537,6 +707,7 @@ class _Rep:
         self.kernel_ms = [float(rep.kernel_ms[i]) for i in range(4)]
         self.kernel_launches = [int(rep.kernel_launches[i]) for i in range(4)]
         self.levels_used = int(rep.levels_used)
+        self.bias_test_passed = bool(rep.bias_test_passed)
 
 
 if __name__ == "__main__":

@@ -56,7 +56,24 @@ typedef enum {
 typedef enum {
     MLMC_LAW_NORMAL = 0,  /* loc + scale * N(0, 1), i.i.d. entries */
     MLMC_LAW_UNIFORM = 1, /* loc + scale * U(-1, 1), i.i.d. entries */
-    MLMC_LAW_REPARAM = 2  /* mean + stdev (entrywise) * N(0, 1) */
+    MLMC_LAW_REPARAM = 2, /* mean + stdev (entrywise) * N(0, 1) */
+    /* The laws of the experiments of Sec. 4, independent entries whose law
+     * depends on the column j (counted from 1); K ~ Poisson(loc),
+     * E ~ Exp(1), z, z' ~ N(0, 1), u ~ U(0, 1).  Both operands take one of
+     * them or neither does (EINVAL); not with FP8 operands (EINVAL).
+     * Element e of column j of realisation k draws its own Philox call,
+     * counter (e, k, j, 3 << 28 | level << 20 | problem), with uniforms
+     * u0, u1, u2: z = sqrt(-2 ln u0) cos(2 pi u1), z' the sine half; K the
+     * smallest integer with P(Poisson <= K) >= u0 (CDF summed term by term
+     * from exp(-loc)); E = -ln u1; the mask is u2 < scale (4) or u1 < scale
+     * (6).  Evaluated in FP64 in every precision. */
+    MLMC_LAW_RAMP_NORMAL = 3,     /* (j scale)(loc - z): Sec. 4.1's x (scale 1/50, loc 0.4) */
+    MLMC_LAW_COS_POISSON_EXP = 4, /* cos(K + 2E) [u < scale]: Sec. 4.1's y (loc 10, scale 0.05);
+                                     loc in (0, 500], scale in [0, 1] */
+    MLMC_LAW_SIN_RAMP = 5,        /* sin(x) + z' x, x = (j scale)(loc - z): Sec. 4.2's A
+                                     (scale 1e-4, loc 0.5) */
+    MLMC_LAW_COS_POISSON_STEP = 6 /* cos(K) H(5 - K) [u < scale]: Sec. 4.2's B (loc 2,
+                                     scale 0.2); loc in (0, 500], scale in [0, 1] */
 } mlmc_law;
 
 typedef enum {
@@ -295,7 +312,8 @@ mlmc_status mlmc_gather_columns(int64_t m, int64_t n, int64_t p, const mlmc_dist
  * w_j = max(1, floor(2^24 s_j / max_i s_i)).  For i.i.d. laws every column
  * has the same moments and w_j = 2^24.  weights: device uint32[n];
  * scratch: device, at least (n + 1) doubles (reparameterised laws).
- * Errors: EINVAL (sizes, null pointers, mixed law kinds). */
+ * Errors: EINVAL (sizes, null pointers, mixed law kinds, the laws of
+ * Sec. 4). */
 mlmc_status mlmc_optimal_index_weights(int64_t m, int64_t n, int64_t p, const mlmc_dist* A,
                                        const mlmc_dist* B, uint32_t* weights, double* scratch,
                                        void* stream);

@@ -81,13 +81,30 @@ mlmc_status check_levels(const mlmc_levels* lv, bool inner)
 mlmc_status check_dist(const mlmc_dist* d, const char* name, int64_t min_ld, bool inner)
 {
     if (!d) return fail(MLMC_EINVAL, "%s is NULL", name);
-    if (d->law < MLMC_LAW_NORMAL || d->law > MLMC_LAW_REPARAM) return fail(MLMC_EINVAL, "%s: unknown law", name);
-    if (d->law == MLMC_LAW_REPARAM) {
+    if (d->law < MLMC_LAW_NORMAL || d->law > MLMC_LAW_COS_POISSON_STEP)
+        return fail(MLMC_EINVAL, "%s: unknown law", name);
+    if (d->law == MLMC_LAW_COS_POISSON_EXP || d->law == MLMC_LAW_COS_POISSON_STEP) {
+        // exp(-loc) stays a normal FP64 number and the CDF walk ends well
+        // inside its 1000 terms
+        if (!(d->loc > 0.0 && d->loc <= 500.0)) return fail(MLMC_EINVAL, "%s: Poisson rate must be in (0, 500]", name);
+        if (!(d->scale >= 0.0 && d->scale <= 1.0))
+            return fail(MLMC_EINVAL, "%s: Bernoulli rate must be in [0, 1]", name);
+    } else if (d->law == MLMC_LAW_REPARAM) {
         if (!d->mean || !d->stdev) return fail(MLMC_EINVAL, "%s: reparam law needs mean and stdev", name);
         if (!inner && d->ld < min_ld) return fail(MLMC_EINVAL, "%s: ld must be >= %lld", name, (long long)min_ld);
     } else if (!isfinite(d->loc) || !isfinite(d->scale)) {
         return fail(MLMC_EINVAL, "%s: loc and scale must be finite", name);
     }
+    return MLMC_OK;
+}
+
+// The laws of Sec. 4 pair only with each other (their gather is a kernel of
+// its own) and are not offered with FP8 operands.
+mlmc_status check_pair(const mlmc_dist* a, const mlmc_dist* b, int32_t prec)
+{
+    const bool ea = a->law >= MLMC_LAW_RAMP_NORMAL, eb = b->law >= MLMC_LAW_RAMP_NORMAL;
+    if (ea != eb) return fail(MLMC_EINVAL, "the laws of the experiments pair only with each other");
+    if (ea && prec == MLMC_PREC_FP8) return fail(MLMC_EINVAL, "the laws of the experiments are not offered with FP8");
     return MLMC_OK;
 }
 
@@ -100,6 +117,8 @@ Law to_law(const mlmc_dist& d)
     l.mean = d.mean;
     l.stdev = d.stdev;
     l.ld = d.ld;
+    // first term of the Poisson CDF walk, exp(-lambda), on the host
+    l.aux = (d.law == MLMC_LAW_COS_POISSON_EXP || d.law == MLMC_LAW_COS_POISSON_STEP) ? exp(-d.loc) : 0.0;
     return l;
 }
 
@@ -287,6 +306,7 @@ mlmc_status mlmc_inner_product_estimate(int64_t n, const mlmc_dist* x, const mlm
     if (st != MLMC_OK) return st;
     if ((st = check_dist(x, "x", 1, true)) != MLMC_OK) return st;
     if ((st = check_dist(y, "y", 1, true)) != MLMC_OK) return st;
+    if ((st = check_pair(x, y, lv->prec)) != MLMC_OK) return st;
     if (!out) return fail(MLMC_EINVAL, "out is NULL");
     const InnerLayout L = inner_layout(lv->num_levels, n, lv->index_weights != nullptr);
     if (!workspace || workspace_bytes < L.total)
@@ -405,6 +425,7 @@ mlmc_status mlmc_matmul_estimate(int64_t m, int64_t n, int64_t p, const mlmc_dis
     if (st != MLMC_OK) return st;
     if ((st = check_dist(A, "A", m, false)) != MLMC_OK) return st;
     if ((st = check_dist(B, "B", p, false)) != MLMC_OK) return st;
+    if ((st = check_pair(A, B, lv->prec)) != MLMC_OK) return st;
     if (!out) return fail(MLMC_EINVAL, "out is NULL");
     MatmulProblem pr{m, n, p, to_law(*A), to_law(*B), lv->problem, out, level_means};
     MatmulPlan plan;
@@ -532,6 +553,9 @@ mlmc_status check_batch(int32_t nprob, const mlmc_problem* probs, const mlmc_lev
             return fail(MLMC_EINVAL, "problem %d: m, p >= 1 and 1 <= n < 2^32 required", i);
         if ((st = check_dist(&pr.A, "A", pr.m, false)) != MLMC_OK) return st;
         if ((st = check_dist(&pr.B, "B", pr.p, false)) != MLMC_OK) return st;
+        if ((st = check_pair(&pr.A, &pr.B, lv->prec)) != MLMC_OK) return st;
+        if ((pr.A.law >= MLMC_LAW_RAMP_NORMAL) != (probs[0].A.law >= MLMC_LAW_RAMP_NORMAL))
+            return fail(MLMC_EINVAL, "problem %d: the laws of the experiments are used by every product or none", i);
         if (!pr.out) return fail(MLMC_EINVAL, "problem %d: out is NULL", i);
         if (pr.problem >= (1u << 20)) return fail(MLMC_EINVAL, "problem %d: stream id must be < 2^20", i);
         ids.push_back(pr.problem);
@@ -762,6 +786,8 @@ mlmc_status mlmc_optimal_index_weights(int64_t m, int64_t n, int64_t p, const ml
     mlmc_status st;
     if ((st = check_dist(A, "A", m, false)) != MLMC_OK) return st;
     if ((st = check_dist(B, "B", p, false)) != MLMC_OK) return st;
+    if (A->law >= MLMC_LAW_RAMP_NORMAL || B->law >= MLMC_LAW_RAMP_NORMAL)
+        return fail(MLMC_EINVAL, "xi** is computed for reparameterised or i.i.d. laws");
     const bool reparam = A->law == MLMC_LAW_REPARAM;
     if (reparam != (B->law == MLMC_LAW_REPARAM))
         return fail(MLMC_EINVAL, "A and B must both be reparameterised, or both i.i.d.");
@@ -782,6 +808,7 @@ mlmc_status mlmc_gather_columns(int64_t m, int64_t n, int64_t p, const mlmc_dist
     mlmc_status st;
     if ((st = check_dist(A, "A", m, false)) != MLMC_OK) return st;
     if ((st = check_dist(B, "B", p, false)) != MLMC_OK) return st;
+    if ((st = check_pair(A, B, prec)) != MLMC_OK) return st;
     StreamKeys keys{(uint32_t)seed, (uint32_t)(seed >> 32), problem};
     hipError_t e = gather_columns_f64(m, n, p, to_law(*A), to_law(*B), keys, level_field, k0, num_samples, c, prec,
                                       AS, BS, static_cast<hipStream_t>(stream));

@@ -138,6 +138,22 @@ __global__ void gather_f64_kernel(int64_t m, int64_t p, uint32_t n, Law A, Law B
     const int64_t s = i / (quads * c);
     const uint32_t k = k0 + (uint32_t)s;
     const uint32_t j = draw_index((uint32_t)t, k, sid_index, key0, key1, n);
+    if (A.kind >= kLawExperimentFirst) {
+        // the laws of Sec. 4 (both operands): one experiment-stream call per element
+        const uint32_t sid_exp = (sid_value & 0x0FFFFFFFu) | (kTagExperiment << 28);
+        for (int r = 0; r < 4; ++r) {
+            const int64_t e = 4 * q + r;
+            if (e >= m + p) break;
+            const Law& L = e < m ? A : B;
+            const Compute v = (Compute)experiment_value(L.kind, L.loc, L.scale, L.aux, (uint32_t)e, k, j, sid_exp,
+                                                        key0, key1);
+            double out = (double)v;
+            if (ROUND_BF16) out = (double)(float)(__bf16)(float)v;
+            if (e < m) AS[(s * c + t) * m + e] = out;
+            else BS[(s * c + t) * p + (e - m)] = out;
+        }
+        return;
+    }
     const Words4 w = philox4x32_10((uint32_t)q, k, j, sid_value, key0, key1);
     const bool normal = A.kind != 1 || B.kind != 1;
     Compute u[4], z[4];
@@ -196,6 +212,7 @@ hipError_t optimal_weights(int64_t m, int64_t n, int64_t p, const Law& A, const 
                            double* scratch, hipStream_t stream)
 {
     const dim3 grid((unsigned)ceil_div(n, 256));
+    if (A.kind >= kLawExperimentFirst || B.kind >= kLawExperimentFirst) return hipErrorInvalidValue;
     if (A.kind != 2 || B.kind != 2) {
         hipLaunchKernelGGL(quantise_weights_kernel, grid, dim3(256), 0, stream, nullptr, nullptr, n, w);
         return hipGetLastError();
@@ -212,6 +229,7 @@ hipError_t gather_columns_f64(int64_t m, int64_t n, int64_t p, const Law& A, con
 {
     const int64_t work = num_samples * c * ceil_div(m + p, 4);
     if (work <= 0) return hipSuccess;
+    if ((A.kind >= kLawExperimentFirst) != (B.kind >= kLawExperimentFirst)) return hipErrorInvalidValue;
     const uint32_t si = stream_id(kTagIndex, level_field, keys.problem);
     const uint32_t sv = stream_id(kTagValue, level_field, keys.problem);
     const dim3 grid((unsigned)ceil_div(work, 256));

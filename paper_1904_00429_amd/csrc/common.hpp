@@ -12,13 +12,54 @@ constexpr int kWave = 64;
 
 // Entry law as the kernels see it (mirrors mlmc_dist of the C ABI).
 struct Law {
-    int32_t kind;      // 0 normal, 1 uniform, 2 reparam
+    int32_t kind;      // 0 normal, 1 uniform, 2 reparam, 3 .. 6 the laws of Sec. 4
     double loc;
     double scale;
     const float* mean;
     const float* stdev;
     int64_t ld;
+    double aux;        // exp(-loc) for the Poisson laws (4, 6), computed on the host
 };
+
+// Laws of the experiments of Sec. 4 (kinds 3 .. 6).  Column j is counted
+// from 1 as in the paper; K ~ Poisson(loc), E ~ Exp(1), z, z' ~ N(0, 1),
+// u ~ U(0, 1):
+//   3  (j scale)(loc - z)                       Sec. 4.1, x_j
+//   4  cos(K + 2E) [u < scale]                  Sec. 4.1, y_j
+//   5  sin(x) + z' x,  x = (j scale)(loc - z)   Sec. 4.2, A_ij
+//   6  cos(K) H(5 - K) [u < scale]              Sec. 4.2, B_jk
+// Element e of the column vector v_j = [A[:, j]; B[j, :]] of realisation k
+// takes a Philox call of its own, counter (e, k, j, experiment stream), and
+// its uniforms u0, u1, u2: Box-Muller on (u0, u1) gives z (cosine half) and
+// z' (sine half); K is the smallest integer with F(K) >= u0, the Poisson CDF
+// accumulated term by term from exp(-loc); E = -ln u1; the Bernoulli factor
+// is u2 < scale (kind 4) or u1 < scale (kind 6).  Evaluated in FP64 in every
+// precision, so the integer decisions (K, the mask) never depend on it.
+constexpr int kLawExperimentFirst = 3;
+
+__device__ inline double experiment_value(int kind, double loc, double scale, double exp_neg_loc, uint32_t e,
+                                          uint32_t k, uint32_t j, uint32_t sid_experiment, uint32_t key0,
+                                          uint32_t key1)
+{
+    const Words4 w = philox4x32_10(e, k, j, sid_experiment, key0, key1);
+    const double u0 = unit_f64(w.w0), u1 = unit_f64(w.w1);
+    if (kind == 3 || kind == 5) {
+        const double rho = sqrt(-2.0 * log(u0));
+        double s, c;
+        sincos(6.283185307179586476925286766559 * u1, &s, &c);
+        const double x = (((double)j + 1.0) * scale) * (loc - rho * c);
+        return kind == 3 ? x : sin(x) + (rho * s) * x;
+    }
+    int K = 0;
+    double pk = exp_neg_loc, F = pk;
+    while (u0 > F && K < 1000) {
+        K += 1;
+        pk = (pk * loc) / (double)K;
+        F = F + pk;
+    }
+    if (kind == 4) return unit_f64(w.w2) < scale ? cos((double)K - 2.0 * log(u1)) : 0.0;
+    return (u1 < scale && K <= 5) ? cos((double)K) : 0.0;
+}
 
 // Welford / Chan statistics of a set of scalars: count, mean, sum of squared
 // deviations.  Merging two sets is exact in exact arithmetic (Chan, Golub,
@@ -75,10 +116,13 @@ __device__ __forceinline__ T target_value(int kind, T x, T theta0, T theta1)
 
 // Law pairs with a specialised kernel instantiation (no per-value law branches
 // in hot loops); every other combination takes the general path.
-enum { kLawsAny = 0, kLawsUniform = 1, kLawsNormal = 2 };
+// kLawsExperiment: both laws are laws of Sec. 4 (they pair only with each
+// other; the entry points reject a mixed pair).
+enum { kLawsAny = 0, kLawsUniform = 1, kLawsNormal = 2, kLawsExperiment = 3 };
 
 __host__ __device__ inline int law_pair_kind(int a, int b)
 {
+    if (a >= kLawExperimentFirst && b >= kLawExperimentFirst) return kLawsExperiment;
     return (a == 1 && b == 1) ? kLawsUniform : (a == 0 && b == 0) ? kLawsNormal : kLawsAny;
 }
 

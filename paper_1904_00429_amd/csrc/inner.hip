@@ -70,6 +70,16 @@ template <typename T, int LAWS>
 __device__ __forceinline__ T inner_product_term(const InnerMultiParams& prm, uint32_t k, uint32_t j,
                                                 uint32_t sid_value)
 {
+    if constexpr (LAWS == kLawsExperiment) {
+        // x_j is element 0 and y_j element 1 of the column vector v_j, each
+        // from its own call of the experiment stream
+        const uint32_t sid_exp = (sid_value & 0x0FFFFFFFu) | (kTagExperiment << 28);
+        const T xv = (T)experiment_value(prm.x.kind, prm.x.loc, prm.x.scale, prm.x.aux, 0u, k, j, sid_exp,
+                                         prm.key0, prm.key1);
+        const T yv = (T)experiment_value(prm.y.kind, prm.y.loc, prm.y.scale, prm.y.aux, 1u, k, j, sid_exp,
+                                         prm.key0, prm.key1);
+        return xv * yv;
+    }
     const Words4 w = philox4x32_10(0u, k, j, sid_value, prm.key0, prm.key1);
     const T u0 = unit<T>(w.w0);
     const T u1 = unit<T>(w.w1);
@@ -301,6 +311,8 @@ static void launch_inner(int laws, dim3 grid, hipStream_t stream, const InnerMul
         hipLaunchKernelGGL((inner_multi_kernel<T, kLawsUniform, FN, IW>), grid, block, 0, stream, prm);
     else if (laws == kLawsNormal)
         hipLaunchKernelGGL((inner_multi_kernel<T, kLawsNormal, FN, IW>), grid, block, 0, stream, prm);
+    else if (laws == kLawsExperiment)
+        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsExperiment, FN, IW>), grid, block, 0, stream, prm);
     else
         hipLaunchKernelGGL((inner_multi_kernel<T, kLawsAny, FN, IW>), grid, block, 0, stream, prm);
 }
@@ -396,6 +408,9 @@ hipError_t inner_levels_run(const LevelRange* ranges, int num_levels, int64_t n,
     }
     if (next == 0) return hipSuccess;
     const int laws = law_pair_kind(x.kind, y.kind);
+    // the laws of Sec. 4 pair only with each other
+    if (laws != kLawsExperiment && (x.kind >= kLawExperimentFirst || y.kind >= kLawExperimentFirst))
+        return hipErrorInvalidValue;
     {
         ScopedTiming t(timer, 0);
         const dim3 grid(next);

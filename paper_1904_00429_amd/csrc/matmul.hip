@@ -185,6 +185,63 @@ template <> struct StoreOf<uint8_t> {
     }
 };
 
+// Column of each of the block's positions (kNoDrawColumn for padding) and
+// its per-draw factor 1 / (n xi_j) (eq. (18) with a general xi; 1 for
+// uniform draws), into LDS; ends with a barrier.
+constexpr uint32_t kNoDrawColumn = 0xFFFFFFFFu;
+
+template <typename Compute>
+__device__ __forceinline__ void draw_block_columns(const GatherParams& prm, int64_t pos_base, int npos_block,
+                                                   uint32_t k, uint32_t n, uint32_t sid_index, uint32_t* cols,
+                                                   Compute* colf)
+{
+    for (int i = threadIdx.x; i < npos_block; i += kGatherThreads) {
+        const int64_t t = draw_of_position(pos_base + i, prm.kc, prm.c, prm.c_prev);
+        uint32_t j = kNoDrawColumn;
+        Compute f = (Compute)1;
+        if (t >= 0) {
+            if (prm.cum) {
+                const uint64_t total = prm.cum[n - 1];
+                j = draw_index_weighted((uint32_t)t, k, sid_index, prm.key0, prm.key1, prm.cum, n, total);
+                f = (Compute)((double)total / ((double)n * (double)prm.iw[j]));
+            } else {
+                j = draw_index((uint32_t)t, k, sid_index, prm.key0, prm.key1, n);
+            }
+        }
+        cols[i] = j;
+        colf[i] = f;
+    }
+    __syncthreads();
+}
+
+// Rows m .. m_pad - 1 of A's block and p .. p_pad - 1 of B's block are zero,
+// so the sketch's entries outside the product see D = 0.
+template <typename Compute, typename Store, int KPACK>
+__device__ __forceinline__ void zero_padding_rows(const GatherParams& prm, int64_t pos_base, int octets, int64_t m,
+                                                  int64_t p, int64_t m_pad, int64_t p_pad, Store* GA, Store* GB)
+{
+    const uint32_t pad_a = (uint32_t)(m_pad - m), pad_rows = (uint32_t)(m_pad - m + p_pad - p);
+    const Store zero = StoreOf<Store>::from((Compute)0, 1.0f);
+    for (uint32_t it = threadIdx.x; it < pad_rows * (uint32_t)octets; it += kGatherThreads) {
+        const uint32_t oc = it / pad_rows;
+        const uint32_t qr = it - oc * pad_rows;
+        const int64_t pos0 = pos_base + (int64_t)oc * kGatherPositions;
+        const int npos = (int)((prm.kpad - pos0) < kGatherPositions ? (prm.kpad - pos0) : kGatherPositions);
+        Store* G = qr < pad_a ? GA : GB;
+        const int64_t R = qr < pad_a ? m_pad : p_pad;
+        const int64_t row = qr < pad_a ? m + qr : p + (qr - pad_a);
+        if constexpr (KPACK == 1) {
+            for (int ip = 0; ip < npos; ++ip) G[(pos0 + ip) * R + row] = zero;
+        } else {
+            typedef Store vec_t __attribute__((ext_vector_type(KPACK)));
+            vec_t vv;
+#pragma unroll
+            for (int ip = 0; ip < KPACK; ++ip) vv[ip] = zero;
+            *reinterpret_cast<vec_t*>(G + ((pos0 / KPACK) * R + row) * KPACK) = vv;
+        }
+    }
+}
+
 // A block covers prm.octets groups of 8 consecutive padded positions of one
 // realisation of one product; its lanes walk the (octet, quad of 4 rows)
 // items, so a product with few rows still keeps every lane busy.
@@ -228,25 +285,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
     const int npos_block = (int)((prm.kpad - pos_base) < kGatherPositions * prm.octets ? (prm.kpad - pos_base)
                                                                                      : kGatherPositions * prm.octets);
     const int octets = (npos_block + kGatherPositions - 1) / kGatherPositions;
-    // column of each position, or kNoDraw for padding
-    constexpr uint32_t kNoDraw = 0xFFFFFFFFu;
-    for (int i = threadIdx.x; i < npos_block; i += kGatherThreads) {
-        const int64_t t = draw_of_position(pos_base + i, prm.kc, prm.c, prm.c_prev);
-        uint32_t j = kNoDraw;
-        Compute f = (Compute)1;
-        if (t >= 0) {
-            if (prm.cum) {
-                const uint64_t total = prm.cum[n - 1];
-                j = draw_index_weighted((uint32_t)t, k, sid_index, prm.key0, prm.key1, prm.cum, n, total);
-                f = (Compute)((double)total / ((double)n * (double)prm.iw[j]));
-            } else {
-                j = draw_index((uint32_t)t, k, sid_index, prm.key0, prm.key1, n);
-            }
-        }
-        cols[i] = j;
-        colf[i] = f;
-    }
-    __syncthreads();
+    draw_block_columns<Compute>(prm, pos_base, npos_block, k, n, sid_index, cols, colf);
     const int64_t rows = m + p;
     const uint32_t quads = (uint32_t)ceil_div(rows, 4);
     const bool normal = LAWS == kLawsNormal || (LAWS == kLawsAny && (LA.kind != 1 || LB.kind != 1));
@@ -361,7 +400,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
 #pragma unroll
         for (int ip = 0; ip < kGatherPositions; ++ip) {
             jv[ip] = cols[ip];
-            ok[ip] = ip < npos_block && jv[ip] != kNoDraw;
+            ok[ip] = ip < npos_block && jv[ip] != kNoDrawColumn;
         }
         for (int64_t q = threadIdx.x; q < (int64_t)quads; q += kGatherThreads) generate(0u, q, jv, ok);
     } else {
@@ -372,33 +411,66 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
 #pragma unroll
             for (int ip = 0; ip < kGatherPositions; ++ip) {
                 jv[ip] = cols[oc * kGatherPositions + ip];
-                ok[ip] = ip < npos && jv[ip] != kNoDraw;
+                ok[ip] = ip < npos && jv[ip] != kNoDrawColumn;
             }
             generate(oc, (int64_t)(it - oc * quads), jv, ok);
         }
     }
-    // rows m .. m_pad - 1 of A's block and p .. p_pad - 1 of B's block are
-    // zero, so the sketch's entries outside the product see D = 0
-    const uint32_t pad_a = (uint32_t)(m_pad - m), pad_rows = (uint32_t)(m_pad - m + p_pad - p);
-    const Store zero = StoreOf<Store>::from((Compute)0, 1.0f);
-    for (uint32_t it = threadIdx.x; it < pad_rows * (uint32_t)octets; it += kGatherThreads) {
-        const uint32_t oc = it / pad_rows;
-        const uint32_t qr = it - oc * pad_rows;
-        const int64_t pos0 = pos_base + (int64_t)oc * kGatherPositions;
-        const int npos = (int)((prm.kpad - pos0) < kGatherPositions ? (prm.kpad - pos0) : kGatherPositions);
-        Store* G = qr < pad_a ? GA : GB;
-        const int64_t R = qr < pad_a ? m_pad : p_pad;
-        const int64_t row = qr < pad_a ? m + qr : p + (qr - pad_a);
-        if constexpr (KPACK == 1) {
-            for (int ip = 0; ip < npos; ++ip) G[(pos0 + ip) * R + row] = zero;
-        } else {
-            typedef Store vec_t __attribute__((ext_vector_type(KPACK)));
-            vec_t vv;
-#pragma unroll
-            for (int ip = 0; ip < KPACK; ++ip) vv[ip] = zero;
-            *reinterpret_cast<vec_t*>(G + ((pos0 / KPACK) * R + row) * KPACK) = vv;
+    zero_padding_rows<Compute, Store, KPACK>(prm, pos_base, octets, m, p, m_pad, p_pad, GA, GB);
+}
+
+// The laws of the experiments of Sec. 4: every element is a Philox call and
+// an FP64 evaluation of its own (experiment_value), so the block's lanes walk
+// its (position, row) items row-fastest, one element each, and store it into
+// the same layouts as gather_kernel.  Not offered with FP8 operands.
+template <typename Compute, typename Store, int KPACK>
+__global__ __launch_bounds__(kGatherThreads) void gather_experiment_kernel(GatherParams prm)
+{
+    constexpr int MAXPOS = kGatherPositions * kGatherMaxOctets;
+    __shared__ uint32_t cols[MAXPOS];
+    __shared__ Compute colf[MAXPOS];
+    const ProblemDesc* Pp = prm.descs + blockIdx.z;
+    const int64_t m = Pp->m, p = Pp->p;
+    const int64_t m_pad = Pp->m_pad, p_pad = Pp->p_pad;
+    const uint32_t n = (uint32_t)Pp->n;
+    const uint32_t sid_problem = Pp->sid_problem;
+    const int64_t rows_prefix = Pp->rows_prefix;
+    const Law LA = Pp->A, LB = Pp->B;
+    const int64_t pos_base = (int64_t)blockIdx.x * kGatherPositions * prm.octets;
+    const int64_t slot = blockIdx.y;
+    const uint32_t k = prm.k_first + (uint32_t)slot;
+    const uint32_t sid_index = stream_id(kTagIndex, prm.level_field, sid_problem);
+    const uint32_t sid_exp = stream_id(kTagExperiment, prm.level_field, sid_problem);
+    const int npos_block = (int)((prm.kpad - pos_base) < kGatherPositions * prm.octets ? (prm.kpad - pos_base)
+                                                                                     : kGatherPositions * prm.octets);
+    const int octets = (npos_block + kGatherPositions - 1) / kGatherPositions;
+    draw_block_columns<Compute>(prm, pos_base, npos_block, k, n, sid_index, cols, colf);
+    const int64_t rows = m + p;
+    const int64_t pass_rows = prm.batch * prm.kpad * (int64_t)prm.elem;
+    Store* __restrict__ GA = reinterpret_cast<Store*>(prm.gbuf + pass_rows * rows_prefix) + slot * prm.kpad * m_pad;
+    Store* __restrict__ GB = reinterpret_cast<Store*>(prm.gbuf + pass_rows * (rows_prefix + m_pad)) + slot * prm.kpad * p_pad;
+    const Compute omega = (Compute)prm.omega;
+    const int64_t items = (int64_t)npos_block * rows;
+    for (int64_t it = threadIdx.x; it < items; it += kGatherThreads) {
+        const int ip = (int)(it / rows);
+        const int64_t e = it - (int64_t)ip * rows;
+        const int64_t pos = pos_base + ip;
+        const uint32_t j = cols[ip];
+        const bool in_a = e < m;
+        Compute v = (Compute)0;
+        if (j != kNoDrawColumn) {
+            const Law& L = in_a ? LA : LB;
+            v = (Compute)experiment_value(L.kind, L.loc, L.scale, L.aux, (uint32_t)e, k, j, sid_exp, prm.key0,
+                                          prm.key1);
+            // the coarse weight and the per-draw factor enter through a_t, as in gather_kernel
+            if (in_a) v = ((pos < prm.kc ? omega : (Compute)1) * colf[ip]) * v;
         }
+        Store* G = in_a ? GA : GB;
+        const int64_t R = in_a ? m_pad : p_pad;
+        const int64_t row = in_a ? e : e - m;
+        G[((pos / KPACK) * R + row) * KPACK + (pos % KPACK)] = StoreOf<Store>::from(v, 1.0f);
     }
+    zero_padding_rows<Compute, Store, KPACK>(prm, pos_base, octets, m, p, m_pad, p_pad, GA, GB);
 }
 
 // ---------------------------------------------------------------------------
@@ -1014,7 +1086,7 @@ bool matmul_plan(const MatmulProblem* probs, int nprob, int prec, int num_levels
     for (int i = 1; i < nprob; ++i)
         if (probs[i].m + probs[i].p < plan.min_rows) plan.min_rows = probs[i].m + probs[i].p;
     for (int i = 0; i < nprob; ++i) {
-        if (probs[i].A.kind == 2 || probs[i].B.kind == 2) plan.iid = false;
+        if (probs[i].A.kind >= 2 || probs[i].B.kind >= 2) plan.iid = false;   // column-dependent laws
         if (probs[i].m % plan.tile != 0 || probs[i].p % plan.tile != 0) plan.whole_tiles = false;
     }
     plan.descs.resize(nprob);
@@ -1058,6 +1130,12 @@ bool matmul_plan(const MatmulProblem* probs, int nprob, int prec, int num_levels
     plan.laws = law_pair_kind(probs[0].A.kind, probs[0].B.kind);
     for (int i = 1; i < nprob; ++i)
         if (law_pair_kind(probs[i].A.kind, probs[i].B.kind) != plan.laws) plan.laws = kLawsAny;
+    // the laws of Sec. 4 have a gather of their own: every product uses them
+    // for both operands, or none does; not with FP8 operands
+    for (int i = 0; i < nprob; ++i) {
+        const bool ea = probs[i].A.kind >= kLawExperimentFirst, eb = probs[i].B.kind >= kLawExperimentFirst;
+        if ((ea || eb) && (plan.laws != kLawsExperiment || prec == 3)) return false;
+    }
     plan.sum_rows = rows;
     plan.sum_mp = mp;
     plan.sum_merge_blocks = mb;
@@ -1197,7 +1275,11 @@ static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t
         g.cum = plan.index_weights ? reinterpret_cast<const uint64_t*>(ws + plan.off_cum) : nullptr;
         const dim3 grid((unsigned)ceil_div(kpad, (int64_t)kGatherPositions * oct), (unsigned)batch,
                         (unsigned)plan.nprob);
-        if (plan.laws == kLawsNormal)
+        if (plan.laws == kLawsExperiment) {
+            if constexpr (sizeof(typename P::In) == 1) return hipErrorInvalidValue;   // not with FP8
+            else hipLaunchKernelGGL((gather_experiment_kernel<Compute, typename P::In, P::KPACK>), grid,
+                                    dim3(kGatherThreads), 0, stream, g);
+        } else if (plan.laws == kLawsNormal)
             hipLaunchKernelGGL((gather_kernel<Compute, typename P::In, P::KPACK, kLawsNormal>), grid,
                                dim3(kGatherThreads), 0, stream, g);
         else if (plan.laws == kLawsUniform)

@@ -11,6 +11,8 @@
 // Stream layout (word 3 of the counter): tag << 28 | level << 20 | problem.
 //   tag 1, index stream:  counter (t / 2, k, 0, .) -> draws t, t+1 of realisation k
 //   tag 2, value stream:  counter (e / 4, k, j, .) -> elements e..e+3 of column j
+//   tag 3, experiment stream: counter (e, k, j, .) -> element e of column j
+//          (the laws of the experiments of Sec. 4, one call per element)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -20,6 +22,7 @@ namespace mlmc {
 
 constexpr uint32_t kTagIndex = 1u;
 constexpr uint32_t kTagValue = 2u;
+constexpr uint32_t kTagExperiment = 3u;
 
 struct Words4 {
     uint32_t w0, w1, w2, w3;

@@ -29,7 +29,12 @@ class Law:
     normal: loc + scale N(0, 1); uniform: loc + scale U(-1, 1);
     reparam: mean + stdev N(0, 1), entrywise, with FP32 device tensors of shape
     (n, m) for A (row j = column j of A, i.e. A stored column-major),
-    (n, p) for B (row-major), (n,) for x and y."""
+    (n, p) for B (row-major), (n,) for x and y.
+    The laws of the experiments of Sec. 4 (both operands take one of them, or
+    neither does; column j counted from 1, K ~ Poisson, E ~ Exp(1)):
+    ramp_normal (j scale)(loc - z), cos_poisson_exp cos(K + 2E) Bern(beta),
+    sin_ramp sin(x) + z' x with x = (j scale)(loc - z), cos_poisson_step
+    cos(K) H(5 - K) Bern(beta)."""
     kind: int
     loc: float = 0.0
     scale: float = 1.0
@@ -43,6 +48,26 @@ class Law:
     @staticmethod
     def uniform(loc: float, scale: float) -> "Law":
         return Law(1, float(loc), float(scale))
+
+    @staticmethod
+    def ramp_normal(scale: float, loc: float) -> "Law":
+        """(j scale)(loc - N(0, 1)); Sec. 4.1's x: ramp_normal(1 / 50, 0.4)."""
+        return Law(3, float(loc), float(scale))
+
+    @staticmethod
+    def cos_poisson_exp(lam: float, beta: float) -> "Law":
+        """cos(Poi(lam) + 2 Exp(1)) Bern(beta); Sec. 4.1's y: cos_poisson_exp(10, 0.05)."""
+        return Law(4, float(lam), float(beta))
+
+    @staticmethod
+    def sin_ramp(scale: float, loc: float) -> "Law":
+        """sin(x) + N(0, 1) x, x = (j scale)(loc - N(0, 1)); Sec. 4.2's A: sin_ramp(1e-4, 0.5)."""
+        return Law(5, float(loc), float(scale))
+
+    @staticmethod
+    def cos_poisson_step(lam: float, beta: float) -> "Law":
+        """cos(K) H(5 - K) Bern(beta), K ~ Poi(lam); Sec. 4.2's B: cos_poisson_step(2, 0.2)."""
+        return Law(6, float(lam), float(beta))
 
     @staticmethod
     def reparam(mean: torch.Tensor, stdev: torch.Tensor) -> "Law":

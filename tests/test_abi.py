@@ -188,3 +188,37 @@ def test_weighted_draws_rejected_with_fp8_and_in_batches(L):
     probs[0].out = 8
     st = L.mlmc_matmul_estimate_batched(1, probs, ctypes.byref(lv), None, 16, 1 << 40, None, None)
     assert st == 1 and b"uniformly" in L.mlmc_last_error()
+
+
+@pytest.mark.parametrize("lawA, lawB, prec, locB, scaleB, words", [
+    (3, 0, 0, 0.0, 1.0, b"pair only"),          # an experiment law with a classic one
+    (0, 4, 1, 10.0, 0.05, b"pair only"),
+    (5, 6, 3, 2.0, 0.2, b"FP8"),                # not with FP8 operands
+    (3, 4, 0, 0.0, 0.05, b"Poisson rate"),      # rate must be positive
+    (3, 4, 0, 600.0, 0.05, b"Poisson rate"),
+    (5, 6, 0, 2.0, 1.5, b"Bernoulli rate"),
+    (7, 6, 0, 2.0, 0.2, b"unknown law"),
+])
+def test_experiment_laws_validated(L, lawA, lawB, prec, locB, scaleB, words):
+    lv, keep = _levels([2, 4], [4, 4], prec=prec)
+    A, B = _dist(lawA, 0.4, 0.02), _dist(lawB, locB, scaleB)
+    st = L.mlmc_matmul_estimate(4, 16, 3, ctypes.byref(A), ctypes.byref(B), ctypes.byref(lv), 8, None,
+                                16, 1 << 40, None, None)
+    assert st == 1 and words in L.mlmc_last_error(), L.mlmc_last_error()
+
+
+def test_experiment_laws_rejected_by_xi_star_and_mixed_batches(L):
+    from paper_1904_00429_amd._lib import Problem
+    A, B = _dist(5, 0.5, 1e-4), _dist(6, 2.0, 0.2)
+    st = L.mlmc_optimal_index_weights(4, 16, 3, ctypes.byref(A), ctypes.byref(B), 16, 16, None)
+    assert st == 1 and b"xi**" in L.mlmc_last_error()
+    lv, keep = _levels([2, 4], [4, 4], prec=1)
+    probs = (Problem * 2)()
+    for i in range(2):
+        probs[i].m, probs[i].n, probs[i].p = 4, 16, 3
+        probs[i].out = 8
+        probs[i].problem = i
+    probs[0].A, probs[0].B = A, B
+    probs[1].A, probs[1].B = _dist(), _dist()
+    st = L.mlmc_matmul_estimate_batched(2, probs, ctypes.byref(lv), None, 16, 1 << 40, None, None)
+    assert st == 1 and b"every product or none" in L.mlmc_last_error()

@@ -1,0 +1,190 @@
+"""GPU parity of the laws of the experiments of Sec. 4 against the oracle on
+the same seeded streams.
+
+Sec. 4.1: x_j = (j/50)(0.4 - z), y_j = cos(K + 2E) Bern(0.05), K ~ Poi(10);
+Sec. 4.2: A_ij = sin(s) + z' s with s = (j 1e-4)(0.5 - z),
+B_jk = cos(K) H(5 - K) Bern(0.2), K ~ Poi(2); j counted from 1.
+
+  - the generated columns element by element: both sides take the Poisson
+    and Bernoulli decisions in FP64 from the same uniforms, so the zero
+    pattern is identical and the values agree to the rounding of the
+    transcendental functions (FP64 1e-13 of the largest value; FP32 and BF16
+    values are the FP64 values rounded: one unit of the format);
+  - estimates of E[f(x^T y)] and E[f(AB)] with the paper's functions in FP64
+    (1e-12), with f(x) = |x| in FP32 (1e-5) and BF16 (0.05 RMSE_est), and
+    with the identity in FP32;
+  - batched products and the adaptive number of levels (M = 10 ladders) in
+    FP64, with the oracle's levels, N_l and stopping decision.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import flush, rel_frob
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _laws41(orc):
+    from paper_1904_00429_amd import Law
+    return ((orc.Law.experiment(orc.LAW_RAMP_NORMAL, 0.4, 1 / 50), Law.ramp_normal(1 / 50, 0.4)),
+            (orc.Law.experiment(orc.LAW_COS_POISSON_EXP, 10.0, 0.05), Law.cos_poisson_exp(10.0, 0.05)))
+
+
+def _laws42(orc, scale=1e-4, beta=0.2):
+    from paper_1904_00429_amd import Law
+    return ((orc.Law.experiment(orc.LAW_SIN_RAMP, 0.5, scale), Law.sin_ramp(scale, 0.5)),
+            (orc.Law.experiment(orc.LAW_COS_POISSON_STEP, 2.0, beta), Law.cos_poisson_step(2.0, beta)))
+
+
+def _func(orc, name):
+    from paper_1904_00429_amd import Func
+    if name == "abs_step":
+        return orc.Func.abs_step(2.0), Func.abs_step(2.0)
+    if name == "inv_abs_step":
+        return orc.Func.inv_abs_step(0.4, 0.01), Func.inv_abs_step(0.4, 0.01)
+    if name == "abs":
+        return orc.Func.abs_step(1e30), Func.abs_step(1e30)
+    return None, None
+
+
+@pytest.mark.parametrize("prec, rtol", [("fp64", 1e-13), ("fp32", 2.0 ** -23), ("bf16", 2.0 ** -8)])
+@pytest.mark.parametrize("which", ["4.1", "4.2"])
+def test_experiment_columns(orc, dev, prec, rtol, which):
+    from paper_1904_00429_amd import gather_columns
+    flush(f"[laws] columns Sec. {which} {prec}")
+    if which == "4.1":
+        (oA, gA), (oB, gB) = _laws41(orc)
+        m, n, p = 1, 10000, 1
+    else:
+        (oA, gA), (oB, gB) = _laws42(orc, scale=1e-3)
+        m, n, p = 37, 1000, 29
+    c, S, k0, lev = 40, 6, 3, 1
+    AS, BS = gather_columns(m, n, p, gA, gB, 11, 2, lev, k0, S, c, prec=prec, device=dev)
+    AS, BS = AS.cpu().numpy(), BS.cpu().numpy()
+    ref_a = np.empty_like(AS)
+    ref_b = np.empty_like(BS)
+    for s in range(S):
+        r = orc.draw_indices(11, 2, lev, k0 + s, c, n)
+        for t in range(c):
+            ref_a[s, t], ref_b[s, t] = orc.column(11, 2, lev, k0 + s, r[t], m, p, oA, oB)
+    for got, ref in ((AS, ref_a), (BS, ref_b)):
+        assert np.array_equal(got == 0.0, ref == 0.0)
+        big = np.abs(ref).max()
+        np.testing.assert_allclose(got, ref, rtol=rtol, atol=1e-13 * big)
+    assert np.count_nonzero(ref_b) > 0 and np.count_nonzero(ref_b == 0.0) > 0
+
+
+INNER = [
+    # precision, f, ladder, N
+    ("fp64", "inv_abs_step", [1, 10, 100, 1000], [4000, 2000, 400, 100]),
+    ("fp64", None, [2, 4, 8, 16, 32], [3000, 1500, 800, 400, 200]),
+    ("fp32", "abs", [1, 10, 100, 1000], [4000, 2000, 400, 100]),
+    ("fp32", None, [4, 8, 16], [2000, 1000, 500]),
+]
+
+
+@pytest.mark.parametrize("case", range(len(INNER)))
+def test_inner_experiment_matches_oracle(orc, dev, case):
+    from paper_1904_00429_amd import inner_product_estimate
+    prec, fname, c, N = INNER[case]
+    flush(f"[laws] inner Sec. 4.1 {prec} {fname} c={c}")
+    (ox, gx), (oy, gy) = _laws41(orc)
+    of, gf = _func(orc, fname)
+    n = 10000
+    est = inner_product_estimate(n, gx, gy, c, n_samples=N, seed=21, prec=prec, level_means=True, device=dev,
+                                 func=gf)
+    ref = orc.estimate(1, n, 1, ox, oy, c, n_samples=N, seed=21, func=of)
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    y = float(est.Y.cpu())
+    scale = abs(ref.Y[0, 0]) + float(np.sqrt(np.sum(np.asarray(ref.level_var) / np.asarray(N))))
+    assert abs(y - ref.Y[0, 0]) <= tol * scale, (y, ref.Y[0, 0])
+    np.testing.assert_allclose(est.level_var, ref.level_var, rtol=1e-10 if prec == "fp64" else 1e-4)
+
+
+MATMUL = [
+    ("fp64", "abs_step", (70, 2000, 40), [1, 10, 100], [300, 100, 30]),
+    ("fp32", "abs", (64, 1000, 128), [2, 8, 32], [200, 100, 50]),
+    ("fp32", None, (70, 1000, 40), [4, 8, 16], [200, 100, 50]),
+    ("bf16", "abs", (64, 1000, 128), [2, 8, 32], [200, 100, 50]),
+    ("bf16", None, (128, 1000, 128), [8, 16, 32], [200, 100, 50]),
+]
+
+
+@pytest.mark.parametrize("case", range(len(MATMUL)))
+def test_matmul_experiment_matches_oracle(orc, dev, case):
+    from paper_1904_00429_amd import matmul_estimate
+    prec, fname, (m, n, p), c, N = MATMUL[case]
+    flush(f"[laws] matmul Sec. 4.2 {prec} {fname} {m}x{n}x{p} c={c}")
+    # the ramp spans the same range of s as the paper's n = 1e4 at this n
+    (oA, gA), (oB, gB) = _laws42(orc, scale=1.0 / n)
+    of, gf = _func(orc, fname)
+    est = matmul_estimate(m, n, p, gA, gB, c, n_samples=N, seed=5, prec=prec, level_means=True, device=dev, func=gf)
+    ref = orc.estimate(m, n, p, oA, oB, c, n_samples=N, seed=5, func=of)
+    Y = est.Y.cpu().numpy()
+    if prec == "bf16":
+        err = np.linalg.norm((Y - ref.Y).ravel())
+        flush(f"  bf16 error {err:.4g} vs rmse_est {ref.rmse_est:.4g}")
+        assert err <= 0.05 * ref.rmse_est
+        np.testing.assert_allclose(est.level_var, ref.level_var, rtol=3e-2)
+        return
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    assert rel_frob(Y, ref.Y) <= tol, rel_frob(Y, ref.Y)
+    np.testing.assert_allclose(est.level_var, ref.level_var, rtol=1e-10 if prec == "fp64" else 1e-5)
+
+
+def test_batched_experiment_matches_oracle(orc, dev):
+    from paper_1904_00429_amd import BatchedEstimate, BatchProblem
+    shapes = [(64, 500, 64), (100, 800, 37)]
+    c, N = [1, 10, 100], [120, 60, 20]
+    flush("[laws] batched Sec. 4.2 fp64")
+    of, gf = _func(orc, "abs_step")
+    probs, refs_in = [], []
+    for i, (m, n, p) in enumerate(shapes):
+        (oA, gA), (oB, gB) = _laws42(orc, scale=1.0 / n)
+        probs.append(BatchProblem(m, n, p, gA, gB, 3 + i))
+        refs_in.append((oA, oB))
+    est = BatchedEstimate(probs, c, N, seed=8, prec="fp64", device=dev, func=gf)
+    V = est.run(level_var=True)
+    torch.cuda.synchronize()
+    for i, (m, n, p) in enumerate(shapes):
+        oA, oB = refs_in[i]
+        ref = orc.estimate(m, n, p, oA, oB, c, n_samples=N, seed=8, problem=3 + i, func=of)
+        Y = est.Y[i].cpu().numpy()
+        assert rel_frob(Y, ref.Y) <= 1e-12, (i, rel_frob(Y, ref.Y))
+        np.testing.assert_allclose(V[:, i], ref.level_var, rtol=1e-10)
+
+
+@pytest.mark.parametrize("kind, eps", [("inner", 5.0), ("matrix", 30.0), ("matrix", 50.0)])
+def test_adaptive_experiment_matches_oracle(orc, dev, kind, eps):
+    from paper_1904_00429_amd import inner_product_estimate, matmul_estimate
+    c = [1, 10, 100, 1000, 10000]
+    flush(f"[laws] adaptive {kind} eps {eps}")
+    if kind == "inner":
+        (oA, gA), (oB, gB) = _laws41(orc)
+        of, gf = _func(orc, "inv_abs_step")
+        m, n, p = 1, 10000, 1
+    else:
+        (oA, gA), (oB, gB) = _laws42(orc, scale=1e-3)
+        of, gf = _func(orc, "abs_step")
+        m, n, p = 8, 1000, 6
+    ref = orc.estimate(m, n, p, oA, oB, c, rmse_target=eps, pilot=50, seed=9, func=of, adaptive=kind)
+    if kind == "inner":
+        est = inner_product_estimate(n, gA, gB, c, rmse_target=eps, pilot=50, seed=9, prec="fp64", device=dev,
+                                     func=gf, adaptive=True, level_means=True)
+    else:
+        est = matmul_estimate(m, n, p, gA, gB, c, rmse_target=eps, pilot=50, seed=9, prec="fp64", device=dev,
+                              func=gf, adaptive=True, level_means=True)
+    flush(f"  levels {est.levels_used} (oracle {ref.levels_used}), N {list(est.n_used)}")
+    assert est.levels_used == ref.levels_used
+    assert est.bias_test_passed == ref.bias_test_passed
+    assert list(est.n_used) == [int(x) for x in ref.n_used]
+    Y = est.Y.cpu().numpy().reshape(ref.Y.shape)
+    assert rel_frob(Y, ref.Y) <= 1e-12
