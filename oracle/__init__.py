@@ -25,7 +25,9 @@ Parity pins and where they are tested (``tests/test_oracle_*.py``):
                      and exact error by brute force, Theorem 3.1's minimum;
   Sec. 4 laws        sample moments against closed forms (characteristic
                      functions of Poisson, exponential and normal variables)
-                     and the Poisson probabilities by chi-square.
+                     and the Poisson probabilities by chi-square;
+  stride coupling    unit-vector probe of the coarse draws (r_{jM}), brute
+                     force over index tuples, closed-form V_l by z-test.
 """
 from __future__ import annotations
 
@@ -103,10 +105,10 @@ def lib():
                                  ctypes.c_uint32, ctypes.c_int64, ctypes.c_int64,
                                  ctypes.c_int64, ctypes.POINTER(_Law), ctypes.POINTER(_Law),
                                  ctypes.c_void_p, ctypes.c_void_p]
-        L.orc_sketch_pair.argtypes = [ctypes.c_int64] * 5 + [ctypes.c_void_p] * 4
+        L.orc_sketch_pair.argtypes = [ctypes.c_int64] * 6 + [ctypes.c_void_p] * 4
         L.orc_level_estimation.restype = ctypes.c_int
         L.orc_level_estimation.argtypes = (
-            [ctypes.c_int64] * 3 + [ctypes.POINTER(_Law)] * 2 + [ctypes.c_int64] * 2
+            [ctypes.c_int64] * 3 + [ctypes.POINTER(_Law)] * 2 + [ctypes.c_int64] * 3
             + [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64,
                ctypes.c_int64, ctypes.POINTER(_Func), ctypes.POINTER(_Weights), ctypes.c_void_p,
                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p])
@@ -115,11 +117,11 @@ def lib():
         L.orc_draw_index_weighted.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                               ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(_Weights)]
         L.orc_optimal_weights.argtypes = ([ctypes.c_int64] * 3 + [ctypes.POINTER(_Law)] * 2 + [ctypes.c_void_p])
-        L.orc_sketch_pair_weighted.argtypes = [ctypes.c_int64] * 4 + [ctypes.c_void_p] * 5
+        L.orc_sketch_pair_weighted.argtypes = [ctypes.c_int64] * 5 + [ctypes.c_void_p] * 5
         L.orc_apply_func.restype = ctypes.c_double
         L.orc_apply_func.argtypes = [ctypes.POINTER(_Func), ctypes.c_double]
         L.orc_level_entries.argtypes = (
-            [ctypes.c_int64] * 3 + [ctypes.POINTER(_Law)] * 2 + [ctypes.c_int64] * 2
+            [ctypes.c_int64] * 3 + [ctypes.POINTER(_Law)] * 2 + [ctypes.c_int64] * 3
             + [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64,
                ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p])
@@ -255,15 +257,17 @@ def draw_index_weighted(seed: int, problem: int, lfield: int, k: int, t: int, we
                                              weights.w.size, ctypes.byref(wc)))
 
 
-def sketch_pair_weighted(c_f: int, c_c: int, factor, AS: np.ndarray, BS: np.ndarray):
-    """Zf, Zc of eq. (18) with per-draw factors 1 / xi_{r_t}."""
+def sketch_pair_weighted(c_f: int, c_c: int, factor, AS: np.ndarray, BS: np.ndarray, stride: int = 0):
+    """Zf, Zc of eq. (18) with per-draw factors 1 / xi_{r_t} (coarse draws:
+    the first c_c, or with stride M > 0 draws M - 1, 2M - 1, ...)."""
     AS = np.ascontiguousarray(AS, dtype=np.float64)
     BS = np.ascontiguousarray(BS, dtype=np.float64)
     factor = np.ascontiguousarray(factor, dtype=np.float64)
     m, p = AS.shape[1], BS.shape[1]
     Zf = np.zeros((m, p))
     Zc = np.zeros((m, p))
-    lib().orc_sketch_pair_weighted(m, p, int(c_f), int(c_c), _ptr(factor), _ptr(AS), _ptr(BS), _ptr(Zf), _ptr(Zc))
+    lib().orc_sketch_pair_weighted(m, p, int(c_f), int(c_c), int(stride), _ptr(factor), _ptr(AS), _ptr(BS),
+                                   _ptr(Zf), _ptr(Zc))
     return Zf, Zc
 
 
@@ -312,16 +316,18 @@ def realisation(seed: int, problem: int, lfield: int, k: int, m: int, n: int, p:
     return Am, Bm
 
 
-def sketch_pair(n: int, c_f: int, c_c: int, AS: np.ndarray, BS: np.ndarray):
+def sketch_pair(n: int, c_f: int, c_c: int, AS: np.ndarray, BS: np.ndarray, stride: int = 0):
     """Fine and coarse sketches (eq. (18), xi = 1/n) of gathered columns.
 
-    AS is (c_f, m): row t is the sampled column a_t; BS is (c_f, p)."""
+    AS is (c_f, m): row t is the sampled column a_t; BS is (c_f, p).  The
+    coarse sketch takes the first c_c draws, or with stride M > 0 the draws
+    M - 1, 2M - 1, ... (r_{jM} of Sec. 3.1)."""
     AS = np.ascontiguousarray(AS, dtype=np.float64)
     BS = np.ascontiguousarray(BS, dtype=np.float64)
     m, p = AS.shape[1], BS.shape[1]
     Zf = np.zeros((m, p))
     Zc = np.zeros((m, p))
-    lib().orc_sketch_pair(m, p, int(n), int(c_f), int(c_c), _ptr(AS), _ptr(BS), _ptr(Zf), _ptr(Zc))
+    lib().orc_sketch_pair(m, p, int(n), int(c_f), int(c_c), int(stride), _ptr(AS), _ptr(BS), _ptr(Zf), _ptr(Zc))
     return Zf, Zc
 
 
@@ -345,12 +351,22 @@ class LevelState:
         return float(self.m2.sum()) / (self.count - 1)
 
 
+def coupling_stride(c_l: int, c_prev: int, coupling: str) -> int:
+    """M = c_l / c_prev for the stride coupling (0: prefix, or level 0)."""
+    if coupling not in ("prefix", "stride"):
+        raise ValueError("coupling must be 'prefix' or 'stride'")
+    return int(c_l) // int(c_prev) if coupling == "stride" and c_prev > 0 else 0
+
+
 def level_estimation(state: LevelState, m: int, n: int, p: int, A: Law, B: Law,
                      c_l: int, c_prev: int, seed: int, problem: int, lfield: int,
                      k_begin: int, k_end: int, want_samples: bool = False,
-                     func: Optional[Func] = None, weights: Optional["Weights"] = None):
+                     func: Optional[Func] = None, weights: Optional["Weights"] = None,
+                     coupling: str = "prefix"):
     """Alg. 1 for realisations [k_begin, k_end), continuing `state` in place;
-    level samples f(Zf) - f(Zc) (identity when func is None)."""
+    level samples f(Zf) - f(Zc) (identity when func is None).  coupling:
+    "prefix" (the coarse sketch takes the first c_prev draws) or "stride"
+    (every M-th draw, M = c_l / c_prev, Sec. 3.1)."""
     cnt = ctypes.c_int64(state.count)
     samples = np.empty((max(k_end - k_begin, 0), m, p)) if want_samples else None
     la, lb = A.c(), B.c()
@@ -360,7 +376,7 @@ def level_estimation(state: LevelState, m: int, n: int, p: int, A: Law, B: Law,
     wc = weights.c() if weights is not None else None
     rc = lib().orc_level_estimation(
         int(m), int(n), int(p), ctypes.byref(la), ctypes.byref(lb), int(c_l), int(c_prev),
-        int(seed), int(problem), int(lfield), int(k_begin), int(k_end), ctypes.byref(fc),
+        coupling_stride(c_l, c_prev, coupling), int(seed), int(problem), int(lfield), int(k_begin), int(k_end), ctypes.byref(fc),
         ctypes.byref(wc) if wc is not None else None,
         ctypes.byref(cnt), _ptr(state.mean), _ptr(state.m2), _ptr(samples) if want_samples else None)
     if rc != 0:
@@ -417,7 +433,8 @@ def estimate(m: int, n: int, p: int, A: Law, B: Law, c: Sequence[int],
              n_samples: Optional[Sequence[int]] = None, rmse_target: float = 0.0,
              pilot: int = 0, seed: int = 0, problem: int = 0, shared: bool = False,
              max_total_draws: int = 0, pool=None, func: Optional[Func] = None,
-             adaptive: Optional[str] = None, weights: Optional[Weights] = None) -> Estimate:
+             adaptive: Optional[str] = None, weights: Optional[Weights] = None,
+             coupling: str = "prefix") -> Estimate:
     """MLMC estimate of E[f(AB)] (f entrywise, identity by default) over the
     ladder c_0 < c_1 < ... < c_L.
 
@@ -440,7 +457,8 @@ def estimate(m: int, n: int, p: int, A: Law, B: Law, c: Sequence[int],
 
     def run(l, k0, k1):
         level_estimation(states[l], m, n, p, A, B, c[l], c[l - 1] if l > 0 else 0,
-                         seed, problem, level_field(l, shared), k0, k1, func=func, weights=weights)
+                         seed, problem, level_field(l, shared), k0, k1, func=func, weights=weights,
+                         coupling=coupling)
 
     def run_all(ranges):
         if pool is None:
@@ -502,7 +520,7 @@ class EntriesEstimate:
 def estimate_entries(m: int, n: int, p: int, A: Law, B: Law, c: Sequence[int],
                      n_samples: Sequence[int], rows: Sequence[int], cols: Sequence[int],
                      seed: int = 0, problem: int = 0, shared: bool = False,
-                     pool=None) -> EntriesEstimate:
+                     pool=None, coupling: str = "prefix") -> EntriesEstimate:
     """The fixed-N estimate of eq. (10) at the entries rows x cols only.
 
     Level l runs realisations 0 .. N_l - 1 exactly as `estimate` does, so its
@@ -523,7 +541,7 @@ def estimate_entries(m: int, n: int, p: int, A: Law, B: Law, c: Sequence[int],
         cnt = ctypes.c_int64(0)
         rc = lib().orc_level_entries(
             int(m), int(n), int(p), ctypes.byref(la), ctypes.byref(lb), int(c[l]),
-            int(c[l - 1]) if l > 0 else 0, int(seed), int(problem), level_field(l, shared), 0,
+            int(c[l - 1]) if l > 0 else 0, coupling_stride(c[l], c[l - 1] if l > 0 else 0, coupling), int(seed), int(problem), level_field(l, shared), 0,
             int(n_samples[l]), nr, _ptr(rows), nc, _ptr(cols), ctypes.byref(cnt),
             _ptr(means[l]), _ptr(m2s[l]))
         if rc != 0:

@@ -13,7 +13,7 @@ from typing import Sequence
 import numpy as np
 import torch
 
-from . import Law, column, draw_index_weighted, draw_indices, level_field
+from . import Law, column, coupling_stride, draw_index_weighted, draw_indices, level_field
 
 
 def standard_normals(seed, problem, lfield, k, cols, m, p):
@@ -28,17 +28,20 @@ def standard_normals(seed, problem, lfield, k, cols, m, p):
 
 def reparam_estimate(MA: torch.Tensor, SA: torch.Tensor, MB: torch.Tensor, SB: torch.Tensor,
                      c: Sequence[int], N: Sequence[int], seed: int = 0, problem: int = 0,
-                     shared: bool = False, weights=None) -> torch.Tensor:
+                     shared: bool = False, weights=None, coupling: str = "prefix") -> torch.Tensor:
     """Y = sum_l (1/N_l) sum_k (Z_l^(k) - Z_{l-1}^(k)) for A = MA^T + SA^T o Z
     (MA, SA: n x m, row j = column j of A) and B = MB + SB o W (n x p).  With
     `weights` (oracle.Weights) the indices are drawn with xi_j = w_j / W and
-    Z_l = (1/c_l) sum_t a_t b_t^T / xi_{r_t} (eq. (18))."""
+    Z_l = (1/c_l) sum_t a_t b_t^T / xi_{r_t} (eq. (18)).  coupling "stride": the
+    coarse sketch takes draws M - 1, 2M - 1, ... (M = c_l / c_{l-1})."""
     n, m = MA.shape
     p = MB.shape[1]
     Y = torch.zeros((m, p), dtype=torch.float64)
     for l, (cl, Nl) in enumerate(zip(c, N)):
         cp = c[l - 1] if l > 0 else 0
         lf = level_field(l, shared)
+        M = coupling_stride(cl, cp, coupling)
+        ci = torch.arange(cp) if M == 0 else M * (torch.arange(cp) + 1) - 1   # coarse draws
         acc = torch.zeros((m, p), dtype=torch.float64)
         for k in range(Nl):
             if weights is None:
@@ -52,20 +55,21 @@ def reparam_estimate(MA: torch.Tensor, SA: torch.Tensor, MB: torch.Tensor, SB: t
             BS = MB[idx] + SB[idx] * W          # c x p: row t = b_t
             if weights is None:
                 Zf = (n / cl) * (AS.T @ BS)
-                Zc = (n / cp) * (AS[:cp].T @ BS[:cp]) if cp > 0 else None
+                Zc = (n / cp) * (AS[ci].T @ BS[ci]) if cp > 0 else None
             else:
                 f = torch.from_numpy(weights.total / weights.w[r].astype(np.float64))[:, None]
                 Zf = ((AS * f).T @ BS) / cl
-                Zc = ((AS[:cp] * f[:cp]).T @ BS[:cp]) / cp if cp > 0 else None
+                Zc = ((AS[ci] * f[ci]).T @ BS[ci]) / cp if cp > 0 else None
             acc = acc + (Zf - Zc if Zc is not None else Zf)
         Y = Y + acc / Nl
     return Y
 
 
-def reparam_gradients(MA, SA, MB, SB, c, N, G, seed=0, problem=0, shared=False, weights=None):
+def reparam_gradients(MA, SA, MB, SB, c, N, G, seed=0, problem=0, shared=False, weights=None,
+                      coupling="prefix"):
     """Gradients of <G, Y> (FP64) with respect to MA, SA, MB, SB (weights held fixed)."""
     leaves = [torch.as_tensor(np.asarray(x, dtype=np.float64)).clone().requires_grad_(True)
               for x in (MA, SA, MB, SB)]
-    Y = reparam_estimate(*leaves, c, N, seed, problem, shared, weights)
+    Y = reparam_estimate(*leaves, c, N, seed, problem, shared, weights, coupling)
     (Y * torch.as_tensor(np.asarray(G, dtype=np.float64))).sum().backward()
     return Y.detach().numpy(), [t.grad.numpy() for t in leaves]

@@ -49,7 +49,10 @@
  *     Bernoulli decision (u < scale, u2 or u1).
  *   - The coarse sketch uses the first c_{l-1} of the c_l fine indices.
  *     Draws are i.i.d., so any fixed subset of c_{l-1} indices has the law the
- *     paper requires; the prefix nests the levels exactly.
+ *     paper requires; the prefix nests the levels exactly.  The stride
+ *     coupling of Sec. 3.1 (every M-th fine index, r_{jM}, j = 1 .. c_{l-1},
+ *     M = c_l / c_{l-1}) is the other subset offered: `stride` = M, or 0 for
+ *     the prefix.
  */
 #include <math.h>
 #include <stdint.h>
@@ -358,11 +361,19 @@ void orc_column(uint64_t seed, uint32_t problem, uint32_t level_field, uint32_t 
         b[q] = law_value(B, seed, problem, level_field, k, j, m + q, j * B->ld + q);
 }
 
+/* Draw number of the j-th coarse draw (0-based j): j (prefix), or
+ * stride (j + 1) - 1, the 0-based position of r_{(j+1) M} (stride coupling). */
+static int64_t coarse_draw(int64_t j, int64_t stride)
+{
+    return stride > 0 ? stride * (j + 1) - 1 : j;
+}
+
 /* Sketches of eq. (18) with general probabilities: Zf = (1/c_f) sum_{t < c_f}
  * a_t b_t^T / xi_t (xi_t = w_{r_t} / W: factor[t] = W / w_{r_t}), likewise
- * Zc over the first c_c draws. */
-void orc_sketch_pair_weighted(int64_t m, int64_t p, int64_t c_f, int64_t c_c, const double* factor,
-                              const double* AS, const double* BS, double* Zf, double* Zc)
+ * Zc over the c_c coarse draws (coarse_draw). */
+void orc_sketch_pair_weighted(int64_t m, int64_t p, int64_t c_f, int64_t c_c, int64_t stride,
+                              const double* factor, const double* AS, const double* BS, double* Zf,
+                              double* Zc)
 {
     for (int64_t i = 0; i < m; ++i) {
         for (int64_t q = 0; q < p; ++q) {
@@ -372,8 +383,10 @@ void orc_sketch_pair_weighted(int64_t m, int64_t p, int64_t c_f, int64_t c_c, co
             Zf[i * p + q] = sf / (double)c_f;
             if (c_c > 0) {
                 double sc = 0.0;
-                for (int64_t t = 0; t < c_c; ++t)
+                for (int64_t j = 0; j < c_c; ++j) {
+                    int64_t t = coarse_draw(j, stride);
                     sc += factor[t] * (AS[t * m + i] * BS[t * p + q]);
+                }
                 Zc[i * p + q] = sc / (double)c_c;
             }
         }
@@ -381,10 +394,11 @@ void orc_sketch_pair_weighted(int64_t m, int64_t p, int64_t c_f, int64_t c_c, co
 }
 
 /* Sketches of Sec. 3, eq. (18) with xi_j = 1/n from gathered columns:
- *   Zf = (n / c_f) sum_{t < c_f} a_t b_t^T,  Zc = (n / c_c) sum_{t < c_c} a_t b_t^T.
+ *   Zf = (n / c_f) sum_{t < c_f} a_t b_t^T,  Zc = (n / c_c) sum over the c_c
+ * coarse draws t = coarse_draw(j, stride) of a_t b_t^T.
  * AS holds a_t at AS + t*m, BS holds b_t at BS + t*p.  Z is m x p row-major.
  * c_c == 0 leaves Zc untouched. */
-void orc_sketch_pair(int64_t m, int64_t p, int64_t n, int64_t c_f, int64_t c_c,
+void orc_sketch_pair(int64_t m, int64_t p, int64_t n, int64_t c_f, int64_t c_c, int64_t stride,
                      const double* AS, const double* BS, double* Zf, double* Zc)
 {
     for (int64_t i = 0; i < m; ++i) {
@@ -395,8 +409,10 @@ void orc_sketch_pair(int64_t m, int64_t p, int64_t n, int64_t c_f, int64_t c_c,
             Zf[i * p + q] = ((double)n / (double)c_f) * sf;
             if (c_c > 0) {
                 double sc = 0.0;
-                for (int64_t t = 0; t < c_c; ++t)
+                for (int64_t j = 0; j < c_c; ++j) {
+                    int64_t t = coarse_draw(j, stride);
                     sc += AS[t * m + i] * BS[t * p + q];
+                }
                 Zc[i * p + q] = ((double)n / (double)c_c) * sc;
             }
         }
@@ -411,12 +427,14 @@ void orc_sketch_pair(int64_t m, int64_t p, int64_t n, int64_t c_f, int64_t c_c,
  * evaluations).  samples_out (nullable) receives every D, row-major.
  * Returns 0, or -1 on bad arguments / allocation failure. */
 int orc_level_estimation(int64_t m, int64_t n, int64_t p, const orc_law* A, const orc_law* B,
-                         int64_t c_l, int64_t c_prev, uint64_t seed, uint32_t problem,
+                         int64_t c_l, int64_t c_prev, int64_t stride, uint64_t seed, uint32_t problem,
                          uint32_t level_field, int64_t k_begin, int64_t k_end, const orc_func* f,
                          const orc_weights* iw, int64_t* count, double* mean, double* m2,
                          double* samples_out)
 {
     if (m < 1 || p < 1 || n < 1 || c_l < 1 || c_prev < 0 || c_prev > c_l || k_end < k_begin)
+        return -1;
+    if (stride < 0 || (stride > 0 && stride * c_prev > c_l))
         return -1;
     int64_t mp = m * p;
     int64_t* r = (int64_t*)malloc(sizeof(int64_t) * (size_t)c_l);
@@ -444,9 +462,9 @@ int orc_level_estimation(int64_t m, int64_t n, int64_t p, const orc_law* A, cons
             orc_column(seed, problem, level_field, (uint32_t)k, r[t], m, p, A, B,
                        AS + t * m, BS + t * p);
         if (iw)
-            orc_sketch_pair_weighted(m, p, c_l, c_prev, factor, AS, BS, Zf, Zc);
+            orc_sketch_pair_weighted(m, p, c_l, c_prev, stride, factor, AS, BS, Zf, Zc);
         else
-            orc_sketch_pair(m, p, n, c_l, c_prev, AS, BS, Zf, Zc);
+            orc_sketch_pair(m, p, n, c_l, c_prev, stride, AS, BS, Zf, Zc);
         *count += 1;
         double cnt = (double)(*count);
         for (int64_t e = 0; e < mp; ++e) {
@@ -470,13 +488,13 @@ int orc_level_estimation(int64_t m, int64_t n, int64_t p, const orc_law* A, cons
  * asked for, so that products far too large for the whole sketch can be
  * checked entry by entry.  mean and m2 are nr x nc, row-major. */
 int orc_level_entries(int64_t m, int64_t n, int64_t p, const orc_law* A, const orc_law* B,
-                      int64_t c_l, int64_t c_prev, uint64_t seed, uint32_t problem,
+                      int64_t c_l, int64_t c_prev, int64_t stride, uint64_t seed, uint32_t problem,
                       uint32_t level_field, int64_t k_begin, int64_t k_end,
                       int64_t nr, const int64_t* rows, int64_t nc, const int64_t* cols,
                       int64_t* count, double* mean, double* m2)
 {
     if (m < 1 || p < 1 || n < 1 || c_l < 1 || c_prev < 0 || c_prev > c_l || k_end < k_begin ||
-        nr < 1 || nc < 1)
+        nr < 1 || nc < 1 || stride < 0 || (stride > 0 && stride * c_prev > c_l))
         return -1;
     for (int64_t a = 0; a < nr; ++a)
         if (rows[a] < 0 || rows[a] >= m) return -1;
@@ -510,8 +528,10 @@ int orc_level_entries(int64_t m, int64_t n, int64_t p, const orc_law* A, const o
                 double d = ((double)n / (double)c_l) * sf;
                 if (c_prev > 0) {
                     double sc = 0.0;
-                    for (int64_t t = 0; t < c_prev; ++t)
+                    for (int64_t j = 0; j < c_prev; ++j) {
+                        int64_t t = coarse_draw(j, stride);
                         sc += AS[t * nr + a] * BS[t * nc + b];
+                    }
                     d = d - ((double)n / (double)c_prev) * sc;
                 }
                 int64_t e = a * nc + b;
