@@ -108,6 +108,15 @@ typedef enum {
  * |Ybar_L| < (sqrt(M) - 1) eps / sqrt(2) (inner product, Sec. 2, eq. (15)),
  * M = c[L] / c[L-1].  Levels never reached report N_l = 0 and add nothing. */
 #define MLMC_FLAG_ADAPTIVE_LEVELS 4u
+/* Stride coupling (Sec. 3.1): the coarse sketch of level l >= 1 takes every
+ * M-th of the c_l fine draws, r_{jM} for j = 1 .. c_{l-1} (0-based draws
+ * M - 1, 2M - 1, ...), M = c_l / c_{l-1}, as the paper writes it.  Without
+ * the flag it takes the first c_{l-1} draws (prefix coupling).  Both subsets
+ * give level samples of the same law (the draws are i.i.d.); only the prefix
+ * nests the levels, so with shared realisations only the prefix makes the
+ * telescoping sum exact.  Every entry point accepts it, the batched ones
+ * included. */
+#define MLMC_FLAG_STRIDE_COUPLING 8u
 #define MLMC_MAX_LEVELS 32
 
 /* Kernel classes of mlmc_report.kernel_ms (MLMC_FLAG_TIMING). */

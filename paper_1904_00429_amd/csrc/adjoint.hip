@@ -3,7 +3,8 @@
 //
 // The estimate is Y = sum_l (1/N_l) sum_k D_{l,k} with
 // D_{l,k} = (n / c_l) sum_t w_t a_t b_t^T (w_t = 1 - c_l / c_{l-1} for the c_{l-1}
-// coarse draws, 1 otherwise; Alg. 1 with the prefix coupling).  Y is bilinear
+// coarse draws, 1 otherwise; Alg. 1 with the prefix coupling, the first
+// c_{l-1} draws, or the stride coupling, draws M - 1, 2M - 1, ...).  Y is bilinear
 // in (a_t, b_t), so for an upstream gradient G = dL/dY (m x p)
 //   dL/da_t = kappa_t G b_t,   dL/db_t = kappa_t G^T a_t,   kappa_t = (n / c_l) w_t / N_l,
 // and the chain rule through a_t = M_A[:, r_t] + S_A[:, r_t] o z_t gives
@@ -170,9 +171,16 @@ __global__ __launch_bounds__(kAdjGatherThreads) void adjoint_gather_kernel(AdjGa
     }
 }
 
+// Draw t is one of the coarse draws of its level sample.
+__device__ __forceinline__ bool coarse_draw(int t, uint32_t c_prev, uint32_t stride)
+{
+    return stride ? ((uint32_t)t + 1u) % stride == 0u : t < (int)c_prev;
+}
+
 struct AdjMfmaParams {
     int64_t m, p, kpad;
     uint32_t c_prev;
+    uint32_t stride;                  // stride coupling M (0: prefix)
     float kappa_coarse, kappa_fine;   // (n / c_l) w_t / N_l for the two segments
     const float* GT;                  // p x m: G^T
     const float* G;                   // m x p
@@ -305,7 +313,7 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_mfma_kernel(AdjMfmaParams
             if (t >= kpad) continue;
             const int32_t col = R[t];
             if (col < 0) continue;
-            float kappa = t < (int)prm.c_prev ? prm.kappa_coarse : prm.kappa_fine;
+            float kappa = coarse_draw(t, prm.c_prev, prm.stride) ? prm.kappa_coarse : prm.kappa_fine;
             if (prm.iw) kappa *= (float)((double)prm.cum[prm.n - 1] / ((double)prm.n * (double)prm.iw[col]));
             const float g = kappa * acc[bj][r];
             unsafeAtomicAdd(dM + (int64_t)col * X + x, g);
@@ -324,6 +332,7 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_mfma_kernel(AdjMfmaParams
 struct AdjBf16Params {
     int64_t m, p, kpad, mk, pk;
     uint32_t c_prev;
+    uint32_t stride;
     float kappa_coarse, kappa_fine;
     const __bf16* Gb;                 // m x pk: G
     const __bf16* GTb;                // p x mk: G^T
@@ -405,7 +414,7 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_mfma_bf16_kernel(AdjBf16P
             if (tt >= kpad) continue;
             const int32_t col = R[tt];
             if (col < 0) continue;
-            float kappa = tt < (int)prm.c_prev ? prm.kappa_coarse : prm.kappa_fine;
+            float kappa = coarse_draw(tt, prm.c_prev, prm.stride) ? prm.kappa_coarse : prm.kappa_fine;
             if (prm.iw) kappa *= (float)((double)prm.cum[prm.n - 1] / ((double)prm.n * (double)prm.iw[col]));
             const float g = kappa * acc[bj][r];
             unsafeAtomicAdd(dM + (int64_t)col * X + x, g);
@@ -469,8 +478,8 @@ size_t adjoint_workspace_size(int64_t m, int64_t n, int64_t p, int num_levels, c
 hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law& B, int num_levels,
                        const int64_t* c, const int64_t* N, const StreamKeys& keys, bool shared,
                        const double* grad, float* dMA, float* dSA, float* dMB, float* dSB,
-                       const uint32_t* index_weights, char* ws, size_t ws_bytes, bool bf16, hipStream_t stream,
-                       KernelTimer* timer)
+                       const uint32_t* index_weights, char* ws, size_t ws_bytes, bool bf16, bool stride,
+                       hipStream_t stream, KernelTimer* timer)
 {
     auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const int64_t mk = round_up_adj(m, 8), pk = round_up_adj(p, 8);
@@ -539,6 +548,7 @@ hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law&
             if (bf16) {
                 AdjBf16Params a;
                 a.m = m; a.p = p; a.kpad = kpad; a.mk = mk; a.pk = pk; a.c_prev = (uint32_t)cp;
+                a.stride = stride && cp > 0 ? (uint32_t)(cl / cp) : 0u;
                 a.kappa_coarse = kc; a.kappa_fine = kf;
                 a.Gb = Gb; a.GTb = GTb; a.ASb = ASb; a.BSb = BSb; a.ZS = ZS; a.WS = WS; a.R = Rr;
                 a.tiles_t = ceil_div(kpad, kAdjTileT);
@@ -557,6 +567,7 @@ hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law&
             }
             AdjMfmaParams a;
             a.m = m; a.p = p; a.kpad = kpad; a.c_prev = (uint32_t)cp;
+            a.stride = stride && cp > 0 ? (uint32_t)(cl / cp) : 0u;
             a.kappa_coarse = kc; a.kappa_fine = kf;
             a.GT = GT; a.G = G; a.AT = AT; a.BT = BT; a.ZS = ZS; a.WS = WS; a.R = Rr;
             a.tiles_t = ceil_div(kpad, kAdjTileT);

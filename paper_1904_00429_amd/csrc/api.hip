@@ -202,6 +202,7 @@ LevelRange range_of(const mlmc_levels* lv, int l, int64_t k_begin, int64_t count
     r.c_prev = l > 0 ? lv->c[l - 1] : 0;
     r.k_begin = k_begin;
     r.count = count;
+    r.stride = (lv->flags & MLMC_FLAG_STRIDE_COUPLING) && l > 0 ? lv->c[l] / lv->c[l - 1] : 0;
     return r;
 }
 
@@ -737,7 +738,8 @@ mlmc_status mlmc_matmul_adjoint_reparam(int64_t m, int64_t n, int64_t p, const m
     hipError_t e = adjoint_run(m, n, p, to_law(*A), to_law(*B), lv->num_levels, lv->c, lv->n_samples, keys_of(lv),
                                (lv->flags & MLMC_FLAG_SHARED_SAMPLES) != 0, grad_out, dMA, dSA, dMB, dSB,
                                lv->index_weights, static_cast<char*>(workspace), workspace_bytes,
-                               lv->prec == MLMC_PREC_BF16, stream, timer);
+                               lv->prec == MLMC_PREC_BF16, (lv->flags & MLMC_FLAG_STRIDE_COUPLING) != 0, stream,
+                               timer);
     return e == hipSuccess ? MLMC_OK : device_fail(e, "adjoint launch");
 }
 

@@ -40,6 +40,7 @@ struct InnerLevel {
     uint32_t g_log2;          // lanes per realisation = 1 << g_log2, at most 256
     uint32_t block_begin, blocks;
     uint32_t sid_index, sid_value;
+    uint32_t stride;          // stride coupling M: the coarse draws are M - 1, 2M - 1, ... (0: prefix)
     double scale;             // n / c
     double scale_c;           // n / c_prev (0 at level 0)
     double omega;             // 1 - c / c_prev, weight of the first c_prev draws
@@ -150,7 +151,10 @@ __device__ __forceinline__ void sum_pairs(const InnerMultiParams& prm, const Inn
 // f(Z_l) - f(Z_{l-1}) with Z_l = (n / c_l)(C + F) and Z_{l-1} = (n / c_{l-1}) C,
 // C and F the sums over the coarse and the remaining draws, so both sums are
 // reduced over the group instead of their weighted combination.
-template <typename T, int LAWS, bool FN, bool IW>
+// ST: stride coupling.  Every pair is summed, and each of its two draws goes
+// to the coarse sum when its number t has (t + 1) % M == 0, else to the fine
+// sum (a separate instantiation, so the prefix kernels are unchanged).
+template <typename T, int LAWS, bool FN, bool IW, bool ST>
 __global__ __launch_bounds__(kInnerBlock) void inner_multi_kernel(InnerMultiParams prm)
 {
     __shared__ double wave_sum[kInnerBlock / kWave];
@@ -185,16 +189,29 @@ __global__ __launch_bounds__(kInnerBlock) void inner_multi_kernel(InnerMultiPara
         // the next pair straddles (its first draw is coarse, its second
         // fine); the rest are fine.  The lane takes pairs q = lane_g (mod G).
         T acc_coarse = (T)0, acc_fine = (T)0;
-        sum_pairs<T, LAWS, IW>(prm, L, (uint32_t)lane_g, coarse_pairs, (uint32_t)G, k, acc_coarse);
-        if (odd_prev && (coarse_pairs & (uint32_t)(G - 1)) == (uint32_t)lane_g) {
-            T a0, a1;
-            pair_terms<T, LAWS, IW>(prm, L, coarse_pairs, k, a0, a1);
-            acc_coarse += a0;
-            acc_fine += a1;
+        if constexpr (ST) {
+            // L.stride >= 2 above level 0 (c_l >= 2 c_{l-1}); 0 at level 0 (no coarse draws)
+            const uint32_t M = L.stride;
+            for (uint32_t q = (uint32_t)lane_g; q < pairs; q += (uint32_t)G) {
+                T a0, a1;
+                pair_terms<T, LAWS, IW>(prm, L, q, k, a0, a1);
+                const bool c0 = M != 0u && (2u * q + 1u) % M == 0u;
+                const bool c1 = M != 0u && (2u * q + 2u) % M == 0u;
+                if (c0) acc_coarse += a0; else acc_fine += a0;
+                if (c1) acc_coarse += a1; else acc_fine += a1;
+            }
+        } else {
+            sum_pairs<T, LAWS, IW>(prm, L, (uint32_t)lane_g, coarse_pairs, (uint32_t)G, k, acc_coarse);
+            if (odd_prev && (coarse_pairs & (uint32_t)(G - 1)) == (uint32_t)lane_g) {
+                T a0, a1;
+                pair_terms<T, LAWS, IW>(prm, L, coarse_pairs, k, a0, a1);
+                acc_coarse += a0;
+                acc_fine += a1;
+            }
+            const uint32_t fine_begin = coarse_pairs + (odd_prev ? 1u : 0u);
+            const uint32_t q_fine = fine_begin + (((uint32_t)lane_g - fine_begin) & (uint32_t)(G - 1));
+            sum_pairs<T, LAWS, IW>(prm, L, q_fine, pairs, (uint32_t)G, k, acc_fine);
         }
-        const uint32_t fine_begin = coarse_pairs + (odd_prev ? 1u : 0u);
-        const uint32_t q_fine = fine_begin + (((uint32_t)lane_g - fine_begin) & (uint32_t)(G - 1));
-        sum_pairs<T, LAWS, IW>(prm, L, q_fine, pairs, (uint32_t)G, k, acc_fine);
         T part = FN ? acc_fine : omega * acc_coarse + acc_fine;
         T part_c = acc_coarse;
         const int width = G < kWave ? G : kWave;
@@ -303,28 +320,36 @@ static uint32_t lanes_log2_for(int64_t c)
     return g;
 }
 
-template <typename T, bool FN, bool IW>
+template <typename T, bool FN, bool IW, bool ST>
 static void launch_inner(int laws, dim3 grid, hipStream_t stream, const InnerMultiParams& prm)
 {
     const dim3 block(kInnerBlock);
     if (laws == kLawsUniform)
-        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsUniform, FN, IW>), grid, block, 0, stream, prm);
+        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsUniform, FN, IW, ST>), grid, block, 0, stream, prm);
     else if (laws == kLawsNormal)
-        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsNormal, FN, IW>), grid, block, 0, stream, prm);
+        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsNormal, FN, IW, ST>), grid, block, 0, stream, prm);
     else if (laws == kLawsExperiment)
-        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsExperiment, FN, IW>), grid, block, 0, stream, prm);
+        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsExperiment, FN, IW, ST>), grid, block, 0, stream, prm);
     else
-        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsAny, FN, IW>), grid, block, 0, stream, prm);
+        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsAny, FN, IW, ST>), grid, block, 0, stream, prm);
 }
 
 template <typename T>
-static void launch_inner_forms(int laws, dim3 grid, hipStream_t stream, const InnerMultiParams& prm)
+static void launch_inner_forms(int laws, dim3 grid, hipStream_t stream, const InnerMultiParams& prm, bool st)
 {
     const bool fn = prm.f.kind != 0, iw = prm.iw != nullptr;
-    if (fn && iw) launch_inner<T, true, true>(laws, grid, stream, prm);
-    else if (fn) launch_inner<T, true, false>(laws, grid, stream, prm);
-    else if (iw) launch_inner<T, false, true>(laws, grid, stream, prm);
-    else launch_inner<T, false, false>(laws, grid, stream, prm);
+    if (st) {
+        // the stride coupling: one instantiation per precision, law pair and form
+        if (fn && iw) launch_inner<T, true, true, true>(laws, grid, stream, prm);
+        else if (fn) launch_inner<T, true, false, true>(laws, grid, stream, prm);
+        else if (iw) launch_inner<T, false, true, true>(laws, grid, stream, prm);
+        else launch_inner<T, false, false, true>(laws, grid, stream, prm);
+        return;
+    }
+    if (fn && iw) launch_inner<T, true, true, false>(laws, grid, stream, prm);
+    else if (fn) launch_inner<T, true, false, false>(laws, grid, stream, prm);
+    else if (iw) launch_inner<T, false, true, false>(laws, grid, stream, prm);
+    else launch_inner<T, false, false, false>(laws, grid, stream, prm);
 }
 
 hipError_t inner_levels_run(const LevelRange* ranges, int num_levels, int64_t n, const Law& x, const Law& y,
@@ -349,6 +374,7 @@ hipError_t inner_levels_run(const LevelRange* ranges, int num_levels, int64_t n,
     prm.y = y;
     prm.partials = partials;
 
+    bool stride = false;   // some level uses the stride coupling
     // deal workgroups to levels in proportion to their draw pairs
     double work[32], total = 0.0;
     for (int i = 0; i < num_levels; ++i) {
@@ -375,6 +401,8 @@ hipError_t inner_levels_run(const LevelRange* ranges, int num_levels, int64_t n,
         L.scale = (double)n / (double)lr.c;
         L.scale_c = lr.c_prev > 0 ? (double)n / (double)lr.c_prev : 0.0;
         L.omega = lr.c_prev > 0 ? 1.0 - (double)lr.c / (double)lr.c_prev : 0.0;
+        L.stride = (uint32_t)lr.stride;
+        if (lr.stride != 0) stride = true;
         int64_t blocks = 0;
         if (L.count > 0) {
             const int64_t groups = (int64_t)1 << (L.g_log2 >= 8 ? 0 : 8 - L.g_log2);
@@ -414,8 +442,8 @@ hipError_t inner_levels_run(const LevelRange* ranges, int num_levels, int64_t n,
     {
         ScopedTiming t(timer, 0);
         const dim3 grid(next);
-        if (prec == 0) launch_inner_forms<double>(laws, grid, stream, prm);
-        else launch_inner_forms<float>(laws, grid, stream, prm);
+        if (prec == 0) launch_inner_forms<double>(laws, grid, stream, prm, stride);
+        else launch_inner_forms<float>(laws, grid, stream, prm, stride);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

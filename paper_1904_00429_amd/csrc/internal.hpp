@@ -19,6 +19,8 @@ struct LevelRange {
     int64_t c_prev;        // c_{l-1}, 0 at level 0
     int64_t k_begin;       // first realisation
     int64_t count;         // number of realisations
+    int64_t stride;        // stride coupling: M = c_l / c_{l-1} (the coarse draws are
+                           // M - 1, 2M - 1, ...), 0: the first c_{l-1} draws
 };
 
 // Optional HIP-event timing of kernel launches, by kernel class (the
@@ -151,8 +153,8 @@ size_t adjoint_workspace_size(int64_t m, int64_t n, int64_t p, int num_levels, c
 hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law& B, int num_levels,
                        const int64_t* c, const int64_t* N, const StreamKeys& keys, bool shared,
                        const double* grad, float* dMA, float* dSA, float* dMB, float* dSB,
-                       const uint32_t* index_weights, char* ws, size_t ws_bytes, bool bf16, hipStream_t stream,
-                       KernelTimer* timer);
+                       const uint32_t* index_weights, char* ws, size_t ws_bytes, bool bf16, bool stride,
+                       hipStream_t stream, KernelTimer* timer);
 
 // ---- building blocks exported for tests -----------------------------------
 hipError_t philox_batch(int64_t count, const uint32_t* ctr, uint32_t key0, uint32_t key1,

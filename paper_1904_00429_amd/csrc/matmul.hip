@@ -151,18 +151,29 @@ struct GatherParams {
     double omega;            // 1 - c_l / c_{l-1}: weight of the coarse draws, folded into a_t
     const uint32_t* iw;      // index weights (NULL: uniform draws)
     const uint64_t* cum;     // their cumulative sums
+    uint32_t stride;         // stride coupling M (0: prefix)
     uint32_t key0, key1;
     uint32_t k_first;        // realisation of batch slot 0
     int elem;
     char* gbuf;              // per product: batch x [kpad/KPACK][m][KPACK], then batch x [..][p][..]
 };
 
-// Draw number t of padded position `pos`, or -1 for padding.
-__device__ __forceinline__ int64_t draw_of_position(int64_t pos, int64_t kc, uint32_t c, uint32_t c_prev)
+// Draw number t of padded position `pos`, or -1 for padding.  Positions
+// [0, kc) hold the c_prev coarse draws, positions [kc, kpad) the others, in
+// increasing t: with the prefix coupling draws 0 .. c_prev - 1, then the
+// rest; with the stride coupling (M = stride) draws M - 1, 2M - 1, ..., then
+// the q-th draw outside that set, t = q + floor(q / (M - 1)).  Within a
+// level the sum over positions is a sum over all c draws either way.
+__device__ __forceinline__ int64_t draw_of_position(int64_t pos, int64_t kc, uint32_t c, uint32_t c_prev,
+                                                   uint32_t stride)
 {
-    if (pos < kc) return pos < (int64_t)c_prev ? pos : -1;
-    const int64_t t = (int64_t)c_prev + (pos - kc);
-    return t < (int64_t)c ? t : -1;
+    if (pos < kc) {
+        if (pos >= (int64_t)c_prev) return -1;
+        return stride ? (int64_t)stride * (pos + 1) - 1 : pos;
+    }
+    const int64_t q = pos - kc;
+    if (q >= (int64_t)c - (int64_t)c_prev) return -1;
+    return stride ? q + q / ((int64_t)stride - 1) : (int64_t)c_prev + q;
 }
 
 template <typename Store> struct StoreOf;
@@ -196,7 +207,7 @@ __device__ __forceinline__ void draw_block_columns(const GatherParams& prm, int6
                                                    Compute* colf)
 {
     for (int i = threadIdx.x; i < npos_block; i += kGatherThreads) {
-        const int64_t t = draw_of_position(pos_base + i, prm.kc, prm.c, prm.c_prev);
+        const int64_t t = draw_of_position(pos_base + i, prm.kc, prm.c, prm.c_prev, prm.stride);
         uint32_t j = kNoDrawColumn;
         Compute f = (Compute)1;
         if (t >= 0) {
@@ -1250,6 +1261,7 @@ static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t
     g.descs = descs;
     g.c = (uint32_t)lr.c;
     g.c_prev = (uint32_t)lr.c_prev;
+    g.stride = (uint32_t)lr.stride;
     g.level_field = lr.level_field;
     g.kc = kc;
     g.kpad = kpad;

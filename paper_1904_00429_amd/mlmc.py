@@ -18,6 +18,8 @@ from ._lib import Dist, Levels, MLMCError, Problem, Report, Tuning, check, lib
 
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "fp8": 3}
 FLAG_SHARED_SAMPLES = 1
+FLAG_STRIDE_COUPLING = 8
+COUPLINGS = ("prefix", "stride")   # coarse draws: the first c_{l-1}, or every M-th (Sec. 3.1)
 FLAG_ADAPTIVE_LEVELS = 4
 SHARED_LEVEL_FIELD = 0xFF
 
@@ -130,9 +132,11 @@ class _LevelsHolder:
 
     def __init__(self, c, n_samples, rmse_target, pilot, seed, prec, shared, problem, max_total_draws,
                  func: Optional[Func] = None, adaptive: bool = False,
-                 index_weights: Optional[torch.Tensor] = None):
+                 index_weights: Optional[torch.Tensor] = None, coupling: str = "prefix"):
         if prec not in PREC:
             raise ValueError(f"prec must be one of {sorted(PREC)}")
+        if coupling not in COUPLINGS:
+            raise ValueError(f"coupling must be one of {COUPLINGS}")
         self.c = (ctypes.c_int64 * len(c))(*[int(v) for v in c])
         self.n = None if n_samples is None else (ctypes.c_int64 * len(n_samples))(*[int(v) for v in n_samples])
         lv = Levels()
@@ -144,7 +148,8 @@ class _LevelsHolder:
         lv.max_total_draws = int(max_total_draws)
         lv.seed = int(seed) & (2**64 - 1)
         lv.prec = PREC[prec]
-        lv.flags = (FLAG_SHARED_SAMPLES if shared else 0) | (FLAG_ADAPTIVE_LEVELS if adaptive else 0)
+        lv.flags = ((FLAG_SHARED_SAMPLES if shared else 0) | (FLAG_ADAPTIVE_LEVELS if adaptive else 0)
+                    | (FLAG_STRIDE_COUPLING if coupling == "stride" else 0))
         lv.problem = int(problem)
         f = func or Func()
         lv.func = int(f.kind)
@@ -180,14 +185,16 @@ def matmul_estimate(m: int, n: int, p: int, A: Law, B: Law, c: Sequence[int],
                     problem: int = 0, max_total_draws: int = 0, level_means: bool = False,
                     report: bool = True, device=None, workspace: Optional[torch.Tensor] = None,
                     out: Optional[torch.Tensor] = None, func: Optional[Func] = None,
-                    adaptive: bool = False, index_weights: Optional[torch.Tensor] = None) -> Result:
+                    adaptive: bool = False, index_weights: Optional[torch.Tensor] = None,
+                    coupling: str = "prefix") -> Result:
     """MLMC estimate of E[f(AB)] on the GPU (mlmc_matmul_estimate; f = identity
     unless func is given; adaptive: number of levels chosen by the bias test,
     c being the longest ladder allowed; index_weights: int32 device tensor of n
-    positive weights, xi_j = w_j / sum w, e.g. optimal_index_weights)."""
+    positive weights, xi_j = w_j / sum w, e.g. optimal_index_weights;
+    coupling: "prefix" or "stride", the coarse draws of each level sample)."""
     device = torch.device(device or "cuda")
     h = _LevelsHolder(c, n_samples, rmse_target, pilot, seed, prec, shared, problem, max_total_draws, func,
-                      adaptive, index_weights)
+                      adaptive, index_weights, coupling)
     ws_bytes = int(lib().mlmc_matmul_workspace_size(int(m), int(n), int(p), ctypes.byref(h.lv)))
     if ws_bytes == 0:
         raise MLMCError(1, "invalid problem: no workspace size")
@@ -213,13 +220,14 @@ def inner_product_estimate(n: int, x: Law, y: Law, c: Sequence[int],
                            report: bool = True, device=None,
                            workspace: Optional[torch.Tensor] = None,
                            out: Optional[torch.Tensor] = None, func: Optional[Func] = None,
-                           adaptive: bool = False, index_weights: Optional[torch.Tensor] = None) -> Result:
+                           adaptive: bool = False, index_weights: Optional[torch.Tensor] = None,
+                           coupling: str = "prefix") -> Result:
     """MLMC estimate of E[f(x^T y)] on the GPU (mlmc_inner_product_estimate;
-    f = identity unless func is given; adaptive and index_weights as for
-    matmul_estimate)."""
+    f = identity unless func is given; adaptive, index_weights and coupling
+    as for matmul_estimate)."""
     device = torch.device(device or "cuda")
     h = _LevelsHolder(c, n_samples, rmse_target, pilot, seed, prec, shared, problem, max_total_draws, func,
-                      adaptive, index_weights)
+                      adaptive, index_weights, coupling)
     ws_bytes = int(lib().mlmc_inner_product_workspace_size(int(n), ctypes.byref(h.lv)))
     if ws_bytes == 0:
         raise MLMCError(1, "invalid problem: no workspace size")
@@ -298,7 +306,7 @@ def matmul_adjoint_reparam(MA: torch.Tensor, SA: torch.Tensor, MB: torch.Tensor,
                            c: Sequence[int], n_samples: Sequence[int], grad_out: torch.Tensor,
                            seed: int = 0, problem: int = 0, shared: bool = False,
                            workspace: Optional[torch.Tensor] = None, prec: str = "fp32",
-                           index_weights: Optional[torch.Tensor] = None):
+                           index_weights: Optional[torch.Tensor] = None, coupling: str = "prefix"):
     """Gradients of <grad_out, Y> with respect to M_A, S_A, M_B, S_B
     (mlmc_matmul_adjoint_reparam).  MA, SA: (n, m) FP32 device tensors (row j =
     column j of A); MB, SB: (n, p).  prec: "fp32" or "bf16" (BF16 operands
@@ -307,7 +315,7 @@ def matmul_adjoint_reparam(MA: torch.Tensor, SA: torch.Tensor, MB: torch.Tensor,
     p = MB.shape[1]
     device = MA.device
     A, B = Law.reparam(MA, SA), Law.reparam(MB, SB)
-    h = _LevelsHolder(c, n_samples, 0.0, 0, seed, prec, shared, problem, 0, None, False, index_weights)
+    h = _LevelsHolder(c, n_samples, 0.0, 0, seed, prec, shared, problem, 0, None, False, index_weights, coupling)
     ws_bytes = int(lib().mlmc_matmul_adjoint_workspace_size(int(m), int(n), int(p), ctypes.byref(h.lv)))
     if ws_bytes == 0:
         raise MLMCError(1, "invalid problem: no workspace size")
@@ -341,10 +349,10 @@ class BatchedEstimate:
 
     def __init__(self, problems: Sequence[BatchProblem], c: Sequence[int], n_samples: Sequence[int],
                  seed: int = 0, prec: str = "fp32", tuning: Optional[dict] = None, device=None,
-                 func: Optional[Func] = None):
+                 func: Optional[Func] = None, coupling: str = "prefix"):
         self.device = torch.device(device or "cuda")
         self.problems = list(problems)
-        self.h = _LevelsHolder(c, n_samples, 0.0, 0, seed, prec, False, 0, 0, func)
+        self.h = _LevelsHolder(c, n_samples, 0.0, 0, seed, prec, False, 0, 0, func, coupling=coupling)
         self.Y = [torch.empty((pr.m, pr.p), dtype=torch.float64, device=self.device) for pr in self.problems]
         arr = (Problem * len(self.problems))()
         for i, pr in enumerate(self.problems):

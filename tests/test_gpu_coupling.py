@@ -1,0 +1,158 @@
+"""GPU parity of the stride coupling (Sec. 3.1: the coarse sketch takes every
+M-th fine draw, r_{jM}, M = c_l / c_{l-1}) against the oracle's stride mode
+on the same seeded inputs: the matrix estimator (every precision, the target
+function form, weighted draws, batches), the inner-product kernel (ladders
+whose coarse draws fall on either draw of a Philox pair) and the adjoint, at
+the tolerances of the prefix coupling (FP64 1e-12, FP32 1e-5, BF16 0.05
+RMSE_est, FP32 adjoint 1e-5).  A one-level ladder has no coarse draws: both
+couplings give the same estimate bit for bit."""
+import numpy as np
+import pytest
+
+from gpu_helpers import flush, laws, rel_frob
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+MATMUL = [
+    # m, n, p, law, ladder, N, precision, f
+    (70, 100, 40, ("normal", 0.1, 0.3), [2, 6, 18], [300, 150, 75], "fp64", None),
+    (64, 300, 128, ("uniform", 0.2, 0.5), [4, 8, 32], [200, 100, 50], "fp64", "abs_step"),
+    (37, 500, 45, ("normal", 0.5, 1.0), [3, 9, 27], [200, 100, 50], "fp32", None),
+    (128, 400, 64, ("normal", 0.5, 1.0), [8, 16, 64], [200, 100, 50], "bf16", None),
+]
+
+
+def _func(orc, name):
+    from paper_1904_00429_amd import Func
+    if name == "abs_step":
+        return orc.Func.abs_step(2.0), Func.abs_step(2.0)
+    if name == "inv_abs_step":
+        return orc.Func.inv_abs_step(0.4, 0.01), Func.inv_abs_step(0.4, 0.01)
+    return None, None
+
+
+@pytest.mark.parametrize("case", range(len(MATMUL)))
+def test_matmul_stride_matches_oracle(orc, dev, case):
+    from paper_1904_00429_amd import matmul_estimate
+    m, n, p, law, c, N, prec, fname = MATMUL[case]
+    flush(f"[stride] matmul {m}x{n}x{p} c={c} {prec} {fname}")
+    oA, gA = laws(orc, law, dev)
+    of, gf = _func(orc, fname)
+    est = matmul_estimate(m, n, p, gA, gA, c, n_samples=N, seed=17, prec=prec, level_means=True, device=dev,
+                          func=gf, coupling="stride")
+    ref = orc.estimate(m, n, p, oA, oA, c, n_samples=N, seed=17, func=of, coupling="stride")
+    Y = est.Y.cpu().numpy()
+    if prec == "bf16":
+        err = np.linalg.norm((Y - ref.Y).ravel())
+        flush(f"  bf16 error {err:.4g} vs rmse_est {ref.rmse_est:.4g}")
+        assert err <= 0.05 * ref.rmse_est
+        np.testing.assert_allclose(est.level_var, ref.level_var, rtol=3e-2)
+        return
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    assert rel_frob(Y, ref.Y) <= tol, rel_frob(Y, ref.Y)
+    np.testing.assert_allclose(est.level_var, ref.level_var, rtol=1e-10 if prec == "fp64" else 1e-5)
+    # the coupling changes the level samples: the prefix estimate differs
+    pre = orc.estimate(m, n, p, oA, oA, c, n_samples=N, seed=17, func=of)
+    assert rel_frob(pre.Y, ref.Y) > 1e-6
+
+
+INNER = [
+    # n, law, ladder, N, precision, f
+    (1000, ("normal", 0.3, 1.0), [1, 3, 9, 27], [4000, 2000, 1000, 500], "fp64", None),
+    (4096, ("uniform", 0.5, 1.0), [2, 4, 16, 64, 256], [2000, 1000, 500, 250, 125], "fp64", None),
+    (1000, ("normal", 0.1, 0.1), [2, 6, 12, 36], [4000, 2000, 1000, 500], "fp64", "inv_abs_step"),
+    (100000, ("uniform", 0.5, 1.0), [64, 192, 768, 1536], [800, 400, 200, 100], "fp32", None),
+]
+
+
+@pytest.mark.parametrize("case", range(len(INNER)))
+def test_inner_stride_matches_oracle(orc, dev, case):
+    from paper_1904_00429_amd import inner_product_estimate
+    n, law, c, N, prec, fname = INNER[case]
+    flush(f"[stride] inner n={n} c={c} {prec} {fname}")
+    ox, gx = laws(orc, law, dev)
+    of, gf = _func(orc, fname)
+    est = inner_product_estimate(n, gx, gx, c, n_samples=N, seed=23, prec=prec, level_means=True, device=dev,
+                                 func=gf, coupling="stride")
+    ref = orc.estimate(1, n, 1, ox, ox, c, n_samples=N, seed=23, func=of, coupling="stride")
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    y = float(est.Y.cpu())
+    scale = abs(ref.Y[0, 0]) + float(np.sqrt(np.sum(np.asarray(ref.level_var) / np.asarray(N))))
+    assert abs(y - ref.Y[0, 0]) <= tol * scale, (y, ref.Y[0, 0])
+    np.testing.assert_allclose(est.level_var, ref.level_var, rtol=1e-10 if prec == "fp64" else 1e-4)
+
+
+def test_one_level_is_the_same_for_both_couplings(orc, dev):
+    from paper_1904_00429_amd import inner_product_estimate, matmul_estimate
+    flush("[stride] one level")
+    _, g = laws(orc, ("normal", 0.5, 1.0), dev)
+    a = matmul_estimate(40, 200, 30, g, g, [16], n_samples=[100], seed=1, prec="fp64", device=dev)
+    b = matmul_estimate(40, 200, 30, g, g, [16], n_samples=[100], seed=1, prec="fp64", device=dev, coupling="stride")
+    assert torch.equal(a.Y, b.Y)
+    a = inner_product_estimate(5000, g, g, [32], n_samples=[1000], seed=1, prec="fp32", device=dev)
+    b = inner_product_estimate(5000, g, g, [32], n_samples=[1000], seed=1, prec="fp32", device=dev, coupling="stride")
+    assert torch.equal(a.Y, b.Y)
+
+
+def test_weighted_stride_matches_oracle(orc, dev):
+    from paper_1904_00429_amd import matmul_estimate, optimal_index_weights
+    m, n, p, c, N = 30, 400, 20, [2, 8, 16], [200, 100, 50]
+    flush("[stride] weighted draws")
+    rng = np.random.default_rng(4)
+    ramp = np.linspace(0.05, 3.0, n)[:, None]
+    MA = (rng.standard_normal((n, m)) * ramp).astype(np.float32)
+    SA = (rng.uniform(0.1, 1.0, (n, m)) * ramp).astype(np.float32)
+    MB = rng.standard_normal((n, p)).astype(np.float32)
+    SB = rng.uniform(0.1, 1.0, (n, p)).astype(np.float32)
+    oA, gA = laws(orc, ("reparam",), dev, MA, SA)
+    oB, gB = laws(orc, ("reparam",), dev, MB, SB)
+    ow = orc.Weights(orc.optimal_weights(m, n, p, oA, oB))
+    gw = optimal_index_weights(m, n, p, gA, gB, device=dev)
+    est = matmul_estimate(m, n, p, gA, gB, c, n_samples=N, seed=6, prec="fp64", device=dev, index_weights=gw,
+                          coupling="stride")
+    ref = orc.estimate(m, n, p, oA, oB, c, n_samples=N, seed=6, weights=ow, coupling="stride")
+    assert rel_frob(est.Y.cpu().numpy(), ref.Y) <= 1e-12
+
+
+def test_batched_stride_matches_oracle(orc, dev):
+    from paper_1904_00429_amd import BatchedEstimate, BatchProblem, Law
+    shapes = [(64, 100, 64), (100, 150, 37)]
+    c, N = [2, 6, 24], [120, 60, 30]
+    flush("[stride] batched fp64")
+    probs = [BatchProblem(m, n, p, Law.normal(0.5, 1.0), Law.normal(0.5, 1.0), 5 + i)
+             for i, (m, n, p) in enumerate(shapes)]
+    est = BatchedEstimate(probs, c, N, seed=2, prec="fp64", device=dev, coupling="stride")
+    V = est.run(level_var=True)
+    torch.cuda.synchronize()
+    law = orc.Law.normal(0.5, 1.0)
+    for i, (m, n, p) in enumerate(shapes):
+        ref = orc.estimate(m, n, p, law, law, c, n_samples=N, seed=2, problem=5 + i, coupling="stride")
+        assert rel_frob(est.Y[i].cpu().numpy(), ref.Y) <= 1e-12
+        np.testing.assert_allclose(V[:, i], ref.level_var, rtol=1e-10)
+
+
+def test_adjoint_stride_matches_reference(orc, dev):
+    from oracle import grad as og
+    from paper_1904_00429_amd import matmul_adjoint_reparam
+    m, n, p, c, N = 24, 300, 17, [2, 6, 18], [20, 10, 5]
+    flush("[stride] adjoint fp32")
+    rng = np.random.default_rng(8)
+    params = [rng.standard_normal((n, m)).astype(np.float32), rng.uniform(0.1, 1.0, (n, m)).astype(np.float32),
+              rng.standard_normal((n, p)).astype(np.float32), rng.uniform(0.1, 1.0, (n, p)).astype(np.float32)]
+    G = rng.standard_normal((m, p))
+    _, ref = og.reparam_gradients(*params, c, N, G, seed=3, coupling="stride")
+    dp = [torch.from_numpy(x).to(dev) for x in params]
+    got = matmul_adjoint_reparam(*dp, c, N, torch.from_numpy(G), seed=3, prec="fp32", coupling="stride")
+    for name, g, r in zip(("dMA", "dSA", "dMB", "dSB"), got, ref):
+        err = rel_frob(g.cpu().numpy(), r)
+        flush(f"  {name} rel err {err:.3g}")
+        assert err <= 1e-5, (name, err)
