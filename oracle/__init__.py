@@ -27,7 +27,10 @@ Parity pins and where they are tested (``tests/test_oracle_*.py``):
                      functions of Poisson, exponential and normal variables)
                      and the Poisson probabilities by chi-square;
   stride coupling    unit-vector probe of the coarse draws (r_{jM}), brute
-                     force over index tuples, closed-form V_l by z-test.
+                     force over index tuples, closed-form V_l by z-test;
+  32-bit index words top bits of the rocRAND-pinned Philox words for
+                     power-of-two n, exact integers, chi-square, closed-form
+                     V_l of the inner product by z-test.
 """
 from __future__ import annotations
 
@@ -99,6 +102,9 @@ def lib():
         L.orc_draw_indices.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                        ctypes.c_uint32, ctypes.c_int64, ctypes.c_int64,
                                        ctypes.c_void_p]
+        L.orc_draw_indices_mode.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                            ctypes.c_uint32, ctypes.c_int64, ctypes.c_int64,
+                                            ctypes.c_int32, ctypes.c_void_p]
         L.orc_uniform.restype = ctypes.c_double
         L.orc_uniform.argtypes = [ctypes.c_uint32]
         L.orc_column.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
@@ -108,7 +114,7 @@ def lib():
         L.orc_sketch_pair.argtypes = [ctypes.c_int64] * 6 + [ctypes.c_void_p] * 4
         L.orc_level_estimation.restype = ctypes.c_int
         L.orc_level_estimation.argtypes = (
-            [ctypes.c_int64] * 3 + [ctypes.POINTER(_Law)] * 2 + [ctypes.c_int64] * 3
+            [ctypes.c_int64] * 3 + [ctypes.POINTER(_Law)] * 2 + [ctypes.c_int64] * 3 + [ctypes.c_int32]
             + [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64,
                ctypes.c_int64, ctypes.POINTER(_Func), ctypes.POINTER(_Weights), ctypes.c_void_p,
                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p])
@@ -286,9 +292,13 @@ def level_field(level: int, shared: bool = False) -> int:
     return SHARED_LEVEL_FIELD if shared else int(level)
 
 
-def draw_indices(seed: int, problem: int, lfield: int, k: int, c: int, n: int) -> np.ndarray:
+def draw_indices(seed: int, problem: int, lfield: int, k: int, c: int, n: int,
+                 word32: bool = False) -> np.ndarray:
+    """Draws 0 .. c-1 of realisation k; word32: four draws per Philox call,
+    r = floor(w n / 2^32) from one 32-bit word (exact for power-of-two n)."""
     r = np.empty(int(c), dtype=np.int64)
-    lib().orc_draw_indices(int(seed), int(problem), int(lfield), int(k), int(c), int(n), _ptr(r))
+    lib().orc_draw_indices_mode(int(seed), int(problem), int(lfield), int(k), int(c), int(n), int(bool(word32)),
+                                _ptr(r))
     return r
 
 
@@ -362,11 +372,12 @@ def level_estimation(state: LevelState, m: int, n: int, p: int, A: Law, B: Law,
                      c_l: int, c_prev: int, seed: int, problem: int, lfield: int,
                      k_begin: int, k_end: int, want_samples: bool = False,
                      func: Optional[Func] = None, weights: Optional["Weights"] = None,
-                     coupling: str = "prefix"):
+                     coupling: str = "prefix", index_word32: bool = False):
     """Alg. 1 for realisations [k_begin, k_end), continuing `state` in place;
     level samples f(Zf) - f(Zc) (identity when func is None).  coupling:
     "prefix" (the coarse sketch takes the first c_prev draws) or "stride"
-    (every M-th draw, M = c_l / c_prev, Sec. 3.1)."""
+    (every M-th draw, M = c_l / c_prev, Sec. 3.1).  index_word32: the indices
+    from 32-bit words (draw_indices(word32=True))."""
     cnt = ctypes.c_int64(state.count)
     samples = np.empty((max(k_end - k_begin, 0), m, p)) if want_samples else None
     la, lb = A.c(), B.c()
@@ -376,7 +387,7 @@ def level_estimation(state: LevelState, m: int, n: int, p: int, A: Law, B: Law,
     wc = weights.c() if weights is not None else None
     rc = lib().orc_level_estimation(
         int(m), int(n), int(p), ctypes.byref(la), ctypes.byref(lb), int(c_l), int(c_prev),
-        coupling_stride(c_l, c_prev, coupling), int(seed), int(problem), int(lfield), int(k_begin), int(k_end), ctypes.byref(fc),
+        coupling_stride(c_l, c_prev, coupling), int(bool(index_word32)), int(seed), int(problem), int(lfield), int(k_begin), int(k_end), ctypes.byref(fc),
         ctypes.byref(wc) if wc is not None else None,
         ctypes.byref(cnt), _ptr(state.mean), _ptr(state.m2), _ptr(samples) if want_samples else None)
     if rc != 0:
@@ -434,7 +445,7 @@ def estimate(m: int, n: int, p: int, A: Law, B: Law, c: Sequence[int],
              pilot: int = 0, seed: int = 0, problem: int = 0, shared: bool = False,
              max_total_draws: int = 0, pool=None, func: Optional[Func] = None,
              adaptive: Optional[str] = None, weights: Optional[Weights] = None,
-             coupling: str = "prefix") -> Estimate:
+             coupling: str = "prefix", index_word32: bool = False) -> Estimate:
     """MLMC estimate of E[f(AB)] (f entrywise, identity by default) over the
     ladder c_0 < c_1 < ... < c_L.
 
@@ -458,7 +469,7 @@ def estimate(m: int, n: int, p: int, A: Law, B: Law, c: Sequence[int],
     def run(l, k0, k1):
         level_estimation(states[l], m, n, p, A, B, c[l], c[l - 1] if l > 0 else 0,
                          seed, problem, level_field(l, shared), k0, k1, func=func, weights=weights,
-                         coupling=coupling)
+                         coupling=coupling, index_word32=index_word32)
 
     def run_all(ranges):
         if pool is None:

@@ -170,11 +170,35 @@ int64_t orc_draw_index(uint64_t seed, uint32_t problem, uint32_t level_field,
     return (int64_t)(uint64_t)(prod >> 64);
 }
 
+/* The same draw from a 32-bit word: draw t uses word t % 4 of the call
+ * (t / 4, k, 0, index stream) and r = floor(w n / 2^32), four draws per
+ * Philox call.  Exactly uniform when n is a power of two (r is then the top
+ * log2 n bits of w); the library offers it for such n only. */
+int64_t orc_draw_index32(uint64_t seed, uint32_t problem, uint32_t level_field,
+                         uint32_t k, int64_t t, int64_t n)
+{
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    uint32_t ctr[4] = { (uint32_t)(t >> 2), k, 0u,
+                        stream_word(ORC_TAG_INDEX, level_field, problem) };
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+    uint64_t prod = (uint64_t)w[t & 3] * (uint64_t)n;
+    return (int64_t)(prod >> 32);
+}
+
+/* Draws 0 .. c-1 of realisation k (word32: the 32-bit draw). */
+void orc_draw_indices_mode(uint64_t seed, uint32_t problem, uint32_t level_field,
+                           uint32_t k, int64_t c, int64_t n, int32_t word32, int64_t* r)
+{
+    for (int64_t t = 0; t < c; ++t)
+        r[t] = word32 ? orc_draw_index32(seed, problem, level_field, k, t, n)
+                      : orc_draw_index(seed, problem, level_field, k, t, n);
+}
+
 void orc_draw_indices(uint64_t seed, uint32_t problem, uint32_t level_field,
                       uint32_t k, int64_t c, int64_t n, int64_t* r)
 {
-    for (int64_t t = 0; t < c; ++t)
-        r[t] = orc_draw_index(seed, problem, level_field, k, t, n);
+    orc_draw_indices_mode(seed, problem, level_field, k, c, n, 0, r);
 }
 
 /* Non-uniform index probabilities (eq. (18) with a general xi): xi_j = w_j / W
@@ -427,7 +451,8 @@ void orc_sketch_pair(int64_t m, int64_t p, int64_t n, int64_t c_f, int64_t c_c, 
  * evaluations).  samples_out (nullable) receives every D, row-major.
  * Returns 0, or -1 on bad arguments / allocation failure. */
 int orc_level_estimation(int64_t m, int64_t n, int64_t p, const orc_law* A, const orc_law* B,
-                         int64_t c_l, int64_t c_prev, int64_t stride, uint64_t seed, uint32_t problem,
+                         int64_t c_l, int64_t c_prev, int64_t stride, int32_t word32, uint64_t seed,
+                         uint32_t problem,
                          uint32_t level_field, int64_t k_begin, int64_t k_end, const orc_func* f,
                          const orc_weights* iw, int64_t* count, double* mean, double* m2,
                          double* samples_out)
@@ -456,7 +481,7 @@ int orc_level_estimation(int64_t m, int64_t n, int64_t p, const orc_law* A, cons
                 factor[t] = (double)iw->total / (double)iw->w[r[t]];
             }
         } else {
-            orc_draw_indices(seed, problem, level_field, (uint32_t)k, c_l, n, r);
+            orc_draw_indices_mode(seed, problem, level_field, (uint32_t)k, c_l, n, word32, r);
         }
         for (int64_t t = 0; t < c_l; ++t)
             orc_column(seed, problem, level_field, (uint32_t)k, r[t], m, p, A, B,
