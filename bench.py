@@ -7,7 +7,9 @@ laws, not arrays: every sampled value is generated inside the timed region
 (the method draws its data).
 
 Default workload: x, y in R^(2^20) with i.i.d. 0.5 + U(-1, 1) entries, ladder
-c_l = 64 * 2^l (l = 0..8), eps = 1e-3 |E[x^T y]|, FP32 arithmetic.
+c_l = 64 * 2^l (l = 0..8), eps = 1e-3 |E[x^T y]|, FP32 arithmetic, index draws
+from 32-bit words (four per Philox call; exactly uniform since n is a power of
+two; --index-words 64 selects the two-per-call 64-bit draws).
 
 Printed: one JSON line with the throughput, the roofline of the dominant
 kernel (device time from HIP events recorded by the library on the stream the
@@ -33,12 +35,13 @@ METRIC = "MLMC product estimates/s at fixed RMSE eps"
 # high multiply are half rate = 2 slots):
 #   1.5 Philox4x32-10 evaluations (half an index call, one value call), each
 #       10 rounds x (2 multiply-adds x 2 + 2 three-input xors x 1) = 60 slots;
+#       1.25 with 32-bit index words (a quarter of an index call);
 #   index map: 1 shift for a power-of-two n, else high multiply + multiply-add = 4;
 #   two uniform values: shift, convert, fused scale and law map = 4 each;
 #   product and accumulation into the level sum = 2.
-def slots_per_draw_inner(n: int) -> float:
+def slots_per_draw_inner(n: int, word32: bool = False) -> float:
     index = 1 if n & (n - 1) == 0 else 4
-    return 1.5 * 60 + index + 2 * 4 + 2
+    return (1.25 if word32 else 1.5) * 60 + index + 2 * 4 + 2
 
 
 # MI355X VALU issue: 256 CUs x 128 lanes per clock x 2.4 GHz = 78.6 T lane-ops/s
@@ -79,6 +82,9 @@ def parse():
                     help="share of every level's realisations the CPU oracle runs")
     ap.add_argument("--func", default="identity", choices=["identity", "abs_step", "inv_abs_step"],
                     help="target function f of E[f(AB)]: |x| H(2 - x) or 1 / (|x| H(x + 0.4) + 0.01) (Sec. 4)")
+    ap.add_argument("--index-words", type=int, default=32, choices=[32, 64],
+                    help="inner product: index draws from 32-bit words (four per Philox call, power-of-two n) "
+                         "or 64-bit words (two per call)")
     ap.add_argument("--adaptive", action="store_true",
                     help="choose the number of levels by the bias test (the workload's ladder is the longest)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -91,7 +97,7 @@ def _oracle_func(oracle, name):
             "inv_abs_step": oracle.Func.inv_abs_step(0.4, 0.01)}[name]
 
 
-def cpu_baseline_inner(wl, n_used, fraction, func="identity"):
+def cpu_baseline_inner(wl, n_used, fraction, func="identity", word32=False):
     """The oracle (single-threaded C) on the first `fraction` of every level's
     realisations of the same workload; scaled to estimates/s."""
     import oracle
@@ -106,7 +112,7 @@ def cpu_baseline_inner(wl, n_used, fraction, func="identity"):
         k = max(2, int(round(N * fraction)))
         st = oracle.LevelState.empty(1, 1)
         oracle.level_estimation(st, 1, wl.n, 1, law, law, wl.c[l], wl.c[l - 1] if l else 0, wl.seed, 0, l, 0, k,
-                                func=f)
+                                func=f, index_word32=word32)
         draws += k * wl.c[l]
     dt = time.perf_counter() - t0
     total_draws = sum(N * c for N, c in zip(n_used, wl.c))
@@ -166,6 +172,8 @@ def main():
     timing_flag = 2
     _OPTS["func"] = _func_of(args.func)
     _OPTS["adaptive"] = bool(args.adaptive)
+    args.index_word32 = args.workload == "inner" and args.index_words == 32
+    _OPTS["index_word32"] = args.index_word32
     if args.workload == "diff":
         return bench_diff(args)
     if args.workload == "batched":
@@ -219,17 +227,18 @@ def main():
 
     if args.workload == "inner":
         avg = k_ms[0] / max(k_n[0], 1)
-        slots = slots_per_draw_inner(wl.n) * draws / max(k_n[0], 1)
+        slots = slots_per_draw_inner(wl.n, args.index_word32) * draws / max(k_n[0], 1)
         achieved = slots / (avg * 1e-3)
         roof = {"bound": "alu", "kernel": f"inner_multi_kernel<{'float' if prec == 'fp32' else 'double'}>",
                 "achieved": achieved / 1e12, "peak": PEAK_VALU_SLOTS / 1e12, "unit": "Tops/s",
                 "frac": achieved / PEAK_VALU_SLOTS, "traffic": measured_traffic("inner_multi_kernel"),
                 "traffic_unit": "bytes per launch",
                 "avg_launch_ms": avg, "launches": k_n[0],
-                "ops_per_draw": slots_per_draw_inner(wl.n)}
+                "ops_per_draw": slots_per_draw_inner(wl.n, args.index_word32)}
         config = {"workload": wl.name, "n": wl.n, "levels": len(wl.c), "c0": wl.c[0], "ratio": 2,
                   "eps": wl.rmse_target, "pilot": wl.pilot, "law": "0.5 + U(-1, 1) i.i.d.",
-                  "prec": prec, "func": args.func, "adaptive": bool(args.adaptive)}
+                  "prec": prec, "func": args.func, "adaptive": bool(args.adaptive),
+                  "index_words": 32 if args.index_word32 else 64}
     else:
         # dominant: the sketch (MFMA) kernel; algorithmic flops 2 m p per draw
         flops = 2.0 * wl.m * wl.p * draws
@@ -277,7 +286,8 @@ def main():
 
     if not args.no_cpu_baseline:
         if args.workload == "inner":
-            out["cpu_baseline"] = cpu_baseline_inner(wl, rep.n_used, args.cpu_fraction, args.func)
+            out["cpu_baseline"] = cpu_baseline_inner(wl, rep.n_used, args.cpu_fraction, args.func,
+                                                     args.index_word32)
         else:
             out["cpu_baseline"] = cpu_baseline_matmul(wl, rep.n_used, 0.001, func=args.func)
     print(json.dumps(out), flush=True)
@@ -660,7 +670,7 @@ def _inner(api, wl, x, prec, dev, want_timing, seed):
 def _call_inner(api, wl, x, prec, dev, ws, out, want_timing, seed):
     import ctypes
     h = api._LevelsHolder(wl.c, None, wl.rmse_target, wl.pilot, seed, prec, False, 0, 0, _OPTS["func"],
-                          _OPTS["adaptive"])
+                          _OPTS["adaptive"], index_word32=_OPTS.get("index_word32", False))
     if want_timing:
         h.lv.flags |= 2
     lib = api.lib()

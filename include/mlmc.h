@@ -117,6 +117,14 @@ typedef enum {
  * telescoping sum exact.  Every entry point accepts it, the batched ones
  * included. */
 #define MLMC_FLAG_STRIDE_COUPLING 8u
+/* Index draws from 32-bit words (inner product only, n a power of two,
+ * uniform draws, laws 0-2): draw t takes word t % 4 of the index-stream call
+ * (t / 4, k, 0, 1 << 28 | level << 20 | problem) and r = floor(w n / 2^32),
+ * the top log2 n bits of w: exactly uniform, four draws per Philox call
+ * instead of two.  A different stream from the default 64-bit draws, so
+ * the estimates differ realisation by realisation (not in law).  EINVAL
+ * otherwise. */
+#define MLMC_FLAG_INDEX_WORD32 16u
 #define MLMC_MAX_LEVELS 32
 
 /* Kernel classes of mlmc_report.kernel_ms (MLMC_FLAG_TIMING). */

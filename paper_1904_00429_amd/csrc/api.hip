@@ -67,6 +67,8 @@ mlmc_status check_levels(const mlmc_levels* lv, bool inner)
     if (lv->max_total_draws < 0) return fail(MLMC_EINVAL, "max_total_draws must be >= 0");
     if (lv->index_weights && lv->prec == MLMC_PREC_FP8)
         return fail(MLMC_EINVAL, "weighted index draws are not offered with FP8 operands");
+    if ((lv->flags & MLMC_FLAG_INDEX_WORD32) && (!inner || lv->index_weights))
+        return fail(MLMC_EINVAL, "32-bit index words are offered for uniform draws of the inner product");
     if ((lv->flags & MLMC_FLAG_ADAPTIVE_LEVELS) && !(lv->rmse_target > 0.0))
         return fail(MLMC_EINVAL, "the adaptive number of levels needs target mode (rmse_target > 0)");
     if (lv->func < MLMC_FUNC_IDENTITY || lv->func > MLMC_FUNC_INV_ABS_STEP)
@@ -308,6 +310,8 @@ mlmc_status mlmc_inner_product_estimate(int64_t n, const mlmc_dist* x, const mlm
     if ((st = check_dist(x, "x", 1, true)) != MLMC_OK) return st;
     if ((st = check_dist(y, "y", 1, true)) != MLMC_OK) return st;
     if ((st = check_pair(x, y, lv->prec)) != MLMC_OK) return st;
+    if ((lv->flags & MLMC_FLAG_INDEX_WORD32) && ((n & (n - 1)) != 0 || x->law >= MLMC_LAW_RAMP_NORMAL))
+        return fail(MLMC_EINVAL, "32-bit index words need a power-of-two n and laws 0-2");
     if (!out) return fail(MLMC_EINVAL, "out is NULL");
     const InnerLayout L = inner_layout(lv->num_levels, n, lv->index_weights != nullptr);
     if (!workspace || workspace_bytes < L.total)
@@ -339,8 +343,8 @@ mlmc_status mlmc_inner_product_estimate(int64_t n, const mlmc_dist* x, const mlm
     auto run_all = [&](const int64_t* k0, const int64_t* cnt) -> hipError_t {
         LevelRange ranges[MLMC_MAX_LEVELS];
         for (int l = 0; l < L1; ++l) ranges[l] = range_of(lv, l, k0[l], cnt[l]);
-        return inner_levels_run(ranges, L1, n, lx, ly, func_of(lv), iw, lv->prec, keys, partials, state, stream,
-                                timer);
+        return inner_levels_run(ranges, L1, n, lx, ly, func_of(lv), iw, lv->prec,
+                                (lv->flags & MLMC_FLAG_INDEX_WORD32) != 0, keys, partials, state, stream, timer);
     };
     std::vector<int64_t> zero(L1, 0), amount(L1, 0);
     int used = L1;

@@ -101,6 +101,35 @@ __device__ __forceinline__ T inner_product_term(const InnerMultiParams& prm, uin
     return xv * yv;
 }
 
+// W32: the four product terms of draw quad g (draws 4g .. 4g + 3) of
+// realisation k from one Philox call of the index stream, r = w >> (32 -
+// log2 n) for each 32-bit word (n a power of two); draws past c give 0.
+template <typename T, int LAWS>
+__device__ __forceinline__ void quad_terms(const InnerMultiParams& prm, const InnerLevel& L, uint32_t g, uint32_t k,
+                                           T (&v)[4])
+{
+    const Words4 w = philox4x32_10(g, k, 0u, L.sid_index, prm.key0, prm.key1);
+    const uint32_t r[4] = {w.w0, w.w1, w.w2, w.w3};
+    const uint32_t sh = prm.n_shift;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t j = sh >= 32u ? 0u : r[i] >> sh;
+        v[i] = (4u * g + (uint32_t)i < L.c) ? inner_product_term<T, LAWS>(prm, k, j, L.sid_value) : (T)0;
+    }
+}
+
+// Sum of the product terms of quads g0, g0 + G, ... below g_end into acc.
+template <typename T, int LAWS>
+__device__ __forceinline__ void sum_quads(const InnerMultiParams& prm, const InnerLevel& L, uint32_t g0,
+                                          uint32_t g_end, uint32_t G, uint32_t k, T& acc)
+{
+    for (uint32_t g = g0; g < g_end; g += G) {
+        T v[4];
+        quad_terms<T, LAWS>(prm, L, g, k, v);
+        acc += (v[0] + v[1]) + (v[2] + v[3]);
+    }
+}
+
 // The two product terms of draw pair q (draws 2q and 2q + 1) of realisation k;
 // IW: weighted draws, each term times 1 / (n xi_j) (eq. (18) with a general xi).
 template <typename T, int LAWS, bool IW>
@@ -154,7 +183,9 @@ __device__ __forceinline__ void sum_pairs(const InnerMultiParams& prm, const Inn
 // ST: stride coupling.  Every pair is summed, and each of its two draws goes
 // to the coarse sum when its number t has (t + 1) % M == 0, else to the fine
 // sum (a separate instantiation, so the prefix kernels are unchanged).
-template <typename T, int LAWS, bool FN, bool IW, bool ST>
+// W32: 32-bit index words, the lane walks draw quads instead of pairs (same
+// coarse range / straddling unit / fine range split, or the stride predicate).
+template <typename T, int LAWS, bool FN, bool IW, bool ST, bool W32>
 __global__ __launch_bounds__(kInnerBlock) void inner_multi_kernel(InnerMultiParams prm)
 {
     __shared__ double wave_sum[kInnerBlock / kWave];
@@ -189,7 +220,38 @@ __global__ __launch_bounds__(kInnerBlock) void inner_multi_kernel(InnerMultiPara
         // the next pair straddles (its first draw is coarse, its second
         // fine); the rest are fine.  The lane takes pairs q = lane_g (mod G).
         T acc_coarse = (T)0, acc_fine = (T)0;
-        if constexpr (ST) {
+        if constexpr (W32) {
+            const uint32_t quads = (L.c + 3u) >> 2;
+            if constexpr (ST) {
+                const uint32_t M = L.stride;
+                for (uint32_t g4 = (uint32_t)lane_g; g4 < quads; g4 += (uint32_t)G) {
+                    T v[4];
+                    quad_terms<T, LAWS>(prm, L, g4, k, v);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        if (M != 0u && (4u * g4 + (uint32_t)i + 1u) % M == 0u) acc_coarse += v[i];
+                        else acc_fine += v[i];
+                    }
+                }
+            } else {
+                // quads below cq hold four coarse draws; with c_prev % 4 = rem > 0
+                // quad cq straddles (its first rem draws are coarse)
+                const uint32_t cq = L.c_prev >> 2, rem = L.c_prev & 3u;
+                sum_quads<T, LAWS>(prm, L, (uint32_t)lane_g, cq, (uint32_t)G, k, acc_coarse);
+                if (rem != 0u && (cq & (uint32_t)(G - 1)) == (uint32_t)lane_g) {
+                    T v[4];
+                    quad_terms<T, LAWS>(prm, L, cq, k, v);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        if ((uint32_t)i < rem) acc_coarse += v[i];
+                        else acc_fine += v[i];
+                    }
+                }
+                const uint32_t fine_begin = cq + (rem != 0u ? 1u : 0u);
+                const uint32_t g_fine = fine_begin + (((uint32_t)lane_g - fine_begin) & (uint32_t)(G - 1));
+                sum_quads<T, LAWS>(prm, L, g_fine, quads, (uint32_t)G, k, acc_fine);
+            }
+        } else if constexpr (ST) {
             // L.stride >= 2 above level 0 (c_l >= 2 c_{l-1}); 0 at level 0 (no coarse draws)
             const uint32_t M = L.stride;
             for (uint32_t q = (uint32_t)lane_g; q < pairs; q += (uint32_t)G) {
@@ -325,19 +387,40 @@ static void launch_inner(int laws, dim3 grid, hipStream_t stream, const InnerMul
 {
     const dim3 block(kInnerBlock);
     if (laws == kLawsUniform)
-        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsUniform, FN, IW, ST>), grid, block, 0, stream, prm);
+        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsUniform, FN, IW, ST, false>), grid, block, 0, stream, prm);
     else if (laws == kLawsNormal)
-        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsNormal, FN, IW, ST>), grid, block, 0, stream, prm);
+        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsNormal, FN, IW, ST, false>), grid, block, 0, stream, prm);
     else if (laws == kLawsExperiment)
-        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsExperiment, FN, IW, ST>), grid, block, 0, stream, prm);
+        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsExperiment, FN, IW, ST, false>), grid, block, 0, stream, prm);
     else
-        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsAny, FN, IW, ST>), grid, block, 0, stream, prm);
+        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsAny, FN, IW, ST, false>), grid, block, 0, stream, prm);
+}
+
+// 32-bit index words: uniform draws and the classic laws only (the host checks)
+template <typename T, bool FN, bool ST>
+static void launch_inner_w32(int laws, dim3 grid, hipStream_t stream, const InnerMultiParams& prm)
+{
+    const dim3 block(kInnerBlock);
+    if (laws == kLawsUniform)
+        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsUniform, FN, false, ST, true>), grid, block, 0, stream, prm);
+    else if (laws == kLawsNormal)
+        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsNormal, FN, false, ST, true>), grid, block, 0, stream, prm);
+    else
+        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsAny, FN, false, ST, true>), grid, block, 0, stream, prm);
 }
 
 template <typename T>
-static void launch_inner_forms(int laws, dim3 grid, hipStream_t stream, const InnerMultiParams& prm, bool st)
+static void launch_inner_forms(int laws, dim3 grid, hipStream_t stream, const InnerMultiParams& prm, bool st,
+                               bool w32)
 {
     const bool fn = prm.f.kind != 0, iw = prm.iw != nullptr;
+    if (w32) {
+        if (fn && st) launch_inner_w32<T, true, true>(laws, grid, stream, prm);
+        else if (fn) launch_inner_w32<T, true, false>(laws, grid, stream, prm);
+        else if (st) launch_inner_w32<T, false, true>(laws, grid, stream, prm);
+        else launch_inner_w32<T, false, false>(laws, grid, stream, prm);
+        return;
+    }
     if (st) {
         // the stride coupling: one instantiation per precision, law pair and form
         if (fn && iw) launch_inner<T, true, true, true>(laws, grid, stream, prm);
@@ -353,8 +436,9 @@ static void launch_inner_forms(int laws, dim3 grid, hipStream_t stream, const In
 }
 
 hipError_t inner_levels_run(const LevelRange* ranges, int num_levels, int64_t n, const Law& x, const Law& y,
-                            const TargetFunc& f, const IndexWeights& iw, int prec, const StreamKeys& keys,
-                            Moments* partials, Moments* level_state, hipStream_t stream, KernelTimer* timer)
+                            const TargetFunc& f, const IndexWeights& iw, int prec, bool index_word32,
+                            const StreamKeys& keys, Moments* partials, Moments* level_state, hipStream_t stream,
+                            KernelTimer* timer)
 {
     InnerMultiParams prm;
     prm.f = f;
@@ -439,11 +523,14 @@ hipError_t inner_levels_run(const LevelRange* ranges, int num_levels, int64_t n,
     // the laws of Sec. 4 pair only with each other
     if (laws != kLawsExperiment && (x.kind >= kLawExperimentFirst || y.kind >= kLawExperimentFirst))
         return hipErrorInvalidValue;
+    // 32-bit index words: power-of-two n, uniform draws, classic laws
+    if (index_word32 && (prm.n_shift == 0xFFFFFFFFu || iw.w || laws == kLawsExperiment))
+        return hipErrorInvalidValue;
     {
         ScopedTiming t(timer, 0);
         const dim3 grid(next);
-        if (prec == 0) launch_inner_forms<double>(laws, grid, stream, prm, stride);
-        else launch_inner_forms<float>(laws, grid, stream, prm, stride);
+        if (prec == 0) launch_inner_forms<double>(laws, grid, stream, prm, stride, index_word32);
+        else launch_inner_forms<float>(laws, grid, stream, prm, stride, index_word32);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -65,10 +65,12 @@ struct StreamKeys {
 size_t inner_partials_capacity();  // Moments slots needed in workspace
 // One launch over every level's range (pilot, extension or fixed mode), then a
 // fold of the workgroup partials into the running level states.
+// index_word32: four index draws per Philox call from 32-bit words (n a power
+// of two, uniform draws, no experiment laws: checked by the caller).
 hipError_t inner_levels_run(const LevelRange* ranges, int num_levels, int64_t n, const Law& x,
                             const Law& y, const TargetFunc& f, const IndexWeights& iw, int prec,
-                            const StreamKeys& keys, Moments* partials, Moments* level_state, hipStream_t stream,
-                            KernelTimer* timer);
+                            bool index_word32, const StreamKeys& keys, Moments* partials, Moments* level_state,
+                            hipStream_t stream, KernelTimer* timer);
 hipError_t inner_telescope(const Moments* level_state, int num_levels, double* out,
                            double* level_means, double* level_var, hipStream_t stream);
 

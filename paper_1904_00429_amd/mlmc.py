@@ -19,6 +19,7 @@ from ._lib import Dist, Levels, MLMCError, Problem, Report, Tuning, check, lib
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "fp8": 3}
 FLAG_SHARED_SAMPLES = 1
 FLAG_STRIDE_COUPLING = 8
+FLAG_INDEX_WORD32 = 16
 COUPLINGS = ("prefix", "stride")   # coarse draws: the first c_{l-1}, or every M-th (Sec. 3.1)
 FLAG_ADAPTIVE_LEVELS = 4
 SHARED_LEVEL_FIELD = 0xFF
@@ -132,7 +133,8 @@ class _LevelsHolder:
 
     def __init__(self, c, n_samples, rmse_target, pilot, seed, prec, shared, problem, max_total_draws,
                  func: Optional[Func] = None, adaptive: bool = False,
-                 index_weights: Optional[torch.Tensor] = None, coupling: str = "prefix"):
+                 index_weights: Optional[torch.Tensor] = None, coupling: str = "prefix",
+                 index_word32: bool = False):
         if prec not in PREC:
             raise ValueError(f"prec must be one of {sorted(PREC)}")
         if coupling not in COUPLINGS:
@@ -149,7 +151,8 @@ class _LevelsHolder:
         lv.seed = int(seed) & (2**64 - 1)
         lv.prec = PREC[prec]
         lv.flags = ((FLAG_SHARED_SAMPLES if shared else 0) | (FLAG_ADAPTIVE_LEVELS if adaptive else 0)
-                    | (FLAG_STRIDE_COUPLING if coupling == "stride" else 0))
+                    | (FLAG_STRIDE_COUPLING if coupling == "stride" else 0)
+                    | (FLAG_INDEX_WORD32 if index_word32 else 0))
         lv.problem = int(problem)
         f = func or Func()
         lv.func = int(f.kind)
@@ -221,13 +224,14 @@ def inner_product_estimate(n: int, x: Law, y: Law, c: Sequence[int],
                            workspace: Optional[torch.Tensor] = None,
                            out: Optional[torch.Tensor] = None, func: Optional[Func] = None,
                            adaptive: bool = False, index_weights: Optional[torch.Tensor] = None,
-                           coupling: str = "prefix") -> Result:
+                           coupling: str = "prefix", index_word32: bool = False) -> Result:
     """MLMC estimate of E[f(x^T y)] on the GPU (mlmc_inner_product_estimate;
     f = identity unless func is given; adaptive, index_weights and coupling
-    as for matmul_estimate)."""
+    as for matmul_estimate; index_word32: four index draws per Philox call
+    from 32-bit words, for power-of-two n)."""
     device = torch.device(device or "cuda")
     h = _LevelsHolder(c, n_samples, rmse_target, pilot, seed, prec, shared, problem, max_total_draws, func,
-                      adaptive, index_weights, coupling)
+                      adaptive, index_weights, coupling, index_word32)
     ws_bytes = int(lib().mlmc_inner_product_workspace_size(int(n), ctypes.byref(h.lv)))
     if ws_bytes == 0:
         raise MLMCError(1, "invalid problem: no workspace size")

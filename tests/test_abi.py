@@ -222,3 +222,29 @@ def test_experiment_laws_rejected_by_xi_star_and_mixed_batches(L):
     probs[1].A, probs[1].B = _dist(), _dist()
     st = L.mlmc_matmul_estimate_batched(2, probs, ctypes.byref(lv), None, 16, 1 << 40, None, None)
     assert st == 1 and b"every product or none" in L.mlmc_last_error()
+
+
+def test_index_word32_validated(L):
+    from paper_1904_00429_amd._lib import Problem
+    lv, keep = _levels([2, 4], [4, 4], prec=1)
+    lv.flags = 16
+    A = _dist(0, 0.5, 1.0)
+    # inner product: n must be a power of two
+    st = L.mlmc_inner_product_estimate(1000, ctypes.byref(A), ctypes.byref(A), ctypes.byref(lv), 8, None,
+                                       16, 1 << 40, None, None)
+    assert st == 1 and b"power-of-two" in L.mlmc_last_error()
+    # laws of the experiments
+    X, Y = _dist(3, 0.4, 0.02), _dist(4, 10.0, 0.05)
+    st = L.mlmc_inner_product_estimate(1024, ctypes.byref(X), ctypes.byref(Y), ctypes.byref(lv), 8, None,
+                                       16, 1 << 40, None, None)
+    assert st == 1
+    # weighted draws
+    lv.index_weights = 16
+    st = L.mlmc_inner_product_estimate(1024, ctypes.byref(A), ctypes.byref(A), ctypes.byref(lv), 8, None,
+                                       16, 1 << 40, None, None)
+    assert st == 1 and b"32-bit index words" in L.mlmc_last_error()
+    lv.index_weights = None
+    # matrix products
+    st = L.mlmc_matmul_estimate(4, 16, 3, ctypes.byref(A), ctypes.byref(A), ctypes.byref(lv), 8, None,
+                                16, 1 << 40, None, None)
+    assert st == 1 and b"32-bit index words" in L.mlmc_last_error()
