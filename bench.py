@@ -493,9 +493,10 @@ def cpu_baseline_experiment(wl, n_used, budget_s=6.0):
 
 def bench_experiments(args):
     """The experiments of Sec. 4 at the paper's sizes: adaptive L on M = 10
-    ladders, eps = 0.1 of the size of E[f] (from an untimed fixed-N reference
-    estimate; Sec. 4.1's N_l scaled by 1/20); estimates/s of each, with the
-    spread of the independent estimates as the observed RMSE."""
+    ladders, eps = 0.1 of the size of E[f] (the workloads' fixed estimate of
+    it; Sec. 4.1's N_l scaled by 1/20); estimates/s of each, with the spread
+    of the independent estimates as the observed RMSE and the mean over their
+    entries (every entry of E[f(AB)] is the same) as a check of the size."""
     import torch
     import paper_1904_00429_amd.mlmc as api
     from paper_1904_00429_amd import workloads
@@ -504,13 +505,7 @@ def bench_experiments(args):
     res = {}
     for wl in (workloads.EXP41_INNER, workloads.EXP42_MATMUL):
         A, B, f = _experiment_laws(wl)
-        print(f"[experiments] {wl.name}: reference", flush=True)
-        ref = _experiment_run(api, wl, A, B, f, "fp64" if wl.kind == "inner" else prec, dev, 10 ** 6,
-                              n_samples=wl.ref_n)
-        # every entry of E[f(AB)] is the same (the laws depend on the column j
-        # of A and row j of B only): the mean of the entries estimates it
-        size = abs(float(ref.Y.mean())) * math.sqrt(wl.m * wl.p)
-        eps = wl.rel_eps * size / math.sqrt(wl.n_scale)
+        size, eps = wl.size, wl.eps
         for i in range(args.warmup):
             _experiment_run(api, wl, A, B, f, prec, dev, 1000 + i, eps=eps)
         torch.cuda.synchronize()
@@ -521,12 +516,13 @@ def bench_experiments(args):
         sec = (time.perf_counter() - t0) / args.steps
         # observed RMSE: spread of the independent estimates around their mean
         ybar = sum(r.Y for r in runs) / len(runs)
+        size_obs = abs(float(ybar.mean())) * math.sqrt(wl.m * wl.p)
         spread = math.sqrt(sum(float(torch.linalg.norm(r.Y - ybar)) ** 2 for r in runs) / max(len(runs) - 1, 1))
         k_ms = [sum(r.kernel_ms[i] for r in runs) / args.steps for i in range(4)]
         k_n = [sum(r.kernel_launches[i] for r in runs) for i in range(4)]
         draws = sum(r.total_draws for r in runs) / args.steps
         entry = {"estimates_per_s": 1.0 / sec, "ms_per_estimate": 1e3 * sec, "eps": eps,
-                 "reference": {"norm": size, "rmse_est": ref.rmse_est, "n_samples": wl.ref_n},
+                 "size": size, "size_from_these_estimates": size_obs,
                  "levels_used": [r.levels_used for r in runs],
                  "bias_test_passed": [r.bias_test_passed for r in runs],
                  "n_used": runs[-1].n_used, "rmse_est": runs[-1].rmse_est, "draws_per_estimate": draws,
