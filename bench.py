@@ -506,12 +506,14 @@ def bench_experiments(args):
     for wl in (workloads.EXP41_INNER, workloads.EXP42_MATMUL):
         A, B, f = _experiment_laws(wl)
         size, eps = wl.size, wl.eps
+        # the inner product computes in FP64 or FP32
+        wprec = prec if wl.kind == "matmul" or prec in ("fp32", "fp64") else "fp32"
         for i in range(args.warmup):
-            _experiment_run(api, wl, A, B, f, prec, dev, 1000 + i, eps=eps)
+            _experiment_run(api, wl, A, B, f, wprec, dev, 1000 + i, eps=eps)
         torch.cuda.synchronize()
         print(f"[experiments] {wl.name}: timing", flush=True)
         t0 = time.perf_counter()
-        runs = [_experiment_run(api, wl, A, B, f, prec, dev, i, eps=eps, timing=True) for i in range(args.steps)]
+        runs = [_experiment_run(api, wl, A, B, f, wprec, dev, i, eps=eps, timing=True) for i in range(args.steps)]
         torch.cuda.synchronize()
         sec = (time.perf_counter() - t0) / args.steps
         # observed RMSE: spread of the independent estimates around their mean

@@ -432,8 +432,9 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
 
 // The laws of the experiments of Sec. 4: every element is a Philox call and
 // an FP64 evaluation of its own (experiment_value), so the block's lanes walk
-// its (position, row) items row-fastest, one element each, and store it into
-// the same layouts as gather_kernel.  Not offered with FP8 operands.
+// its (position, row) items row-fastest, one element each (a wave then shares
+// one position: all of its lanes generate values, or all store padding), and
+// store them into the same layouts as gather_kernel.  Not offered with FP8.
 template <typename Compute, typename Store, int KPACK>
 __global__ __launch_bounds__(kGatherThreads) void gather_experiment_kernel(GatherParams prm)
 {
@@ -556,7 +557,10 @@ struct SketchShape {
 // STATS: 0 Welford; 1 sums shifted by E[D] (i.i.d. laws); 2 the same for
 // products that fill whole tiles (no masking code); 3 (whole tiles, short
 // realisations) a second accumulator collects every realisation's sum
-// through the same MFMAs, so a realisation costs one fma per entry.
+// through the same MFMAs, so a realisation costs one fma per entry; 4 and 5
+// a target function f of kind 1 and 2 (fixed at compile time, so only its
+// own arithmetic is emitted per entry); 6 and 7 the same at level 0, which
+// has no coarse sketch (no copied accumulators, fewer registers).
 template <typename P, int WR, int WC, int NBR, int NBC, int PF, int WPE, int STATS>
 __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchParams prm)
 {
@@ -646,11 +650,13 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
         // outside the product see zero-padded operand rows: D = 0 there, and
         // the shift is not applied to them.
         constexpr bool DUAL = STATS == 3;
-        // STATS 4: a target function f.  The accumulator is copied when the
+        // STATS 4, 5: a target function f.  The accumulator is copied when the
         // coarse draws are done (the gathered a_t are unweighted), and the
         // level sample of every entry is f(n / c_l acc) - f(n / c_{l-1} snap),
         // or f(n / c_0 acc) at level 0, into Welford's mean and M2.
-        constexpr bool FUNC = STATS == 4;
+        constexpr bool FUNC = STATS >= 4;
+        constexpr int fkind = FUNC ? (STATS - 4) % 2 + 1 : 0;
+        constexpr bool FUNC_COARSE = STATS == 4 || STATS == 5;   // levels above 0
         Acc run[DUAL ? 1 : NE];
 #pragma unroll
         for (int e = 0; e < (DUAL ? 1 : NE); ++e) run[e] = (Acc)0;
@@ -663,10 +669,9 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
 #pragma unroll
                     for (int r = 0; r < P::REGS; ++r) tot[bi][bj][r] = (Acc)0;
         }
-        typename P::AccVec snap[FUNC ? NBR : 1][FUNC ? NBC : 1];
-        const bool has_coarse = prm.c_prev > 0u;
+        typename P::AccVec snap[FUNC_COARSE ? NBR : 1][FUNC_COARSE ? NBC : 1];
+        const bool has_coarse = FUNC_COARSE && prm.c_prev > 0u;
         const Acc scale_c = (Acc)(has_coarse ? (double)Pd.n / (double)prm.c_prev * Pd.post : 0.0);
-        const int fkind = prm.func.kind;
         const Acc th0 = (Acc)prm.func.theta0, th1 = (Acc)prm.func.theta1;
         double m2_sum = 0.0;
         Acc count = (Acc)0;
@@ -767,7 +772,8 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
                             Acc d;
                             if constexpr (FUNC) {
                                 d = target_value(fkind, scale * acc[bi][bj][r], th0, th1);
-                                if (has_coarse) d -= target_value(fkind, scale_c * snap[bi][bj][r], th0, th1);
+                                if constexpr (FUNC_COARSE)
+                                    if (has_coarse) d -= target_value(fkind, scale_c * snap[bi][bj][r], th0, th1);
                             } else {
                                 d = scale * acc[bi][bj][r];
                             }
@@ -812,7 +818,7 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
                 for (int i = 0; i < run_steps; ++i) step(LA, LB, (st + i) * P::KSTEP);
                 st += run_steps;
                 o += run_steps * P::KSTEP;
-                if constexpr (FUNC) {
+                if constexpr (FUNC_COARSE) {
                     if (kc > 0 && o == kc) {
 #pragma unroll
                         for (int bi = 0; bi < NBR; ++bi)
@@ -1341,10 +1347,19 @@ static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t
         constexpr bool kFuncForm = NBR * NBC * P::REGS <= 16;   // the layouts a target function uses
         if (plan.func.kind != 0) {
             // the copied accumulators need more than 128 registers: two waves per SIMD
-            if constexpr (kFuncForm)
-                hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, (WPE > 2 ? 2 : WPE), 4>), grid, block, 0,
-                                   stream, s);
-            else
+            if constexpr (kFuncForm) {
+                // level 0 (no coarse sketch): the statistics fit the full occupancy
+                if (lr.c_prev == 0 && plan.func.kind == 1)
+                    hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, WPE, 6>), grid, block, 0, stream, s);
+                else if (lr.c_prev == 0)
+                    hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, WPE, 7>), grid, block, 0, stream, s);
+                else if (plan.func.kind == 1)
+                    hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, (WPE > 2 ? 2 : WPE), 4>), grid, block,
+                                       0, stream, s);
+                else
+                    hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, (WPE > 2 ? 2 : WPE), 5>), grid, block,
+                                       0, stream, s);
+            } else
                 return hipErrorInvalidConfiguration;   // matmul_plan picks tile 64 for a target function
         } else if (plan.iid && plan.whole_tiles && kDualForm && lr.c <= kDualMaxDraws)
             hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, WPE, kDualForm ? 3 : 0>), grid, block, 0,
