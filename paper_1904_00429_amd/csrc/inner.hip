@@ -1,4 +1,4 @@
-// Inner-product level sampling (Sec. 2; Alg. 1 with m = p = 1, f = identity).
+// Inner-product level sampling (Sec. 2; Alg. 1 with m = p = 1).
 //
 // A level sample of realisation k is
 //   D_k = (n / c) * ( (1 - c / c_prev) * sum_{t < c_prev} x_{r_t} y_{r_t}
@@ -8,16 +8,21 @@
 // sketch alone.  Nothing is read from memory except reparameterised
 // means/scales: indices and values are regenerated from the counter-based
 // stream, so the kernel is bound by VALU issue (Philox is 90% of the work).
+// Separate instantiations (template flags, so the plain kernel is unchanged)
+// give the other forms: a target function f (FN: f of both sketches), weighted
+// index draws (IW: per-draw factor 1 / (n xi_j)), the stride coupling (ST: the
+// coarse draws are every M-th draw) and 32-bit index words (W32).
 //
 // One launch covers every level of a phase (the pilot, or the extension):
 // workgroups are dealt to levels in proportion to each level's draw count, so
 // the whole GPU works on all levels at once and no level runs a grid too small
 // to fill the chip.  Inside a level, a group of G lanes (a power of two, up to
 // the whole 256-lane workgroup) owns one realisation at a time; its lanes take
-// draw pairs (2q, 2q+1), which share one Philox call of the index stream.  G
-// is chosen so every lane gets at least eight pairs, which amortises the
-// per-realisation reduction (a butterfly of cross-lane shuffles, plus an LDS
-// step when the group spans several waves).
+// draw pairs (2q, 2q+1), which share one Philox call of the index stream (with
+// 32-bit index words, draw quads 4g .. 4g+3 share one call).  G is chosen so
+// every lane gets at least eight pairs, which amortises the per-realisation
+// reduction (a butterfly of cross-lane shuffles, plus an LDS step when the
+// group spans several waves).
 //
 // Statistics: every lane of a group holds D_k after the reduction and updates
 // FP64 sums shifted by the group's first sample K (n, S1 = sum (D - K),

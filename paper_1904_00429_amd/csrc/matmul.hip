@@ -1,5 +1,10 @@
-// Matrix-product MLMC pipeline (Sec. 3; Alg. 1 per level, f = identity) over
-// a table of independent products (one product is the one-entry table).
+// Matrix-product MLMC pipeline (Sec. 3; Alg. 1 per level) over a table of
+// independent products (one product is the one-entry table).  Described for
+// f = identity and the prefix coupling; a target function f keeps the coarse
+// sum apart (the accumulator is copied where the coarse draws end), weighted
+// draws scale a_t by 1 / (n xi_j), the stride coupling places the draws
+// M - 1, 2M - 1, ... in the coarse segment, and the laws of Sec. 4 have a
+// gather of their own.
 //
 // Per pass over a batch of S realisations of one level l (every product of
 // the table shares the ladder and N_l; each has its own shape, law and
