@@ -30,7 +30,9 @@ Parity pins and where they are tested (``tests/test_oracle_*.py``):
                      force over index tuples, closed-form V_l by z-test;
   32-bit index words top bits of the rocRAND-pinned Philox words for
                      power-of-two n, exact integers, chi-square, closed-form
-                     V_l of the inner product by z-test.
+                     V_l of the inner product by z-test;
+  16-bit values      the halves of the rocRAND-pinned words, the Box-Muller
+                     identities, moments, closed-form V_l by z-test.
 """
 from __future__ import annotations
 
@@ -72,7 +74,7 @@ class _Law(ctypes.Structure):
     _fields_ = [("law", ctypes.c_int32), ("loc", ctypes.c_double),
                 ("scale", ctypes.c_double), ("mean", ctypes.c_void_p),
                 ("stdev", ctypes.c_void_p), ("ld", ctypes.c_int64),
-                ("exp_neg_loc", ctypes.c_double)]
+                ("exp_neg_loc", ctypes.c_double), ("value16", ctypes.c_int32)]
 
 
 class _Weights(ctypes.Structure):
@@ -155,6 +157,7 @@ class Law:
     mean: Optional[np.ndarray] = None
     stdev: Optional[np.ndarray] = None
     ld: int = 0
+    value16: bool = False     # laws 0-2: 16-bit uniforms, eight per Philox call
     _keep: list = field(default_factory=list, repr=False)
 
     @staticmethod
@@ -175,12 +178,20 @@ class Law:
         return Law(LAW_REPARAM, 0.0, 0.0, np.ascontiguousarray(mean, dtype=np.float64),
                    np.ascontiguousarray(stdev, dtype=np.float64), int(ld))
 
+    def with_value16(self) -> "Law":
+        """The same law with values from 16-bit uniforms: element e of column
+        j takes the low (even e) or high (odd e) half h of word (e/2) % 4 of
+        the call (e/8, k, j, value stream), u = (h + 1/2) 2^-16; normals by
+        Box-Muller on the pair (e & ~1, e | 1), which shares one word."""
+        return Law(self.law, self.loc, self.scale, self.mean, self.stdev, self.ld, True)
+
     def c(self) -> _Law:
         s = _Law()
         s.law = self.law
         s.loc = self.loc
         s.scale = self.scale
         s.exp_neg_loc = math.exp(-self.loc) if self.law in (LAW_COS_POISSON_EXP, LAW_COS_POISSON_STEP) else 0.0
+        s.value16 = 1 if self.value16 else 0
         if self.law == LAW_REPARAM:
             s.mean = _ptr(self.mean)
             s.stdev = _ptr(self.stdev)

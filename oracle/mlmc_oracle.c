@@ -37,6 +37,9 @@
  *     z_e = sqrt(-2 ln u_e) cos(2 pi u_{e+1}), z_{e+1} = ... sin(...).
  *     Values are keyed by the column, so a repeated index reuses the same
  *     column of the same realisation A^(k), B^(k) (Alg. 1 draws the pair first).
+ *   - Optional 16-bit uniforms for the laws normal, uniform and reparam
+ *     (orc_law.value16): element e uses half (e & 1) of word (e/2) % 4 of the
+ *     call (e/8, k, j, 2<<28 | level<<20 | problem), eight per call.
  *   - Optional non-uniform probabilities xi_j = w_j / W from integer weights
  *     (eq. (18) with a general xi; Theorem 3.1's xi** quantised, see
  *     orc_optimal_weights): the same 64-bit word x gives T = floor(x W / 2^64)
@@ -92,6 +95,7 @@ typedef struct {
     const double* stdev;
     int64_t ld;
     double exp_neg_loc;
+    int32_t value16;   /* laws 0-2: 16-bit uniforms, two per 32-bit word (see value_uniform16) */
 } orc_law;
 
 /* Target function f of Sec. 3, applied entrywise to a sketch.
@@ -297,14 +301,37 @@ static uint32_t value_word(uint64_t seed, uint32_t problem, uint32_t level_field
     return w[e & 3];
 }
 
-/* Standard normal number e of the vector of column j (Box-Muller). */
-static double std_normal(uint64_t seed, uint32_t problem, uint32_t level_field,
-                         uint32_t k, int64_t j, int64_t e)
+/* 16-bit uniforms: element e of column j uses the call (e/8, k, j, value
+ * stream) and, of its word (e/2) % 4, the low half for even e and the high
+ * half for odd e: u = (h + 1/2) 2^-16, eight uniforms per call. */
+static double value_uniform16(uint64_t seed, uint32_t problem, uint32_t level_field,
+                              uint32_t k, int64_t j, int64_t e)
+{
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    uint32_t ctr[4] = { (uint32_t)(e >> 3), k, (uint32_t)j,
+                        stream_word(ORC_TAG_VALUE, level_field, problem) };
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+    uint32_t word = w[(e >> 1) & 3];
+    uint32_t h = (e & 1) ? (word >> 16) : (word & 0xFFFFu);
+    return ((double)h + 0.5) * 0x1p-16;
+}
+
+/* Standard normal number e of the vector of column j (Box-Muller on the
+ * uniforms of elements e & ~1 and e | 1). */
+static double std_normal_mode(uint64_t seed, uint32_t problem, uint32_t level_field,
+                              uint32_t k, int64_t j, int64_t e, int32_t value16)
 {
     const double two_pi = 6.283185307179586476925286766559;
     int64_t e0 = e & ~(int64_t)1;
-    double u1 = orc_uniform(value_word(seed, problem, level_field, k, j, e0));
-    double u2 = orc_uniform(value_word(seed, problem, level_field, k, j, e0 + 1));
+    double u1, u2;
+    if (value16) {
+        u1 = value_uniform16(seed, problem, level_field, k, j, e0);
+        u2 = value_uniform16(seed, problem, level_field, k, j, e0 + 1);
+    } else {
+        u1 = orc_uniform(value_word(seed, problem, level_field, k, j, e0));
+        u2 = orc_uniform(value_word(seed, problem, level_field, k, j, e0 + 1));
+    }
     double radius = sqrt(-2.0 * log(u1));
     double angle = two_pi * u2;
     return (e & 1) ? radius * sin(angle) : radius * cos(angle);
@@ -365,10 +392,11 @@ static double law_value(const orc_law* law, uint64_t seed, uint32_t problem,
     if (law->law >= ORC_LAW_RAMP_NORMAL)
         return experiment_value(law, seed, problem, level_field, k, j, e);
     if (law->law == ORC_LAW_UNIFORM) {
-        double u = orc_uniform(value_word(seed, problem, level_field, k, j, e));
+        double u = law->value16 ? value_uniform16(seed, problem, level_field, k, j, e)
+                                : orc_uniform(value_word(seed, problem, level_field, k, j, e));
         return law->loc + law->scale * (2.0 * u - 1.0);
     }
-    double z = std_normal(seed, problem, level_field, k, j, e);
+    double z = std_normal_mode(seed, problem, level_field, k, j, e, law->value16);
     if (law->law == ORC_LAW_REPARAM)
         return law->mean[mat_index] + law->stdev[mat_index] * z;
     return law->loc + law->scale * z;
