@@ -85,6 +85,8 @@ def parse():
     ap.add_argument("--index-words", type=int, default=32, choices=[32, 64],
                     help="inner product: index draws from 32-bit words (four per Philox call, power-of-two n) "
                          "or 64-bit words (two per call)")
+    ap.add_argument("--value-bits", type=int, default=23, choices=[16, 23],
+                    help="matrix workloads: uniforms of the generated values (16: eight per Philox call)")
     ap.add_argument("--adaptive", action="store_true",
                     help="choose the number of levels by the bias test (the workload's ladder is the longest)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -174,6 +176,7 @@ def main():
     _OPTS["adaptive"] = bool(args.adaptive)
     args.index_word32 = args.workload == "inner" and args.index_words == 32
     _OPTS["index_word32"] = args.index_word32
+    _OPTS["value16"] = args.value_bits == 16 and args.workload != "inner"
     if args.workload == "diff":
         return bench_diff(args)
     if args.workload == "batched":
@@ -252,7 +255,7 @@ def main():
                 "merge_ms_per_step": k_ms[2] / args.steps}
         config = {"workload": wl.name, "m": wl.m, "n": wl.n, "p": wl.p, "levels": len(wl.c), "c0": wl.c[0],
                   "ratio": 2, "eps": wl.rmse_target, "pilot": wl.pilot, "prec": prec, "func": args.func,
-                  "adaptive": bool(args.adaptive)}
+                  "adaptive": bool(args.adaptive), "value_bits": 16 if _OPTS.get("value16") else 23}
 
     out = {"metric": METRIC, "value": value, "unit": "estimates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
@@ -270,7 +273,8 @@ def main():
         ys = {}
         for pr in (prec, "fp64"):
             ys[pr] = matmul_estimate(wl.m, wl.n, wl.p, a, a, wl.c, n_samples=rep.n_used, seed=0, prec=pr,
-                                     device=dev, report=True, func=_OPTS["func"])
+                                     device=dev, report=True, func=_OPTS["func"],
+                                     value16=_OPTS.get("value16", False))
         out["precision_check"] = {
             "lp_minus_fp64_frob": float(torch.linalg.norm(ys[prec].Y - ys["fp64"].Y)),
             "rmse_est_fp64": ys["fp64"].rmse_est, "seed": 0, "n_samples": rep.n_used}
@@ -589,7 +593,8 @@ def bench_batched(args):
     out = {}
     for prec in ("fp8", "fp32"):
         best = autotune.tune(probs, c, N, prec=prec, device=dev)
-        est = BatchedEstimate(probs, c, N, seed=0, prec=prec, tuning=best, device=dev)
+        est = BatchedEstimate(probs, c, N, seed=0, prec=prec, tuning=best, device=dev,
+                              value16=_OPTS.get("value16", False))
         est.capture()
         sec = _time_replays(est, args.steps, args.warmup)
         out[prec] = {"s_per_estimate": sec, "tuning": best, "mfma_tflops_whole_graph": flops / sec / 1e12}
@@ -602,7 +607,7 @@ def bench_batched(args):
            "ms_per_step": 1e3 * out["fp8"]["s_per_estimate"], "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "fp8", "data": "synthetic",
            "config": {"workload": "batched-256-uneven", "products": len(shapes), "c0": c[0], "levels": len(c),
-                      "N": N, "graph": True},
+                      "N": N, "graph": True, "value_bits": 16 if _OPTS.get("value16") else 23},
            "products_per_s": len(shapes) * value,
            "fp32_value": 1.0 / out["fp32"]["s_per_estimate"],
            "fp8_over_fp32": out["fp32"]["s_per_estimate"] / out["fp8"]["s_per_estimate"],
@@ -687,7 +692,7 @@ def _matmul(api, wl, a, prec, dev, want_timing, seed):
     import torch
     h = api._LevelsHolder(wl.c, wl.n_samples, wl.rmse_target if wl.n_samples is None else 0.0,
                           wl.pilot, seed, prec, False, 0, 0, _OPTS["func"],
-                          _OPTS["adaptive"] and wl.n_samples is None)
+                          _OPTS["adaptive"] and wl.n_samples is None, value16=_OPTS.get("value16", False))
     if want_timing:
         h.lv.flags |= 2
     lib = api.lib()

@@ -125,6 +125,15 @@ typedef enum {
  * the estimates differ realisation by realisation (not in law).  EINVAL
  * otherwise. */
 #define MLMC_FLAG_INDEX_WORD32 16u
+/* Values from 16-bit uniforms (matrix products, batched included; laws 0-2;
+ * not the adjoint): element e of column j takes half (e & 1: high, else
+ * low) of word (e / 2) % 4 of the value-stream call (e / 8, k, j,
+ * 2 << 28 | level << 20 | problem), u = (h + 1/2) 2^-16, so one Philox call
+ * gives eight values instead of four; normals by Box-Muller on the two halves
+ * of a word (pairs (e & ~1, e | 1) as in the default stream).  The normal is
+ * then truncated at 4.85 standard deviations (variance low by about 1e-5
+ * relative, mean exact by symmetry).  EINVAL otherwise. */
+#define MLMC_FLAG_VALUE16 32u
 #define MLMC_MAX_LEVELS 32
 
 /* Kernel classes of mlmc_report.kernel_ms (MLMC_FLAG_TIMING). */

@@ -67,6 +67,8 @@ mlmc_status check_levels(const mlmc_levels* lv, bool inner)
     if (lv->max_total_draws < 0) return fail(MLMC_EINVAL, "max_total_draws must be >= 0");
     if (lv->index_weights && lv->prec == MLMC_PREC_FP8)
         return fail(MLMC_EINVAL, "weighted index draws are not offered with FP8 operands");
+    if ((lv->flags & MLMC_FLAG_VALUE16) && inner)
+        return fail(MLMC_EINVAL, "16-bit value uniforms are offered for matrix products");
     if ((lv->flags & MLMC_FLAG_INDEX_WORD32) && (!inner || lv->index_weights))
         return fail(MLMC_EINVAL, "32-bit index words are offered for uniform draws of the inner product");
     if ((lv->flags & MLMC_FLAG_ADAPTIVE_LEVELS) && !(lv->rmse_target > 0.0))
@@ -102,11 +104,13 @@ mlmc_status check_dist(const mlmc_dist* d, const char* name, int64_t min_ld, boo
 
 // The laws of Sec. 4 pair only with each other (their gather is a kernel of
 // its own) and are not offered with FP8 operands.
-mlmc_status check_pair(const mlmc_dist* a, const mlmc_dist* b, int32_t prec)
+mlmc_status check_pair(const mlmc_dist* a, const mlmc_dist* b, int32_t prec, uint32_t flags = 0)
 {
     const bool ea = a->law >= MLMC_LAW_RAMP_NORMAL, eb = b->law >= MLMC_LAW_RAMP_NORMAL;
     if (ea != eb) return fail(MLMC_EINVAL, "the laws of the experiments pair only with each other");
     if (ea && prec == MLMC_PREC_FP8) return fail(MLMC_EINVAL, "the laws of the experiments are not offered with FP8");
+    if (ea && (flags & MLMC_FLAG_VALUE16))
+        return fail(MLMC_EINVAL, "the laws of the experiments have their own stream (no 16-bit values)");
     return MLMC_OK;
 }
 
@@ -430,12 +434,13 @@ mlmc_status mlmc_matmul_estimate(int64_t m, int64_t n, int64_t p, const mlmc_dis
     if (st != MLMC_OK) return st;
     if ((st = check_dist(A, "A", m, false)) != MLMC_OK) return st;
     if ((st = check_dist(B, "B", p, false)) != MLMC_OK) return st;
-    if ((st = check_pair(A, B, lv->prec)) != MLMC_OK) return st;
+    if ((st = check_pair(A, B, lv->prec, lv->flags)) != MLMC_OK) return st;
     if (!out) return fail(MLMC_EINVAL, "out is NULL");
     MatmulProblem pr{m, n, p, to_law(*A), to_law(*B), lv->problem, out, level_means};
     MatmulPlan plan;
     if (!matmul_plan(&pr, 1, lv->prec, lv->num_levels, lv->c, nullptr, func_of(lv), lv->index_weights, plan))
         return fail(MLMC_EINVAL, "no launch plan for this shape and precision");
+    plan.value16 = (lv->flags & MLMC_FLAG_VALUE16) != 0;
     if (!workspace || workspace_bytes < plan.total)
         return fail(MLMC_EWORKSPACE, "workspace needs %zu bytes", plan.total);
     hipStream_t stream = static_cast<hipStream_t>(stream_ptr);
@@ -558,7 +563,7 @@ mlmc_status check_batch(int32_t nprob, const mlmc_problem* probs, const mlmc_lev
             return fail(MLMC_EINVAL, "problem %d: m, p >= 1 and 1 <= n < 2^32 required", i);
         if ((st = check_dist(&pr.A, "A", pr.m, false)) != MLMC_OK) return st;
         if ((st = check_dist(&pr.B, "B", pr.p, false)) != MLMC_OK) return st;
-        if ((st = check_pair(&pr.A, &pr.B, lv->prec)) != MLMC_OK) return st;
+        if ((st = check_pair(&pr.A, &pr.B, lv->prec, lv->flags)) != MLMC_OK) return st;
         if ((pr.A.law >= MLMC_LAW_RAMP_NORMAL) != (probs[0].A.law >= MLMC_LAW_RAMP_NORMAL))
             return fail(MLMC_EINVAL, "problem %d: the laws of the experiments are used by every product or none", i);
         if (!pr.out) return fail(MLMC_EINVAL, "problem %d: out is NULL", i);
@@ -630,6 +635,7 @@ mlmc_status mlmc_matmul_estimate_batched(int32_t nprob, const mlmc_problem* prob
     MatmulPlan plan;
     if (!matmul_plan(pr.data(), nprob, lv->prec, lv->num_levels, lv->c, &tune, func_of(lv), nullptr, plan))
         return fail(MLMC_EINVAL, "no launch plan for this table");
+    plan.value16 = (lv->flags & MLMC_FLAG_VALUE16) != 0;
     if (!workspace || workspace_bytes < plan.total)
         return fail(MLMC_EWORKSPACE, "workspace needs %zu bytes", plan.total);
     hipStream_t stream = static_cast<hipStream_t>(stream_ptr);
@@ -661,6 +667,7 @@ mlmc_status mlmc_matmul_batched_graph_create(int32_t nprob, const mlmc_problem* 
     MatmulPlan plan;
     if (!matmul_plan(pr.data(), nprob, lv->prec, lv->num_levels, lv->c, &tune, func_of(lv), nullptr, plan))
         return fail(MLMC_EINVAL, "no launch plan for this table");
+    plan.value16 = (lv->flags & MLMC_FLAG_VALUE16) != 0;
     if (!workspace || workspace_bytes < plan.total)
         return fail(MLMC_EWORKSPACE, "workspace needs %zu bytes", plan.total);
     hipStream_t stream = static_cast<hipStream_t>(stream_ptr);
@@ -733,6 +740,7 @@ mlmc_status mlmc_matmul_adjoint_reparam(int64_t m, int64_t n, int64_t p, const m
     if ((st = check_dist(B, "B", p, false)) != MLMC_OK) return st;
     if (A->law != MLMC_LAW_REPARAM || B->law != MLMC_LAW_REPARAM)
         return fail(MLMC_EINVAL, "the adjoint is defined for reparameterised laws");
+    if (lv->flags & MLMC_FLAG_VALUE16) return fail(MLMC_EINVAL, "the adjoint regenerates 23-bit values only");
     if (!grad_out || !dMA || !dSA || !dMB || !dSB) return fail(MLMC_EINVAL, "null gradient pointer");
     const size_t need = adjoint_workspace_size(m, n, p, lv->num_levels, lv->c, lv->index_weights != nullptr);
     if (!workspace || workspace_bytes < need) return fail(MLMC_EWORKSPACE, "workspace needs %zu bytes", need);

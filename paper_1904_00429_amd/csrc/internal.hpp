@@ -118,6 +118,7 @@ struct MatmulPlan {
     const uint32_t* index_weights;   // NULL: uniform draws
     size_t off_cum;                  // the cumulative weights (n uint64) when index_weights is set
     bool iid;                  // no product has a reparameterised law
+    bool value16 = false;      // values from 16-bit uniforms (eight per Philox call)
     bool whole_tiles;          // every m and p is a multiple of the workgroup tile
     int64_t min_rows;          // smallest m + p over the products
     int64_t kpad_max;

@@ -261,7 +261,9 @@ __device__ __forceinline__ void zero_padding_rows(const GatherParams& prm, int64
 // A block covers prm.octets groups of 8 consecutive padded positions of one
 // realisation of one product; its lanes walk the (octet, quad of 4 rows)
 // items, so a product with few rows still keeps every lane busy.
-template <typename Compute, typename Store, int KPACK, int LAWS>
+// V16: values from 16-bit uniforms, eight per Philox call (rows 8h .. 8h+7 per
+// lane item instead of 4q .. 4q+3).
+template <typename Compute, typename Store, int KPACK, int LAWS, bool V16>
 __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm)
 {
     constexpr int MAXPOS = kGatherPositions * kGatherMaxOctets;
@@ -314,49 +316,40 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
     // for t < c_{l-1}, 1 otherwise).
     const Compute omega = (Compute)prm.omega;
     // values of rows 4q .. 4q+3 at the 8 positions of group oc
-    auto generate = [&](uint32_t oc, int64_t q, const uint32_t* jv, const bool* ok) {
-        const Compute* fv = colf + oc * kGatherPositions;
-        const int64_t pos0 = pos_base + (int64_t)oc * kGatherPositions;
-        const int npos = (int)((prm.kpad - pos0) < kGatherPositions ? (prm.kpad - pos0) : kGatherPositions);
-        Val vals[kGatherPositions][4];
+    // Values of rows 4q .. 4q+3 of position ip (column j, a_t weight wa)
+    // from their uniforms u and normals z.
+    auto values4 = [&](int64_t q, uint32_t j, Compute wa, const Compute* u, const Compute* z, Val* out) {
         const int64_t e0 = 4 * q;
+        if (e0 + 3 < m) {            // the whole quad is in A's column
 #pragma unroll
-        for (int ip = 0; ip < kGatherPositions; ++ip) {
-            if (!ok[ip]) {
+            for (int r = 0; r < 4; ++r)
+                out[r] = to_val(wa * LA.template eval<LAWS>(z[r], u[r], (int64_t)j * LA.ld + e0 + r), pre_a);
+        } else if (e0 >= m) {        // the whole quad is in B's row
 #pragma unroll
-                for (int r = 0; r < 4; ++r) vals[ip][r] = to_val((Compute)0, 1.0f);
-                continue;
-            }
-            const uint32_t j = jv[ip];
-            const Compute wa = (pos0 + ip < prm.kc ? omega : (Compute)1) * fv[ip];
-            const Words4 w = philox4x32_10((uint32_t)q, k, j, sid_value, prm.key0, prm.key1);
-            Compute u[4], z[4];
-            quad_values<Compute>(w, normal, u[0], u[1], u[2], u[3], z[0], z[1], z[2], z[3]);
-            if (e0 + 3 < m) {            // the whole quad is in A's column
+            for (int r = 0; r < 4; ++r)
+                out[r] = to_val(LB.template eval<LAWS>(z[r], u[r], (int64_t)j * LB.ld + (e0 + r - m)), pre_b);
+        } else {
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    vals[ip][r] = to_val(wa * LA.template eval<LAWS>(z[r], u[r], (int64_t)j * LA.ld + e0 + r), pre_a);
-            } else if (e0 >= m) {        // the whole quad is in B's row
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    vals[ip][r] = to_val(LB.template eval<LAWS>(z[r], u[r], (int64_t)j * LB.ld + (e0 + r - m)), pre_b);
-            } else {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int64_t e = e0 + r;
-                    Compute v = (Compute)0;
-                    float pre = 1.0f;
-                    if (e < m) {
-                        v = wa * LA.template eval<LAWS>(z[r], u[r], (int64_t)j * LA.ld + e);
-                        pre = pre_a;
-                    } else if (e < rows) {
-                        v = LB.template eval<LAWS>(z[r], u[r], (int64_t)j * LB.ld + (e - m));
-                        pre = pre_b;
-                    }
-                    vals[ip][r] = to_val(v, pre);
+            for (int r = 0; r < 4; ++r) {
+                const int64_t e = e0 + r;
+                Compute v = (Compute)0;
+                float pre = 1.0f;
+                if (e < m) {
+                    v = wa * LA.template eval<LAWS>(z[r], u[r], (int64_t)j * LA.ld + e);
+                    pre = pre_a;
+                } else if (e < rows) {
+                    v = LB.template eval<LAWS>(z[r], u[r], (int64_t)j * LB.ld + (e - m));
+                    pre = pre_b;
                 }
+                out[r] = to_val(v, pre);
             }
         }
+    };
+    // Stores of rows 4q .. 4q+3 at the 8 positions of group oc.
+    auto store4 = [&](uint32_t oc, int64_t q, Val (&vals)[kGatherPositions][4]) {
+        const int64_t pos0 = pos_base + (int64_t)oc * kGatherPositions;
+        const int npos = (int)((prm.kpad - pos0) < kGatherPositions ? (prm.kpad - pos0) : kGatherPositions);
+        const int64_t e0 = 4 * q;
         if constexpr (KPACK == 1) {
             // rows 4q .. 4q+3 of one position are adjacent: one vector store
             // per position when the quad lies in A, or in B at an aligned row
@@ -409,6 +402,61 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
             }
         }
     };
+    // values of rows 4q .. 4q+3 at the 8 positions of group oc: one
+    // value-stream call per position (23-bit uniforms, four per call)
+    auto generate = [&](uint32_t oc, int64_t q, const uint32_t* jv, const bool* ok) {
+        const Compute* fv = colf + oc * kGatherPositions;
+        const int64_t pos0 = pos_base + (int64_t)oc * kGatherPositions;
+        Val vals[kGatherPositions][4];
+#pragma unroll
+        for (int ip = 0; ip < kGatherPositions; ++ip) {
+            if (!ok[ip]) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) vals[ip][r] = to_val((Compute)0, 1.0f);
+                continue;
+            }
+            const uint32_t j = jv[ip];
+            const Compute wa = (pos0 + ip < prm.kc ? omega : (Compute)1) * fv[ip];
+            const Words4 w = philox4x32_10((uint32_t)q, k, j, sid_value, prm.key0, prm.key1);
+            Compute u[4], z[4];
+            quad_values<Compute>(w, normal, u[0], u[1], u[2], u[3], z[0], z[1], z[2], z[3]);
+            values4(q, j, wa, u, z, vals[ip]);
+        }
+        store4(oc, q, vals);
+    };
+    // V16: rows 8h .. 8h+7 (quads 2h and 2h+1) from one call per position,
+    // whose four words give eight 16-bit uniforms (element 8h + 2i + b takes
+    // half b of word i); normals by Box-Muller on the two halves of a word
+    auto generate16 = [&](uint32_t oc, int64_t h, const uint32_t* jv, const bool* ok) {
+        const Compute* fv = colf + oc * kGatherPositions;
+        const int64_t pos0 = pos_base + (int64_t)oc * kGatherPositions;
+        const bool second = 2 * h + 1 < (int64_t)quads;
+        Val lo[kGatherPositions][4], hi[kGatherPositions][4];
+#pragma unroll
+        for (int ip = 0; ip < kGatherPositions; ++ip) {
+            if (!ok[ip]) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) lo[ip][r] = hi[ip][r] = to_val((Compute)0, 1.0f);
+                continue;
+            }
+            const uint32_t j = jv[ip];
+            const Compute wa = (pos0 + ip < prm.kc ? omega : (Compute)1) * fv[ip];
+            const Words4 w = philox4x32_10((uint32_t)h, k, j, sid_value, prm.key0, prm.key1);
+            const uint32_t wd[4] = {w.w0, w.w1, w.w2, w.w3};
+            Compute u[8], z[8];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                u[2 * i] = unit16<Compute>(wd[i] & 0xFFFFu);
+                u[2 * i + 1] = unit16<Compute>(wd[i] >> 16);
+                if (normal) box_muller(u[2 * i], u[2 * i + 1], z[2 * i], z[2 * i + 1]);
+                else z[2 * i] = z[2 * i + 1] = (Compute)0;
+            }
+            values4(2 * h, j, wa, u, z, lo[ip]);
+            if (second) values4(2 * h + 1, j, wa, u + 4, z + 4, hi[ip]);
+        }
+        store4(oc, 2 * h, lo);
+        if (second) store4(oc, 2 * h + 1, hi);
+    };
     uint32_t jv[kGatherPositions];
     bool ok[kGatherPositions];
     if (octets == 1) {
@@ -418,18 +466,24 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
             jv[ip] = cols[ip];
             ok[ip] = ip < npos_block && jv[ip] != kNoDrawColumn;
         }
-        for (int64_t q = threadIdx.x; q < (int64_t)quads; q += kGatherThreads) generate(0u, q, jv, ok);
+        if constexpr (V16) {
+            for (int64_t h = threadIdx.x; h < (int64_t)((quads + 1) / 2); h += kGatherThreads) generate16(0u, h, jv, ok);
+        } else {
+            for (int64_t q = threadIdx.x; q < (int64_t)quads; q += kGatherThreads) generate(0u, q, jv, ok);
+        }
     } else {
-        const uint32_t items = quads * (uint32_t)octets;
+        const uint32_t units = V16 ? (quads + 1) / 2 : quads;   // lane items per position group
+        const uint32_t items = units * (uint32_t)octets;
         for (uint32_t it = threadIdx.x; it < items; it += kGatherThreads) {
-            const uint32_t oc = it / quads;
+            const uint32_t oc = it / units;
             const int npos = npos_block - (int)oc * kGatherPositions;
 #pragma unroll
             for (int ip = 0; ip < kGatherPositions; ++ip) {
                 jv[ip] = cols[oc * kGatherPositions + ip];
                 ok[ip] = ip < npos && jv[ip] != kNoDrawColumn;
             }
-            generate(oc, (int64_t)(it - oc * quads), jv, ok);
+            if constexpr (V16) generate16(oc, (int64_t)(it - oc * units), jv, ok);
+            else generate(oc, (int64_t)(it - oc * units), jv, ok);
         }
     }
     zero_padding_rows<Compute, Store, KPACK>(prm, pos_base, octets, m, p, m_pad, p_pad, GA, GB);
@@ -1302,14 +1356,24 @@ static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t
             if constexpr (sizeof(typename P::In) == 1) return hipErrorInvalidValue;   // not with FP8
             else hipLaunchKernelGGL((gather_experiment_kernel<Compute, typename P::In, P::KPACK>), grid,
                                     dim3(kGatherThreads), 0, stream, g);
+        } else if (plan.value16) {
+            if (plan.laws == kLawsNormal)
+                hipLaunchKernelGGL((gather_kernel<Compute, typename P::In, P::KPACK, kLawsNormal, true>), grid,
+                                   dim3(kGatherThreads), 0, stream, g);
+            else if (plan.laws == kLawsUniform)
+                hipLaunchKernelGGL((gather_kernel<Compute, typename P::In, P::KPACK, kLawsUniform, true>), grid,
+                                   dim3(kGatherThreads), 0, stream, g);
+            else
+                hipLaunchKernelGGL((gather_kernel<Compute, typename P::In, P::KPACK, kLawsAny, true>), grid,
+                                   dim3(kGatherThreads), 0, stream, g);
         } else if (plan.laws == kLawsNormal)
-            hipLaunchKernelGGL((gather_kernel<Compute, typename P::In, P::KPACK, kLawsNormal>), grid,
+            hipLaunchKernelGGL((gather_kernel<Compute, typename P::In, P::KPACK, kLawsNormal, false>), grid,
                                dim3(kGatherThreads), 0, stream, g);
         else if (plan.laws == kLawsUniform)
-            hipLaunchKernelGGL((gather_kernel<Compute, typename P::In, P::KPACK, kLawsUniform>), grid,
+            hipLaunchKernelGGL((gather_kernel<Compute, typename P::In, P::KPACK, kLawsUniform, false>), grid,
                                dim3(kGatherThreads), 0, stream, g);
         else
-            hipLaunchKernelGGL((gather_kernel<Compute, typename P::In, P::KPACK, kLawsAny>), grid,
+            hipLaunchKernelGGL((gather_kernel<Compute, typename P::In, P::KPACK, kLawsAny, false>), grid,
                                dim3(kGatherThreads), 0, stream, g);
     }
     hipError_t err = hipGetLastError();

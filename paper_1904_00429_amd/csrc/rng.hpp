@@ -149,6 +149,15 @@ __device__ __forceinline__ void box_muller(double u, double v, double& z0, doubl
     z1 = rho * s;
 }
 
+// 16-bit uniforms (the optional cheaper value generation): u = (h + 1/2)
+// 2^-16 for a 16-bit h, exact in FP32 and FP64, never 0 or 1.
+template <typename T>
+__device__ __forceinline__ T unit16(uint32_t h);
+template <>
+__device__ __forceinline__ float unit16<float>(uint32_t h) { return __builtin_fmaf((float)h, 0x1p-16f, 0x1p-17f); }
+template <>
+__device__ __forceinline__ double unit16<double>(uint32_t h) { return ((double)h + 0.5) * 0x1p-16; }
+
 template <typename T>
 __device__ __forceinline__ T unit(uint32_t w);
 template <>

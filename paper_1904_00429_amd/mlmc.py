@@ -20,6 +20,7 @@ PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "fp8": 3}
 FLAG_SHARED_SAMPLES = 1
 FLAG_STRIDE_COUPLING = 8
 FLAG_INDEX_WORD32 = 16
+FLAG_VALUE16 = 32
 COUPLINGS = ("prefix", "stride")   # coarse draws: the first c_{l-1}, or every M-th (Sec. 3.1)
 FLAG_ADAPTIVE_LEVELS = 4
 SHARED_LEVEL_FIELD = 0xFF
@@ -134,7 +135,7 @@ class _LevelsHolder:
     def __init__(self, c, n_samples, rmse_target, pilot, seed, prec, shared, problem, max_total_draws,
                  func: Optional[Func] = None, adaptive: bool = False,
                  index_weights: Optional[torch.Tensor] = None, coupling: str = "prefix",
-                 index_word32: bool = False):
+                 index_word32: bool = False, value16: bool = False):
         if prec not in PREC:
             raise ValueError(f"prec must be one of {sorted(PREC)}")
         if coupling not in COUPLINGS:
@@ -152,7 +153,8 @@ class _LevelsHolder:
         lv.prec = PREC[prec]
         lv.flags = ((FLAG_SHARED_SAMPLES if shared else 0) | (FLAG_ADAPTIVE_LEVELS if adaptive else 0)
                     | (FLAG_STRIDE_COUPLING if coupling == "stride" else 0)
-                    | (FLAG_INDEX_WORD32 if index_word32 else 0))
+                    | (FLAG_INDEX_WORD32 if index_word32 else 0)
+                    | (FLAG_VALUE16 if value16 else 0))
         lv.problem = int(problem)
         f = func or Func()
         lv.func = int(f.kind)
@@ -189,15 +191,16 @@ def matmul_estimate(m: int, n: int, p: int, A: Law, B: Law, c: Sequence[int],
                     report: bool = True, device=None, workspace: Optional[torch.Tensor] = None,
                     out: Optional[torch.Tensor] = None, func: Optional[Func] = None,
                     adaptive: bool = False, index_weights: Optional[torch.Tensor] = None,
-                    coupling: str = "prefix") -> Result:
+                    coupling: str = "prefix", value16: bool = False) -> Result:
     """MLMC estimate of E[f(AB)] on the GPU (mlmc_matmul_estimate; f = identity
     unless func is given; adaptive: number of levels chosen by the bias test,
     c being the longest ladder allowed; index_weights: int32 device tensor of n
     positive weights, xi_j = w_j / sum w, e.g. optimal_index_weights;
-    coupling: "prefix" or "stride", the coarse draws of each level sample)."""
+    coupling: "prefix" or "stride", the coarse draws of each level sample;
+    value16: values from 16-bit uniforms, eight per Philox call)."""
     device = torch.device(device or "cuda")
     h = _LevelsHolder(c, n_samples, rmse_target, pilot, seed, prec, shared, problem, max_total_draws, func,
-                      adaptive, index_weights, coupling)
+                      adaptive, index_weights, coupling, value16=value16)
     ws_bytes = int(lib().mlmc_matmul_workspace_size(int(m), int(n), int(p), ctypes.byref(h.lv)))
     if ws_bytes == 0:
         raise MLMCError(1, "invalid problem: no workspace size")
@@ -353,10 +356,11 @@ class BatchedEstimate:
 
     def __init__(self, problems: Sequence[BatchProblem], c: Sequence[int], n_samples: Sequence[int],
                  seed: int = 0, prec: str = "fp32", tuning: Optional[dict] = None, device=None,
-                 func: Optional[Func] = None, coupling: str = "prefix"):
+                 func: Optional[Func] = None, coupling: str = "prefix", value16: bool = False):
         self.device = torch.device(device or "cuda")
         self.problems = list(problems)
-        self.h = _LevelsHolder(c, n_samples, 0.0, 0, seed, prec, False, 0, 0, func, coupling=coupling)
+        self.h = _LevelsHolder(c, n_samples, 0.0, 0, seed, prec, False, 0, 0, func, coupling=coupling,
+                               value16=value16)
         self.Y = [torch.empty((pr.m, pr.p), dtype=torch.float64, device=self.device) for pr in self.problems]
         arr = (Problem * len(self.problems))()
         for i, pr in enumerate(self.problems):

@@ -248,3 +248,16 @@ def test_index_word32_validated(L):
     st = L.mlmc_matmul_estimate(4, 16, 3, ctypes.byref(A), ctypes.byref(A), ctypes.byref(lv), 8, None,
                                 16, 1 << 40, None, None)
     assert st == 1 and b"32-bit index words" in L.mlmc_last_error()
+
+
+def test_value16_validated(L):
+    lv, keep = _levels([2, 4], [4, 4], prec=1)
+    lv.flags = 32
+    A = _dist(0, 0.5, 1.0)
+    st = L.mlmc_inner_product_estimate(1024, ctypes.byref(A), ctypes.byref(A), ctypes.byref(lv), 8, None,
+                                       16, 1 << 40, None, None)
+    assert st == 1 and b"16-bit value" in L.mlmc_last_error()
+    X, Y = _dist(5, 0.5, 1e-4), _dist(6, 2.0, 0.2)
+    st = L.mlmc_matmul_estimate(4, 16, 3, ctypes.byref(X), ctypes.byref(Y), ctypes.byref(lv), 8, None,
+                                16, 1 << 40, None, None)
+    assert st == 1 and b"own stream" in L.mlmc_last_error()

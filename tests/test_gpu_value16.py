@@ -1,0 +1,102 @@
+"""GPU parity of the 16-bit value uniforms (MLMC_FLAG_VALUE16: eight values
+per Philox call) against the oracle's value16 laws on the same seeded
+inputs: the matrix estimator in every precision (ragged shapes, every
+classic law), with a target function, with weighted draws, and batches; at
+the tolerances of the default stream (FP64 1e-12, FP32 1e-5, BF16 0.05 and
+FP8 0.25 RMSE_est)."""
+import numpy as np
+import pytest
+
+from gpu_helpers import flush, laws, rel_frob
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _reparam(seed, n, m, p):
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal((n, m)).astype(np.float32), rng.uniform(0.1, 1.0, (n, m)).astype(np.float32),
+            rng.standard_normal((n, p)).astype(np.float32), rng.uniform(0.1, 1.0, (n, p)).astype(np.float32))
+
+
+CASES = [
+    # m, n, p, law, ladder, N, precision
+    (70, 100, 41, ("normal", 0.5, 1.0), [2, 4, 8], [300, 150, 75], "fp64"),     # ragged rows: partial octets
+    (37, 300, 45, ("uniform", 0.2, 0.7), [3, 6, 12], [200, 100, 50], "fp64"),
+    (29, 200, 13, ("reparam",), [2, 4, 8], [200, 100, 50], "fp64"),
+    (70, 500, 41, ("normal", 0.5, 1.0), [4, 8, 16], [200, 100, 50], "fp32"),
+    (128, 500, 128, ("normal", 0.5, 1.0), [16, 32, 64], [200, 100, 50], "bf16"),
+    (128, 500, 128, ("normal", 0.5, 1.0), [16, 32, 64], [200, 100, 50], "fp8"),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_matmul_value16_matches_oracle(orc, dev, case):
+    from paper_1904_00429_amd import matmul_estimate
+    m, n, p, law, c, N, prec = CASES[case]
+    flush(f"[value16] {m}x{n}x{p} {law[0]} {prec}")
+    if law[0] == "reparam":
+        MA, SA, MB, SB = _reparam(case, n, m, p)
+        oA, gA = laws(orc, law, dev, MA, SA)
+        oB, gB = laws(orc, law, dev, MB, SB)
+    else:
+        oA, gA = laws(orc, law, dev)
+        oB, gB = oA, gA
+    est = matmul_estimate(m, n, p, gA, gB, c, n_samples=N, seed=31, prec=prec, level_means=True, device=dev,
+                          value16=True)
+    ref = orc.estimate(m, n, p, oA.with_value16(), oB.with_value16(), c, n_samples=N, seed=31)
+    Y = est.Y.cpu().numpy()
+    if prec in ("bf16", "fp8"):
+        err = np.linalg.norm((Y - ref.Y).ravel())
+        flush(f"  {prec} error {err:.4g} vs rmse_est {ref.rmse_est:.4g}")
+        assert err <= (0.05 if prec == "bf16" else 0.25) * ref.rmse_est
+        np.testing.assert_allclose(est.level_var, ref.level_var, rtol=3e-2 if prec == "bf16" else 0.15)
+        return
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    assert rel_frob(Y, ref.Y) <= tol, rel_frob(Y, ref.Y)
+    np.testing.assert_allclose(est.level_var, ref.level_var, rtol=1e-10 if prec == "fp64" else 1e-5)
+    # a different value stream from the default one
+    other = orc.estimate(m, n, p, oA, oB, c, n_samples=N, seed=31)
+    assert rel_frob(other.Y, ref.Y) > 1e-6
+
+
+def test_value16_with_func_and_weights(orc, dev):
+    from paper_1904_00429_amd import Func, matmul_estimate, optimal_index_weights
+    m, n, p, c, N = 40, 300, 33, [2, 4, 8], [200, 100, 50]
+    flush("[value16] f and weighted draws")
+    MA, SA, MB, SB = _reparam(9, n, m, p)
+    MA *= np.linspace(0.1, 2.0, n)[:, None].astype(np.float32)
+    oA, gA = laws(orc, ("reparam",), dev, MA, SA)
+    oB, gB = laws(orc, ("reparam",), dev, MB, SB)
+    ow = orc.Weights(orc.optimal_weights(m, n, p, oA, oB))
+    gw = optimal_index_weights(m, n, p, gA, gB, device=dev)
+    est = matmul_estimate(m, n, p, gA, gB, c, n_samples=N, seed=4, prec="fp64", device=dev, value16=True,
+                          index_weights=gw, func=Func.abs_step(2.0))
+    ref = orc.estimate(m, n, p, oA.with_value16(), oB.with_value16(), c, n_samples=N, seed=4, weights=ow,
+                       func=orc.Func.abs_step(2.0))
+    assert rel_frob(est.Y.cpu().numpy(), ref.Y) <= 1e-12
+
+
+def test_batched_value16_matches_oracle(orc, dev):
+    from paper_1904_00429_amd import BatchedEstimate, BatchProblem, Law
+    shapes = [(64, 100, 64), (100, 150, 37), (20, 90, 129)]
+    c, N = [4, 8, 16], [120, 60, 30]
+    flush("[value16] batched fp64")
+    probs = [BatchProblem(m, n, p, Law.normal(0.3 + i, 1.0), Law.normal(0.5, 2.0), 7 + i)
+             for i, (m, n, p) in enumerate(shapes)]
+    est = BatchedEstimate(probs, c, N, seed=5, prec="fp64", device=dev, value16=True)
+    V = est.run(level_var=True)
+    torch.cuda.synchronize()
+    for i, (m, n, p) in enumerate(shapes):
+        A = orc.Law.normal(0.3 + i, 1.0).with_value16()
+        B = orc.Law.normal(0.5, 2.0).with_value16()
+        ref = orc.estimate(m, n, p, A, B, c, n_samples=N, seed=5, problem=7 + i)
+        assert rel_frob(est.Y[i].cpu().numpy(), ref.Y) <= 1e-12, i
+        np.testing.assert_allclose(V[:, i], ref.level_var, rtol=1e-10)
