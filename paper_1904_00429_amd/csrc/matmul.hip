@@ -316,8 +316,9 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
     // for t < c_{l-1}, 1 otherwise).
     const Compute omega = (Compute)prm.omega;
     // values of rows 4q .. 4q+3 at the 8 positions of group oc
-    // Values of rows 4q .. 4q+3 of position ip (column j, a_t weight wa)
-    // from their uniforms u and normals z.
+    // V16 helpers (the default path below keeps its own fused form, whose
+    // code the compiler schedules better): values of rows 4q .. 4q+3 of one
+    // position (column j, a_t weight wa) from their uniforms u and normals z,
     auto values4 = [&](int64_t q, uint32_t j, Compute wa, const Compute* u, const Compute* z, Val* out) {
         const int64_t e0 = 4 * q;
         if (e0 + 3 < m) {            // the whole quad is in A's column
@@ -345,7 +346,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
             }
         }
     };
-    // Stores of rows 4q .. 4q+3 at the 8 positions of group oc.
+    // and their stores at the 8 positions of group oc.
     auto store4 = [&](uint32_t oc, int64_t q, Val (&vals)[kGatherPositions][4]) {
         const int64_t pos0 = pos_base + (int64_t)oc * kGatherPositions;
         const int npos = (int)((prm.kpad - pos0) < kGatherPositions ? (prm.kpad - pos0) : kGatherPositions);
@@ -407,7 +408,9 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
     auto generate = [&](uint32_t oc, int64_t q, const uint32_t* jv, const bool* ok) {
         const Compute* fv = colf + oc * kGatherPositions;
         const int64_t pos0 = pos_base + (int64_t)oc * kGatherPositions;
+        const int npos = (int)((prm.kpad - pos0) < kGatherPositions ? (prm.kpad - pos0) : kGatherPositions);
         Val vals[kGatherPositions][4];
+        const int64_t e0 = 4 * q;
 #pragma unroll
         for (int ip = 0; ip < kGatherPositions; ++ip) {
             if (!ok[ip]) {
@@ -420,9 +423,82 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
             const Words4 w = philox4x32_10((uint32_t)q, k, j, sid_value, prm.key0, prm.key1);
             Compute u[4], z[4];
             quad_values<Compute>(w, normal, u[0], u[1], u[2], u[3], z[0], z[1], z[2], z[3]);
-            values4(q, j, wa, u, z, vals[ip]);
+            if (e0 + 3 < m) {            // the whole quad is in A's column
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    vals[ip][r] = to_val(wa * LA.template eval<LAWS>(z[r], u[r], (int64_t)j * LA.ld + e0 + r), pre_a);
+            } else if (e0 >= m) {        // the whole quad is in B's row
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    vals[ip][r] = to_val(LB.template eval<LAWS>(z[r], u[r], (int64_t)j * LB.ld + (e0 + r - m)), pre_b);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t e = e0 + r;
+                    Compute v = (Compute)0;
+                    float pre = 1.0f;
+                    if (e < m) {
+                        v = wa * LA.template eval<LAWS>(z[r], u[r], (int64_t)j * LA.ld + e);
+                        pre = pre_a;
+                    } else if (e < rows) {
+                        v = LB.template eval<LAWS>(z[r], u[r], (int64_t)j * LB.ld + (e - m));
+                        pre = pre_b;
+                    }
+                    vals[ip][r] = to_val(v, pre);
+                }
+            }
         }
-        store4(oc, q, vals);
+        if constexpr (KPACK == 1) {
+            // rows 4q .. 4q+3 of one position are adjacent: one vector store
+            // per position when the quad lies in A, or in B at an aligned row
+            const bool in_a = e0 + 3 < m;
+            const bool in_b = e0 >= m && e0 + 3 < rows && ((e0 - m) & 3) == 0;
+            if (in_a || in_b) {
+                typedef Store vec4_t __attribute__((ext_vector_type(4)));
+                Store* G = in_a ? GA : GB;
+                const int64_t R = in_a ? m_pad : p_pad;
+                const int64_t row = in_a ? e0 : e0 - m;
+#pragma unroll
+                for (int ip = 0; ip < kGatherPositions; ++ip) {
+                    if (ip < npos) {
+                        vec4_t vv;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) vv[r] = vals[ip][r];
+                        *reinterpret_cast<vec4_t*>(G + (pos0 + ip) * R + row) = vv;
+                    }
+                }
+                return;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t e = e0 + r;
+            if (e >= rows) break;
+            Store* G = e < m ? GA : GB;
+            const int64_t R = e < m ? m_pad : p_pad;
+            const int64_t row = e < m ? e : e - m;
+            if constexpr (KPACK == 1) {
+#pragma unroll
+                for (int ip = 0; ip < kGatherPositions; ++ip)
+                    if (ip < npos) G[(pos0 + ip) * R + row] = vals[ip][r];
+            } else if constexpr (kFp8) {
+                // positions pos0 .. pos0+7 are one packed group of 8 draws:
+                // OCP e4m3, round to nearest even, two values per conversion
+                uint2 vv;
+                int w = __builtin_amdgcn_cvt_pk_fp8_f32(vals[0][r], vals[1][r], 0, false);
+                vv.x = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(vals[2][r], vals[3][r], w, true);
+                w = __builtin_amdgcn_cvt_pk_fp8_f32(vals[4][r], vals[5][r], 0, false);
+                vv.y = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(vals[6][r], vals[7][r], w, true);
+                *reinterpret_cast<uint2*>(G + ((pos0 / KPACK) * R + row) * KPACK) = vv;
+            } else {
+                // positions pos0 .. pos0+7 are one packed group of 8 draws
+                typedef Store vec_t __attribute__((ext_vector_type(KPACK)));
+                vec_t vv;
+#pragma unroll
+                for (int ip = 0; ip < KPACK; ++ip) vv[ip] = vals[ip][r];
+                *reinterpret_cast<vec_t*>(G + ((pos0 / KPACK) * R + row) * KPACK) = vv;
+            }
+        }
     };
     // V16: rows 8h .. 8h+7 (quads 2h and 2h+1) from one call per position,
     // whose four words give eight 16-bit uniforms (element 8h + 2i + b takes
