@@ -165,8 +165,7 @@ def main():
               f"level statistics per phase)", file=sys.stderr)
         sys.exit(2)
     import torch
-    from paper_1904_00429_amd import Law, inner_product_estimate, matmul_estimate, workloads
-    from paper_1904_00429_amd.mlmc import FLAG_SHARED_SAMPLES  # noqa: F401
+    from paper_1904_00429_amd import Law, workloads
     import paper_1904_00429_amd.mlmc as api
 
     dev = torch.device("cuda:0")

@@ -13,7 +13,6 @@ from typing import Optional, Sequence
 
 import torch
 
-from . import _lib
 from ._lib import Dist, Levels, MLMCError, Problem, Report, Tuning, check, lib
 
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "fp8": 3}
