@@ -185,6 +185,11 @@ def main():
     if args.workload == "importance":
         return bench_importance(args)
     if args.workload == "experiments":
+        # a Sec. 4.2 estimate takes seconds: fewer steps unless asked for
+        if "--steps" not in sys.argv:
+            args.steps = 3
+        if "--warmup" not in sys.argv:
+            args.warmup = 1
         return bench_experiments(args)
     if args.workload == "inner":
         wl = workloads.INNER_2POW20
