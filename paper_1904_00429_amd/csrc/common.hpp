@@ -58,7 +58,17 @@ __device__ inline double experiment_value(int kind, double loc, double scale, do
         F = F + pk;
     }
     if (kind == 4) return unit_f64(w.w2) < scale ? cos((double)K - 2.0 * log(u1)) : 0.0;
-    return (u1 < scale && K <= 5) ? cos((double)K) : 0.0;
+    // the stepped law takes cos(K) for K = 0 .. 5 only: a table of the
+    // correctly rounded values instead of an FP64 cosine per element
+    if (!(u1 < scale && K <= 5)) return 0.0;
+    switch (K) {
+    case 0: return 1.0;
+    case 1: return 0x1.14a280fb5068cp-1;
+    case 2: return -0x1.aa22657537205p-2;
+    case 3: return -0x1.fae04be85e5d2p-1;
+    case 4: return -0x1.4eaa606db24c1p-1;
+    default: return 0x1.22785706b4ad9p-2;
+    }
 }
 
 // Welford / Chan statistics of a set of scalars: count, mean, sum of squared
