@@ -125,8 +125,8 @@ typedef enum {
  * the estimates differ realisation by realisation (not in law).  EINVAL
  * otherwise. */
 #define MLMC_FLAG_INDEX_WORD32 16u
-/* Values from 16-bit uniforms (matrix products, batched included; laws 0-2;
- * not the adjoint): element e of column j takes half (e & 1: high, else
+/* Values from 16-bit uniforms (matrix products, batched included, and the
+ * adjoint, which regenerates the forward's values; laws 0-2): element e of column j takes half (e & 1: high, else
  * low) of word (e / 2) % 4 of the value-stream call (e / 8, k, j,
  * 2 << 28 | level << 20 | problem), u = (h + 1/2) 2^-16, so one Philox call
  * gives eight values instead of four; normals by Box-Muller on the two halves

@@ -16,9 +16,12 @@ import torch
 from . import Law, column, coupling_stride, draw_index_weighted, draw_indices, level_field
 
 
-def standard_normals(seed, problem, lfield, k, cols, m, p):
-    """z (len(cols) x m) and w (len(cols) x p) of the draws of realisation k."""
+def standard_normals(seed, problem, lfield, k, cols, m, p, value16=False):
+    """z (len(cols) x m) and w (len(cols) x p) of the draws of realisation k
+    (value16: the 16-bit value uniforms)."""
     unit = Law.normal(0.0, 1.0)
+    if value16:
+        unit = unit.with_value16()
     Z = np.empty((len(cols), m))
     W = np.empty((len(cols), p))
     for t, j in enumerate(cols):
@@ -28,7 +31,8 @@ def standard_normals(seed, problem, lfield, k, cols, m, p):
 
 def reparam_estimate(MA: torch.Tensor, SA: torch.Tensor, MB: torch.Tensor, SB: torch.Tensor,
                      c: Sequence[int], N: Sequence[int], seed: int = 0, problem: int = 0,
-                     shared: bool = False, weights=None, coupling: str = "prefix") -> torch.Tensor:
+                     shared: bool = False, weights=None, coupling: str = "prefix",
+                     value16: bool = False) -> torch.Tensor:
     """Y = sum_l (1/N_l) sum_k (Z_l^(k) - Z_{l-1}^(k)) for A = MA^T + SA^T o Z
     (MA, SA: n x m, row j = column j of A) and B = MB + SB o W (n x p).  With
     `weights` (oracle.Weights) the indices are drawn with xi_j = w_j / W and
@@ -49,7 +53,7 @@ def reparam_estimate(MA: torch.Tensor, SA: torch.Tensor, MB: torch.Tensor, SB: t
             else:
                 r = np.array([draw_index_weighted(seed, problem, lf, k, t, weights) for t in range(cl)],
                              dtype=np.int64)
-            Z, W = standard_normals(seed, problem, lf, k, r, m, p)
+            Z, W = standard_normals(seed, problem, lf, k, r, m, p, value16)
             idx = torch.from_numpy(r)
             AS = MA[idx] + SA[idx] * Z          # c x m: row t = a_t
             BS = MB[idx] + SB[idx] * W          # c x p: row t = b_t
@@ -66,10 +70,10 @@ def reparam_estimate(MA: torch.Tensor, SA: torch.Tensor, MB: torch.Tensor, SB: t
 
 
 def reparam_gradients(MA, SA, MB, SB, c, N, G, seed=0, problem=0, shared=False, weights=None,
-                      coupling="prefix"):
+                      coupling="prefix", value16=False):
     """Gradients of <G, Y> (FP64) with respect to MA, SA, MB, SB (weights held fixed)."""
     leaves = [torch.as_tensor(np.asarray(x, dtype=np.float64)).clone().requires_grad_(True)
               for x in (MA, SA, MB, SB)]
-    Y = reparam_estimate(*leaves, c, N, seed, problem, shared, weights, coupling)
+    Y = reparam_estimate(*leaves, c, N, seed, problem, shared, weights, coupling, value16)
     (Y * torch.as_tensor(np.asarray(G, dtype=np.float64))).sum().backward()
     return Y.detach().numpy(), [t.grad.numpy() for t in leaves]

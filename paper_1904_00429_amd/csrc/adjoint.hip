@@ -52,6 +52,7 @@ struct AdjGatherParams {
     __bf16* BSb;                  // batch x kpad x pk
     int64_t mk, pk;
     const uint64_t* cum;          // cumulative index weights (NULL: uniform draws)
+    bool value16;                 // the forward's values came from 16-bit uniforms
 };
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
@@ -92,9 +93,22 @@ __global__ __launch_bounds__(kAdjGatherThreads) void adjoint_gather_kernel(AdjGa
                 continue;
             }
             const uint32_t j = cols[ip];
-            const Words4 w = philox4x32_10((uint32_t)q, k, j, prm.sid_value, prm.key0, prm.key1);
             float u[4], z[4];
-            quad_values<float>(w, true, u[0], u[1], u[2], u[3], z[0], z[1], z[2], z[3]);
+            if (prm.value16) {
+                // rows 4q .. 4q+3 are halves of words 2 (q & 1) and 2 (q & 1) + 1
+                // of the call for rows 8 (q / 2) .. 8 (q / 2) + 7
+                const Words4 w = philox4x32_10((uint32_t)(q >> 1), k, j, prm.sid_value, prm.key0, prm.key1);
+                const uint32_t a = (q & 1) ? w.w2 : w.w0, b = (q & 1) ? w.w3 : w.w1;
+                u[0] = unit16<float>(a & 0xFFFFu);
+                u[1] = unit16<float>(a >> 16);
+                u[2] = unit16<float>(b & 0xFFFFu);
+                u[3] = unit16<float>(b >> 16);
+                box_muller(u[0], u[1], z[0], z[1]);
+                box_muller(u[2], u[3], z[2], z[3]);
+            } else {
+                const Words4 w = philox4x32_10((uint32_t)q, k, j, prm.sid_value, prm.key0, prm.key1);
+                quad_values<float>(w, true, u[0], u[1], u[2], u[3], z[0], z[1], z[2], z[3]);
+            }
             for (int r = 0; r < 4; ++r) {
                 const int64_t e = 4 * q + r;
                 float v = 0.0f;
@@ -479,7 +493,7 @@ hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law&
                        const int64_t* c, const int64_t* N, const StreamKeys& keys, bool shared,
                        const double* grad, float* dMA, float* dSA, float* dMB, float* dSB,
                        const uint32_t* index_weights, char* ws, size_t ws_bytes, bool bf16, bool stride,
-                       hipStream_t stream, KernelTimer* timer)
+                       bool value16, hipStream_t stream, KernelTimer* timer)
 {
     auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const int64_t mk = round_up_adj(m, 8), pk = round_up_adj(p, 8);
@@ -538,6 +552,7 @@ hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law&
             g.AT = AT; g.BT = BT; g.ZS = ZS; g.WS = WS; g.R = Rr;
             g.ASb = ASb; g.BSb = BSb; g.mk = mk; g.pk = pk;
             g.cum = cum;
+            g.value16 = value16;
             {
                 ScopedTiming t(timer, 1);
                 const dim3 grid((unsigned)(kpad / kAdjPositions), (unsigned)S);

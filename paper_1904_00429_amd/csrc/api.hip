@@ -740,7 +740,6 @@ mlmc_status mlmc_matmul_adjoint_reparam(int64_t m, int64_t n, int64_t p, const m
     if ((st = check_dist(B, "B", p, false)) != MLMC_OK) return st;
     if (A->law != MLMC_LAW_REPARAM || B->law != MLMC_LAW_REPARAM)
         return fail(MLMC_EINVAL, "the adjoint is defined for reparameterised laws");
-    if (lv->flags & MLMC_FLAG_VALUE16) return fail(MLMC_EINVAL, "the adjoint regenerates 23-bit values only");
     if (!grad_out || !dMA || !dSA || !dMB || !dSB) return fail(MLMC_EINVAL, "null gradient pointer");
     const size_t need = adjoint_workspace_size(m, n, p, lv->num_levels, lv->c, lv->index_weights != nullptr);
     if (!workspace || workspace_bytes < need) return fail(MLMC_EWORKSPACE, "workspace needs %zu bytes", need);
@@ -750,8 +749,8 @@ mlmc_status mlmc_matmul_adjoint_reparam(int64_t m, int64_t n, int64_t p, const m
     hipError_t e = adjoint_run(m, n, p, to_law(*A), to_law(*B), lv->num_levels, lv->c, lv->n_samples, keys_of(lv),
                                (lv->flags & MLMC_FLAG_SHARED_SAMPLES) != 0, grad_out, dMA, dSA, dMB, dSB,
                                lv->index_weights, static_cast<char*>(workspace), workspace_bytes,
-                               lv->prec == MLMC_PREC_BF16, (lv->flags & MLMC_FLAG_STRIDE_COUPLING) != 0, stream,
-                               timer);
+                               lv->prec == MLMC_PREC_BF16, (lv->flags & MLMC_FLAG_STRIDE_COUPLING) != 0,
+                               (lv->flags & MLMC_FLAG_VALUE16) != 0, stream, timer);
     return e == hipSuccess ? MLMC_OK : device_fail(e, "adjoint launch");
 }
 

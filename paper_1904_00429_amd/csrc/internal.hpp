@@ -157,7 +157,7 @@ hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law&
                        const int64_t* c, const int64_t* N, const StreamKeys& keys, bool shared,
                        const double* grad, float* dMA, float* dSA, float* dMB, float* dSB,
                        const uint32_t* index_weights, char* ws, size_t ws_bytes, bool bf16, bool stride,
-                       hipStream_t stream, KernelTimer* timer);
+                       bool value16, hipStream_t stream, KernelTimer* timer);
 
 // ---- building blocks exported for tests -----------------------------------
 hipError_t philox_batch(int64_t count, const uint32_t* ctr, uint32_t key0, uint32_t key1,

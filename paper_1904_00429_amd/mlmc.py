@@ -312,7 +312,8 @@ def matmul_adjoint_reparam(MA: torch.Tensor, SA: torch.Tensor, MB: torch.Tensor,
                            c: Sequence[int], n_samples: Sequence[int], grad_out: torch.Tensor,
                            seed: int = 0, problem: int = 0, shared: bool = False,
                            workspace: Optional[torch.Tensor] = None, prec: str = "fp32",
-                           index_weights: Optional[torch.Tensor] = None, coupling: str = "prefix"):
+                           index_weights: Optional[torch.Tensor] = None, coupling: str = "prefix",
+                           value16: bool = False):
     """Gradients of <grad_out, Y> with respect to M_A, S_A, M_B, S_B
     (mlmc_matmul_adjoint_reparam).  MA, SA: (n, m) FP32 device tensors (row j =
     column j of A); MB, SB: (n, p).  prec: "fp32" or "bf16" (BF16 operands
@@ -321,7 +322,8 @@ def matmul_adjoint_reparam(MA: torch.Tensor, SA: torch.Tensor, MB: torch.Tensor,
     p = MB.shape[1]
     device = MA.device
     A, B = Law.reparam(MA, SA), Law.reparam(MB, SB)
-    h = _LevelsHolder(c, n_samples, 0.0, 0, seed, prec, shared, problem, 0, None, False, index_weights, coupling)
+    h = _LevelsHolder(c, n_samples, 0.0, 0, seed, prec, shared, problem, 0, None, False, index_weights, coupling,
+                      value16=value16)
     ws_bytes = int(lib().mlmc_matmul_adjoint_workspace_size(int(m), int(n), int(p), ctypes.byref(h.lv)))
     if ws_bytes == 0:
         raise MLMCError(1, "invalid problem: no workspace size")

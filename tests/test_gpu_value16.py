@@ -100,3 +100,20 @@ def test_batched_value16_matches_oracle(orc, dev):
         ref = orc.estimate(m, n, p, A, B, c, n_samples=N, seed=5, problem=7 + i)
         assert rel_frob(est.Y[i].cpu().numpy(), ref.Y) <= 1e-12, i
         np.testing.assert_allclose(V[:, i], ref.level_var, rtol=1e-10)
+
+
+@pytest.mark.parametrize("prec, tol", [("fp32", 1e-5), ("bf16", 1e-2)])
+def test_adjoint_value16_matches_reference(orc, dev, prec, tol):
+    from oracle import grad as og
+    from paper_1904_00429_amd import matmul_adjoint_reparam
+    m, n, p, c, N = 26, 300, 19, [4, 8, 16], [20, 10, 5]
+    flush(f"[value16] adjoint {prec}")
+    params = _reparam(21, n, m, p)
+    G = np.random.default_rng(22).standard_normal((m, p))
+    _, ref = og.reparam_gradients(*params, c, N, G, seed=5, value16=True)
+    dp = [torch.from_numpy(x).to(dev) for x in params]
+    got = matmul_adjoint_reparam(*dp, c, N, torch.from_numpy(G), seed=5, prec=prec, value16=True)
+    for name, g, r in zip(("dMA", "dSA", "dMB", "dSB"), got, ref):
+        err = rel_frob(g.cpu().numpy(), r)
+        flush(f"  {name} rel err {err:.3g}")
+        assert err <= tol, (name, err)

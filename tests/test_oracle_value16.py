@@ -71,3 +71,18 @@ def test_level_variance_closed_form_value16():
         dev = ((D - st.mean.reshape(m, p)) ** 2).reshape(N, -1).sum(axis=1)
         se = dev.std() / math.sqrt(N)
         assert abs(st.variance - V_true[l]) < 5 * se, (l, st.variance, V_true[l], se)
+
+
+def test_gradient_reference_value16_matches_the_c_oracle():
+    import torch
+    from oracle import grad as og
+    rng = np.random.default_rng(3)
+    m, n, p = 3, 30, 2
+    MA, SA = rng.normal(size=(n, m)), rng.uniform(0.1, 1.0, size=(n, m))
+    MB, SB = rng.normal(size=(n, p)), rng.uniform(0.1, 1.0, size=(n, p))
+    c, N = [2, 4, 8], [20, 10, 5]
+    A = orc.Law.reparam(MA, SA, m).with_value16()
+    B = orc.Law.reparam(MB, SB, p).with_value16()
+    ref = orc.estimate(m, n, p, A, B, c, n_samples=N, seed=7)
+    Y = og.reparam_estimate(*[torch.from_numpy(x) for x in (MA, SA, MB, SB)], c, N, seed=7, value16=True)
+    assert np.abs(Y.numpy() - ref.Y).max() <= 1e-12 * np.abs(ref.Y).max()
