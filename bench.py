@@ -85,8 +85,10 @@ def parse():
     ap.add_argument("--index-words", type=int, default=32, choices=[32, 64],
                     help="inner product: index draws from 32-bit words (four per Philox call, power-of-two n) "
                          "or 64-bit words (two per call)")
-    ap.add_argument("--value-bits", type=int, default=23, choices=[16, 23],
-                    help="matrix workloads: uniforms of the generated values (16: eight per Philox call)")
+    ap.add_argument("--value-bits", default="auto", choices=["auto", "16", "23"],
+                    help="matrix workloads: uniforms of the generated values (16: eight per Philox call); "
+                         "auto: 16 for BF16 and FP8 operands (their rounding is far coarser than 2^-16), "
+                         "23 for FP32 and FP64")
     ap.add_argument("--adaptive", action="store_true",
                     help="choose the number of levels by the bias test (the workload's ladder is the longest)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -175,7 +177,7 @@ def main():
     _OPTS["adaptive"] = bool(args.adaptive)
     args.index_word32 = args.workload == "inner" and args.index_words == 32
     _OPTS["index_word32"] = args.index_word32
-    _OPTS["value16"] = args.value_bits == 16 and args.workload != "inner"
+    _OPTS["value_bits"] = args.value_bits
     if args.workload == "diff":
         return bench_diff(args)
     if args.workload == "batched":
@@ -259,7 +261,7 @@ def main():
                 "merge_ms_per_step": k_ms[2] / args.steps}
         config = {"workload": wl.name, "m": wl.m, "n": wl.n, "p": wl.p, "levels": len(wl.c), "c0": wl.c[0],
                   "ratio": 2, "eps": wl.rmse_target, "pilot": wl.pilot, "prec": prec, "func": args.func,
-                  "adaptive": bool(args.adaptive), "value_bits": 16 if _OPTS.get("value16") else 23}
+                  "adaptive": bool(args.adaptive), "value_bits": 16 if _value16(prec) else 23}
 
     out = {"metric": METRIC, "value": value, "unit": "estimates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
@@ -277,8 +279,7 @@ def main():
         ys = {}
         for pr in (prec, "fp64"):
             ys[pr] = matmul_estimate(wl.m, wl.n, wl.p, a, a, wl.c, n_samples=rep.n_used, seed=0, prec=pr,
-                                     device=dev, report=True, func=_OPTS["func"],
-                                     value16=_OPTS.get("value16", False))
+                                     device=dev, report=True, func=_OPTS["func"], value16=_value16(prec))
         out["precision_check"] = {
             "lp_minus_fp64_frob": float(torch.linalg.norm(ys[prec].Y - ys["fp64"].Y)),
             "rmse_est_fp64": ys["fp64"].rmse_est, "seed": 0, "n_samples": rep.n_used}
@@ -597,8 +598,7 @@ def bench_batched(args):
     out = {}
     for prec in ("fp8", "fp32"):
         best = autotune.tune(probs, c, N, prec=prec, device=dev)
-        est = BatchedEstimate(probs, c, N, seed=0, prec=prec, tuning=best, device=dev,
-                              value16=_OPTS.get("value16", False))
+        est = BatchedEstimate(probs, c, N, seed=0, prec=prec, tuning=best, device=dev, value16=_value16(prec))
         est.capture()
         sec = _time_replays(est, args.steps, args.warmup)
         out[prec] = {"s_per_estimate": sec, "tuning": best, "mfma_tflops_whole_graph": flops / sec / 1e12}
@@ -611,7 +611,8 @@ def bench_batched(args):
            "ms_per_step": 1e3 * out["fp8"]["s_per_estimate"], "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "fp8", "data": "synthetic",
            "config": {"workload": "batched-256-uneven", "products": len(shapes), "c0": c[0], "levels": len(c),
-                      "N": N, "graph": True, "value_bits": 16 if _OPTS.get("value16") else 23},
+                      "N": N, "graph": True,
+                      "value_bits": {"fp8": 16 if _value16("fp8") else 23, "fp32": 16 if _value16("fp32") else 23}},
            "products_per_s": len(shapes) * value,
            "fp32_value": 1.0 / out["fp32"]["s_per_estimate"],
            "fp8_over_fp32": out["fp32"]["s_per_estimate"] / out["fp8"]["s_per_estimate"],
@@ -660,6 +661,12 @@ _WS = {}
 _OPTS = {"func": None, "adaptive": False}
 
 
+def _value16(prec: str) -> bool:
+    """16-bit value uniforms for this operand precision (--value-bits)."""
+    vb = _OPTS.get("value_bits", "auto")
+    return vb == "16" or (vb == "auto" and prec in ("bf16", "fp8"))
+
+
 def _func_of(name):
     from paper_1904_00429_amd import Func
     return {"identity": None, "abs_step": Func.abs_step(2.0), "inv_abs_step": Func.inv_abs_step(0.4, 0.01)}[name]
@@ -696,7 +703,7 @@ def _matmul(api, wl, a, prec, dev, want_timing, seed):
     import torch
     h = api._LevelsHolder(wl.c, wl.n_samples, wl.rmse_target if wl.n_samples is None else 0.0,
                           wl.pilot, seed, prec, False, 0, 0, _OPTS["func"],
-                          _OPTS["adaptive"] and wl.n_samples is None, value16=_OPTS.get("value16", False))
+                          _OPTS["adaptive"] and wl.n_samples is None, value16=_value16(prec))
     if want_timing:
         h.lv.flags |= 2
     lib = api.lib()

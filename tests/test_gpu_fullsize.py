@@ -57,8 +57,8 @@ def test_inner_2pow20_target_mode_full(orc, dev, prec):
     assert est.rmse_est <= wl.rmse_target / math.sqrt(2) * 1.05
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp32"])
-def test_matmul_1024x65536x1024_target_mode_sampled_entries(orc, dev, prec):
+@pytest.mark.parametrize("prec, value16", [("bf16", True), ("bf16", False), ("fp32", False)])
+def test_matmul_1024x65536x1024_target_mode_sampled_entries(orc, dev, prec, value16):
     """The precision-form workload at its full size and in the benchmark's
     launch configuration (target mode: 64-realisation pilot, eq. (28), then
     extension), checked at an 8 x 8 grid of output entries that the oracle
@@ -66,18 +66,22 @@ def test_matmul_1024x65536x1024_target_mode_sampled_entries(orc, dev, prec):
 
     FP32: relative error 1e-5 over the sampled entries, level by level.
     BF16: RMS error over the sampled entries <= 5% of the estimator's own
-    standard deviation there (sum_l var_l / N_l from the oracle's samples)."""
+    standard deviation there (sum_l var_l / N_l from the oracle's samples).
+    BF16 is timed with 16-bit value uniforms (eight per Philox call); the
+    oracle then draws from the same 16-bit streams."""
     from paper_1904_00429_amd import Law, matmul_estimate, workloads
     wl = workloads.MATMUL_LARGE
-    flush(f"full-size target-mode matmul prec={prec} m={wl.m} n={wl.n} p={wl.p}")
+    flush(f"full-size target-mode matmul prec={prec} value16={value16} m={wl.m} n={wl.n} p={wl.p}")
     g = Law.normal(wl.law_a[1], wl.law_a[2])
     est = matmul_estimate(wl.m, wl.n, wl.p, g, g, wl.c, rmse_target=wl.rmse_target, pilot=wl.pilot,
-                          seed=3, prec=prec, level_means=True, device=dev)
+                          seed=3, prec=prec, level_means=True, device=dev, value16=value16)
     N = [int(x) for x in est.n_used]
     flush(f"  N_l = {N}")
     rows = list(range(3, wl.m, wl.m // 8))
     cols = list(range(wl.p - 1, 0, -(wl.p // 8)))
     o = orc.Law.normal(wl.law_a[1], wl.law_a[2])
+    if value16:
+        o = o.with_value16()
     with ThreadPoolExecutor(max_workers=min(len(wl.c), os.cpu_count() or 4)) as pool:
         ref = orc.estimate_entries(wl.m, wl.n, wl.p, o, o, wl.c, N, rows, cols, seed=3, pool=pool)
     ix = np.ix_(rows, cols)
