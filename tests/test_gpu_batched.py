@@ -126,11 +126,10 @@ def test_autotuner_picks_and_caches(dev, tmp_path, monkeypatch):
     assert autotune.tune(probs, C, N, prec="fp8", device=dev) == best
 
 
-@pytest.fixture(scope="module")
-def full_batch(orc):
+def _full_batch(orc, value16):
     """The benchmarked batch (256 uneven products, c_l = 16 * 2^l, l = 0..6,
     N_l = 2048 * 2^-l); the oracle evaluates every 4th product at a 4 x 4 grid
-    of entries."""
+    of entries, with the 16-bit value uniforms when value16 is set."""
     from paper_1904_00429_amd import workloads
     shapes, mus, c, N = workloads.batched_products()
     picked = list(range(0, len(shapes), 4))
@@ -138,6 +137,8 @@ def full_batch(orc):
     def one(i):
         m, n, p = shapes[i]
         law = orc.Law.normal(mus[i], 1.0)
+        if value16:
+            law = law.with_value16()
         rows = [0, m // 3, (2 * m) // 3, m - 1]
         cols = [p - 1, p // 2, 1, p // 4]
         return rows, cols, orc.estimate_entries(m, n, p, law, law, c, N, rows, cols, seed=0, problem=i)
@@ -146,18 +147,29 @@ def full_batch(orc):
     return shapes, mus, c, N, picked, refs
 
 
-@pytest.mark.parametrize("prec", ["fp8", "fp32"])
+@pytest.fixture(scope="module")
+def full_batch(orc):
+    return _full_batch(orc, False)
+
+
+@pytest.fixture(scope="module")
+def full_batch16(orc):
+    return _full_batch(orc, True)
+
+
+@pytest.mark.parametrize("prec, value16", [("fp8", True), ("fp8", False), ("fp32", False)])
 @pytest.mark.parametrize("tile", [64, 128])
-def test_full_batch_sampled_entries(dev, full_batch, prec, tile):
+def test_full_batch_sampled_entries(request, dev, prec, value16, tile):
     """The benchmarked batch in its launch configuration (one captured graph
-    per estimate, both tile shapes the autotuner chooses between), checked at
-    sampled entries of sampled products."""
+    per estimate, both tile shapes the autotuner chooses between; FP8 is timed
+    with 16-bit value uniforms), checked at sampled entries of sampled
+    products."""
     from paper_1904_00429_amd import BatchedEstimate, BatchProblem, Law
-    shapes, mus, c, N, picked, refs = full_batch
-    flush(f"full batch prec={prec} tile={tile} products={len(shapes)}")
+    shapes, mus, c, N, picked, refs = request.getfixturevalue("full_batch16" if value16 else "full_batch")
+    flush(f"full batch prec={prec} value16={value16} tile={tile} products={len(shapes)}")
     probs = [BatchProblem(m, n, p, Law.normal(mu, 1.0), Law.normal(mu, 1.0), i)
              for i, ((m, n, p), mu) in enumerate(zip(shapes, mus))]
-    est = BatchedEstimate(probs, c, N, seed=0, prec=prec, tuning={"tile": tile}, device=dev)
+    est = BatchedEstimate(probs, c, N, seed=0, prec=prec, tuning={"tile": tile}, device=dev, value16=value16)
     est.capture()
     est.replay()
     torch.cuda.synchronize()
