@@ -86,9 +86,9 @@ def parse():
                     help="inner product: index draws from 32-bit words (four per Philox call, power-of-two n) "
                          "or 64-bit words (two per call)")
     ap.add_argument("--value-bits", default="auto", choices=["auto", "16", "23"],
-                    help="matrix workloads: uniforms of the generated values (16: eight per Philox call); "
-                         "auto: 16 for BF16 and FP8 operands (their rounding is far coarser than 2^-16), "
-                         "23 for FP32 and FP64")
+                    help="matrix and differentiation workloads: uniforms of the generated values (16: eight per Philox call); "
+                         "auto: 16 for BF16 and FP8 operands of the i.i.d. matrix workloads (their rounding is far "
+                         "coarser than 2^-16), 23 for FP32, FP64 and the differentiation workload")
     ap.add_argument("--adaptive", action="store_true",
                     help="choose the number of levels by the bias test (the workload's ladder is the longest)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -317,11 +317,14 @@ def bench_diff(args):
     prec = args.prec or "fp32"
     if prec not in ("fp32", "bf16"):
         raise SystemExit("the differentiation form runs in fp32 or bf16")
+    # 16-bit values only when asked for: with reparameterised laws they
+    # measured slower in BF16 (47.2 against 50.7 estimates/s)
+    v16 = _OPTS.get("value_bits") == "16"
 
     def step(seed):
         for t in leaves:
             t.grad = None
-        Y = mlmc_matmul(*leaves, wl.c, wl.n_samples, seed=seed, prec=prec)
+        Y = mlmc_matmul(*leaves, wl.c, wl.n_samples, seed=seed, prec=prec, value16=v16)
         loss = ((Y - Tt) ** 2).sum()
         loss.backward()
         return loss
@@ -340,7 +343,8 @@ def bench_diff(args):
     flops = 2.0 * 2.0 * wl.m * wl.p * draws
     t1 = time.perf_counter()
     grads = api.matmul_adjoint_reparam(*[t.detach() for t in leaves], wl.c, wl.n_samples,
-                                       torch.ones((wl.m, wl.p), dtype=torch.float64, device=dev), prec=prec)
+                                       torch.ones((wl.m, wl.p), dtype=torch.float64, device=dev), prec=prec,
+                                       value16=v16)
     torch.cuda.synchronize()
     adj_ms = 1e3 * (time.perf_counter() - t1)
     out = {"metric": "MLMC product estimates/s with gradients (forward + adjoint)", "value": args.steps / elapsed,
@@ -348,7 +352,7 @@ def bench_diff(args):
            "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": {"fp32": "f32", "bf16": "bf16"}[prec], "data": "synthetic",
            "config": {"workload": wl.name, "m": wl.m, "n": wl.n, "p": wl.p, "levels": len(wl.c), "c0": wl.c[0],
-                      "n_samples": wl.n_samples, "prec": prec},
+                      "n_samples": wl.n_samples, "prec": prec, "value_bits": 16 if v16 else 23},
            "adjoint_ms_wall": adj_ms,
            "adjoint_roofline": {"bound": "mfma", "achieved": flops / (adj_ms * 1e-3) / 1e12,
                                 "peak": PEAK_MFMA[prec] / 1e12, "unit": "TFLOP/s",
