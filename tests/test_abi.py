@@ -174,7 +174,7 @@ def test_adjoint_rejects_fp64_and_fp8(L):
 
 
 def test_weighted_draws_rejected_with_fp8_and_in_batches(L):
-    from paper_1904_00429_amd._lib import Problem, Tuning
+    from paper_1904_00429_amd._lib import Problem
     lv, keep = _levels([2, 4], [4, 4], prec=3)
     lv.index_weights = 16
     A, B = _dist(), _dist()

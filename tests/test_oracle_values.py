@@ -6,7 +6,6 @@ a repeated index reuses it, Alg. 1 draws the pair A^(k), B^(k) before the
 indices) and the uniform map's exactness.
 """
 import numpy as np
-import pytest
 from scipy import stats
 
 
