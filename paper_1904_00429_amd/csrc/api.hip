@@ -49,7 +49,9 @@ mlmc_status check_levels(const mlmc_levels* lv, bool inner)
             return fail(MLMC_EINVAL, "c[%d] = %lld is not an integer multiple >= 2 of c[%d] = %lld", l,
                         (long long)lv->c[l], l - 1, (long long)lv->c[l - 1]);
     }
-    if (lv->c[lv->num_levels - 1] >= kU32) return fail(MLMC_EINVAL, "c_L must be < 2^32");
+    // below 2^31, every 32-bit count of draws, pairs, quads and padded K
+    // positions the kernels form from c stays in range
+    if (lv->c[lv->num_levels - 1] >= ((int64_t)1 << 31)) return fail(MLMC_EINVAL, "c_L must be < 2^31");
     if (lv->prec < MLMC_PREC_FP64 || lv->prec > (inner ? MLMC_PREC_FP32 : MLMC_PREC_FP8))
         return fail(MLMC_EINVAL, "unsupported precision %d", lv->prec);
     if (lv->problem >= (1u << 20)) return fail(MLMC_EINVAL, "problem id must be < 2^20");

@@ -64,6 +64,7 @@ def _dist(law=0, loc=0.0, scale=1.0):
 
 @pytest.mark.parametrize("case", [
     dict(m=0), dict(p=0), dict(n=0), dict(n=2**32), dict(c=[]), dict(c=[4, 6]), dict(c=[4, 4]),
+    dict(c=[2, 2**31]), dict(c=[2**32 - 1]),
     dict(c=[0, 4]), dict(N=[1, 0]), dict(N=None), dict(eps=1.0, pilot=1, N=None),
     dict(eps=1.0, pilot=10), dict(prec=7), dict(lawA=2), dict(out=False),
 ])
@@ -102,6 +103,17 @@ def test_inner_rejects_bf16(L):
     st = L.mlmc_inner_product_estimate(16, ctypes.byref(A), ctypes.byref(B), ctypes.byref(lv), 8, None,
                                        16, 1 << 30, None, None)
     assert st == 1
+
+
+@pytest.mark.parametrize("c", [[2**31], [3, 3 * 2**30], [2**32 - 1]])
+def test_inner_rejects_ladders_from_2pow31(L, c):
+    # the kernels count draws, pairs and quads of a realisation in 32 bits
+    lv, keep = _levels(c, [4] * len(c), prec=0)
+    A, B = _dist(), _dist()
+    st = L.mlmc_inner_product_estimate(16, ctypes.byref(A), ctypes.byref(B), ctypes.byref(lv), 8, None,
+                                       16, 1 << 30, None, None)
+    assert st == 1
+    assert b"2^31" in L.mlmc_last_error()
 
 
 def test_workspace_size_scales_with_shape(L):
