@@ -47,7 +47,7 @@ def slots_per_draw_inner(n: int, word32: bool = False) -> float:
 # MI355X VALU issue: 256 CUs x 128 lanes per clock x 2.4 GHz = 78.6 T lane-ops/s
 # (the 157.3 TFLOP/s FP32 vector peak counts an FMA as two flops).
 PEAK_VALU_SLOTS = 256 * 128 * 2.4e9
-PEAK_MFMA = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15}
+PEAK_MFMA = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "fp8": 5.0e15}
 PEAK_HBM = 8.0e12
 
 

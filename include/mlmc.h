@@ -158,7 +158,8 @@ typedef struct {
 
 /* The level ladder and the sampling mode (Alg. 2 with a fixed finest level).
  *   c[l]: indices per realisation at level l (host array, num_levels entries);
- *         c[0] >= 1, c[l] an integer multiple >= 2 of c[l-1], c_L < 2^31.
+ *         c[0] >= 1, c[l] an integer multiple >= 2 of c[l-1], c_L < 2^31
+ *         (inner product), c_L < 2^28 (matrix products and the adjoint).
  *   Fixed mode: n_samples[l] = N_l >= 1 (host array), rmse_target = 0.
  *   Target mode: n_samples = NULL, rmse_target = eps > 0 (total Frobenius
  *         RMSE: E||Y - E[AB]||_F^2 <= eps^2); pilot_samples >= 2 realisations

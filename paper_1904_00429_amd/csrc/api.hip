@@ -52,6 +52,11 @@ mlmc_status check_levels(const mlmc_levels* lv, bool inner)
     // below 2^31, every 32-bit count of draws, pairs, quads and padded K
     // positions the kernels form from c stays in range
     if (lv->c[lv->num_levels - 1] >= ((int64_t)1 << 31)) return fail(MLMC_EINVAL, "c_L must be < 2^31");
+    // matrix products: the gather grid has 8 lanes per padded K position in
+    // one 32-bit launch dimension, and a pass's padded positions are counted
+    // in 32 bits; c_L < 2^28 keeps both in range
+    if (!inner && lv->c[lv->num_levels - 1] >= ((int64_t)1 << 28))
+        return fail(MLMC_EINVAL, "matrix products need c_L < 2^28");
     if (lv->prec < MLMC_PREC_FP64 || lv->prec > (inner ? MLMC_PREC_FP32 : MLMC_PREC_FP8))
         return fail(MLMC_EINVAL, "unsupported precision %d", lv->prec);
     if (lv->problem >= (1u << 20)) return fail(MLMC_EINVAL, "problem id must be < 2^20");
@@ -111,6 +116,9 @@ mlmc_status check_pair(const mlmc_dist* a, const mlmc_dist* b, int32_t prec, uin
     const bool ea = a->law >= MLMC_LAW_RAMP_NORMAL, eb = b->law >= MLMC_LAW_RAMP_NORMAL;
     if (ea != eb) return fail(MLMC_EINVAL, "the laws of the experiments pair only with each other");
     if (ea && prec == MLMC_PREC_FP8) return fail(MLMC_EINVAL, "the laws of the experiments are not offered with FP8");
+    // the FP8 operand scales are derived from i.i.d. law parameters
+    if ((a->law == MLMC_LAW_REPARAM || b->law == MLMC_LAW_REPARAM) && prec == MLMC_PREC_FP8)
+        return fail(MLMC_EINVAL, "reparameterised laws are not offered with FP8 operands");
     if (ea && (flags & MLMC_FLAG_VALUE16))
         return fail(MLMC_EINVAL, "the laws of the experiments have their own stream (no 16-bit values)");
     return MLMC_OK;

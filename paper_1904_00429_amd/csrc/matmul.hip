@@ -1574,6 +1574,8 @@ hipError_t matmul_level_run(const MatmulPlan& plan, const LevelRange& lr, int64_
     int64_t level_batch = plan.gather_bytes / per_sample;
     if (level_batch < 1) level_batch = 1;
     if (level_batch > 65535) level_batch = 65535;
+    // the sketch counts a group's padded positions in 32 bits
+    if (level_batch > INT32_MAX / kpad) level_batch = INT32_MAX / kpad;
     for (int64_t b = 0; b < lr.count; b += level_batch) {
         const int64_t batch = (lr.count - b) < level_batch ? (lr.count - b) : level_batch;
         hipError_t err;

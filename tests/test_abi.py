@@ -64,7 +64,7 @@ def _dist(law=0, loc=0.0, scale=1.0):
 
 @pytest.mark.parametrize("case", [
     dict(m=0), dict(p=0), dict(n=0), dict(n=2**32), dict(c=[]), dict(c=[4, 6]), dict(c=[4, 4]),
-    dict(c=[2, 2**31]), dict(c=[2**32 - 1]),
+    dict(c=[2, 2**31]), dict(c=[2**32 - 1]), dict(c=[2**27, 2**28]), dict(lawA=2, prec=3),
     dict(c=[0, 4]), dict(N=[1, 0]), dict(N=None), dict(eps=1.0, pilot=1, N=None),
     dict(eps=1.0, pilot=10), dict(prec=7), dict(lawA=2), dict(out=False),
 ])
@@ -171,6 +171,15 @@ def test_adaptive_levels_need_target_mode(L):
     st = L.mlmc_inner_product_estimate(16, ctypes.byref(A), ctypes.byref(B), ctypes.byref(lv), 8, None,
                                        16, 1 << 40, None, None)
     assert st == 1
+
+
+def test_matrix_ladder_cap_in_workspace_size(L):
+    # c_L < 2^28 for matrix products (gather grid and 32-bit position counts),
+    # checked without a device call through the workspace query
+    for c, ok in (([2**26, 2**27], True), ([2**27, 2**28], False), ([3, 2**29 * 3], False)):
+        lv, keep = _levels(c, [4, 4], prec=1)
+        assert (L.mlmc_matmul_workspace_size(4, 16, 3, ctypes.byref(lv)) > 0) == ok, c
+        assert (L.mlmc_matmul_adjoint_workspace_size(4, 16, 3, ctypes.byref(lv)) > 0) == ok, c
 
 
 def test_adjoint_rejects_fp64_and_fp8(L):
