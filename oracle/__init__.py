@@ -74,7 +74,8 @@ class _Law(ctypes.Structure):
     _fields_ = [("law", ctypes.c_int32), ("loc", ctypes.c_double),
                 ("scale", ctypes.c_double), ("mean", ctypes.c_void_p),
                 ("stdev", ctypes.c_void_p), ("ld", ctypes.c_int64),
-                ("exp_neg_loc", ctypes.c_double), ("value16", ctypes.c_int32)]
+                ("exp_neg_loc", ctypes.c_double), ("value16", ctypes.c_int32),
+                ("operand", ctypes.c_int32), ("scale_exp", ctypes.c_void_p)]
 
 
 class _Weights(ctypes.Structure):
@@ -126,6 +127,10 @@ def lib():
                                               ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(_Weights)]
         L.orc_optimal_weights.argtypes = ([ctypes.c_int64] * 3 + [ctypes.POINTER(_Law)] * 2 + [ctypes.c_void_p])
         L.orc_sketch_pair_weighted.argtypes = [ctypes.c_int64] * 5 + [ctypes.c_void_p] * 5
+        L.orc_operand_value.restype = ctypes.c_double
+        L.orc_operand_value.argtypes = [ctypes.POINTER(_Law), ctypes.c_int64, ctypes.c_double]
+        L.orc_reparam_bounds.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                         ctypes.c_int64, ctypes.c_void_p]
         L.orc_apply_func.restype = ctypes.c_double
         L.orc_apply_func.argtypes = [ctypes.POINTER(_Func), ctypes.c_double]
         L.orc_level_entries.argtypes = (
@@ -158,6 +163,8 @@ class Law:
     stdev: Optional[np.ndarray] = None
     ld: int = 0
     value16: bool = False     # laws 0-2: 16-bit uniforms, eight per Philox call
+    operand: int = 0          # OPERAND_*: the format the contraction reads the values in
+    scale_exp: Optional[np.ndarray] = None   # FP8: exponent s of 2^s per row of A / column of B
     _keep: list = field(default_factory=list, repr=False)
 
     @staticmethod
@@ -183,7 +190,16 @@ class Law:
         j takes the low (even e) or high (odd e) half h of word (e/2) % 4 of
         the call (e/8, k, j, value stream), u = (h + 1/2) 2^-16; normals by
         Box-Muller on the pair (e & ~1, e | 1), which shares one word."""
-        return Law(self.law, self.loc, self.scale, self.mean, self.stdev, self.ld, True)
+        return Law(self.law, self.loc, self.scale, self.mean, self.stdev, self.ld, True, self.operand,
+                   self.scale_exp)
+
+    def with_operand(self, operand: int, scale_exp: Optional[np.ndarray] = None) -> "Law":
+        """The same law read by the contraction in a narrower format
+        (orc_operand_value): OPERAND_BF16, or OPERAND_FP8_E4M3 with the
+        exponents s of the power-of-two scales 2^s of every row of A (or
+        column of B), e.g. from fp8_scale_exponents."""
+        se = None if scale_exp is None else np.ascontiguousarray(scale_exp, dtype=np.int32)
+        return Law(self.law, self.loc, self.scale, self.mean, self.stdev, self.ld, self.value16, int(operand), se)
 
     def c(self) -> _Law:
         s = _Law()
@@ -192,11 +208,52 @@ class Law:
         s.scale = self.scale
         s.exp_neg_loc = math.exp(-self.loc) if self.law in (LAW_COS_POISSON_EXP, LAW_COS_POISSON_STEP) else 0.0
         s.value16 = 1 if self.value16 else 0
+        s.operand = self.operand
+        s.scale_exp = _ptr(self.scale_exp) if self.scale_exp is not None else None
         if self.law == LAW_REPARAM:
             s.mean = _ptr(self.mean)
             s.stdev = _ptr(self.stdev)
             s.ld = self.ld
         return s
+
+
+OPERAND_EXACT, OPERAND_BF16, OPERAND_FP8_E4M3 = 0, 1, 2
+
+
+def operand_value(law: Law, idx: int, v: float) -> float:
+    """orc_operand_value: v as the contraction reads it under law.operand."""
+    return float(lib().orc_operand_value(ctypes.byref(law.c()), int(idx), float(v)))
+
+
+def fp8_scale_exponent(bound: float) -> int:
+    """The exponent s of the FP8 operand scale 2^s: the largest s with
+    2^s bound <= 256 (entries up to the bound then sit in e4m3's top binades,
+    below its largest value 448), clamped to [-20, 20]; 0 for a zero bound.
+    Exact: bound = f 2^E with f in [1/2, 1) gives s = 8 - E, or 9 - E when
+    f = 1/2."""
+    if not bound > 0.0:
+        return 0
+    f, E = math.frexp(bound)
+    s = 8 - E + (1 if f == 0.5 else 0)
+    return max(-20, min(20, s))
+
+
+def fp8_scale_exponents(law: Law, count: int, side: str) -> np.ndarray:
+    """Scale exponents of the rows of A (side "A", count = m) or the columns
+    of B (side "B", count = p).  The bound of an entry is |loc| + 6 |scale|
+    (normal), |loc| + |scale| (uniform), fma(6, |stdev|, |mean|) per entry
+    (reparameterised; the maximum over the n columns of A's row or rows of
+    B's column)."""
+    if law.law == LAW_NORMAL:
+        return np.full(count, fp8_scale_exponent(abs(law.loc) + 6.0 * abs(law.scale)), dtype=np.int32)
+    if law.law == LAW_UNIFORM:
+        return np.full(count, fp8_scale_exponent(abs(law.loc) + abs(law.scale)), dtype=np.int32)
+    if law.law != LAW_REPARAM:
+        raise ValueError("FP8 operands take the normal, uniform or reparameterised laws")
+    n = law.mean.size // law.ld
+    bound = np.empty(count)
+    lib().orc_reparam_bounds(_ptr(law.mean), _ptr(law.stdev), n, law.ld, count, _ptr(bound))
+    return np.array([fp8_scale_exponent(b) for b in bound], dtype=np.int32)
 
 
 # --------------------------------------------------------------------------
@@ -439,6 +496,14 @@ class Estimate:
     rmse_est: float               # sqrt(sum_l V_l / N_l)
     levels_used: int = 0          # adaptive mode: levels that were run
     bias_test_passed: bool = True  # adaptive mode: the stopping test held
+    entry_var: Optional[np.ndarray] = None  # (L+1) x m x p: unbiased variance of one level sample per entry
+
+    @property
+    def entry_sd(self) -> np.ndarray:
+        """Standard deviation of every entry of Y: sqrt(sum_l var_l / N_l)
+        (levels are independent, eq. (10)); levels with no realisation add 0."""
+        N = np.maximum(np.asarray(self.n_used, dtype=np.float64), 1.0)
+        return np.sqrt(np.sum(self.entry_var / N[:, None, None], axis=0))
 
 
 def bias_bound(c: Sequence[int], L: int, eps: float, kind: str) -> float:
@@ -510,7 +575,7 @@ def estimate(m: int, n: int, p: int, A: Law, B: Law, c: Sequence[int],
         V = np.array([s.variance for s in states])
         N = np.array([s.count for s in states], dtype=np.int64)
         rmse = math.sqrt(float(np.sum(V[:used] / N[:used])))
-        return Estimate(means.sum(axis=0), means, V, N, rmse, used, passed)
+        return Estimate(means.sum(axis=0), means, V, N, rmse, used, passed, _entry_var(states, m, p))
     if rmse_target > 0:
         if pilot < 2:
             raise ValueError("target mode needs a pilot of at least 2 realisations")
@@ -528,7 +593,12 @@ def estimate(m: int, n: int, p: int, A: Law, B: Law, c: Sequence[int],
     V = np.array([s.variance for s in states])
     N = np.array([s.count for s in states], dtype=np.int64)
     rmse = math.sqrt(float(np.sum(V / N)))
-    return Estimate(means.sum(axis=0), means, V, N, rmse, L1, True)
+    return Estimate(means.sum(axis=0), means, V, N, rmse, L1, True, _entry_var(states, m, p))
+
+
+def _entry_var(states, m: int, p: int) -> np.ndarray:
+    """Per-entry unbiased variance of one level sample, M2 / (N_l - 1) (0 below two realisations)."""
+    return np.stack([s.m2.reshape(m, p) / (s.count - 1) if s.count >= 2 else np.zeros((m, p)) for s in states])
 
 
 @dataclass

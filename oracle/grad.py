@@ -77,3 +77,45 @@ def reparam_gradients(MA, SA, MB, SB, c, N, G, seed=0, problem=0, shared=False, 
     Y = reparam_estimate(*leaves, c, N, seed, problem, shared, weights, coupling, value16)
     (Y * torch.as_tensor(np.asarray(G, dtype=np.float64))).sum().backward()
     return Y.detach().numpy(), [t.grad.numpy() for t in leaves]
+
+
+def reparam_gradients_at(MA, SA, MB, SB, c, N, G, cols, seed=0, problem=0, coupling="prefix", value16=False):
+    """The same gradients restricted to the rows `cols` of MA, SA, MB, SB
+    (columns j of A and rows j of B), for products whose full gradient the
+    CPU cannot afford.
+
+    Only the terms a_t b_t^T whose draw r_t is one of `cols` depend on those
+    rows, so <G, Y> restricted to them has the same gradient there: every
+    index of every realisation is drawn (as reparam_estimate does), and only
+    the hit draws' columns are generated and entered into the restricted
+    objective sum_l (1/N_l) sum_k <G, Z_l^hits - Z_{l-1}^hits>.  Returns the
+    four gradients as arrays of shape (len(cols), m) and (len(cols), p)."""
+    cols = [int(j) for j in cols]
+    n, m = np.asarray(MA).shape
+    p = np.asarray(MB).shape[1]
+    pos = {j: i for i, j in enumerate(cols)}
+    J = torch.tensor(cols)
+    leaves = [torch.as_tensor(np.asarray(x, dtype=np.float64))[J].clone().requires_grad_(True)
+              for x in (MA, SA, MB, SB)]
+    mA, sA, mB, sB = leaves
+    Gt = torch.as_tensor(np.asarray(G, dtype=np.float64))
+    obj = torch.zeros((), dtype=torch.float64)
+    for l, (cl, Nl) in enumerate(zip(c, N)):
+        cp = c[l - 1] if l > 0 else 0
+        M = coupling_stride(cl, cp, coupling)
+        coarse = set(range(cp)) if M == 0 else {M * (i + 1) - 1 for i in range(cp)}
+        lf = level_field(l, False)
+        for k in range(Nl):
+            r = draw_indices(seed, problem, lf, k, cl, n)
+            hits = [t for t in range(cl) if int(r[t]) in pos]
+            if not hits:
+                continue
+            Z, W = standard_normals(seed, problem, lf, k, r[hits], m, p, value16)
+            idx = torch.tensor([pos[int(r[t])] for t in hits])
+            a = mA[idx] + sA[idx] * Z            # hit draws' a_t
+            b = mB[idx] + sB[idx] * W            # and b_t
+            wt = torch.tensor([n / cl - (n / cp if t in coarse else 0.0) for t in hits], dtype=torch.float64)
+            # <G, sum_t w_t a_t b_t^T> = sum_t w_t a_t^T G b_t
+            obj = obj + ((a @ Gt) * b).sum(dim=1).mul(wt).sum() / Nl
+    obj.backward()
+    return [t.grad.numpy() if t.grad is not None else np.zeros(tuple(t.shape)) for t in leaves]

@@ -96,7 +96,15 @@ typedef struct {
     int64_t ld;
     double exp_neg_loc;
     int32_t value16;   /* laws 0-2: 16-bit uniforms, two per 32-bit word (see value_uniform16) */
+    int32_t operand;   /* ORC_OPERAND_*: the format the contraction reads the value in (see operand_value) */
+    const int32_t* scale_exp;  /* FP8: exponent s of the power-of-two scale 2^s of each row of A (length m)
+                                  or column of B (length p); NULL: s = 0 */
 } orc_law;
+
+/* Operand formats of the precision form (Sec. 3's sketch with its gathered
+ * operands held in a narrower format; the contraction itself stays exact
+ * here, in FP64). */
+enum { ORC_OPERAND_EXACT = 0, ORC_OPERAND_BF16 = 1, ORC_OPERAND_FP8_E4M3 = 2 };
 
 /* Target function f of Sec. 3, applied entrywise to a sketch.
  *   ORC_F_IDENTITY:     f(x) = x
@@ -383,6 +391,65 @@ static double experiment_value(const orc_law* law, uint64_t seed, uint32_t probl
     return (u[1] < law->scale && K <= 5) ? cos((double)K) : 0.0;
 }
 
+/* x rounded to `bits` significant bits, ties to even (rint in the default
+ * rounding mode), with the spacing of the binade 2^min_exp kept below it
+ * (gradual underflow). */
+static double round_significand(double x, int bits, int min_exp)
+{
+    if (x == 0.0)
+        return x;
+    int E;
+    frexp(x, &E);                 /* |x| in [2^(E-1), 2^E) */
+    int e = E - 1;
+    if (e < min_exp)
+        e = min_exp;
+    double quantum = ldexp(1.0, e - (bits - 1));
+    return rint(x / quantum) * quantum;
+}
+
+/* The value v of a row of A or column of B (index idx) as the contraction
+ * reads it.  Values are generated in FP32 by the precision form, so v is
+ * first rounded to FP32; then
+ *   BF16: 8 significant bits (FP32's exponent range);
+ *   FP8 e4m3 (OCP: 4 exponent bits with bias 7, 3 mantissa bits, no
+ *   infinities, largest finite value 448, spacing 2^-9 below 2^-6): v is
+ *   multiplied by the power of two 2^s of its row or column, clamped to
+ *   [-448, 448], rounded to 4 significant bits, and divided by 2^s again
+ *   (the contraction undoes the scales exactly). */
+double orc_operand_value(const orc_law* law, int64_t idx, double v)
+{
+    if (law->operand == ORC_OPERAND_BF16)
+        return round_significand((double)(float)v, 8, -126);
+    if (law->operand == ORC_OPERAND_FP8_E4M3) {
+        int s = law->scale_exp ? law->scale_exp[idx] : 0;
+        double x = (double)(float)ldexp(v, s);
+        if (x > 448.0)
+            x = 448.0;
+        if (x < -448.0)
+            x = -448.0;
+        return ldexp(round_significand(x, 4, -6), -s);
+    }
+    return v;
+}
+
+/* Bound of the reparameterised entries of each row i < count of A
+ * (element (i, j) at j*ld + i) or column of B (element (j, q) at j*ld + q):
+ * out[i] = max over the n columns (rows) j of fma(6, |stdev|, |mean|), the
+ * input of the FP8 scale rule. */
+void orc_reparam_bounds(const double* mean, const double* stdev, int64_t n, int64_t ld, int64_t count,
+                        double* out)
+{
+    for (int64_t i = 0; i < count; ++i) {
+        double b = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            double v = fma(6.0, fabs(stdev[j * ld + i]), fabs(mean[j * ld + i]));
+            if (v > b)
+                b = v;
+        }
+        out[i] = b;
+    }
+}
+
 /* Entry (row, col) of one realisation, produced from the element number e of
  * the column vector v_j. */
 static double law_value(const orc_law* law, uint64_t seed, uint32_t problem,
@@ -408,9 +475,9 @@ void orc_column(uint64_t seed, uint32_t problem, uint32_t level_field, uint32_t 
                 double* a, double* b)
 {
     for (int64_t i = 0; i < m; ++i)
-        a[i] = law_value(A, seed, problem, level_field, k, j, i, j * A->ld + i);
+        a[i] = orc_operand_value(A, i, law_value(A, seed, problem, level_field, k, j, i, j * A->ld + i));
     for (int64_t q = 0; q < p; ++q)
-        b[q] = law_value(B, seed, problem, level_field, k, j, m + q, j * B->ld + q);
+        b[q] = orc_operand_value(B, q, law_value(B, seed, problem, level_field, k, j, m + q, j * B->ld + q));
 }
 
 /* Draw number of the j-th coarse draw (0-based j): j (prefix), or
@@ -565,11 +632,11 @@ int orc_level_entries(int64_t m, int64_t n, int64_t p, const orc_law* A, const o
         for (int64_t t = 0; t < c_l; ++t) {
             int64_t j = r[t];
             for (int64_t a = 0; a < nr; ++a)
-                AS[t * nr + a] = law_value(A, seed, problem, level_field, (uint32_t)k, j, rows[a],
-                                           j * A->ld + rows[a]);
+                AS[t * nr + a] = orc_operand_value(A, rows[a], law_value(A, seed, problem, level_field, (uint32_t)k, j,
+                                                                         rows[a], j * A->ld + rows[a]));
             for (int64_t b = 0; b < nc; ++b)
-                BS[t * nc + b] = law_value(B, seed, problem, level_field, (uint32_t)k, j, m + cols[b],
-                                           j * B->ld + cols[b]);
+                BS[t * nc + b] = orc_operand_value(B, cols[b], law_value(B, seed, problem, level_field, (uint32_t)k, j,
+                                                                         m + cols[b], j * B->ld + cols[b]));
         }
         *count += 1;
         double cnt = (double)(*count);

@@ -33,7 +33,7 @@ def test_slots_per_draw_inner():
 
 def test_peaks_are_the_published_ones():
     assert bench.PEAK_VALU_SLOTS == pytest.approx(78.6e12, rel=1e-3)
-    assert bench.PEAK_MFMA == {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15}
+    assert bench.PEAK_MFMA == {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "fp8": 5.0e15}
     assert bench.PEAK_HBM == 8.0e12
 
 
@@ -45,3 +45,8 @@ def test_peaks_are_the_published_ones():
 def test_value_bits_choice(monkeypatch, bits, expect):
     monkeypatch.setitem(bench._OPTS, "value_bits", bits)
     assert {p: bench._value16(p) for p in expect} == expect
+
+
+def test_host_threads_and_cpu_model():
+    assert 1 <= bench.host_threads() <= 16
+    assert isinstance(bench.cpu_model(), str) and bench.cpu_model()

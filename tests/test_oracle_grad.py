@@ -82,3 +82,20 @@ def test_expected_gradient_of_linear_functional(grad_mod):
         se = a.std(axis=0, ddof=1) / math.sqrt(seeds) + 1e-12
         z = np.abs(mean - expected[i]) / se
         assert z.max() < 5.0, (i, z.max())
+
+
+@pytest.mark.parametrize("coupling", ["prefix", "stride"])
+def test_restricted_gradient_equals_full_rows(coupling):
+    """The entry-restricted gradient equals the full autograd gradient at the
+    chosen rows (including rows no draw hit, whose gradient is 0)."""
+    from oracle import grad as og
+    rng = np.random.default_rng(5)
+    m, n, p, c, N = 7, 23, 5, [2, 4, 8], [12, 6, 3]
+    MA, MB = rng.standard_normal((n, m)), rng.standard_normal((n, p))
+    SA, SB = rng.uniform(0.1, 1, (n, m)), rng.uniform(0.1, 1, (n, p))
+    G = rng.standard_normal((m, p))
+    _, full = og.reparam_gradients(MA, SA, MB, SB, c, N, G, seed=4, coupling=coupling)
+    cols = [0, 5, 9, 22, 13]
+    part = og.reparam_gradients_at(MA, SA, MB, SB, c, N, G, cols, seed=4, coupling=coupling)
+    for f, g in zip(full, part):
+        np.testing.assert_allclose(g, f[cols], rtol=1e-12, atol=1e-12 * np.abs(f).max())
