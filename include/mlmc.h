@@ -229,6 +229,31 @@ mlmc_status mlmc_inner_product_estimate(int64_t n, const mlmc_dist* x, const mlm
                                         size_t workspace_bytes, mlmc_report* report,
                                         void* stream);
 
+/* ---- Allocation-free inner product -----------------------------------------
+ * For callers that cannot allocate device memory or pass a workspace: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  The same estimate as mlmc_inner_product_estimate (same
+ * arguments, modes and results, bit for bit), with its workspace taken from a
+ * fixed device array of MLMC_NOALLOC_SCRATCH_BYTES that the library holds on
+ * each GPU it runs on until the process ends (its address is looked up once
+ * per device, on the first call there).  The caller still passes the output
+ * (and level_means).  Nothing is allocated: no hipMalloc, hipFree or torch
+ * allocation.
+ *   Limit: the workspace the estimate needs must fit the array; it does for
+ *   any n and ladder with uniform draws (about 0.2 MB); weighted draws add
+ *   8 n bytes (n up to about 4.9e5).  Beyond it: MLMC_EINVAL.
+ *   Every call on one GPU shares that GPU's array and leaves the last call's
+ *   contents in it (each call clears what must start at zero); calls that
+ *   overlap on one GPU (concurrent streams or threads) race and give wrong
+ *   results.  Errors: as mlmc_inner_product_estimate, plus EINVAL above the
+ *   limit and EDEVICE if the array's address cannot be obtained. */
+#define MLMC_NOALLOC_SCRATCH_BYTES ((size_t)4 << 20)
+size_t mlmc_inner_product_noalloc_limit(void);
+mlmc_status mlmc_inner_product_estimate_noalloc(int64_t n, const mlmc_dist* x, const mlmc_dist* y,
+                                                const mlmc_levels* levels, double* out,
+                                                double* level_means, mlmc_report* report,
+                                                void* stream);
+
 /* ---- Batching --------------------------------------------------------------
  * Many independent products of uneven shapes through one pipeline: every pass
  * gathers the sampled columns of all products in one launch, one persistent

@@ -17,6 +17,7 @@ EXPORTED = [
     "mlmc_matmul_batched_workspace_size", "mlmc_matmul_estimate_batched",
     "mlmc_matmul_batched_graph_create", "mlmc_graph_launch", "mlmc_graph_destroy",
     "mlmc_optimal_index_weights", "mlmc_sample_indices_weighted",
+    "mlmc_inner_product_noalloc_limit", "mlmc_inner_product_estimate_noalloc",
 ]
 
 
@@ -81,6 +82,10 @@ def lib() -> ctypes.CDLL:
     L.mlmc_matmul_estimate.argtypes = [i64, i64, i64, DP, DP, LP, vp, vp, vp, ctypes.c_size_t, RP, vp]
     L.mlmc_inner_product_estimate.restype = ctypes.c_int
     L.mlmc_inner_product_estimate.argtypes = [i64, DP, DP, LP, vp, vp, vp, ctypes.c_size_t, RP, vp]
+    L.mlmc_inner_product_noalloc_limit.restype = ctypes.c_size_t
+    L.mlmc_inner_product_noalloc_limit.argtypes = []
+    L.mlmc_inner_product_estimate_noalloc.restype = ctypes.c_int
+    L.mlmc_inner_product_estimate_noalloc.argtypes = [i64, DP, DP, LP, vp, vp, RP, vp]
     L.mlmc_philox4x32_10.restype = ctypes.c_int
     L.mlmc_philox4x32_10.argtypes = [i64, vp, u64, vp, vp]
     L.mlmc_sample_indices.restype = ctypes.c_int

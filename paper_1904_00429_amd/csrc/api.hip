@@ -6,6 +6,7 @@
 #include <stdio.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -551,6 +552,80 @@ mlmc_status mlmc_matmul_estimate(int64_t m, int64_t n, int64_t p, const mlmc_dis
         fill_report(lv, counts.data(), var.data(), timer, report, used, passed);
     }
     return MLMC_OK;
+}
+
+}  // extern "C"
+
+// ---- allocation-free inner product ----------------------------------------
+// The inner-product estimator's device workspace (level states, workgroup
+// partials, V_l, cumulative index weights) as one fixed array per GPU, for
+// callers that cannot allocate.  In host code the name `scratch` is a
+// host-side stand-in, not a device address: only the address that
+// hipGetSymbolAddress returns, taken once per device with that device
+// current, is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[MLMC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices];
+
+// The device address of `scratch` on the device of `stream` (the current
+// device for the null stream).
+mlmc_status scratch_for_stream(hipStream_t stream, void** out)
+{
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return device_fail(e, "hipGetDevice");
+    int dev = cur;
+    if (stream && (e = hipStreamGetDevice(stream, &dev)) != hipSuccess) return device_fail(e, "hipStreamGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(MLMC_EDEVICE, "device %d is beyond the library's table of %d", dev,
+                                                   kMaxDevices);
+    std::lock_guard<std::mutex> guard(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        if (dev != cur && (e = hipSetDevice(dev)) != hipSuccess) return device_fail(e, "hipSetDevice");
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (dev != cur) {
+            const hipError_t r = hipSetDevice(cur);
+            if (e == hipSuccess && r != hipSuccess) return device_fail(r, "hipSetDevice (restore)");
+        }
+        if (e != hipSuccess) return device_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(MLMC_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MLMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mlmc_inner_product_noalloc_limit(void) { return MLMC_NOALLOC_SCRATCH_BYTES; }
+
+mlmc_status mlmc_inner_product_estimate_noalloc(int64_t n, const mlmc_dist* x, const mlmc_dist* y,
+                                                const mlmc_levels* lv, double* out, double* level_means,
+                                                mlmc_report* report, void* stream_ptr)
+{
+    g_last_error.clear();
+    if (!lv || lv->num_levels < 1 || lv->num_levels > MLMC_MAX_LEVELS)
+        return fail(MLMC_EINVAL, "num_levels must be in [1, %d]", MLMC_MAX_LEVELS);
+    if (n < 1 || n >= kU32) return fail(MLMC_EINVAL, "n must be in [1, 2^32)");
+    const size_t need = inner_layout(lv->num_levels, n, lv->index_weights != nullptr).total;
+    if (need > MLMC_NOALLOC_SCRATCH_BYTES)
+        return fail(MLMC_EINVAL,
+                    "the estimate needs %zu bytes of scratch, beyond the allocation-free limit of %zu "
+                    "(weighted draws need 8 n bytes: n too large)",
+                    need, (size_t)MLMC_NOALLOC_SCRATCH_BYTES);
+    void* ws = nullptr;
+    const mlmc_status st = scratch_for_stream(static_cast<hipStream_t>(stream_ptr), &ws);
+    if (st != MLMC_OK) return st;
+    // the estimator clears its level states itself and writes every partial
+    // before it reads it, so the previous call's contents do not matter
+    return mlmc_inner_product_estimate(n, x, y, lv, out, level_means, ws, MLMC_NOALLOC_SCRATCH_BYTES, report,
+                                       stream_ptr);
 }
 
 }  // extern "C"

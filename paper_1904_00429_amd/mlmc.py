@@ -252,6 +252,30 @@ def inner_product_estimate(n: int, x: Law, y: Law, c: Sequence[int],
     return _result(out, means, rep, len(c))
 
 
+def inner_product_estimate_noalloc(n: int, x: Law, y: Law, c: Sequence[int],
+                                   n_samples: Optional[Sequence[int]] = None, rmse_target: float = 0.0,
+                                   pilot: int = 0, seed: int = 0, prec: str = "fp64", out: torch.Tensor = None,
+                                   level_means: Optional[torch.Tensor] = None, report: bool = True,
+                                   func: Optional[Func] = None, adaptive: bool = False,
+                                   index_weights: Optional[torch.Tensor] = None, coupling: str = "prefix",
+                                   index_word32: bool = False) -> Result:
+    """mlmc_inner_product_estimate_noalloc: the inner-product estimate with
+    the library's fixed per-GPU scratch array as its workspace.  The caller
+    passes the output (a device FP64 scalar) and, optionally, the level-means
+    vector; nothing is allocated here."""
+    if out is None:
+        raise ValueError("out (a device FP64 scalar tensor) is required")
+    h = _LevelsHolder(c, n_samples, rmse_target, pilot, seed, prec, False, 0, 0, func,
+                      adaptive, index_weights, coupling, index_word32)
+    dx, dy = x.c(), y.c()
+    rep = Report()
+    check(lib().mlmc_inner_product_estimate_noalloc(int(n), ctypes.byref(dx), ctypes.byref(dy),
+                                                    ctypes.byref(h.lv), out.data_ptr(),
+                                                    level_means.data_ptr() if level_means is not None else None,
+                                                    ctypes.byref(rep) if report else None, _stream(out.device)))
+    return _result(out, level_means, rep, len(c))
+
+
 def philox(ctr: torch.Tensor, seed: int) -> torch.Tensor:
     """Philox4x32-10 of device counters (count x 4, int32 holding uint32 bits)."""
     ctr = ctr.contiguous()

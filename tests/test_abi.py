@@ -282,3 +282,23 @@ def test_value16_validated(L):
     st = L.mlmc_matmul_estimate(4, 16, 3, ctypes.byref(X), ctypes.byref(Y), ctypes.byref(lv), 8, None,
                                 16, 1 << 40, None, None)
     assert st == 1 and b"own stream" in L.mlmc_last_error()
+
+
+def test_noalloc_limit_checked_before_the_device(L):
+    # weighted draws need 8 n bytes of scratch: beyond the fixed array -> EINVAL,
+    # decided on the host before any device call
+    limit = L.mlmc_inner_product_noalloc_limit()
+    assert limit == 4 << 20
+    lv, keep = _levels([4, 8], [10, 10], prec=0)
+    lv.index_weights = 8   # never dereferenced: the size check comes first
+    A, B = _dist(), _dist()
+    n = limit // 8 + 1024
+    st = L.mlmc_inner_product_estimate_noalloc(n, ctypes.byref(A), ctypes.byref(B), ctypes.byref(lv), 8, None,
+                                               None, None)
+    assert st == 1
+    assert b"allocation-free limit" in L.mlmc_last_error()
+    bad, keep2 = _levels([4, 8], [10, 10], prec=0)
+    bad.num_levels = 0
+    st = L.mlmc_inner_product_estimate_noalloc(16, ctypes.byref(A), ctypes.byref(B), ctypes.byref(bad), 8, None,
+                                               None, None)
+    assert st == 1
