@@ -72,9 +72,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="inner", choices=["inner", "matmul-large", "matmul-small", "diff", "batched", "matmul-large-fixed",
+    ap.add_argument("--workload", default="matmul-large", choices=["inner", "matmul-large", "matmul-small", "diff", "batched", "matmul-large-fixed",
                              "importance", "experiments"])
-    ap.add_argument("--prec", default=None, help="fp32 (default) or fp64; bf16 for matmul")
+    ap.add_argument("--prec", default=None,
+                    help="matmul-large: fp64 (default), fp32, bf16 or fp8; inner: fp32 (default) or fp64")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="matmul-large: skip the FP32 and BF16 runs of the same workload after the headline")
+    ap.add_argument("--form-steps", type=int, default=None,
+                    help="timed estimates of each extra precision (default: max(3, steps / 2))")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-check", action="store_true",
                     help="skip the low-precision vs FP64 comparison of the matrix workloads")
@@ -126,37 +131,84 @@ def cpu_baseline_inner(wl, n_used, fraction, func="identity", word32=False):
                       f"realisations), {dt:.1f} s, scaled by draws"}
 
 
-def cpu_baseline_matmul(wl, n_used, fraction, edge=256, func="identity"):
-    """The oracle (one core) on the same ladder, laws and N_l with m = p = edge.
+def cpu_model() -> str:
+    """The host CPU's model name (as lscpu prints it)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads() -> int:
+    """Threads the all-cores baseline uses: the CPUs this process may run on,
+    at most 16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline_matmul(wl, n_used, fraction, edge=256, func="identity", all_fraction=0.004):
+    """The oracle on the same ladder, laws and N_l with m = p = edge, on one
+    core and on all the host threads.
 
     A full-shape realisation of the finest level costs the oracle minutes, so
-    each level runs max(1, fraction N_l) realisations at the reduced shape; the
-    time per realisation t_l gives sum_l N_l t_l, scaled by m p / edge^2 (the
+    each level runs a sample of realisations at the reduced shape; the time
+    per realisation t_l gives sum_l N_l t_l, scaled by m p / edge^2 (the
     oracle's sketch loop, m p (c_l + c_{l-1}) multiply-adds per realisation,
-    dominates its per-realisation cost)."""
+    dominates its per-realisation cost).  One core: max(1, fraction N_l)
+    realisations per level.  All threads: max(threads, all_fraction N_l)
+    realisations per level, split into one contiguous range per thread (the C
+    oracle runs outside the interpreter lock), timed by the wall clock."""
+    from concurrent.futures import ThreadPoolExecutor
     import oracle
     oracle.build(force=False)
     law = oracle.Law.normal(wl.law_a[1], wl.law_a[2])
     f = _oracle_func(oracle, func)
     m, p = min(edge, wl.m), min(edge, wl.p)
-    total = 0.0
-    run = 0
+    scale = (wl.m * wl.p) / float(m * p)
+
+    def run(l, k0, k1):
+        st = oracle.LevelState.empty(m, p)
+        oracle.level_estimation(st, m, wl.n, p, law, law, wl.c[l], wl.c[l - 1] if l else 0,
+                                wl.seed, 0, l, k0, k1, func=f)
+
+    total, run1 = 0.0, 0
     t_all = time.perf_counter()
     for l, N in enumerate(n_used):
         if N == 0:
             continue
         k = max(1, int(round(N * fraction)))
-        st = oracle.LevelState.empty(m, p)
         t0 = time.perf_counter()
-        oracle.level_estimation(st, m, wl.n, p, law, law, wl.c[l], wl.c[l - 1] if l else 0,
-                                wl.seed, 0, l, 0, k, func=f)
+        run(l, 0, k)
         total += N * (time.perf_counter() - t0) / k
-        run += k
-    total *= (wl.m * wl.p) / float(m * p)
-    dt = time.perf_counter() - t_all
-    return {"value": 1.0 / total, "unit": "estimates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{run} realisations (max(1, {fraction} N_l) per level) at m = p = {m}, {dt:.1f} s; "
-                      f"sum_l N_l t_l scaled by m p / {m * p}"}
+        run1 += k
+    dt1 = time.perf_counter() - t_all
+    threads = host_threads()
+    total_mt, run_mt = 0.0, 0
+    t_all = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        for l, N in enumerate(n_used):
+            if N == 0:
+                continue
+            k = max(threads, int(round(N * all_fraction)))
+            cuts = [k * i // threads for i in range(threads + 1)]
+            t0 = time.perf_counter()
+            list(ex.map(lambda i: run(l, cuts[i], cuts[i + 1]), range(threads)))
+            total_mt += N * (time.perf_counter() - t0) / k
+            run_mt += k
+    dtm = time.perf_counter() - t_all
+    return {"value": 1.0 / (total_mt * scale), "unit": "estimates/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"{run_mt} realisations (max({threads}, {all_fraction} N_l) per level, split over {threads} "
+                      f"threads) at m = p = {m}, {dtm:.1f} s wall; sum_l N_l t_l scaled by m p / {m * p}",
+            "one_core": {"value": 1.0 / (total * scale), "cores": 1,
+                         "sample": f"{run1} realisations (max(1, {fraction} N_l) per level) at m = p = {m}, "
+                                   f"{dt1:.1f} s"}}
 
 
 def main():
@@ -203,7 +255,7 @@ def main():
             return _inner(api, wl, x, prec, dev, want_timing, seed)
     else:
         wl = workloads.MATMUL_LARGE if args.workload == "matmul-large" else workloads.MATMUL_SMALL_FP64
-        prec = args.prec or ("bf16" if args.workload == "matmul-large" else "fp64")
+        prec = args.prec or "fp64"
         a = Law.normal(wl.law_a[1], wl.law_a[2])
         expected = wl.n * wl.law_a[1] * wl.law_b[1]
 
@@ -265,26 +317,69 @@ def main():
 
     out = {"metric": METRIC, "value": value, "unit": "estimates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16"}[prec],
+           "vs_baseline": None, "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16", "fp8": "fp8_e4m3"}[prec],
            "data": "synthetic (entries generated inside the estimate)", "config": config, "roofline": roof,
            "n_used": rep.n_used, "draws_per_step": draws / args.steps, "rmse_est": rep.rmse_est,
            "rmse_observed": rmse_obs, "levels_used": rep.levels_used, "kernel_ms_per_step": {
                "sample": k_ms[0] / args.steps, "gather": k_ms[1] / args.steps, "merge": k_ms[2] / args.steps,
                "final": k_ms[3] / args.steps}}
 
-    if args.workload != "inner" and prec != "fp64" and not args.no_precision_check and not args.adaptive:
-        # precision form: the same estimate (seed 0, the N_l of the last step,
-        # fixed mode) in the low precision and in FP64, outside the timed region
+    forms = {}
+    if args.workload == "matmul-large" and not args.no_forms and not args.adaptive:
+        # the same workload in the other precisions of the precision form:
+        # estimates/s and the sketch's share of its MFMA peak, each timed like
+        # the headline (fresh seeds, target mode, every value generated inside)
+        k_form = args.form_steps or max(3, args.steps // 2)
+        for pr in ("fp64", "fp32", "bf16"):
+            if pr == prec:
+                forms[pr] = {"estimates_per_s": value, "ms_per_estimate": ms_per_step,
+                             "sketch_frac": roof["frac"] if roof["bound"] == "mfma" else None}
+                continue
+            _matmul(api, wl, a, pr, dev, False, 2000)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            runs = [_matmul(api, wl, a, pr, dev, True, 3000 + i) for i in range(k_form)]
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t1) / k_form
+            sk_ms = sum(r.kernel_ms[0] for r in runs)
+            fl = 2.0 * wl.m * wl.p * sum(r.total_draws for r in runs)
+            forms[pr] = {"estimates_per_s": 1.0 / sec, "ms_per_estimate": 1e3 * sec, "steps": k_form,
+                         "value_bits": 16 if _value16(pr) else 23,
+                         "sketch_tflops": fl / (sk_ms * 1e-3) / 1e12,
+                         "sketch_frac": fl / (sk_ms * 1e-3) / PEAK_MFMA[pr],
+                         "kernel_ms_per_estimate": {
+                             "sketch": sk_ms / k_form, "gather": sum(r.kernel_ms[1] for r in runs) / k_form,
+                             "merge": sum(r.kernel_ms[2] for r in runs) / k_form,
+                             "final": sum(r.kernel_ms[3] for r in runs) / k_form},
+                         "rmse_est": runs[-1].rmse_est}
+            del runs
+        out["forms"] = forms
+        if "fp32" in forms and "bf16" in forms:
+            out["bf16_over_fp32"] = forms["bf16"]["estimates_per_s"] / forms["fp32"]["estimates_per_s"]
+
+    lps = [pr for pr in forms if pr != "fp64"] or ([prec] if prec != "fp64" else [])
+    if args.workload != "inner" and lps and not args.no_precision_check and not args.adaptive:
+        # precision form: the same estimate (seed 0, the N_l of the last timed
+        # step, fixed mode) in each lower precision and in FP64, outside the
+        # timed region; the rounding error is reported next to RMSE_est
         from paper_1904_00429_amd import matmul_estimate
-        ys = {}
-        for pr in (prec, "fp64"):
-            ys[pr] = matmul_estimate(wl.m, wl.n, wl.p, a, a, wl.c, n_samples=rep.n_used, seed=0, prec=pr,
-                                     device=dev, report=True, func=_OPTS["func"], value16=_value16(prec))
-        out["precision_check"] = {
-            "lp_minus_fp64_frob": float(torch.linalg.norm(ys[prec].Y - ys["fp64"].Y)),
-            "rmse_est_fp64": ys["fp64"].rmse_est, "seed": 0, "n_samples": rep.n_used}
-        del ys
+        y64 = {}                      # FP64 reference per value stream (16- or 23-bit uniforms)
+        checks = {}
+        for pr in lps:
+            v16 = _value16(pr)
+            if v16 not in y64:
+                y64[v16] = matmul_estimate(wl.m, wl.n, wl.p, a, a, wl.c, n_samples=rep.n_used, seed=0, prec="fp64",
+                                           device=dev, report=True, func=_OPTS["func"], value16=v16)
+            ylp = matmul_estimate(wl.m, wl.n, wl.p, a, a, wl.c, n_samples=rep.n_used, seed=0, prec=pr,
+                                  device=dev, report=True, func=_OPTS["func"], value16=v16)
+            d = float(torch.linalg.norm(ylp.Y - y64[v16].Y))
+            checks[pr] = {"lp_minus_fp64_frob": d, "rmse_est_fp64": y64[v16].rmse_est,
+                          "over_rmse_est": d / y64[v16].rmse_est, "value_bits": 16 if v16 else 23}
+            del ylp
+        out["precision_check"] = {"seed": 0, "n_samples": rep.n_used, "forms": checks}
+        del y64
         torch.cuda.empty_cache()
+
 
     if args.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
@@ -559,7 +654,7 @@ def bench_experiments(args):
     out = {"metric": "MLMC estimates/s of E[f(AB)] on the laws of Sec. 4.2 (adaptive L, eps 0.1 relative)",
            "value": e["estimates_per_s"], "unit": "estimates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": e["ms_per_estimate"], "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16"}[prec],
+           "scaling": "weak", "vs_baseline": None, "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16", "fp8": "fp8_e4m3"}[prec],
            "data": "synthetic (the laws of Sec. 4 generated inside the estimate)",
            "config": {"workload": wl.name, "m": wl.m, "n": wl.n, "p": wl.p, "ladder": "c_l = 10^l, l <= 6",
                       "func": "|x| H(2 - x)", "eps": e["eps"], "prec": prec, "adaptive": True},

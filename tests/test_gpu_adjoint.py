@@ -207,3 +207,28 @@ def test_autograd_bf16_forward_and_adjoint(orc, dev):
     _, ref = og.reparam_gradients(*params, c, N, 2 * (Yg - T), seed=3)
     for g, r in zip(leaves, ref):
         assert rel_frob(g.grad.cpu().numpy(), r) <= 1e-2
+
+
+@pytest.mark.parametrize("prec, tol", [("fp32", 1e-5), ("bf16", 1e-2)])
+def test_adjoint_full_workload_sampled_columns(orc, dev, prec, tol):
+    """The differentiation workload as benchmarked: 512 x 32768 x 512,
+    c_l = 32 * 2^l (l = 0..6), N_l = 4096 * 2^-l (about 28 draws hit each
+    column, so repeated indices and their atomic adds are the rule), checked
+    at eight columns j against the entry-restricted gradient reference."""
+    from oracle import grad as og
+    from paper_1904_00429_amd import matmul_adjoint_reparam, workloads
+    wl = workloads.DIFF_512x32768x512
+    m, n, p = wl.m, wl.n, wl.p
+    flush(f"adjoint full workload {prec}: N={wl.n_samples}")
+    params = _params(61, n, m, p)
+    G = np.random.default_rng(62).standard_normal((m, p))
+    dp = [torch.from_numpy(x).to(dev) for x in params]
+    got = [g.cpu().numpy() for g in matmul_adjoint_reparam(*dp, wl.c, wl.n_samples, torch.from_numpy(G), seed=8,
+                                                           prec=prec)]
+    cols = sorted(np.random.default_rng(63).choice(n, 8, replace=False).tolist())
+    ref = og.reparam_gradients_at(*params, wl.c, wl.n_samples, G, cols, seed=8)
+    for name, g, r in zip(("dMA", "dSA", "dMB", "dSB"), got, ref):
+        assert np.abs(r).max() > 0, name            # the sampled columns were drawn
+        err = rel_frob(g[cols], r)
+        flush(f"  {name} rel err at columns {cols}: {err:.3g}")
+        assert err <= tol, (name, err)

@@ -10,14 +10,13 @@ more than it moves the sketch: FP32 1e-5 relative, BF16 0.05 RMSE_est, FP8
 0.25 RMSE_est, as for the identity.  The laws put the sketches on both sides
 of the steps (means near the steps, spreads of order one at low levels).
 """
-import math
 import os
 from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
 
-from gpu_helpers import flush, laws, rel_frob
+from gpu_helpers import check_estimate, operand_law, flush, laws, rel_frob
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -45,25 +44,8 @@ def _funcs(orc, name):
     return orc.Func.abs_step(1e30), Func.abs_step(1e30)      # |x|
 
 
-def _compare(est, ref, prec):
-    Y = est.Y.cpu().numpy().reshape(ref.Y.shape)
-    V = np.array(est.level_var)
-    assert list(est.n_used) == list(ref.n_used)
-    if prec in ("bf16", "fp8"):
-        err = np.linalg.norm((Y - ref.Y).ravel())
-        flush(f"  {prec} rounding error {err:.4g} vs rmse_est {ref.rmse_est:.4g}")
-        assert err <= (0.05 if prec == "bf16" else 0.25) * ref.rmse_est
-        np.testing.assert_allclose(V, ref.level_var, rtol=3e-2 if prec == "bf16" else 0.15)
-        return
-    tol = 1e-12 if prec == "fp64" else 1e-5
-    means = est.level_means.cpu().numpy().reshape(ref.level_means.shape)
-    ynorm = float(np.linalg.norm(ref.Y.ravel()))
-    assert rel_frob(Y, ref.Y) <= tol, rel_frob(Y, ref.Y)
-    for l in range(len(V)):
-        d = np.linalg.norm((means[l] - ref.level_means[l]).ravel())
-        assert d <= tol * (math.sqrt(ref.level_var[l]) + ynorm), (l, d, ref.level_var[l])
-    np.testing.assert_allclose(V, ref.level_var, rtol=1e-10 if prec == "fp64" else 1e-5,
-                               atol=(tol * ynorm) ** 2)
+def _compare(est, ref, prec, ref_q=None, label=""):
+    check_estimate(est, ref, prec, ref_q, label)
 
 
 INNER_CASES = [
@@ -99,15 +81,17 @@ MATMUL_CASES = [
 def test_matmul_func_matches_oracle(orc, dev, pool, case, prec, fname):
     from paper_1904_00429_amd import matmul_estimate
     m, n, p, law, c, N = MATMUL_CASES[case]
-    if prec == "fp8" and law[0] != "normal":
-        pytest.skip("the FP8 form takes i.i.d. normal laws in these cases")
     flush(f"[matmul f] case {case} {prec} {fname}")
     oA, gA = laws(orc, law, dev)
     of, gf = _funcs(orc, fname)
     est = matmul_estimate(m, n, p, gA, gA, c, n_samples=N, seed=13, prec=prec, level_means=True, device=dev,
                           func=gf)
     ref = orc.estimate(m, n, p, oA, oA, c, n_samples=N, seed=13, pool=pool, func=of)
-    _compare(est, ref, prec)
+    ref_q = None
+    if prec in ("bf16", "fp8"):
+        ref_q = orc.estimate(m, n, p, operand_law(orc, oA, prec, m, "A"), operand_law(orc, oA, prec, p, "B"), c,
+                             n_samples=N, seed=13, pool=pool, func=of)
+    _compare(est, ref, prec, ref_q, f"case {case} {fname}")
 
 
 def test_matmul_func_single_level(orc, dev):

@@ -48,7 +48,7 @@ def test_inner_index32_matches_oracle(orc, dev, case):
     scale = abs(ref.Y[0, 0]) + float(np.sqrt(np.sum(np.asarray(ref.level_var) / np.asarray(N))))
     assert abs(y - ref.Y[0, 0]) <= tol * scale, (y, ref.Y[0, 0])
     # (n = 1: D_l = 0 for l >= 1 up to rounding, which the two sides leave differently)
-    np.testing.assert_allclose(est.level_var, ref.level_var, rtol=1e-10 if prec == "fp64" else 1e-4,
+    np.testing.assert_allclose(est.level_var, ref.level_var, rtol=1e-10 if prec == "fp64" else 1e-5,
                                atol=1e-20 * max(ref.level_var))
     if n > 1:
         # a different index stream from the 64-bit draws
