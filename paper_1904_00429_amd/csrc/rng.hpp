@@ -140,11 +140,80 @@ __device__ __forceinline__ void box_muller(float u, float v, float& z0, float& z
     z1 = rho * __builtin_amdgcn_sinf(v);
 }
 
+// FP64 pair for the uniforms of this library only (u, v on the grids
+// (h + 1/2) 2^-23 or 2^-16: in (0, 1), at most 24 significant bits), from
+// series with their range reductions done exactly:
+//   ln u: u = m 2^e with m in [sqrt(1/2), sqrt(2)); ln m = 2 atanh(s),
+//     s = (m - 1) / (m + 1), |s| <= 0.1716, summed as
+//     2 s (1 + s^2/3 + s^4/5 + ... + s^20/21) (the next term is below 1e-18
+//     relative);
+//   cos 2 pi v, sin 2 pi v: v = k/4 + r with k = rint(4 v) and |r| <= 1/8
+//     (both exact), the Taylor series of cos and sin at x = 2 pi r
+//     (|x| <= pi/4; terms to x^18 and x^17, the rest below 1e-19), then k
+//     quarter turns.
+// About two units in the last place; no argument reduction for large
+// arguments, no special cases.
+__device__ __forceinline__ double ln_unit(double u)
+{
+    int e;
+    double m = frexp(u, &e);                       // u = m 2^e, m in [1/2, 1)
+    if (m < 0.70710678118654752440) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0);
+    const double s2 = s * s;
+    double p = 1.0 / 21.0;
+    p = fma(p, s2, 1.0 / 19.0);
+    p = fma(p, s2, 1.0 / 17.0);
+    p = fma(p, s2, 1.0 / 15.0);
+    p = fma(p, s2, 1.0 / 13.0);
+    p = fma(p, s2, 1.0 / 11.0);
+    p = fma(p, s2, 1.0 / 9.0);
+    p = fma(p, s2, 1.0 / 7.0);
+    p = fma(p, s2, 1.0 / 5.0);
+    p = fma(p, s2, 1.0 / 3.0);
+    p = fma(p, s2, 1.0);
+    return fma((double)e, 0.69314718055994530942, 2.0 * s * p);
+}
+
+__device__ __forceinline__ void sincos_turns(double v, double& sn, double& cs)
+{
+    const double k = rint(4.0 * v);
+    const double r = fma(k, -0.25, v);
+    const double x = r * 6.283185307179586476925286766559;
+    const double x2 = x * x;
+    // sin x = x (1 - x^2/3! + x^4/5! - ... - x^16/17!)
+    double ps = -1.0 / 355687428096000.0;
+    ps = fma(ps, x2, 1.0 / 1307674368000.0);
+    ps = fma(ps, x2, -1.0 / 6227020800.0);
+    ps = fma(ps, x2, 1.0 / 39916800.0);
+    ps = fma(ps, x2, -1.0 / 362880.0);
+    ps = fma(ps, x2, 1.0 / 5040.0);
+    ps = fma(ps, x2, -1.0 / 120.0);
+    ps = fma(ps, x2, 1.0 / 6.0);
+    const double sx = fma(-x * x2, ps, x);
+    // cos x = 1 - x^2/2! + x^4/4! - ... - x^18/18!
+    double pc = -1.0 / 6402373705728000.0;
+    pc = fma(pc, x2, 1.0 / 20922789888000.0);
+    pc = fma(pc, x2, -1.0 / 87178291200.0);
+    pc = fma(pc, x2, 1.0 / 479001600.0);
+    pc = fma(pc, x2, -1.0 / 3628800.0);
+    pc = fma(pc, x2, 1.0 / 40320.0);
+    pc = fma(pc, x2, -1.0 / 720.0);
+    pc = fma(pc, x2, 1.0 / 24.0);
+    pc = fma(pc, x2, -0.5);
+    const double cx = fma(x2, pc, 1.0);
+    const int q = (int)k & 3;
+    sn = q == 0 ? sx : (q == 1 ? cx : (q == 2 ? -sx : -cx));
+    cs = q == 0 ? cx : (q == 1 ? -sx : (q == 2 ? -cx : sx));
+}
+
 __device__ __forceinline__ void box_muller(double u, double v, double& z0, double& z1)
 {
-    const double rho = sqrt(-2.0 * log(u));
+    const double rho = sqrt(-2.0 * ln_unit(u));
     double s, c;
-    sincos(6.283185307179586476925286766559 * v, &s, &c);
+    sincos_turns(v, s, c);
     z0 = rho * c;
     z1 = rho * s;
 }

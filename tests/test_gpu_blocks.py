@@ -65,3 +65,27 @@ def test_gather_columns(orc, dev, prec, rtol, atol, law):
             a, b = orc.column(7, 0, lev, k0 + s, r[t], m, p, oA, oB)
             np.testing.assert_allclose(AS[s, t], a, rtol=rtol, atol=atol)
             np.testing.assert_allclose(BS[s, t], b, rtol=rtol, atol=atol)
+
+
+def test_fp64_normals_to_a_few_ulp(orc, dev):
+    """The FP64 Box-Muller pairs (series for ln, cos and sin after exact range
+    reductions of the grid uniforms) against the oracle's libm on about 3e5
+    values.  The oracle rounds its angle 2 pi v to FP64 before the cosine (up
+    to 2^-51 absolute for angles in [4, 8)), so its z carries up to
+    rho 2^-51 <= 5.8 2^-51 (rho = sqrt(-2 ln u), u >= 2^-24) of its own:
+    bound 16 units in the last place of max(1, |z|)."""
+    from paper_1904_00429_amd import gather_columns
+    flush("gather fp64 normals, many values")
+    m, n, p, c, S = 300, 100003, 300, 64, 8
+    oA, gA = laws(orc, ("normal", 0.0, 1.0), dev)
+    AS, BS = gather_columns(m, n, p, gA, gA, 11, 0, 3, 0, S, c, prec="fp64", device=dev)
+    AS, BS = AS.cpu().numpy(), BS.cpu().numpy()
+    worst = 0.0
+    for s in range(S):
+        r = orc.draw_indices(11, 0, 3, s, c, n)
+        for t in range(c):
+            a, b = orc.column(11, 0, 3, s, r[t], m, p, oA, oA)
+            for got, ref in ((AS[s, t], a), (BS[s, t], b)):
+                worst = max(worst, float(np.max(np.abs(got - ref) / np.maximum(1.0, np.abs(ref)))))
+    flush(f"  max |dz| / max(1, |z|) = {worst:.3g} = {worst / 2.0 ** -52:.2f} ulp")
+    assert worst <= 16 * 2.0 ** -52
