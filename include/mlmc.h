@@ -80,9 +80,14 @@ typedef enum {
     MLMC_PREC_FP64 = 0,   /* values, products and sums in FP64 */
     MLMC_PREC_FP32 = 1,   /* values and contraction in FP32, statistics FP64 */
     MLMC_PREC_BF16 = 2,   /* gathered operands BF16 (RNE), FP32 accumulation (MFMA) */
-    MLMC_PREC_FP8 = 3     /* gathered operands OCP FP8 e4m3 (RNE, saturated), FP32 accumulation;
-                             per-product power-of-two pre-scales of A's columns and B's rows
-                             (one per matrix: the entries are i.i.d.), undone in the epilogue */
+    MLMC_PREC_FP8 = 3     /* gathered operands OCP FP8 e4m3 (RNE, saturated at +-448), FP32
+                             accumulation on v_mfma_scale_f32_32x32x64_f8f6f4: every row i of A
+                             and column q of B is multiplied by a power of two 2^s before its
+                             rounding, s the largest exponent with 2^s bound <= 256 (clamped to
+                             [-20, 20]), where bound = fma(6, |scale|, |loc|) (normal),
+                             |loc| + |scale| (uniform), or the maximum over the n columns of
+                             fma(6, |stdev|, |mean|) (reparameterised, per row / column); the
+                             MFMA's E8M0 operand scales undo the factors */
 } mlmc_prec;
 
 /* Target function f (Sec. 3): the estimate is of E[f(AB)] (E[f(x^T y)] for

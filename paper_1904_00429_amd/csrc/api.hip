@@ -117,9 +117,6 @@ mlmc_status check_pair(const mlmc_dist* a, const mlmc_dist* b, int32_t prec, uin
     const bool ea = a->law >= MLMC_LAW_RAMP_NORMAL, eb = b->law >= MLMC_LAW_RAMP_NORMAL;
     if (ea != eb) return fail(MLMC_EINVAL, "the laws of the experiments pair only with each other");
     if (ea && prec == MLMC_PREC_FP8) return fail(MLMC_EINVAL, "the laws of the experiments are not offered with FP8");
-    // the FP8 operand scales are derived from i.i.d. law parameters
-    if ((a->law == MLMC_LAW_REPARAM || b->law == MLMC_LAW_REPARAM) && prec == MLMC_PREC_FP8)
-        return fail(MLMC_EINVAL, "reparameterised laws are not offered with FP8 operands");
     if (ea && (flags & MLMC_FLAG_VALUE16))
         return fail(MLMC_EINVAL, "the laws of the experiments have their own stream (no 16-bit values)");
     return MLMC_OK;

@@ -100,8 +100,9 @@ struct ProblemDesc {
     int64_t rows_prefix;       // sum of (m_pad + p_pad) over earlier products
     int64_t mp_prefix;         // sum of m p over earlier products
     int64_t merge_blocks, between_prefix;
-    float pre_a, pre_b;        // FP8 operand pre-scales (powers of two), else 1
-    double post;               // 1 / (pre_a pre_b)
+    float pre_a, pre_b;        // FP8, i.i.d. laws: the row (column) factor 2^s folded into the law's constants, else 1
+    const int8_t* exp_a;       // FP8: exponent s of the factor 2^s of every row of A (m_pad) ...
+    const int8_t* exp_b;       // ... and column of B (p_pad), in workspace; NULL otherwise
     double mean0;              // E[Z_0] entry for i.i.d. laws: n E[a] E[b]
     double* out;
     double* level_means;
@@ -113,6 +114,7 @@ struct MatmulPlan {
     int64_t c[32];
     int nprob;
     int kstep, kpack, elem, nb, tile;
+    int kmem;                  // shortest padded realisation (a divisor of kstep)
     int laws;                  // law pair shared by every product (kLaws*), else kLawsAny
     TargetFunc func;           // f of E[f(AB)]; not the identity: both sketches kept (tile 64)
     const uint32_t* index_weights;   // NULL: uniform draws
@@ -128,6 +130,12 @@ struct MatmulPlan {
         off_gather, off_part_mean, off_part_m2, total;
     std::vector<ProblemDesc> descs;
     std::vector<int32_t> tile_owner;
+    // FP8: the exponents of the rows of A and columns of B, product after
+    // product (m_pad then p_pad entries at rows_prefix); reparameterised
+    // operands' entries are filled on the device by matmul_reset
+    std::vector<int8_t> exp_host;
+    bool fp8_reparam = false;
+    size_t off_exp = 0, off_bound = 0;
 };
 
 // index_weights: NULL, or (one product) the device weights whose cumulative
@@ -137,6 +145,8 @@ bool matmul_plan(const MatmulProblem* probs, int nprob, int prec, int num_levels
                  MatmulPlan& plan);
 // copies the problem table into the workspace (synchronises `stream`)
 hipError_t matmul_upload(const MatmulPlan& plan, char* ws, hipStream_t stream);
+// zeroes the level state; FP8 with reparameterised laws: the operand
+// exponents from the current means and scales
 hipError_t matmul_reset(const MatmulPlan& plan, char* ws, hipStream_t stream);
 hipError_t matmul_level_run(const MatmulPlan& plan, const LevelRange& lr, int64_t done_before,
                             const StreamKeys& keys, char* ws, hipStream_t stream, KernelTimer* timer);

@@ -43,6 +43,9 @@ namespace mlmc {
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(1))) void* GlobalPtr;   // the operands of global_load_lds
+typedef __attribute__((address_space(3))) void* LdsPtr;
 
 constexpr int kMergeThreads = 256;
 constexpr int kGatherThreads = 64;
@@ -63,15 +66,10 @@ struct PolicyF64 {  // v_mfma_f64_16x16x4_f64
     using AccVec = f64x4;
     using FragT = double;
     static constexpr int KSTEP = 4, KPACK = 1, BLK = 16, REGS = 4;
+    static constexpr bool SCALED = false;
     // f64 results: lane l, register r holds row l / 16 + 4 r, column l % 16
     static __device__ __forceinline__ int row_of(int lane, int r) { return lane / 16 + 4 * r; }
     static __device__ __forceinline__ int col_of(int lane) { return lane % 16; }
-    static __device__ __forceinline__ double load(const double* G, int64_t rows, int64_t row0, int64_t kk, int lane)
-    {
-        const int64_t row = row0 + (lane % 16);
-        const int64_t t = kk + lane / 16;
-        return row < rows ? G[t * rows + row] : 0.0;
-    }
     static __device__ __forceinline__ f64x4 mma(double a, double b, f64x4 c)
     {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -90,12 +88,7 @@ struct PolicyF32 : Block32 {  // v_mfma_f32_32x32x2_f32
     using AccVec = f32x16;
     using FragT = float;
     static constexpr int KSTEP = 2, KPACK = 1, BLK = 32, REGS = 16;
-    static __device__ __forceinline__ float load(const float* G, int64_t rows, int64_t row0, int64_t kk, int lane)
-    {
-        const int64_t row = row0 + (lane % 32);
-        const int64_t t = kk + lane / 32;
-        return row < rows ? G[t * rows + row] : 0.0f;
-    }
+    static constexpr bool SCALED = false;
     static __device__ __forceinline__ f32x16 mma(float a, float b, f32x16 c)
     {
         return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
@@ -108,39 +101,30 @@ struct PolicyBF16 : Block32 {  // v_mfma_f32_32x32x16_bf16: a lane holds 8 conse
     using AccVec = f32x16;
     using FragT = bf16x8;
     static constexpr int KSTEP = 16, KPACK = 8, BLK = 32, REGS = 16;
-    static __device__ __forceinline__ bf16x8 load(const __bf16* G, int64_t rows, int64_t row0, int64_t kk, int lane)
-    {
-        const int64_t row = row0 + (lane % 32);
-        const int64_t kb = kk / 8 + lane / 32;
-        bf16x8 v;
-        if (row < rows) {
-            v = *reinterpret_cast<const bf16x8*>(G + (kb * rows + row) * 8);
-        } else {
-            for (int i = 0; i < 8; ++i) v[i] = (__bf16)0.0f;
-        }
-        return v;
-    }
+    static constexpr bool SCALED = false;
     static __device__ __forceinline__ f32x16 mma(bf16x8 a, bf16x8 b, f32x16 c)
     {
         return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
     }
 };
 
-struct PolicyFP8 : Block32 {  // v_mfma_f32_32x32x16_fp8_fp8 (OCP e4m3 on gfx950): 8 draws of one row per lane
+// v_mfma_scale_f32_32x32x64_f8f6f4 with both operands OCP e4m3 (format code
+// 0): lane l holds 32 consecutive draws of row (A) or column (B) l % 32, the
+// draws 32 (l / 32) .. 32 (l / 32) + 31 of the step, and an E8M0 scale (a
+// biased exponent, 2^(e - 127)) for them in byte 0 of its scale operand.
+// The scales are the inverses of the power-of-two factors the gather
+// multiplied each row of A and column of B by, so the FP32 accumulator holds
+// the unscaled sum.
+struct PolicyFP8 : Block32 {
     using In = uint8_t;
     using Acc = float;
     using AccVec = f32x16;
-    using FragT = long;
-    static constexpr int KSTEP = 16, KPACK = 8, BLK = 32, REGS = 16;
-    static __device__ __forceinline__ long load(const uint8_t* G, int64_t rows, int64_t row0, int64_t kk, int lane)
+    using FragT = i32x8;
+    static constexpr int KSTEP = 64, KPACK = 8, BLK = 32, REGS = 16;
+    static constexpr bool SCALED = true;
+    static __device__ __forceinline__ f32x16 mma(const i32x8& a, const i32x8& b, f32x16 c, int sa, int sb)
     {
-        const int64_t row = row0 + (lane % 32);
-        const int64_t kb = kk / 8 + lane / 32;
-        return row < rows ? *reinterpret_cast<const long*>(G + (kb * rows + row) * 8) : 0l;
-    }
-    static __device__ __forceinline__ f32x16 mma(long a, long b, f32x16 c)
-    {
-        return __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a, b, c, 0, 0, 0);
+        return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, sa, 0, sb);
     }
 };
 
@@ -282,17 +266,31 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
     LawEval<Compute> LA = LawEval<Compute>::make(Pp->A);
     LawEval<Compute> LB = LawEval<Compute>::make(Pp->B);
     float pre_a = Pp->pre_a, pre_b = Pp->pre_b;
-    if constexpr (kFp8) {
-        // the power-of-two operand pre-scales fold exactly into the law
-        // constants (i.i.d. laws only in FP8)
+    // FP8: each row of A (column of B) is multiplied by its factor 2^s before
+    // the rounding to e4m3 (the sketch's MFMA scales undo it).  Two i.i.d.
+    // laws have one factor each, folded exactly into their constants; other
+    // law pairs (reparameterised operands) read the factor of every row from
+    // the product's exponent tables.
+    constexpr bool kRowScaled = kFp8 && LAWS == kLawsAny;
+    const int8_t* exp_a = Pp->exp_a;
+    const int8_t* exp_b = Pp->exp_b;
+    if constexpr (kFp8 && !kRowScaled) {
         LA.mul *= pre_a; LA.add *= pre_a;
         LB.mul *= pre_b; LB.add *= pre_b;
-        pre_a = pre_b = 1.0f;
     }
+    if constexpr (kFp8) pre_a = pre_b = 1.0f;
+    auto pa = [&](int64_t row) -> float {
+        if constexpr (kRowScaled) return ldexpf(1.0f, (int)exp_a[row]);
+        else return pre_a;
+    };
+    auto pb = [&](int64_t col) -> float {
+        if constexpr (kRowScaled) return ldexpf(1.0f, (int)exp_b[col]);
+        else return pre_b;
+    };
     // FP8 values stay FP32 (saturated to +-448) until they are packed in pairs
     using Val = typename std::conditional<kFp8, float, Store>::type;
     auto to_val = [](Compute v, float pre) -> Val {
-        if constexpr (kFp8) return __builtin_amdgcn_fmed3f((float)v, 448.0f, -448.0f);
+        if constexpr (kFp8) return __builtin_amdgcn_fmed3f((float)v * pre, 448.0f, -448.0f);
         else return StoreOf<Store>::from(v, pre);
     };
     const int64_t pos_base = (int64_t)blockIdx.x * kGatherPositions * prm.octets;
@@ -324,11 +322,11 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
         if (e0 + 3 < m) {            // the whole quad is in A's column
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                out[r] = to_val(wa * LA.template eval<LAWS>(z[r], u[r], (int64_t)j * LA.ld + e0 + r), pre_a);
+                out[r] = to_val(wa * LA.template eval<LAWS>(z[r], u[r], (int64_t)j * LA.ld + e0 + r), pa(e0 + r));
         } else if (e0 >= m) {        // the whole quad is in B's row
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                out[r] = to_val(LB.template eval<LAWS>(z[r], u[r], (int64_t)j * LB.ld + (e0 + r - m)), pre_b);
+                out[r] = to_val(LB.template eval<LAWS>(z[r], u[r], (int64_t)j * LB.ld + (e0 + r - m)), pb(e0 + r - m));
         } else {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -337,10 +335,10 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
                 float pre = 1.0f;
                 if (e < m) {
                     v = wa * LA.template eval<LAWS>(z[r], u[r], (int64_t)j * LA.ld + e);
-                    pre = pre_a;
+                    pre = pa(e);
                 } else if (e < rows) {
                     v = LB.template eval<LAWS>(z[r], u[r], (int64_t)j * LB.ld + (e - m));
-                    pre = pre_b;
+                    pre = pb(e - m);
                 }
                 out[r] = to_val(v, pre);
             }
@@ -426,11 +424,11 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
             if (e0 + 3 < m) {            // the whole quad is in A's column
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    vals[ip][r] = to_val(wa * LA.template eval<LAWS>(z[r], u[r], (int64_t)j * LA.ld + e0 + r), pre_a);
+                    vals[ip][r] = to_val(wa * LA.template eval<LAWS>(z[r], u[r], (int64_t)j * LA.ld + e0 + r), pa(e0 + r));
             } else if (e0 >= m) {        // the whole quad is in B's row
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    vals[ip][r] = to_val(LB.template eval<LAWS>(z[r], u[r], (int64_t)j * LB.ld + (e0 + r - m)), pre_b);
+                    vals[ip][r] = to_val(LB.template eval<LAWS>(z[r], u[r], (int64_t)j * LB.ld + (e0 + r - m)), pb(e0 + r - m));
             } else {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -439,10 +437,10 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
                     float pre = 1.0f;
                     if (e < m) {
                         v = wa * LA.template eval<LAWS>(z[r], u[r], (int64_t)j * LA.ld + e);
-                        pre = pre_a;
+                        pre = pa(e);
                     } else if (e < rows) {
                         v = LB.template eval<LAWS>(z[r], u[r], (int64_t)j * LB.ld + (e - m));
-                        pre = pre_b;
+                        pre = pb(e - m);
                     }
                     vals[ip][r] = to_val(v, pre);
                 }
@@ -666,9 +664,22 @@ template <> struct LdsFrag<PolicyBF16> {
     }
 };
 template <> struct LdsFrag<PolicyFP8> {
-    static __device__ __forceinline__ long load(const uint8_t* L, int BM, int kk, int row, int lane)
+    // the lane's 32 draws are four packed groups of 8 of its row; groups
+    // 4 (lane / 32) + q at or past valid8 (a step longer than its
+    // realisation) are zero and not read
+    static __device__ __forceinline__ i32x8 load(const uint8_t* L, int BM, int kk, int row, int lane, int valid8)
     {
-        return *reinterpret_cast<const long*>(L + ((kk / 8 + lane / 32) * BM + row + lane % 32) * 8);
+        const int g0 = 4 * (lane / 32);
+        const uint8_t* base = L + ((kk / 8 + g0) * BM + row + lane % 32) * 8;
+        i32x8 v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int2 w = make_int2(0, 0);
+            if (g0 + q < valid8) w = *reinterpret_cast<const int2*>(base + q * BM * 8);
+            v[2 * q] = w.x;
+            v[2 * q + 1] = w.y;
+        }
+        return v;
     }
 };
 
@@ -687,7 +698,6 @@ struct SketchShape {
     static_assert(BM == WC * WTC, "square workgroup tile");
 };
 
-// PF register sets (1 or 2) hold the global loads of the next PF chunks.
 // WPE: waves per SIMD the register allocation must leave room for.
 // STATS: 0 Welford; 1 sums shifted by E[D] (i.i.d. laws); 2 the same for
 // products that fill whole tiles (no masking code); 3 (whole tiles, short
@@ -696,7 +706,7 @@ struct SketchShape {
 // a target function f of kind 1 and 2 (fixed at compile time, so only its
 // own arithmetic is emitted per entry); 6 and 7 the same at level 0, which
 // has no coarse sketch (no copied accumulators, fewer registers).
-template <typename P, int WR, int WC, int NBR, int NBC, int PF, int WPE, int STATS>
+template <typename P, int WR, int WC, int NBR, int NBC, int WPE, int STATS>
 __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchParams prm)
 {
     using In = typename P::In;
@@ -712,7 +722,11 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
     constexpr int V_SLAB = BM * P::KPACK / VEC;      // vectors per slab of one operand
     constexpr int VPT = SLABS * V_SLAB / THREADS;    // vectors per thread per operand
     static_assert(SLABS * V_SLAB % THREADS == 0, "chunk must split evenly over the workgroup");
-    __shared__ __align__(16) In lds[2][2][KC * BM];  // [buffer][A, B][chunk]
+    // two staging buffers, separate arrays so that the compiler sees the
+    // loads into one and the fragment reads from the other as disjoint (no
+    // wait on the loads in flight before each read)
+    __shared__ __align__(16) In lds0[2][KC * BM];     // [A, B][chunk]
+    __shared__ __align__(16) In lds1[2][KC * BM];
     __shared__ double red[THREADS / kWave];
 
     const int lane = threadIdx.x % kWave;
@@ -739,19 +753,22 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
         const In* GA0 = reinterpret_cast<const In*>(prm.gbuf + pass_rows * Pd.rows_prefix) + s_begin * prm.kpad * m_pad;
         const In* GB0 = reinterpret_cast<const In*>(prm.gbuf + pass_rows * (Pd.rows_prefix + m_pad)) +
                         s_begin * prm.kpad * p_pad;
-        const double scale64 = (double)Pd.n / (double)prm.c * Pd.post;
+        const double scale64 = (double)Pd.n / (double)prm.c;
         const Acc scale = (Acc)scale64;
         const int kc = (int)prm.kc;
         const int kpad = (int)prm.kpad;
         const int npos = (int)(s_end - s_begin) * kpad;     // positions of the group's stream
         const int total = (npos + KC - 1) / KC;             // chunks; a chunk may span realisations
 
-        // Chunk c holds stream positions [c KC, c KC + KC).  The chunk's base
-        // is uniform (scalar); a thread's vectors sit at fixed element offsets
-        // from it.  The register sets keep the global loads of the next PF
-        // chunks in flight while the MFMAs run on the chunk staged in LDS.
-        uint4 ra[PF][VPT], rb[PF][VPT];
-        auto fetch = [&](int set, int c) {
+        // Chunk c holds stream positions [c KC, c KC + KC).  Its loads go
+        // straight from global memory into LDS buffer c & 1
+        // (global_load_lds_dwordx4: the 16 bytes of lane i land at the wave's
+        // base plus 16 i, which is the staging layout), so no registers hold
+        // them; chunk c + 1 is in flight while the MFMAs run on chunk c.
+        // Vectors past the group's positions are not loaded (their LDS slots
+        // are never read).
+        auto fetch = [&](auto which, int c) {
+            In (&dst)[2][KC * BM] = decltype(which)::value ? lds1 : lds0;
             const int k0 = c * KC;
             const In* ga = GA0 + (int64_t)k0 * m_pad;
             const In* gb = GB0 + (int64_t)k0 * p_pad;
@@ -759,21 +776,15 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
             for (int v = 0; v < VPT; ++v) {
                 const int vid = threadIdx.x + v * THREADS;
                 const int slab = vid / V_SLAB, iv = vid % V_SLAB;
+                const int wbase = (wave * kWave + v * THREADS) * VEC;   // the wave's first vector
                 if (k0 + slab * P::KPACK < npos) {
-                    ra[set][v] = *reinterpret_cast<const uint4*>(ga + (slab * m_pad + trow) * P::KPACK + iv * VEC);
-                    rb[set][v] = *reinterpret_cast<const uint4*>(gb + (slab * p_pad + tcol) * P::KPACK + iv * VEC);
-                } else {
-                    ra[set][v] = make_uint4(0, 0, 0, 0);
-                    rb[set][v] = make_uint4(0, 0, 0, 0);
+                    __builtin_amdgcn_global_load_lds(
+                        (GlobalPtr)(ga + (slab * m_pad + trow) * P::KPACK + iv * VEC), (LdsPtr)&dst[0][wbase], 16,
+                        0, 0);
+                    __builtin_amdgcn_global_load_lds(
+                        (GlobalPtr)(gb + (slab * p_pad + tcol) * P::KPACK + iv * VEC), (LdsPtr)&dst[1][wbase], 16,
+                        0, 0);
                 }
-            }
-        };
-        auto stash = [&](int set, int buf) {
-#pragma unroll
-            for (int v = 0; v < VPT; ++v) {
-                const int vid = threadIdx.x + v * THREADS;
-                *reinterpret_cast<uint4*>(&lds[buf][0][vid * VEC]) = ra[set][v];
-                *reinterpret_cast<uint4*>(&lds[buf][1][vid * VEC]) = rb[set][v];
             }
         };
 
@@ -806,7 +817,7 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
         }
         typename P::AccVec snap[FUNC_COARSE ? NBR : 1][FUNC_COARSE ? NBC : 1];
         const bool has_coarse = FUNC_COARSE && prm.c_prev > 0u;
-        const Acc scale_c = (Acc)(has_coarse ? (double)Pd.n / (double)prm.c_prev * Pd.post : 0.0);
+        const Acc scale_c = (Acc)(has_coarse ? (double)Pd.n / (double)prm.c_prev : 0.0);
         const Acc th0 = (Acc)prm.func.theta0, th1 = (Acc)prm.func.theta1;
         double m2_sum = 0.0;
         Acc count = (Acc)0;
@@ -839,19 +850,53 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
 #pragma unroll
                 for (int r = 0; r < P::REGS; ++r) acc[bi][bj][r] = (Acc)0;
 
-        // one MFMA step at position offset kk of the staged chunk
-        auto step = [&](const In* LA, const In* LB, int kk) {
+        // FP8: the E8M0 scales of the lane's rows of A and columns of B
+        // (127 - s for the factor 2^s the gather applied), fixed for the tile
+        int sa[P::SCALED ? NBR : 1], sb[P::SCALED ? NBC : 1];
+        if constexpr (P::SCALED) {
+#pragma unroll
+            for (int bi = 0; bi < NBR; ++bi) sa[bi] = 127 - (int)Pd.exp_a[trow + wrow + bi * P::BLK + lane % 32];
+#pragma unroll
+            for (int bj = 0; bj < NBC; ++bj) sb[bj] = 127 - (int)Pd.exp_b[tcol + wcol + bj * P::BLK + lane % 32];
+        }
+        // FP8: a realisation shorter than the MFMA's 64 draws (kpad 16 or 32,
+        // a divisor of 64, so it never crosses a chunk) is one step whose
+        // fragments are zero past its draws; otherwise steps are whole
+        int SL = P::KSTEP;
+        if constexpr (P::SCALED) SL = kpad < P::KSTEP ? kpad : P::KSTEP;
+        // one MFMA step at position offset kk of the staged chunk.  FP32 and
+        // narrower: the first step of a realisation starts its accumulator
+        // from zero (the MFMA's accumulator input is the constant 0, no
+        // clearing after the previous realisation); FP64 clears the
+        // accumulator after each realisation (a second copy of the step would
+        // not fit its registers)
+        constexpr bool kZeroStart = sizeof(In) <= 4;
+        auto step = [&](const In* LA, const In* LB, int kk, auto first) {
+            constexpr bool FIRST = decltype(first)::value;
+            const typename P::AccVec zero = {};
             FragT a[NBR], b[NBC];
+            if constexpr (P::SCALED) {
 #pragma unroll
-            for (int bi = 0; bi < NBR; ++bi) a[bi] = LdsFrag<P>::load(LA, BM, kk, wrow + bi * P::BLK, lane);
+                for (int bi = 0; bi < NBR; ++bi) a[bi] = LdsFrag<P>::load(LA, BM, kk, wrow + bi * P::BLK, lane, SL / 8);
 #pragma unroll
-            for (int bj = 0; bj < NBC; ++bj) b[bj] = LdsFrag<P>::load(LB, BM, kk, wcol + bj * P::BLK, lane);
+                for (int bj = 0; bj < NBC; ++bj) b[bj] = LdsFrag<P>::load(LB, BM, kk, wcol + bj * P::BLK, lane, SL / 8);
+            } else {
+#pragma unroll
+                for (int bi = 0; bi < NBR; ++bi) a[bi] = LdsFrag<P>::load(LA, BM, kk, wrow + bi * P::BLK, lane);
+#pragma unroll
+                for (int bj = 0; bj < NBC; ++bj) b[bj] = LdsFrag<P>::load(LB, BM, kk, wcol + bj * P::BLK, lane);
+            }
 #pragma unroll
             for (int bi = 0; bi < NBR; ++bi)
 #pragma unroll
                 for (int bj = 0; bj < NBC; ++bj) {
-                    acc[bi][bj] = P::mma(a[bi], b[bj], acc[bi][bj]);
-                    if constexpr (DUAL) tot[bi][bj] = P::mma(a[bi], b[bj], tot[bi][bj]);
+                    if constexpr (P::SCALED) {
+                        acc[bi][bj] = P::mma(a[bi], b[bj], FIRST ? zero : acc[bi][bj], sa[bi], sb[bj]);
+                        if constexpr (DUAL) tot[bi][bj] = P::mma(a[bi], b[bj], tot[bi][bj], sa[bi], sb[bj]);
+                    } else {
+                        acc[bi][bj] = P::mma(a[bi], b[bj], FIRST ? zero : acc[bi][bj]);
+                        if constexpr (DUAL) tot[bi][bj] = P::mma(a[bi], b[bj], tot[bi][bj]);
+                    }
                 }
         };
         // the realisation is complete: D = scale * acc enters the statistics
@@ -868,7 +913,6 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
                         for (int r = 0; r < P::REGS; ++r) {
                             const Acc d = acc[bi][bj][r] - shift;
                             part = fma(d, d, part);
-                            acc[bi][bj][r] = (Acc)0;
                         }
             } else if constexpr (SHIFTED) {
                 if (!ragged) {
@@ -881,7 +925,6 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
                                 const Acc d = acc[bi][bj][r] - shift;
                                 run[e] += d;
                                 part = fma(d, d, part);
-                                acc[bi][bj][r] = (Acc)0;
                             }
                 } else {
 #pragma unroll
@@ -893,7 +936,6 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
                                 const Acc d = ((inside >> e) & 1ull) ? acc[bi][bj][r] - shift : (Acc)0;
                                 run[e] += d;
                                 part = fma(d, d, part);
-                                acc[bi][bj][r] = (Acc)0;
                             }
                 }
             } else {
@@ -915,44 +957,49 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
                             const Acc delta = d - run[e];
                             run[e] += delta * inv;
                             part += delta * (d - run[e]);
-                            acc[bi][bj][r] = (Acc)0;
                         }
+            }
+            if constexpr (!kZeroStart) {
+#pragma unroll
+                for (int bi = 0; bi < NBR; ++bi)
+#pragma unroll
+                    for (int bj = 0; bj < NBC; ++bj)
+#pragma unroll
+                        for (int r = 0; r < P::REGS; ++r) acc[bi][bj][r] = (Acc)0;
             }
             m2_sum += (double)part;
         };
 
-        if (total > 0) {
-            fetch(0, 0);
-            stash(0, 0);
-        }
-        if constexpr (PF == 2) {
-            if (total > 1) fetch(1, 1);
-        }
+        if (total > 0) fetch(std::integral_constant<int, 0>(), 0);
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         int o = 0;                               // position within the current realisation
-        for (int c = 0; c < total; ++c) {
-            const int buf = c & 1;
-            if constexpr (PF == 2) {
-                if (c + 2 < total) {             // chunk c + 2 into the set chunk c came through
-                    if (buf == 0) fetch(0, c + 2);
-                    else fetch(1, c + 2);
-                }
-            } else {
-                if (c + 1 < total) fetch(0, c + 1);
-            }
-            const In* LA = lds[buf][0];
-            const In* LB = lds[buf][1];
+        // chunk c from buffer c & 1 (a compile-time choice), chunk c + 1 into
+        // the other buffer, which every wave finished reading before the
+        // previous barrier
+        auto chunk = [&](auto which, int c) {
+            constexpr int W = decltype(which)::value;
+            if (c + 1 < total) fetch(std::integral_constant<int, 1 - W>(), c + 1);
+            const In* LA = W ? lds1[0] : lds0[0];
+            const In* LB = W ? lds1[1] : lds0[1];
             const int left = npos - c * KC;
-            const int steps = (left < KC ? left : KC) / P::KSTEP;
+            const int steps = (left < KC ? left : KC) / SL;
             // runs of steps that end at the chunk's end or the end of a realisation
             for (int st = 0; st < steps;) {
                 // FUNC: a run also ends where the coarse draws end (o = kc)
                 const int stop = FUNC && o < kc ? kc : kpad;
-                int run_steps = (stop - o) / P::KSTEP;
+                int run_steps = (stop - o) / SL;
                 if (run_steps > steps - st) run_steps = steps - st;
-                for (int i = 0; i < run_steps; ++i) step(LA, LB, (st + i) * P::KSTEP);
+                int i = 0;
+                if constexpr (kZeroStart) {
+                    if (o == 0 && run_steps > 0) {
+                        step(LA, LB, st * SL, std::true_type());
+                        i = 1;
+                    }
+                }
+                for (; i < run_steps; ++i) step(LA, LB, (st + i) * SL, std::false_type());
                 st += run_steps;
-                o += run_steps * P::KSTEP;
+                o += run_steps * SL;
                 if constexpr (FUNC_COARSE) {
                     if (kc > 0 && o == kc) {
 #pragma unroll
@@ -966,15 +1013,12 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
                     o = 0;
                 }
             }
-            if (c + 1 < total) {                 // chunk c + 1 into the other LDS buffer
-                if constexpr (PF == 2) {
-                    if (buf == 0) stash(1, 1);
-                    else stash(0, 0);
-                } else {
-                    stash(0, buf ^ 1);
-                }
-            }
+            __builtin_amdgcn_s_waitcnt(0);      // this wave's loads of chunk c + 1
             __syncthreads();
+        };
+        for (int c = 0; c < total; c += 2) {
+            chunk(std::integral_constant<int, 0>(), c);
+            if (c + 1 < total) chunk(std::integral_constant<int, 1>(), c + 1);
         }
 
         // group mean of every in-range entry, and the group's within sum of
@@ -1161,17 +1205,19 @@ __global__ void fill_kernel(double* p, int64_t count, double v)
 // ---------------------------------------------------------------------------
 // Host side: plan, passes, finalize.
 // ---------------------------------------------------------------------------
+// kmem: the shortest padded realisation (FP8: 16 draws, whose MFMA step of
+// 64 draws then reads zeros past them; the others pad to whole steps)
 struct PolicyShape {
-    int kstep, kpack, blk, elem;
+    int kstep, kpack, blk, elem, kmem;
 };
 
 static PolicyShape policy_shape(int prec)
 {
     switch (prec) {
-    case 0: return {PolicyF64::KSTEP, 1, PolicyF64::BLK, 8};
-    case 1: return {PolicyF32::KSTEP, 1, PolicyF32::BLK, 4};
-    case 2: return {PolicyBF16::KSTEP, PolicyBF16::KPACK, PolicyBF16::BLK, 2};
-    default: return {PolicyFP8::KSTEP, PolicyFP8::KPACK, PolicyFP8::BLK, 1};
+    case 0: return {PolicyF64::KSTEP, 1, PolicyF64::BLK, 8, PolicyF64::KSTEP};
+    case 1: return {PolicyF32::KSTEP, 1, PolicyF32::BLK, 4, PolicyF32::KSTEP};
+    case 2: return {PolicyBF16::KSTEP, PolicyBF16::KPACK, PolicyBF16::BLK, 2, PolicyBF16::KSTEP};
+    default: return {PolicyFP8::KSTEP, PolicyFP8::KPACK, PolicyFP8::BLK, 1, 16};
     }
 }
 
@@ -1179,25 +1225,46 @@ static int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 
 static void level_padding(const MatmulPlan& plan, int64_t c, int64_t c_prev, int64_t& kc, int64_t& kpad)
 {
+    if (plan.func.kind == 0) {
+        // the coarse weight is folded into the operands: the coarse and fine
+        // draws are one run of positions, padded once, to a divisor of the
+        // contraction step (FP8: 16 or 32 draws) or to whole steps
+        kc = c_prev;
+        kpad = round_up(c, plan.kmem);
+        if (kpad > plan.kstep || plan.kstep % kpad != 0) kpad = round_up(kpad, plan.kstep);
+        kpad = round_up(kpad, plan.kpack);
+        return;
+    }
+    // a target function copies the accumulator where the coarse draws end:
+    // that boundary falls on a contraction step
     kc = round_up(c_prev, plan.kstep);
     kpad = kc + round_up(c - c_prev, plan.kstep);
     // the packed layouts group 8 positions; the gather kernel writes whole groups
     kpad = round_up(kpad, plan.kpack);
 }
 
-// FP8 operand pre-scale: a power of two that brings a bound of the entries
-// near 256 (inside e4m3's +-448); exact, and undone in the sketch's scale.
-static float fp8_prescale(const Law& law)
+// FP8 scale rule: the exponent s of the factor 2^s that each row of A (column
+// of B) is multiplied by before its rounding to e4m3: the largest s with
+// 2^s bound <= 256 (entries up to the bound sit in e4m3's top binades, below
+// its largest value 448), clamped to [-20, 20], 0 for a zero bound.  Exact:
+// bound = f 2^E with f in [1/2, 1) gives s = 8 - E, or 9 - E when f = 1/2.
+__host__ __device__ inline int fp8_scale_exponent(double bound)
 {
-    double bound;
-    if (law.kind == 0) bound = fabs(law.loc) + 6.0 * fabs(law.scale);
-    else if (law.kind == 1) bound = fabs(law.loc) + fabs(law.scale);
-    else return 1.0f;
-    if (!(bound > 0.0)) return 1.0f;
-    int ex = (int)floor(log2(256.0 / bound));
-    if (ex > 20) ex = 20;
-    if (ex < -20) ex = -20;
-    return (float)ldexp(1.0, ex);
+    if (!(bound > 0.0)) return 0;
+    int E;
+    const double f = frexp(bound, &E);
+    int s = 8 - E + (f == 0.5 ? 1 : 0);
+    return s < -20 ? -20 : (s > 20 ? 20 : s);
+}
+
+// Bound of the entries of an i.i.d. law: |loc| + 6 |scale| (normal, as
+// fma(6, |scale|, |loc|)) or |loc| + |scale| (uniform); reparameterised laws
+// take fma(6, |stdev|, |mean|) per entry, maximised over each row of A
+// (column of B) on the device (fp8_bound_kernel).
+static double fp8_iid_bound(const Law& law)
+{
+    if (law.kind == 0) return fma(6.0, fabs(law.scale), fabs(law.loc));
+    return fabs(law.loc) + fabs(law.scale);
 }
 
 bool matmul_plan(const MatmulProblem* probs, int nprob, int prec, int num_levels, const int64_t* c,
@@ -1215,17 +1282,31 @@ bool matmul_plan(const MatmulProblem* probs, int nprob, int prec, int num_levels
     for (int l = 0; l < num_levels; ++l) plan.c[l] = c[l];
     const PolicyShape ps = policy_shape(prec);
     plan.kstep = ps.kstep;
+    plan.kmem = ps.kmem;
     plan.kpack = ps.kpack;
     plan.elem = ps.elem;
     // workgroup tile: 128 (4 x 2 waves of 32 x 64) for the 32 x 32 MFMA
     // blocks unless tuned to 64 (2 x 2 waves of 32 x 32); f64 blocks are 16
     // wide and always use tile 64 (2 x 2 waves of 32 x 32 in 16 x 16 blocks)
     plan.nb = 2;
-    if (tune && tune->tile > 0 && prec != 0) plan.nb = tune->tile <= 2 * ps.blk ? 1 : 2;
+    int want_tile = tune && tune->tile > 0 ? tune->tile : 0;
+    if (const char* env = getenv("MLMC_SKETCH_TILE")) {
+        const int v = atoi(env);
+        if (v == 64 || v == 128) want_tile = v;
+    }
+    if (want_tile > 0 && prec != 0) plan.nb = want_tile <= 2 * ps.blk ? 1 : 2;
     // a target function keeps the coarse sketch beside the fine one: the
     // 32 x 32-per-wave layout (tile 64) leaves room for the extra registers
     if (func.kind != 0 && prec != 0) plan.nb = 1;
     plan.tile = 2 * plan.nb * ps.blk;
+    // f64: 2 x 2 waves of 32 x 32 (tile 64), or 4 x 4 such waves (tile 128:
+    // twice the flops per byte staged, the same registers per wave)
+    // (by default for products of at least 512 x 512, measured faster there)
+    if (prec == 0) {
+        bool large = true;
+        for (int i = 0; i < nprob; ++i) large = large && probs[i].m >= 512 && probs[i].p >= 512;
+        plan.tile = func.kind == 0 && (want_tile == 128 || (want_tile == 0 && large)) ? 128 : 64;
+    }
     plan.kpad_max = 0;
     for (int l = 0; l < num_levels; ++l) {
         int64_t kc, kpad;
@@ -1243,6 +1324,8 @@ bool matmul_plan(const MatmulProblem* probs, int nprob, int prec, int num_levels
     }
     plan.descs.resize(nprob);
     plan.tile_owner.clear();
+    plan.exp_host.clear();
+    plan.fp8_reparam = false;
     int64_t rows = 0, mp = 0, mb = 0, tiles = 0;
     plan.max_mp = 0;
     plan.max_merge_blocks = 0;
@@ -1264,9 +1347,18 @@ bool matmul_plan(const MatmulProblem* probs, int nprob, int prec, int num_levels
         d.mp_prefix = mp;
         d.merge_blocks = ceil_div(pr.m * pr.p, kMergeThreads);
         d.between_prefix = mb;
-        d.pre_a = prec == 3 ? fp8_prescale(pr.A) : 1.0f;
-        d.pre_b = prec == 3 ? fp8_prescale(pr.B) : 1.0f;
-        d.post = 1.0 / ((double)d.pre_a * (double)d.pre_b);
+        // FP8: per-row (A) and per-column (B) exponents; an i.i.d. law has one
+        // for all its rows, folded into its constants by the gather
+        const int sa = prec == 3 && pr.A.kind != 2 ? fp8_scale_exponent(fp8_iid_bound(pr.A)) : 0;
+        const int sb = prec == 3 && pr.B.kind != 2 ? fp8_scale_exponent(fp8_iid_bound(pr.B)) : 0;
+        d.pre_a = (float)ldexp(1.0, sa);
+        d.pre_b = (float)ldexp(1.0, sb);
+        d.exp_a = d.exp_b = nullptr;     // set to the workspace tables by matmul_upload
+        if (prec == 3) {
+            plan.exp_host.insert(plan.exp_host.end(), (size_t)d.m_pad, (int8_t)sa);
+            plan.exp_host.insert(plan.exp_host.end(), (size_t)d.p_pad, (int8_t)sb);
+            if (pr.A.kind == 2 || pr.B.kind == 2) plan.fp8_reparam = true;
+        }
         // both i.i.d. laws have mean loc: E[Z_0] = n loc_A loc_B in every entry
         d.mean0 = plan.iid ? (double)pr.n * pr.A.loc * pr.B.loc : 0.0;
         d.out = pr.out;
@@ -1323,6 +1415,9 @@ bool matmul_plan(const MatmulProblem* probs, int nprob, int prec, int num_levels
     plan.off_desc = off;       off = align(off + sizeof(ProblemDesc) * nprob);
     plan.off_tile_owner = off; off = align(off + sizeof(int32_t) * tiles);
     plan.off_cum = off;        off = align(off + (index_weights ? sizeof(uint64_t) * probs[0].n : 0));
+    plan.off_exp = off;        off = align(off + (prec == 3 ? (size_t)rows : 0));
+    // (FP8 always: the workspace query describes the shapes, not the laws)
+    plan.off_bound = off;      off = align(off + (prec == 3 ? sizeof(double) * rows : 0));
     plan.off_gather = off;     off = align(off + (size_t)plan.gather_bytes);
     plan.off_part_mean = off;  off = align(off + sizeof(double) * plan.groups_max * mp);
     plan.off_part_m2 = off;    off = align(off + sizeof(double) * plan.groups_max * tiles);
@@ -1346,7 +1441,18 @@ hipError_t fill_doubles(double* p, int64_t count, double v, hipStream_t stream)
 
 hipError_t matmul_upload(const MatmulPlan& plan, char* ws, hipStream_t stream)
 {
-    hipError_t e = hipMemcpyAsync(ws + plan.off_desc, plan.descs.data(), sizeof(ProblemDesc) * plan.nprob,
+    std::vector<ProblemDesc> descs(plan.descs);
+    if (plan.prec == 3) {
+        int8_t* tables = reinterpret_cast<int8_t*>(ws + plan.off_exp);
+        for (ProblemDesc& d : descs) {
+            d.exp_a = tables + d.rows_prefix;
+            d.exp_b = tables + d.rows_prefix + d.m_pad;
+        }
+        hipError_t e = hipMemcpyAsync(tables, plan.exp_host.data(), plan.exp_host.size(), hipMemcpyHostToDevice,
+                                      stream);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipMemcpyAsync(ws + plan.off_desc, descs.data(), sizeof(ProblemDesc) * plan.nprob,
                                   hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(ws + plan.off_tile_owner, plan.tile_owner.data(), sizeof(int32_t) * plan.total_tiles,
@@ -1386,13 +1492,67 @@ double* matmul_norm_ptr(const MatmulPlan& plan, char* ws)
     return reinterpret_cast<double*>(ws + plan.off_norm);
 }
 
+// FP8 with reparameterised laws: the bound of every row of A (column of B),
+// the maximum over the n columns (rows) j of fma(6, |stdev|, |mean|) in FP64,
+// by an atomic maximum on the bit patterns (non-negative doubles order like
+// their bits).  Grid: (ceil(count / 256), up to 4096 ranges of j of at least
+// kBoundChunk); A's row i of column j sits at j ld + i, B's column q of row j
+// at j ld + q, so both walk j.
+constexpr int kBoundChunk = 256;
+
+__global__ __launch_bounds__(256) void fp8_bound_kernel(const float* mean, const float* stdev, int64_t ld, int64_t n,
+                                                        int64_t count, unsigned long long* bound)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= count) return;
+    const int64_t chunk = ceil_div(n, (int64_t)gridDim.y);
+    const int64_t j0 = (int64_t)blockIdx.y * chunk;
+    const int64_t j1 = j0 + chunk < n ? j0 + chunk : n;
+    double b = 0.0;
+    for (int64_t j = j0; j < j1; ++j) {
+        const double v = fma(6.0, fabs((double)stdev[j * ld + i]), fabs((double)mean[j * ld + i]));
+        b = v > b ? v : b;
+    }
+    atomicMax(bound + i, (unsigned long long)__double_as_longlong(b));
+}
+
+// The exponents of the rows (columns) of reparameterised operands from their bounds.
+__global__ void fp8_exponent_kernel(const double* bound, int64_t count, int8_t* exps)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) exps[i] = (int8_t)fp8_scale_exponent(bound[i]);
+}
+
 hipError_t matmul_reset(const MatmulPlan& plan, char* ws, hipStream_t stream)
 {
     // means, between, within and var are contiguous at the start of the workspace
-    return fill_doubles(reinterpret_cast<double*>(ws), plan.state_doubles, 0.0, stream);
+    hipError_t e = fill_doubles(reinterpret_cast<double*>(ws), plan.state_doubles, 0.0, stream);
+    if (e != hipSuccess || !plan.fp8_reparam) return e;
+    // FP8 exponents of reparameterised operands, from the current means and scales
+    double* bound = reinterpret_cast<double*>(ws + plan.off_bound);
+    int8_t* tables = reinterpret_cast<int8_t*>(ws + plan.off_exp);
+    for (const ProblemDesc& d : plan.descs) {
+        for (int side = 0; side < 2; ++side) {
+            const Law& law = side == 0 ? d.A : d.B;
+            if (law.kind != 2) continue;
+            const int64_t count = side == 0 ? d.m : d.p;
+            const int64_t off = d.rows_prefix + (side == 0 ? 0 : d.m_pad);
+            if ((e = fill_doubles(bound + off, count, 0.0, stream)) != hipSuccess) return e;
+            int64_t chunks = ceil_div(d.n, (int64_t)kBoundChunk);
+            if (chunks > 4096) chunks = 4096;
+            hipLaunchKernelGGL(fp8_bound_kernel, dim3((unsigned)ceil_div(count, (int64_t)256), (unsigned)chunks),
+                               dim3(256), 0, stream, law.mean, law.stdev, law.ld, d.n, count,
+                               reinterpret_cast<unsigned long long*>(bound + off));
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            hipLaunchKernelGGL(fp8_exponent_kernel, dim3((unsigned)ceil_div(count, (int64_t)256)), dim3(256), 0,
+                               stream, bound + off, count, tables + off);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
 }
 
-template <typename P, typename Compute, int WR, int WC, int NBR, int NBC, int PF, int WPE>
+template <typename P, typename Compute, int WR, int WC, int NBR, int NBC, int WPE>
 static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t k_first, int64_t batch,
                            int64_t done_before, int64_t kc, int64_t kpad, const StreamKeys& keys, char* ws,
                            hipStream_t stream, KernelTimer* timer)
@@ -1485,38 +1645,39 @@ static hipError_t run_pass(const MatmulPlan& plan, const LevelRange& lr, int64_t
         // fills whole tiles), except in the 4 x 2-wave BF16/FP32 kernels,
         // where their extra live values spill (measured slower than Welford);
         // the masked form only where a lane holds at most 32 entries
-        constexpr bool kShiftedFits = !(WR == 4 && sizeof(typename P::In) >= 2);
+        constexpr bool kShiftedFits = !(WR == 4 && WC == 2 && sizeof(typename P::In) >= 2);
         constexpr bool kMaskedFits = kShiftedFits && NBR * NBC * P::REGS <= 32;
         constexpr bool kDualForm = sizeof(typename P::In) <= 2;   // BF16, FP8: FP32 totals suffice
         const dim3 grid((unsigned)blocks), block(kWave * WR * WC);
-        constexpr bool kFuncForm = NBR * NBC * P::REGS <= 16;   // the layouts a target function uses
+        // the layouts a target function uses (2 x 2 waves; never the f64 4 x 4)
+        constexpr bool kFuncForm = NBR * NBC * P::REGS <= 16 && WR * WC == 4;
         if (plan.func.kind != 0) {
             // the copied accumulators need more than 128 registers: two waves per SIMD
             if constexpr (kFuncForm) {
                 // level 0 (no coarse sketch): the statistics fit the full occupancy
                 if (lr.c_prev == 0 && plan.func.kind == 1)
-                    hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, WPE, 6>), grid, block, 0, stream, s);
+                    hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, WPE, 6>), grid, block, 0, stream, s);
                 else if (lr.c_prev == 0)
-                    hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, WPE, 7>), grid, block, 0, stream, s);
+                    hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, WPE, 7>), grid, block, 0, stream, s);
                 else if (plan.func.kind == 1)
-                    hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, (WPE > 2 ? 2 : WPE), 4>), grid, block,
+                    hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, (WPE > 2 ? 2 : WPE), 4>), grid, block,
                                        0, stream, s);
                 else
-                    hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, (WPE > 2 ? 2 : WPE), 5>), grid, block,
+                    hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, (WPE > 2 ? 2 : WPE), 5>), grid, block,
                                        0, stream, s);
             } else
                 return hipErrorInvalidConfiguration;   // matmul_plan picks tile 64 for a target function
         } else if (plan.iid && plan.whole_tiles && kDualForm && lr.c <= kDualMaxDraws)
-            hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, WPE, kDualForm ? 3 : 0>), grid, block, 0,
+            hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, WPE, kDualForm ? 3 : 0>), grid, block, 0,
                                stream, s);
         else if (plan.iid && kShiftedFits && plan.whole_tiles)
-            hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, WPE, kShiftedFits ? 2 : 0>), grid, block, 0,
+            hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, WPE, kShiftedFits ? 2 : 0>), grid, block, 0,
                                stream, s);
         else if (plan.iid && kMaskedFits)
-            hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, WPE, kMaskedFits ? 1 : 0>), grid, block, 0,
+            hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, WPE, kMaskedFits ? 1 : 0>), grid, block, 0,
                                stream, s);
         else
-            hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, PF, WPE, 0>), grid, block, 0, stream, s);
+            hipLaunchKernelGGL((sketch_kernel<P, WR, WC, NBR, NBC, WPE, 0>), grid, block, 0, stream, s);
     }
     err = hipGetLastError();
     if (err != hipSuccess) return err;
@@ -1550,19 +1711,13 @@ static hipError_t run_pass_nb(const MatmulPlan& plan, const LevelRange& lr, int6
                               int64_t done_before, int64_t kc, int64_t kpad, const StreamKeys& keys, char* ws,
                               hipStream_t stream, KernelTimer* timer)
 {
-    // tile 64: 2 x 2 waves of 32 x 32.  Tile 128: BF16/FP32 2 x 2 waves of
-    // 64 x 64 (two waves per SIMD, fewer LDS fragment reads per MFMA), FP8
-    // 4 x 2 waves of 32 x 64 (four waves per SIMD; measured faster on the
-    // small products of batches)
+    // tile 64: 2 x 2 waves of 32 x 32.  Tile 128: 2 x 2 waves of 64 x 64
+    // (two waves per SIMD; each fragment read from LDS feeds two MFMAs)
     if (plan.tile == 64)
-        return run_pass<P, Compute, 2, 2, 1, 1, 2, 4>(plan, lr, k_first, batch, done_before, kc, kpad, keys, ws, stream,
+        return run_pass<P, Compute, 2, 2, 1, 1, 4>(plan, lr, k_first, batch, done_before, kc, kpad, keys, ws, stream,
                                                    timer);
-    if constexpr (sizeof(typename P::In) >= 2)
-        return run_pass<P, Compute, 2, 2, 2, 2, 1, 2>(plan, lr, k_first, batch, done_before, kc, kpad, keys, ws, stream,
-                                                   timer);
-    else
-        return run_pass<P, Compute, 4, 2, 1, 2, 1, 4>(plan, lr, k_first, batch, done_before, kc, kpad, keys, ws, stream,
-                                                   timer);
+    return run_pass<P, Compute, 2, 2, 2, 2, 2>(plan, lr, k_first, batch, done_before, kc, kpad, keys, ws, stream,
+                                               timer);
 }
 
 hipError_t matmul_level_run(const MatmulPlan& plan, const LevelRange& lr, int64_t done_before, const StreamKeys& keys,
@@ -1580,8 +1735,11 @@ hipError_t matmul_level_run(const MatmulPlan& plan, const LevelRange& lr, int64_
         const int64_t batch = (lr.count - b) < level_batch ? (lr.count - b) : level_batch;
         hipError_t err;
         const int64_t k_first = lr.k_begin + b, before = done_before + b;
-        if (plan.prec == 0)
-            err = run_pass<PolicyF64, double, 2, 2, 2, 2, 2, 2>(plan, lr, k_first, batch, before, kc, kpad, keys, ws,
+        if (plan.prec == 0 && plan.tile == 128)
+            err = run_pass<PolicyF64, double, 4, 4, 2, 2, 4>(plan, lr, k_first, batch, before, kc, kpad, keys, ws,
+                                                             stream, timer);
+        else if (plan.prec == 0)
+            err = run_pass<PolicyF64, double, 2, 2, 2, 2, 2>(plan, lr, k_first, batch, before, kc, kpad, keys, ws,
                                                              stream, timer);
         else if (plan.prec == 1)
             err = run_pass_nb<PolicyF32, float>(plan, lr, k_first, batch, before, kc, kpad, keys, ws, stream, timer);

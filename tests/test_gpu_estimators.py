@@ -101,10 +101,12 @@ def test_inner_shared_telescoping(orc, dev):
 MATMUL_CASES = [
     # m, n, p, law A, law B, ladder, N, precisions
     (64, 256, 64, ("normal", 1.0, 1.0), ("normal", 1.0, 1.0), [4, 8, 16, 32], [1000, 500, 250, 125], ["fp64", "fp32"]),
-    (37, 500, 45, ("normal", 0.5, 1.0), ("uniform", 0.2, 1.5), [5, 10, 20], [700, 300, 100], ["fp64", "fp32", "bf16"]),
+    (37, 500, 45, ("normal", 0.5, 1.0), ("uniform", 0.2, 1.5), [5, 10, 20], [700, 300, 100], ["fp64", "fp32", "bf16", "fp8"]),
     (300, 1000, 200, ("normal", 0.5, 1.0), ("normal", 0.5, 1.0), [8, 16, 32], [1000, 300, 90], ["fp64", "fp32", "bf16"]),
-    (70, 3000, 129, ("reparam",), ("reparam",), [16, 32, 64, 128], [400, 200, 100, 50], ["fp64", "fp32", "bf16"]),
+    (70, 3000, 129, ("reparam",), ("reparam",), [16, 32, 64, 128], [400, 200, 100, 50], ["fp64", "fp32", "bf16", "fp8"]),
     (1, 2000, 1, ("uniform", 0.5, 1.0), ("uniform", 0.5, 1.0), [2, 4, 8], [500, 200, 100], ["fp64", "fp32"]),
+    # at least 512 x 512 (the FP64 128 x 128 tiles of 4 x 4 waves), ragged
+    (520, 700, 600, ("normal", 0.5, 1.0), ("normal", 0.3, 1.0), [4, 8], [60, 30], ["fp64"]),
     # |E[D_0]| far above its spread (mean^2 / variance ~ 1e3 per entry), ragged tiles:
     # the level-0 statistics must not cancel
     (100, 600, 37, ("normal", 5.0, 0.1), ("uniform", -3.0, 0.05), [4, 8, 16], [400, 200, 100], ["fp64", "fp32"]),
@@ -126,7 +128,7 @@ def test_matmul_fixed(orc, dev, pool, case, prec):
     est = matmul_estimate(m, n, p, gA, gB, c, n_samples=N, seed=21, prec=prec, level_means=True, device=dev)
     ref = orc.estimate(m, n, p, oA, oB, c, n_samples=N, seed=21, pool=pool)
     ref_q = None
-    if prec == "bf16":
+    if prec in ("bf16", "fp8"):
         ref_q = orc.estimate(m, n, p, operand_law(orc, oA, prec, m, "A"), operand_law(orc, oB, prec, p, "B"), c,
                              n_samples=N, seed=21, pool=pool)
     _compare(est, ref, prec, ref_q, f"case {case}")
