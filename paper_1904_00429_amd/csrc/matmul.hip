@@ -193,9 +193,9 @@ constexpr uint32_t kNoDrawColumn = 0xFFFFFFFFu;
 template <typename Compute>
 __device__ __forceinline__ void draw_block_columns(const GatherParams& prm, int64_t pos_base, int npos_block,
                                                    uint32_t k, uint32_t n, uint32_t sid_index, uint32_t* cols,
-                                                   Compute* colf)
+                                                   Compute* colf, int tid, int nthreads)
 {
-    for (int i = threadIdx.x; i < npos_block; i += kGatherThreads) {
+    for (int i = tid; i < npos_block; i += nthreads) {
         const int64_t t = draw_of_position(pos_base + i, prm.kc, prm.c, prm.c_prev, prm.stride);
         uint32_t j = kNoDrawColumn;
         Compute f = (Compute)1;
@@ -218,11 +218,12 @@ __device__ __forceinline__ void draw_block_columns(const GatherParams& prm, int6
 // so the sketch's entries outside the product see D = 0.
 template <typename Compute, typename Store, int KPACK>
 __device__ __forceinline__ void zero_padding_rows(const GatherParams& prm, int64_t pos_base, int octets, int64_t m,
-                                                  int64_t p, int64_t m_pad, int64_t p_pad, Store* GA, Store* GB)
+                                                  int64_t p, int64_t m_pad, int64_t p_pad, Store* GA, Store* GB,
+                                                  int tid, int nthreads)
 {
     const uint32_t pad_a = (uint32_t)(m_pad - m), pad_rows = (uint32_t)(m_pad - m + p_pad - p);
     const Store zero = StoreOf<Store>::from((Compute)0, 1.0f);
-    for (uint32_t it = threadIdx.x; it < pad_rows * (uint32_t)octets; it += kGatherThreads) {
+    for (uint32_t it = (uint32_t)tid; it < pad_rows * (uint32_t)octets; it += (uint32_t)nthreads) {
         const uint32_t oc = it / pad_rows;
         const uint32_t qr = it - oc * pad_rows;
         const int64_t pos0 = pos_base + (int64_t)oc * kGatherPositions;
@@ -247,16 +248,18 @@ __device__ __forceinline__ void zero_padding_rows(const GatherParams& prm, int64
 // items, so a product with few rows still keeps every lane busy.
 // V16: values from 16-bit uniforms, eight per Philox call (rows 8h .. 8h+7 per
 // lane item instead of 4q .. 4q+3).
+constexpr int kGatherMaxPos = kGatherPositions * kGatherMaxOctets;
+
+// One gather block (bx: group of octets of positions, by: realisation slot,
+// bz: product), by `nthreads` threads (tid the thread's index), with the
+// LDS arrays cols and colf of kGatherMaxPos entries.
 template <typename Compute, typename Store, int KPACK, int LAWS, bool V16>
-__global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm)
+__device__ __forceinline__ void gather_unit(const GatherParams& prm, uint32_t bx, uint32_t by, uint32_t bz, int tid,
+                                            int nthreads, uint32_t* cols, Compute* colf)
 {
-    constexpr int MAXPOS = kGatherPositions * kGatherMaxOctets;
-    __shared__ uint32_t cols[MAXPOS];
-    // per-draw factor 1 / (n xi_j) of eq. (18) with weighted draws (1 uniform)
-    __shared__ Compute colf[MAXPOS];
     // the product's description is copied to registers once: the stores into
     // the gathered buffer below could otherwise alias it and force reloads
-    const ProblemDesc* Pp = prm.descs + blockIdx.z;
+    const ProblemDesc* Pp = prm.descs + bz;
     const int64_t m = Pp->m, p = Pp->p;
     const int64_t m_pad = Pp->m_pad, p_pad = Pp->p_pad;
     const uint32_t n = (uint32_t)Pp->n;
@@ -293,15 +296,15 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
         if constexpr (kFp8) return __builtin_amdgcn_fmed3f((float)v * pre, 448.0f, -448.0f);
         else return StoreOf<Store>::from(v, pre);
     };
-    const int64_t pos_base = (int64_t)blockIdx.x * kGatherPositions * prm.octets;
-    const int64_t slot = blockIdx.y;
+    const int64_t pos_base = (int64_t)bx * kGatherPositions * prm.octets;
+    const int64_t slot = by;
     const uint32_t k = prm.k_first + (uint32_t)slot;
     const uint32_t sid_index = stream_id(kTagIndex, prm.level_field, sid_problem);
     const uint32_t sid_value = stream_id(kTagValue, prm.level_field, sid_problem);
     const int npos_block = (int)((prm.kpad - pos_base) < kGatherPositions * prm.octets ? (prm.kpad - pos_base)
                                                                                      : kGatherPositions * prm.octets);
     const int octets = (npos_block + kGatherPositions - 1) / kGatherPositions;
-    draw_block_columns<Compute>(prm, pos_base, npos_block, k, n, sid_index, cols, colf);
+    draw_block_columns<Compute>(prm, pos_base, npos_block, k, n, sid_index, cols, colf, tid, nthreads);
     const int64_t rows = m + p;
     const uint32_t quads = (uint32_t)ceil_div(rows, 4);
     const bool normal = LAWS == kLawsNormal || (LAWS == kLawsAny && (LA.kind != 1 || LB.kind != 1));
@@ -541,14 +544,14 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
             ok[ip] = ip < npos_block && jv[ip] != kNoDrawColumn;
         }
         if constexpr (V16) {
-            for (int64_t h = threadIdx.x; h < (int64_t)((quads + 1) / 2); h += kGatherThreads) generate16(0u, h, jv, ok);
+            for (int64_t h = tid; h < (int64_t)((quads + 1) / 2); h += nthreads) generate16(0u, h, jv, ok);
         } else {
-            for (int64_t q = threadIdx.x; q < (int64_t)quads; q += kGatherThreads) generate(0u, q, jv, ok);
+            for (int64_t q = tid; q < (int64_t)quads; q += nthreads) generate(0u, q, jv, ok);
         }
     } else {
         const uint32_t units = V16 ? (quads + 1) / 2 : quads;   // lane items per position group
         const uint32_t items = units * (uint32_t)octets;
-        for (uint32_t it = threadIdx.x; it < items; it += kGatherThreads) {
+        for (uint32_t it = (uint32_t)tid; it < items; it += (uint32_t)nthreads) {
             const uint32_t oc = it / units;
             const int npos = npos_block - (int)oc * kGatherPositions;
 #pragma unroll
@@ -560,7 +563,17 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
             else generate(oc, (int64_t)(it - oc * units), jv, ok);
         }
     }
-    zero_padding_rows<Compute, Store, KPACK>(prm, pos_base, octets, m, p, m_pad, p_pad, GA, GB);
+    zero_padding_rows<Compute, Store, KPACK>(prm, pos_base, octets, m, p, m_pad, p_pad, GA, GB, tid, nthreads);
+}
+
+template <typename Compute, typename Store, int KPACK, int LAWS, bool V16>
+__global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm)
+{
+    __shared__ uint32_t cols[kGatherMaxPos];
+    // per-draw factor 1 / (n xi_j) of eq. (18) with weighted draws (1 uniform)
+    __shared__ Compute colf[kGatherMaxPos];
+    gather_unit<Compute, Store, KPACK, LAWS, V16>(prm, blockIdx.x, blockIdx.y, blockIdx.z, threadIdx.x, kGatherThreads,
+                                                 cols, colf);
 }
 
 // The laws of the experiments of Sec. 4: every element is a Philox call and
@@ -571,9 +584,8 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherParams prm
 template <typename Compute, typename Store, int KPACK>
 __global__ __launch_bounds__(kGatherThreads) void gather_experiment_kernel(GatherParams prm)
 {
-    constexpr int MAXPOS = kGatherPositions * kGatherMaxOctets;
-    __shared__ uint32_t cols[MAXPOS];
-    __shared__ Compute colf[MAXPOS];
+    __shared__ uint32_t cols[kGatherMaxPos];
+    __shared__ Compute colf[kGatherMaxPos];
     const ProblemDesc* Pp = prm.descs + blockIdx.z;
     const int64_t m = Pp->m, p = Pp->p;
     const int64_t m_pad = Pp->m_pad, p_pad = Pp->p_pad;
@@ -589,7 +601,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_experiment_kernel(Gathe
     const int npos_block = (int)((prm.kpad - pos_base) < kGatherPositions * prm.octets ? (prm.kpad - pos_base)
                                                                                      : kGatherPositions * prm.octets);
     const int octets = (npos_block + kGatherPositions - 1) / kGatherPositions;
-    draw_block_columns<Compute>(prm, pos_base, npos_block, k, n, sid_index, cols, colf);
+    draw_block_columns<Compute>(prm, pos_base, npos_block, k, n, sid_index, cols, colf, threadIdx.x, kGatherThreads);
     const int64_t rows = m + p;
     const int64_t pass_rows = prm.batch * prm.kpad * (int64_t)prm.elem;
     Store* __restrict__ GA = reinterpret_cast<Store*>(prm.gbuf + pass_rows * rows_prefix) + slot * prm.kpad * m_pad;
@@ -615,7 +627,8 @@ __global__ __launch_bounds__(kGatherThreads) void gather_experiment_kernel(Gathe
         const int64_t row = in_a ? e : e - m;
         G[((pos / KPACK) * R + row) * KPACK + (pos % KPACK)] = StoreOf<Store>::from(v, 1.0f);
     }
-    zero_padding_rows<Compute, Store, KPACK>(prm, pos_base, octets, m, p, m_pad, p_pad, GA, GB);
+    zero_padding_rows<Compute, Store, KPACK>(prm, pos_base, octets, m, p, m_pad, p_pad, GA, GB, threadIdx.x,
+                                             kGatherThreads);
 }
 
 // ---------------------------------------------------------------------------
@@ -900,9 +913,16 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
                 }
         };
         // the realisation is complete: D = scale * acc enters the statistics
+        // The squared deviations go into kParts independent partial sums
+        // (entry e into part e % kParts): one running sum would chain every
+        // entry's fma on the previous one.
+        constexpr int kParts = 4;
+        static_assert(kParts == 4, "the partial sums are added pairwise below");
         auto realisation_done = [&]() {
             count += (Acc)1;
-            Acc part = (Acc)0;
+            Acc part[kParts];
+#pragma unroll
+            for (int q = 0; q < kParts; ++q) part[q] = (Acc)0;
             int e = 0;
             if constexpr (DUAL) {
 #pragma unroll
@@ -910,9 +930,9 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
 #pragma unroll
                     for (int bj = 0; bj < NBC; ++bj)
 #pragma unroll
-                        for (int r = 0; r < P::REGS; ++r) {
+                        for (int r = 0; r < P::REGS; ++r, ++e) {
                             const Acc d = acc[bi][bj][r] - shift;
-                            part = fma(d, d, part);
+                            part[e % kParts] = fma(d, d, part[e % kParts]);
                         }
             } else if constexpr (SHIFTED) {
                 if (!ragged) {
@@ -924,7 +944,7 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
                             for (int r = 0; r < P::REGS; ++r, ++e) {
                                 const Acc d = acc[bi][bj][r] - shift;
                                 run[e] += d;
-                                part = fma(d, d, part);
+                                part[e % kParts] = fma(d, d, part[e % kParts]);
                             }
                 } else {
 #pragma unroll
@@ -935,7 +955,7 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
                             for (int r = 0; r < P::REGS; ++r, ++e) {
                                 const Acc d = ((inside >> e) & 1ull) ? acc[bi][bj][r] - shift : (Acc)0;
                                 run[e] += d;
-                                part = fma(d, d, part);
+                                part[e % kParts] = fma(d, d, part[e % kParts]);
                             }
                 }
             } else {
@@ -956,7 +976,7 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
                             }
                             const Acc delta = d - run[e];
                             run[e] += delta * inv;
-                            part += delta * (d - run[e]);
+                            part[e % kParts] += delta * (d - run[e]);
                         }
             }
             if constexpr (!kZeroStart) {
@@ -967,7 +987,7 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void sketch_kernel(SketchPara
 #pragma unroll
                         for (int r = 0; r < P::REGS; ++r) acc[bi][bj][r] = (Acc)0;
             }
-            m2_sum += (double)part;
+            m2_sum += (double)((part[0] + part[1]) + (part[2] + part[3]));
         };
 
         if (total > 0) fetch(std::integral_constant<int, 0>(), 0);
