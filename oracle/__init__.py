@@ -119,8 +119,11 @@ def lib():
         L.orc_level_estimation.argtypes = (
             [ctypes.c_int64] * 3 + [ctypes.POINTER(_Law)] * 2 + [ctypes.c_int64] * 3 + [ctypes.c_int32]
             + [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64,
-               ctypes.c_int64, ctypes.POINTER(_Func), ctypes.POINTER(_Weights), ctypes.c_void_p,
+               ctypes.c_int64, ctypes.POINTER(_Func), ctypes.POINTER(_Weights), ctypes.c_int32, ctypes.c_void_p,
                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p])
+        L.orc_multiset.restype = ctypes.c_int64
+        L.orc_multiset.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.orc_weights_cumulative.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
         L.orc_draw_index_weighted.restype = ctypes.c_int64
         L.orc_draw_index_weighted.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
@@ -440,12 +443,14 @@ def level_estimation(state: LevelState, m: int, n: int, p: int, A: Law, B: Law,
                      c_l: int, c_prev: int, seed: int, problem: int, lfield: int,
                      k_begin: int, k_end: int, want_samples: bool = False,
                      func: Optional[Func] = None, weights: Optional["Weights"] = None,
-                     coupling: str = "prefix", index_word32: bool = False):
+                     coupling: str = "prefix", index_word32: bool = False, as_set: bool = False):
     """Alg. 1 for realisations [k_begin, k_end), continuing `state` in place;
     level samples f(Zf) - f(Zc) (identity when func is None).  coupling:
     "prefix" (the coarse sketch takes the first c_prev draws) or "stride"
     (every M-th draw, M = c_l / c_prev, Sec. 3.1).  index_word32: the indices
-    from 32-bit words (draw_indices(word32=True))."""
+    from 32-bit words (draw_indices(word32=True)).  as_set: each index tuple
+    is taken as a set with multiplicities (the note after Alg. 1), every
+    distinct column read once."""
     cnt = ctypes.c_int64(state.count)
     samples = np.empty((max(k_end - k_begin, 0), m, p)) if want_samples else None
     la, lb = A.c(), B.c()
@@ -456,12 +461,27 @@ def level_estimation(state: LevelState, m: int, n: int, p: int, A: Law, B: Law,
     rc = lib().orc_level_estimation(
         int(m), int(n), int(p), ctypes.byref(la), ctypes.byref(lb), int(c_l), int(c_prev),
         coupling_stride(c_l, c_prev, coupling), int(bool(index_word32)), int(seed), int(problem), int(lfield), int(k_begin), int(k_end), ctypes.byref(fc),
-        ctypes.byref(wc) if wc is not None else None,
+        ctypes.byref(wc) if wc is not None else None, int(bool(as_set)),
         ctypes.byref(cnt), _ptr(state.mean), _ptr(state.m2), _ptr(samples) if want_samples else None)
     if rc != 0:
         raise ValueError("orc_level_estimation rejected its arguments")
     state.count = cnt.value
     return samples
+
+
+def multiset(r: Sequence[int], c_c: int = 0, stride: int = 0):
+    """The index tuple r as a set with multiplicities (the note after Alg. 1):
+    (distinct values ascending, draws per value, coarse draws per value) for
+    the c_c coarse draws of the coupling (stride 0: the first c_c)."""
+    r = np.ascontiguousarray(r, dtype=np.int64)
+    c_f = len(r)
+    j = np.empty(c_f, dtype=np.int64)
+    mf = np.empty(c_f, dtype=np.int64)
+    mc = np.empty(c_f, dtype=np.int64)
+    u = lib().orc_multiset(c_f, _ptr(r), int(c_c), int(stride), _ptr(j), _ptr(mf), _ptr(mc))
+    if u < 0:
+        raise ValueError("orc_multiset rejected its arguments")
+    return j[:u].copy(), mf[:u].copy(), mc[:u].copy()
 
 
 # --------------------------------------------------------------------------
@@ -521,7 +541,7 @@ def estimate(m: int, n: int, p: int, A: Law, B: Law, c: Sequence[int],
              pilot: int = 0, seed: int = 0, problem: int = 0, shared: bool = False,
              max_total_draws: int = 0, pool=None, func: Optional[Func] = None,
              adaptive: Optional[str] = None, weights: Optional[Weights] = None,
-             coupling: str = "prefix", index_word32: bool = False) -> Estimate:
+             coupling: str = "prefix", index_word32: bool = False, as_set: bool = False) -> Estimate:
     """MLMC estimate of E[f(AB)] (f entrywise, identity by default) over the
     ladder c_0 < c_1 < ... < c_L.
 
@@ -545,7 +565,7 @@ def estimate(m: int, n: int, p: int, A: Law, B: Law, c: Sequence[int],
     def run(l, k0, k1):
         level_estimation(states[l], m, n, p, A, B, c[l], c[l - 1] if l > 0 else 0,
                          seed, problem, level_field(l, shared), k0, k1, func=func, weights=weights,
-                         coupling=coupling, index_word32=index_word32)
+                         coupling=coupling, index_word32=index_word32, as_set=as_set)
 
     def run_all(ranges):
         if pool is None:

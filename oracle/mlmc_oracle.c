@@ -538,18 +538,90 @@ void orc_sketch_pair(int64_t m, int64_t p, int64_t n, int64_t c_f, int64_t c_c, 
     }
 }
 
+static int cmp_int64(const void* a, const void* b)
+{
+    int64_t x = *(const int64_t*)a, y = *(const int64_t*)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+/* The tuple (r_0, ..., r_{c_f - 1}) of one realisation as a set with
+ * multiplicities (the simplification noted after Alg. 1 in Sec. 3.1): its
+ * distinct values in increasing order into j_out, and for each the number of
+ * all draws (mu_f) and of the c_c coarse draws (coarse_draw(i, stride),
+ * i < c_c: mu_c) that took it.  Returns the number of distinct values, or -1
+ * on bad arguments / allocation failure.  The outputs hold c_f entries. */
+int64_t orc_multiset(int64_t c_f, const int64_t* r, int64_t c_c, int64_t stride, int64_t* j_out,
+                     int64_t* mu_f, int64_t* mu_c)
+{
+    if (c_f < 1 || c_c < 0 || c_c > c_f || stride < 0 || (stride > 0 && stride * c_c > c_f)) return -1;
+    int64_t* sorted = (int64_t*)malloc(sizeof(int64_t) * (size_t)c_f);
+    if (!sorted) return -1;
+    memcpy(sorted, r, sizeof(int64_t) * (size_t)c_f);
+    qsort(sorted, (size_t)c_f, sizeof(int64_t), cmp_int64);
+    int64_t u = 0;
+    for (int64_t t = 0; t < c_f; ++t) {
+        if (u == 0 || sorted[t] != j_out[u - 1]) {
+            j_out[u] = sorted[t];
+            mu_f[u] = 0;
+            mu_c[u] = 0;
+            ++u;
+        }
+        mu_f[u - 1] += 1;
+    }
+    for (int64_t i = 0; i < c_c; ++i) {
+        const int64_t j = r[coarse_draw(i, stride)];
+        int64_t lo = 0, hi = u - 1;          /* binary search: j is in j_out */
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) / 2;
+            if (j_out[mid] < j) lo = mid + 1;
+            else hi = mid;
+        }
+        mu_c[lo] += 1;
+    }
+    free(sorted);
+    return u;
+}
+
+/* The sketches of eq. (18) from the set form: with the u distinct columns
+ * a_j (AS + i*m) and rows b_j (BS + i*p) read once each,
+ *   Zf = (1 / c_f) sum_i mu_f(i) g_i a_i b_i^T,   Zc = (1 / c_c) sum_i mu_c(i) g_i a_i b_i^T,
+ * g_i = n (uniform draws) or factor[i] = W / w_j (weighted draws).  Equal to
+ * orc_sketch_pair / orc_sketch_pair_weighted up to the order of the sums.
+ * c_c == 0 leaves Zc untouched. */
+void orc_sketch_pair_set(int64_t m, int64_t p, int64_t n, int64_t c_f, int64_t c_c, int64_t u,
+                         const int64_t* mu_f, const int64_t* mu_c, const double* factor, const double* AS,
+                         const double* BS, double* Zf, double* Zc)
+{
+    for (int64_t i = 0; i < m; ++i) {
+        for (int64_t q = 0; q < p; ++q) {
+            double sf = 0.0, sc = 0.0;
+            for (int64_t v = 0; v < u; ++v) {
+                const double g = factor ? factor[v] : (double)n;
+                const double ab = g * (AS[v * m + i] * BS[v * p + q]);
+                sf += (double)mu_f[v] * ab;
+                if (c_c > 0) sc += (double)mu_c[v] * ab;
+            }
+            Zf[i * p + q] = sf / (double)c_f;
+            if (c_c > 0) Zc[i * p + q] = sc / (double)c_c;
+        }
+    }
+}
+
 /* Alg. 1 (level_estimation) for realisations k_begin <= k < k_end of one
  * level.  Level sample D = f(Zf) - f(Zc) (l > 0) or f(Zf) (l = 0,
  * c_prev == 0), f entrywise (NULL: identity).  Per entry, Welford's running
  * mean/M2 are updated in place, so
  * a call can continue the samples of an earlier call (Alg. 2 reuses earlier
  * evaluations).  samples_out (nullable) receives every D, row-major.
- * Returns 0, or -1 on bad arguments / allocation failure. */
+ * as_set: each realisation's index tuple is taken as a set with
+ * multiplicities (orc_multiset), its distinct columns read once
+ * (orc_sketch_pair_set).  Returns 0, or -1 on bad arguments / allocation
+ * failure. */
 int orc_level_estimation(int64_t m, int64_t n, int64_t p, const orc_law* A, const orc_law* B,
                          int64_t c_l, int64_t c_prev, int64_t stride, int32_t word32, uint64_t seed,
                          uint32_t problem,
                          uint32_t level_field, int64_t k_begin, int64_t k_end, const orc_func* f,
-                         const orc_weights* iw, int64_t* count, double* mean, double* m2,
+                         const orc_weights* iw, int32_t as_set, int64_t* count, double* mean, double* m2,
                          double* samples_out)
 {
     if (m < 1 || p < 1 || n < 1 || c_l < 1 || c_prev < 0 || c_prev > c_l || k_end < k_begin)
@@ -563,10 +635,13 @@ int orc_level_estimation(int64_t m, int64_t n, int64_t p, const orc_law* A, cons
     double* Zf = (double*)malloc(sizeof(double) * (size_t)mp);
     double* Zc = (double*)malloc(sizeof(double) * (size_t)mp);
     double* factor = (double*)malloc(sizeof(double) * (size_t)c_l);
-    if (!r || !AS || !BS || !Zf || !Zc || !factor) {
-        free(r); free(AS); free(BS); free(Zf); free(Zc); free(factor);
+    int64_t* js = (int64_t*)malloc(sizeof(int64_t) * (size_t)c_l * 3);
+    if (!r || !AS || !BS || !Zf || !Zc || !factor || !js) {
+        free(r); free(AS); free(BS); free(Zf); free(Zc); free(factor); free(js);
         return -1;
     }
+    int64_t* mu_f = js + c_l;
+    int64_t* mu_c = js + 2 * c_l;
     for (int64_t k = k_begin; k < k_end; ++k) {
         /* Sample c_l indices (uniformly, or with probabilities w_j / W), then
          * read the sampled columns of the realisation A^(k), B^(k). */
@@ -578,13 +653,26 @@ int orc_level_estimation(int64_t m, int64_t n, int64_t p, const orc_law* A, cons
         } else {
             orc_draw_indices_mode(seed, problem, level_field, (uint32_t)k, c_l, n, word32, r);
         }
-        for (int64_t t = 0; t < c_l; ++t)
-            orc_column(seed, problem, level_field, (uint32_t)k, r[t], m, p, A, B,
-                       AS + t * m, BS + t * p);
-        if (iw)
-            orc_sketch_pair_weighted(m, p, c_l, c_prev, stride, factor, AS, BS, Zf, Zc);
-        else
-            orc_sketch_pair(m, p, n, c_l, c_prev, stride, AS, BS, Zf, Zc);
+        if (as_set) {
+            const int64_t u = orc_multiset(c_l, r, c_prev, stride, js, mu_f, mu_c);
+            if (u < 0) {
+                free(r); free(AS); free(BS); free(Zf); free(Zc); free(factor); free(js);
+                return -1;
+            }
+            for (int64_t v = 0; v < u; ++v) {
+                orc_column(seed, problem, level_field, (uint32_t)k, js[v], m, p, A, B, AS + v * m, BS + v * p);
+                if (iw) factor[v] = (double)iw->total / (double)iw->w[js[v]];
+            }
+            orc_sketch_pair_set(m, p, n, c_l, c_prev, u, mu_f, mu_c, iw ? factor : NULL, AS, BS, Zf, Zc);
+        } else {
+            for (int64_t t = 0; t < c_l; ++t)
+                orc_column(seed, problem, level_field, (uint32_t)k, r[t], m, p, A, B,
+                           AS + t * m, BS + t * p);
+            if (iw)
+                orc_sketch_pair_weighted(m, p, c_l, c_prev, stride, factor, AS, BS, Zf, Zc);
+            else
+                orc_sketch_pair(m, p, n, c_l, c_prev, stride, AS, BS, Zf, Zc);
+        }
         *count += 1;
         double cnt = (double)(*count);
         for (int64_t e = 0; e < mp; ++e) {
@@ -597,7 +685,7 @@ int orc_level_estimation(int64_t m, int64_t n, int64_t p, const orc_law* A, cons
             m2[e] += delta * (d - mean[e]);
         }
     }
-    free(r); free(AS); free(BS); free(Zf); free(Zc); free(factor);
+    free(r); free(AS); free(BS); free(Zf); free(Zc); free(factor); free(js);
     return 0;
 }
 
