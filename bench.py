@@ -704,6 +704,15 @@ def bench_batched(args):
         est.release()
         del est
         torch.cuda.empty_cache()
+        # the single-launch form beside it (one persistent kernel for every
+        # pass of every level), at the tile where the table is whole
+        single = {"tile": 64, "target_blocks": 0, "gather_budget": 768 << 20, "single_launch": 1}
+        est = BatchedEstimate(probs, c, N, seed=0, prec=prec, tuning=single, device=dev, value16=_value16(prec))
+        est.capture()
+        out[prec]["single_launch_s_per_estimate"] = _time_replays(est, args.steps, args.warmup)
+        est.release()
+        del est
+        torch.cuda.empty_cache()
     value = 1.0 / out["fp8"]["s_per_estimate"]
     res = {"metric": "MLMC batched estimates/s (256 products per estimate, fixed N_l)", "value": value,
            "unit": "estimates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

@@ -139,6 +139,18 @@ typedef enum {
  * then truncated at 4.85 standard deviations (variance low by about 1e-5
  * relative, mean exact by symmetry).  EINVAL otherwise. */
 #define MLMC_FLAG_VALUE16 32u
+/* Set form of every realisation (the note after Alg. 1 in Sec. 3.1: the
+ * index tuple (r_1, ..., r_{c_l}) mapped to a set of distinct indices with
+ * multiplicities): before the gather, each realisation's distinct indices
+ * are counted (coarse draws and the others apart) and each distinct column
+ * of A^(k) and row of B^(k) is generated once, at the first position that
+ * drew it, weighted by the sum of the weights of its draws; the repeats stay
+ * zero.  The estimate equals the default tuple form up to the order of the
+ * sums, and a realisation generates at most min(c_l, n) columns.  Matrix
+ * products (batched included), FP64 or FP32 operands, f = identity, uniform
+ * index draws; EINVAL otherwise.  The contraction still runs over all c_l
+ * positions. */
+#define MLMC_FLAG_SET_FORM 64u
 #define MLMC_MAX_LEVELS 32
 
 /* Kernel classes of mlmc_report.kernel_ms (MLMC_FLAG_TIMING). */
@@ -277,11 +289,23 @@ typedef struct {
 /* Launch shape (all zero = defaults; chosen by the autotuner of the Python
  * package): tile = workgroup output tile edge (64 or 128; FP64 uses 64),
  * target_blocks = sketch work items per pass, gather_budget = bytes of
- * gathered operands per pass. */
+ * gathered operands per pass.  single_launch = 1: the whole estimate (every
+ * pass of every level) in one persistent kernel, whose phase p gathers pass p
+ * while it sketches pass p - 1, its work claimed from per-XCD queues (sketch
+ * tiles first, then gather chunks) and its phases ended by bounded grid-wide
+ * barriers; built for FP32, BF16 and FP8 operands, i.i.d. normal or uniform
+ * laws, f = identity, and products in whole tiles at tile 64 or of any shape
+ * at tile 128 (other tables, and 0, take a gather, a sketch and a merge
+ * launch per pass).  It gives the same estimate as
+ * the launch-per-pass form with one realisation group per pass.  Its
+ * workgroups must all be resident at once: its grid is the device's resident
+ * capacity for it, and a barrier that waits past ten seconds makes every
+ * output NaN (and the call EDEVICE when it reads level_var). */
 typedef struct {
     int32_t tile;
     int64_t target_blocks;
     int64_t gather_budget;
+    int32_t single_launch;
 } mlmc_tuning;
 
 size_t mlmc_matmul_batched_workspace_size(int32_t nprob, const mlmc_problem* probs,

@@ -43,7 +43,7 @@ class Problem(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("target_blocks", ctypes.c_int64),
-                ("gather_budget", ctypes.c_int64)]
+                ("gather_budget", ctypes.c_int64), ("single_launch", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):

@@ -3,7 +3,8 @@
 Candidates: workgroup output tile (64 or 128) x sketch work items per pass
 (target_blocks) x bytes of gathered operands per pass (gather_budget: the
 larger budget means fewer, larger passes and fewer merges of the level
-state).  Each candidate runs the batch's whole ladder with a quarter of every
+state), and the single-launch form at either tile (batches it is not built
+for plan the launch-per-pass form for it).  Each candidate runs the batch's whole ladder with a quarter of every
 level's realisations on the GPU (warm-up, then timed with HIP events via
 torch on the current stream); the fastest is cached in a JSON file keyed by
 a signature of the batch (precision, ladder head, per-product shapes bucketed
@@ -20,8 +21,9 @@ import torch
 
 from .mlmc import BatchedEstimate, BatchProblem
 
-CANDIDATES = [{"tile": t, "target_blocks": b, "gather_budget": g}
-              for t in (64, 128) for b in (1024, 4096) for g in (192 << 20, 768 << 20)]
+CANDIDATES = [{"tile": t, "target_blocks": b, "gather_budget": g, "single_launch": 0}
+              for t in (64, 128) for b in (1024, 4096) for g in (192 << 20, 768 << 20)] + \
+             [{"tile": t, "target_blocks": 0, "gather_budget": 768 << 20, "single_launch": 1} for t in (64, 128)]
 
 
 def cache_path() -> str:

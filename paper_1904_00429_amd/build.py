@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmlmc.so")
-SOURCES = ["api.hip", "inner.hip", "matmul.hip", "blocks.hip", "adjoint.hip"]
+SOURCES = ["api.hip", "inner.hip", "matmul.hip", "persist.hip", "blocks.hip", "adjoint.hip"]
 ARCH = os.environ.get("MLMC_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

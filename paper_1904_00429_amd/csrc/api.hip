@@ -4,6 +4,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <string.h>
 
 #include <algorithm>
 #include <mutex>
@@ -87,6 +88,13 @@ mlmc_status check_levels(const mlmc_levels* lv, bool inner)
         return fail(MLMC_EINVAL, "target function parameters must be finite");
     if (lv->func == MLMC_FUNC_INV_ABS_STEP && !(lv->func_param[1] > 0.0))
         return fail(MLMC_EINVAL, "1 / (|x| H(x + theta0) + theta1) needs theta1 > 0");
+    if (lv->flags & MLMC_FLAG_SET_FORM) {
+        if (inner) return fail(MLMC_EINVAL, "the set form is offered for matrix products");
+        if (lv->prec != MLMC_PREC_FP64 && lv->prec != MLMC_PREC_FP32)
+            return fail(MLMC_EINVAL, "the set form takes FP64 or FP32 operands");
+        if (lv->func != MLMC_FUNC_IDENTITY) return fail(MLMC_EINVAL, "the set form takes f = identity");
+        if (lv->index_weights) return fail(MLMC_EINVAL, "the set form takes uniform index draws");
+    }
     return MLMC_OK;
 }
 
@@ -150,29 +158,25 @@ StreamKeys keys_of(const mlmc_levels* lv)
     return k;
 }
 
-// eq. (28): N_l = ceil(2 eps^-2 sqrt(V_l / C_l) sum_j sqrt(V_j C_j)), C_l = c_l.
-// eq. (28) over levels 0 .. nlev - 1
+// The status of eq. (28)'s schedule_counts as a C ABI status.
+mlmc_status schedule_status(const mlmc_levels* lv, int code, int bad_level, double bad_value)
+{
+    if (code == 1)
+        return fail(MLMC_EBUDGET, "scheduled N_%d = %g exceeds the realisation counter range", bad_level, bad_value);
+    if (code == 2)
+        return fail(MLMC_EBUDGET, "scheduled draws %.6g exceed max_total_draws %lld", bad_value,
+                    (long long)lv->max_total_draws);
+    return MLMC_OK;
+}
+
+// eq. (28) over levels 0 .. nlev - 1 on the host
 mlmc_status schedule(const mlmc_levels* lv, const double* var, int nlev, int64_t* n_out)
 {
-    const double eps = lv->rmse_target;
-    double total = 0.0;
-    for (int l = 0; l < nlev; ++l) total += sqrt(var[l] * (double)lv->c[l]);
-    for (int l = 0; l < nlev; ++l) {
-        const double nl = ceil(2.0 / (eps * eps) * sqrt(var[l] / (double)lv->c[l]) * total);
-        if (!(nl < (double)kU32))
-            return fail(MLMC_EBUDGET, "scheduled N_%d = %g exceeds the realisation counter range", l, nl);
-        int64_t v = (int64_t)nl;
-        if (v < lv->pilot_samples) v = lv->pilot_samples;
-        n_out[l] = v;
-    }
-    if (lv->max_total_draws > 0) {
-        double draws = 0.0;
-        for (int l = 0; l < nlev; ++l) draws += (double)n_out[l] * (double)lv->c[l];
-        if (draws > (double)lv->max_total_draws)
-            return fail(MLMC_EBUDGET, "scheduled draws %.6g exceed max_total_draws %lld", draws,
-                        (long long)lv->max_total_draws);
-    }
-    return MLMC_OK;
+    int bad_level = 0;
+    double bad_value = 0.0;
+    const int code = schedule_counts(lv->rmse_target, lv->c, var, nlev, lv->pilot_samples, lv->max_total_draws,
+                                     n_out, &bad_level, &bad_value);
+    return schedule_status(lv, code, bad_level, bad_value);
 }
 
 // The bias test of the adaptive loop on the finest level mean so far (its
@@ -223,7 +227,7 @@ LevelRange range_of(const mlmc_levels* lv, int l, int64_t k_begin, int64_t count
 // Inner-product workspace: per-level Moments, workgroup partials, V_l, and
 // the cumulative index weights when the draws are weighted.
 struct InnerLayout {
-    size_t off_state, off_partials, off_var, off_cum, total;
+    size_t off_state, off_partials, off_var, off_cum, off_slot, off_counts, off_status, total;
 };
 
 InnerLayout inner_layout(int num_levels, int64_t n, bool weighted)
@@ -232,9 +236,13 @@ InnerLayout inner_layout(int num_levels, int64_t n, bool weighted)
     auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
     L.off_state = 0;
     L.off_partials = align(sizeof(Moments) * num_levels);
+    // V_l, then the scheduled counts and the schedule's status: one readback
     L.off_var = align(L.off_partials + sizeof(Moments) * inner_partials_capacity());
-    L.off_cum = align(L.off_var + sizeof(double) * num_levels);
-    L.total = align(L.off_cum + (weighted ? sizeof(uint64_t) * n : 0));
+    L.off_counts = L.off_var + sizeof(double) * num_levels;
+    L.off_status = L.off_counts + sizeof(int64_t) * num_levels;
+    L.off_cum = align(L.off_status + 2 * sizeof(int32_t) + sizeof(double));
+    L.off_slot = align(L.off_cum + (weighted ? sizeof(uint64_t) * n : 0));
+    L.total = align(L.off_slot + inner_slot_bytes());
     return L;
 }
 
@@ -307,6 +315,7 @@ size_t mlmc_matmul_workspace_size(int64_t m, int64_t n, int64_t p, const mlmc_le
     if (!matmul_plan(&pr, 1, levels->prec, levels->num_levels, levels->c, nullptr, func_of(levels),
                      levels->index_weights, plan))
         return 0;
+    if (levels->flags & MLMC_FLAG_SET_FORM) matmul_plan_set_form(plan);
     return plan.total;
 }
 
@@ -333,6 +342,7 @@ mlmc_status mlmc_inner_product_estimate(int64_t n, const mlmc_dist* x, const mlm
     Moments* state = reinterpret_cast<Moments*>(ws + L.off_state);
     Moments* partials = reinterpret_cast<Moments*>(ws + L.off_partials);
     double* var_dev = reinterpret_cast<double*>(ws + L.off_var);
+    InnerSlot* slot = reinterpret_cast<InnerSlot*>(ws + L.off_slot);
     const IndexWeights iw{lv->index_weights,
                           lv->index_weights ? reinterpret_cast<const uint64_t*>(ws + L.off_cum) : nullptr};
     const Law lx = to_law(*x), ly = to_law(*y);
@@ -342,21 +352,22 @@ mlmc_status mlmc_inner_product_estimate(int64_t n, const mlmc_dist* x, const mlm
     std::vector<double> var(L1, 0.0);
     KernelTimer timer_obj(stream);
     KernelTimer* timer = (lv->flags & MLMC_FLAG_TIMING) ? &timer_obj : nullptr;
-    hipError_t e;
-    {
+    hipError_t e = hipSuccess;
+    if (iw.w) {
         ScopedTiming t(timer, MLMC_KERNEL_FINAL);
-        e = fill_doubles(reinterpret_cast<double*>(state), 3 * L1, 0.0, stream);
-        if (e == hipSuccess && iw.w)
-            e = build_cumulative(iw.w, n, reinterpret_cast<uint64_t*>(ws + L.off_cum), stream);
+        e = build_cumulative(iw.w, n, reinterpret_cast<uint64_t*>(ws + L.off_cum), stream);
     }
-    if (e != hipSuccess) return device_fail(e, "state reset");
+    if (e != hipSuccess) return device_fail(e, "cumulative weights");
+    const InnerTelescope tele{out, level_means, var_dev};
+    const bool word32 = (lv->flags & MLMC_FLAG_INDEX_WORD32) != 0;
 
-    // every level of a phase goes into one launch
-    auto run_all = [&](const int64_t* k0, const int64_t* cnt) -> hipError_t {
+    // every level of a phase goes into one launch; the first phase of an
+    // estimate clears the level states, the last one telescopes
+    auto run_all = [&](const int64_t* k0, const int64_t* cnt, bool first, bool last) -> hipError_t {
         LevelRange ranges[MLMC_MAX_LEVELS];
         for (int l = 0; l < L1; ++l) ranges[l] = range_of(lv, l, k0[l], cnt[l]);
-        return inner_levels_run(ranges, L1, n, lx, ly, func_of(lv), iw, lv->prec,
-                                (lv->flags & MLMC_FLAG_INDEX_WORD32) != 0, keys, partials, state, stream, timer);
+        return inner_levels_run(ranges, L1, n, lx, ly, func_of(lv), iw, lv->prec, word32, keys, partials, state,
+                                slot, first, last ? &tele : nullptr, stream, timer);
     };
     std::vector<int64_t> zero(L1, 0), amount(L1, 0);
     int used = L1;
@@ -370,7 +381,8 @@ mlmc_status mlmc_inner_product_estimate(int64_t n, const mlmc_dist* x, const mlm
         for (int L = 0; L < L1 && !passed; ++L) {
             std::fill(amount.begin(), amount.end(), 0);
             amount[L] = lv->pilot_samples;
-            if ((e = run_all(counts.data(), amount.data())) != hipSuccess) return device_fail(e, "pilot launch");
+            if ((e = run_all(counts.data(), amount.data(), L == 0, false)) != hipSuccess)
+                return device_fail(e, "pilot launch");
             counts[L] = lv->pilot_samples;
             used = L + 1;
             {
@@ -384,7 +396,8 @@ mlmc_status mlmc_inner_product_estimate(int64_t n, const mlmc_dist* x, const mlm
                 return device_fail(e, "level statistics readback");
             if ((st = schedule(lv, var.data(), used, target.data())) != MLMC_OK) return st;
             for (int l = 0; l < L1; ++l) amount[l] = l < used && target[l] > counts[l] ? target[l] - counts[l] : 0;
-            if ((e = run_all(counts.data(), amount.data())) != hipSuccess) return device_fail(e, "extension launch");
+            if ((e = run_all(counts.data(), amount.data(), false, false)) != hipSuccess)
+                return device_fail(e, "extension launch");
             for (int l = 0; l < L1; ++l) counts[l] += amount[l];
             if (used >= 3) {
                 Moments fin;
@@ -396,32 +409,48 @@ mlmc_status mlmc_inner_product_estimate(int64_t n, const mlmc_dist* x, const mlm
             }
         }
     } else if (lv->rmse_target > 0.0) {
-        for (int l = 0; l < L1; ++l) amount[l] = lv->pilot_samples;
-        if ((e = run_all(zero.data(), amount.data())) != hipSuccess) return device_fail(e, "pilot launch");
-        for (int l = 0; l < L1; ++l) counts[l] = lv->pilot_samples;
-        {
-            ScopedTiming t(timer, MLMC_KERNEL_FINAL);
-            e = inner_telescope(state, L1, out, nullptr, var_dev, stream);
+        // the pilot, eq. (28) and the extension, all on the device: one
+        // synchronisation at the end reads V_l, N_l and the schedule's status
+        InnerScheduleInputs sch;
+        sch.eps = lv->rmse_target;
+        sch.pilot = lv->pilot_samples;
+        sch.max_total_draws = lv->max_total_draws;
+        sch.c = lv->c;
+        LevelRange pilot[MLMC_MAX_LEVELS];
+        for (int l = 0; l < L1; ++l) {
+            pilot[l] = range_of(lv, l, 0, lv->pilot_samples);
+            sch.level_field[l] = pilot[l].level_field;
+            sch.stride[l] = (uint32_t)pilot[l].stride;
         }
-        if (e != hipSuccess) return device_fail(e, "pilot statistics");
-        if ((e = hipMemcpyAsync(var.data(), var_dev, sizeof(double) * L1, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+        sch.counts = reinterpret_cast<int64_t*>(ws + L.off_counts);
+        sch.status = reinterpret_cast<int32_t*>(ws + L.off_status);
+        sch.status_value = reinterpret_cast<double*>(ws + L.off_status + 2 * sizeof(int32_t));
+        if ((e = inner_target_run(sch, pilot, L1, n, lx, ly, func_of(lv), iw, lv->prec, word32, keys, partials, state,
+                                  slot, tele, stream, timer)) != hipSuccess)
+            return device_fail(e, "target-mode launch");
+        std::vector<char> back(sizeof(double) * L1 + sizeof(int64_t) * L1 + 2 * sizeof(int32_t) + sizeof(double));
+        if ((e = hipMemcpyAsync(back.data(), var_dev, back.size(), hipMemcpyDeviceToHost, stream)) != hipSuccess ||
             (e = hipStreamSynchronize(stream)) != hipSuccess)
-            return device_fail(e, "pilot readback");
-        std::vector<int64_t> target(L1);
-        if ((st = schedule(lv, var.data(), L1, target.data())) != MLMC_OK) return st;
-        for (int l = 0; l < L1; ++l) amount[l] = target[l] - counts[l];
-        if ((e = run_all(counts.data(), amount.data())) != hipSuccess) return device_fail(e, "extension launch");
-        for (int l = 0; l < L1; ++l) counts[l] = target[l];
+            return device_fail(e, "schedule readback");
+        memcpy(var.data(), back.data(), sizeof(double) * L1);
+        memcpy(counts.data(), back.data() + sizeof(double) * L1, sizeof(int64_t) * L1);
+        int32_t code[2];
+        double value;
+        memcpy(code, back.data() + 16 * L1, sizeof(code));
+        memcpy(&value, back.data() + 16 * L1 + sizeof(code), sizeof(value));
+        if ((st = schedule_status(lv, code[0], code[1], value)) != MLMC_OK) return st;
+        if (report) fill_report(lv, counts.data(), var.data(), timer, report, used, passed);
+        return MLMC_OK;
     } else {
         for (int l = 0; l < L1; ++l) amount[l] = lv->n_samples[l];
-        if ((e = run_all(zero.data(), amount.data())) != hipSuccess) return device_fail(e, "level launch");
+        if ((e = run_all(zero.data(), amount.data(), true, true)) != hipSuccess) return device_fail(e, "level launch");
         for (int l = 0; l < L1; ++l) counts[l] = lv->n_samples[l];
     }
-    {
+    if (lv->flags & MLMC_FLAG_ADAPTIVE_LEVELS) {
         ScopedTiming t(timer, MLMC_KERNEL_FINAL);
         e = inner_telescope(state, L1, out, level_means, var_dev, stream);
+        if (e != hipSuccess) return device_fail(e, "telescope");
     }
-    if (e != hipSuccess) return device_fail(e, "telescope");
     if (report) {
         if ((e = hipMemcpyAsync(var.data(), var_dev, sizeof(double) * L1, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
             (e = hipStreamSynchronize(stream)) != hipSuccess)
@@ -449,6 +478,7 @@ mlmc_status mlmc_matmul_estimate(int64_t m, int64_t n, int64_t p, const mlmc_dis
     if (!matmul_plan(&pr, 1, lv->prec, lv->num_levels, lv->c, nullptr, func_of(lv), lv->index_weights, plan))
         return fail(MLMC_EINVAL, "no launch plan for this shape and precision");
     plan.value16 = (lv->flags & MLMC_FLAG_VALUE16) != 0;
+    if (lv->flags & MLMC_FLAG_SET_FORM) matmul_plan_set_form(plan);
     if (!workspace || workspace_bytes < plan.total)
         return fail(MLMC_EWORKSPACE, "workspace needs %zu bytes", plan.total);
     hipStream_t stream = static_cast<hipStream_t>(stream_ptr);
@@ -656,17 +686,42 @@ mlmc_status check_batch(int32_t nprob, const mlmc_problem* probs, const mlmc_lev
     std::sort(ids.begin(), ids.end());
     for (size_t i = 1; i < ids.size(); ++i)
         if (ids[i] == ids[i - 1]) return fail(MLMC_EINVAL, "duplicate stream id %u", ids[i]);
-    tuning = MatmulTuning{0, 0, 0};
+    tuning = MatmulTuning{0, 0, 0, 0};
     if (tune) {
         if (tune->tile != 0 && tune->tile != 64 && tune->tile != 128)
             return fail(MLMC_EINVAL, "tuning.tile must be 0, 64 or 128");
         if (tune->target_blocks < 0 || tune->gather_budget < 0) return fail(MLMC_EINVAL, "negative tuning value");
-        tuning = MatmulTuning{tune->tile, tune->target_blocks, tune->gather_budget};
+        if (tune->single_launch != 0 && tune->single_launch != 1)
+            return fail(MLMC_EINVAL, "tuning.single_launch must be 0 or 1");
+        tuning = MatmulTuning{tune->tile, tune->target_blocks, tune->gather_budget, tune->single_launch};
     }
     return MLMC_OK;
 }
 
-// Enqueues a whole fixed-N batched estimate (no host synchronisation).
+// The launch plan of a batched estimate: the table checked, the shapes
+// planned, and the single-launch form chosen where it is built.
+mlmc_status plan_batch(int32_t nprob, const mlmc_problem* probs, const mlmc_levels* lv, const mlmc_tuning* tuning,
+                       MatmulPlan& plan)
+{
+    std::vector<MatmulProblem> pr;
+    MatmulTuning tune;
+    mlmc_status st = check_batch(nprob, probs, lv, tuning, pr, tune);
+    if (st != MLMC_OK) return st;
+    if (!matmul_plan(pr.data(), nprob, lv->prec, lv->num_levels, lv->c, &tune, func_of(lv), nullptr, plan))
+        return fail(MLMC_EINVAL, "no launch plan for this table");
+    plan.value16 = (lv->flags & MLMC_FLAG_VALUE16) != 0;
+    if (lv->flags & MLMC_FLAG_SET_FORM) matmul_plan_set_form(plan);
+    if (tune.single_launch) {
+        std::vector<LevelRange> ranges;
+        for (int l = 0; l < lv->num_levels; ++l) ranges.push_back(range_of(lv, l, 0, lv->n_samples[l]));
+        matmul_plan_persistent(plan, ranges.data(), lv->num_levels);
+    }
+    return MLMC_OK;
+}
+
+// Enqueues a whole fixed-N batched estimate (no host synchronisation): the
+// reset, then one persistent launch for every pass of every level (or a
+// gather, a sketch and a merge launch per pass), then the finalisation.
 hipError_t enqueue_batched(const MatmulPlan& plan, const mlmc_levels* lv, char* ws, hipStream_t stream,
                            KernelTimer* timer)
 {
@@ -677,9 +732,14 @@ hipError_t enqueue_batched(const MatmulPlan& plan, const mlmc_levels* lv, char* 
     }
     if (e != hipSuccess) return e;
     const StreamKeys keys = keys_of(lv);
-    for (int l = 0; l < lv->num_levels; ++l)
-        if ((e = matmul_level_run(plan, range_of(lv, l, 0, lv->n_samples[l]), 0, keys, ws, stream, timer)) != hipSuccess)
-            return e;
+    if (plan.persistent) {
+        if ((e = matmul_persistent_run(plan, keys, ws, stream, timer)) != hipSuccess) return e;
+    } else {
+        for (int l = 0; l < lv->num_levels; ++l)
+            if ((e = matmul_level_run(plan, range_of(lv, l, 0, lv->n_samples[l]), 0, keys, ws, stream, timer)) !=
+                hipSuccess)
+                return e;
+    }
     ScopedTiming t(timer, MLMC_KERNEL_FINAL);
     return matmul_finalize(plan, lv->n_samples, ws, true, stream);
 }
@@ -696,12 +756,8 @@ extern "C" {
 size_t mlmc_matmul_batched_workspace_size(int32_t nprob, const mlmc_problem* probs, const mlmc_levels* levels,
                                           const mlmc_tuning* tuning)
 {
-    std::vector<MatmulProblem> pr;
-    MatmulTuning tune;
-    if (check_batch(nprob, probs, levels, tuning, pr, tune) != MLMC_OK) return 0;
     MatmulPlan plan;
-    if (!matmul_plan(pr.data(), nprob, levels->prec, levels->num_levels, levels->c, &tune, func_of(levels), nullptr, plan))
-        return 0;
+    if (plan_batch(nprob, probs, levels, tuning, plan) != MLMC_OK) return 0;
     return plan.total;
 }
 
@@ -710,14 +766,9 @@ mlmc_status mlmc_matmul_estimate_batched(int32_t nprob, const mlmc_problem* prob
                                          double* level_var, void* stream_ptr)
 {
     g_last_error.clear();
-    std::vector<MatmulProblem> pr;
-    MatmulTuning tune;
-    mlmc_status st = check_batch(nprob, probs, lv, tuning, pr, tune);
-    if (st != MLMC_OK) return st;
     MatmulPlan plan;
-    if (!matmul_plan(pr.data(), nprob, lv->prec, lv->num_levels, lv->c, &tune, func_of(lv), nullptr, plan))
-        return fail(MLMC_EINVAL, "no launch plan for this table");
-    plan.value16 = (lv->flags & MLMC_FLAG_VALUE16) != 0;
+    mlmc_status st = plan_batch(nprob, probs, lv, tuning, plan);
+    if (st != MLMC_OK) return st;
     if (!workspace || workspace_bytes < plan.total)
         return fail(MLMC_EWORKSPACE, "workspace needs %zu bytes", plan.total);
     hipStream_t stream = static_cast<hipStream_t>(stream_ptr);
@@ -730,6 +781,10 @@ mlmc_status mlmc_matmul_estimate_batched(int32_t nprob, const mlmc_problem* prob
                                 hipMemcpyDeviceToHost, stream)) != hipSuccess ||
             (e = hipStreamSynchronize(stream)) != hipSuccess)
             return device_fail(e, "level variance readback");
+        bool failed = false;
+        if ((e = matmul_persistent_status(plan, ws, stream, &failed)) != hipSuccess)
+            return device_fail(e, "status readback");
+        if (failed) return fail(MLMC_EDEVICE, "the single-launch estimate gave up at a phase barrier");
     }
     return MLMC_OK;
 }
@@ -742,14 +797,9 @@ mlmc_status mlmc_matmul_batched_graph_create(int32_t nprob, const mlmc_problem* 
     if (!graph) return fail(MLMC_EINVAL, "graph is NULL");
     *graph = nullptr;
     if (!stream_ptr) return fail(MLMC_EINVAL, "graph capture needs a non-null stream");
-    std::vector<MatmulProblem> pr;
-    MatmulTuning tune;
-    mlmc_status st = check_batch(nprob, probs, lv, tuning, pr, tune);
-    if (st != MLMC_OK) return st;
     MatmulPlan plan;
-    if (!matmul_plan(pr.data(), nprob, lv->prec, lv->num_levels, lv->c, &tune, func_of(lv), nullptr, plan))
-        return fail(MLMC_EINVAL, "no launch plan for this table");
-    plan.value16 = (lv->flags & MLMC_FLAG_VALUE16) != 0;
+    mlmc_status st = plan_batch(nprob, probs, lv, tuning, plan);
+    if (st != MLMC_OK) return st;
     if (!workspace || workspace_bytes < plan.total)
         return fail(MLMC_EWORKSPACE, "workspace needs %zu bytes", plan.total);
     hipStream_t stream = static_cast<hipStream_t>(stream_ptr);

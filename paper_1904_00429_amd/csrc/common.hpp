@@ -75,6 +75,41 @@ __device__ inline double experiment_value(int kind, double loc, double scale, do
 // deviations.  Merging two sets is exact in exact arithmetic (Chan, Golub,
 // LeVeque 1979) and is evaluated in a fixed order everywhere, so results are
 // bitwise reproducible.
+// Remark 3.6, eq. (28): N_l = ceil(2 eps^-2 sqrt(V_l / C_l) sum_j sqrt(V_j C_j))
+// with C_l = c_l, over levels 0 .. nlev - 1, each at least `pilot`.  One
+// definition for the host and the device (the same operations in the same
+// order, no contraction), so both schedule the same N_l.  Returns 0, 1 when
+// some N_l reaches 2^32 (bad_level: which), or 2 when the draws
+// sum_l N_l c_l exceed max_total_draws (> 0).
+__host__ __device__ inline int schedule_counts(double eps, const int64_t* c, const double* var, int nlev,
+                                               int64_t pilot, int64_t max_total_draws, int64_t* n_out,
+                                               int* bad_level, double* bad_value)
+{
+#pragma clang fp contract(off)
+    double total = 0.0;
+    for (int l = 0; l < nlev; ++l) total += sqrt(var[l] * (double)c[l]);
+    for (int l = 0; l < nlev; ++l) {
+        const double nl = ceil(2.0 / (eps * eps) * sqrt(var[l] / (double)c[l]) * total);
+        if (!(nl < 4294967296.0)) {
+            *bad_level = l;
+            *bad_value = nl;
+            return 1;
+        }
+        int64_t v = (int64_t)nl;
+        if (v < pilot) v = pilot;
+        n_out[l] = v;
+    }
+    if (max_total_draws > 0) {
+        double draws = 0.0;
+        for (int l = 0; l < nlev; ++l) draws += (double)n_out[l] * (double)c[l];
+        if (draws > (double)max_total_draws) {
+            *bad_value = draws;
+            return 2;
+        }
+    }
+    return 0;
+}
+
 struct Moments {
     double n;
     double mean;

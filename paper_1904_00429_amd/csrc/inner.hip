@@ -61,7 +61,28 @@ struct InnerMultiParams {
     const uint32_t* iw;       // index weights (IW kernels): xi_j = w_j / W
     const uint64_t* cum;      // their cumulative sums, W = cum[n - 1]
     Moments* partials;        // one per workgroup
+    uint32_t total_blocks;    // workgroups with work (a larger grid's others leave at once)
     InnerLevel lev[32];
+};
+
+// One block per level: fold that level's workgroup partials (thread i takes
+// partials i, i + 256, ... in order, then a tree), then append the result to
+// the level's running state.
+struct InnerFoldParams {
+    int32_t num_levels;
+    uint32_t block_begin[32];
+    uint32_t blocks[32];
+    const Moments* partials;
+    Moments* level_state;
+};
+
+// The parameters of a phase's level launch and fold, in device memory: the
+// kernels read them from there, so a launch whose partition the device
+// computes (after eq. (28) on the device) is enqueued like any other.
+struct InnerSlot {
+    InnerMultiParams multi;
+    InnerFoldParams fold;
+    uint32_t arrivals;        // fold workgroups done (the last one runs the fold's tail)
 };
 
 // Index from its two Philox words; a power-of-two n is the top bits of the
@@ -191,8 +212,10 @@ __device__ __forceinline__ void sum_pairs(const InnerMultiParams& prm, const Inn
 // W32: 32-bit index words, the lane walks draw quads instead of pairs (same
 // coarse range / straddling unit / fine range split, or the stride predicate).
 template <typename T, int LAWS, bool FN, bool IW, bool ST, bool W32>
-__global__ __launch_bounds__(kInnerBlock) void inner_multi_kernel(InnerMultiParams prm)
+__global__ __launch_bounds__(kInnerBlock) void inner_multi_kernel(const InnerMultiParams* __restrict__ pp)
 {
+    const InnerMultiParams& prm = *pp;
+    if (blockIdx.x >= prm.total_blocks) return;
     __shared__ double wave_sum[kInnerBlock / kWave];
     __shared__ double wave_sum_c[FN ? kInnerBlock / kWave : 1];
     __shared__ Moments slots[kInnerBlock];
@@ -335,33 +358,6 @@ __global__ __launch_bounds__(kInnerBlock) void inner_multi_kernel(InnerMultiPara
     if (threadIdx.x == 0) prm.partials[blockIdx.x] = slots[0];
 }
 
-// One block per level: fold that level's workgroup partials (thread i takes
-// partials i, i + 256, ... in order, then a tree), then append the result to
-// the level's running state.
-struct InnerFoldParams {
-    int32_t num_levels;
-    uint32_t block_begin[32];
-    uint32_t blocks[32];
-    const Moments* partials;
-    Moments* level_state;
-};
-
-__global__ __launch_bounds__(kInnerBlock) void inner_fold_kernel(InnerFoldParams prm)
-{
-    __shared__ Moments slots[kInnerBlock];
-    const int l = blockIdx.x;
-    const Moments* part = prm.partials + prm.block_begin[l];
-    Moments st = {0.0, 0.0, 0.0};
-    for (uint32_t i = threadIdx.x; i < prm.blocks[l]; i += kInnerBlock) st = chan_merge(st, part[i]);
-    slots[threadIdx.x] = st;
-    __syncthreads();
-    for (int half = kInnerBlock >> 1; half > 0; half >>= 1) {
-        if ((int)threadIdx.x < half) slots[threadIdx.x] = chan_merge(slots[threadIdx.x], slots[threadIdx.x + half]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0 && prm.blocks[l] > 0) prm.level_state[l] = chan_merge(prm.level_state[l], slots[0]);
-}
-
 __global__ void inner_telescope_kernel(const Moments* level_state, int num_levels, double* out,
                                        double* level_means, double* level_var)
 {
@@ -379,7 +375,7 @@ __global__ void inner_telescope_kernel(const Moments* level_state, int num_level
 size_t inner_partials_capacity() { return kInnerMaxBlocks; }
 
 // Lanes per realisation: at least eight draw pairs per lane, at most a workgroup.
-static uint32_t lanes_log2_for(int64_t c)
+__host__ __device__ inline uint32_t lanes_log2_for(int64_t c)
 {
     const int64_t pairs = (c + 1) / 2;
     uint32_t g = 0;
@@ -387,95 +383,23 @@ static uint32_t lanes_log2_for(int64_t c)
     return g;
 }
 
-template <typename T, bool FN, bool IW, bool ST>
-static void launch_inner(int laws, dim3 grid, hipStream_t stream, const InnerMultiParams& prm)
+// The partition of a phase's launch over its levels (host for the pilot and
+// fixed phases, device for the extension that eq. (28) schedules there):
+// workgroups dealt to levels in proportion to their draw pairs, at most
+// kInnerMaxBlocks in all.  Fills the level fields of prm and the fold's
+// ranges; returns the number of workgroups with work.
+__host__ __device__ inline uint32_t inner_partition(const LevelRange* ranges, int num_levels, int64_t n,
+                                                    uint32_t problem, InnerMultiParams& prm, InnerFoldParams& fold)
 {
-    const dim3 block(kInnerBlock);
-    if (laws == kLawsUniform)
-        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsUniform, FN, IW, ST, false>), grid, block, 0, stream, prm);
-    else if (laws == kLawsNormal)
-        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsNormal, FN, IW, ST, false>), grid, block, 0, stream, prm);
-    else if (laws == kLawsExperiment)
-        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsExperiment, FN, IW, ST, false>), grid, block, 0, stream, prm);
-    else
-        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsAny, FN, IW, ST, false>), grid, block, 0, stream, prm);
-}
-
-// 32-bit index words: uniform draws and the classic laws only (the host checks)
-template <typename T, bool FN, bool ST>
-static void launch_inner_w32(int laws, dim3 grid, hipStream_t stream, const InnerMultiParams& prm)
-{
-    const dim3 block(kInnerBlock);
-    if (laws == kLawsUniform)
-        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsUniform, FN, false, ST, true>), grid, block, 0, stream, prm);
-    else if (laws == kLawsNormal)
-        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsNormal, FN, false, ST, true>), grid, block, 0, stream, prm);
-    else
-        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsAny, FN, false, ST, true>), grid, block, 0, stream, prm);
-}
-
-template <typename T>
-static void launch_inner_forms(int laws, dim3 grid, hipStream_t stream, const InnerMultiParams& prm, bool st,
-                               bool w32)
-{
-    const bool fn = prm.f.kind != 0, iw = prm.iw != nullptr;
-    if (w32) {
-        if (fn && st) launch_inner_w32<T, true, true>(laws, grid, stream, prm);
-        else if (fn) launch_inner_w32<T, true, false>(laws, grid, stream, prm);
-        else if (st) launch_inner_w32<T, false, true>(laws, grid, stream, prm);
-        else launch_inner_w32<T, false, false>(laws, grid, stream, prm);
-        return;
-    }
-    if (st) {
-        // the stride coupling: one instantiation per precision, law pair and form
-        if (fn && iw) launch_inner<T, true, true, true>(laws, grid, stream, prm);
-        else if (fn) launch_inner<T, true, false, true>(laws, grid, stream, prm);
-        else if (iw) launch_inner<T, false, true, true>(laws, grid, stream, prm);
-        else launch_inner<T, false, false, true>(laws, grid, stream, prm);
-        return;
-    }
-    if (fn && iw) launch_inner<T, true, true, false>(laws, grid, stream, prm);
-    else if (fn) launch_inner<T, true, false, false>(laws, grid, stream, prm);
-    else if (iw) launch_inner<T, false, true, false>(laws, grid, stream, prm);
-    else launch_inner<T, false, false, false>(laws, grid, stream, prm);
-}
-
-hipError_t inner_levels_run(const LevelRange* ranges, int num_levels, int64_t n, const Law& x, const Law& y,
-                            const TargetFunc& f, const IndexWeights& iw, int prec, bool index_word32,
-                            const StreamKeys& keys, Moments* partials, Moments* level_state, hipStream_t stream,
-                            KernelTimer* timer)
-{
-    InnerMultiParams prm;
-    prm.f = f;
-    prm.iw = iw.w;
-    prm.cum = iw.cum;
-    prm.n = (uint32_t)n;
-    prm.n_shift = 0xFFFFFFFFu;
-    if ((n & (n - 1)) == 0) {
-        uint32_t lg = 0;
-        while ((int64_t(1) << lg) < n) ++lg;
-        prm.n_shift = 32u - lg;     // n = 1 gives a shift of 32: every index is 0
-    }
-    prm.key0 = keys.key0;
-    prm.key1 = keys.key1;
-    prm.num_levels = num_levels;
-    prm.x = x;
-    prm.y = y;
-    prm.partials = partials;
-
-    bool stride = false;   // some level uses the stride coupling
-    // deal workgroups to levels in proportion to their draw pairs
     double work[32], total = 0.0;
     for (int i = 0; i < num_levels; ++i) {
         work[i] = ranges[i].count > 0 ? (double)ranges[i].count * (double)((ranges[i].c + 1) / 2) : 0.0;
         total += work[i];
     }
-    if (total <= 0.0) return hipSuccess;
     double target = total / (double)kInnerMinPairsPerBlock;
     if (target > (double)kInnerTargetBlocks) target = (double)kInnerTargetBlocks;
     if (target < 1.0) target = 1.0;
     uint32_t next = 0;
-    InnerFoldParams fold;
     fold.num_levels = num_levels;
     for (int i = 0; i < num_levels; ++i) {
         const LevelRange& lr = ranges[i];
@@ -485,15 +409,14 @@ hipError_t inner_levels_run(const LevelRange* ranges, int num_levels, int64_t n,
         L.k_begin = (uint32_t)lr.k_begin;
         L.count = (uint32_t)(lr.count > 0 ? lr.count : 0);
         L.g_log2 = lanes_log2_for(lr.c);
-        L.sid_index = stream_id(kTagIndex, lr.level_field, keys.problem);
-        L.sid_value = stream_id(kTagValue, lr.level_field, keys.problem);
+        L.sid_index = stream_id(kTagIndex, lr.level_field, problem);
+        L.sid_value = stream_id(kTagValue, lr.level_field, problem);
         L.scale = (double)n / (double)lr.c;
         L.scale_c = lr.c_prev > 0 ? (double)n / (double)lr.c_prev : 0.0;
         L.omega = lr.c_prev > 0 ? 1.0 - (double)lr.c / (double)lr.c_prev : 0.0;
         L.stride = (uint32_t)lr.stride;
-        if (lr.stride != 0) stride = true;
         int64_t blocks = 0;
-        if (L.count > 0) {
+        if (L.count > 0 && total > 0.0) {
             const int64_t groups = (int64_t)1 << (L.g_log2 >= 8 ? 0 : 8 - L.g_log2);
             const int64_t most = ceil_div(L.count, groups);
             blocks = (int64_t)(target * work[i] / total + 0.5);
@@ -523,30 +446,341 @@ hipError_t inner_levels_run(const LevelRange* ranges, int num_levels, int64_t n,
         }
         next = again;
     }
-    if (next == 0) return hipSuccess;
+    prm.total_blocks = next;
+    return next;
+}
+
+// Copies a phase's parameters into their device slot (a kernel, so that the
+// copy is captured like any launch); with `zero`, also clears the first
+// `levels` level states (the start of an estimate).
+__global__ void inner_store_kernel(InnerSlot src, InnerSlot* dst, Moments* zero, int levels)
+{
+    const uint32_t* a = reinterpret_cast<const uint32_t*>(&src);
+    uint32_t* b = reinterpret_cast<uint32_t*>(dst);
+    for (uint32_t i = threadIdx.x; i < sizeof(InnerSlot) / 4; i += blockDim.x) b[i] = a[i];
+    if (zero && (int)threadIdx.x < levels) zero[threadIdx.x] = Moments{0.0, 0.0, 0.0};
+}
+
+// eq. (28) on the device after the pilot: V_l of every level (the telescope's
+// formula), N_l by schedule_counts (the host's arithmetic), and the extension's
+// partition into the parameter slot; counts[l] = the realisations level l has
+// after the extension (the pilot's when the schedule fails, whose code goes to
+// status).  One thread.
+struct InnerScheduleParams {
+    InnerMultiParams base;           // the laws, keys and partials of the launch
+    int32_t num_levels;
+    double eps;
+    int64_t pilot, max_total_draws, n;
+    uint32_t problem;
+    int64_t c[32];
+    uint32_t level_field[32], stride[32];
+    const Moments* level_state;
+    InnerSlot* slot;
+    int64_t* counts;
+    int32_t* status;                 // schedule_counts' code, then its level
+    double* status_value;
+};
+
+// eq. (28) on the device into `out` (the extension's parameters).  One thread.
+__device__ inline void inner_schedule(const InnerScheduleParams& sp, InnerSlot& out)
+{
+    const int L1 = sp.num_levels;
+    double var[32];
+    int64_t N[32];
+    for (int l = 0; l < L1; ++l) {
+        const Moments st = sp.level_state[l];
+        var[l] = st.n > 1.0 ? st.m2 / (st.n - 1.0) : 0.0;
+    }
+    int bad_level = 0;
+    double bad_value = 0.0;
+    const int code = schedule_counts(sp.eps, sp.c, var, L1, sp.pilot, sp.max_total_draws, N, &bad_level, &bad_value);
+    LevelRange ranges[32];
+    for (int l = 0; l < L1; ++l) {
+        LevelRange& r = ranges[l];
+        r.level = l;
+        r.level_field = sp.level_field[l];
+        r.c = sp.c[l];
+        r.c_prev = l > 0 ? sp.c[l - 1] : 0;
+        r.k_begin = sp.pilot;
+        r.count = code == 0 ? N[l] - sp.pilot : 0;
+        r.stride = sp.stride[l];
+        sp.counts[l] = code == 0 ? N[l] : sp.pilot;
+    }
+    out.multi = sp.base;
+    inner_partition(ranges, L1, sp.n, sp.problem, out.multi, out.fold);
+    out.fold.partials = sp.base.partials;
+    out.fold.level_state = const_cast<Moments*>(sp.level_state);
+    sp.status[0] = code;
+    sp.status[1] = bad_level;
+    *sp.status_value = bad_value;
+}
+
+// What the fold kernel does after folding: nothing, eq. (28) for the next
+// phase (its parameters into the slot the fold has read), or the telescoping
+// sum with the level means and variances.
+struct InnerTail {
+    InnerScheduleParams sched;       // TAIL 1
+    double* out;                     // TAIL 2: Y, then level means (nullable) and V_l
+    double* level_means;
+    double* level_var;
+};
+
+// One workgroup per level folds that level's workgroup partials (thread i
+// takes partials i, i + 256, ... in order, then a tree in LDS) and appends the
+// result to the level's running state; the last workgroup to finish (an
+// arrival counter in the slot, released and acquired at agent scope) runs the
+// tail and clears the counter.
+template <int TAIL>
+__global__ __launch_bounds__(kInnerBlock) void inner_fold_kernel(InnerSlot* slot, InnerTail tail)
+{
+    __shared__ Moments slots[kInnerBlock];
+    __shared__ InnerSlot next[1];
+    __shared__ int last;
+    const InnerFoldParams& prm = slot->fold;
+    const int l = blockIdx.x;
+    const int L1 = prm.num_levels;
+    const Moments* part = prm.partials + prm.block_begin[l];
+    const uint32_t blocks = prm.blocks[l];
+    Moments st = {0.0, 0.0, 0.0};
+    for (uint32_t i = threadIdx.x; i < blocks; i += kInnerBlock) st = chan_merge(st, part[i]);
+    slots[threadIdx.x] = st;
+    __syncthreads();
+    for (int half = kInnerBlock >> 1; half > 0; half >>= 1) {
+        if ((int)threadIdx.x < half) slots[threadIdx.x] = chan_merge(slots[threadIdx.x], slots[threadIdx.x + half]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && blocks > 0) prm.level_state[l] = chan_merge(prm.level_state[l], slots[0]);
+    if constexpr (TAIL == 0) return;
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const uint32_t ticket = __hip_atomic_fetch_add(&slot->arrivals, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        last = ticket == (uint32_t)L1 - 1u;
+        if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    if (!last) return;
+    if constexpr (TAIL == 1) {
+        // every other workgroup is done with the slot: thread 0 schedules the
+        // next phase into LDS (its counter cleared), then the workgroup
+        // writes the slot
+        if (threadIdx.x == 0) {
+            inner_schedule(tail.sched, next[0]);
+            next[0].arrivals = 0u;
+        }
+        __syncthreads();
+        const uint32_t* a = reinterpret_cast<const uint32_t*>(&next[0]);
+        uint32_t* b = reinterpret_cast<uint32_t*>(slot);
+        for (uint32_t i = threadIdx.x; i < sizeof(InnerSlot) / 4; i += blockDim.x) b[i] = a[i];
+    }
+    if constexpr (TAIL == 2) {
+        if (threadIdx.x == 0) {
+            double y = 0.0;
+            for (int v = 0; v < L1; ++v) {
+                const Moments sv = prm.level_state[v];
+                y += sv.mean;
+                if (tail.level_means) tail.level_means[v] = sv.mean;
+                tail.level_var[v] = sv.n > 1.0 ? sv.m2 / (sv.n - 1.0) : 0.0;
+            }
+            *tail.out = y;
+            __hip_atomic_store(&slot->arrivals, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+template <typename T, bool FN, bool IW, bool ST>
+static void launch_inner(int laws, dim3 grid, hipStream_t stream, const InnerMultiParams* prm)
+{
+    const dim3 block(kInnerBlock);
+    if (laws == kLawsUniform)
+        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsUniform, FN, IW, ST, false>), grid, block, 0, stream, prm);
+    else if (laws == kLawsNormal)
+        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsNormal, FN, IW, ST, false>), grid, block, 0, stream, prm);
+    else if (laws == kLawsExperiment)
+        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsExperiment, FN, IW, ST, false>), grid, block, 0, stream, prm);
+    else
+        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsAny, FN, IW, ST, false>), grid, block, 0, stream, prm);
+}
+
+// 32-bit index words: uniform draws and the classic laws only (the host checks)
+template <typename T, bool FN, bool ST>
+static void launch_inner_w32(int laws, dim3 grid, hipStream_t stream, const InnerMultiParams* prm)
+{
+    const dim3 block(kInnerBlock);
+    if (laws == kLawsUniform)
+        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsUniform, FN, false, ST, true>), grid, block, 0, stream, prm);
+    else if (laws == kLawsNormal)
+        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsNormal, FN, false, ST, true>), grid, block, 0, stream, prm);
+    else
+        hipLaunchKernelGGL((inner_multi_kernel<T, kLawsAny, FN, false, ST, true>), grid, block, 0, stream, prm);
+}
+
+template <typename T>
+static void launch_inner_forms(int laws, dim3 grid, hipStream_t stream, const InnerMultiParams* prm, bool fn,
+                               bool iw, bool st, bool w32)
+{
+    if (w32) {
+        if (fn && st) launch_inner_w32<T, true, true>(laws, grid, stream, prm);
+        else if (fn) launch_inner_w32<T, true, false>(laws, grid, stream, prm);
+        else if (st) launch_inner_w32<T, false, true>(laws, grid, stream, prm);
+        else launch_inner_w32<T, false, false>(laws, grid, stream, prm);
+        return;
+    }
+    if (st) {
+        // the stride coupling: one instantiation per precision, law pair and form
+        if (fn && iw) launch_inner<T, true, true, true>(laws, grid, stream, prm);
+        else if (fn) launch_inner<T, true, false, true>(laws, grid, stream, prm);
+        else if (iw) launch_inner<T, false, true, true>(laws, grid, stream, prm);
+        else launch_inner<T, false, false, true>(laws, grid, stream, prm);
+        return;
+    }
+    if (fn && iw) launch_inner<T, true, true, false>(laws, grid, stream, prm);
+    else if (fn) launch_inner<T, true, false, false>(laws, grid, stream, prm);
+    else if (iw) launch_inner<T, false, true, false>(laws, grid, stream, prm);
+    else launch_inner<T, false, false, false>(laws, grid, stream, prm);
+}
+
+// The parameters of a launch that do not depend on the levels.
+static InnerMultiParams inner_base(int64_t n, const Law& x, const Law& y, const TargetFunc& f, const IndexWeights& iw,
+                                   const StreamKeys& keys, int num_levels, Moments* partials)
+{
+    InnerMultiParams prm;
+    prm.f = f;
+    prm.iw = iw.w;
+    prm.cum = iw.cum;
+    prm.n = (uint32_t)n;
+    prm.n_shift = 0xFFFFFFFFu;
+    if ((n & (n - 1)) == 0) {
+        uint32_t lg = 0;
+        while ((int64_t(1) << lg) < n) ++lg;
+        prm.n_shift = 32u - lg;     // n = 1 gives a shift of 32: every index is 0
+    }
+    prm.key0 = keys.key0;
+    prm.key1 = keys.key1;
+    prm.num_levels = num_levels;
+    prm.x = x;
+    prm.y = y;
+    prm.partials = partials;
+    prm.total_blocks = 0;
+    return prm;
+}
+
+// The level launch (grid workgroups, parameters in the slot), then the fold
+// with its tail.
+template <int TAIL>
+static hipError_t inner_launch(dim3 grid, int num_levels, const Law& x, const Law& y, const TargetFunc& f,
+                               const IndexWeights& iw, int prec, bool stride, bool index_word32, int64_t n,
+                               InnerSlot* slot, const InnerTail& tail, hipStream_t stream, KernelTimer* timer)
+{
     const int laws = law_pair_kind(x.kind, y.kind);
     // the laws of Sec. 4 pair only with each other
     if (laws != kLawsExperiment && (x.kind >= kLawExperimentFirst || y.kind >= kLawExperimentFirst))
         return hipErrorInvalidValue;
     // 32-bit index words: power-of-two n, uniform draws, classic laws
-    if (index_word32 && (prm.n_shift == 0xFFFFFFFFu || iw.w || laws == kLawsExperiment))
-        return hipErrorInvalidValue;
+    if (index_word32 && ((n & (n - 1)) != 0 || iw.w || laws == kLawsExperiment)) return hipErrorInvalidValue;
     {
         ScopedTiming t(timer, 0);
-        const dim3 grid(next);
-        if (prec == 0) launch_inner_forms<double>(laws, grid, stream, prm, stride, index_word32);
-        else launch_inner_forms<float>(laws, grid, stream, prm, stride, index_word32);
+        const InnerMultiParams* pp = &slot->multi;
+        if (prec == 0) launch_inner_forms<double>(laws, grid, stream, pp, f.kind != 0, iw.w != nullptr, stride,
+                                                  index_word32);
+        else launch_inner_forms<float>(laws, grid, stream, pp, f.kind != 0, iw.w != nullptr, stride, index_word32);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    fold.partials = partials;
-    fold.level_state = level_state;
     {
-        ScopedTiming t(timer, 2);
-        hipLaunchKernelGGL(inner_fold_kernel, dim3((unsigned)num_levels), dim3(kInnerBlock), 0, stream, fold);
+        ScopedTiming t(timer, TAIL == 0 ? 2 : 3);
+        hipLaunchKernelGGL((inner_fold_kernel<TAIL>), dim3((unsigned)num_levels), dim3(kInnerBlock), 0, stream, slot,
+                           tail);
     }
     return hipGetLastError();
 }
+
+// The slot of a host-partitioned phase, stored by a kernel (which also clears
+// the level states at the start of an estimate).
+static hipError_t inner_store(const LevelRange* ranges, int num_levels, int64_t n, const Law& x, const Law& y,
+                              const TargetFunc& f, const IndexWeights& iw, const StreamKeys& keys, Moments* partials,
+                              Moments* level_state, InnerSlot* slot, bool zero_state, uint32_t* next, bool* stride,
+                              hipStream_t stream, KernelTimer* timer)
+{
+    InnerSlot host;
+    host.multi = inner_base(n, x, y, f, iw, keys, num_levels, partials);
+    *next = inner_partition(ranges, num_levels, n, keys.problem, host.multi, host.fold);
+    host.fold.partials = partials;
+    host.fold.level_state = level_state;
+    host.arrivals = 0u;
+    *stride = false;   // some level uses the stride coupling
+    for (int i = 0; i < num_levels; ++i) *stride = *stride || ranges[i].stride != 0;
+    ScopedTiming t(timer, 3);
+    hipLaunchKernelGGL(inner_store_kernel, dim3(1), dim3(256), 0, stream, host, slot, zero_state ? level_state : nullptr,
+                       num_levels);
+    return hipGetLastError();
+}
+
+hipError_t inner_levels_run(const LevelRange* ranges, int num_levels, int64_t n, const Law& x, const Law& y,
+                            const TargetFunc& f, const IndexWeights& iw, int prec, bool index_word32,
+                            const StreamKeys& keys, Moments* partials, Moments* level_state, InnerSlot* slot,
+                            bool zero_state, const InnerTelescope* tele, hipStream_t stream, KernelTimer* timer)
+{
+    uint32_t next = 0;
+    bool stride = false;
+    hipError_t e = inner_store(ranges, num_levels, n, x, y, f, iw, keys, partials, level_state, slot, zero_state, &next,
+                               &stride, stream, timer);
+    if (e != hipSuccess) return e;
+    InnerTail tail = {};
+    if (!tele)
+        return inner_launch<0>(dim3(next > 0 ? next : 1), num_levels, x, y, f, iw, prec, stride, index_word32, n,
+                               slot, tail, stream, timer);
+    tail.out = tele->out;
+    tail.level_means = tele->level_means;
+    tail.level_var = tele->level_var;
+    return inner_launch<2>(dim3(next > 0 ? next : 1), num_levels, x, y, f, iw, prec, stride, index_word32, n, slot,
+                           tail, stream, timer);
+}
+
+hipError_t inner_target_run(const InnerScheduleInputs& s, const LevelRange* pilot, int num_levels, int64_t n,
+                            const Law& x, const Law& y, const TargetFunc& f, const IndexWeights& iw, int prec,
+                            bool index_word32, const StreamKeys& keys, Moments* partials, Moments* level_state,
+                            InnerSlot* slot, const InnerTelescope& tele, hipStream_t stream, KernelTimer* timer)
+{
+    uint32_t next = 0;
+    bool stride = false;
+    hipError_t e = inner_store(pilot, num_levels, n, x, y, f, iw, keys, partials, level_state, slot, true, &next,
+                               &stride, stream, timer);
+    if (e != hipSuccess) return e;
+    InnerTail tail = {};
+    InnerScheduleParams& sp = tail.sched;
+    sp.base = inner_base(n, x, y, f, iw, keys, num_levels, partials);
+    sp.num_levels = num_levels;
+    sp.eps = s.eps;
+    sp.pilot = s.pilot;
+    sp.max_total_draws = s.max_total_draws;
+    sp.n = n;
+    sp.problem = keys.problem;
+    for (int l = 0; l < num_levels; ++l) {
+        sp.c[l] = s.c[l];
+        sp.level_field[l] = s.level_field[l];
+        sp.stride[l] = s.stride[l];
+    }
+    sp.level_state = level_state;
+    sp.slot = slot;
+    sp.counts = s.counts;
+    sp.status = s.status;
+    sp.status_value = s.status_value;
+    // the pilot, then its fold, which runs eq. (28) and writes the extension's slot
+    e = inner_launch<1>(dim3(next > 0 ? next : 1), num_levels, x, y, f, iw, prec, stride, index_word32, n, slot,
+                        tail, stream, timer);
+    if (e != hipSuccess) return e;
+    // the extension's partition is known on the device only: the largest
+    // grid, whose workgroups past it leave at once; then the fold with the
+    // telescoping sum
+    InnerTail last = {};
+    last.out = tele.out;
+    last.level_means = tele.level_means;
+    last.level_var = tele.level_var;
+    return inner_launch<2>(dim3(kInnerMaxBlocks), num_levels, x, y, f, iw, prec, stride, index_word32, n, slot, last,
+                           stream, timer);
+}
+
+size_t inner_slot_bytes() { return sizeof(InnerSlot); }
 
 hipError_t inner_telescope(const Moments* level_state, int num_levels, double* out, double* level_means,
                            double* level_var, hipStream_t stream)

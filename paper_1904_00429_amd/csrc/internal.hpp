@@ -63,14 +63,49 @@ struct StreamKeys {
 // ---- inner product (m = p = 1) -------------------------------------------
 // Device state per level: one Moments (count, mean, M2) of the level samples.
 size_t inner_partials_capacity();  // Moments slots needed in workspace
+struct InnerSlot;                   // a launch's parameters in device memory
+size_t inner_slot_bytes();
 // One launch over every level's range (pilot, extension or fixed mode), then a
 // fold of the workgroup partials into the running level states.
 // index_word32: four index draws per Philox call from 32-bit words (n a power
 // of two, uniform draws, no experiment laws: checked by the caller).
+// Where a phase's fold writes the estimate (the last phase of a fixed or
+// target-mode estimate): Y, the level means (nullable) and V_l.
+struct InnerTelescope {
+    double* out;
+    double* level_means;
+    double* level_var;
+};
+// One phase over every level's range: its parameters stored into the slot by
+// a kernel (zero_state: the level states cleared first), the level launch, and
+// a one-workgroup fold of the partials into the level states (with tele, then
+// the telescoping sum).
 hipError_t inner_levels_run(const LevelRange* ranges, int num_levels, int64_t n, const Law& x,
                             const Law& y, const TargetFunc& f, const IndexWeights& iw, int prec,
                             bool index_word32, const StreamKeys& keys, Moments* partials, Moments* level_state,
-                            hipStream_t stream, KernelTimer* timer);
+                            InnerSlot* slot, bool zero_state, const InnerTelescope* tele, hipStream_t stream,
+                            KernelTimer* timer);
+// Target mode with no host synchronisation: the pilot (pilot ranges, level
+// states cleared), its fold, which evaluates eq. (28) on the device from the
+// level states (schedule_counts, the host's arithmetic) and writes the
+// extension's partition into the slot, the extension of every level to
+// max(N_l, pilot) realisations, and the last fold with the telescoping sum.
+// counts (device, num_levels) receives the realisations of every level
+// after it, status (device) the schedule's code and failing level (the
+// extension is empty when it is not 0), status_value the offending number.
+struct InnerScheduleInputs {
+    double eps;
+    int64_t pilot, max_total_draws;
+    const int64_t* c;                    // host, num_levels
+    uint32_t level_field[32], stride[32];
+    int64_t* counts;
+    int32_t* status;
+    double* status_value;
+};
+hipError_t inner_target_run(const InnerScheduleInputs& s, const LevelRange* pilot, int num_levels, int64_t n,
+                            const Law& x, const Law& y, const TargetFunc& f, const IndexWeights& iw, int prec,
+                            bool index_word32, const StreamKeys& keys, Moments* partials, Moments* level_state,
+                            InnerSlot* slot, const InnerTelescope& tele, hipStream_t stream, KernelTimer* timer);
 hipError_t inner_telescope(const Moments* level_state, int num_levels, double* out,
                            double* level_means, double* level_var, hipStream_t stream);
 
@@ -88,6 +123,7 @@ struct MatmulTuning {
     int tile;                  // workgroup output tile edge (0: default)
     int64_t target_blocks;     // sketch work items per pass (0: default)
     int64_t gather_budget;     // bytes of gathered operands per pass (0: default)
+    int single_launch;         // 1: the persistent single-launch form where it is built
 };
 
 // Device-side description of one product of the table.
@@ -106,6 +142,22 @@ struct ProblemDesc {
     double mean0;              // E[Z_0] entry for i.i.d. laws: n E[a] E[b]
     double* out;
     double* level_means;
+};
+
+// One pass of the single-launch (persistent) form of a fixed-N_l estimate: a
+// batch of realisations of one level, gathered in one phase of the launch and
+// sketched in the next.
+struct PassDesc {
+    int32_t level;
+    int32_t stats;             // the sketch's statistics form: 2 shifted sums, 3 two accumulators
+    uint32_t c, c_prev, stride, level_field;
+    uint32_t k_first;          // realisation of the batch's first slot
+    int32_t octets;            // gather position groups per unit
+    int64_t kc, kpad, batch;
+    int64_t gx;                // gather units along the positions
+    int64_t units;             // gx * batch * nprob
+    double done_before;        // realisations of the level merged by earlier passes
+    double omega;              // 1 - c_l / c_{l-1}: the coarse draws' weight (1 at level 0)
 };
 
 struct MatmulPlan {
@@ -136,6 +188,17 @@ struct MatmulPlan {
     std::vector<int8_t> exp_host;
     bool fp8_reparam = false;
     size_t off_exp = 0, off_bound = 0;
+    // the single-launch form (matmul_plan_persistent): its passes, their
+    // table and phase counters in workspace, and the second gather buffer
+    bool persistent = false;
+    std::vector<PassDesc> passes;
+    size_t off_passes = 0, off_sync = 0, off_gather2 = 0;
+    int64_t sync_words = 0;
+    // the set form of a realisation (matmul_plan_set_form): per-realisation
+    // hash tables and position weights in workspace
+    bool set_form = false;
+    size_t off_set = 0;
+    int64_t set_bytes = 0;
 };
 
 // index_weights: NULL, or (one product) the device weights whose cumulative
@@ -150,6 +213,28 @@ hipError_t matmul_upload(const MatmulPlan& plan, char* ws, hipStream_t stream);
 hipError_t matmul_reset(const MatmulPlan& plan, char* ws, hipStream_t stream);
 hipError_t matmul_level_run(const MatmulPlan& plan, const LevelRange& lr, int64_t done_before,
                             const StreamKeys& keys, char* ws, hipStream_t stream, KernelTimer* timer);
+// The single-launch form of a fixed-N_l estimate (ranges: each level's
+// realisations): every level's passes run in one persistent kernel whose
+// phase p gathers pass p while it sketches pass p - 1.  Sets plan.persistent
+// when the plan's form has such a kernel (FP32, BF16 or FP8 operands, i.i.d.
+// normal or uniform laws, f = identity, uniform draws, products in whole
+// tiles at tile 64 or of any shape at tile 128) and then lays out its
+// workspace after plan.total (the pass table is copied by matmul_upload).
+void matmul_plan_persistent(MatmulPlan& plan, const LevelRange* ranges, int num_levels);
+// The set form of every realisation (the note after Alg. 1 in Sec. 3.1): the
+// index tuple is mapped to its distinct indices with their multiplicities
+// before the gather, each distinct column is generated once, at the first
+// position that drew it, weighted by the sum of the weights of the draws that
+// took it, and the other positions are left zero.  f = identity, uniform
+// draws, FP64 / FP32 operands (checked by the caller).  Lays out the tables
+// after plan.total; the passes then also bound their batch by that region.
+void matmul_plan_set_form(MatmulPlan& plan);
+// Runs the planned passes: one fill of the phase counters and one launch.
+hipError_t matmul_persistent_run(const MatmulPlan& plan, const StreamKeys& keys, char* ws, hipStream_t stream,
+                                 KernelTimer* timer);
+// Non-zero when a launch of the single-launch form gave up on a phase barrier
+// (its workgroups were not all resident); reads the flag (synchronises).
+hipError_t matmul_persistent_status(const MatmulPlan& plan, char* ws, hipStream_t stream, bool* failed);
 // V_l of every product (levels x nprob at matmul_level_var_ptr); with
 // write_outputs, also the telescoping sums and level means
 hipError_t matmul_finalize(const MatmulPlan& plan, const int64_t* counts, char* ws, bool write_outputs,

@@ -20,6 +20,7 @@ FLAG_SHARED_SAMPLES = 1
 FLAG_STRIDE_COUPLING = 8
 FLAG_INDEX_WORD32 = 16
 FLAG_VALUE16 = 32
+FLAG_SET_FORM = 64
 COUPLINGS = ("prefix", "stride")   # coarse draws: the first c_{l-1}, or every M-th (Sec. 3.1)
 FLAG_ADAPTIVE_LEVELS = 4
 SHARED_LEVEL_FIELD = 0xFF
@@ -134,7 +135,7 @@ class _LevelsHolder:
     def __init__(self, c, n_samples, rmse_target, pilot, seed, prec, shared, problem, max_total_draws,
                  func: Optional[Func] = None, adaptive: bool = False,
                  index_weights: Optional[torch.Tensor] = None, coupling: str = "prefix",
-                 index_word32: bool = False, value16: bool = False):
+                 index_word32: bool = False, value16: bool = False, set_form: bool = False):
         if prec not in PREC:
             raise ValueError(f"prec must be one of {sorted(PREC)}")
         if coupling not in COUPLINGS:
@@ -153,7 +154,7 @@ class _LevelsHolder:
         lv.flags = ((FLAG_SHARED_SAMPLES if shared else 0) | (FLAG_ADAPTIVE_LEVELS if adaptive else 0)
                     | (FLAG_STRIDE_COUPLING if coupling == "stride" else 0)
                     | (FLAG_INDEX_WORD32 if index_word32 else 0)
-                    | (FLAG_VALUE16 if value16 else 0))
+                    | (FLAG_VALUE16 if value16 else 0) | (FLAG_SET_FORM if set_form else 0))
         lv.problem = int(problem)
         f = func or Func()
         lv.func = int(f.kind)
@@ -190,16 +191,17 @@ def matmul_estimate(m: int, n: int, p: int, A: Law, B: Law, c: Sequence[int],
                     report: bool = True, device=None, workspace: Optional[torch.Tensor] = None,
                     out: Optional[torch.Tensor] = None, func: Optional[Func] = None,
                     adaptive: bool = False, index_weights: Optional[torch.Tensor] = None,
-                    coupling: str = "prefix", value16: bool = False) -> Result:
+                    coupling: str = "prefix", value16: bool = False, set_form: bool = False) -> Result:
     """MLMC estimate of E[f(AB)] on the GPU (mlmc_matmul_estimate; f = identity
     unless func is given; adaptive: number of levels chosen by the bias test,
     c being the longest ladder allowed; index_weights: int32 device tensor of n
     positive weights, xi_j = w_j / sum w, e.g. optimal_index_weights;
     coupling: "prefix" or "stride", the coarse draws of each level sample;
-    value16: values from 16-bit uniforms, eight per Philox call)."""
+    value16: values from 16-bit uniforms, eight per Philox call; set_form:
+    each realisation's index tuple as a set with multiplicities)."""
     device = torch.device(device or "cuda")
     h = _LevelsHolder(c, n_samples, rmse_target, pilot, seed, prec, shared, problem, max_total_draws, func,
-                      adaptive, index_weights, coupling, value16=value16)
+                      adaptive, index_weights, coupling, value16=value16, set_form=set_form)
     ws_bytes = int(lib().mlmc_matmul_workspace_size(int(m), int(n), int(p), ctypes.byref(h.lv)))
     if ws_bytes == 0:
         raise MLMCError(1, "invalid problem: no workspace size")
@@ -381,11 +383,12 @@ class BatchedEstimate:
 
     def __init__(self, problems: Sequence[BatchProblem], c: Sequence[int], n_samples: Sequence[int],
                  seed: int = 0, prec: str = "fp32", tuning: Optional[dict] = None, device=None,
-                 func: Optional[Func] = None, coupling: str = "prefix", value16: bool = False):
+                 func: Optional[Func] = None, coupling: str = "prefix", value16: bool = False,
+                 set_form: bool = False):
         self.device = torch.device(device or "cuda")
         self.problems = list(problems)
         self.h = _LevelsHolder(c, n_samples, 0.0, 0, seed, prec, False, 0, 0, func, coupling=coupling,
-                               value16=value16)
+                               value16=value16, set_form=set_form)
         self.Y = [torch.empty((pr.m, pr.p), dtype=torch.float64, device=self.device) for pr in self.problems]
         arr = (Problem * len(self.problems))()
         for i, pr in enumerate(self.problems):
@@ -400,6 +403,7 @@ class BatchedEstimate:
         self.tuning.tile = int(t.get("tile", 0))
         self.tuning.target_blocks = int(t.get("target_blocks", 0))
         self.tuning.gather_budget = int(t.get("gather_budget", 0))
+        self.tuning.single_launch = int(t.get("single_launch", 0))
         self.ws_bytes = int(lib().mlmc_matmul_batched_workspace_size(len(arr), arr, ctypes.byref(self.h.lv),
                                                                      ctypes.byref(self.tuning)))
         if self.ws_bytes == 0:

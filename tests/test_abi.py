@@ -302,3 +302,56 @@ def test_noalloc_limit_checked_before_the_device(L):
     st = L.mlmc_inner_product_estimate_noalloc(16, ctypes.byref(A), ctypes.byref(B), ctypes.byref(bad), 8, None,
                                                None, None)
     assert st == 1
+
+
+@pytest.mark.parametrize("prec, func, weights, inner, what", [
+    (2, 0, False, False, b"FP64 or FP32"), (3, 0, False, False, b"FP64 or FP32"),
+    (0, 1, False, False, b"f = identity"), (1, 0, True, False, b"uniform index draws"),
+    (0, 0, False, True, b"matrix products"),
+])
+def test_set_form_validated(L, prec, func, weights, inner, what):
+    lv, keep = _levels([2, 4], [4, 4], prec=prec)
+    lv.flags = 64
+    lv.func = func
+    lv.func_param[0] = 2.0
+    if weights:
+        lv.index_weights = 8   # never dereferenced: the flag check comes first
+    A = _dist(0, 0.5, 1.0)
+    if inner:
+        st = L.mlmc_inner_product_estimate(1024, ctypes.byref(A), ctypes.byref(A), ctypes.byref(lv), 8, None,
+                                           16, 1 << 40, None, None)
+    else:
+        st = L.mlmc_matmul_estimate(4, 16, 3, ctypes.byref(A), ctypes.byref(A), ctypes.byref(lv), 8, None,
+                                    16, 1 << 40, None, None)
+    assert st == 1 and what in L.mlmc_last_error()
+
+
+def test_set_form_and_single_launch_workspace(L):
+    """The set form adds its tables to the workspace; single_launch = 1 adds a
+    second gather buffer where the single-launch kernel is built (FP32, i.i.d.
+    normal laws, whole tiles) and nothing elsewhere (FP64); an out-of-range
+    single_launch is rejected."""
+    from paper_1904_00429_amd._lib import Problem, Tuning
+    lv, keep = _levels([2, 4], [4, 4], prec=1)
+    base = L.mlmc_matmul_workspace_size(64, 1000, 64, ctypes.byref(lv))
+    lv.flags = 64
+    assert L.mlmc_matmul_workspace_size(64, 1000, 64, ctypes.byref(lv)) > base
+    lv.flags = 0
+    arr = (Problem * 2)()
+    for i in range(2):
+        arr[i].m, arr[i].n, arr[i].p = 64, 1000 + i, 128
+        arr[i].A, arr[i].B = _dist(0, 0.5, 1.0), _dist(0, 0.5, 1.0)
+        arr[i].problem = i
+        arr[i].out = 8
+    t = Tuning()
+    t.tile = 64
+    plain = L.mlmc_matmul_batched_workspace_size(2, arr, ctypes.byref(lv), ctypes.byref(t))
+    t.single_launch = 1
+    assert L.mlmc_matmul_batched_workspace_size(2, arr, ctypes.byref(lv), ctypes.byref(t)) > plain
+    lv.prec = 0
+    t.single_launch = 0
+    plain64 = L.mlmc_matmul_batched_workspace_size(2, arr, ctypes.byref(lv), ctypes.byref(t))
+    t.single_launch = 1
+    assert L.mlmc_matmul_batched_workspace_size(2, arr, ctypes.byref(lv), ctypes.byref(t)) == plain64
+    t.single_launch = 2
+    assert L.mlmc_matmul_batched_workspace_size(2, arr, ctypes.byref(lv), ctypes.byref(t)) == 0
