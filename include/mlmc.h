@@ -346,12 +346,20 @@ mlmc_status mlmc_graph_destroy(mlmc_graph graph);
  *   grad_out: device FP64, m x p row-major, dL/dY.
  *   dMA, dSA: device FP32 in the layout of A's mean/stdev (column-major m x n,
  *             ld = A->ld); dMB, dSB: layout of B's (row-major n x p, ld = B->ld).
- *             Gradients are ADDED (FP32 atomics, so the last bits depend on
- *             the order in which workgroups finish); zero them first.
+ *             Gradients are ADDED; zero them first.  No atomics: the draws
+ *             of each batch of realisations are sorted by column (a stable
+ *             radix sort) and each column's terms are summed in draw order
+ *             by one owner, so a call gives the same bits on every run.
+ *             Calls that overlap on the same gradient arrays race.
  * Arithmetic (levels->prec): MLMC_PREC_FP32 — FP32 values, FP32 MFMA
  * contraction and accumulation; MLMC_PREC_BF16 — the regenerated values and
  * G rounded to BF16 (nearest even), BF16 MFMA, FP32 accumulation and FP32
  * gradients.  Other precisions: MLMC_EINVAL.
+ * Workspace (mlmc_matmul_adjoint_workspace_size, with the same levels,
+ * n_samples included): G in the contraction's layouts plus the buffers of
+ * one pass of draws (the draws of all levels are taken in passes of as many
+ * as fit): room for every draw of the call, capped at 4 GiB (about 0.5 M
+ * draws of a 512 x 512 problem).
  * Errors: EINVAL (laws not reparameterised, target mode, f other than the
  * identity, precision other than FP32/BF16, null pointers, and the
  * conditions of mlmc_matmul_estimate), EWORKSPACE, EDEVICE. */

@@ -13,479 +13,886 @@
 // realisation are regenerated from the counter-based stream, exactly as the
 // forward drew them, and the sampled columns are regenerated from M and S.
 //
-// Per pass over a batch of realisations of one level:
-//   adjoint_gather:  per realisation, A_S^T (m x K, [i][t]), B_S^T (p x K,
-//                    [q][t]) for the MFMA operands, Z_S (K x m, [t][i]) and
-//                    W_S (K x p, [t][q]) for the epilogue, and the indices;
-//   adjoint_mfma:    U^T = B_S G^T (K x m) and V = A_S^T G (K x p) with
-//                    v_mfma_f32_32x32x2_f32 on LDS-staged operand chunks;
-//                    each output row t is scaled by
-//                    kappa_t and added (FP32 atomics, a contiguous row of the
-//                    gradient per draw) into row r_t of dM/dS.
+// Every draw adds into the gradient column of its index, and many draws hit
+// the same column (a few per column and level at the differentiation
+// workload's sizes, thousands with a skewed index law).  The draws of a pass
+// (a batch of realisations of one level) are therefore put in column order
+// first, and each column's sum is formed in that order by one owner; nothing
+// is added atomically, so the gradients are the same bits on every run.
+//
+// Per pass (E = S c_l draws, flat draw number e = s c_l + t):
+//   adj_keys:     the column r of every draw, drawn as the forward drew it;
+//   adj_radix_*:  a stable LSD radix sort of the draw numbers by column
+//                 (8-bit digits: histogram, scan, scatter), so the draws of
+//                 one column are adjacent and in draw order;
+//   adj_gather:   in sorted order, each draw's regenerated a_t and b_t
+//                 (position-major rows, FP32 or BF16), its normals and kappa_t;
+//   adj_tile:     U^T = B_S G^T (E x m) and V = A_S^T G (E x p) on MFMA, one
+//                 workgroup per 64 sorted draws x 128 gradient columns; the
+//                 rows scaled by kappa_t (dM), and also by the normal (dS), are
+//                 summed down each column segment in LDS; a segment inside the
+//                 tile is added to its gradient row by a plain read-modify-
+//                 write, a segment that crosses the tile's edge leaves its
+//                 partial sum in a carry slot;
+//   adj_fixup:    each crossing segment's partials, summed in tile order and
+//                 added once.
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace mlmc {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
-
-constexpr int kAdjGatherThreads = 64;
-constexpr int kAdjPositions = 8;
-constexpr int kAdjThreads = 256;
-constexpr int kAdjKStep = 2;
-constexpr int64_t kAdjBudget = 192ll << 20;
-
-struct AdjGatherParams {
-    int64_t m, p;
-    uint32_t n, c, c_prev;
-    int64_t kpad;                 // draws per realisation rounded up to kAdjPositions
-    uint32_t key0, key1, sid_index, sid_value;
-    uint32_t k_first;
-    Law A, B;
-    float* AT;                    // batch x m x kpad
-    float* BT;                    // batch x p x kpad
-    float* ZS;                    // batch x kpad x m
-    float* WS;                    // batch x kpad x p
-    int32_t* R;                   // batch x kpad (-1 for padding)
-    // BF16 form: the values position-major instead of AT/BT, element (t, i)
-    // at t mk + i (mk, pk: m and p rounded up to 8)
-    __bf16* ASb;                  // batch x kpad x mk
-    __bf16* BSb;                  // batch x kpad x pk
-    int64_t mk, pk;
-    const uint64_t* cum;          // cumulative index weights (NULL: uniform draws)
-    bool value16;                 // the forward's values came from 16-bit uniforms
-};
-
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-template <bool BF16>
-__global__ __launch_bounds__(kAdjGatherThreads) void adjoint_gather_kernel(AdjGatherParams prm)
-{
-    __shared__ uint32_t cols[kAdjPositions];
-    __shared__ int valid[kAdjPositions];
-    const int64_t pos0 = (int64_t)blockIdx.x * kAdjPositions;
-    const int64_t slot = blockIdx.y;
-    const uint32_t k = prm.k_first + (uint32_t)slot;
-    if (threadIdx.x < kAdjPositions) {
-        const int64_t t = pos0 + threadIdx.x;
-        const bool ok = t < (int64_t)prm.c;
-        valid[threadIdx.x] = ok;
-        uint32_t j = 0u;
-        if (ok)
-            j = prm.cum ? draw_index_weighted((uint32_t)t, k, prm.sid_index, prm.key0, prm.key1, prm.cum, prm.n,
-                                              prm.cum[prm.n - 1])
-                        : draw_index((uint32_t)t, k, prm.sid_index, prm.key0, prm.key1, prm.n);
-        cols[threadIdx.x] = j;
-        prm.R[slot * prm.kpad + t] = ok ? (int32_t)j : -1;
-    }
-    __syncthreads();
-    const int64_t rows = prm.m + prm.p;
-    const int64_t quads = ceil_div(rows, 4);
-    float* AT = prm.AT + slot * prm.m * prm.kpad;
-    float* BT = prm.BT + slot * prm.p * prm.kpad;
-    float* ZS = prm.ZS + slot * prm.kpad * prm.m;
-    float* WS = prm.WS + slot * prm.kpad * prm.p;
-    for (int64_t q = threadIdx.x; q < quads; q += kAdjGatherThreads) {
-        float val[kAdjPositions][4], nrm[kAdjPositions][4];
-        for (int ip = 0; ip < kAdjPositions; ++ip) {
-            if (!valid[ip]) {
-                for (int r = 0; r < 4; ++r) { val[ip][r] = 0.0f; nrm[ip][r] = 0.0f; }
-                continue;
-            }
-            const uint32_t j = cols[ip];
-            float u[4], z[4];
-            if (prm.value16) {
-                // rows 4q .. 4q+3 are halves of words 2 (q & 1) and 2 (q & 1) + 1
-                // of the call for rows 8 (q / 2) .. 8 (q / 2) + 7
-                const Words4 w = philox4x32_10((uint32_t)(q >> 1), k, j, prm.sid_value, prm.key0, prm.key1);
-                const uint32_t a = (q & 1) ? w.w2 : w.w0, b = (q & 1) ? w.w3 : w.w1;
-                u[0] = unit16<float>(a & 0xFFFFu);
-                u[1] = unit16<float>(a >> 16);
-                u[2] = unit16<float>(b & 0xFFFFu);
-                u[3] = unit16<float>(b >> 16);
-                box_muller(u[0], u[1], z[0], z[1]);
-                box_muller(u[2], u[3], z[2], z[3]);
-            } else {
-                const Words4 w = philox4x32_10((uint32_t)q, k, j, prm.sid_value, prm.key0, prm.key1);
-                quad_values<float>(w, true, u[0], u[1], u[2], u[3], z[0], z[1], z[2], z[3]);
-            }
-            for (int r = 0; r < 4; ++r) {
-                const int64_t e = 4 * q + r;
-                float v = 0.0f;
-                if (e < prm.m) v = law_value<float>(prm.A, z[r], u[r], (int64_t)j * prm.A.ld + e);
-                else if (e < rows) v = law_value<float>(prm.B, z[r], u[r], (int64_t)j * prm.B.ld + (e - prm.m));
-                val[ip][r] = v;
-                nrm[ip][r] = z[r];
-            }
-        }
-        const int64_t e0 = 4 * q;
-        if constexpr (BF16) {
-            // position-major BF16 values (round to nearest even): the quad's
-            // four rows are adjacent, one 8-byte store per position when they
-            // lie in A, or in B at a row that is a multiple of 4
-            __bf16* AS = prm.ASb + slot * prm.kpad * prm.mk;
-            __bf16* BS = prm.BSb + slot * prm.kpad * prm.pk;
-            const bool qa = e0 + 3 < prm.m;
-            const bool qb = e0 >= prm.m && e0 + 3 < rows && ((e0 - prm.m) & 3) == 0;
-            if (qa || qb) {
-                __bf16* V = qa ? AS : BS;
-                const int64_t st = qa ? prm.mk : prm.pk;
-                const int64_t row = qa ? e0 : e0 - prm.m;
-                for (int ip = 0; ip < kAdjPositions; ++ip) {
-                    bf16x4 v;
-                    for (int r = 0; r < 4; ++r) v[r] = (__bf16)val[ip][r];
-                    *reinterpret_cast<bf16x4*>(V + (pos0 + ip) * st + row) = v;
-                }
-            } else {
-                for (int r = 0; r < 4; ++r) {
-                    const int64_t e = e0 + r;
-                    if (e >= rows) break;
-                    const bool in_a = e < prm.m;
-                    __bf16* V = in_a ? AS : BS;
-                    const int64_t st = in_a ? prm.mk : prm.pk;
-                    const int64_t row = in_a ? e : e - prm.m;
-                    for (int ip = 0; ip < kAdjPositions; ++ip) V[(pos0 + ip) * st + row] = (__bf16)val[ip][r];
-                }
-            }
-        } else {
-            // K-major values: a row's eight positions are adjacent (two 16-byte
-            // stores; kpad and pos0 are multiples of 8)
-            for (int r = 0; r < 4; ++r) {
-                const int64_t e = e0 + r;
-                if (e >= rows) break;
-                const bool in_a = e < prm.m;
-                const int64_t row = in_a ? e : e - prm.m;
-                float4* T = reinterpret_cast<float4*>((in_a ? AT + row * prm.kpad : BT + row * prm.kpad) + pos0);
-                T[0] = make_float4(val[0][r], val[1][r], val[2][r], val[3][r]);
-                T[1] = make_float4(val[4][r], val[5][r], val[6][r], val[7][r]);
-            }
-        }
-        // position-major normals: the quad's four rows are adjacent (one
-        // 16-byte store per position when the row count keeps them aligned)
-        const bool quad_a = e0 + 3 < prm.m && (prm.m & 3) == 0;
-        const bool quad_b = e0 >= prm.m && e0 + 3 < rows && (prm.m & 3) == 0 && (prm.p & 3) == 0;
-        if (quad_a || quad_b) {
-            float* N = quad_a ? ZS : WS;
-            const int64_t R = quad_a ? prm.m : prm.p;
-            const int64_t row = quad_a ? e0 : e0 - prm.m;
-            for (int ip = 0; ip < kAdjPositions; ++ip)
-                *reinterpret_cast<float4*>(N + (pos0 + ip) * R + row) =
-                    make_float4(nrm[ip][0], nrm[ip][1], nrm[ip][2], nrm[ip][3]);
-        } else {
-            for (int r = 0; r < 4; ++r) {
-                const int64_t e = e0 + r;
-                if (e >= rows) break;
-                const bool in_a = e < prm.m;
-                float* N = in_a ? ZS : WS;
-                const int64_t R = in_a ? prm.m : prm.p;
-                const int64_t row = in_a ? e : e - prm.m;
-                for (int ip = 0; ip < kAdjPositions; ++ip) N[(pos0 + ip) * R + row] = nrm[ip][r];
-            }
-        }
-    }
-}
+constexpr int kAdjThreads = 256;
+constexpr int kAdjRows = 64;              // sorted draws per tile
+constexpr int kAdjCols = 128;             // gradient columns per tile
+constexpr int64_t kAdjBudget = 4ll << 30;    // pass buffers at most
+constexpr uint32_t kNoKey = 0xFFFFFFFFu;  // past the ends of the sorted list (n < 2^32)
 
-// Draw t is one of the coarse draws of its level sample.
-__device__ __forceinline__ bool coarse_draw(int t, uint32_t c_prev, uint32_t stride)
-{
-    return stride ? ((uint32_t)t + 1u) % stride == 0u : t < (int)c_prev;
-}
-
-struct AdjMfmaParams {
-    int64_t m, p, kpad;
-    uint32_t c_prev;
-    uint32_t stride;                  // stride coupling M (0: prefix)
-    float kappa_coarse, kappa_fine;   // (n / c_l) w_t / N_l for the two segments
-    const float* GT;                  // p x m: G^T
-    const float* G;                   // m x p
-    const float* AT;                  // batch x m x kpad
-    const float* BT;                  // batch x p x kpad
-    const float* ZS;                  // batch x kpad x m
-    const float* WS;                  // batch x kpad x p
-    const int32_t* R;                 // batch x kpad
-    int64_t tiles_t, tiles_u_cols, tiles_v_cols;
-    float* dMA; float* dSA;           // n x m
-    float* dMB; float* dSB;           // n x p
-    const uint32_t* iw;               // index weights (NULL: uniform): factor 1 / (n xi_j) per draw
-    const uint64_t* cum;
-    uint32_t n;
-};
-
-// One 64 x 128 tile of U^T (rows t, columns i; K = p) or of V (rows t,
-// columns q; K = m) for one realisation, then the scaled scatter-add.  Both
-// operands are K-major ([k][t] and [k][x]); chunks of kAdjChunk k-values are
-// staged in LDS with 16-byte loads, double-buffered so the next chunk's
-// global loads are in flight during the MFMAs.  2 x 2 waves, each 32 x 64
-// (two 32x32x2 f32 blocks sharing the t fragment).
-constexpr int kAdjChunk = 32;
-constexpr int kAdjTileT = 64, kAdjTileX = 128;
-
-__global__ __launch_bounds__(kAdjThreads) void adjoint_mfma_kernel(AdjMfmaParams prm)
-{
-    constexpr int VA = kAdjChunk * kAdjTileT / 4 / kAdjThreads;   // uint4 per thread, t operand
-    constexpr int VB = kAdjChunk * kAdjTileX / 4 / kAdjThreads;   // uint4 per thread, x operand
-    __shared__ __align__(16) float lds_a[2][kAdjChunk * kAdjTileT];
-    __shared__ __align__(16) float lds_b[2][kAdjChunk * kAdjTileX];
-    const int lane = threadIdx.x % kWave;
-    const int wave = threadIdx.x / kWave;
-    const int64_t s = blockIdx.y;
-    int64_t tile = blockIdx.x;
-    const int64_t u_tiles = prm.tiles_t * prm.tiles_u_cols;
-    const bool is_u = tile < u_tiles;
-    if (!is_u) tile -= u_tiles;
-    const int64_t cols_tiles = is_u ? prm.tiles_u_cols : prm.tiles_v_cols;
-    const int tb = (int)(tile / cols_tiles) * kAdjTileT;     // first t of the tile
-    const int xb = (int)(tile % cols_tiles) * kAdjTileX;     // first x of the tile
-    const int wt = (wave / 2) * 32, wx = (wave % 2) * 64;    // wave tile inside the workgroup tile
-    const int K = (int)(is_u ? prm.p : prm.m);               // contraction length
-    const int X = (int)(is_u ? prm.m : prm.p);               // output columns
-    const int kpad = (int)prm.kpad;
-    // t operand [k][t] (row stride kpad): the transposed gathered operand of the other matrix
-    const float* Aop = is_u ? prm.BT + s * prm.p * prm.kpad : prm.AT + s * prm.m * prm.kpad;
-    // x operand [k][x] (row stride X): G^T (p x m) for U^T, G (m x p) for V
-    const float* Bop = is_u ? prm.GT : prm.G;
-    const bool vec_x = (X % 4) == 0;                         // 16-byte rows of the x operand
-
-    float4 ra[VA], rb[VB];
-    auto fetch = [&](int c) {
-        const int k0 = c * kAdjChunk;
-#pragma unroll
-        for (int v = 0; v < VA; ++v) {
-            const int vid = threadIdx.x + v * kAdjThreads;
-            const int kk = vid / (kAdjTileT / 4), t = tb + (vid % (kAdjTileT / 4)) * 4;
-            const int k = k0 + kk;
-            // kpad is a multiple of 8, so a vector of 4 t values is whole or absent
-            ra[v] = (k < K && t < kpad) ? *reinterpret_cast<const float4*>(Aop + (int64_t)k * kpad + t)
-                                        : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-#pragma unroll
-        for (int v = 0; v < VB; ++v) {
-            const int vid = threadIdx.x + v * kAdjThreads;
-            const int kk = vid / (kAdjTileX / 4), x = xb + (vid % (kAdjTileX / 4)) * 4;
-            const int k = k0 + kk;
-            float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (k < K) {
-                const float* row = Bop + (int64_t)k * X;
-                if (vec_x && x < X) {
-                    val = *reinterpret_cast<const float4*>(row + x);
-                } else {
-                    if (x < X) val.x = row[x];
-                    if (x + 1 < X) val.y = row[x + 1];
-                    if (x + 2 < X) val.z = row[x + 2];
-                    if (x + 3 < X) val.w = row[x + 3];
-                }
-            }
-            rb[v] = val;
-        }
-    };
-    auto stash = [&](int buf) {
-#pragma unroll
-        for (int v = 0; v < VA; ++v)
-            *reinterpret_cast<float4*>(&lds_a[buf][(threadIdx.x + v * kAdjThreads) * 4]) = ra[v];
-#pragma unroll
-        for (int v = 0; v < VB; ++v)
-            *reinterpret_cast<float4*>(&lds_b[buf][(threadIdx.x + v * kAdjThreads) * 4]) = rb[v];
-    };
-
-    f32x16 acc[2];
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[bj][r] = 0.0f;
-    const int chunks = (K + kAdjChunk - 1) / kAdjChunk;
-    fetch(0);
-    stash(0);
-    __syncthreads();
-    for (int c = 0; c < chunks; ++c) {
-        const int buf = c & 1;
-        if (c + 1 < chunks) fetch(c + 1);
-        const float* LA = lds_a[buf];
-        const float* LB = lds_b[buf];
-#pragma unroll 4
-        for (int kk = 0; kk < kAdjChunk; kk += kAdjKStep) {
-            const float a = LA[(kk + lane / 32) * kAdjTileT + wt + lane % 32];
-            const float b0 = LB[(kk + lane / 32) * kAdjTileX + wx + lane % 32];
-            const float b1 = LB[(kk + lane / 32) * kAdjTileX + wx + 32 + lane % 32];
-            acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b0, acc[0], 0, 0, 0);
-            acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b1, acc[1], 0, 0, 0);
-        }
-        if (c + 1 < chunks) stash(buf ^ 1);
-        __syncthreads();
-    }
-    // epilogue: lane l, register r holds row 8(r/4) + 4(l/32) + r%4, column l%32 of its block
-    const int32_t* R = prm.R + s * prm.kpad;
-    const float* N = is_u ? prm.ZS + s * prm.kpad * prm.m : prm.WS + s * prm.kpad * prm.p;
-    float* dM = is_u ? prm.dMA : prm.dMB;
-    float* dS = is_u ? prm.dSA : prm.dSB;
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-        const int x = xb + wx + bj * 32 + lane % 32;
-        if (x >= X) continue;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int t = tb + wt + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
-            if (t >= kpad) continue;
-            const int32_t col = R[t];
-            if (col < 0) continue;
-            float kappa = coarse_draw(t, prm.c_prev, prm.stride) ? prm.kappa_coarse : prm.kappa_fine;
-            if (prm.iw) kappa *= (float)((double)prm.cum[prm.n - 1] / ((double)prm.n * (double)prm.iw[col]));
-            const float g = kappa * acc[bj][r];
-            unsafeAtomicAdd(dM + (int64_t)col * X + x, g);
-            unsafeAtomicAdd(dS + (int64_t)col * X + x, g * N[(int64_t)t * X + x]);
-        }
-    }
-}
-
-// BF16 form of the same tiles: both operands are K-contiguous, so a lane's
-// fragment (8 consecutive K of its row t or column x) is one 16-byte load
-// from global memory (L2-resident: the values of one realisation and G),
-// and v_mfma_f32_32x32x16_bf16 accumulates in FP32.  t operand: the
-// position-major BF16 values of the other matrix ([t][K], row stride KS);
-// x operand: G (for U^T, [i][q]) or G^T (for V, [q][i]) in BF16, stride KS.
-// The accumulator layout is that of the FP32 kernel, so is the epilogue.
-struct AdjBf16Params {
-    int64_t m, p, kpad, mk, pk;
-    uint32_t c_prev;
-    uint32_t stride;
-    float kappa_coarse, kappa_fine;
-    const __bf16* Gb;                 // m x pk: G
-    const __bf16* GTb;                // p x mk: G^T
-    const __bf16* ASb;                // batch x kpad x mk
-    const __bf16* BSb;                // batch x kpad x pk
-    const float* ZS;                  // batch x kpad x m
-    const float* WS;                  // batch x kpad x p
-    const int32_t* R;                 // batch x kpad
-    int64_t tiles_t, tiles_u_cols, tiles_v_cols;
-    float* dMA; float* dSA;
-    float* dMB; float* dSB;
-    const uint32_t* iw;
-    const uint64_t* cum;
-    uint32_t n;
-};
-
-// 8 consecutive K values of one row (stride KS), zero beyond K or for an
-// absent row; KS and k0 are multiples of 8, so the vector is aligned.
-__device__ __forceinline__ bf16x8 adj_frag(const __bf16* base, int64_t row, bool row_ok, int k0, int K, int64_t KS)
-{
-    bf16x8 v;
-    if (row_ok && k0 + 8 <= K) {
-        v = *reinterpret_cast<const bf16x8*>(base + row * KS + k0);
-    } else {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) v[i] = (row_ok && k0 + i < K) ? base[row * KS + k0 + i] : (__bf16)0.0f;
-    }
-    return v;
-}
-
-__global__ __launch_bounds__(kAdjThreads) void adjoint_mfma_bf16_kernel(AdjBf16Params prm)
-{
-    const int lane = threadIdx.x % kWave;
-    const int wave = threadIdx.x / kWave;
-    const int64_t s = blockIdx.y;
-    int64_t tile = blockIdx.x;
-    const int64_t u_tiles = prm.tiles_t * prm.tiles_u_cols;
-    const bool is_u = tile < u_tiles;
-    if (!is_u) tile -= u_tiles;
-    const int64_t cols_tiles = is_u ? prm.tiles_u_cols : prm.tiles_v_cols;
-    const int tb = (int)(tile / cols_tiles) * kAdjTileT;
-    const int xb = (int)(tile % cols_tiles) * kAdjTileX;
-    const int wt = (wave / 2) * 32, wx = (wave % 2) * 64;
-    const int K = (int)(is_u ? prm.p : prm.m);
-    const int X = (int)(is_u ? prm.m : prm.p);
-    const int64_t KS = is_u ? prm.pk : prm.mk;
-    const int kpad = (int)prm.kpad;
-    const __bf16* Aop = is_u ? prm.BSb + s * prm.kpad * prm.pk : prm.ASb + s * prm.kpad * prm.mk;
-    const __bf16* Bop = is_u ? prm.Gb : prm.GTb;
-    const int t = tb + wt + lane % 32;
-    const int x0 = xb + wx + lane % 32, x1 = x0 + 32;
-    const bool t_ok = t < kpad, x0_ok = x0 < X, x1_ok = x1 < X;
-    const int koff = 8 * (lane / 32);
-
-    f32x16 acc[2];
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[bj][r] = 0.0f;
-#pragma unroll 2
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        const bf16x8 a = adj_frag(Aop, t, t_ok, k0 + koff, K, KS);
-        const bf16x8 b0 = adj_frag(Bop, x0, x0_ok, k0 + koff, K, KS);
-        const bf16x8 b1 = adj_frag(Bop, x1, x1_ok, k0 + koff, K, KS);
-        acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc[0], 0, 0, 0);
-        acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc[1], 0, 0, 0);
-    }
-    const int32_t* R = prm.R + s * prm.kpad;
-    const float* N = is_u ? prm.ZS + s * prm.kpad * prm.m : prm.WS + s * prm.kpad * prm.p;
-    float* dM = is_u ? prm.dMA : prm.dMB;
-    float* dS = is_u ? prm.dSA : prm.dSB;
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-        const int x = xb + wx + bj * 32 + lane % 32;
-        if (x >= X) continue;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int tt = tb + wt + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
-            if (tt >= kpad) continue;
-            const int32_t col = R[tt];
-            if (col < 0) continue;
-            float kappa = coarse_draw(tt, prm.c_prev, prm.stride) ? prm.kappa_coarse : prm.kappa_fine;
-            if (prm.iw) kappa *= (float)((double)prm.cum[prm.n - 1] / ((double)prm.n * (double)prm.iw[col]));
-            const float g = kappa * acc[bj][r];
-            unsafeAtomicAdd(dM + (int64_t)col * X + x, g);
-            unsafeAtomicAdd(dS + (int64_t)col * X + x, g * N[(int64_t)tt * X + x]);
-        }
-    }
-}
-
-// G and G^T in BF16 (round to nearest even), K-contiguous with padded strides
-__global__ void grad_prepare_bf16_kernel(const double* grad, int64_t m, int64_t p, int64_t mk, int64_t pk,
-                                         __bf16* Gb, __bf16* GTb)
-{
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m * p) return;
-    const int64_t i = e / p, q = e % p;
-    const __bf16 v = (__bf16)(float)grad[e];
-    Gb[i * pk + q] = v;
-    GTb[q * mk + i] = v;
-}
-
-__global__ void grad_prepare_kernel(const double* grad, int64_t m, int64_t p, float* G, float* GT)
-{
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m * p) return;
-    const int64_t i = e / p, q = e % p;
-    const float v = (float)grad[e];
-    G[e] = v;
-    GT[q * m + i] = v;
-}
+constexpr int kSortThreads = 256;         // one thread per digit value
+constexpr int kSortItems = 16;
+constexpr int kSortBlock = kSortThreads * kSortItems;
+constexpr int kSortScanThreads = 1024;
 
 static int64_t round_up_adj(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 
-// Head of the workspace: G and G^T in FP32, then in BF16 (padded strides).
+// Draw t is one of the coarse draws of its level sample.
+__device__ __forceinline__ bool coarse_draw(uint32_t t, uint32_t c_prev, uint32_t stride)
+{
+    return stride ? (t + 1u) % stride == 0u : t < c_prev;
+}
+
+// ---- the draws of a pass ------------------------------------------------------
+// The draws of every level are numbered in one sequence (level by level,
+// realisation by realisation, t = 0 .. c_l - 1); a pass takes a contiguous
+// range of it, so that a pass may hold whole levels or parts of several.
+constexpr int kAdjMaxLevels = 32;
+
+struct AdjLevelTable {
+    int32_t nlev;
+    int64_t first[kAdjMaxLevels + 1];     // number of each level's first draw; first[nlev]: all draws
+    uint32_t c[kAdjMaxLevels], c_prev[kAdjMaxLevels], stride[kAdjMaxLevels];
+    uint32_t sid_index[kAdjMaxLevels], sid_value[kAdjMaxLevels];
+    float kappa_coarse[kAdjMaxLevels], kappa_fine[kAdjMaxLevels];
+};
+
+struct AdjDraw {
+    int l;
+    uint32_t k, t;                        // realisation and position in it
+};
+
+__device__ __forceinline__ AdjDraw adj_draw(const AdjLevelTable& lt, int64_t g)
+{
+    int l = 0;
+    while (l + 1 < lt.nlev && g >= lt.first[l + 1]) ++l;
+    const int64_t r = g - lt.first[l];
+    AdjDraw d;
+    d.l = l;
+    d.k = (uint32_t)(r / lt.c[l]);
+    d.t = (uint32_t)(r % lt.c[l]);
+    return d;
+}
+
+struct AdjKeyParams {
+    AdjLevelTable lt;
+    int64_t g0, E;                        // the pass: draws g0 .. g0 + E - 1
+    uint32_t n;
+    uint32_t key0, key1;
+    const uint64_t* cum;                  // cumulative index weights (NULL: uniform draws)
+    uint32_t* keys;
+    uint32_t* vals;
+};
+
+__global__ __launch_bounds__(256) void adj_keys_kernel(AdjKeyParams prm)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= prm.E) return;
+    const AdjDraw d = adj_draw(prm.lt, prm.g0 + e);
+    const uint32_t sid = prm.lt.sid_index[d.l];
+    prm.keys[e] = prm.cum ? draw_index_weighted(d.t, d.k, sid, prm.key0, prm.key1, prm.cum, prm.n, prm.cum[prm.n - 1])
+                          : draw_index(d.t, d.k, sid, prm.key0, prm.key1, prm.n);
+    prm.vals[e] = (uint32_t)e;
+}
+
+// ---- stable LSD radix sort by column (8-bit digits) ---------------------------
+// counts[d * nb + b]: draws of block b whose digit is d (integer LDS atomics:
+// the counts do not depend on their order).
+__global__ __launch_bounds__(kSortThreads) void adj_radix_hist_kernel(const uint32_t* keys, int64_t E, int shift,
+                                                                       uint32_t* counts, int64_t nb)
+{
+    __shared__ uint32_t h[kSortThreads];
+    h[threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortBlock;
+    for (int i = 0; i < kSortItems; ++i) {
+        const int64_t e = base + (int64_t)i * kSortThreads + threadIdx.x;
+        if (e < E) atomicAdd(&h[(keys[e] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    counts[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive prefix sum of the digit-major counts, in place (one workgroup).
+__global__ __launch_bounds__(kSortScanThreads) void adj_radix_scan_kernel(uint32_t* counts, int64_t len)
+{
+    __shared__ uint32_t part[kSortScanThreads];
+    const int64_t per = (len + kSortScanThreads - 1) / kSortScanThreads;
+    const int64_t b = (int64_t)threadIdx.x * per;
+    const int64_t e = b + per < len ? b + per : len;
+    uint32_t s = 0u;
+    for (int64_t i = b; i < e; ++i) s += counts[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < kSortScanThreads; off <<= 1) {
+        const uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+    for (int64_t i = b; i < e; ++i) {
+        const uint32_t c = counts[i];
+        counts[i] = run;
+        run += c;
+    }
+}
+
+// Block b places its draws, in their order, after every draw of a smaller
+// digit and after the draws of the same digit in blocks before b.  Inside the
+// block the draws go in rounds of 256 (round-major, then thread order, which
+// is their order): a wave finds the lanes that share its digit with eight
+// ballots, and the waves' counts per digit, kept in LDS, order the waves.
+__global__ __launch_bounds__(kSortThreads) void adj_radix_scatter_kernel(const uint32_t* kin, const uint32_t* vin,
+                                                                          uint32_t* kout, uint32_t* vout, int64_t E,
+                                                                          int shift, const uint32_t* offsets,
+                                                                          int64_t nb)
+{
+    constexpr int W = kSortThreads / kWave;
+    __shared__ uint32_t run[kSortThreads];
+    __shared__ uint32_t wcnt[W][kSortThreads];
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    run[threadIdx.x] = offsets[(int64_t)threadIdx.x * nb + blockIdx.x];
+    for (int w = 0; w < W; ++w) wcnt[w][threadIdx.x] = 0u;
+    __syncthreads();
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int64_t base = (int64_t)blockIdx.x * kSortBlock;
+    for (int i = 0; i < kSortItems; ++i) {
+        const int64_t e = base + (int64_t)i * kSortThreads + threadIdx.x;
+        const bool ok = e < E;
+        uint32_t key = 0u, val = 0u, d = 0u;
+        if (ok) {
+            key = kin[e];
+            val = vin[e];
+            d = (key >> shift) & 255u;
+        }
+        uint64_t peers = __ballot(ok);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool on = (d >> bit) & 1u;
+            const uint64_t m = __ballot(on);
+            peers &= on ? m : ~m;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & below);
+        if (ok && rank == 0u) wcnt[wave][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (ok) {
+            uint32_t pos = run[d] + rank;
+            for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        uint32_t tot = 0u;
+        for (int w = 0; w < W; ++w) {
+            tot += wcnt[w][threadIdx.x];
+            wcnt[w][threadIdx.x] = 0u;
+        }
+        run[threadIdx.x] += tot;
+        __syncthreads();
+    }
+}
+
+// ---- regeneration of the sampled columns, in sorted order --------------------
+// The contraction's t operand is stored tile-blocked, so that each K-chunk
+// of a tile is one contiguous block that the tile kernel copies straight into
+// LDS: FP32 values at [tile][k][row] (k < Kc, row < 64), BF16 at
+// [tile][k / 8][row][k % 8]; Kc is K rounded up to kAdjKc, and the rows past
+// K and the draws past the end of the last tile hold zeros.  The normals stay
+// position-major ([draw][row], row stride m or p rounded up to 8): the
+// epilogue reads them along the gradient columns.
+constexpr int kAdjKc = 128;               // four chunks of either precision
+
+struct AdjGatherParams {
+    AdjLevelTable lt;
+    int64_t m, p, g0, E;
+    int64_t kca, kcb;             // K of the two operand blocks: m and p rounded up to kAdjKc
+    int64_t ma, pa;               // row strides of the normals (m, p rounded up to 8)
+    uint32_t n;
+    uint32_t key0, key1;
+    Law A, B;
+    const uint32_t* keys;         // sorted columns
+    const uint32_t* vals;         // sorted draw numbers (within the pass)
+    const uint32_t* iw;           // index weights (NULL: uniform): kappa_t also times 1 / (n xi_j)
+    const uint64_t* cum;
+    void* VA;                     // tiles x kca x 64: values of a_t (FP32, or BF16 in the same region)
+    void* VB;                     // tiles x kcb x 64: values of b_t
+    float* ZA;                    // E x ma normals of a_t
+    float* ZB;                    // E x pa normals of b_t
+    float* kap;                   // E
+    bool value16;                 // the forward's values came from 16-bit uniforms
+};
+
+// Element (k, row) of a tile block of K-extent kc.
+__device__ __forceinline__ int64_t adj_blk_f32(int64_t T, int64_t kc, int64_t k, int row)
+{
+    return (T * kc + k) * kAdjRows + row;
+}
+__device__ __forceinline__ int64_t adj_blk_bf16(int64_t T, int64_t kc, int64_t k, int row)
+{
+    return ((T * (kc / 8) + k / 8) * kAdjRows + row) * 8 + (k % 8);
+}
+
+// One workgroup per tile of 64 sorted draws.  The rows of each operand are
+// taken in blocks of 64 (k0 .. k0 + 63 of a or of b, up to the padded K): for
+// a block, every (Philox quad of rows, group of four draws) pair generates
+// its values and normals, the normals go straight to global memory
+// (position-major, a quad's four rows adjacent) and the values into an LDS
+// tile [row][draw]; the tile is then written out in the blocked layout with
+// whole 16-byte vectors (FP32: a row's 64 draws, 256 bytes; BF16: eight
+// rows of one draw).  Rows past K and draws past the pass hold zeros.
+constexpr int kAdjGatherBlock = 64;
+
+template <bool BF16>
+__global__ __launch_bounds__(kAdjThreads) void adj_gather_kernel(AdjGatherParams prm)
+{
+    __shared__ uint32_t cols[kAdjRows];
+    __shared__ uint32_t reals[kAdjRows];
+    __shared__ uint32_t sids[kAdjRows];
+    __shared__ __align__(16) float tile[kAdjGatherBlock][kAdjRows];   // [row of the block][draw]
+    const int64_t T = blockIdx.x;
+    const int64_t e_first = T * kAdjRows;
+    const int64_t left = prm.E - e_first;
+    const int nvalid = left < kAdjRows ? (int)left : kAdjRows;
+    if (threadIdx.x < kAdjRows) {
+        const int64_t e = e_first + threadIdx.x;
+        uint32_t j = 0u, k = 0u, sid = 0u;
+        if ((int)threadIdx.x < nvalid) {
+            const AdjDraw d = adj_draw(prm.lt, prm.g0 + prm.vals[e]);
+            j = prm.keys[e];
+            k = d.k;
+            sid = prm.lt.sid_value[d.l];
+            float kappa = coarse_draw(d.t, prm.lt.c_prev[d.l], prm.lt.stride[d.l]) ? prm.lt.kappa_coarse[d.l]
+                                                                                     : prm.lt.kappa_fine[d.l];
+            if (prm.iw) kappa *= (float)((double)prm.cum[prm.n - 1] / ((double)prm.n * (double)prm.iw[j]));
+            prm.kap[e] = kappa;
+        }
+        cols[threadIdx.x] = j;
+        reals[threadIdx.x] = k;
+        sids[threadIdx.x] = sid;
+    }
+    const int64_t m = prm.m, rows = prm.m + prm.p;
+    const int ngroups = (nvalid + 3) / 4;                 // groups of four draws with a valid one
+    for (int part = 0; part < 2; ++part) {
+        const int64_t K = part ? prm.p : m;               // rows of the operand
+        const int64_t kc = part ? prm.kcb : prm.kca;      // its padded K
+        const int64_t off = part ? m : 0;                 // its first row in [a; b]
+        float* Zp = part ? prm.ZB : prm.ZA;
+        const int64_t zs = part ? prm.pa : prm.ma;
+        for (int64_t k0 = 0; k0 < kc; k0 += kAdjGatherBlock) {
+            __syncthreads();                              // the tile is free (and the draw table written)
+            // rows k0 .. k1 - 1 of the operand are real; the rest of the tile is zero
+            const int64_t k1 = K < k0 + kAdjGatherBlock ? K : k0 + kAdjGatherBlock;
+            for (int i = threadIdx.x; i < kAdjGatherBlock * kAdjRows; i += kAdjThreads) {
+                const int rr = i / kAdjRows, d = i % kAdjRows;
+                if (k0 + rr >= k1 || d >= nvalid) tile[rr][d] = 0.0f;
+            }
+            if (k0 < k1) {
+                // quads of [a; b] rows covering rows off + k0 .. off + k1 - 1
+                const int64_t q_lo = (off + k0) / 4, q_hi = (off + k1 - 1) / 4;
+                const int nq = (int)(q_hi - q_lo + 1);
+                for (int item = threadIdx.x; item < nq * ngroups; item += kAdjThreads) {
+                    const int g = item / nq;
+                    const int64_t q = q_lo + item % nq;
+                    const int64_t e0 = 4 * q;
+                    for (int dd = 0; dd < 4; ++dd) {
+                        const int r = 4 * g + dd;
+                        if (r >= nvalid) break;
+                        const uint32_t j = cols[r], kr = reals[r], sid = sids[r];
+                        float u[4], z[4];
+                        if (prm.value16) {
+                            // rows 4q .. 4q+3 are halves of words 2 (q & 1) and 2 (q & 1) + 1
+                            // of the call for rows 8 (q / 2) .. 8 (q / 2) + 7
+                            const Words4 w = philox4x32_10((uint32_t)(q >> 1), kr, j, sid, prm.key0, prm.key1);
+                            const uint32_t a = (q & 1) ? w.w2 : w.w0, b = (q & 1) ? w.w3 : w.w1;
+                            u[0] = unit16<float>(a & 0xFFFFu);
+                            u[1] = unit16<float>(a >> 16);
+                            u[2] = unit16<float>(b & 0xFFFFu);
+                            u[3] = unit16<float>(b >> 16);
+                            box_muller(u[0], u[1], z[0], z[1]);
+                            box_muller(u[2], u[3], z[2], z[3]);
+                        } else {
+                            const Words4 w = philox4x32_10((uint32_t)q, kr, j, sid, prm.key0, prm.key1);
+                            quad_values<float>(w, true, u[0], u[1], u[2], u[3], z[0], z[1], z[2], z[3]);
+                        }
+                        // the quad's rows that lie in this block of this operand
+                        const int64_t dr = e_first + r;
+                        const bool whole = e0 >= off + k0 && e0 + 3 < off + k1 && ((e0 - off) & 3) == 0;
+                        if (whole) {
+                            const int64_t k = e0 - off;
+                            const Law& law = part ? prm.B : prm.A;
+                            for (int i2 = 0; i2 < 4; ++i2)
+                                tile[k - k0 + i2][r] = law_value<float>(law, z[i2], u[i2], (int64_t)j * law.ld + k + i2);
+                            *reinterpret_cast<float4*>(Zp + dr * zs + k) = make_float4(z[0], z[1], z[2], z[3]);
+                        } else {
+                            for (int i2 = 0; i2 < 4; ++i2) {
+                                const int64_t e = e0 + i2;
+                                if (e < off + k0 || e >= off + k1 || e >= rows) continue;
+                                const int64_t k = e - off;
+                                const Law& law = part ? prm.B : prm.A;
+                                tile[k - k0][r] = law_value<float>(law, z[i2], u[i2], (int64_t)j * law.ld + k);
+                                Zp[dr * zs + k] = z[i2];
+                            }
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            // write the block out
+            if constexpr (!BF16) {
+                float* V = static_cast<float*>(part ? prm.VB : prm.VA);
+                for (int i = threadIdx.x; i < kAdjGatherBlock * kAdjRows / 4; i += kAdjThreads) {
+                    const int rr = i / (kAdjRows / 4), d4 = i % (kAdjRows / 4);
+                    *reinterpret_cast<float4*>(V + adj_blk_f32(T, kc, k0 + rr, 4 * d4)) =
+                        *reinterpret_cast<const float4*>(&tile[rr][4 * d4]);
+                }
+            } else {
+                __bf16* V = static_cast<__bf16*>(part ? prm.VB : prm.VA);
+                for (int i = threadIdx.x; i < (kAdjGatherBlock / 8) * kAdjRows; i += kAdjThreads) {
+                    const int g8 = i / kAdjRows, d = i % kAdjRows;
+                    bf16x8 v;
+#pragma unroll
+                    for (int i2 = 0; i2 < 8; ++i2) v[i2] = (__bf16)tile[8 * g8 + i2][d];
+                    *reinterpret_cast<bf16x8*>(V + adj_blk_bf16(T, kc, k0 + 8 * g8, d)) = v;
+                }
+            }
+        }
+    }
+}
+
+// ---- contraction tiles and the segmented sums --------------------------------
+typedef __attribute__((address_space(1))) void* AdjGlobalPtr;   // operands of global_load_lds
+typedef __attribute__((address_space(3))) void* AdjLdsPtr;
+
+struct AdjTileParams {
+    int64_t m, p, E;
+    int64_t kca, kcb;             // K extents of the t operand blocks (of a_t and of b_t)
+    int64_t ma, pa;               // row strides of the normals
+    int64_t xpad_m, xpad_p;       // m, p rounded up to 128
+    const void* XU;               // x operand of U = B_S G^T: FP32 [kcb][xpad_m] (G^T), BF16 blocked
+    const void* XV;               // x operand of V = A_S^T G: FP32 [kca][xpad_p] (G), BF16 blocked
+    const void* VA;               // t operand of V (values of a_t), tile-blocked
+    const void* VB;               // t operand of U (values of b_t)
+    const float* ZA;
+    const float* ZB;
+    const float* kap;
+    const uint32_t* keys;
+    int64_t tiles;                // row tiles (64 sorted draws each)
+    int64_t tiles_u, tiles_v;     // column tiles of U; those of V follow
+    float* dMA; float* dSA; int64_t lda;
+    float* dMB; float* dSB; int64_t ldb;
+    float* carry;                 // tiles x 2 (first, last) x 2 (dM, dS) x (m + p)
+};
+
+// K-chunk of a stage: 16 (FP32) or 32 (BF16) k; a stage holds the chunk's t
+// block (64 rows, 4 KB) and x block (128 columns, 8 KB); kAdjStages stages
+// keep two chunks' loads in flight during the MFMAs of a third.
+constexpr int kAdjStages = 4;
+constexpr int kAdjStageBytes = 12 * 1024;
+constexpr size_t kAdjSums = kAdjRows * kAdjCols * sizeof(float);
+constexpr size_t kAdjLds = (size_t)kAdjStages * kAdjStageBytes > kAdjSums ? (size_t)kAdjStages * kAdjStageBytes
+                                                                            : kAdjSums;
+constexpr int kAdjBatch = 8;              // gradient read-modify-writes in flight per thread
+static_assert(kAdjKc % (4 * 32) == 0, "the padded K holds a whole number of four-chunk steps");
+constexpr int kAdjXcds = 8;               // accelerator complex dies of an MI355X, each with its own L2
+
+struct AdjTileShape {
+    int64_t T;                    // tile of sorted draws
+    bool is_u;
+    int xt;                       // column tile (of U or of V)
+    int xb;                       // first gradient column of the tile
+    int X;                        // gradient columns
+    int wt, wx;                   // the wave's 32 x 64 block inside the tile
+};
+
+// Workgroups are dealt to the XCDs in turn (workgroup i to XCD i % 8); the
+// tiles are numbered so that each XCD takes a contiguous range of them, and
+// the column tiles of one row tile are adjacent: the workgroups that read
+// the same t block then run on one XCD at about the same time and share it
+// through that XCD's L2.
+__device__ __forceinline__ AdjTileShape adj_shape(const AdjTileParams& prm)
+{
+    // the grid has fewer than 2^31 workgroups: 32-bit arithmetic
+    const uint32_t xt = (uint32_t)(prm.tiles_u + prm.tiles_v);
+    const uint32_t total = (uint32_t)prm.tiles * xt;
+    const uint32_t i = blockIdx.x;
+    const uint32_t xcd = i % kAdjXcds, local = i / kAdjXcds;
+    const uint32_t q = total / kAdjXcds, rem = total % kAdjXcds;
+    const uint32_t li = xcd * q + (xcd < rem ? xcd : rem) + local;
+    AdjTileShape s;
+    s.T = li / xt;
+    int64_t ct = li % xt;
+    s.is_u = ct < prm.tiles_u;
+    if (!s.is_u) ct -= prm.tiles_u;
+    s.xt = (int)ct;
+    s.xb = (int)ct * kAdjCols;
+    s.X = (int)(s.is_u ? prm.m : prm.p);
+    const int wave = threadIdx.x / kWave;
+    s.wt = (wave / 2) * 32;
+    s.wx = (wave % 2) * 64;
+    return s;
+}
+
+// Segments of the tile's rows, the same for every column: skey[0] is the
+// column of the draw before the tile, skey[1 + r] row r's, skey[65] the one
+// after the tile (kNoKey past either end); fin[0 .. nfin) lists the rows that
+// close a segment lying inside the tile (finished here); the first segment
+// goes to carry slot 0 when it began in an earlier tile, the last to slot 1
+// when it continues into the next.
+struct AdjSegments {
+    uint32_t skey[kAdjRows + 2];
+    float kap[kAdjRows];          // kappa_t of the tile's rows (0 past the end)
+    uint64_t ends;                // bit r: row r closes a segment
+    int began;                    // the first segment began in an earlier tile
+    int cont;                     // the last segment continues into the next tile
+    uint8_t fin[kAdjRows];
+    int nfin;
+};
+
+__device__ __forceinline__ void adj_load_keys(const AdjTileParams& prm, int64_t T, AdjSegments& sg)
+{
+    const int64_t r0 = T * kAdjRows;
+    if (threadIdx.x < kAdjRows + 2) {
+        const int64_t e = r0 - 1 + threadIdx.x;
+        sg.skey[threadIdx.x] = (e >= 0 && e < prm.E) ? prm.keys[e] : kNoKey;
+    }
+    if (threadIdx.x < kAdjRows) {
+        const int64_t e = r0 + threadIdx.x;
+        sg.kap[threadIdx.x] = e < prm.E ? prm.kap[e] : 0.0f;
+    }
+}
+
+__device__ __forceinline__ void adj_segments(AdjSegments& sg, int rows)
+{
+    int n = 0, start = 0;
+    uint64_t ends = 0ull;
+    sg.began = sg.skey[0] == sg.skey[1];
+    sg.cont = rows == kAdjRows && sg.skey[kAdjRows + 1] == sg.skey[kAdjRows];
+    for (int r = 0; r < rows; ++r) {
+        if (r == rows - 1 || sg.skey[r + 2] != sg.skey[r + 1]) {
+            ends |= 1ull << r;
+            const bool began = start == 0 && sg.began;
+            const bool cont = r == rows - 1 && sg.cont;
+            if (!began && !cont) sg.fin[n++] = (uint8_t)r;
+            start = r + 1;
+        }
+    }
+    sg.ends = ends;
+    sg.nfin = n;
+}
+
+// Row t of the epilogue's 64 x 128 sums lives in one of three stage arrays
+// (24 rows each).
+struct AdjRows {
+    float* s0;
+    float* s1;
+    float* s2;
+    __device__ __forceinline__ float* row(int t) const
+    {
+        return t < 24 ? s0 + t * kAdjCols : t < 48 ? s1 + (t - 24) * kAdjCols : s2 + (t - 48) * kAdjCols;
+    }
+};
+
+// The accumulators (lane l, register r of block bj: row 8(r/4) + 4(l/32) + r%4,
+// column 32 bj + l%32 of the wave's block) times kappa_t (dM), then times
+// kappa_t z_t (dS), each in turn through LDS: 128 threads walk their column
+// down the rows in draw order and leave each segment's sum in the row that
+// closes it (or in its carry slot); then all threads add the finished sums
+// into the gradient rows, kAdjBatch independent read-modify-writes at a time.
+__device__ __forceinline__ void adj_epilogue(const AdjTileParams& prm, const AdjTileShape& sh, const f32x16 (&acc)[2],
+                                             const AdjRows& sv, AdjSegments& sg)
+{
+    const int lane = threadIdx.x % kWave;
+    const int64_t r0 = sh.T * kAdjRows;
+    const int64_t left = prm.E - r0;
+    const int rows = left < kAdjRows ? (int)left : kAdjRows;
+    if (threadIdx.x == 0) adj_segments(sg, rows);
+    const float* Z = sh.is_u ? prm.ZA : prm.ZB;
+    const int64_t zs = sh.is_u ? prm.ma : prm.pa;
+    const int64_t ld = sh.is_u ? prm.lda : prm.ldb;
+    const int64_t cw = prm.m + prm.p;
+    for (int which = 0; which < 2; ++which) {
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            const int xl = sh.wx + bj * 32 + lane % 32;
+            const int x = sh.xb + xl;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int t = sh.wt + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
+                const bool ok = r0 + t < prm.E && x < sh.X;
+                const float v = sg.kap[t] * acc[bj][r];
+                sv.row(t)[xl] = (which && ok) ? v * Z[(r0 + t) * zs + x] : v;
+            }
+        }
+        __syncthreads();
+        // the walk: the running sum in row order; the segment ends are the
+        // same for every column (uniform branches)
+        if (threadIdx.x < kAdjCols) {
+            const int xl = threadIdx.x, x = sh.xb + xl;
+            if (x < sh.X) {
+                const int64_t ccol = (sh.is_u ? 0 : prm.m) + x;
+                const uint64_t ends = sg.ends;
+                float sum = 0.0f;
+                bool first = true;
+#pragma unroll 1
+                for (int r = 0; r < rows; ++r) {
+                    float* cell = sv.row(r) + xl;
+                    sum += *cell;
+                    if ((ends >> r) & 1ull) {
+                        const bool began = first && sg.began;
+                        const bool cont = r == rows - 1 && sg.cont;
+                        if (began || cont)
+                            prm.carry[((sh.T * 2 + (began ? 0 : 1)) * 2 + which) * cw + ccol] = sum;
+                        else
+                            *cell = sum;
+                        sum = 0.0f;
+                        first = false;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        float* grad = sh.is_u ? (which ? prm.dSA : prm.dMA) : (which ? prm.dSB : prm.dMB);
+        const int items = sg.nfin * kAdjCols;
+        for (int base = 0; base < items; base += kAdjThreads * kAdjBatch) {
+            float* ptr[kAdjBatch];
+            float v[kAdjBatch], g[kAdjBatch];
+#pragma unroll
+            for (int u = 0; u < kAdjBatch; ++u) {
+                const int i = base + u * kAdjThreads + (int)threadIdx.x;
+                const int r = i < items ? sg.fin[i / kAdjCols] : 0;
+                const int xl = i % kAdjCols, x = sh.xb + xl;
+                ptr[u] = nullptr;
+                if (i < items && x < sh.X) {
+                    ptr[u] = grad + (int64_t)sg.skey[r + 1] * ld + x;
+                    v[u] = sv.row(r)[xl];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kAdjBatch; ++u)
+                if (ptr[u]) g[u] = *ptr[u];
+#pragma unroll
+            for (int u = 0; u < kAdjBatch; ++u)
+                if (ptr[u]) *ptr[u] = g[u] + v[u];
+        }
+        __syncthreads();
+    }
+}
+
+// U^T = B_S G^T (rows: the tile's sorted draws, columns i) or V = A_S^T G
+// (columns q).  FP32: v_mfma_f32_32x32x2_f32, chunks of 16 k; BF16:
+// v_mfma_f32_32x32x16_bf16 (FP32 accumulation), chunks of 32 k.  A chunk's t
+// block (4 KB) and x block (8 KB) go straight from global memory into one of
+// four LDS stage arrays (global_load_lds_dwordx4: lane i's 16 bytes land at
+// the wave's base plus 16 i, which is the stored layout), so no registers
+// hold them; the chunks c + 1 and c + 2 are in flight while the MFMAs run on
+// chunk c, and the loads of chunk c + 3 are issued once every wave is past
+// chunk c - 1.  The stage arrays are separate objects so that the fragment
+// reads of one are not made to wait for the loads into the others.  2 x 2
+// waves, each 32 x 64 (two blocks sharing the t fragment).
+template <bool BF16>
+__global__ __launch_bounds__(kAdjThreads) void adj_tile_kernel(AdjTileParams prm)
+{
+    constexpr int C = BF16 ? 32 : 16;                  // k per chunk
+    constexpr int kLoads = 3;                          // global_load_lds per thread per chunk
+    __shared__ __align__(16) char st0[kAdjStageBytes];
+    __shared__ __align__(16) char st1[kAdjStageBytes];
+    __shared__ __align__(16) char st2[kAdjStageBytes];
+    __shared__ __align__(16) char st3[kAdjStageBytes];
+    __shared__ AdjSegments sg;
+    const AdjTileShape sh = adj_shape(prm);
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    adj_load_keys(prm, sh.T, sg);
+    const int64_t kc = sh.is_u ? prm.kcb : prm.kca;    // padded contraction length (multiple of 4 C)
+    const int64_t esz = BF16 ? 2 : 4;
+    // the tile's t block: kc x 64 values, 4 KB per chunk
+    const char* tsrc = static_cast<const char*>(sh.is_u ? prm.VB : prm.VA) + sh.T * kc * kAdjRows * esz;
+    const char* xsrc = static_cast<const char*>(sh.is_u ? prm.XU : prm.XV);
+    const int64_t xpad = sh.is_u ? prm.xpad_m : prm.xpad_p;
+    if constexpr (BF16) xsrc += (int64_t)sh.xt * kc * kAdjCols * esz;   // blocked: [tile][k/8][128][8]
+
+    auto issue = [&](int c, char* st) {
+        __builtin_amdgcn_global_load_lds((AdjGlobalPtr)(tsrc + (int64_t)c * 4096 + threadIdx.x * 16),
+                                         (AdjLdsPtr)(st + wave * 1024), 16, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const int vid = threadIdx.x + v * kAdjThreads;
+            const char* src;
+            if constexpr (BF16) {
+                src = xsrc + (int64_t)c * 8192 + vid * 16;
+            } else {
+                const int k = vid / 32, x4 = vid % 32;  // [k][128] floats
+                src = xsrc + (((int64_t)c * C + k) * xpad + sh.xb + 4 * x4) * 4;
+            }
+            __builtin_amdgcn_global_load_lds((AdjGlobalPtr)src, (AdjLdsPtr)(st + 4096 + (v * kAdjThreads + wave * kWave) * 16),
+                                             16, 0, 0);
+        }
+    };
+    f32x16 acc[2];
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[bj][r] = 0.0f;
+    auto compute = [&](const char* st) {
+        if constexpr (BF16) {
+            const __bf16* A = reinterpret_cast<const __bf16*>(st);          // [4][64][8]
+            const __bf16* B = reinterpret_cast<const __bf16*>(st + 4096);   // [4][128][8]
+#pragma unroll
+            for (int kk = 0; kk < C; kk += 16) {
+                const int g = kk / 8 + lane / 32;
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(A + (g * kAdjRows + sh.wt + lane % 32) * 8);
+                const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(B + (g * kAdjCols + sh.wx + lane % 32) * 8);
+                const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(B + (g * kAdjCols + sh.wx + 32 + lane % 32) * 8);
+                acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc[1], 0, 0, 0);
+            }
+        } else {
+            const float* A = reinterpret_cast<const float*>(st);            // [16][64]
+            const float* B = reinterpret_cast<const float*>(st + 4096);     // [16][128]
+#pragma unroll
+            for (int kk = 0; kk < C; kk += 2) {
+                const float a = A[(kk + lane / 32) * kAdjRows + sh.wt + lane % 32];
+                const float b0 = B[(kk + lane / 32) * kAdjCols + sh.wx + lane % 32];
+                const float b1 = B[(kk + lane / 32) * kAdjCols + sh.wx + 32 + lane % 32];
+                acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b0, acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b1, acc[1], 0, 0, 0);
+            }
+        }
+    };
+    // Every step issues one chunk (past the last one, the last chunk again,
+    // into a stage that is not read any more), so at the wait for chunk c
+    // exactly the loads of the two chunks after it are younger: vmcnt counts
+    // the outstanding loads in issue order.
+    auto wait_chunk = [&]() {
+        // s_waitcnt: vmcnt in bits 3:0 (and 15:14), expcnt 6:4 and lgkmcnt 11:8 left at their maxima
+        __builtin_amdgcn_s_waitcnt(0x0F70 | (2 * kLoads));
+    };
+    // The stage handover needs only the workgroup barrier: each wave has
+    // waited for its own loads of the chunk (vmcnt), and the LDS reads of the
+    // stage it overwrites next were consumed by MFMAs before the barrier.
+    // __syncthreads would also fence global memory, i.e. wait for every load
+    // still in flight.
+    auto handover = [&]() { asm volatile("s_barrier" ::: "memory"); };
+    const int chunks = (int)(kc / C);                  // a multiple of 4
+    issue(0, st0);
+    issue(1, st1);
+    issue(2, st2);
+    auto next = [&](int c) { return c < chunks ? c : chunks - 1; };
+    for (int c = 0; c < chunks; c += 4) {
+        wait_chunk();
+        handover();
+        issue(next(c + 3), st3);
+        compute(st0);
+        wait_chunk();
+        handover();
+        issue(next(c + 4), st0);
+        compute(st1);
+        wait_chunk();
+        handover();
+        issue(next(c + 5), st1);
+        compute(st2);
+        wait_chunk();
+        handover();
+        issue(next(c + 6), st2);
+        compute(st3);
+    }
+    __syncthreads();                                   // the repeated last loads have landed
+    adj_epilogue(prm, sh, acc, AdjRows{reinterpret_cast<float*>(st0), reinterpret_cast<float*>(st1),
+                                       reinterpret_cast<float*>(st2)}, sg);
+}
+
+// A column segment that crosses tile edges: its first tile T (whose last
+// segment continues and began in T) adds T's partial and those of the tiles
+// it runs through, in tile order, and writes the gradient row once.
+struct AdjFixParams {
+    int64_t m, p, E;
+    const uint32_t* keys;
+    const float* carry;
+    float* dMA; float* dSA; int64_t lda;
+    float* dMB; float* dSB; int64_t ldb;
+};
+
+__device__ __forceinline__ bool adj_continues(const uint32_t* keys, int64_t E, int64_t T)
+{
+    const int64_t l = T * kAdjRows + kAdjRows - 1;
+    return l + 1 < E && keys[l] == keys[l + 1];
+}
+
+__global__ __launch_bounds__(kAdjThreads) void adj_fixup_kernel(AdjFixParams prm)
+{
+    const int64_t T = blockIdx.x;
+    const uint32_t* keys = prm.keys;
+    if (!adj_continues(keys, prm.E, T)) return;
+    const int64_t f = T * kAdjRows;
+    const bool whole = keys[f] == keys[f + kAdjRows - 1];
+    const bool began = T > 0 && keys[f - 1] == keys[f];
+    if (whole && began) return;                           // inside a chain that starts earlier
+    const uint32_t j = keys[f + kAdjRows - 1];
+    const int64_t cw = prm.m + prm.p;
+    for (int64_t ci = threadIdx.x; ci < 2 * cw; ci += kAdjThreads) {
+        const int which = ci >= cw;
+        const int64_t col = ci - which * cw;
+        float sum = prm.carry[((T * 2 + 1) * 2 + which) * cw + col];
+        for (int64_t t2 = T + 1;; ++t2) {
+            sum += prm.carry[((t2 * 2 + 0) * 2 + which) * cw + col];
+            const int64_t f2 = t2 * kAdjRows;
+            if (!(adj_continues(keys, prm.E, t2) && keys[f2] == keys[f2 + kAdjRows - 1])) break;
+        }
+        float* g = col < prm.m ? (which ? prm.dSA : prm.dMA) + (int64_t)j * prm.lda + col
+                               : (which ? prm.dSB : prm.dMB) + (int64_t)j * prm.ldb + (col - prm.m);
+        *g += sum;
+    }
+}
+
+// ---- G, workspace and the pass loop -------------------------------------------
+// The x operands from G = dL/dY (FP64, m x p row-major), with zeros in the
+// padding: FP32 G^T as [kcb][xpad_m] and G as [kca][xpad_p]; BF16 (round to
+// nearest even) blocked per column tile, [tile][k / 8][128][k % 8]: for U,
+// column x = i and k = q (the value G[i][q]); for V, x = q and k = i.
+struct AdjXOperands {
+    int64_t m, p, kca, kcb, xpad_m, xpad_p;
+    const double* grad;
+    void* XU;
+    void* XV;
+};
+
+template <bool BF16>
+__global__ __launch_bounds__(256) void adj_x_operands_kernel(AdjXOperands o)
+{
+    const int64_t nu = o.kcb * o.xpad_m, nv = o.kca * o.xpad_p;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= nu + nv) return;
+    const bool u = e < nu;
+    const int64_t f = u ? e : e - nu;
+    const int64_t kc = u ? o.kcb : o.kca;
+    int64_t k, x;
+    if constexpr (BF16) {
+        // f = ((tile * (kc / 8) + k / 8) * 128 + x % 128) * 8 + k % 8
+        const int64_t k8 = f % 8, xl = (f / 8) % kAdjCols, g = f / (8 * kAdjCols);
+        k = (g % (kc / 8)) * 8 + k8;
+        x = (g / (kc / 8)) * kAdjCols + xl;
+    } else {
+        const int64_t xpad = u ? o.xpad_m : o.xpad_p;
+        k = f / xpad;
+        x = f % xpad;
+    }
+    // U: x = i < m, k = q < p; V: x = q < p, k = i < m
+    const int64_t i = u ? x : k, q = u ? k : x;
+    const float v = (i < o.m && q < o.p) ? (float)o.grad[i * o.p + q] : 0.0f;
+    if constexpr (BF16) static_cast<__bf16*>(u ? o.XU : o.XV)[f] = (__bf16)v;
+    else static_cast<float*>(u ? o.XU : o.XV)[f] = v;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct AdjDims {
+    int64_t kca, kcb, ma, pa, xpad_m, xpad_p;
+};
+
+static AdjDims adj_dims(int64_t m, int64_t p)
+{
+    AdjDims d;
+    d.kca = round_up_adj(m, kAdjKc);
+    d.kcb = round_up_adj(p, kAdjKc);
+    d.ma = round_up_adj(m, 8);
+    d.pa = round_up_adj(p, 8);
+    d.xpad_m = round_up_adj(m, kAdjCols);
+    d.xpad_p = round_up_adj(p, kAdjCols);
+    return d;
+}
+
+// Head of the workspace: the two x operands (FP32 sizes; BF16 uses half).
 static size_t adj_head_bytes(int64_t m, int64_t p)
 {
-    auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const int64_t mk = round_up_adj(m, 8), pk = round_up_adj(p, 8);
-    return align(2 * m * p * sizeof(float)) + align((size_t)(m * pk + p * mk) * sizeof(__bf16));
+    const AdjDims d = adj_dims(m, p);
+    return align256((size_t)(d.kcb * d.xpad_m) * 4) + align256((size_t)(d.kca * d.xpad_p) * 4);
 }
 
-// Bytes per draw position of the gathered values of A (or B): FP32 K-major
-// or BF16 position-major with the row padded to 8, whichever is larger.
-static int64_t adj_value_bytes(int64_t rows)
+// The buffers of a pass of E draws (values sized for FP32, which BF16 halves).
+struct AdjPassLayout {
+    size_t keys0, vals0, keys1, vals1, counts, VA, VB, ZA, ZB, kap, carry, total;
+};
+
+static AdjPassLayout adj_pass_layout(int64_t E, int64_t m, int64_t p)
 {
-    const int64_t f32 = 4 * rows, b16 = 2 * round_up_adj(rows, 8);
-    return f32 > b16 ? f32 : b16;
+    const AdjDims d = adj_dims(m, p);
+    const int64_t nb = ceil_div(E, kSortBlock), tiles = ceil_div(E, kAdjRows);
+    AdjPassLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { const size_t at = off; off = align256(off + bytes); return at; };
+    L.keys0 = take(4 * (size_t)E);
+    L.vals0 = take(4 * (size_t)E);
+    L.keys1 = take(4 * (size_t)E);
+    L.vals1 = take(4 * (size_t)E);
+    L.counts = take(4 * (size_t)kSortThreads * (size_t)nb);
+    L.VA = take(4 * (size_t)(tiles * kAdjRows * d.kca));
+    L.VB = take(4 * (size_t)(tiles * kAdjRows * d.kcb));
+    L.ZA = take(4 * (size_t)(E * d.ma));
+    L.ZB = take(4 * (size_t)(E * d.pa));
+    L.kap = take(4 * (size_t)E);
+    L.carry = take(4 * (size_t)(tiles * 4 * (m + p)));
+    L.total = off;
+    return L;
 }
 
-size_t adjoint_workspace_size(int64_t m, int64_t n, int64_t p, int num_levels, const int64_t* c, bool weighted)
+// Draws per pass: the most whose buffers fit the budget (at least 64), with
+// at most 2^30 draws and a tile grid below 2^31 workgroups.
+static int64_t adj_pass_draws(int64_t m, int64_t p, size_t budget)
 {
-    const int64_t kpad = round_up_adj(c[num_levels - 1], kAdjPositions);
-    const int64_t per_sample = kpad * (adj_value_bytes(m) + adj_value_bytes(p) + (m + p) * 4 + 4);
-    int64_t budget = kAdjBudget < per_sample ? per_sample : kAdjBudget;
-    // slack for the five 256-byte-aligned regions of a pass
-    size_t total = (size_t)budget + 2048;
-    total += adj_head_bytes(m, p);
-    if (weighted) total += ((size_t)n * sizeof(uint64_t) + 255) & ~(size_t)255;
+    const size_t per = adj_pass_layout(kAdjRows, m, p).total / kAdjRows + 1;
+    int64_t E = (int64_t)(budget / per);
+    const int64_t xt = ceil_div(m, kAdjCols) + ceil_div(p, kAdjCols);
+    int64_t cap = ((1ll << 31) - 1) / xt * kAdjRows;
+    if (cap > (1ll << 30)) cap = 1ll << 30;
+    if (E > cap) E = cap;
+    E = E / kAdjRows * kAdjRows;
+    if (E < kAdjRows) E = kAdjRows;
+    while (E > kAdjRows && adj_pass_layout(E, m, p).total > budget) E -= kAdjRows;
+    return E;
+}
+
+// Pass buffers: room for every draw of the call, or kAdjBudget when that is
+// less (N NULL: kAdjBudget); always room for one 64-draw pass.
+static size_t adj_budget(int64_t m, int64_t p, int num_levels, const int64_t* c, const int64_t* N)
+{
+    size_t need = (size_t)kAdjBudget;
+    if (N) {
+        int64_t draws = 0;
+        for (int l = 0; l < num_levels; ++l) draws += N[l] * c[l];
+        const size_t all = adj_pass_layout(draws, m, p).total;
+        if (all < need) need = all;
+    }
+    const size_t one = adj_pass_layout(kAdjRows, m, p).total;
+    return need > one ? need : one;
+}
+
+size_t adjoint_workspace_size(int64_t m, int64_t n, int64_t p, int num_levels, const int64_t* c, const int64_t* N,
+                              bool weighted)
+{
+    size_t total = adj_budget(m, p, num_levels, c, N) + adj_head_bytes(m, p);
+    if (weighted) total += align256((size_t)n * sizeof(uint64_t));
     return total;
 }
 
@@ -495,109 +902,128 @@ hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law&
                        const uint32_t* index_weights, char* ws, size_t ws_bytes, bool bf16, bool stride,
                        bool value16, hipStream_t stream, KernelTimer* timer)
 {
-    auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const int64_t mk = round_up_adj(m, 8), pk = round_up_adj(p, 8);
-    float* G = reinterpret_cast<float*>(ws);
-    float* GT = G + m * p;
-    __bf16* Gb = reinterpret_cast<__bf16*>(ws + align(2 * m * p * sizeof(float)));
-    __bf16* GTb = Gb + m * pk;
+    const AdjDims dims = adj_dims(m, p);
+    AdjXOperands xo;
+    xo.m = m; xo.p = p; xo.kca = dims.kca; xo.kcb = dims.kcb; xo.xpad_m = dims.xpad_m; xo.xpad_p = dims.xpad_p;
+    xo.grad = grad;
+    xo.XU = ws;
+    xo.XV = ws + align256((size_t)(dims.kcb * dims.xpad_m) * 4);
     const size_t head = adj_head_bytes(m, p);
     // the cumulative index weights follow the head
     uint64_t* cum = index_weights ? reinterpret_cast<uint64_t*>(ws + head) : nullptr;
-    const size_t cum_bytes = index_weights ? align((size_t)n * sizeof(uint64_t)) : 0;
+    const size_t cum_bytes = index_weights ? align256((size_t)n * sizeof(uint64_t)) : 0;
     char* buf = ws + head + cum_bytes;
-    const size_t budget = ws_bytes - head - cum_bytes;
+    const size_t budget = adj_budget(m, p, num_levels, c, N);
+    if (head + cum_bytes + budget > ws_bytes) return hipErrorInvalidValue;
     {
         ScopedTiming t(timer, 3);
+        const int64_t total = dims.kcb * dims.xpad_m + dims.kca * dims.xpad_p;
         if (bf16)
-            hipLaunchKernelGGL(grad_prepare_bf16_kernel, dim3((unsigned)ceil_div(m * p, 256)), dim3(256), 0, stream,
-                               grad, m, p, mk, pk, Gb, GTb);
+            hipLaunchKernelGGL(adj_x_operands_kernel<true>, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, stream,
+                               xo);
         else
-            hipLaunchKernelGGL(grad_prepare_kernel, dim3((unsigned)ceil_div(m * p, 256)), dim3(256), 0, stream, grad,
-                               m, p, G, GT);
+            hipLaunchKernelGGL(adj_x_operands_kernel<false>, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0,
+                               stream, xo);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (index_weights && (e = build_cumulative(index_weights, n, cum, stream)) != hipSuccess) return e;
+    // digits of the column: 8 bits per sort pass
+    int bits = 0;
+    while (bits < 32 && ((uint64_t)(n - 1) >> bits) != 0) ++bits;
+    const int digit_passes = (bits + 7) / 8;
+    AdjLevelTable lt;
+    lt.nlev = num_levels;
+    lt.first[0] = 0;
     for (int l = 0; l < num_levels; ++l) {
         const int64_t cl = c[l], cp = l > 0 ? c[l - 1] : 0;
-        const int64_t kpad = round_up_adj(cl, kAdjPositions);
-        const size_t per_sample = (size_t)kpad * (adj_value_bytes(m) + adj_value_bytes(p) + (m + p) * 4 + 4) + 5 * 256;
-        int64_t batch = (int64_t)(budget / per_sample);
-        if (batch < 1) batch = 1;
-        if (batch > 65535) batch = 65535;
         const double base = (double)n / (double)cl / (double)N[l];
-        const float kc = (float)(base * (cp > 0 ? 1.0 - (double)cl / (double)cp : 1.0));
-        const float kf = (float)base;
-        for (int64_t b0 = 0; b0 < N[l]; b0 += batch) {
-            const int64_t S = (N[l] - b0) < batch ? (N[l] - b0) : batch;
-            size_t off = 0;
-            // FP32: K-major AT, BT; BF16: position-major ASb, BSb in the same regions
-            float* AT = reinterpret_cast<float*>(buf + off); off = align(off + (size_t)(S * kpad * adj_value_bytes(m)));
-            float* BT = reinterpret_cast<float*>(buf + off); off = align(off + (size_t)(S * kpad * adj_value_bytes(p)));
-            __bf16* ASb = reinterpret_cast<__bf16*>(AT);
-            __bf16* BSb = reinterpret_cast<__bf16*>(BT);
-            float* ZS = reinterpret_cast<float*>(buf + off); off = align(off + sizeof(float) * S * kpad * m);
-            float* WS = reinterpret_cast<float*>(buf + off); off = align(off + sizeof(float) * S * kpad * p);
-            int32_t* Rr = reinterpret_cast<int32_t*>(buf + off); off = align(off + sizeof(int32_t) * S * kpad);
-            if (off > budget) return hipErrorInvalidValue;
+        const uint32_t lf = shared ? 0xFFu : (uint32_t)l;
+        lt.c[l] = (uint32_t)cl;
+        lt.c_prev[l] = (uint32_t)cp;
+        lt.stride[l] = stride && cp > 0 ? (uint32_t)(cl / cp) : 0u;
+        lt.sid_index[l] = stream_id(kTagIndex, lf, keys.problem);
+        lt.sid_value[l] = stream_id(kTagValue, lf, keys.problem);
+        lt.kappa_coarse[l] = (float)(base * (cp > 0 ? 1.0 - (double)cl / (double)cp : 1.0));
+        lt.kappa_fine[l] = (float)base;
+        lt.first[l + 1] = lt.first[l] + N[l] * cl;
+    }
+    const int64_t draws = lt.first[num_levels];
+    const int64_t per_pass = adj_pass_draws(m, p, budget);
+    for (int64_t g0 = 0; g0 < draws; g0 += per_pass) {
+        const int64_t E = (draws - g0) < per_pass ? (draws - g0) : per_pass;
+        const AdjPassLayout L = adj_pass_layout(E, m, p);
+        if (L.total > budget) return hipErrorInvalidValue;
+        uint32_t* kbuf[2] = {reinterpret_cast<uint32_t*>(buf + L.keys0), reinterpret_cast<uint32_t*>(buf + L.keys1)};
+        uint32_t* vbuf[2] = {reinterpret_cast<uint32_t*>(buf + L.vals0), reinterpret_cast<uint32_t*>(buf + L.vals1)};
+        uint32_t* counts = reinterpret_cast<uint32_t*>(buf + L.counts);
+        const int64_t nb = ceil_div(E, kSortBlock), tiles = ceil_div(E, kAdjRows);
+        int cur = 0;
+        {
+            ScopedTiming t(timer, 1);
+            AdjKeyParams kp;
+            kp.lt = lt;
+            kp.g0 = g0; kp.E = E; kp.n = (uint32_t)n;
+            kp.key0 = keys.key0; kp.key1 = keys.key1;
+            kp.cum = cum; kp.keys = kbuf[0]; kp.vals = vbuf[0];
+            hipLaunchKernelGGL(adj_keys_kernel, dim3((unsigned)ceil_div(E, 256)), dim3(256), 0, stream, kp);
+            for (int d = 0; d < digit_passes; ++d) {
+                hipLaunchKernelGGL(adj_radix_hist_kernel, dim3((unsigned)nb), dim3(kSortThreads), 0, stream,
+                                   kbuf[cur], E, 8 * d, counts, nb);
+                hipLaunchKernelGGL(adj_radix_scan_kernel, dim3(1), dim3(kSortScanThreads), 0, stream, counts,
+                                   (int64_t)kSortThreads * nb);
+                hipLaunchKernelGGL(adj_radix_scatter_kernel, dim3((unsigned)nb), dim3(kSortThreads), 0, stream,
+                                   kbuf[cur], vbuf[cur], kbuf[cur ^ 1], vbuf[cur ^ 1], E, 8 * d, counts, nb);
+                cur ^= 1;
+            }
             AdjGatherParams g;
-            g.m = m; g.p = p; g.n = (uint32_t)n; g.c = (uint32_t)cl; g.c_prev = (uint32_t)cp; g.kpad = kpad;
+            g.lt = lt;
+            g.m = m; g.p = p; g.g0 = g0; g.E = E;
+            g.kca = dims.kca; g.kcb = dims.kcb; g.ma = dims.ma; g.pa = dims.pa;
+            g.n = (uint32_t)n;
             g.key0 = keys.key0; g.key1 = keys.key1;
-            const uint32_t lf = shared ? 0xFFu : (uint32_t)l;
-            g.sid_index = stream_id(kTagIndex, lf, keys.problem);
-            g.sid_value = stream_id(kTagValue, lf, keys.problem);
-            g.k_first = (uint32_t)b0;
             g.A = A; g.B = B;
-            g.AT = AT; g.BT = BT; g.ZS = ZS; g.WS = WS; g.R = Rr;
-            g.ASb = ASb; g.BSb = BSb; g.mk = mk; g.pk = pk;
-            g.cum = cum;
+            g.keys = kbuf[cur]; g.vals = vbuf[cur];
+            g.iw = index_weights; g.cum = cum;
+            g.VA = buf + L.VA; g.VB = buf + L.VB;
+            g.ZA = reinterpret_cast<float*>(buf + L.ZA); g.ZB = reinterpret_cast<float*>(buf + L.ZB);
+            g.kap = reinterpret_cast<float*>(buf + L.kap);
             g.value16 = value16;
-            {
-                ScopedTiming t(timer, 1);
-                const dim3 grid((unsigned)(kpad / kAdjPositions), (unsigned)S);
-                if (bf16) hipLaunchKernelGGL(adjoint_gather_kernel<true>, grid, dim3(kAdjGatherThreads), 0, stream, g);
-                else hipLaunchKernelGGL(adjoint_gather_kernel<false>, grid, dim3(kAdjGatherThreads), 0, stream, g);
-            }
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-            if (bf16) {
-                AdjBf16Params a;
-                a.m = m; a.p = p; a.kpad = kpad; a.mk = mk; a.pk = pk; a.c_prev = (uint32_t)cp;
-                a.stride = stride && cp > 0 ? (uint32_t)(cl / cp) : 0u;
-                a.kappa_coarse = kc; a.kappa_fine = kf;
-                a.Gb = Gb; a.GTb = GTb; a.ASb = ASb; a.BSb = BSb; a.ZS = ZS; a.WS = WS; a.R = Rr;
-                a.tiles_t = ceil_div(kpad, kAdjTileT);
-                a.tiles_u_cols = ceil_div(m, kAdjTileX);
-                a.tiles_v_cols = ceil_div(p, kAdjTileX);
-                a.dMA = dMA; a.dSA = dSA; a.dMB = dMB; a.dSB = dSB;
-                a.iw = index_weights; a.cum = cum; a.n = (uint32_t)n;
-                const int64_t tiles = a.tiles_t * (a.tiles_u_cols + a.tiles_v_cols);
-                {
-                    ScopedTiming t(timer, 0);
-                    hipLaunchKernelGGL(adjoint_mfma_bf16_kernel, dim3((unsigned)tiles, (unsigned)S), dim3(kAdjThreads),
-                                       0, stream, a);
-                }
-                if ((e = hipGetLastError()) != hipSuccess) return e;
-                continue;
-            }
-            AdjMfmaParams a;
-            a.m = m; a.p = p; a.kpad = kpad; a.c_prev = (uint32_t)cp;
-            a.stride = stride && cp > 0 ? (uint32_t)(cl / cp) : 0u;
-            a.kappa_coarse = kc; a.kappa_fine = kf;
-            a.GT = GT; a.G = G; a.AT = AT; a.BT = BT; a.ZS = ZS; a.WS = WS; a.R = Rr;
-            a.tiles_t = ceil_div(kpad, kAdjTileT);
-            a.tiles_u_cols = ceil_div(m, kAdjTileX);
-            a.tiles_v_cols = ceil_div(p, kAdjTileX);
-            a.dMA = dMA; a.dSA = dSA; a.dMB = dMB; a.dSB = dSB;
-            a.iw = index_weights; a.cum = cum; a.n = (uint32_t)n;
-            const int64_t tiles = a.tiles_t * (a.tiles_u_cols + a.tiles_v_cols);
-            {
-                ScopedTiming t(timer, 0);
-                hipLaunchKernelGGL(adjoint_mfma_kernel, dim3((unsigned)tiles, (unsigned)S), dim3(kAdjThreads), 0,
-                                   stream, a);
-            }
-            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if (bf16) hipLaunchKernelGGL(adj_gather_kernel<true>, dim3((unsigned)tiles), dim3(kAdjThreads), 0, stream, g);
+            else hipLaunchKernelGGL(adj_gather_kernel<false>, dim3((unsigned)tiles), dim3(kAdjThreads), 0, stream, g);
         }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        AdjTileParams a;
+        a.m = m; a.p = p; a.E = E; a.kca = dims.kca; a.kcb = dims.kcb; a.ma = dims.ma; a.pa = dims.pa;
+        a.xpad_m = dims.xpad_m; a.xpad_p = dims.xpad_p;
+        a.XU = xo.XU; a.XV = xo.XV;
+        a.VA = buf + L.VA; a.VB = buf + L.VB;
+        a.ZA = reinterpret_cast<const float*>(buf + L.ZA); a.ZB = reinterpret_cast<const float*>(buf + L.ZB);
+        a.kap = reinterpret_cast<const float*>(buf + L.kap);
+        a.keys = kbuf[cur];
+        a.tiles = tiles;
+        a.tiles_u = ceil_div(m, kAdjCols);
+        a.tiles_v = ceil_div(p, kAdjCols);
+        a.dMA = dMA; a.dSA = dSA; a.lda = A.ld;
+        a.dMB = dMB; a.dSB = dSB; a.ldb = B.ld;
+        a.carry = reinterpret_cast<float*>(buf + L.carry);
+        {
+            ScopedTiming t(timer, 0);
+            const dim3 grid((unsigned)(tiles * (a.tiles_u + a.tiles_v)));
+            if (bf16) hipLaunchKernelGGL(adj_tile_kernel<true>, grid, dim3(kAdjThreads), 0, stream, a);
+            else hipLaunchKernelGGL(adj_tile_kernel<false>, grid, dim3(kAdjThreads), 0, stream, a);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        AdjFixParams f;
+        f.m = m; f.p = p; f.E = E; f.keys = kbuf[cur];
+        f.carry = reinterpret_cast<const float*>(buf + L.carry);
+        f.dMA = dMA; f.dSA = dSA; f.lda = A.ld;
+        f.dMB = dMB; f.dSB = dSB; f.ldb = B.ld;
+        {
+            ScopedTiming t(timer, 2);
+            hipLaunchKernelGGL(adj_fixup_kernel, dim3((unsigned)tiles), dim3(kAdjThreads), 0, stream, f);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
 }

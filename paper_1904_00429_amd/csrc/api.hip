@@ -850,7 +850,8 @@ mlmc_status mlmc_graph_destroy(mlmc_graph graph)
 size_t mlmc_matmul_adjoint_workspace_size(int64_t m, int64_t n, int64_t p, const mlmc_levels* levels)
 {
     if (check_levels(levels, false) != MLMC_OK || m < 1 || p < 1 || n < 1) return 0;
-    return adjoint_workspace_size(m, n, p, levels->num_levels, levels->c, levels->index_weights != nullptr);
+    return adjoint_workspace_size(m, n, p, levels->num_levels, levels->c, levels->n_samples,
+                                  levels->index_weights != nullptr);
 }
 
 mlmc_status mlmc_matmul_adjoint_reparam(int64_t m, int64_t n, int64_t p, const mlmc_dist* A, const mlmc_dist* B,
@@ -873,7 +874,8 @@ mlmc_status mlmc_matmul_adjoint_reparam(int64_t m, int64_t n, int64_t p, const m
     if (A->law != MLMC_LAW_REPARAM || B->law != MLMC_LAW_REPARAM)
         return fail(MLMC_EINVAL, "the adjoint is defined for reparameterised laws");
     if (!grad_out || !dMA || !dSA || !dMB || !dSB) return fail(MLMC_EINVAL, "null gradient pointer");
-    const size_t need = adjoint_workspace_size(m, n, p, lv->num_levels, lv->c, lv->index_weights != nullptr);
+    const size_t need =
+        adjoint_workspace_size(m, n, p, lv->num_levels, lv->c, lv->n_samples, lv->index_weights != nullptr);
     if (!workspace || workspace_bytes < need) return fail(MLMC_EWORKSPACE, "workspace needs %zu bytes", need);
     hipStream_t stream = static_cast<hipStream_t>(stream_ptr);
     KernelTimer timer_obj(stream);

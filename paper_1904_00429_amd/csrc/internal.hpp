@@ -247,7 +247,9 @@ double* matmul_norm_ptr(const MatmulPlan& plan, char* ws);
 hipError_t fill_doubles(double* p, int64_t count, double v, hipStream_t stream);
 
 // ---- adjoint of the matrix estimator (reparameterised laws) ---------------
-size_t adjoint_workspace_size(int64_t m, int64_t n, int64_t p, int num_levels, const int64_t* c, bool weighted);
+// N: the forward's N_l (NULL: the largest size any N_l can need)
+size_t adjoint_workspace_size(int64_t m, int64_t n, int64_t p, int num_levels, const int64_t* c, const int64_t* N,
+                              bool weighted);
 hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law& B, int num_levels,
                        const int64_t* c, const int64_t* N, const StreamKeys& keys, bool shared,
                        const double* grad, float* dMA, float* dSA, float* dMB, float* dSB,
