@@ -469,6 +469,7 @@ struct AdjSegments {
     int cont;                     // the last segment continues into the next tile
     uint8_t fin[kAdjRows];
     int nfin;
+    float part[kAdjCols];         // the walk's upper-half share of a segment across rows 31 | 32
 };
 
 __device__ __forceinline__ void adj_load_keys(const AdjTileParams& prm, int64_t T, AdjSegments& sg)
@@ -517,13 +518,17 @@ struct AdjRows {
 
 // The accumulators (lane l, register r of block bj: row 8(r/4) + 4(l/32) + r%4,
 // column 32 bj + l%32 of the wave's block) times kappa_t (dM), then times
-// kappa_t z_t (dS), each in turn through LDS: 128 threads walk their column
-// down the rows in draw order and leave each segment's sum in the row that
-// closes it (or in its carry slot); then all threads add the finished sums
-// into the gradient rows, kAdjBatch independent read-modify-writes at a time.
+// kappa_t z_t (dS), each in turn through LDS.  The walk down the rows is
+// split in two halves, rows 0 .. 31 and 32 .. 63, each walked by 128 threads
+// (one per column): a segment that runs across row 31 | 32 is finished from
+// the two halves' partial sums (upper + lower) after a barrier.  A finished
+// segment's sum is left in the row that closes it (or in its carry slot);
+// then all threads add the finished sums into the gradient rows, kAdjBatch
+// independent read-modify-writes at a time.
 __device__ __forceinline__ void adj_epilogue(const AdjTileParams& prm, const AdjTileShape& sh, const f32x16 (&acc)[2],
                                              const AdjRows& sv, AdjSegments& sg)
 {
+    constexpr int H = kAdjRows / 2;
     const int lane = threadIdx.x % kWave;
     const int64_t r0 = sh.T * kAdjRows;
     const int64_t left = prm.E - r0;
@@ -533,46 +538,60 @@ __device__ __forceinline__ void adj_epilogue(const AdjTileParams& prm, const Adj
     const int64_t zs = sh.is_u ? prm.ma : prm.pa;
     const int64_t ld = sh.is_u ? prm.lda : prm.ldb;
     const int64_t cw = prm.m + prm.p;
+    const bool lower = threadIdx.x >= kAdjCols;            // walks rows H .. rows - 1
+    const int xl = threadIdx.x % kAdjCols, x = sh.xb + xl;
+    const int64_t ccol = (sh.is_u ? 0 : prm.m) + x;
     for (int which = 0; which < 2; ++which) {
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) {
-            const int xl = sh.wx + bj * 32 + lane % 32;
-            const int x = sh.xb + xl;
+            const int xw = sh.wx + bj * 32 + lane % 32;
+            const int xg = sh.xb + xw;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int t = sh.wt + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
-                const bool ok = r0 + t < prm.E && x < sh.X;
+                const bool ok = r0 + t < prm.E && xg < sh.X;
                 const float v = sg.kap[t] * acc[bj][r];
-                sv.row(t)[xl] = (which && ok) ? v * Z[(r0 + t) * zs + x] : v;
+                sv.row(t)[xw] = (which && ok) ? v * Z[(r0 + t) * zs + xg] : v;
             }
         }
         __syncthreads();
-        // the walk: the running sum in row order; the segment ends are the
-        // same for every column (uniform branches)
-        if (threadIdx.x < kAdjCols) {
-            const int xl = threadIdx.x, x = sh.xb + xl;
-            if (x < sh.X) {
-                const int64_t ccol = (sh.is_u ? 0 : prm.m) + x;
-                const uint64_t ends = sg.ends;
-                float sum = 0.0f;
-                bool first = true;
+        // segment ends are the same for every column (uniform branches)
+        const uint64_t ends = sg.ends;
+        const bool span = rows > H && !((ends >> (H - 1)) & 1ull);   // a segment runs across H - 1 | H
+        const bool span_began = span && sg.began && (ends & ((1ull << H) - 1ull)) == 0ull;
+        float held = 0.0f;                                 // the lower half's share of that segment
+        int held_row = -1;
+        auto finish = [&](int r, float sum, bool began) {
+            const bool cont = r == rows - 1 && sg.cont;
+            if (began || cont)
+                prm.carry[((sh.T * 2 + (began ? 0 : 1)) * 2 + which) * cw + ccol] = sum;
+            else
+                sv.row(r)[xl] = sum;
+        };
+        if (x < sh.X) {
+            const int r_begin = lower ? H : 0;
+            const int r_end = lower ? rows : (rows < H ? rows : H);
+            float sum = 0.0f;
+            bool first = true;
 #pragma unroll 1
-                for (int r = 0; r < rows; ++r) {
-                    float* cell = sv.row(r) + xl;
-                    sum += *cell;
-                    if ((ends >> r) & 1ull) {
-                        const bool began = first && sg.began;
-                        const bool cont = r == rows - 1 && sg.cont;
-                        if (began || cont)
-                            prm.carry[((sh.T * 2 + (began ? 0 : 1)) * 2 + which) * cw + ccol] = sum;
-                        else
-                            *cell = sum;
-                        sum = 0.0f;
-                        first = false;
+            for (int r = r_begin; r < r_end; ++r) {
+                float* cell = sv.row(r) + xl;
+                sum += *cell;
+                if ((ends >> r) & 1ull) {
+                    if (lower && first && span) {
+                        held = sum;
+                        held_row = r;
+                    } else {
+                        finish(r, sum, first && (lower ? false : sg.began));
                     }
+                    sum = 0.0f;
+                    first = false;
                 }
             }
+            if (!lower && span) sg.part[xl] = sum;        // the upper half's share
         }
+        __syncthreads();
+        if (lower && x < sh.X && held_row >= 0) finish(held_row, sg.part[xl] + held, span_began);
         __syncthreads();
         float* grad = sh.is_u ? (which ? prm.dSA : prm.dMA) : (which ? prm.dSB : prm.dMB);
         const int items = sg.nfin * kAdjCols;
