@@ -229,7 +229,6 @@ struct AdjGatherParams {
     AdjLevelTable lt;
     int64_t m, p, g0, E;
     int64_t kca, kcb;             // K of the two operand blocks: m and p rounded up to kAdjKc
-    int64_t ma, pa;               // row strides of the normals (m, p rounded up to 8)
     uint32_t n;
     uint32_t key0, key1;
     Law A, B;
@@ -239,11 +238,32 @@ struct AdjGatherParams {
     const uint64_t* cum;
     void* VA;                     // tiles x kca x 64: values of a_t (FP32, or BF16 in the same region)
     void* VB;                     // tiles x kcb x 64: values of b_t
-    float* ZA;                    // E x ma normals of a_t
-    float* ZB;                    // E x pa normals of b_t
     float* kap;                   // E
+    uint2* info;                  // E: (realisation, value stream) of each sorted draw
     bool value16;                 // the forward's values came from 16-bit uniforms
 };
+
+// Uniforms and normals of rows 4q .. 4q+3 of [a; b] for draw column j of
+// realisation k, as the forward generated them.
+__device__ __forceinline__ void adj_quad(bool value16, uint32_t q, uint32_t k, uint32_t j, uint32_t sid, uint32_t key0,
+                                         uint32_t key1, float (&u)[4], float (&z)[4])
+{
+    if (value16) {
+        // rows 4q .. 4q+3 are halves of words 2 (q & 1) and 2 (q & 1) + 1
+        // of the call for rows 8 (q / 2) .. 8 (q / 2) + 7
+        const Words4 w = philox4x32_10(q >> 1, k, j, sid, key0, key1);
+        const uint32_t a = (q & 1u) ? w.w2 : w.w0, b = (q & 1u) ? w.w3 : w.w1;
+        u[0] = unit16<float>(a & 0xFFFFu);
+        u[1] = unit16<float>(a >> 16);
+        u[2] = unit16<float>(b & 0xFFFFu);
+        u[3] = unit16<float>(b >> 16);
+        box_muller(u[0], u[1], z[0], z[1]);
+        box_muller(u[2], u[3], z[2], z[3]);
+    } else {
+        const Words4 w = philox4x32_10(q, k, j, sid, key0, key1);
+        quad_values<float>(w, true, u[0], u[1], u[2], u[3], z[0], z[1], z[2], z[3]);
+    }
+}
 
 // Element (k, row) of a tile block of K-extent kc.
 __device__ __forceinline__ int64_t adj_blk_f32(int64_t T, int64_t kc, int64_t k, int row)
@@ -288,6 +308,7 @@ __global__ __launch_bounds__(kAdjThreads) void adj_gather_kernel(AdjGatherParams
                                                                                      : prm.lt.kappa_fine[d.l];
             if (prm.iw) kappa *= (float)((double)prm.cum[prm.n - 1] / ((double)prm.n * (double)prm.iw[j]));
             prm.kap[e] = kappa;
+            prm.info[e] = make_uint2(k, sid);
         }
         cols[threadIdx.x] = j;
         reals[threadIdx.x] = k;
@@ -299,8 +320,6 @@ __global__ __launch_bounds__(kAdjThreads) void adj_gather_kernel(AdjGatherParams
         const int64_t K = part ? prm.p : m;               // rows of the operand
         const int64_t kc = part ? prm.kcb : prm.kca;      // its padded K
         const int64_t off = part ? m : 0;                 // its first row in [a; b]
-        float* Zp = part ? prm.ZB : prm.ZA;
-        const int64_t zs = part ? prm.pa : prm.ma;
         for (int64_t k0 = 0; k0 < kc; k0 += kAdjGatherBlock) {
             __syncthreads();                              // the tile is free (and the draw table written)
             // rows k0 .. k1 - 1 of the operand are real; the rest of the tile is zero
@@ -322,39 +341,14 @@ __global__ __launch_bounds__(kAdjThreads) void adj_gather_kernel(AdjGatherParams
                         if (r >= nvalid) break;
                         const uint32_t j = cols[r], kr = reals[r], sid = sids[r];
                         float u[4], z[4];
-                        if (prm.value16) {
-                            // rows 4q .. 4q+3 are halves of words 2 (q & 1) and 2 (q & 1) + 1
-                            // of the call for rows 8 (q / 2) .. 8 (q / 2) + 7
-                            const Words4 w = philox4x32_10((uint32_t)(q >> 1), kr, j, sid, prm.key0, prm.key1);
-                            const uint32_t a = (q & 1) ? w.w2 : w.w0, b = (q & 1) ? w.w3 : w.w1;
-                            u[0] = unit16<float>(a & 0xFFFFu);
-                            u[1] = unit16<float>(a >> 16);
-                            u[2] = unit16<float>(b & 0xFFFFu);
-                            u[3] = unit16<float>(b >> 16);
-                            box_muller(u[0], u[1], z[0], z[1]);
-                            box_muller(u[2], u[3], z[2], z[3]);
-                        } else {
-                            const Words4 w = philox4x32_10((uint32_t)q, kr, j, sid, prm.key0, prm.key1);
-                            quad_values<float>(w, true, u[0], u[1], u[2], u[3], z[0], z[1], z[2], z[3]);
-                        }
+                        adj_quad(prm.value16, (uint32_t)q, kr, j, sid, prm.key0, prm.key1, u, z);
                         // the quad's rows that lie in this block of this operand
-                        const int64_t dr = e_first + r;
-                        const bool whole = e0 >= off + k0 && e0 + 3 < off + k1 && ((e0 - off) & 3) == 0;
-                        if (whole) {
-                            const int64_t k = e0 - off;
-                            const Law& law = part ? prm.B : prm.A;
-                            for (int i2 = 0; i2 < 4; ++i2)
-                                tile[k - k0 + i2][r] = law_value<float>(law, z[i2], u[i2], (int64_t)j * law.ld + k + i2);
-                            *reinterpret_cast<float4*>(Zp + dr * zs + k) = make_float4(z[0], z[1], z[2], z[3]);
-                        } else {
-                            for (int i2 = 0; i2 < 4; ++i2) {
-                                const int64_t e = e0 + i2;
-                                if (e < off + k0 || e >= off + k1 || e >= rows) continue;
-                                const int64_t k = e - off;
-                                const Law& law = part ? prm.B : prm.A;
-                                tile[k - k0][r] = law_value<float>(law, z[i2], u[i2], (int64_t)j * law.ld + k);
-                                Zp[dr * zs + k] = z[i2];
-                            }
+                        const Law& law = part ? prm.B : prm.A;
+                        for (int i2 = 0; i2 < 4; ++i2) {
+                            const int64_t e = e0 + i2;
+                            if (e < off + k0 || e >= off + k1 || e >= rows) continue;
+                            const int64_t k = e - off;
+                            tile[k - k0][r] = law_value<float>(law, z[i2], u[i2], (int64_t)j * law.ld + k);
                         }
                     }
                 }
@@ -389,16 +383,16 @@ typedef __attribute__((address_space(3))) void* AdjLdsPtr;
 struct AdjTileParams {
     int64_t m, p, E;
     int64_t kca, kcb;             // K extents of the t operand blocks (of a_t and of b_t)
-    int64_t ma, pa;               // row strides of the normals
     int64_t xpad_m, xpad_p;       // m, p rounded up to 128
     const void* XU;               // x operand of U = B_S G^T: FP32 [kcb][xpad_m] (G^T), BF16 blocked
     const void* XV;               // x operand of V = A_S^T G: FP32 [kca][xpad_p] (G), BF16 blocked
     const void* VA;               // t operand of V (values of a_t), tile-blocked
     const void* VB;               // t operand of U (values of b_t)
-    const float* ZA;
-    const float* ZB;
     const float* kap;
+    const uint2* info;            // (realisation, value stream) of each sorted draw
     const uint32_t* keys;
+    uint32_t key0, key1;
+    bool value16;
     int64_t tiles;                // row tiles (64 sorted draws each)
     int64_t tiles_u, tiles_v;     // column tiles of U; those of V follow
     float* dMA; float* dSA; int64_t lda;
@@ -464,6 +458,7 @@ __device__ __forceinline__ AdjTileShape adj_shape(const AdjTileParams& prm)
 struct AdjSegments {
     uint32_t skey[kAdjRows + 2];
     float kap[kAdjRows];          // kappa_t of the tile's rows (0 past the end)
+    uint2 info[kAdjRows];         // (realisation, value stream) of the tile's rows
     uint64_t ends;                // bit r: row r closes a segment
     int began;                    // the first segment began in an earlier tile
     int cont;                     // the last segment continues into the next tile
@@ -482,6 +477,7 @@ __device__ __forceinline__ void adj_load_keys(const AdjTileParams& prm, int64_t 
     if (threadIdx.x < kAdjRows) {
         const int64_t e = r0 + threadIdx.x;
         sg.kap[threadIdx.x] = e < prm.E ? prm.kap[e] : 0.0f;
+        sg.info[threadIdx.x] = e < prm.E ? prm.info[e] : make_uint2(0u, 0u);
     }
 }
 
@@ -534,8 +530,6 @@ __device__ __forceinline__ void adj_epilogue(const AdjTileParams& prm, const Adj
     const int64_t left = prm.E - r0;
     const int rows = left < kAdjRows ? (int)left : kAdjRows;
     if (threadIdx.x == 0) adj_segments(sg, rows);
-    const float* Z = sh.is_u ? prm.ZA : prm.ZB;
-    const int64_t zs = sh.is_u ? prm.ma : prm.pa;
     const int64_t ld = sh.is_u ? prm.lda : prm.ldb;
     const int64_t cw = prm.m + prm.p;
     const bool lower = threadIdx.x >= kAdjCols;            // walks rows H .. rows - 1
@@ -545,16 +539,35 @@ __device__ __forceinline__ void adj_epilogue(const AdjTileParams& prm, const Adj
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) {
             const int xw = sh.wx + bj * 32 + lane % 32;
-            const int xg = sh.xb + xw;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int t = sh.wt + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
-                const bool ok = r0 + t < prm.E && xg < sh.X;
-                const float v = sg.kap[t] * acc[bj][r];
-                sv.row(t)[xw] = (which && ok) ? v * Z[(r0 + t) * zs + xg] : v;
+                sv.row(t)[xw] = sg.kap[t] * acc[bj][r];
             }
         }
         __syncthreads();
+        if (which) {
+            // the normals of the tile's columns, regenerated from the draws'
+            // streams (one Philox quad of rows per item), multiply in place
+            const int64_t off = sh.is_u ? 0 : prm.m;        // the columns' first row in [a; b]
+            const int x_end = sh.xb + kAdjCols < sh.X ? sh.xb + kAdjCols : sh.X;
+            const int64_t q_lo = (off + sh.xb) / 4, q_hi = (off + x_end - 1) / 4;
+            const int nq = (int)(q_hi - q_lo + 1);
+            for (int item = threadIdx.x; item < rows * nq; item += kAdjThreads) {
+                const int t = item / nq;
+                const int64_t q = q_lo + item % nq;
+                const uint2 inf = sg.info[t];
+                float u[4], z[4];
+                adj_quad(prm.value16, (uint32_t)q, inf.x, sg.skey[t + 1], inf.y, prm.key0, prm.key1, u, z);
+                float* row = sv.row(t);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int64_t c = 4 * q + i - off;            // gradient column
+                    if (c >= sh.xb && c < x_end) row[c - sh.xb] *= z[i];
+                }
+            }
+            __syncthreads();
+        }
         // segment ends are the same for every column (uniform branches)
         const uint64_t ends = sg.ends;
         const bool span = rows > H && !((ends >> (H - 1)) & 1ull);   // a segment runs across H - 1 | H
@@ -827,7 +840,7 @@ __global__ __launch_bounds__(256) void adj_x_operands_kernel(AdjXOperands o)
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct AdjDims {
-    int64_t kca, kcb, ma, pa, xpad_m, xpad_p;
+    int64_t kca, kcb, xpad_m, xpad_p;
 };
 
 static AdjDims adj_dims(int64_t m, int64_t p)
@@ -835,8 +848,6 @@ static AdjDims adj_dims(int64_t m, int64_t p)
     AdjDims d;
     d.kca = round_up_adj(m, kAdjKc);
     d.kcb = round_up_adj(p, kAdjKc);
-    d.ma = round_up_adj(m, 8);
-    d.pa = round_up_adj(p, 8);
     d.xpad_m = round_up_adj(m, kAdjCols);
     d.xpad_p = round_up_adj(p, kAdjCols);
     return d;
@@ -851,7 +862,7 @@ static size_t adj_head_bytes(int64_t m, int64_t p)
 
 // The buffers of a pass of E draws (values sized for FP32, which BF16 halves).
 struct AdjPassLayout {
-    size_t keys0, vals0, keys1, vals1, counts, VA, VB, ZA, ZB, kap, carry, total;
+    size_t keys0, vals0, keys1, vals1, counts, VA, VB, info, kap, carry, total;
 };
 
 static AdjPassLayout adj_pass_layout(int64_t E, int64_t m, int64_t p)
@@ -868,8 +879,7 @@ static AdjPassLayout adj_pass_layout(int64_t E, int64_t m, int64_t p)
     L.counts = take(4 * (size_t)kSortThreads * (size_t)nb);
     L.VA = take(4 * (size_t)(tiles * kAdjRows * d.kca));
     L.VB = take(4 * (size_t)(tiles * kAdjRows * d.kcb));
-    L.ZA = take(4 * (size_t)(E * d.ma));
-    L.ZB = take(4 * (size_t)(E * d.pa));
+    L.info = take(8 * (size_t)E);
     L.kap = take(4 * (size_t)E);
     L.carry = take(4 * (size_t)(tiles * 4 * (m + p)));
     L.total = off;
@@ -998,14 +1008,14 @@ hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law&
             AdjGatherParams g;
             g.lt = lt;
             g.m = m; g.p = p; g.g0 = g0; g.E = E;
-            g.kca = dims.kca; g.kcb = dims.kcb; g.ma = dims.ma; g.pa = dims.pa;
+            g.kca = dims.kca; g.kcb = dims.kcb;
             g.n = (uint32_t)n;
             g.key0 = keys.key0; g.key1 = keys.key1;
             g.A = A; g.B = B;
             g.keys = kbuf[cur]; g.vals = vbuf[cur];
             g.iw = index_weights; g.cum = cum;
             g.VA = buf + L.VA; g.VB = buf + L.VB;
-            g.ZA = reinterpret_cast<float*>(buf + L.ZA); g.ZB = reinterpret_cast<float*>(buf + L.ZB);
+            g.info = reinterpret_cast<uint2*>(buf + L.info);
             g.kap = reinterpret_cast<float*>(buf + L.kap);
             g.value16 = value16;
             if (bf16) hipLaunchKernelGGL(adj_gather_kernel<true>, dim3((unsigned)tiles), dim3(kAdjThreads), 0, stream, g);
@@ -1013,11 +1023,12 @@ hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law&
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         AdjTileParams a;
-        a.m = m; a.p = p; a.E = E; a.kca = dims.kca; a.kcb = dims.kcb; a.ma = dims.ma; a.pa = dims.pa;
+        a.m = m; a.p = p; a.E = E; a.kca = dims.kca; a.kcb = dims.kcb;
         a.xpad_m = dims.xpad_m; a.xpad_p = dims.xpad_p;
         a.XU = xo.XU; a.XV = xo.XV;
         a.VA = buf + L.VA; a.VB = buf + L.VB;
-        a.ZA = reinterpret_cast<const float*>(buf + L.ZA); a.ZB = reinterpret_cast<const float*>(buf + L.ZB);
+        a.info = reinterpret_cast<const uint2*>(buf + L.info);
+        a.key0 = keys.key0; a.key1 = keys.key1; a.value16 = value16;
         a.kap = reinterpret_cast<const float*>(buf + L.kap);
         a.keys = kbuf[cur];
         a.tiles = tiles;
