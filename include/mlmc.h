@@ -358,8 +358,11 @@ mlmc_status mlmc_graph_destroy(mlmc_graph graph);
  * Workspace (mlmc_matmul_adjoint_workspace_size, with the same levels,
  * n_samples included): G in the contraction's layouts plus the buffers of
  * one pass of draws (the draws of all levels are taken in passes of as many
- * as fit): room for every draw of the call, capped at 4 GiB (about 0.5 M
- * draws of a 512 x 512 problem).
+ * as fit): room for every draw of the call, capped at 4 GiB (about 0.95 M
+ * draws of a 512 x 512 problem).  A smaller workspace also works, down to
+ * the buffers of a 64-draw pass (more passes; EWORKSPACE below that, the
+ * message giving both sizes); the summation order, and so the last bits,
+ * follow the passes.
  * Errors: EINVAL (laws not reparameterised, target mode, f other than the
  * identity, precision other than FP32/BF16, null pointers, and the
  * conditions of mlmc_matmul_estimate), EWORKSPACE, EDEVICE. */

@@ -886,15 +886,17 @@ static AdjPassLayout adj_pass_layout(int64_t E, int64_t m, int64_t p)
     return L;
 }
 
-// Draws per pass: the most whose buffers fit the budget (at least 64), with
-// at most 2^30 draws and a tile grid below 2^31 workgroups.
-static int64_t adj_pass_draws(int64_t m, int64_t p, size_t budget)
+// Draws per pass: all of them when their buffers fit the budget, else the
+// most that fit (at least 64); at most 2^30 draws and a tile grid below 2^31
+// workgroups.
+static int64_t adj_pass_draws(int64_t m, int64_t p, size_t budget, int64_t draws)
 {
-    const size_t per = adj_pass_layout(kAdjRows, m, p).total / kAdjRows + 1;
-    int64_t E = (int64_t)(budget / per);
     const int64_t xt = ceil_div(m, kAdjCols) + ceil_div(p, kAdjCols);
     int64_t cap = ((1ll << 31) - 1) / xt * kAdjRows;
     if (cap > (1ll << 30)) cap = 1ll << 30;
+    if (draws <= cap && adj_pass_layout(draws, m, p).total <= budget) return draws;
+    const size_t per = adj_pass_layout(kAdjRows, m, p).total / kAdjRows + 1;
+    int64_t E = (int64_t)(budget / per);
     if (E > cap) E = cap;
     E = E / kAdjRows * kAdjRows;
     if (E < kAdjRows) E = kAdjRows;
@@ -925,6 +927,13 @@ size_t adjoint_workspace_size(int64_t m, int64_t n, int64_t p, int num_levels, c
     return total;
 }
 
+size_t adjoint_workspace_min(int64_t m, int64_t n, int64_t p, bool weighted)
+{
+    size_t total = adj_pass_layout(kAdjRows, m, p).total + adj_head_bytes(m, p);
+    if (weighted) total += align256((size_t)n * sizeof(uint64_t));
+    return total;
+}
+
 hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law& B, int num_levels,
                        const int64_t* c, const int64_t* N, const StreamKeys& keys, bool shared,
                        const double* grad, float* dMA, float* dSA, float* dMB, float* dSB,
@@ -942,8 +951,11 @@ hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law&
     uint64_t* cum = index_weights ? reinterpret_cast<uint64_t*>(ws + head) : nullptr;
     const size_t cum_bytes = index_weights ? align256((size_t)n * sizeof(uint64_t)) : 0;
     char* buf = ws + head + cum_bytes;
-    const size_t budget = adj_budget(m, p, num_levels, c, N);
-    if (head + cum_bytes + budget > ws_bytes) return hipErrorInvalidValue;
+    // the pass buffers: what the workspace holds, up to what all draws need
+    if (head + cum_bytes + adj_pass_layout(kAdjRows, m, p).total > ws_bytes) return hipErrorInvalidValue;
+    size_t budget = ws_bytes - head - cum_bytes;
+    const size_t want = adj_budget(m, p, num_levels, c, N);
+    if (budget > want) budget = want;
     {
         ScopedTiming t(timer, 3);
         const int64_t total = dims.kcb * dims.xpad_m + dims.kca * dims.xpad_p;
@@ -978,7 +990,7 @@ hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law&
         lt.first[l + 1] = lt.first[l] + N[l] * cl;
     }
     const int64_t draws = lt.first[num_levels];
-    const int64_t per_pass = adj_pass_draws(m, p, budget);
+    const int64_t per_pass = adj_pass_draws(m, p, budget, draws);
     for (int64_t g0 = 0; g0 < draws; g0 += per_pass) {
         const int64_t E = (draws - g0) < per_pass ? (draws - g0) : per_pass;
         const AdjPassLayout L = adj_pass_layout(E, m, p);

@@ -874,9 +874,12 @@ mlmc_status mlmc_matmul_adjoint_reparam(int64_t m, int64_t n, int64_t p, const m
     if (A->law != MLMC_LAW_REPARAM || B->law != MLMC_LAW_REPARAM)
         return fail(MLMC_EINVAL, "the adjoint is defined for reparameterised laws");
     if (!grad_out || !dMA || !dSA || !dMB || !dSB) return fail(MLMC_EINVAL, "null gradient pointer");
-    const size_t need =
-        adjoint_workspace_size(m, n, p, lv->num_levels, lv->c, lv->n_samples, lv->index_weights != nullptr);
-    if (!workspace || workspace_bytes < need) return fail(MLMC_EWORKSPACE, "workspace needs %zu bytes", need);
+    // any workspace from the least one up works (a smaller one takes more passes)
+    const size_t need = adjoint_workspace_min(m, n, p, lv->index_weights != nullptr);
+    if (!workspace || workspace_bytes < need)
+        return fail(MLMC_EWORKSPACE, "workspace needs at least %zu bytes (%zu for the fewest passes)", need,
+                    adjoint_workspace_size(m, n, p, lv->num_levels, lv->c, lv->n_samples,
+                                           lv->index_weights != nullptr));
     hipStream_t stream = static_cast<hipStream_t>(stream_ptr);
     KernelTimer timer_obj(stream);
     KernelTimer* timer = (lv->flags & MLMC_FLAG_TIMING) ? &timer_obj : nullptr;

@@ -250,6 +250,8 @@ hipError_t fill_doubles(double* p, int64_t count, double v, hipStream_t stream);
 // N: the forward's N_l (NULL: the largest size any N_l can need)
 size_t adjoint_workspace_size(int64_t m, int64_t n, int64_t p, int num_levels, const int64_t* c, const int64_t* N,
                               bool weighted);
+// The least workspace the adjoint runs with (passes of 64 draws).
+size_t adjoint_workspace_min(int64_t m, int64_t n, int64_t p, bool weighted);
 hipError_t adjoint_run(int64_t m, int64_t n, int64_t p, const Law& A, const Law& B, int num_levels,
                        const int64_t* c, const int64_t* N, const StreamKeys& keys, bool shared,
                        const double* grad, float* dMA, float* dSA, float* dMB, float* dSB,

@@ -339,11 +339,13 @@ def matmul_adjoint_reparam(MA: torch.Tensor, SA: torch.Tensor, MB: torch.Tensor,
                            seed: int = 0, problem: int = 0, shared: bool = False,
                            workspace: Optional[torch.Tensor] = None, prec: str = "fp32",
                            index_weights: Optional[torch.Tensor] = None, coupling: str = "prefix",
-                           value16: bool = False):
+                           value16: bool = False, max_workspace_bytes: Optional[int] = None):
     """Gradients of <grad_out, Y> with respect to M_A, S_A, M_B, S_B
     (mlmc_matmul_adjoint_reparam).  MA, SA: (n, m) FP32 device tensors (row j =
     column j of A); MB, SB: (n, p).  prec: "fp32" or "bf16" (BF16 operands
-    on MFMA, FP32 accumulation).  Returns (dMA, dSA, dMB, dSB), FP32."""
+    on MFMA, FP32 accumulation).  max_workspace_bytes: use at most this much
+    workspace (the draws then go in more passes).  Returns (dMA, dSA, dMB,
+    dSB), FP32."""
     n, m = MA.shape
     p = MB.shape[1]
     device = MA.device
@@ -353,6 +355,8 @@ def matmul_adjoint_reparam(MA: torch.Tensor, SA: torch.Tensor, MB: torch.Tensor,
     ws_bytes = int(lib().mlmc_matmul_adjoint_workspace_size(int(m), int(n), int(p), ctypes.byref(h.lv)))
     if ws_bytes == 0:
         raise MLMCError(1, "invalid problem: no workspace size")
+    if max_workspace_bytes is not None:
+        ws_bytes = min(ws_bytes, int(max_workspace_bytes))
     if workspace is None or workspace.numel() < ws_bytes:
         workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=device)
     g = grad_out.to(device=device, dtype=torch.float64).contiguous()

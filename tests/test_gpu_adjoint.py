@@ -287,3 +287,27 @@ def test_adjoint_is_deterministic(dev, prec):
     for name, x, y in zip(("dMA", "dSA", "dMB", "dSB"), a, b):
         assert torch.equal(x, y), name
         assert bool(torch.isfinite(x).all()), name
+
+
+@pytest.mark.parametrize("prec, tol", [("fp32", 1e-5), ("bf16", 1e-2)])
+def test_adjoint_small_workspace_many_passes(orc, dev, prec, tol):
+    """A workspace far below the one-pass size: the draws of all levels go in
+    passes of a few hundred, which cut through levels, realisations and
+    column segments; the gradients stay within the tolerance of the
+    reference, and agree with the one-pass call up to the summation order."""
+    from oracle import grad as og
+    from paper_1904_00429_amd import matmul_adjoint_reparam
+    m, n, p, c, N = 20, 5, 30, [8, 32, 128], [30, 12, 5]
+    flush(f"adjoint many passes {prec}")
+    params = _params(77, n, m, p)
+    G = np.random.default_rng(78).standard_normal((m, p))
+    dp = [torch.from_numpy(x).to(dev) for x in params]
+    one = [g.cpu().numpy() for g in matmul_adjoint_reparam(*dp, c, N, torch.from_numpy(G), seed=6, prec=prec)]
+    # about 300 draws per pass (G's two operand buffers, then 64-draw steps)
+    small = [g.cpu().numpy() for g in matmul_adjoint_reparam(*dp, c, N, torch.from_numpy(G), seed=6, prec=prec,
+                                                             max_workspace_bytes=400 << 10)]
+    _, ref = og.reparam_gradients(*params, c, N, G, seed=6)
+    for name, a, b, r in zip(("dMA", "dSA", "dMB", "dSB"), one, small, ref):
+        flush(f"  {name} one pass {rel_frob(a, r):.3g}, many passes {rel_frob(b, r):.3g}")
+        assert rel_frob(b, r) <= tol, name
+        assert rel_frob(b, a) <= (1e-6 if prec == "fp32" else 1e-3), name
