@@ -135,28 +135,35 @@ __global__ __launch_bounds__(kSortThreads) void adj_radix_hist_kernel(const uint
     counts[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
-// Exclusive prefix sum of the digit-major counts, in place (one workgroup).
+// Exclusive prefix sum of the digit-major counts, in place (one workgroup):
+// each wave takes a contiguous segment, sums it (coalesced), the waves'
+// totals give each segment's offset, and the wave scans its segment 64
+// entries at a time with lane shuffles.
 __global__ __launch_bounds__(kSortScanThreads) void adj_radix_scan_kernel(uint32_t* counts, int64_t len)
 {
-    __shared__ uint32_t part[kSortScanThreads];
-    const int64_t per = (len + kSortScanThreads - 1) / kSortScanThreads;
-    const int64_t b = (int64_t)threadIdx.x * per;
+    constexpr int W = kSortScanThreads / kWave;
+    __shared__ uint32_t wsum[W];
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const int64_t per = (len + W - 1) / W;
+    const int64_t b = (int64_t)wave * per;
     const int64_t e = b + per < len ? b + per : len;
     uint32_t s = 0u;
-    for (int64_t i = b; i < e; ++i) s += counts[i];
-    part[threadIdx.x] = s;
+    for (int64_t i = b + lane; i < e; i += kWave) s += counts[i];
+    for (int off = kWave / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) wsum[wave] = s;
     __syncthreads();
-    for (int off = 1; off < kSortScanThreads; off <<= 1) {
-        const uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
-    }
-    uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
-    for (int64_t i = b; i < e; ++i) {
-        const uint32_t c = counts[i];
-        counts[i] = run;
-        run += c;
+    uint32_t run = 0u;
+    for (int w = 0; w < wave; ++w) run += wsum[w];
+    for (int64_t base = b; base < e; base += kWave) {
+        const int64_t i = base + lane;
+        const uint32_t c = i < e ? counts[i] : 0u;
+        uint32_t x = c;                                    // inclusive scan over the 64 entries
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (i < e) counts[i] = run + x - c;
+        run += __shfl(x, kWave - 1);
     }
 }
 
@@ -316,6 +323,11 @@ __global__ __launch_bounds__(kAdjThreads) void adj_gather_kernel(AdjGatherParams
     }
     const int64_t m = prm.m, rows = prm.m + prm.p;
     const int ngroups = (nvalid + 3) / 4;                 // groups of four draws with a valid one
+    // reparameterised laws whose rows allow 16-byte loads of four means / scales
+    auto vec_law = [](const Law& l) {
+        return l.kind == 2 && (l.ld & 3) == 0 && ((uintptr_t)l.mean & 15) == 0 && ((uintptr_t)l.stdev & 15) == 0;
+    };
+    const bool vec_ms[2] = {vec_law(prm.A), vec_law(prm.B)};
     for (int part = 0; part < 2; ++part) {
         const int64_t K = part ? prm.p : m;               // rows of the operand
         const int64_t kc = part ? prm.kcb : prm.kca;      // its padded K
@@ -344,11 +356,24 @@ __global__ __launch_bounds__(kAdjThreads) void adj_gather_kernel(AdjGatherParams
                         adj_quad(prm.value16, (uint32_t)q, kr, j, sid, prm.key0, prm.key1, u, z);
                         // the quad's rows that lie in this block of this operand
                         const Law& law = part ? prm.B : prm.A;
-                        for (int i2 = 0; i2 < 4; ++i2) {
-                            const int64_t e = e0 + i2;
-                            if (e < off + k0 || e >= off + k1 || e >= rows) continue;
-                            const int64_t k = e - off;
-                            tile[k - k0][r] = law_value<float>(law, z[i2], u[i2], (int64_t)j * law.ld + k);
+                        const bool whole = e0 >= off + k0 && e0 + 3 < off + k1 && ((e0 - off) & 3) == 0;
+                        if (whole && vec_ms[part]) {
+                            // a whole aligned quad of a reparameterised law: the
+                            // four means and scales as two 16-byte loads
+                            const int64_t k = e0 - off, idx = (int64_t)j * law.ld + k;
+                            const float4 mu = *reinterpret_cast<const float4*>(law.mean + idx);
+                            const float4 sd = *reinterpret_cast<const float4*>(law.stdev + idx);
+                            tile[k - k0][r] = fmaf(sd.x, z[0], mu.x);
+                            tile[k - k0 + 1][r] = fmaf(sd.y, z[1], mu.y);
+                            tile[k - k0 + 2][r] = fmaf(sd.z, z[2], mu.z);
+                            tile[k - k0 + 3][r] = fmaf(sd.w, z[3], mu.w);
+                        } else {
+                            for (int i2 = 0; i2 < 4; ++i2) {
+                                const int64_t e = e0 + i2;
+                                if (e < off + k0 || e >= off + k1 || e >= rows) continue;
+                                const int64_t k = e - off;
+                                tile[k - k0][r] = law_value<float>(law, z[i2], u[i2], (int64_t)j * law.ld + k);
+                            }
                         }
                     }
                 }
