@@ -743,8 +743,9 @@ __global__ __launch_bounds__(kAdjThreads) void adj_tile_kernel(AdjTileParams prm
     // exactly the loads of the two chunks after it are younger: vmcnt counts
     // the outstanding loads in issue order.
     auto wait_chunk = [&]() {
-        // s_waitcnt: vmcnt in bits 3:0 (and 15:14), expcnt 6:4 and lgkmcnt 11:8 left at their maxima
-        __builtin_amdgcn_s_waitcnt(0x0F70 | (2 * kLoads));
+        // s_waitcnt: vmcnt in bits 3:0 (and 15:14), lgkmcnt 11:8 at 0 (this
+        // wave's fragment reads are done), expcnt 6:4 left at its maximum
+        __builtin_amdgcn_s_waitcnt(0x0070 | (2 * kLoads));
     };
     // The stage handover needs only the workgroup barrier: each wave has
     // waited for its own loads of the chunk (vmcnt), and the LDS reads of the
