@@ -355,3 +355,36 @@ def test_set_form_and_single_launch_workspace(L):
     assert L.mlmc_matmul_batched_workspace_size(2, arr, ctypes.byref(lv), ctypes.byref(t)) == plain64
     t.single_launch = 2
     assert L.mlmc_matmul_batched_workspace_size(2, arr, ctypes.byref(lv), ctypes.byref(t)) == 0
+
+
+def test_adjoint_workspace_follows_the_draws(L):
+    # room for every draw of the call (one pass), so the size grows with N_l,
+    # up to 4 GiB of pass buffers (plus G's two operand buffers)
+    sizes = []
+    for N in ([4, 4], [40, 40], [4000, 4000]):
+        lv, keep = _levels([32, 64], N, prec=1)
+        sizes.append(L.mlmc_matmul_adjoint_workspace_size(512, 32768, 512, ctypes.byref(lv)))
+    assert 0 < sizes[0] < sizes[1] < sizes[2]
+    # the differentiation workload (917504 draws) fits one pass; ten and a
+    # hundred times its N_l are capped
+    c = [32 * 2 ** l for l in range(7)]
+    caps = []
+    for scale in (1, 10, 100):
+        lv, keep = _levels(c, [scale * (4096 >> l) for l in range(7)], prec=1)
+        caps.append(L.mlmc_matmul_adjoint_workspace_size(512, 32768, 512, ctypes.byref(lv)))
+    assert caps[0] < caps[1] == caps[2]
+    assert (4 << 30) < caps[1] < (4 << 30) + (8 << 20)
+
+
+def test_adjoint_workspace_below_one_pass_rejected(L):
+    # any workspace from one 64-draw pass up is taken (more passes); below
+    # that EWORKSPACE, with both sizes in the message, before any device call
+    lv, keep = _levels([2, 4], [4, 4], prec=1)
+    A, B = _dist(2), _dist(2)
+    A.mean = A.stdev = B.mean = B.stdev = 16
+    A.ld, B.ld = 4, 3
+    st = L.mlmc_matmul_adjoint_reparam(4, 16, 3, ctypes.byref(A), ctypes.byref(B), ctypes.byref(lv), 16, 16, 16,
+                                       16, 16, 16, 4096, None)
+    assert st == 4
+    msg = L.mlmc_last_error()
+    assert b"at least" in msg and b"fewest passes" in msg
