@@ -290,14 +290,15 @@ typedef struct {
  * package): tile = workgroup output tile edge (64 or 128; FP64 uses 64),
  * target_blocks = sketch work items per pass, gather_budget = bytes of
  * gathered operands per pass.  single_launch = 1: the whole estimate (every
- * pass of every level) in one persistent kernel, whose phase p gathers pass p
- * while it sketches pass p - 1, its work claimed from per-XCD queues (sketch
- * tiles first, then gather chunks) and its phases ended by bounded grid-wide
- * barriers; built for FP32, BF16 and FP8 operands, i.i.d. normal or uniform
- * laws, f = identity, and products in whole tiles at tile 64 or of any shape
- * at tile 128 (other tables, and 0, take a gather, a sketch and a merge
- * launch per pass).  It gives the same estimate as
- * the launch-per-pass form with one realisation group per pass.  Its
+ * pass of every level) in one persistent kernel, whose step p gathers pass p
+ * into one of three buffers and sketches pass p - 1 from another, its work
+ * claimed from per-XCD queues, the sketch of each step behind a bounded
+ * grid-wide barrier (workspace: three gather buffers); built for FP32, BF16
+ * and FP8 operands, i.i.d. normal or uniform laws, f = identity, and
+ * products in whole tiles at tile 64 or of any shape at tile 128 (other
+ * tables, and 0, take a gather, a sketch and a merge launch per pass).  It
+ * gives the same estimate as the launch-per-pass form with one realisation
+ * group per pass.  Its
  * workgroups must all be resident at once: its grid is the device's resident
  * capacity for it, and a barrier that waits past ten seconds makes every
  * output NaN (and the call EDEVICE when it reads level_var). */

@@ -189,10 +189,11 @@ struct MatmulPlan {
     bool fp8_reparam = false;
     size_t off_exp = 0, off_bound = 0;
     // the single-launch form (matmul_plan_persistent): its passes, their
-    // table and phase counters in workspace, and the second gather buffer
+    // table and step counters in workspace, and the second and third gather
+    // buffers
     bool persistent = false;
     std::vector<PassDesc> passes;
-    size_t off_passes = 0, off_sync = 0, off_gather2 = 0;
+    size_t off_passes = 0, off_sync = 0, off_gather2 = 0, off_gather3 = 0;
     int64_t sync_words = 0;
     // the set form of a realisation (matmul_plan_set_form): per-realisation
     // hash tables and position weights in workspace

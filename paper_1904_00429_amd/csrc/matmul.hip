@@ -522,6 +522,7 @@ void matmul_plan_persistent(MatmulPlan& plan, const LevelRange* ranges, int num_
     plan.sync_words = (passes + 1) * kPhaseWords + kSyncStride;
     plan.off_sync = off;    off = align(off + sizeof(uint32_t) * plan.sync_words);
     plan.off_gather2 = off; off = align(off + (size_t)plan.gather_bytes);
+    plan.off_gather3 = off; off = align(off + (size_t)plan.gather_bytes);
     plan.total = off;
 }
 

@@ -30,11 +30,12 @@ constexpr int64_t kSketchMaxBlocks = 8192;
 constexpr int kXcds = 8;                     // accelerator complex dies of an MI355X
 constexpr int64_t kDualMaxDraws = 32;        // realisations this short use the two-accumulator statistics
 static_assert(kGatherThreads == kWave, "a gather unit is one wave");
-// single-launch form: per phase one claim counter per XCD queue and one
-// arrival counter, each on a 64-byte line of its own
+// single-launch form: per step one claim counter per XCD queue of the
+// sketch, one per XCD queue of the gather and one arrival counter, each on a
+// 64-byte line of its own
 constexpr int64_t kPersistentMaxPasses = 1 << 16;
 constexpr int kSyncStride = 16;                    // uint32 words between counters
-constexpr int kPhaseWords = (kXcds + 1) * kSyncStride;
+constexpr int kPhaseWords = (2 * kXcds + 1) * kSyncStride;
 
 // ---------------------------------------------------------------------------
 // Contraction policies: operand type, MFMA shape, fragment layout.  A

@@ -1,35 +1,37 @@
 // Single-launch form of a fixed-N_l matrix-product estimate over a table of
 // products (Sec. 3, Alg. 1 per level): every level's passes run in one
-// persistent kernel.  A pass is a batch of realisations of one level; phase p
-// of the launch gathers the sampled columns of pass p into one of two buffers
-// while it sketches pass p - 1 from the other, so the VALU-bound generation
+// persistent kernel.  A pass is a batch of realisations of one level; step p
+// of the launch gathers the sampled columns of pass p into one of three
+// buffers and sketches pass p - 1 from another, so the VALU-bound generation
 // of one pass overlaps the MFMA-bound contraction of the previous one, and the
-// work of a phase is claimed from queues rather than dealt by a grid:
+// work of a step is claimed from queues rather than dealt by a grid:
 //
-//   * a phase's work items are the sketch tiles of pass p - 1 (longest first)
-//     and then chunks of 64 gather units of pass p (a unit is one wave's block
-//     of positions of one realisation of one product);
-//   * the items are split into one contiguous queue per XCD (a product's tiles
+//   * a step's work lists are the chunks of 16 gather units of pass p (a unit
+//     is one wave's block of positions of one realisation of one product) and
+//     the sketch tiles of pass p - 1 (a tile over the whole batch);
+//   * each list is split into one contiguous queue per XCD (a product's tiles
 //     stay together, so their operand rows are shared through that XCD's L2);
 //     a workgroup drains the queue of its own XCD, then the others';
-//   * a phase ends at a grid-wide barrier: every thread releases its writes at
-//     agent scope, one thread per workgroup arrives on the phase's counter and
-//     waits for the whole grid, then acquires.  The grid never exceeds the
-//     workgroups the device holds at once, and the wait is bounded: past its
-//     limit the launch raises an error flag and every workgroup leaves.
+//   * between the two lists of step p a workgroup waits at barrier p - 1,
+//     where every workgroup arrives after the sketch of step p - 1: every
+//     thread releases its writes at agent scope, one thread per workgroup
+//     arrives on the barrier's counter; the waiter polls it for the whole
+//     grid, then acquires.  The grid never exceeds the workgroups the device
+//     holds at once, and the wait is bounded: past its limit the launch raises
+//     an error flag and every workgroup leaves.
 //
-// Sketches of consecutive passes of one level are in consecutive phases, so
-// their merges into the level state (the fused Chan merge of the sketch
-// epilogue) keep the order of the launch-per-pass form; passes of different
-// levels touch different state.  The arithmetic is that of the launch-per-pass
-// form (the same device functions on the same passes), so both give the same
-// estimate.
+// Sketches of consecutive passes of one level are in consecutive steps, each
+// behind the barrier after the previous one, so their merges into the level
+// state (the fused Chan merge of the sketch epilogue) keep the order of the
+// launch-per-pass form; passes of different levels touch different state.
+// The arithmetic is that of the launch-per-pass form (the same device
+// functions on the same passes), so both give the same estimate.
 #include "matmul_device.hpp"
 #include "mlmc.h"
 
 namespace mlmc {
 
-constexpr int64_t kUnitsPerItem = 64;   // gather units per queue item
+constexpr int64_t kUnitsPerItem = 16;   // gather units per queue item
 
 struct PersistParams {
     const ProblemDesc* descs;
@@ -38,21 +40,21 @@ struct PersistParams {
     const PassDesc* passes;
     int32_t num_passes;
     int32_t elem;
-    char* gbuf0;                 // gather buffer of the even passes
-    char* gbuf1;                 // and of the odd ones
+    char* gbuf[3];               // gather buffer of pass p: gbuf[p % 3]
     int64_t sum_mp;
     double* level_mean;          // levels x sum_mp
     double* tile_acc;            // levels x total_tiles
     uint32_t key0, key1;
-    uint32_t* sync;              // (num_passes + 1) phases x kPhaseWords, then the error flag
+    uint32_t* sync;              // (num_passes + 1) steps x kPhaseWords, then the error flag
     int64_t timeout_ticks;       // wall-clock ticks a workgroup may wait at a barrier
 };
 
 // Sketch item `item` (an output tile over the whole batch) of pass `pass`.
 template <typename P, int WR, int WC, int NBR, int NBC>
-__device__ __noinline__ void sketch_of_pass(const PersistParams& prm, const PassDesc& d, int pass, int64_t item,
-                                               typename SketchStage<P, WR, WC, NBR, NBC>::Buf& lds0,
-                                               typename SketchStage<P, WR, WC, NBR, NBC>::Buf& lds1, double* red)
+__device__ __attribute__((always_inline)) void sketch_of_pass(
+    const PersistParams& prm, const PassDesc& d, int pass, int64_t item,
+    typename SketchStage<P, WR, WC, NBR, NBC>::Buf& lds0, typename SketchStage<P, WR, WC, NBR, NBC>::Buf& lds1,
+    double* red)
 {
     SketchParams s = {};
     s.descs = prm.descs;
@@ -65,7 +67,7 @@ __device__ __noinline__ void sketch_of_pass(const PersistParams& prm, const Pass
     s.elem = prm.elem;
     s.c = d.c;
     s.c_prev = d.c_prev;
-    s.gbuf = pass % 2 == 0 ? prm.gbuf0 : prm.gbuf1;
+    s.gbuf = prm.gbuf[pass % 3];
     s.sum_mp = prm.sum_mp;
     s.fuse = 1;
     s.done_before = d.done_before;
@@ -90,8 +92,9 @@ __device__ __noinline__ void sketch_of_pass(const PersistParams& prm, const Pass
 
 // Gather item `item` of pass `pass`: kUnitsPerItem units, one wave each.
 template <typename P, typename Compute, int WAVES, int LAWS, bool V16>
-__device__ __noinline__ void gather_of_pass(const PersistParams& prm, const PassDesc& d, int pass, int64_t item,
-                                               int wave, int lane, uint32_t* cols, Compute* colf)
+__device__ __attribute__((always_inline)) void gather_of_pass(const PersistParams& prm, const PassDesc& d, int pass,
+                                                               int64_t item, int wave, int lane, uint32_t* cols,
+                                                               Compute* colf)
 {
     GatherParams g = {};
     g.descs = prm.descs;
@@ -108,7 +111,7 @@ __device__ __noinline__ void gather_of_pass(const PersistParams& prm, const Pass
     g.key1 = prm.key1;
     g.k_first = d.k_first;
     g.elem = prm.elem;
-    g.gbuf = pass % 2 == 0 ? prm.gbuf0 : prm.gbuf1;
+    g.gbuf = prm.gbuf[pass % 3];
     const int64_t units = d.units, gx = d.gx, per_prob = d.gx * d.batch;
     const int64_t u0 = item * kUnitsPerItem;
     const int64_t u1 = u0 + kUnitsPerItem < units ? u0 + kUnitsPerItem : units;
@@ -117,6 +120,30 @@ __device__ __noinline__ void gather_of_pass(const PersistParams& prm, const Pass
         const int64_t by = r / gx, bx = r - by * gx;
         gather_unit<Compute, typename P::In, P::KPACK, LAWS, V16>(g, (uint32_t)bx, (uint32_t)by, (uint32_t)bz, lane,
                                                                   kWave, cols, colf);
+    }
+}
+
+// Claims the items [0, n) of one work list from its per-XCD queues (counters
+// at `counters`, kSyncStride apart) and runs `work` on each: the queue of the
+// workgroup's own XCD first, then the others'.
+template <typename Work>
+__device__ __attribute__((always_inline)) void drain_queues(uint32_t* counters, int64_t n, int home,
+                                                             int64_t* claimed, Work&& work)
+{
+    for (int qi = 0; qi < kXcds; ++qi) {
+        const int q = (home + qi) % kXcds;
+        const int64_t first = n * q / kXcds, len = n * (q + 1) / kXcds - first;
+        if (len == 0) continue;
+        for (;;) {
+            if (threadIdx.x == 0)
+                *claimed = (int64_t)__hip_atomic_fetch_add(counters + q * kSyncStride, 1u, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            const int64_t i = *claimed;
+            __syncthreads();
+            if (i >= len) break;
+            work(first + i);
+        }
     }
 }
 
@@ -136,63 +163,58 @@ __global__ __launch_bounds__(kWave * WR * WC, WPE) void persistent_kernel(Persis
     const int home = (int)(blockIdx.x % kXcds);    // workgroups are dealt to the XCDs round-robin
     uint32_t* const error = prm.sync + (int64_t)(prm.num_passes + 1) * kPhaseWords;
 
+    // Step ph: gather pass ph; wait at barrier ph - 1; sketch pass ph - 1;
+    // arrive at barrier ph.  The gather of pass ph overwrites the buffer that
+    // the sketch of pass ph - 3 read, which every workgroup finished before
+    // arriving at barrier ph - 2, and this workgroup waited there in step
+    // ph - 1: so a workgroup gathers as soon as it has sketched, and the wait
+    // for the slowest workgroup of a barrier overlaps the next gather.
     for (int ph = 0; ph <= prm.num_passes; ++ph) {
         uint32_t* const words = prm.sync + (int64_t)ph * kPhaseWords;
-        const int64_t n_s = ph > 0 ? prm.total_tiles : 0;
-        const int64_t n_g = ph < prm.num_passes ? ceil_div(prm.passes[ph].units, kUnitsPerItem) : 0;
-        for (int qi = 0; qi < kXcds; ++qi) {
-            const int q = (home + qi) % kXcds;
-            const int64_t s0 = n_s * q / kXcds, s1 = n_s * (q + 1) / kXcds;
-            const int64_t g0 = n_g * q / kXcds, g1 = n_g * (q + 1) / kXcds;
-            const int64_t len = (s1 - s0) + (g1 - g0);
-            if (len == 0) continue;
-            for (;;) {
-                if (threadIdx.x == 0)
-                    claimed = (int64_t)__hip_atomic_fetch_add(words + q * kSyncStride, 1u, __ATOMIC_RELAXED,
-                                                              __HIP_MEMORY_SCOPE_AGENT);
-                __syncthreads();
-                const int64_t i = claimed;
-                __syncthreads();
-                if (i >= len) break;
-                // one call per item: the sketch and the gather are functions of
-                // their own, so each is register-allocated alone and neither
-                // holds the other's state
-                if (i < s1 - s0)
-                    sketch_of_pass<P, WR, WC, NBR, NBC>(prm, prm.passes[ph - 1], ph - 1, s0 + i, lds0, lds1, red);
-                else
-                    gather_of_pass<P, Compute, WAVES, LAWS, V16>(prm, prm.passes[ph], ph, g0 + i - (s1 - s0), wave,
-                                                                 lane, cols[wave], colf[wave]);
+        if (ph < prm.num_passes)
+            drain_queues(words + kXcds * kSyncStride, ceil_div(prm.passes[ph].units, kUnitsPerItem), home, &claimed,
+                         [&](int64_t item) {
+                             gather_of_pass<P, Compute, WAVES, LAWS, V16>(prm, prm.passes[ph], ph, item, wave, lane,
+                                                                          cols[wave], colf[wave]);
+                         });
+        if (ph > 0) {
+            // barrier ph - 1: the gather of pass ph - 1 and the sketch of
+            // pass ph - 2 (the level state this one merges into) are done
+            if (threadIdx.x == 0) {
+                const uint32_t* const arrive = words - kPhaseWords + 2 * kXcds * kSyncStride;
+                const int64_t t0 = wall_clock64();
+                int ok = 1;
+                while (__hip_atomic_load(arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gridDim.x) {
+                    if (__hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+                        wall_clock64() - t0 > prm.timeout_ticks) {
+                        __hip_atomic_store(error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        ok = 0;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(8);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                phase_ok = ok;
             }
+            __syncthreads();
+            if (!phase_ok) return;
+            drain_queues(words, prm.total_tiles, home, &claimed, [&](int64_t item) {
+                sketch_of_pass<P, WR, WC, NBR, NBC>(prm, prm.passes[ph - 1], ph - 1, item, lds0, lds1, red);
+            });
         }
-        // phase barrier
+        // arrive at barrier ph (the last one has no waiter: the launch's end
+        // orders the finalisation after it)
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t* const arrive = words + kXcds * kSyncStride;
-            __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const int64_t t0 = wall_clock64();
-            int ok = 1;
-            while (__hip_atomic_load(arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gridDim.x) {
-                if (__hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
-                    wall_clock64() - t0 > prm.timeout_ticks) {
-                    __hip_atomic_store(error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ok = 0;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(8);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            phase_ok = ok;
-        }
-        __syncthreads();
-        if (!phase_ok) return;
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(words + 2 * kXcds * kSyncStride, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
 namespace {
 
 // Workgroups the device holds at once for `kernel` (all of them take part in
-// every phase barrier), or 0 when the query fails.
+// every barrier), or 0 when the query fails.
 template <typename K>
 int64_t resident_capacity(K kernel, int threads)
 {
@@ -224,15 +246,16 @@ hipError_t launch_persistent(const MatmulPlan& plan, const StreamKeys& keys, cha
     prm.passes = reinterpret_cast<const PassDesc*>(ws + plan.off_passes);
     prm.num_passes = (int32_t)plan.passes.size();
     prm.elem = plan.elem;
-    prm.gbuf0 = ws + plan.off_gather;
-    prm.gbuf1 = ws + plan.off_gather2;
+    prm.gbuf[0] = ws + plan.off_gather;
+    prm.gbuf[1] = ws + plan.off_gather2;
+    prm.gbuf[2] = ws + plan.off_gather3;
     prm.sum_mp = plan.sum_mp;
     prm.level_mean = reinterpret_cast<double*>(ws + plan.off_means);
     prm.tile_acc = reinterpret_cast<double*>(ws + plan.off_tile_acc);
     prm.key0 = keys.key0;
     prm.key1 = keys.key1;
     prm.sync = reinterpret_cast<uint32_t*>(ws + plan.off_sync);
-    // a phase lasts milliseconds; ten seconds means some workgroup never ran
+    // a step lasts milliseconds; ten seconds means some workgroup never ran
     prm.timeout_ticks = (int64_t)rate_khz * 1000 * 10;
     hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(threads), 0, stream, prm);
     return hipGetLastError();
@@ -257,25 +280,27 @@ hipError_t matmul_persistent_run(const MatmulPlan& plan, const StreamKeys& keys,
     if (!plan.persistent) return hipErrorInvalidValue;
     hipError_t e;
     {
-        // the claim and arrival counters of every phase and the error flag start at zero
+        // the claim and arrival counters of every step and the error flag start at zero
         ScopedTiming t(timer, MLMC_KERNEL_FINAL);
         e = fill_doubles(reinterpret_cast<double*>(ws + plan.off_sync), ceil_div(plan.sync_words, 2), 0.0, stream);
     }
     if (e != hipSuccess) return e;
     ScopedTiming t(timer, MLMC_KERNEL_SAMPLE);
     // the workgroup shapes of the launch-per-pass form: tile 64 is 2 x 2 waves
-    // of one MFMA block (four waves per SIMD), tile 128 2 x 2 waves of 2 x 2
-    // blocks (two)
+    // of one MFMA block, tile 128 2 x 2 waves of 2 x 2 blocks; the gather and
+    // the sketch share one register allocation, which fits three waves per
+    // SIMD at tile 64 (measured faster than four, where more of it spills)
+    // and two at tile 128
     switch (plan.prec) {
     case 1:
         return plan.tile == 128 ? launch_laws<PolicyF32, float, 2, 2, 2, 2, 2>(plan, keys, ws, stream)
-                                : launch_laws<PolicyF32, float, 2, 2, 1, 1, 4>(plan, keys, ws, stream);
+                                : launch_laws<PolicyF32, float, 2, 2, 1, 1, 3>(plan, keys, ws, stream);
     case 2:
         return plan.tile == 128 ? launch_laws<PolicyBF16, float, 2, 2, 2, 2, 2>(plan, keys, ws, stream)
-                                : launch_laws<PolicyBF16, float, 2, 2, 1, 1, 4>(plan, keys, ws, stream);
+                                : launch_laws<PolicyBF16, float, 2, 2, 1, 1, 3>(plan, keys, ws, stream);
     case 3:
         return plan.tile == 128 ? launch_laws<PolicyFP8, float, 2, 2, 2, 2, 2>(plan, keys, ws, stream)
-                                : launch_laws<PolicyFP8, float, 2, 2, 1, 1, 4>(plan, keys, ws, stream);
+                                : launch_laws<PolicyFP8, float, 2, 2, 1, 1, 3>(plan, keys, ws, stream);
     default:
         return hipErrorInvalidValue;   // FP64 keeps the launch-per-pass form
     }
