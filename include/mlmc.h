@@ -332,6 +332,34 @@ mlmc_status mlmc_matmul_batched_graph_create(int32_t nprob, const mlmc_problem* 
 mlmc_status mlmc_graph_launch(mlmc_graph graph, void* stream);
 mlmc_status mlmc_graph_destroy(mlmc_graph graph);
 
+/* One inner-product estimate (Sec. 2; fixed N_l, or target mode: the pilot,
+ * eq. (28) and the extension, all on the device) captured into a hipGraph
+ * and replayed by mlmc_graph_launch, with no host synchronisation inside:
+ * replays back to back pay one graph launch per estimate instead of the
+ * direct call's launches and its readback.  Arguments as
+ * mlmc_inner_product_estimate; out, level_means, the workspace and the
+ * index weights must stay valid while the graph exists, and each replay
+ * recomputes the estimate with the captured seed into out and level_means.
+ * The schedule's N_l, V_l and status stay in the workspace: read them with
+ * mlmc_inner_product_graph_report.  Errors as mlmc_inner_product_estimate;
+ * EINVAL also for a NULL graph or stream, MLMC_FLAG_ADAPTIVE_LEVELS (Alg. 2's
+ * bias test runs on the host) and MLMC_FLAG_TIMING. */
+mlmc_status mlmc_inner_product_graph_create(int64_t n, const mlmc_dist* x, const mlmc_dist* y,
+                                            const mlmc_levels* levels, double* out,
+                                            double* level_means, void* workspace,
+                                            size_t workspace_bytes, void* stream,
+                                            mlmc_graph* graph);
+/* After a replay of that graph on `stream`: synchronises the stream, reads
+ * V_l (and in target mode N_l and the schedule's status) from the workspace
+ * into *report (NULL: status only) and returns the status the direct call
+ * would have returned: EBUDGET when eq. (28) asked for more realisations
+ * than the counter range or more draws than max_total_draws, EDEVICE for a
+ * device error.
+ * n, levels and the workspace are the ones the graph was created with. */
+mlmc_status mlmc_inner_product_graph_report(int64_t n, const mlmc_levels* levels,
+                                            const void* workspace, size_t workspace_bytes,
+                                            mlmc_report* report, void* stream);
+
 /* ---- Differentiation ------------------------------------------------------
  * Adjoint of mlmc_matmul_estimate for reparameterised laws A = M_A + S_A o Z,
  * B = M_B + S_B o W (both MLMC_LAW_REPARAM).  Y = sum_l Ybar_l is bilinear in

@@ -18,6 +18,7 @@ EXPORTED = [
     "mlmc_matmul_batched_graph_create", "mlmc_graph_launch", "mlmc_graph_destroy",
     "mlmc_optimal_index_weights", "mlmc_sample_indices_weighted",
     "mlmc_inner_product_noalloc_limit", "mlmc_inner_product_estimate_noalloc",
+    "mlmc_inner_product_graph_create", "mlmc_inner_product_graph_report",
 ]
 
 
@@ -108,6 +109,11 @@ def lib() -> ctypes.CDLL:
     L.mlmc_matmul_batched_graph_create.restype = ctypes.c_int
     L.mlmc_matmul_batched_graph_create.argtypes = [i32, PP, LP, TP, vp, ctypes.c_size_t, vp,
                                                    ctypes.POINTER(ctypes.c_void_p)]
+    L.mlmc_inner_product_graph_create.restype = ctypes.c_int
+    L.mlmc_inner_product_graph_create.argtypes = [i64, DP, DP, LP, vp, vp, vp, ctypes.c_size_t, vp,
+                                                  ctypes.POINTER(ctypes.c_void_p)]
+    L.mlmc_inner_product_graph_report.restype = ctypes.c_int
+    L.mlmc_inner_product_graph_report.argtypes = [i64, LP, vp, ctypes.c_size_t, RP, vp]
     L.mlmc_graph_launch.restype = ctypes.c_int
     L.mlmc_graph_launch.argtypes = [vp, vp]
     L.mlmc_graph_destroy.restype = ctypes.c_int

@@ -284,6 +284,106 @@ void KernelTimer::collect(double* ms, int64_t* launches) const
 
 }  // namespace mlmc
 
+namespace {
+
+// Arguments of an inner-product estimate, checked before any device call.
+mlmc_status check_inner(int64_t n, const mlmc_dist* x, const mlmc_dist* y, const mlmc_levels* lv,
+                        const double* out, const void* workspace, size_t workspace_bytes)
+{
+    if (n < 1 || n >= kU32) return fail(MLMC_EINVAL, "n must be in [1, 2^32)");
+    mlmc_status st = check_levels(lv, true);
+    if (st != MLMC_OK) return st;
+    if ((st = check_dist(x, "x", 1, true)) != MLMC_OK) return st;
+    if ((st = check_dist(y, "y", 1, true)) != MLMC_OK) return st;
+    if ((st = check_pair(x, y, lv->prec)) != MLMC_OK) return st;
+    if ((lv->flags & MLMC_FLAG_INDEX_WORD32) && ((n & (n - 1)) != 0 || x->law >= MLMC_LAW_RAMP_NORMAL))
+        return fail(MLMC_EINVAL, "32-bit index words need a power-of-two n and laws 0-2");
+    if (!out) return fail(MLMC_EINVAL, "out is NULL");
+    const InnerLayout L = inner_layout(lv->num_levels, n, lv->index_weights != nullptr);
+    if (!workspace || workspace_bytes < L.total) return fail(MLMC_EWORKSPACE, "workspace needs %zu bytes", L.total);
+    return MLMC_OK;
+}
+
+// The device work of a non-adaptive inner-product estimate: fixed N_l, or
+// target mode (the pilot, eq. (28) on the device, the extension).  Launches
+// only, no synchronisation: a stream capture records all of it.
+hipError_t inner_enqueue(int64_t n, const mlmc_dist* x, const mlmc_dist* y, const mlmc_levels* lv, double* out,
+                         double* level_means, char* ws, hipStream_t stream, KernelTimer* timer)
+{
+    const InnerLayout L = inner_layout(lv->num_levels, n, lv->index_weights != nullptr);
+    Moments* state = reinterpret_cast<Moments*>(ws + L.off_state);
+    Moments* partials = reinterpret_cast<Moments*>(ws + L.off_partials);
+    double* var_dev = reinterpret_cast<double*>(ws + L.off_var);
+    InnerSlot* slot = reinterpret_cast<InnerSlot*>(ws + L.off_slot);
+    const IndexWeights iw{lv->index_weights,
+                          lv->index_weights ? reinterpret_cast<const uint64_t*>(ws + L.off_cum) : nullptr};
+    hipError_t e = hipSuccess;
+    if (iw.w) {
+        ScopedTiming t(timer, MLMC_KERNEL_FINAL);
+        if ((e = build_cumulative(iw.w, n, reinterpret_cast<uint64_t*>(ws + L.off_cum), stream)) != hipSuccess)
+            return e;
+    }
+    const Law lx = to_law(*x), ly = to_law(*y);
+    const StreamKeys keys = keys_of(lv);
+    const int L1 = lv->num_levels;
+    const bool word32 = (lv->flags & MLMC_FLAG_INDEX_WORD32) != 0;
+    const InnerTelescope tele{out, level_means, var_dev};
+    if (lv->rmse_target > 0.0) {
+        InnerScheduleInputs sch;
+        sch.eps = lv->rmse_target;
+        sch.pilot = lv->pilot_samples;
+        sch.max_total_draws = lv->max_total_draws;
+        sch.c = lv->c;
+        LevelRange pilot[MLMC_MAX_LEVELS];
+        for (int l = 0; l < L1; ++l) {
+            pilot[l] = range_of(lv, l, 0, lv->pilot_samples);
+            sch.level_field[l] = pilot[l].level_field;
+            sch.stride[l] = (uint32_t)pilot[l].stride;
+        }
+        sch.counts = reinterpret_cast<int64_t*>(ws + L.off_counts);
+        sch.status = reinterpret_cast<int32_t*>(ws + L.off_status);
+        sch.status_value = reinterpret_cast<double*>(ws + L.off_status + 2 * sizeof(int32_t));
+        return inner_target_run(sch, pilot, L1, n, lx, ly, func_of(lv), iw, lv->prec, word32, keys, partials, state,
+                                slot, tele, stream, timer);
+    }
+    LevelRange ranges[MLMC_MAX_LEVELS];
+    for (int l = 0; l < L1; ++l) ranges[l] = range_of(lv, l, 0, lv->n_samples[l]);
+    return inner_levels_run(ranges, L1, n, lx, ly, func_of(lv), iw, lv->prec, word32, keys, partials, state, slot,
+                            true, &tele, stream, timer);
+}
+
+// V_l and N_l of a non-adaptive estimate that has been enqueued on `stream`
+// (synchronises it), and in target mode the schedule's status: one readback
+// of V_l, N_l and the status, which lie in that order in the workspace.
+mlmc_status inner_collect(int64_t n, const mlmc_levels* lv, const char* ws, hipStream_t stream, double* var,
+                          int64_t* counts)
+{
+    const InnerLayout L = inner_layout(lv->num_levels, n, lv->index_weights != nullptr);
+    const int L1 = lv->num_levels;
+    hipError_t e = hipSuccess;
+    if (lv->rmse_target <= 0.0) {
+        if ((e = hipMemcpyAsync(var, ws + L.off_var, sizeof(double) * L1, hipMemcpyDeviceToHost, stream)) !=
+                hipSuccess ||
+            (e = hipStreamSynchronize(stream)) != hipSuccess)
+            return device_fail(e, "level variance readback");
+        for (int l = 0; l < L1; ++l) counts[l] = lv->n_samples[l];
+        return MLMC_OK;
+    }
+    std::vector<char> back(sizeof(double) * L1 + sizeof(int64_t) * L1 + 2 * sizeof(int32_t) + sizeof(double));
+    if ((e = hipMemcpyAsync(back.data(), ws + L.off_var, back.size(), hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(stream)) != hipSuccess)
+        return device_fail(e, "schedule readback");
+    memcpy(var, back.data(), sizeof(double) * L1);
+    memcpy(counts, back.data() + sizeof(double) * L1, sizeof(int64_t) * L1);
+    int32_t code[2];
+    double value;
+    memcpy(code, back.data() + 16 * L1, sizeof(code));
+    memcpy(&value, back.data() + 16 * L1 + sizeof(code), sizeof(value));
+    return schedule_status(lv, code[0], code[1], value);
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* mlmc_status_string(mlmc_status st)
@@ -325,20 +425,28 @@ mlmc_status mlmc_inner_product_estimate(int64_t n, const mlmc_dist* x, const mlm
                                         void* stream_ptr)
 {
     g_last_error.clear();
-    if (n < 1 || n >= kU32) return fail(MLMC_EINVAL, "n must be in [1, 2^32)");
-    mlmc_status st = check_levels(lv, true);
+    mlmc_status st = check_inner(n, x, y, lv, out, workspace, workspace_bytes);
     if (st != MLMC_OK) return st;
-    if ((st = check_dist(x, "x", 1, true)) != MLMC_OK) return st;
-    if ((st = check_dist(y, "y", 1, true)) != MLMC_OK) return st;
-    if ((st = check_pair(x, y, lv->prec)) != MLMC_OK) return st;
-    if ((lv->flags & MLMC_FLAG_INDEX_WORD32) && ((n & (n - 1)) != 0 || x->law >= MLMC_LAW_RAMP_NORMAL))
-        return fail(MLMC_EINVAL, "32-bit index words need a power-of-two n and laws 0-2");
-    if (!out) return fail(MLMC_EINVAL, "out is NULL");
-    const InnerLayout L = inner_layout(lv->num_levels, n, lv->index_weights != nullptr);
-    if (!workspace || workspace_bytes < L.total)
-        return fail(MLMC_EWORKSPACE, "workspace needs %zu bytes", L.total);
     hipStream_t stream = static_cast<hipStream_t>(stream_ptr);
     char* ws = static_cast<char*>(workspace);
+    const int L1 = lv->num_levels;
+    std::vector<int64_t> counts(L1, 0);
+    std::vector<double> var(L1, 0.0);
+    KernelTimer timer_obj(stream);
+    KernelTimer* timer = (lv->flags & MLMC_FLAG_TIMING) ? &timer_obj : nullptr;
+    hipError_t e = hipSuccess;
+    if (!(lv->flags & MLMC_FLAG_ADAPTIVE_LEVELS)) {
+        // fixed N_l, or target mode with eq. (28) on the device: one
+        // synchronisation at the end (target mode reads V_l, N_l and the
+        // schedule's status; fixed N_l only when a report is asked for)
+        if ((e = inner_enqueue(n, x, y, lv, out, level_means, ws, stream, timer)) != hipSuccess)
+            return device_fail(e, lv->rmse_target > 0.0 ? "target-mode launch" : "level launch");
+        if (lv->rmse_target <= 0.0 && !report) return MLMC_OK;
+        if ((st = inner_collect(n, lv, ws, stream, var.data(), counts.data())) != MLMC_OK) return st;
+        if (report) fill_report(lv, counts.data(), var.data(), timer, report, L1, true);
+        return MLMC_OK;
+    }
+    const InnerLayout L = inner_layout(L1, n, lv->index_weights != nullptr);
     Moments* state = reinterpret_cast<Moments*>(ws + L.off_state);
     Moments* partials = reinterpret_cast<Moments*>(ws + L.off_partials);
     double* var_dev = reinterpret_cast<double*>(ws + L.off_var);
@@ -347,106 +455,55 @@ mlmc_status mlmc_inner_product_estimate(int64_t n, const mlmc_dist* x, const mlm
                           lv->index_weights ? reinterpret_cast<const uint64_t*>(ws + L.off_cum) : nullptr};
     const Law lx = to_law(*x), ly = to_law(*y);
     const StreamKeys keys = keys_of(lv);
-    const int L1 = lv->num_levels;
-    std::vector<int64_t> counts(L1, 0);
-    std::vector<double> var(L1, 0.0);
-    KernelTimer timer_obj(stream);
-    KernelTimer* timer = (lv->flags & MLMC_FLAG_TIMING) ? &timer_obj : nullptr;
-    hipError_t e = hipSuccess;
     if (iw.w) {
         ScopedTiming t(timer, MLMC_KERNEL_FINAL);
         e = build_cumulative(iw.w, n, reinterpret_cast<uint64_t*>(ws + L.off_cum), stream);
     }
     if (e != hipSuccess) return device_fail(e, "cumulative weights");
-    const InnerTelescope tele{out, level_means, var_dev};
     const bool word32 = (lv->flags & MLMC_FLAG_INDEX_WORD32) != 0;
 
     // every level of a phase goes into one launch; the first phase of an
-    // estimate clears the level states, the last one telescopes
-    auto run_all = [&](const int64_t* k0, const int64_t* cnt, bool first, bool last) -> hipError_t {
+    // estimate clears the level states
+    auto run_all = [&](const int64_t* k0, const int64_t* cnt, bool first) -> hipError_t {
         LevelRange ranges[MLMC_MAX_LEVELS];
         for (int l = 0; l < L1; ++l) ranges[l] = range_of(lv, l, k0[l], cnt[l]);
         return inner_levels_run(ranges, L1, n, lx, ly, func_of(lv), iw, lv->prec, word32, keys, partials, state,
-                                slot, first, last ? &tele : nullptr, stream, timer);
+                                slot, first, nullptr, stream, timer);
     };
-    std::vector<int64_t> zero(L1, 0), amount(L1, 0);
-    int used = L1;
-    bool passed = true;
-    if (lv->flags & MLMC_FLAG_ADAPTIVE_LEVELS) {
-        // Alg. 2's loop over L: pilot of the new level, eq. (28) over the
-        // levels so far, extension of every level, then the bias test
-        used = 0;
-        passed = false;
-        std::vector<int64_t> target(L1);
-        for (int L = 0; L < L1 && !passed; ++L) {
-            std::fill(amount.begin(), amount.end(), 0);
-            amount[L] = lv->pilot_samples;
-            if ((e = run_all(counts.data(), amount.data(), L == 0, false)) != hipSuccess)
-                return device_fail(e, "pilot launch");
-            counts[L] = lv->pilot_samples;
-            used = L + 1;
-            {
-                ScopedTiming t(timer, MLMC_KERNEL_FINAL);
-                e = inner_telescope(state, L1, out, nullptr, var_dev, stream);
-            }
-            if (e != hipSuccess) return device_fail(e, "level statistics");
-            if ((e = hipMemcpyAsync(var.data(), var_dev, sizeof(double) * L1, hipMemcpyDeviceToHost, stream)) !=
-                    hipSuccess ||
-                (e = hipStreamSynchronize(stream)) != hipSuccess)
-                return device_fail(e, "level statistics readback");
-            if ((st = schedule(lv, var.data(), used, target.data())) != MLMC_OK) return st;
-            for (int l = 0; l < L1; ++l) amount[l] = l < used && target[l] > counts[l] ? target[l] - counts[l] : 0;
-            if ((e = run_all(counts.data(), amount.data(), false, false)) != hipSuccess)
-                return device_fail(e, "extension launch");
-            for (int l = 0; l < L1; ++l) counts[l] += amount[l];
-            if (used >= 3) {
-                Moments fin;
-                if ((e = hipMemcpyAsync(&fin, state + L, sizeof(Moments), hipMemcpyDeviceToHost, stream)) !=
-                        hipSuccess ||
-                    (e = hipStreamSynchronize(stream)) != hipSuccess)
-                    return device_fail(e, "level mean readback");
-                passed = bias_test(lv, L, fabs(fin.mean), true);
-            }
+    // Alg. 2's loop over L: pilot of the new level, eq. (28) over the levels
+    // so far, extension of every level, then the bias test
+    std::vector<int64_t> amount(L1, 0), target(L1);
+    int used = 0;
+    bool passed = false;
+    for (int L = 0; L < L1 && !passed; ++L) {
+        std::fill(amount.begin(), amount.end(), 0);
+        amount[L] = lv->pilot_samples;
+        if ((e = run_all(counts.data(), amount.data(), L == 0)) != hipSuccess) return device_fail(e, "pilot launch");
+        counts[L] = lv->pilot_samples;
+        used = L + 1;
+        {
+            ScopedTiming t(timer, MLMC_KERNEL_FINAL);
+            e = inner_telescope(state, L1, out, nullptr, var_dev, stream);
         }
-    } else if (lv->rmse_target > 0.0) {
-        // the pilot, eq. (28) and the extension, all on the device: one
-        // synchronisation at the end reads V_l, N_l and the schedule's status
-        InnerScheduleInputs sch;
-        sch.eps = lv->rmse_target;
-        sch.pilot = lv->pilot_samples;
-        sch.max_total_draws = lv->max_total_draws;
-        sch.c = lv->c;
-        LevelRange pilot[MLMC_MAX_LEVELS];
-        for (int l = 0; l < L1; ++l) {
-            pilot[l] = range_of(lv, l, 0, lv->pilot_samples);
-            sch.level_field[l] = pilot[l].level_field;
-            sch.stride[l] = (uint32_t)pilot[l].stride;
-        }
-        sch.counts = reinterpret_cast<int64_t*>(ws + L.off_counts);
-        sch.status = reinterpret_cast<int32_t*>(ws + L.off_status);
-        sch.status_value = reinterpret_cast<double*>(ws + L.off_status + 2 * sizeof(int32_t));
-        if ((e = inner_target_run(sch, pilot, L1, n, lx, ly, func_of(lv), iw, lv->prec, word32, keys, partials, state,
-                                  slot, tele, stream, timer)) != hipSuccess)
-            return device_fail(e, "target-mode launch");
-        std::vector<char> back(sizeof(double) * L1 + sizeof(int64_t) * L1 + 2 * sizeof(int32_t) + sizeof(double));
-        if ((e = hipMemcpyAsync(back.data(), var_dev, back.size(), hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+        if (e != hipSuccess) return device_fail(e, "level statistics");
+        if ((e = hipMemcpyAsync(var.data(), var_dev, sizeof(double) * L1, hipMemcpyDeviceToHost, stream)) !=
+                hipSuccess ||
             (e = hipStreamSynchronize(stream)) != hipSuccess)
-            return device_fail(e, "schedule readback");
-        memcpy(var.data(), back.data(), sizeof(double) * L1);
-        memcpy(counts.data(), back.data() + sizeof(double) * L1, sizeof(int64_t) * L1);
-        int32_t code[2];
-        double value;
-        memcpy(code, back.data() + 16 * L1, sizeof(code));
-        memcpy(&value, back.data() + 16 * L1 + sizeof(code), sizeof(value));
-        if ((st = schedule_status(lv, code[0], code[1], value)) != MLMC_OK) return st;
-        if (report) fill_report(lv, counts.data(), var.data(), timer, report, used, passed);
-        return MLMC_OK;
-    } else {
-        for (int l = 0; l < L1; ++l) amount[l] = lv->n_samples[l];
-        if ((e = run_all(zero.data(), amount.data(), true, true)) != hipSuccess) return device_fail(e, "level launch");
-        for (int l = 0; l < L1; ++l) counts[l] = lv->n_samples[l];
+            return device_fail(e, "level statistics readback");
+        if ((st = schedule(lv, var.data(), used, target.data())) != MLMC_OK) return st;
+        for (int l = 0; l < L1; ++l) amount[l] = l < used && target[l] > counts[l] ? target[l] - counts[l] : 0;
+        if ((e = run_all(counts.data(), amount.data(), false)) != hipSuccess)
+            return device_fail(e, "extension launch");
+        for (int l = 0; l < L1; ++l) counts[l] += amount[l];
+        if (used >= 3) {
+            Moments fin;
+            if ((e = hipMemcpyAsync(&fin, state + L, sizeof(Moments), hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+                (e = hipStreamSynchronize(stream)) != hipSuccess)
+                return device_fail(e, "level mean readback");
+            passed = bias_test(lv, L, fabs(fin.mean), true);
+        }
     }
-    if (lv->flags & MLMC_FLAG_ADAPTIVE_LEVELS) {
+    {
         ScopedTiming t(timer, MLMC_KERNEL_FINAL);
         e = inner_telescope(state, L1, out, level_means, var_dev, stream);
         if (e != hipSuccess) return device_fail(e, "telescope");
@@ -844,6 +901,63 @@ mlmc_status mlmc_graph_destroy(mlmc_graph graph)
     delete graph;
     if (e1 != hipSuccess) return device_fail(e1, "graph exec destroy");
     if (e2 != hipSuccess) return device_fail(e2, "graph destroy");
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_inner_product_graph_create(int64_t n, const mlmc_dist* x, const mlmc_dist* y,
+                                            const mlmc_levels* lv, double* out, double* level_means,
+                                            void* workspace, size_t workspace_bytes, void* stream_ptr,
+                                            mlmc_graph* graph)
+{
+    g_last_error.clear();
+    if (!graph) return fail(MLMC_EINVAL, "graph is NULL");
+    *graph = nullptr;
+    if (!stream_ptr) return fail(MLMC_EINVAL, "graph capture needs a non-null stream");
+    mlmc_status st = check_inner(n, x, y, lv, out, workspace, workspace_bytes);
+    if (st != MLMC_OK) return st;
+    if (lv->flags & MLMC_FLAG_ADAPTIVE_LEVELS)
+        return fail(MLMC_EINVAL, "the adaptive loop over L reads its bias test on the host: no graph form");
+    if (lv->flags & MLMC_FLAG_TIMING) return fail(MLMC_EINVAL, "kernel timing is not available in a graph");
+    hipStream_t stream = static_cast<hipStream_t>(stream_ptr);
+    mlmc_graph g = new mlmc_graph_s();
+    hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        delete g;
+        return device_fail(e, "begin capture");
+    }
+    const hipError_t launch = inner_enqueue(n, x, y, lv, out, level_means, static_cast<char*>(workspace), stream,
+                                            nullptr);
+    e = hipStreamEndCapture(stream, &g->graph);
+    if (launch != hipSuccess || e != hipSuccess) {
+        if (g->graph) hipGraphDestroy(g->graph);
+        delete g;
+        return device_fail(launch != hipSuccess ? launch : e, "capture");
+    }
+    if ((e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0)) != hipSuccess) {
+        hipGraphDestroy(g->graph);
+        delete g;
+        return device_fail(e, "instantiate");
+    }
+    *graph = g;
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_inner_product_graph_report(int64_t n, const mlmc_levels* lv, const void* workspace,
+                                            size_t workspace_bytes, mlmc_report* report, void* stream_ptr)
+{
+    g_last_error.clear();
+    if (n < 1 || n >= kU32) return fail(MLMC_EINVAL, "n must be in [1, 2^32)");
+    mlmc_status st = check_levels(lv, true);
+    if (st != MLMC_OK) return st;
+    if (lv->flags & MLMC_FLAG_ADAPTIVE_LEVELS) return fail(MLMC_EINVAL, "adaptive estimates have no graph form");
+    const size_t need = inner_layout(lv->num_levels, n, lv->index_weights != nullptr).total;
+    if (!workspace || workspace_bytes < need) return fail(MLMC_EWORKSPACE, "workspace needs %zu bytes", need);
+    std::vector<int64_t> counts(lv->num_levels, 0);
+    std::vector<double> var(lv->num_levels, 0.0);
+    if ((st = inner_collect(n, lv, static_cast<const char*>(workspace), static_cast<hipStream_t>(stream_ptr),
+                            var.data(), counts.data())) != MLMC_OK)
+        return st;
+    if (report) fill_report(lv, counts.data(), var.data(), nullptr, report, lv->num_levels, true);
     return MLMC_OK;
 }
 

@@ -278,6 +278,66 @@ def inner_product_estimate_noalloc(n: int, x: Law, y: Law, c: Sequence[int],
     return _result(out, level_means, rep, len(c))
 
 
+class InnerProductGraph:
+    """One inner-product estimate (fixed N_l, or target mode with eq. (28) on
+    the device) captured into a hipGraph (mlmc_inner_product_graph_create)
+    and replayed on the current stream; after a replay `out` (and `means`)
+    hold the estimate, and report() reads V_l, N_l and the schedule's status
+    (mlmc_inner_product_graph_report, which synchronises the stream)."""
+
+    def __init__(self, n: int, x: Law, y: Law, c: Sequence[int], n_samples: Optional[Sequence[int]] = None,
+                 rmse_target: float = 0.0, pilot: int = 0, seed: int = 0, prec: str = "fp64",
+                 max_total_draws: int = 0, level_means: bool = False, device=None, func: Optional[Func] = None,
+                 index_weights: Optional[torch.Tensor] = None, coupling: str = "prefix",
+                 index_word32: bool = False, stream: Optional[torch.cuda.Stream] = None):
+        self.device = torch.device(device or "cuda")
+        self.n = int(n)
+        self.num_levels = len(c)
+        self.h = _LevelsHolder(c, n_samples, rmse_target, pilot, seed, prec, False, 0, max_total_draws, func,
+                               False, index_weights, coupling, index_word32)
+        self.ws_bytes = int(lib().mlmc_inner_product_workspace_size(self.n, ctypes.byref(self.h.lv)))
+        if self.ws_bytes == 0:
+            raise MLMCError(1, "invalid problem: no workspace size")
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.out = torch.empty((), dtype=torch.float64, device=self.device)
+        self.means = torch.empty((len(c),), dtype=torch.float64, device=self.device) if level_means else None
+        self._dx, self._dy = x.c(), y.c()
+        self.graph = None
+        stream = stream or torch.cuda.Stream(device=self.device)
+        handle = ctypes.c_void_p()
+        check(lib().mlmc_inner_product_graph_create(self.n, ctypes.byref(self._dx), ctypes.byref(self._dy),
+                                                    ctypes.byref(self.h.lv), self.out.data_ptr(),
+                                                    self.means.data_ptr() if self.means is not None else None,
+                                                    self.workspace.data_ptr(), self.ws_bytes, stream.cuda_stream,
+                                                    ctypes.byref(handle)))
+        self.graph = handle
+
+    def replay(self):
+        """Launch the captured estimate on the current stream."""
+        if self.graph is None:
+            raise RuntimeError("the graph has been released")
+        check(lib().mlmc_graph_launch(self.graph, _stream(self.device)))
+
+    def report(self) -> Result:
+        """N_l, V_l and the RMSE estimate of the last replay; raises the
+        schedule's status (EBUDGET) like the direct call."""
+        rep = Report()
+        check(lib().mlmc_inner_product_graph_report(self.n, ctypes.byref(self.h.lv), self.workspace.data_ptr(),
+                                                    self.ws_bytes, ctypes.byref(rep), _stream(self.device)))
+        return _result(self.out, self.means, rep, self.num_levels)
+
+    def release(self):
+        if self.graph is not None:
+            check(lib().mlmc_graph_destroy(self.graph))
+            self.graph = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
 def philox(ctr: torch.Tensor, seed: int) -> torch.Tensor:
     """Philox4x32-10 of device counters (count x 4, int32 holding uint32 bits)."""
     ctr = ctr.contiguous()

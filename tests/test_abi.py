@@ -327,10 +327,10 @@ def test_set_form_validated(L, prec, func, weights, inner, what):
 
 
 def test_set_form_and_single_launch_workspace(L):
-    """The set form adds its tables to the workspace; single_launch = 1 adds a
-    second gather buffer where the single-launch kernel is built (FP32, i.i.d.
-    normal laws, whole tiles) and nothing elsewhere (FP64); an out-of-range
-    single_launch is rejected."""
+    """The set form adds its tables to the workspace; single_launch = 1 adds
+    the second and third gather buffers where the single-launch kernel is
+    built (FP32, i.i.d. normal laws, whole tiles) and nothing elsewhere
+    (FP64); an out-of-range single_launch is rejected."""
     from paper_1904_00429_amd._lib import Problem, Tuning
     lv, keep = _levels([2, 4], [4, 4], prec=1)
     base = L.mlmc_matmul_workspace_size(64, 1000, 64, ctypes.byref(lv))
@@ -388,3 +388,39 @@ def test_adjoint_workspace_below_one_pass_rejected(L):
     assert st == 4
     msg = L.mlmc_last_error()
     assert b"at least" in msg and b"fewest passes" in msg
+
+
+def test_inner_graph_arguments_checked_before_the_device(L):
+    """mlmc_inner_product_graph_create refuses a NULL graph or stream, the
+    adaptive loop (its bias test runs on the host), kernel timing and a short
+    workspace before any device call; the report call checks its own."""
+    lv, keep = _levels([4, 8], [10, 10], prec=0)
+    x = _dist(1, 0.5, 1.0)
+    need = L.mlmc_inner_product_workspace_size(1024, ctypes.byref(lv))
+    g = ctypes.c_void_p()
+    st = L.mlmc_inner_product_graph_create(1024, ctypes.byref(x), ctypes.byref(x), ctypes.byref(lv), 8, None,
+                                           16, need, 8, None)
+    assert st == 1 and b"graph is NULL" in L.mlmc_last_error()
+    st = L.mlmc_inner_product_graph_create(1024, ctypes.byref(x), ctypes.byref(x), ctypes.byref(lv), 8, None,
+                                           16, need, None, ctypes.byref(g))
+    assert st == 1 and b"stream" in L.mlmc_last_error() and not g.value
+    st = L.mlmc_inner_product_graph_create(1024, ctypes.byref(x), ctypes.byref(x), ctypes.byref(lv), 8, None,
+                                           16, need - 1, 8, ctypes.byref(g))
+    assert st == 4
+    lv.flags = 2                                      # timing
+    st = L.mlmc_inner_product_graph_create(1024, ctypes.byref(x), ctypes.byref(x), ctypes.byref(lv), 8, None,
+                                           16, need, 8, ctypes.byref(g))
+    assert st == 1 and b"timing" in L.mlmc_last_error()
+    ad, keep2 = _levels([4, 8, 16], None, eps=1.0, pilot=10, prec=0)
+    ad.flags = 4                                      # adaptive levels
+    need_ad = L.mlmc_inner_product_workspace_size(1024, ctypes.byref(ad))
+    st = L.mlmc_inner_product_graph_create(1024, ctypes.byref(x), ctypes.byref(x), ctypes.byref(ad), 8, None,
+                                           16, need_ad, 8, ctypes.byref(g))
+    assert st == 1 and b"adaptive" in L.mlmc_last_error() and not g.value
+    st = L.mlmc_inner_product_graph_report(1024, ctypes.byref(ad), 16, need_ad, None, None)
+    assert st == 1
+    lv.flags = 0
+    st = L.mlmc_inner_product_graph_report(1024, ctypes.byref(lv), 16, need - 1, None, None)
+    assert st == 4
+    st = L.mlmc_inner_product_graph_report(0, ctypes.byref(lv), 16, need, None, None)
+    assert st == 1
