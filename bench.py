@@ -333,7 +333,7 @@ def main():
         # estimates/s and the sketch's share of its MFMA peak, each timed like
         # the headline (fresh seeds, target mode, every value generated inside)
         k_form = args.form_steps or max(3, args.steps // 2)
-        for pr in ("fp64", "fp32", "bf16"):
+        for pr in ("fp64", "fp32", "bf16", "fp8"):
             if pr == prec:
                 forms[pr] = {"estimates_per_s": value, "ms_per_estimate": ms_per_step,
                              "sketch_frac": roof["frac"] if roof["bound"] == "mfma" else None}
@@ -359,6 +359,8 @@ def main():
         out["forms"] = forms
         if "fp32" in forms and "bf16" in forms:
             out["bf16_over_fp32"] = forms["bf16"]["estimates_per_s"] / forms["fp32"]["estimates_per_s"]
+        if "fp32" in forms and "fp8" in forms:
+            out["fp8_over_fp32"] = forms["fp8"]["estimates_per_s"] / forms["fp32"]["estimates_per_s"]
 
     lps = [pr for pr in forms if pr != "fp64"] or ([prec] if prec != "fp64" else [])
     if args.workload != "inner" and lps and not args.no_precision_check and not args.adaptive:
