@@ -142,3 +142,29 @@ def test_entry_variances_sum_to_level_variances(orc):
     np.testing.assert_allclose(est.entry_var[1], D.var(axis=0, ddof=1), rtol=1e-10)
     sd = est.entry_sd
     assert sd.shape == (m, p) and np.all(sd > 0)
+
+
+def test_e4m3_round_to_nearest_bias_of_the_scaled_normal_law(orc):
+    """Round-to-nearest on e4m3's grid is biased where the density falls
+    across a power of two (the cell of 2^k reaches a quarter of the lower
+    spacing below it and half of the upper one above it).  For N(0.5, 1)
+    under its FP8 scale 2^5 (mean 16, sd 32) the rounded mean is low by about
+    7.1e-4 relative, computed here by quadrature of the rounding against the
+    normal density; A and B independent, a product's mean is low by twice
+    that: 23 per entry of E[AB] = n mu^2 = 16384 at n = 65536, the size of the
+    FP8 form's measured rounding error on that workload."""
+    s = int(orc.fp8_scale_exponents(orc.Law.normal(0.5, 1.0), 1, "A")[0])
+    assert s == 5
+    mu, sd = 0.5 * 2.0 ** s, 2.0 ** s
+    h = 2.0 ** -12
+    x = np.arange(mu - 14 * sd, mu + 14 * sd, h)
+    dens = np.exp(-0.5 * ((x - mu) / sd) ** 2) / (sd * math.sqrt(2.0 * math.pi))
+    r = torch.from_numpy(np.clip(x, -448.0, 448.0).astype(np.float32)).to(torch.float8_e4m3fn).to(
+        torch.float64).numpy()
+    mean_x = float(np.sum(x * dens) * h)
+    mean_r = float(np.sum(r * dens) * h)
+    beta = (mean_r - mean_x) / mean_x
+    assert abs(mean_x - mu) < 1e-9 * mu
+    assert -7.4e-4 < beta < -6.8e-4
+    per_entry = 65536 * 0.25 * (1.0 - (1.0 + beta) ** 2)
+    assert 22.0 < per_entry < 24.5
