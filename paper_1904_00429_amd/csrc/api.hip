@@ -871,12 +871,12 @@ mlmc_status mlmc_matmul_batched_graph_create(int32_t nprob, const mlmc_problem* 
     hipError_t launch = enqueue_batched(plan, lv, ws, stream, nullptr);
     e = hipStreamEndCapture(stream, &g->graph);
     if (launch != hipSuccess || e != hipSuccess) {
-        if (g->graph) hipGraphDestroy(g->graph);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
         delete g;
         return device_fail(launch != hipSuccess ? launch : e, "capture");
     }
     if ((e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0)) != hipSuccess) {
-        hipGraphDestroy(g->graph);
+        (void)hipGraphDestroy(g->graph);
         delete g;
         return device_fail(e, "instantiate");
     }
@@ -929,12 +929,12 @@ mlmc_status mlmc_inner_product_graph_create(int64_t n, const mlmc_dist* x, const
                                             nullptr);
     e = hipStreamEndCapture(stream, &g->graph);
     if (launch != hipSuccess || e != hipSuccess) {
-        if (g->graph) hipGraphDestroy(g->graph);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
         delete g;
         return device_fail(launch != hipSuccess ? launch : e, "capture");
     }
     if ((e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0)) != hipSuccess) {
-        hipGraphDestroy(g->graph);
+        (void)hipGraphDestroy(g->graph);
         delete g;
         return device_fail(e, "instantiate");
     }
